@@ -1,0 +1,97 @@
+"""Seeded synthetic inputs for the coefficient-inversion workloads.
+
+This module draws the random numbers a run consumes and nothing else: white
+noise for prior draws, observation locations, observation noise and the
+Gaussian probe matrix of the randomized eigensolver.  It holds none of the
+method's arithmetic, so both the CPU oracle and the GPU library can take its
+output as input.
+
+Every draw comes from NumPy's Philox4x64-10 bit generator keyed by
+(seed, stream); the stream numbers below fix which draw is which, so two
+callers with the same seed see bit-identical arrays.
+
+Workload shapes follow the paper's Poisson example (Sec. 5.1): a unit-square
+mesh, pointwise observations at uniformly drawn locations with i.i.d. Gaussian
+noise, and a bilaplacian Gaussian prior.  The sizes are those of the workloads
+listed in ``WORKLOADS``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MASTER_SEED = 1909
+
+# Stream identifiers (second Philox key word).
+STREAM_TRUTH = 0      # white noise of the prior draw that serves as the true field
+STREAM_OBS_POINTS = 1  # observation locations
+STREAM_OBS_NOISE = 2  # observation noise
+STREAM_OMEGA = 3      # Gaussian probe matrix of the randomized eigensolver
+STREAM_POST = 4       # white noise of posterior samples
+STREAM_TEST = 7       # generic test vectors (directions, right-hand sides)
+
+# Synthetic workloads shaped like the paper's Poisson example, scaled up.
+WORKLOADS = {
+    "poisson32": dict(N=32, q=100, gamma=0.1, delta=0.5, m_prior=-2.0, k=50, p=20),
+    "poisson256": dict(N=256, q=400, gamma=0.1, delta=0.5, m_prior=-2.0, k=50, p=20),
+    "poisson1024": dict(N=1024, q=2000, gamma=0.05, delta=1.0, m_prior=-2.0, k=200, p=20),
+}
+
+
+def _gen(seed: int, stream: int) -> np.random.Generator:
+    key = (int(seed) & ((1 << 64) - 1)) | ((int(stream) & ((1 << 64) - 1)) << 64)
+    return np.random.Generator(np.random.Philox(key=key))
+
+
+def n_nodes(N: int) -> int:
+    return (N + 1) * (N + 1)
+
+
+def n_noise(N: int) -> int:
+    """Length of one white-noise vector: 3 edge-midpoint values per triangle."""
+    return 6 * N * N
+
+
+def white_noise(N: int, ns: int = 1, seed: int = MASTER_SEED,
+                stream: int = STREAM_TRUTH) -> np.ndarray:
+    """i.i.d. N(0,1) array of shape (ns, 6 N^2), one row per draw."""
+    return _gen(seed, stream).standard_normal((ns, n_noise(N)))
+
+
+def obs_points(q: int, seed: int = MASTER_SEED, lo: float = 0.05,
+               hi: float = 0.95) -> np.ndarray:
+    """(q, 2) locations drawn uniformly in [lo, hi]^2."""
+    return _gen(seed, STREAM_OBS_POINTS).uniform(lo, hi, size=(q, 2))
+
+
+def obs_noise(q: int, seed: int = MASTER_SEED) -> np.ndarray:
+    """(q,) i.i.d. N(0,1) draws that scale into observation noise."""
+    return _gen(seed, STREAM_OBS_NOISE).standard_normal(q)
+
+
+def omega(n: int, b: int, seed: int = MASTER_SEED) -> np.ndarray:
+    """Gaussian probe matrix stored column by column: shape (b, n)."""
+    return _gen(seed, STREAM_OMEGA).standard_normal((b, n))
+
+
+def test_vectors(n: int, b: int, seed: int = MASTER_SEED,
+                 stream: int = STREAM_TEST, scale: float = 1.0) -> np.ndarray:
+    """(b, n) i.i.d. N(0, scale^2) vectors for directions and right-hand sides."""
+    return scale * _gen(seed, stream).standard_normal((b, n))
+
+
+def smooth_field(N: int, seed: int = MASTER_SEED, stream: int = STREAM_TEST,
+                 modes: int = 4, amp: float = 0.5) -> np.ndarray:
+    """Nodal values of a random smooth trigonometric field (for tests only).
+
+    f(x, y) = sum_{a,b < modes} c_ab cos(pi a x) cos(pi b y) / (1 + a^2 + b^2)
+    with c_ab ~ N(0, amp^2).  Returned in node order k = j (N+1) + i.
+    """
+    g = _gen(seed, stream)
+    c = amp * g.standard_normal((modes, modes))
+    x = np.linspace(0.0, 1.0, N + 1)
+    X, Y = np.meshgrid(x, x)  # Y varies along rows: X[j, i] = x_i, Y[j, i] = y_j
+    f = np.zeros_like(X)
+    for a in range(modes):
+        for b in range(modes):
+            f += c[a, b] * np.cos(np.pi * a * X) * np.cos(np.pi * b * Y) / (1.0 + a * a + b * b)
+    return f.reshape(-1)
