@@ -1,0 +1,218 @@
+/*
+ * hinv.h -- C ABI of libhinv, Hessian actions for Bayesian inversion of the
+ * Poisson log-coefficient problem on MI355X (gfx950).
+ *
+ * The operations follow the problem statement of Villa, Petra & Ghattas,
+ * "hIPPYlib: an extensible software framework for large-scale inverse
+ * problems governed by PDEs; Part I" (ACM TOMS; arXiv:1909.03948):
+ *
+ *   forward   -div(e^m grad u) = 0 in (0,1)^2, u = 0 on y = 0, u = 1 on y = 1,
+ *             zero flux on x = 0, 1                     (Sec. 5.1, Eq. equ:poi)
+ *   cost      J(m) = 1/2 sigma^-2 |B u - d|^2 + 1/2 |m - m_pr|^2_R
+ *                                                       (Sec. 5.1, Eq. eq:cost-elliptic)
+ *   gradient  adjoint solve + g = R (m - m_pr) + C(u)^T p (App. A, Eqs. eq:firstadj,
+ *                                                        eq:firstcontrol)
+ *   Hessian   incremental forward / adjoint solves and the Hessian action
+ *             (App. A, Eqs. eq:incrementals1-3; Sec. 2.1, Eq. eq:abstract_hessianAction)
+ *   prior     R = K_A M^-1 K_A, K_A = gamma K + delta M + beta M_boundary
+ *             (Sec. 5.1, Eq. eq:PoissonPrior; Sec. 2.3), prior draws through the
+ *             rectangular mass factor (Sec. 4.3.1, Eq. eq:sample_prior; App. C)
+ *   MAP       inexact Newton-CG (Alg. 1)
+ *   low rank  double-pass randomized generalized eigensolver with PreCholQR
+ *             (Alg. 2, Alg. 4; Eq. eq:eigenproblem_1)
+ *   samples   y = (I - V S V^T R) x (Sec. 4.3.2, Eq. eq:sample_post)
+ *
+ * Discretization: P1 state and parameter on the N x N right-diagonal
+ * triangulation of the unit square; node k(i,j) = j (N+1) + i; the diagonal of
+ * cell (i,j) joins (i,j) and (i+1,j+1); triangle t = 2 (j N + i) + s, s = 0 for
+ * the lower and 1 for the upper triangle; e^m is integrated with the centroid
+ * rule, c_T = exp((m_a + m_r + m_b) / 3).
+ *
+ * Conventions
+ *   - Every function returns an int status (HINV_OK or a negative HINV_E*).
+ *     On error the detail string is available from hinv_last_error(ctx).
+ *   - Vector arguments are DEVICE pointers to FP64 data owned by the caller.
+ *     A vector of the parameter or state space has n = (N+1)^2 entries in node
+ *     order.  A multivector of nrhs columns is column-major with leading
+ *     dimension ld >= n (column c starts at ptr + c * ld).  The library never
+ *     frees or retains caller memory beyond the call.
+ *   - State-like vectors (u) hold their Dirichlet values; adjoint-like and
+ *     incremental vectors (p, uhat, phat) are zero on the Dirichlet nodes.
+ *   - All work is enqueued on the context's HIP stream.  Functions that return
+ *     host values (cost, info structs, eigenvalues) synchronize that stream.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - Iterative solves stop at |b - A x|_2 / |b|_2 <= rtol per column, the
+ *     residual evaluated in FP64.  A column that does not get there within the
+ *     iteration limit makes the call return HINV_ENOCONV; outputs are still
+ *     written and info->status holds the same code.
+ */
+#ifndef HINV_H
+#define HINV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HINV_OK        0
+#define HINV_EINVAL   -1   /* invalid argument (null pointer, bad size or mode) */
+#define HINV_ENOMEM   -2   /* device allocation failed */
+#define HINV_EHIP     -3   /* HIP runtime error */
+#define HINV_ENOCONV  -4   /* an iterative solve missed its tolerance */
+#define HINV_ESTATE   -5   /* call out of order (e.g. Hessian before hinv_linearize) */
+#define HINV_ENEGEIG  -6   /* eigenvalue <= -1 passed to the posterior sampler */
+#define HINV_EBREAK   -7   /* Cholesky breakdown in PreCholQR (rank-deficient probe block) */
+
+/* Hessian modes (App. A; Gauss-Newton per the footnote to Eq. eq:laplace_approx) */
+#define HINV_HESS_FULL       0  /* misfit + prior */
+#define HINV_HESS_MISFIT     1  /* data-misfit part only */
+#define HINV_HESS_GN_FULL    2  /* Gauss-Newton misfit + prior */
+#define HINV_HESS_GN_MISFIT  3  /* Gauss-Newton misfit only */
+
+/* solver precision */
+#define HINV_PREC_FP64     0  /* FP64 multigrid-preconditioned CG */
+#define HINV_PREC_FP32_IR  1  /* FP32 multigrid-PCG inside FP64 iterative refinement */
+
+/* precision of the T = Q^T (A Q) block product of the eigensolver */
+#define HINV_TPROD_FP64    0  /* FP64 matrix cores */
+#define HINV_TPROD_BF16    1  /* BF16 inputs, FP32 accumulation */
+
+typedef struct hinv_ctx hinv_ctx;
+typedef struct hinv_problem hinv_problem;
+
+typedef struct {
+    int    N;          /* cells per side, a power of two >= 4 */
+    double gamma;      /* prior diffusion weight (> 0) */
+    double delta;      /* prior reaction weight (> 0) */
+    double beta;       /* Robin coefficient; NaN selects sqrt(gamma*delta)/1.42 */
+    double m_prior;    /* constant prior mean */
+    int    q;          /* number of observations (>= 0) */
+    const double* obs_xy; /* HOST array [2q]: (x0, y0, x1, y1, ...) in [0,1]^2 */
+    const double* d_obs;  /* HOST array [q] of data, may be NULL (zeros) */
+    double sigma;      /* noise standard deviation (> 0) */
+    int    precision;  /* HINV_PREC_* for the state-equation solves */
+    double rtol;       /* relative residual of every solve, e.g. 1e-10 */
+    int    max_iter;   /* iteration cap per solve (0: 200) */
+} hinv_problem_desc;
+
+typedef struct {
+    int    status;        /* HINV_OK or HINV_ENOCONV */
+    int    solves;        /* number of solves (columns x systems) */
+    int    iterations;    /* total PCG iterations, all precisions and refinement steps */
+    int    refinements;   /* FP64 refinement steps */
+    int    fallbacks;     /* FP32_IR solves that switched to FP64 after stagnating */
+    double max_relres;    /* largest final FP64 relative residual over the solves */
+} hinv_solve_info;
+
+typedef struct {
+    double rel_tol;      /* stop when |g_i| <= rel_tol |g_0| (default 1e-6) */
+    double abs_tol;      /* ... or |g_i| <= abs_tol (default 0) */
+    int    max_iter;     /* Newton iterations (default 50) */
+    int    max_backtrack;/* Armijo backtracking steps (default 10) */
+    double c_armijo;     /* Armijo constant (default 1e-4) */
+    int    max_cg;       /* CG iterations per Newton step (default 500) */
+    int    gauss_newton; /* 1: Gauss-Newton Hessian in the CG */
+} hinv_newton_opts;
+
+#define HINV_NEWTON_MAXREC 64
+typedef struct {
+    int    status;        /* HINV_OK, HINV_ENOCONV (max_iter) or HINV_ESTATE (line search failed) */
+    int    iterations;    /* Newton iterations taken */
+    int    converged;
+    int    hessian_applies; /* total Hessian actions in the CG loops */
+    double cost[HINV_NEWTON_MAXREC + 1];
+    double gnorm[HINV_NEWTON_MAXREC + 1];
+    int    cg_iters[HINV_NEWTON_MAXREC];
+    double alpha[HINV_NEWTON_MAXREC];
+    hinv_solve_info solves; /* accumulated over all PDE solves */
+} hinv_newton_info;
+
+/* ---- context ------------------------------------------------------------- */
+/* Creates a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream). */
+int hinv_ctx_create(int device, void* hip_stream, hinv_ctx** out);
+int hinv_ctx_destroy(hinv_ctx* ctx);
+/* Switches the stream later calls enqueue on. */
+int hinv_ctx_set_stream(hinv_ctx* ctx, void* hip_stream);
+const char* hinv_last_error(const hinv_ctx* ctx);
+const char* hinv_status_string(int status);
+
+/* ---- problem -------------------------------------------------------------- */
+/* Builds mesh data, prior multigrid hierarchy and observation operator.
+ * Observation points are located in their cells on the device; the host only
+ * sorts the resulting node indices to build the transpose. */
+int hinv_problem_create(hinv_ctx* ctx, const hinv_problem_desc* d, hinv_problem** out);
+int hinv_problem_destroy(hinv_problem* p);
+/* n = (N+1)^2 */
+int hinv_problem_size(const hinv_problem* p, int* n);
+/* Replaces the data vector d (host array of q values) and/or sigma (> 0). */
+int hinv_set_data(hinv_problem* p, const double* d_obs_host, double sigma);
+/* Overrides precision and tolerance of the state-equation solves. */
+int hinv_set_solver(hinv_problem* p, int precision, double rtol, int max_iter);
+
+/* ---- forward problem and cost (Sec. 5.1) ----------------------------------- */
+/* u[n]: solution of the forward problem at m[n] (Dirichlet values included). */
+int hinv_forward(hinv_problem* p, const double* m, double* u, hinv_solve_info* info);
+/* Host outputs: misfit = 1/2 sigma^-2 |B u - d|^2, reg = 1/2 (m-m_pr)^T R (m-m_pr). */
+int hinv_cost(hinv_problem* p, const double* m, const double* u, double* misfit, double* reg);
+/* Observations B u (q values, device). */
+int hinv_observe(hinv_problem* p, const double* u, double* Bu);
+
+/* ---- adjoint and gradient (App. A) -------------------------------------- */
+/* p[n]: adjoint state; g[n]: gradient of J at m (u from hinv_forward). */
+int hinv_gradient(hinv_problem* p, const double* m, const double* u, double* adj, double* g,
+                  hinv_solve_info* info);
+
+/* ---- Hessian action (App. A) ---------------------------------------------- */
+/* Fixes the point (m, u, p) of later Hessian actions; builds the multigrid
+ * hierarchy of A(m). u and adj must be the forward and adjoint solutions at m. */
+int hinv_linearize(hinv_problem* p, const double* m, const double* u, const double* adj);
+/* Incremental forward: uhat[:,c] solves A uhat = -C(u) mhat[:,c] (Eq. eq:incrementals1). */
+int hinv_inc_forward(hinv_problem* p, int nrhs, const double* mhat, int ldm,
+                     double* uhat, int ldu, hinv_solve_info* info);
+/* Incremental adjoint: phat solves A phat = -(B^T B uhat / sigma^2 + C(p) mhat)
+ * (Eq. eq:incrementals2); gauss_newton = 1 drops C(p) mhat. */
+int hinv_inc_adjoint(hinv_problem* p, int nrhs, int gauss_newton, const double* mhat, int ldm,
+                     const double* uhat, int ldu, double* phat, int ldp, hinv_solve_info* info);
+/* out[:,c] = H mhat[:,c] in the given HINV_HESS_* mode (Eq. eq:incrementals3).
+ * All nrhs columns go through one batched multi-right-hand-side solve. */
+int hinv_hessian_apply(hinv_problem* p, int mode, int nrhs, const double* mhat, int ldm,
+                       double* out, int ldo, hinv_solve_info* info);
+
+/* ---- prior (Sec. 5.1, Sec. 2.3, Sec. 4.3.1) ------------------------------- */
+/* y = R x and y = R^{-1} x, column by column (all nrhs at once). */
+int hinv_prior_apply(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy);
+int hinv_prior_solve(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy,
+                     hinv_solve_info* info);
+/* out[:,s] = m_pr + K_A^{-1} C_M eta[:,s]: a draw from N(m_pr, R^{-1}).
+ * eta: device, ns columns of 6 N^2 i.i.d. N(0,1) values with leading dimension
+ * ldeta; entry 3 t + e sits at the midpoint of edge e of triangle t, edges
+ * e0 = (a, r), e1 = (r, b), e2 = (a, b) with r the right-angle vertex. */
+int hinv_prior_sample(hinv_problem* p, int ns, const double* eta, int ldeta, double* out, int ldo,
+                      hinv_solve_info* info);
+
+/* ---- MAP point (Alg. 1) ---------------------------------------------------- */
+/* m0 may be NULL (start from m_pr).  opts may be NULL (defaults).  On return
+ * the problem is linearized at m_map. */
+int hinv_map_newton(hinv_problem* p, const double* m0, double* m_map,
+                    const hinv_newton_opts* opts, hinv_newton_info* info);
+
+/* ---- low-rank posterior (Alg. 2, Alg. 4) --------------------------------- */
+/* Double-pass randomized eigensolver for H_misfit v = lambda R v at the current
+ * linearization point.  omega: device n x s block (s = k + oversampling).
+ * mode: HINV_HESS_MISFIT or HINV_HESS_GN_MISFIT.  tprod: HINV_TPROD_*.
+ * lambda: HOST array [k] (descending); V: device n x k, R-orthonormal. */
+int hinv_lowrank_eig(hinv_problem* p, int mode, int tprod, int s, const double* omega, int ldo,
+                     int k, double* lambda_host, double* V, int ldv, hinv_solve_info* info);
+/* out[:,j] = m_map + (I - V S V^T R) x_j with x_j = K_A^{-1} C_M eta[:,j] and
+ * S = diag(1 - (1 + lambda)^{-1/2}) (Eq. eq:sample_post).  lambda: HOST [k]. */
+int hinv_posterior_sample(hinv_problem* p, const double* m_map, int k, const double* lambda_host,
+                          const double* V, int ldv, int ns, const double* eta, int ldeta,
+                          double* out, int ldo, hinv_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HINV_H */

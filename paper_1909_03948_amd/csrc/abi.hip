@@ -1,0 +1,363 @@
+// extern "C" entry points of libhinv (declared and documented in include/hinv.h).
+// Each entry validates its arguments, runs the operation on the context's
+// stream and turns internal errors into status codes.
+#include <cmath>
+#include <new>
+
+#include "algos.h"
+#include "problem.h"
+
+struct hinv_ctx {
+    hinv::Ctx c;
+};
+
+struct hinv_problem {
+    hinv_ctx* owner;
+    std::unique_ptr<hinv::Problem> p;
+};
+
+namespace {
+
+thread_local std::string g_noctx_err;
+
+template <class F>
+int guarded(hinv::Ctx* c, F f) {
+    try {
+        f();
+        return HINV_OK;
+    } catch (const hinv::Error& e) {
+        if (c) c->err = e.msg;
+        else g_noctx_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        return HINV_ENOMEM;
+    } catch (const std::exception& e) {
+        if (c) c->err = e.what();
+        return HINV_EHIP;
+    }
+}
+
+void fill_info(hinv_solve_info* info, const hinv::SolveStats& s) {
+    if (!info) return;
+    info->status = s.converged ? HINV_OK : HINV_ENOCONV;
+    info->solves = s.solves;
+    info->iterations = s.iterations;
+    info->refinements = s.refinements;
+    info->fallbacks = s.fallbacks;
+    info->max_relres = s.max_relres;
+}
+
+int conv_status(const hinv::SolveStats& s) { return s.converged ? HINV_OK : HINV_ENOCONV; }
+
+#define REQUIRE(cond, msg) \
+    do {                   \
+        if (!(cond)) hinv::fail(HINV_EINVAL, msg); \
+    } while (0)
+
+hinv::Ctx* ctx_of(hinv_problem* p) { return p ? &p->owner->c : nullptr; }
+
+void set_device(hinv::Ctx* c) { HINV_HIP(hipSetDevice(c->device)); }
+
+}  // namespace
+
+extern "C" {
+
+const char* hinv_status_string(int s) {
+    switch (s) {
+        case HINV_OK: return "ok";
+        case HINV_EINVAL: return "invalid argument";
+        case HINV_ENOMEM: return "out of device memory";
+        case HINV_EHIP: return "HIP runtime error";
+        case HINV_ENOCONV: return "iterative solve did not reach its tolerance";
+        case HINV_ESTATE: return "call out of order";
+        case HINV_ENEGEIG: return "eigenvalue <= -1 passed to the posterior sampler";
+        case HINV_EBREAK: return "Cholesky breakdown in PreCholQR";
+        default: return "unknown status";
+    }
+}
+
+int hinv_ctx_create(int device, void* stream, hinv_ctx** out) {
+    if (!out) return HINV_EINVAL;
+    *out = nullptr;
+    hinv_ctx* c = new (std::nothrow) hinv_ctx;
+    if (!c) return HINV_ENOMEM;
+    const int rc = guarded(nullptr, [&] {
+        int ndev = 0;
+        HINV_HIP(hipGetDeviceCount(&ndev));
+        REQUIRE(device >= 0 && device < ndev, "no such HIP device");
+        c->c.device = device;
+        c->c.stream = (hipStream_t)stream;
+        HINV_HIP(hipSetDevice(device));
+    });
+    if (rc != HINV_OK) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return HINV_OK;
+}
+
+int hinv_ctx_destroy(hinv_ctx* c) {
+    if (!c) return HINV_EINVAL;
+    delete c;
+    return HINV_OK;
+}
+
+int hinv_ctx_set_stream(hinv_ctx* c, void* stream) {
+    if (!c) return HINV_EINVAL;
+    c->c.stream = (hipStream_t)stream;
+    return HINV_OK;
+}
+
+const char* hinv_last_error(const hinv_ctx* c) {
+    if (!c) return g_noctx_err.c_str();
+    return c->c.err.c_str();
+}
+
+int hinv_problem_create(hinv_ctx* c, const hinv_problem_desc* d, hinv_problem** out) {
+    if (!c || !d || !out) return HINV_EINVAL;
+    *out = nullptr;
+    return guarded(&c->c, [&] {
+        REQUIRE(d->N >= 4 && d->N <= 8192 && (d->N & (d->N - 1)) == 0,
+                "N must be a power of two in [4, 8192]");
+        REQUIRE(d->gamma > 0 && d->delta > 0, "gamma and delta must be positive");
+        REQUIRE(std::isnan(d->beta) || d->beta >= 0, "beta must be >= 0 or NaN");
+        REQUIRE(d->q >= 0, "q must be >= 0");
+        REQUIRE(d->q == 0 || d->obs_xy, "obs_xy is required when q > 0");
+        REQUIRE(d->sigma > 0, "sigma must be positive");
+        REQUIRE(d->precision == HINV_PREC_FP64 || d->precision == HINV_PREC_FP32_IR, "bad precision");
+        REQUIRE(d->rtol > 0 && d->rtol < 1, "rtol must be in (0, 1)");
+        for (int o = 0; o < d->q; ++o) {
+            const double x = d->obs_xy[2 * o], y = d->obs_xy[2 * o + 1];
+            REQUIRE(x >= 0 && x <= 1 && y >= 0 && y <= 1, "observation point outside [0,1]^2");
+        }
+        set_device(&c->c);
+        auto hp = std::make_unique<hinv_problem>();
+        hp->owner = c;
+        hp->p = std::make_unique<hinv::Problem>(&c->c, *d);
+        *out = hp.release();
+    });
+}
+
+int hinv_problem_destroy(hinv_problem* p) {
+    if (!p) return HINV_EINVAL;
+    delete p;
+    return HINV_OK;
+}
+
+int hinv_problem_size(const hinv_problem* p, int* n) {
+    if (!p || !n) return HINV_EINVAL;
+    *n = p->p->n;
+    return HINV_OK;
+}
+
+int hinv_set_data(hinv_problem* p, const double* d_obs, double sigma) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        REQUIRE(sigma > 0 || std::isnan(sigma), "sigma must be positive (or NaN to keep it)");
+        p->p->set_data(d_obs, std::isnan(sigma) ? -1.0 : sigma);
+    });
+}
+
+int hinv_set_solver(hinv_problem* p, int precision, double rtol, int max_iter) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        REQUIRE(precision == HINV_PREC_FP64 || precision == HINV_PREC_FP32_IR, "bad precision");
+        REQUIRE(rtol > 0 && rtol < 1, "rtol must be in (0, 1)");
+        p->p->precision = precision;
+        p->p->rtol = rtol;
+        p->p->max_iter = max_iter > 0 ? max_iter : 200;
+    });
+}
+
+int hinv_forward(hinv_problem* p, const double* m, double* u, hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        REQUIRE(m && u, "null vector");
+        p->p->forward(m, u, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_cost(hinv_problem* p, const double* m, const double* u, double* misfit, double* reg) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        REQUIRE(m && u && misfit && reg, "null argument");
+        p->p->cost(m, u, misfit, reg);
+    });
+}
+
+int hinv_observe(hinv_problem* p, const double* u, double* Bu) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        REQUIRE(u && (Bu || p->p->q == 0), "null argument");
+        p->p->observe(u, p->p->n, 1, Bu, p->p->q, false);
+    });
+}
+
+int hinv_gradient(hinv_problem* p, const double* m, const double* u, double* adj, double* g,
+                  hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        REQUIRE(m && u && adj && g, "null vector");
+        p->p->gradient(m, u, adj, g, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_linearize(hinv_problem* p, const double* m, const double* u, const double* adj) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        REQUIRE(m && u && adj, "null vector");
+        p->p->linearize(m, u, adj);
+    });
+}
+
+int hinv_inc_forward(hinv_problem* p, int nrhs, const double* mhat, int ldm, double* uhat, int ldu,
+                     hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(nrhs >= 0 && ldm >= n && ldu >= n, "bad size or leading dimension");
+        REQUIRE(nrhs == 0 || (mhat && uhat), "null vector");
+        if (nrhs) p->p->inc_forward(nrhs, mhat, ldm, uhat, ldu, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_inc_adjoint(hinv_problem* p, int nrhs, int gauss_newton, const double* mhat, int ldm,
+                     const double* uhat, int ldu, double* phat, int ldp, hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(nrhs >= 0 && ldm >= n && ldu >= n && ldp >= n, "bad size or leading dimension");
+        REQUIRE(nrhs == 0 || (mhat && uhat && phat), "null vector");
+        if (nrhs) p->p->inc_adjoint(nrhs, gauss_newton != 0, mhat, ldm, uhat, ldu, phat, ldp, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_hessian_apply(hinv_problem* p, int mode, int nrhs, const double* mhat, int ldm,
+                       double* out, int ldo, hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(mode >= HINV_HESS_FULL && mode <= HINV_HESS_GN_MISFIT, "bad Hessian mode");
+        REQUIRE(nrhs >= 0 && ldm >= n && ldo >= n, "bad size or leading dimension");
+        REQUIRE(nrhs == 0 || (mhat && out), "null vector");
+        if (nrhs) p->p->hessian(mode, nrhs, mhat, ldm, out, ldo, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_prior_apply(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(nrhs >= 0 && ldx >= n && ldy >= n, "bad size or leading dimension");
+        REQUIRE(nrhs == 0 || (x && y), "null vector");
+        if (nrhs) p->p->prior_apply(nrhs, x, ldx, y, ldy);
+    });
+}
+
+int hinv_prior_solve(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy,
+                     hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(nrhs >= 0 && ldx >= n && ldy >= n, "bad size or leading dimension");
+        REQUIRE(nrhs == 0 || (x && y), "null vector");
+        if (nrhs) p->p->prior_solve(nrhs, x, ldx, y, ldy, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_prior_sample(hinv_problem* p, int ns, const double* eta, int ldeta, double* out, int ldo,
+                      hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n, N = p->p->N;
+        REQUIRE(ns >= 0 && ldeta >= 6 * N * N && ldo >= n, "bad size or leading dimension");
+        REQUIRE(ns == 0 || (eta && out), "null vector");
+        if (ns) p->p->prior_sample(ns, eta, ldeta, out, ldo, true, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_map_newton(hinv_problem* p, const double* m0, double* m_map, const hinv_newton_opts* opts,
+                    hinv_newton_info* info) {
+    if (!p) return HINV_EINVAL;
+    int status = HINV_OK;
+    int rc = guarded(ctx_of(p), [&] {
+        REQUIRE(m_map, "null output");
+        hinv_newton_opts o;
+        o.rel_tol = 1e-6;
+        o.abs_tol = 0.0;
+        o.max_iter = 50;
+        o.max_backtrack = 10;
+        o.c_armijo = 1e-4;
+        o.max_cg = 500;
+        o.gauss_newton = 0;
+        if (opts) o = *opts;
+        REQUIRE(o.max_iter >= 0 && o.max_iter <= HINV_NEWTON_MAXREC, "max_iter out of range");
+        REQUIRE(o.max_backtrack >= 0 && o.max_cg >= 1, "bad Newton options");
+        hinv_newton_info tmp;
+        status = hinv::map_newton(*p->p, m0, m_map, o, info ? info : &tmp);
+    });
+    return rc != HINV_OK ? rc : status;
+}
+
+int hinv_lowrank_eig(hinv_problem* p, int mode, int tprod, int s, const double* omega, int ldo,
+                     int k, double* lambda_host, double* V, int ldv, hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int status = HINV_OK;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(mode == HINV_HESS_MISFIT || mode == HINV_HESS_GN_MISFIT, "mode must be a misfit mode");
+        REQUIRE(tprod == HINV_TPROD_FP64 || tprod == HINV_TPROD_BF16, "bad block-product precision");
+        REQUIRE(s >= 1 && s <= 512 && s <= n, "probe count s must be in [1, min(512, n)]");
+        REQUIRE(k >= 1 && k <= s, "k must be in [1, s]");
+        REQUIRE(ldo >= n && ldv >= n, "bad leading dimension");
+        REQUIRE(omega && lambda_host && V, "null argument");
+        status = hinv::lowrank_eig(*p->p, mode, tprod, s, omega, ldo, k, lambda_host, V, ldv, &st);
+    });
+    fill_info(info, st);
+    if (rc != HINV_OK) return rc;
+    if (status != HINV_OK) return status;
+    return conv_status(st);
+}
+
+int hinv_posterior_sample(hinv_problem* p, const double* m_map, int k, const double* lambda_host,
+                          const double* V, int ldv, int ns, const double* eta, int ldeta,
+                          double* out, int ldo, hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n, N = p->p->N;
+        REQUIRE(k >= 0 && ns >= 0 && ldv >= n && ldo >= n && ldeta >= 6 * N * N, "bad size");
+        REQUIRE(m_map && (k == 0 || (lambda_host && V)) && (ns == 0 || (eta && out)), "null argument");
+        for (int i = 0; i < k; ++i)
+            if (!(lambda_host[i] > -1.0)) hinv::fail(HINV_ENEGEIG, "eigenvalue <= -1");
+        if (ns) hinv::posterior_sample(*p->p, m_map, k, lambda_host, V, ldv, ns, eta, ldeta, out, ldo, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+}  // extern "C"

@@ -1,0 +1,22 @@
+// Host drivers of the paper's algorithms; all vector and matrix work runs in
+// device kernels, the host only makes the scalar decisions.
+#pragma once
+
+#include "problem.h"
+
+namespace hinv {
+
+// Inexact Newton-CG (Alg. 1).  Returns HINV_OK, HINV_ENOCONV or HINV_ESTATE.
+int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_opts& o,
+               hinv_newton_info* info);
+
+// Double-pass randomized generalized eigensolver (Alg. 2) with PreCholQR (Alg. 4).
+int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int ldo, int k,
+                double* lambda_host, double* V, int ldv, SolveStats* st);
+
+// Posterior samples through the low-rank update (Sec. 4.3.2).
+void posterior_sample(Problem& P, const double* m_map, int k, const double* lambda_host,
+                      const double* V, int ldv, int ns, const double* eta, int ldeta, double* out,
+                      int ldo, SolveStats* st);
+
+}  // namespace hinv

@@ -1,0 +1,253 @@
+// Drivers of the paper's algorithms on top of the device operations.
+#include <algorithm>
+#include <cmath>
+
+#include "algos.h"
+#include "dense.h"
+
+namespace hinv {
+
+namespace {
+
+__global__ void k_fill_cols(int n, double v, double* __restrict__ x) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) x[k] = v;
+}
+
+__global__ void k_post_scale(int k, const double* __restrict__ lam, double* __restrict__ s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) s[i] = 1.0 - 1.0 / sqrt(1.0 + lam[i]);
+}
+
+__global__ void k_add_vec(int n, const double* __restrict__ v, double* __restrict__ x, int ld) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) x[(size_t)blockIdx.y * ld + k] += v[k];
+}
+
+double nrm(Ctx* c, int n, const double* x) { return std::sqrt(dev_dot(c, n, x, x)); }
+
+}  // namespace
+
+// ------------------------------------------------------------ Newton-CG ---
+// Algorithm 1 with the readings: eta_i = min(0.5, sqrt(|g_i|/|g_0|)); CG
+// preconditioned by R^{-1}, started at zero, stopped at |H mhat + g| <= eta |g|
+// or at non-positive curvature (first iteration: take the preconditioned
+// steepest-descent direction); Armijo backtracking with step halving.
+int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_opts& o,
+               hinv_newton_info* info) {
+    Ctx* c = P.ctx;
+    const int n = P.n;
+    std::memset(info, 0, sizeof(*info));
+    DBuf<double> buf;
+    buf.ensure((size_t)n * 10);
+    double* m = m_map;
+    double* u = buf.get();
+    double* p = u + n;
+    double* g = p + n;
+    double* mh = g + n;
+    double* r = mh + n;
+    double* z = r + n;
+    double* d = z + n;
+    double* Hd = d + n;
+    double* mt = Hd + n;
+    double* ut = mt + n;
+    SolveStats st;
+    if (m0)
+        dev_copy(c, n, 1, m0, n, m, n);
+    else
+        dev_fill(c, n, P.m_prior, m);
+    P.forward(m, u, &st);
+    double mis, reg;
+    P.cost(m, u, &mis, &reg);
+    double J = mis + reg;
+    info->cost[0] = J;
+    const int hmode = o.gauss_newton ? HINV_HESS_GN_FULL : HINV_HESS_FULL;
+    double g0 = -1.0;
+    int status = HINV_ENOCONV;
+    int it = 0;
+    bool have_grad_at_m = false;
+    while (it < o.max_iter) {
+        P.gradient(m, u, p, g, &st);
+        have_grad_at_m = true;
+        const double gn = nrm(c, n, g);
+        info->gnorm[it] = gn;
+        if (g0 < 0) g0 = gn;
+        if (gn <= std::max(o.rel_tol * g0, o.abs_tol)) {
+            info->converged = 1;
+            status = HINV_OK;
+            break;
+        }
+        const double eta = std::min(0.5, std::sqrt(gn / g0));
+        P.linearize(m, u, p);
+        // --- CG on H mhat = -g ---
+        dev_fill(c, n, 0.0, mh);
+        dev_copy(c, n, 1, g, n, r, n);
+        dev_axpby(c, n, 0.0, g, -1.0, r);  // r = -g
+        P.prior_solve(1, r, n, z, n, &st);
+        dev_copy(c, n, 1, z, n, d, n);
+        double rz = dev_dot(c, n, r, z);
+        int ncg = 0;
+        for (int k = 0; k < o.max_cg; ++k) {
+            P.hessian(hmode, 1, d, n, Hd, n, &st);
+            ++info->hessian_applies;
+            ++ncg;
+            const double dHd = dev_dot(c, n, d, Hd);
+            if (!(dHd > 0.0)) {
+                if (k == 0) dev_copy(c, n, 1, d, n, mh, n);
+                break;
+            }
+            const double alpha = rz / dHd;
+            dev_axpby(c, n, alpha, d, 1.0, mh);
+            dev_axpby(c, n, -alpha, Hd, 1.0, r);
+            if (nrm(c, n, r) <= eta * gn) break;
+            P.prior_solve(1, r, n, z, n, &st);
+            const double rzn = dev_dot(c, n, r, z);
+            dev_axpby(c, n, 1.0, z, rzn / rz, d);  // d = z + beta d
+            rz = rzn;
+        }
+        info->cg_iters[it] = ncg;
+        // --- Armijo backtracking ---
+        const double gm = dev_dot(c, n, g, mh);
+        double alpha = 1.0;
+        bool accepted = false;
+        for (int j = 0; j < o.max_backtrack; ++j) {
+            dev_copy(c, n, 1, m, n, mt, n);
+            dev_axpby(c, n, alpha, mh, 1.0, mt);
+            // a trial point whose forward solve misses its tolerance is rejected
+            SolveStats trial;
+            P.forward(mt, ut, &trial);
+            const bool solved = trial.converged;
+            trial.converged = true;  // counted, but a failed trial does not fail the run
+            st.add(trial);
+            double mt_mis, mt_reg;
+            P.cost(mt, ut, &mt_mis, &mt_reg);
+            const double Jt = mt_mis + mt_reg;
+            if (solved && Jt < J + alpha * o.c_armijo * gm) {
+                dev_copy(c, n, 1, mt, n, m, n);
+                dev_copy(c, n, 1, ut, n, u, n);
+                J = Jt;
+                accepted = true;
+                break;
+            }
+            alpha *= 0.5;
+        }
+        info->alpha[it] = alpha;
+        info->cost[it + 1] = J;
+        have_grad_at_m = false;
+        ++it;
+        if (!accepted) {
+            status = HINV_ESTATE;
+            break;
+        }
+    }
+    info->iterations = it;
+    // leave the problem linearized at the returned point
+    if (!have_grad_at_m) {
+        P.gradient(m, u, p, g, &st);
+        if (it <= HINV_NEWTON_MAXREC) info->gnorm[it] = nrm(c, n, g);
+    }
+    P.linearize(m, u, p);
+    HINV_HIP(hipStreamSynchronize(c->stream));
+    info->status = status;
+    info->solves.status = st.converged ? HINV_OK : HINV_ENOCONV;
+    info->solves.solves = st.solves;
+    info->solves.iterations = st.iterations;
+    info->solves.refinements = st.refinements;
+    info->solves.fallbacks = st.fallbacks;
+    info->solves.max_relres = st.max_relres;
+    if (status == HINV_OK && !st.converged) status = HINV_ENOCONV;
+    return status;
+}
+
+// ------------------------------------------------------- double pass ---
+namespace {
+
+// Orthonormal basis Z of span(Y) (the qr(Y) step of Algorithm 4) by shifted
+// CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Zhang, Yamamoto 2020): one
+// Cholesky QR on the Gram matrix shifted by 11 (n s + s (s+1)) u tr(Y^T Y),
+// then two plain Cholesky QR passes.  Y is overwritten by Z.
+bool orthonormalize(Ctx* c, DenseWork& w, int n, int s, double* Y, double* tmp, double* G,
+                    double* Ri) {
+    for (int pass = 0; pass < 3; ++pass) {
+        gram(c, w, n, s, s, Y, n, Y, n, G, s);
+        double shift = 0.0;
+        if (pass == 0) {
+            const double tr = trace(c, w, s, G, s);
+            shift = 11.0 * ((double)n * s + (double)s * (s + 1)) * 1.1102230246251565e-16 * tr;
+        }
+        if (!cholesky_upper(c, w, s, G, s, shift)) return false;
+        tri_inverse_upper(c, s, G, s, Ri, s);
+        gemm_tall(c, n, s, s, 1.0, Y, n, Ri, s, 0.0, tmp, n);
+        dev_copy(c, n, s, tmp, n, Y, n);
+    }
+    return true;
+}
+
+}  // namespace
+
+int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int ldo, int k,
+                double* lambda_host, double* V, int ldv, SolveStats* st) {
+    Ctx* c = P.ctx;
+    const int n = P.n;
+    DBuf<double> big, small;
+    big.ensure((size_t)n * s * 3);
+    small.ensure((size_t)s * s * 4 + s);
+    double* Y = big.get();
+    double* Zb = Y + (size_t)n * s;
+    double* W = Zb + (size_t)n * s;
+    double* G = small.get();
+    double* Ri = G + (size_t)s * s;
+    double* T = Ri + (size_t)s * s;
+    double* S = T + (size_t)s * s;
+    double* lam = S + (size_t)s * s;
+    DenseWork dw;
+    // pass 1: Ybar = A Omega, Y = B^-1 Ybar  (A = H_misfit, B = R)
+    P.hessian(mode, s, omega, ldo, W, n, st);
+    P.prior_solve(s, W, n, Y, n, st);
+    // PreCholQR (Algorithm 4)
+    if (!orthonormalize(c, dw, n, s, Y, W, G, Ri)) return HINV_EBREAK;  // Y <- Z
+    P.prior_apply(s, Y, n, Zb, n);                                         // Zbar = B Z
+    gram(c, dw, n, s, s, Y, n, Zb, n, G, s);                               // Z^T Zbar
+    if (!cholesky_upper(c, dw, s, G, s, 0.0)) return HINV_EBREAK;          // R_Z
+    tri_inverse_upper(c, s, G, s, Ri, s);
+    gemm_tall(c, n, s, s, 1.0, Y, n, Ri, s, 0.0, W, n);                    // Q = Z R_Z^-1
+    // pass 2: T = Q^T A Q
+    P.hessian(mode, s, W, n, Zb, n, st);
+    gram(c, dw, n, s, s, W, n, Zb, n, T, s, tprod == HINV_TPROD_BF16);
+    sym_eig(c, dw, s, T, s, S, s, lam);
+    gemm_tall(c, n, s, k, 1.0, W, n, S, s, 0.0, V, ldv);                   // V = Q S_k
+    HINV_HIP(hipMemcpyAsync(lambda_host, lam, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    HINV_HIP(hipStreamSynchronize(c->stream));
+    return HINV_OK;
+}
+
+// ------------------------------------------------------ posterior sample ---
+void posterior_sample(Problem& P, const double* m_map, int k, const double* lambda_host,
+                      const double* V, int ldv, int ns, const double* eta, int ldeta, double* out,
+                      int ldo, SolveStats* st) {
+    Ctx* c = P.ctx;
+    const int n = P.n;
+    DBuf<double> Wk, small;
+    // x = K_A^-1 C_M eta (zero-mean prior draws)
+    P.prior_sample(ns, eta, ldeta, out, ldo, false, st);
+    if (k > 0) {
+        Wk.ensure((size_t)n * k);
+        small.ensure((size_t)k * ns + 2 * (size_t)k);
+        double* C = small.get();
+        double* lam = C + (size_t)k * ns;
+        double* sc = lam + k;
+        P.prior_apply(k, V, ldv, Wk.get(), n);                 // W = R V
+        DenseWork dw;
+        gram(c, dw, n, k, ns, Wk.get(), n, out, ldo, C, k);     // W^T x = V^T R x
+        HINV_HIP(hipMemcpyAsync(lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+        k_post_scale<<<ceil_div(k, 256), 256, 0, c->stream>>>(k, lam, sc);
+        HINV_LAUNCH_CHECK();
+        scale_rows(c, k, ns, sc, C, k);                        // S V^T R x
+        gemm_tall(c, n, k, ns, -1.0, V, ldv, C, k, 1.0, out, ldo);  // x - V S V^T R x
+    }
+    k_add_vec<<<dim3(ceil_div(n, 256), ns), 256, 0, c->stream>>>(n, m_map, out, ldo);
+    HINV_LAUNCH_CHECK();
+    HINV_HIP(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace hinv

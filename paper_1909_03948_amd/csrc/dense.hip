@@ -1,0 +1,412 @@
+// Dense kernels: matrix-core tall-skinny products and one-workgroup s x s
+// factorizations (s = k + oversampling <= 512).
+//
+// Matrix-core operand layouts (wave64), checked on the device:
+//   f64 16x16x4:   A (16 x 4): lane l holds A[l % 16][l / 16]
+//                  B (4 x 16): lane l holds B[l / 16][l % 16]
+//                  D (16 x 16): lane l, item v holds D[4 v + l / 16][l % 16]
+//   bf16 16x16x16: A: lane l holds A[l % 16][4 (l / 16) + e], e = 0..3
+//                  B: lane l holds B[4 (l / 16) + e][l % 16]
+//                  D: lane l, item v holds D[4 (l / 16) + v][l % 16]
+#include <algorithm>
+
+#include "dense.h"
+
+namespace hinv {
+
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline short to_bf16(double x) {
+    // round-to-nearest-even of the float value
+    const float f = (float)x;
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+constexpr int kWaves = 4;  // waves per workgroup in the block-product kernels
+
+// Split-K Gram: grid.x = output tile (16 x 16), grid.y = K chunk.
+// Each of the 4 waves walks every 4th group of 4 rows of the chunk.
+__global__ __launch_bounds__(256) void k_gram_f64(int n, int s1, int s2, int chunk,
+                                                  const double* __restrict__ X, int ldx,
+                                                  const double* __restrict__ Y, int ldy,
+                                                  double* __restrict__ part) {
+    const int tiles_i = (s1 + 15) / 16;
+    const int ti = blockIdx.x % tiles_i, tj = blockIdx.x / tiles_i;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = ti * 16 + (lane & 15), j = tj * 16 + (lane & 15);
+    const int kr = lane >> 4;
+    const int k_begin = blockIdx.y * chunk;
+    const int k_end = min(n, k_begin + chunk);
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
+    const double* yc = Y + (size_t)(j < s2 ? j : 0) * ldy;
+    for (int k0 = k_begin + wave * 4; k0 < k_end; k0 += 4 * kWaves) {
+        const int k = k0 + kr;
+        const double a = (i < s1 && k < k_end) ? xc[k] : 0.0;
+        const double b = (j < s2 && k < k_end) ? yc[k] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    __shared__ double red[kWaves][16][16];
+    for (int v = 0; v < 4; ++v) red[wave][4 * v + (lane >> 4)][lane & 15] = acc[v];
+    __syncthreads();
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;  // 256 threads = 16 x 16
+    double sum = 0.0;
+    for (int w = 0; w < kWaves; ++w) sum += red[w][r][c];
+    const int gi = ti * 16 + r, gj = tj * 16 + c;
+    if (gi < s1 && gj < s2) part[((size_t)blockIdx.y * s2 + gj) * s1 + gi] = sum;
+}
+
+__global__ __launch_bounds__(256) void k_gram_bf16(int n, int s1, int s2, int chunk,
+                                                   const double* __restrict__ X, int ldx,
+                                                   const double* __restrict__ Y, int ldy,
+                                                   double* __restrict__ part) {
+    const int tiles_i = (s1 + 15) / 16;
+    const int ti = blockIdx.x % tiles_i, tj = blockIdx.x / tiles_i;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = ti * 16 + (lane & 15), j = tj * 16 + (lane & 15);
+    const int kq = (lane >> 4) * 4;
+    const int k_begin = blockIdx.y * chunk;
+    const int k_end = min(n, k_begin + chunk);
+    f4_t acc = {0.f, 0.f, 0.f, 0.f};
+    const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
+    const double* yc = Y + (size_t)(j < s2 ? j : 0) * ldy;
+    for (int k0 = k_begin + wave * 16; k0 < k_end; k0 += 16 * kWaves) {
+        s4_t a, b;
+        for (int e = 0; e < 4; ++e) {
+            const int k = k0 + kq + e;
+            a[e] = to_bf16((i < s1 && k < k_end) ? xc[k] : 0.0);
+            b[e] = to_bf16((j < s2 && k < k_end) ? yc[k] : 0.0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    __shared__ float red[kWaves][16][16];
+    for (int v = 0; v < 4; ++v) red[wave][4 * (lane >> 4) + v][lane & 15] = acc[v];
+    __syncthreads();
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    double sum = 0.0;
+    for (int w = 0; w < kWaves; ++w) sum += (double)red[w][r][c];
+    const int gi = ti * 16 + r, gj = tj * 16 + c;
+    if (gi < s1 && gj < s2) part[((size_t)blockIdx.y * s2 + gj) * s1 + gi] = sum;
+}
+
+__global__ void k_gram_reduce(int s1, int s2, int nsplit, const double* __restrict__ part,
+                              double* __restrict__ C, int ldc) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= s1 * s2) return;
+    const int i = id % s1, j = id / s1;
+    double s = 0.0;
+    for (int p = 0; p < nsplit; ++p) s += part[((size_t)p * s2 + j) * s1 + i];
+    C[i + (size_t)j * ldc] = s;
+}
+
+// C = alpha X B + beta C; grid.x: 16-row strips (4 per workgroup), grid.y: 16-column tiles.
+__global__ __launch_bounds__(256) void k_gemm_tall(int n, int s, int t, double alpha,
+                                                   const double* __restrict__ X, int ldx,
+                                                   const double* __restrict__ B, int ldb,
+                                                   double beta, double* __restrict__ C, int ldc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = (blockIdx.x * kWaves + wave) * 16;
+    if (r0 >= n) return;
+    const int c0 = blockIdx.y * 16;
+    const int row = r0 + (lane & 15), colb = c0 + (lane & 15), kr = lane >> 4;
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < s; k0 += 4) {
+        const int k = k0 + kr;
+        const double a = (row < n && k < s) ? X[(size_t)k * ldx + row] : 0.0;
+        const double b = (colb < t && k < s) ? B[k + (size_t)colb * ldb] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    const int cc = c0 + (lane & 15);
+    if (cc >= t) return;
+    for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + 4 * v + (lane >> 4);
+        if (rr < n) {
+            double* dst = C + (size_t)cc * ldc + rr;
+            *dst = alpha * acc[v] + (beta != 0.0 ? beta * *dst : 0.0);
+        }
+    }
+}
+
+// Upper Cholesky in place, one workgroup; A(a, c) = A[a + c lda].
+__global__ void k_cholesky(int s, double* __restrict__ A, int lda, double shift, int* __restrict__ flag) {
+    __shared__ double rj;
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    for (int i = threadIdx.x; i < s; i += blockDim.x) A[i + (size_t)i * lda] += shift;
+    __syncthreads();
+    for (int j = 0; j < s; ++j) {
+        if (threadIdx.x == 0) {
+            const double piv = A[j + (size_t)j * lda];
+            if (!(piv > 0.0)) bad = 1;
+            rj = bad ? 1.0 : sqrt(piv);
+            A[j + (size_t)j * lda] = rj;
+        }
+        __syncthreads();
+        if (bad) break;
+        for (int c = j + 1 + threadIdx.x; c < s; c += blockDim.x) A[j + (size_t)c * lda] /= rj;
+        __syncthreads();
+        const int m = s - j - 1;
+        for (int id = threadIdx.x; id < m * m; id += blockDim.x) {
+            const int a = j + 1 + id % m, c = j + 1 + id / m;
+            if (a <= c) A[a + (size_t)c * lda] -= A[j + (size_t)a * lda] * A[j + (size_t)c * lda];
+        }
+        __syncthreads();
+    }
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
+        const int a = id % s, c = id / s;
+        if (a > c) A[a + (size_t)c * lda] = 0.0;
+    }
+    if (threadIdx.x == 0) *flag = bad;
+}
+
+// Rinv = R^-1 (upper), column by column, one workgroup.
+__global__ void k_tri_inverse(int s, const double* __restrict__ R, int ldr, double* __restrict__ Ri, int ldi) {
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) Ri[id % s + (size_t)(id / s) * ldi] = 0.0;
+    __syncthreads();
+    for (int j = 0; j < s; ++j) {
+        const double rjj = R[j + (size_t)j * ldr];
+        for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+            double v;
+            if (i == j) {
+                v = 1.0 / rjj;
+            } else {
+                double acc = 0.0;
+                for (int k = i; k < j; ++k) acc += Ri[i + (size_t)k * ldi] * R[k + (size_t)j * ldr];
+                v = -acc / rjj;
+            }
+            Ri[i + (size_t)j * ldi] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Parallel cyclic Jacobi (round-robin pairing), one workgroup.
+__global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restrict__ S, int lds,
+                         int max_sweeps) {
+    const int m = s + (s & 1);
+    const int np = m / 2;
+    __shared__ double cs[256], sn[256];
+    __shared__ int pp[256], qq[256];
+    __shared__ double offn, totn;
+    __shared__ double wsum[32];
+    // symmetrize, S = I
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
+        const int a = id % s, c = id / s;
+        if (a < c) {
+            const double v = 0.5 * (T[a + (size_t)c * ldt] + T[c + (size_t)a * ldt]);
+            T[a + (size_t)c * ldt] = v;
+            T[c + (size_t)a * ldt] = v;
+        }
+        S[a + (size_t)c * lds] = a == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        // off-diagonal and total Frobenius norms
+        double o = 0.0, t = 0.0;
+        for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
+            const int a = id % s, c = id / s;
+            const double v = T[a + (size_t)c * ldt];
+            t += v * v;
+            if (a != c) o += v * v;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            o += __shfl_xor(o, off, 64);
+            t += __shfl_xor(t, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            wsum[threadIdx.x >> 6] = o;
+            wsum[16 + (threadIdx.x >> 6)] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double so = 0.0, st = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                so += wsum[w];
+                st += wsum[16 + w];
+            }
+            offn = so;
+            totn = st;
+        }
+        __syncthreads();
+        if (offn <= 1e-30 * totn || totn == 0.0) break;
+        for (int step = 0; step < m - 1; ++step) {
+            for (int k = threadIdx.x; k < np; k += blockDim.x) {
+                int p, q;
+                if (k == 0) {
+                    p = step;
+                    q = m - 1;
+                } else {
+                    p = (step + k) % (m - 1);
+                    q = (step - k + (m - 1)) % (m - 1);
+                }
+                if (p > q) {
+                    const int tmp = p;
+                    p = q;
+                    q = tmp;
+                }
+                double c = 1.0, sv = 0.0;
+                if (q < s) {
+                    const double apq = T[p + (size_t)q * ldt];
+                    if (apq != 0.0) {
+                        const double th = (T[q + (size_t)q * ldt] - T[p + (size_t)p * ldt]) / (2.0 * apq);
+                        const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        sv = tt * c;
+                    }
+                }
+                pp[k] = p;
+                qq[k] = q;
+                cs[k] = c;
+                sn[k] = sv;
+            }
+            __syncthreads();
+            // rows p, q  <- J^T T
+            for (int id = threadIdx.x; id < np * s; id += blockDim.x) {
+                const int k = id % np, c = id / np;
+                const int p = pp[k], q = qq[k];
+                if (q >= s) continue;
+                const double tp = T[p + (size_t)c * ldt], tq = T[q + (size_t)c * ldt];
+                T[p + (size_t)c * ldt] = cs[k] * tp - sn[k] * tq;
+                T[q + (size_t)c * ldt] = sn[k] * tp + cs[k] * tq;
+            }
+            __syncthreads();
+            // columns p, q  <- T J, S J
+            for (int id = threadIdx.x; id < np * s; id += blockDim.x) {
+                const int k = id % np, r = id / np;
+                const int p = pp[k], q = qq[k];
+                if (q >= s) continue;
+                const double tp = T[r + (size_t)p * ldt], tq = T[r + (size_t)q * ldt];
+                T[r + (size_t)p * ldt] = cs[k] * tp - sn[k] * tq;
+                T[r + (size_t)q * ldt] = sn[k] * tp + cs[k] * tq;
+                const double sp = S[r + (size_t)p * lds], sq = S[r + (size_t)q * lds];
+                S[r + (size_t)p * lds] = cs[k] * sp - sn[k] * sq;
+                S[r + (size_t)q * lds] = sn[k] * sp + cs[k] * sq;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Sorts the eigenpairs by decreasing eigenvalue: column c of S goes to column
+// rank(c) of Sout, and lam[rank(c)] = lam_unsorted[c] (ties keep index order).
+__global__ void k_eig_permute(int s, const double* __restrict__ lam_unsorted, const double* __restrict__ S,
+                              int lds, double* __restrict__ Sout, int ldo, double* __restrict__ lam) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= s * s) return;
+    const int r = id % s, c = id / s;
+    const double lc = lam_unsorted[c];
+    int rank = 0;
+    for (int j = 0; j < s; ++j) {
+        const double lj = lam_unsorted[j];
+        rank += (lj > lc) || (lj == lc && j < c);
+    }
+    Sout[r + (size_t)rank * ldo] = S[r + (size_t)c * lds];
+    if (r == 0) lam[rank] = lc;
+}
+
+__global__ void k_diag_copy(int s, const double* __restrict__ T, int ldt, double* __restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < s) d[i] = T[i + (size_t)i * ldt];
+}
+
+__global__ void k_trace(int s, const double* __restrict__ A, int lda, double* __restrict__ out) {
+    __shared__ double w[16];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < s; i += blockDim.x) v += A[i + (size_t)i * lda];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += w[k];
+        *out = t;
+    }
+}
+
+__global__ void k_scale_rows(int s, int t, const double* __restrict__ d, double* __restrict__ B, int ldb) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= s * t) return;
+    const int i = id % s, j = id / s;
+    B[i + (size_t)j * ldb] *= d[i];
+}
+
+}  // namespace
+
+void gram(Ctx* ctx, DenseWork& w, int n, int s1, int s2, const double* X, int ldx, const double* Y,
+          int ldy, double* C, int ldc, bool bf16) {
+    const int tiles = ((s1 + 15) / 16) * ((s2 + 15) / 16);
+    const int unit = bf16 ? 16 * kWaves : 4 * kWaves;
+    int nsplit = std::max(1, std::min(ceil_div(4096, 4 * tiles), ceil_div(n, 4 * unit)));
+    int chunk = ceil_div(ceil_div(n, nsplit), unit) * unit;
+    nsplit = ceil_div(n, chunk);
+    w.part.ensure((size_t)nsplit * s1 * s2);
+    if (bf16)
+        k_gram_bf16<<<dim3(tiles, nsplit), 256, 0, ctx->stream>>>(n, s1, s2, chunk, X, ldx, Y, ldy,
+                                                                 w.part.get());
+    else
+        k_gram_f64<<<dim3(tiles, nsplit), 256, 0, ctx->stream>>>(n, s1, s2, chunk, X, ldx, Y, ldy,
+                                                                w.part.get());
+    HINV_LAUNCH_CHECK();
+    k_gram_reduce<<<ceil_div(s1 * s2, 256), 256, 0, ctx->stream>>>(s1, s2, nsplit, w.part.get(), C, ldc);
+    HINV_LAUNCH_CHECK();
+}
+
+void gemm_tall(Ctx* ctx, int n, int s, int t, double alpha, const double* X, int ldx,
+               const double* B, int ldb, double beta, double* C, int ldc) {
+    if (n <= 0 || t <= 0) return;
+    const dim3 g(ceil_div(ceil_div(n, 16), kWaves), ceil_div(t, 16));
+    k_gemm_tall<<<g, 256, 0, ctx->stream>>>(n, s, t, alpha, X, ldx, B, ldb, beta, C, ldc);
+    HINV_LAUNCH_CHECK();
+}
+
+bool cholesky_upper(Ctx* ctx, DenseWork& w, int s, double* A, int lda, double shift) {
+    w.flag.ensure(1);
+    k_cholesky<<<1, 1024, 0, ctx->stream>>>(s, A, lda, shift, w.flag.get());
+    HINV_LAUNCH_CHECK();
+    int bad = 0;
+    HINV_HIP(hipMemcpyAsync(&bad, w.flag.get(), sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HINV_HIP(hipStreamSynchronize(ctx->stream));
+    return bad == 0;
+}
+
+void tri_inverse_upper(Ctx* ctx, int s, const double* R, int ldr, double* Rinv, int ldi) {
+    k_tri_inverse<<<1, 1024, 0, ctx->stream>>>(s, R, ldr, Rinv, ldi);
+    HINV_LAUNCH_CHECK();
+}
+
+void sym_eig(Ctx* ctx, DenseWork& w, int s, double* T, int ldt, double* S, int lds, double* lam) {
+    if (s > 512) fail(HINV_EINVAL, "eigenproblem larger than 512");
+    w.part.ensure((size_t)s * s + s);
+    double* Stmp = w.part.get();
+    double* lam_u = Stmp + (size_t)s * s;
+    k_jacobi<<<1, 1024, 0, ctx->stream>>>(s, T, ldt, Stmp, s, 40);
+    HINV_LAUNCH_CHECK();
+    k_diag_copy<<<ceil_div(s, 256), 256, 0, ctx->stream>>>(s, T, ldt, lam_u);
+    HINV_LAUNCH_CHECK();
+    k_eig_permute<<<ceil_div(s * s, 256), 256, 0, ctx->stream>>>(s, lam_u, Stmp, s, S, lds, lam);
+    HINV_LAUNCH_CHECK();
+}
+
+double trace(Ctx* ctx, DenseWork& w, int s, const double* A, int lda) {
+    w.part.ensure(1);
+    k_trace<<<1, 1024, 0, ctx->stream>>>(s, A, lda, w.part.get());
+    HINV_LAUNCH_CHECK();
+    double t = 0.0;
+    HINV_HIP(hipMemcpyAsync(&t, w.part.get(), sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HINV_HIP(hipStreamSynchronize(ctx->stream));
+    return t;
+}
+
+void scale_rows(Ctx* ctx, int s, int t, const double* d, double* B, int ldb) {
+    if (s * t == 0) return;
+    k_scale_rows<<<ceil_div(s * t, 256), 256, 0, ctx->stream>>>(s, t, d, B, ldb);
+    HINV_LAUNCH_CHECK();
+}
+
+}  // namespace hinv

@@ -1,0 +1,157 @@
+// Device-side stencil operators on the structured right-diagonal mesh and
+// block reductions, shared by the solver and problem translation units.
+#pragma once
+
+#include "common.h"
+
+namespace hinv {
+
+// ------------------------------------------------------------ reductions ---
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over a workgroup of kBlock threads, fixed order; result valid in thread 0.
+// Call at most once per kernel (the LDS slot is not reused).
+__device__ inline double block_sum(double v) {
+    __shared__ double part[kBlock / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) part[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) r += part[i];
+    return r;
+}
+
+// ------------------------------------------------------- state operator ---
+// A(m) restricted to the free nodes (0 < j < N): the P1 stiffness with the
+// per-triangle coefficient c_T is a five-point stencil on this mesh (the
+// diagonal edge is opposite a right angle).  wE[k] is the weight of edge
+// (i,j)-(i+1,j) = (c_lower(i,j) + c_upper(i,j-1)) / 2, wN[k] the weight of edge
+// (i,j)-(i,j+1) = (c_upper(i,j) + c_lower(i-1,j)) / 2 (absent triangles count
+// zero); the diagonal is the sum of the four incident edge weights.
+template <typename T>
+struct OpA {
+    int N;
+    const T* wE;
+    const T* wN;
+    const T* dinv;  // 1 / diagonal on free nodes, 0 on Dirichlet nodes
+    __device__ bool is_free(int, int j) const { return j > 0 && j < N; }
+    __device__ T inv_diag(int, int, int k) const { return dinv[k]; }
+    // Row k of A_FF applied to the vector given by xat(i, j, k); call on free nodes only.
+    template <class F>
+    __device__ T apply(int i, int j, int k, F xat) const {
+        T s = 0, d = 0;
+        if (i < N) {
+            const T w = wE[k];
+            d += w;
+            s += w * xat(i + 1, j, k + 1);
+        }
+        if (i > 0) {
+            const T w = wE[k - 1];
+            d += w;
+            s += w * xat(i - 1, j, k - 1);
+        }
+        {
+            const T w = wN[k];
+            d += w;
+            if (j + 1 < N) s += w * xat(i, j + 1, k + N + 1);
+        }
+        {
+            const T w = wN[k - N - 1];
+            d += w;
+            if (j - 1 > 0) s += w * xat(i, j - 1, k - N - 1);
+        }
+        return d * xat(i, j, k) - s;
+    }
+};
+
+// ------------------------------------------------------- prior operator ---
+// K_A = g K + dl M + bt M_boundary with Theta = I (every node is a dof).
+// K: unit five-point stiffness (edge weight = number of adjacent triangles / 2).
+// M: P1 mass, |T|/12 (1 + delta_vw) per triangle, |T| = h^2/2; couples the
+//    four axis neighbours and the two diagonal neighbours (i+-1, j+-1).
+// M_boundary: (h/6) [[2,1],[1,2]] on every boundary edge.
+// Coefficients are computed on the fly from (i, j): no storage, no traffic.
+template <typename T>
+struct OpKA {
+    int N;
+    double h, g, dl, bt;
+    __device__ bool is_free(int, int) const { return true; }
+    struct Row {
+        double c, e, w, n, s, ne, sw;
+    };
+    __device__ Row row(int i, int j) const {
+        const double h2 = h * h;
+        const int hasE = i < N, hasW = i > 0, hasN = j < N, hasS = j > 0;
+        const int jin = (j < N) + (j > 0);  // triangles on a horizontal edge at row j
+        const int iin = (i < N) + (i > 0);  // triangles on a vertical edge at column i
+        const int bh = (j == 0 || j == N);  // horizontal edges at row j are boundary edges
+        const int bv = (i == 0 || i == N);  // vertical edges at column i are boundary edges
+        Row r;
+        const double eh = -g * 0.5 * jin + dl * jin * h2 / 24.0 + bt * (h / 6.0) * bh;
+        const double ev = -g * 0.5 * iin + dl * iin * h2 / 24.0 + bt * (h / 6.0) * bv;
+        r.e = hasE ? eh : 0.0;
+        r.w = hasW ? eh : 0.0;
+        r.n = hasN ? ev : 0.0;
+        r.s = hasS ? ev : 0.0;
+        r.ne = (hasE && hasN) ? dl * h2 / 12.0 : 0.0;
+        r.sw = (hasW && hasS) ? dl * h2 / 12.0 : 0.0;
+        const int ntri = 2 * (hasE && hasN) + (hasW && hasN) + (hasE && hasS) + 2 * (hasW && hasS);
+        const int nbe = bh * (hasE + hasW) + bv * (hasN + hasS);
+        r.c = g * 0.5 * (jin * (hasE + hasW) + iin * (hasN + hasS)) + dl * ntri * h2 / 12.0 +
+              bt * (h / 3.0) * nbe;
+        return r;
+    }
+    __device__ T inv_diag(int i, int j, int) const { return (T)(1.0 / row(i, j).c); }
+    template <class F>
+    __device__ T apply(int i, int j, int k, F xat) const {
+        const Row r = row(i, j);
+        const int N1 = N + 1;
+        T acc = (T)r.c * xat(i, j, k);
+        if (i < N) acc += (T)r.e * xat(i + 1, j, k + 1);
+        if (i > 0) acc += (T)r.w * xat(i - 1, j, k - 1);
+        if (j < N) acc += (T)r.n * xat(i, j + 1, k + N1);
+        if (j > 0) acc += (T)r.s * xat(i, j - 1, k - N1);
+        if (i < N && j < N) acc += (T)r.ne * xat(i + 1, j + 1, k + N1 + 1);
+        if (i > 0 && j > 0) acc += (T)r.sw * xat(i - 1, j - 1, k - N1 - 1);
+        return acc;
+    }
+};
+
+// ------------------------------------------------------------ triangles ---
+// Node indices (a, r, b) of triangle s (0 lower, 1 upper) of cell (ci, cj).
+__device__ inline void tri_nodes(int N, int ci, int cj, int s, int& ka, int& kr, int& kb) {
+    ka = knode(ci, cj, N);
+    kb = knode(ci + 1, cj + 1, N);
+    kr = s == 0 ? knode(ci + 1, cj, N) : knode(ci, cj + 1, N);
+}
+
+// Unit-coefficient element bilinear form |T| grad v . grad w on a right
+// triangle with legs h, in (a, r, b) order:
+// 1/2 [(v_a - v_r)(w_a - w_r) + (v_r - v_b)(w_r - w_b)].
+__device__ inline double tri_form(double va, double vr, double vb, double wa, double wr,
+                                  double wb) {
+    return 0.5 * ((va - vr) * (wa - wr) + (vr - vb) * (wr - wb));
+}
+
+// Visits the (up to 6) triangles incident to node (i, j): f(ci, cj, s, role)
+// with role 0/1/2 = the node is vertex a/r/b of the triangle.
+template <class F>
+__device__ inline void for_incident_triangles(int N, int i, int j, F f) {
+    if (i < N && j < N) {
+        f(i, j, 0, 0);
+        f(i, j, 1, 0);
+    }
+    if (i > 0 && j < N) f(i - 1, j, 0, 1);  // lower of cell (i-1, j): r = (i, j)
+    if (i < N && j > 0) f(i, j - 1, 1, 1);  // upper of cell (i, j-1): r = (i, j)
+    if (i > 0 && j > 0) {
+        f(i - 1, j - 1, 0, 2);
+        f(i - 1, j - 1, 1, 2);
+    }
+}
+
+}  // namespace hinv

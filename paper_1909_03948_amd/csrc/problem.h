@@ -1,0 +1,78 @@
+// The inverse-problem object behind hinv_problem: mesh-sized device data, the
+// two multigrid hierarchies (state operator A(m), prior operator K_A) and the
+// operations of the method.
+#pragma once
+
+#include <memory>
+
+#include "solver.h"
+
+namespace hinv {
+
+class Problem {
+  public:
+    Problem(Ctx* ctx, const hinv_problem_desc& d);
+
+    Ctx* ctx;
+    int N, n, q;
+    double gamma, delta, beta, m_prior, sigma;
+    int precision;
+    double rtol;
+    int max_iter;
+
+    std::unique_ptr<Hierarchy> HA;  // state operator A(m)
+    std::unique_ptr<Hierarchy> HK;  // prior operator K_A
+
+    // observation operator: 3 (node, weight) pairs per point; transpose in CSR
+    DBuf<double> obs_xy, obs_w, d;
+    DBuf<int> obs_node, t_node, t_ptr, t_ent;
+    int n_touch = 0;
+
+    // linearization point
+    DBuf<double> m_lin, u_lin, p_lin;
+    bool linearized = false;
+    bool ha_is_lin = false;
+
+    void set_data(const double* d_host, double sig);
+
+    // --- operations (device pointers, FP64) ---
+    void forward(const double* m, double* u, SolveStats* st);
+    void observe(const double* u, int ldu, int nc, double* out, int ldo, bool minus_data);
+    void cost(const double* m, const double* u, double* misfit, double* reg);
+    void gradient(const double* m, const double* u, double* p, double* g, SolveStats* st);
+    void linearize(const double* m, const double* u, const double* p);
+    void inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st);
+    void inc_adjoint(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
+                     double* phat, int ldp, SolveStats* st);
+    void hessian(int mode, int nc, const double* mhat, int ldm, double* out, int ldo,
+                 SolveStats* st);
+    void prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate = false);
+    void prior_solve(int nc, const double* x, int ldx, double* y, int ldy, SolveStats* st);
+    void mass_apply(int nc, const double* x, int ldx, double* y, int ldy);
+    void mass_solve(int nc, const double* x, int ldx, double* y, int ldy);
+    void prior_sample(int ns, const double* eta, int ldeta, double* out, int ldo, bool add_mean,
+                      SolveStats* st);
+
+    // scratch of n x cap columns
+    double* scratch(int which, int nc);
+    double* obs_scratch(int nc);
+
+  private:
+    void ensure_lin_hierarchy();
+    static constexpr int kScratch = 8;
+    int cap_ = 0;
+    DBuf<double> w_[kScratch];
+    int qcap_ = 0;
+    DBuf<double> wq_;
+    DBuf<double> red_;
+};
+
+// ---- device vector helpers (FP64, single stream) ---------------------------
+double dev_dot(Ctx* ctx, int n, const double* a, const double* b);
+void dev_dots(Ctx* ctx, int n, int nc, const double* a, int lda, const double* b, int ldb,
+              double* host_out);
+void dev_axpby(Ctx* ctx, int n, double a, const double* x, double b, double* y);  // y = a x + b y
+void dev_copy(Ctx* ctx, int n, int nc, const double* x, int ldx, double* y, int ldy);
+void dev_fill(Ctx* ctx, int n, double v, double* y);
+
+}  // namespace hinv

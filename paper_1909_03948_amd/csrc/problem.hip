@@ -1,0 +1,621 @@
+// Operations of the Poisson coefficient-inversion problem on the device.
+//
+//   forward         A(m)_FF u_F = -A(m)_FD u_D          (Sec. 5.1, Eq. eq:poisson_weak)
+//   cost            1/2 sigma^-2 |B u - d|^2 + 1/2 (m - m_pr)^T R (m - m_pr)
+//                                                        (Sec. 5.1, Eq. eq:cost-elliptic)
+//   adjoint         A_FF p_F = -[B^T (B u - d)]_F / sigma^2              (App. A, eq:firstadj)
+//   gradient        g_v = [R (m - m_pr)]_v + sum_{T ni v} (c_T / 3) |T| grad u . grad p
+//                                                        (App. A, eq:firstcontrol)
+//   inc. forward    A_FF uhat_F = -[K[s] u]_F, s_T = (c_T/3) sum_{w in T} mhat_w
+//                                                        (App. A, eq:incrementals1)
+//   inc. adjoint    A_FF phat_F = -[B^T B uhat / sigma^2 + K[s] p]_F  (eq:incrementals2)
+//   Hessian         (H mhat)_v = sum_{T ni v} (c_T/3) |T| (grad u . grad phat + grad uhat . grad p)
+//                    + sum_{T ni v} (c_T/9) (sum_{w in T} mhat_w) |T| grad u . grad p [+ R mhat]
+//                                                        (eq:incrementals3)
+//   prior           R = K_A M^-1 K_A, R^-1 = K_A^-1 M K_A^-1           (Sec. 5.1, Sec. 2.3)
+//   prior draw      m_pr + K_A^-1 C_M eta, C_M C_M^T = M  (Sec. 4.3.1, App. C)
+//
+// c_T = exp((m_a + m_r + m_b) / 3) (centroid rule); K[s] is the stiffness with
+// per-triangle coefficient s_T, a five-point stencil on this mesh.
+#include <algorithm>
+
+#include "grid.h"
+#include "problem.h"
+
+namespace hinv {
+
+namespace {
+
+inline dim3 grid2(int n, int nc) { return dim3(ceil_div(n, kBlock), nc); }
+
+template <typename T>
+__device__ inline T* colp(T* p, int ld) {
+    return p + (size_t)blockIdx.y * ld;
+}
+
+// ---------------------------------------------------------- observations ---
+// Point (x, y) lies in cell (i, j) = (min(floor(x N), N-1), min(floor(y N), N-1)),
+// local offsets xi = x N - i, zeta = y N - j.  Lower triangle when xi >= zeta:
+// P1 weights (1 - xi, xi - zeta, zeta) on (k(i,j), k(i+1,j), k(i+1,j+1));
+// upper: (1 - zeta, zeta - xi, xi) on (k(i,j), k(i,j+1), k(i+1,j+1)).
+__global__ void k_obs_setup(int N, int q, const double* __restrict__ xy, int* __restrict__ node,
+                            double* __restrict__ w) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= q) return;
+    const double x = xy[2 * o] * N, y = xy[2 * o + 1] * N;
+    int i = (int)floor(x), j = (int)floor(y);
+    i = i < 0 ? 0 : (i > N - 1 ? N - 1 : i);
+    j = j < 0 ? 0 : (j > N - 1 ? N - 1 : j);
+    const double xi = x - i, ze = y - j;
+    node[3 * o] = knode(i, j, N);
+    node[3 * o + 2] = knode(i + 1, j + 1, N);
+    if (xi >= ze) {
+        node[3 * o + 1] = knode(i + 1, j, N);
+        w[3 * o] = 1.0 - xi;
+        w[3 * o + 1] = xi - ze;
+        w[3 * o + 2] = ze;
+    } else {
+        node[3 * o + 1] = knode(i, j + 1, N);
+        w[3 * o] = 1.0 - ze;
+        w[3 * o + 1] = ze - xi;
+        w[3 * o + 2] = xi;
+    }
+}
+
+// out[o] = (B u)_o - d_o (d may be null).
+__global__ void k_obs_gather(int q, const int* __restrict__ node, const double* __restrict__ w,
+                             const double* __restrict__ u, int ldu, const double* __restrict__ d,
+                             double* __restrict__ out, int ldo) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= q) return;
+    const double* uc = colp(u, ldu);
+    double v = w[3 * o] * uc[node[3 * o]] + w[3 * o + 1] * uc[node[3 * o + 1]] +
+               w[3 * o + 2] * uc[node[3 * o + 2]];
+    if (d) v -= d[o];
+    colp(out, ldo)[o] = v;
+}
+
+// y[node] += scale * (B^T v)[node] over the nodes touched by observations (CSR, fixed order).
+__global__ void k_obs_scatter(int nt, const int* __restrict__ tnode, const int* __restrict__ tptr,
+                              const int* __restrict__ tent, const double* __restrict__ w,
+                              const double* __restrict__ v, int ldv, double scale,
+                              double* __restrict__ y, int ldy) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const double* vc = colp(v, ldv);
+    double s = 0.0;
+    for (int e = tptr[t]; e < tptr[t + 1]; ++e) {
+        const int ent = tent[e];
+        s += w[ent] * vc[ent / 3];
+    }
+    colp(y, ldy)[tnode[t]] += scale * s;
+}
+
+// ----------------------------------------------------- state equation ---
+// -A_FD u_D with u_D = 0 on y = 0 and 1 on y = 1: only row j = N-1 couples to
+// the top boundary, through its north edge weight.
+__global__ void k_forward_rhs(int N, const double* __restrict__ wN, double* __restrict__ rhs) {
+    const int N1 = N + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N1 * N1) return;
+    const int j = k / N1;
+    rhs[k] = (j == N - 1) ? wN[k] : 0.0;
+}
+
+__global__ void k_set_top(int N, double* __restrict__ u) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= N) u[knode(i, N, N)] = 1.0;
+}
+
+// Per-triangle sensitivity coefficient s_T = (c_T/3)(mhat_a + mhat_r + mhat_b).
+__device__ inline double sens_coef(int N, const double* cT, const double* mh, int ci, int cj, int s) {
+    if (ci < 0 || ci >= N || cj < 0 || cj >= N) return 0.0;
+    int ka, kr, kb;
+    tri_nodes(N, ci, cj, s, ka, kr, kb);
+    return cT[2 * (cj * N + ci) + s] * (1.0 / 3.0) * (mh[ka] + mh[kr] + mh[kb]);
+}
+
+// y[:,c] = scale * (K[s(mhat[:,c])] w)_k on free rows, 0 on Dirichlet rows.
+// w is one full state-space vector (its Dirichlet values take part).
+__global__ void k_sens(int N, const double* __restrict__ cT, const double* __restrict__ mhat,
+                       int ldm, const double* __restrict__ w, double scale, double* __restrict__ y,
+                       int ldy) {
+    const int N1 = N + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N1 * N1) return;
+    const int i = k % N1, j = k / N1;
+    double v = 0.0;
+    if (j > 0 && j < N) {
+        const double* mh = colp(mhat, ldm);
+        const double wk = w[k];
+        if (i < N) {
+            const double e = 0.5 * (sens_coef(N, cT, mh, i, j, 0) + sens_coef(N, cT, mh, i, j - 1, 1));
+            v += e * (wk - w[k + 1]);
+        }
+        if (i > 0) {
+            const double e = 0.5 * (sens_coef(N, cT, mh, i - 1, j, 0) +
+                                    sens_coef(N, cT, mh, i - 1, j - 1, 1));
+            v += e * (wk - w[k - 1]);
+        }
+        {
+            const double e = 0.5 * (sens_coef(N, cT, mh, i, j, 1) + sens_coef(N, cT, mh, i - 1, j, 0));
+            v += e * (wk - w[k + N1]);
+        }
+        {
+            const double e = 0.5 * (sens_coef(N, cT, mh, i, j - 1, 1) +
+                                    sens_coef(N, cT, mh, i - 1, j - 1, 0));
+            v += e * (wk - w[k - N1]);
+        }
+        v *= scale;
+    }
+    colp(y, ldy)[k] = v;
+}
+
+// Hessian output without the prior term (see file header).  gn drops the
+// terms that carry the adjoint p.
+__global__ void k_hess_out(int N, const double* __restrict__ cT, const double* __restrict__ u,
+                           const double* __restrict__ p, const double* __restrict__ uh, int ldu,
+                           const double* __restrict__ ph, int ldp, const double* __restrict__ mh,
+                           int ldm, double* __restrict__ out, int ldo, int gn) {
+    const int N1 = N + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N1 * N1) return;
+    const int i = k % N1, j = k / N1;
+    const double* uhc = colp(uh, ldu);
+    const double* phc = colp(ph, ldp);
+    const double* mhc = colp(mh, ldm);
+    double acc = 0.0;
+    for_incident_triangles(N, i, j, [&](int ci, int cj, int s, int) {
+        int a, r, b;
+        tri_nodes(N, ci, cj, s, a, r, b);
+        const double c = cT[2 * (cj * N + ci) + s];
+        double v = tri_form(u[a], u[r], u[b], phc[a], phc[r], phc[b]);
+        if (!gn) {
+            v += tri_form(uhc[a], uhc[r], uhc[b], p[a], p[r], p[b]);
+            v += (1.0 / 3.0) * (mhc[a] + mhc[r] + mhc[b]) * tri_form(u[a], u[r], u[b], p[a], p[r], p[b]);
+        }
+        acc += c * (1.0 / 3.0) * v;
+    });
+    colp(out, ldo)[k] = acc;
+}
+
+// g_v = sum_{T ni v} (c_T/3) |T| grad u . grad p  (data part of the gradient).
+__global__ void k_grad(int N, const double* __restrict__ cT, const double* __restrict__ u,
+                       const double* __restrict__ p, double* __restrict__ g) {
+    const int N1 = N + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N1 * N1) return;
+    const int i = k % N1, j = k / N1;
+    double acc = 0.0;
+    for_incident_triangles(N, i, j, [&](int ci, int cj, int s, int) {
+        int a, r, b;
+        tri_nodes(N, ci, cj, s, a, r, b);
+        acc += cT[2 * (cj * N + ci) + s] * (1.0 / 3.0) * tri_form(u[a], u[r], u[b], p[a], p[r], p[b]);
+    });
+    g[k] = acc;
+}
+
+// (C_M eta)_v: every edge midpoint of a triangle carries one normal with
+// quadrature weight |T|/3 and basis value 1/2 at both edge ends, so the
+// entry of C_M is sqrt(|T|/3) / 2 = h / (2 sqrt 6).  Edges in (a, r, b) order:
+// e0 = (a, r), e1 = (r, b), e2 = (a, b).
+__global__ void k_mass_factor(int N, const double* __restrict__ eta, int lde,
+                              double* __restrict__ out, int ldo) {
+    const int N1 = N + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N1 * N1) return;
+    const int i = k % N1, j = k / N1;
+    const double* ec = colp(eta, lde);
+    double acc = 0.0;
+    for_incident_triangles(N, i, j, [&](int ci, int cj, int s, int role) {
+        const int t = 2 * (cj * N + ci) + s;
+        // a: e0, e2;  r: e0, e1;  b: e1, e2
+        const int ea = role == 2 ? 1 : 0;
+        const int eb = role == 1 ? 1 : 2;
+        acc += ec[3 * t + ea] + ec[3 * t + eb];
+    });
+    colp(out, ldo)[k] = acc * (0.5 / (N * sqrt(6.0)));
+}
+
+// y = op x + beta y (FP64, all rows of the prior / mass operator).
+__global__ void k_prior_apply(OpKA<double> op, const double* __restrict__ x, int ldx,
+                              double* __restrict__ y, int ldy, double beta) {
+    const int N1 = op.N + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N1 * N1) return;
+    const int i = k % N1, j = k / N1;
+    const double* xc = colp(x, ldx);
+    double v = op.apply(i, j, k, [&](int, int, int kk) { return xc[kk]; });
+    double* yc = colp(y, ldy);
+    if (beta != 0.0) v += beta * yc[k];
+    yc[k] = v;
+}
+
+// One Chebyshev step for M x = b with the Jacobi-scaled spectrum in [1/2, 2]:
+// r <- r - M d, x <- x + d, dn = c1 d + c2 D^-1 r.
+__global__ void k_cheb_mass(OpKA<double> op, double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ d, double* __restrict__ dn, int ld,
+                            double c1, double c2) {
+    const int N1 = op.N + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N1 * N1) return;
+    const int i = k % N1, j = k / N1;
+    const double* dc = colp(d, ld);
+    const double Md = op.apply(i, j, k, [&](int, int, int kk) { return dc[kk]; });
+    double* rc = colp(r, ld);
+    const double rn = rc[k] - Md;
+    rc[k] = rn;
+    colp(x, ld)[k] += dc[k];
+    colp(dn, ld)[k] = c1 * dc[k] + c2 * op.inv_diag(i, j, k) * rn;
+}
+
+// x = 0, r = b, d = D^-1 b / theta.
+__global__ void k_cheb_mass_init(OpKA<double> op, const double* __restrict__ b, int ldb,
+                                 double* __restrict__ x, double* __restrict__ r,
+                                 double* __restrict__ d, int ld, double inv_theta) {
+    const int N1 = op.N + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N1 * N1) return;
+    const int i = k % N1, j = k / N1;
+    const double bv = colp(b, ldb)[k];
+    colp(x, ld)[k] = 0.0;
+    colp(r, ld)[k] = bv;
+    colp(d, ld)[k] = op.inv_diag(i, j, k) * bv * inv_theta;
+}
+
+__global__ void k_add_scalar(int n, double v, double* __restrict__ x, int ld) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) colp(x, ld)[k] += v;
+}
+
+__global__ void k_axpby(int n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) y[k] = a * x[k] + b * y[k];
+}
+
+__global__ void k_fill(int n, double v, double* __restrict__ y) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) y[k] = v;
+}
+
+__global__ void k_copy(int n, const double* __restrict__ x, int ldx, double* __restrict__ y, int ldy) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) colp(y, ldy)[k] = colp(x, ldx)[k];
+}
+
+__global__ void k_dot_partial(int n, const double* __restrict__ a, int lda,
+                              const double* __restrict__ b, int ldb, double* __restrict__ partial) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (k < n) v = colp(a, lda)[k] * colp(b, ldb)[k];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_dot_finish(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[(size_t)blockIdx.x * nblk + b];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+OpKA<double> prior_op(int N, double g, double dl, double bt) {
+    OpKA<double> op;
+    op.N = N;
+    op.h = 1.0 / N;
+    op.g = g;
+    op.dl = dl;
+    op.bt = bt;
+    return op;
+}
+
+// Chebyshev iteration count for M: error factor 2 (1/3)^K <= 2e-15.
+constexpr int kMassCheb = 32;
+
+}  // namespace
+
+// ----------------------------------------------------------- vector ops ---
+void dev_dots(Ctx* ctx, int n, int nc, const double* a, int lda, const double* b, int ldb,
+              double* host_out) {
+    const int nblk = ceil_div(n, kBlock);
+    ctx->red.ensure((size_t)nblk * nc + nc);
+    k_dot_partial<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(n, a, lda, b, ldb, ctx->red.get());
+    HINV_LAUNCH_CHECK();
+    double* out = ctx->red.get() + (size_t)nblk * nc;
+    k_dot_finish<<<nc, kBlock, 0, ctx->stream>>>(ctx->red.get(), nblk, out);
+    HINV_LAUNCH_CHECK();
+    HINV_HIP(hipMemcpyAsync(host_out, out, sizeof(double) * nc, hipMemcpyDeviceToHost, ctx->stream));
+    HINV_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+double dev_dot(Ctx* ctx, int n, const double* a, const double* b) {
+    double r;
+    dev_dots(ctx, n, 1, a, n, b, n, &r);
+    return r;
+}
+
+void dev_axpby(Ctx* ctx, int n, double a, const double* x, double b, double* y) {
+    k_axpby<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(n, a, x, b, y);
+    HINV_LAUNCH_CHECK();
+}
+
+void dev_copy(Ctx* ctx, int n, int nc, const double* x, int ldx, double* y, int ldy) {
+    if (nc <= 0) return;
+    k_copy<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(n, x, ldx, y, ldy);
+    HINV_LAUNCH_CHECK();
+}
+
+void dev_fill(Ctx* ctx, int n, double v, double* y) {
+    k_fill<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(n, v, y);
+    HINV_LAUNCH_CHECK();
+}
+
+// -------------------------------------------------------------- problem ---
+Problem::Problem(Ctx* c, const hinv_problem_desc& desc)
+    : ctx(c), N(desc.N), n((desc.N + 1) * (desc.N + 1)), q(desc.q), gamma(desc.gamma),
+      delta(desc.delta), m_prior(desc.m_prior), sigma(desc.sigma), precision(desc.precision),
+      rtol(desc.rtol), max_iter(desc.max_iter > 0 ? desc.max_iter : 200) {
+    beta = std::isnan(desc.beta) ? std::sqrt(gamma * delta) / 1.42 : desc.beta;
+    PriorParams pp{gamma, delta, beta};
+    HA = std::make_unique<Hierarchy>(ctx, kOpState, N, pp);
+    HK = std::make_unique<Hierarchy>(ctx, kOpPrior, N, pp);
+    m_lin.ensure(n);
+    u_lin.ensure(n);
+    p_lin.ensure(n);
+    hipStream_t s = ctx->stream;
+    if (q > 0) {
+        obs_xy.ensure(2 * (size_t)q);
+        obs_w.ensure(3 * (size_t)q);
+        obs_node.ensure(3 * (size_t)q);
+        d.ensure(q);
+        HINV_HIP(hipMemcpyAsync(obs_xy.get(), desc.obs_xy, sizeof(double) * 2 * q, hipMemcpyHostToDevice, s));
+        k_obs_setup<<<ceil_div(q, kBlock), kBlock, 0, s>>>(N, q, obs_xy.get(), obs_node.get(), obs_w.get());
+        HINV_LAUNCH_CHECK();
+        // transpose structure: node -> list of (3 o + a), built from the device's node indices
+        std::vector<int> hn(3 * (size_t)q);
+        HINV_HIP(hipMemcpyAsync(hn.data(), obs_node.get(), sizeof(int) * 3 * q, hipMemcpyDeviceToHost, s));
+        HINV_HIP(hipStreamSynchronize(s));
+        std::vector<int> order(3 * (size_t)q);
+        for (int e = 0; e < 3 * q; ++e) order[e] = e;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hn[a] < hn[b]; });
+        std::vector<int> tn, tp, te;
+        for (int e = 0; e < 3 * q; ++e) {
+            const int nd = hn[order[e]];
+            if (tn.empty() || tn.back() != nd) {
+                tn.push_back(nd);
+                tp.push_back(e);
+            }
+            te.push_back(order[e]);
+        }
+        tp.push_back(3 * q);
+        n_touch = (int)tn.size();
+        t_node.ensure(tn.size());
+        t_ptr.ensure(tp.size());
+        t_ent.ensure(te.size());
+        HINV_HIP(hipMemcpyAsync(t_node.get(), tn.data(), sizeof(int) * tn.size(), hipMemcpyHostToDevice, s));
+        HINV_HIP(hipMemcpyAsync(t_ptr.get(), tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, s));
+        HINV_HIP(hipMemcpyAsync(t_ent.get(), te.data(), sizeof(int) * te.size(), hipMemcpyHostToDevice, s));
+        HINV_HIP(hipStreamSynchronize(s));
+        set_data(desc.d_obs, sigma);
+    }
+}
+
+void Problem::set_data(const double* d_host, double sig) {
+    if (sig > 0) sigma = sig;
+    if (q == 0) return;
+    hipStream_t s = ctx->stream;
+    if (d_host) {
+        HINV_HIP(hipMemcpyAsync(d.get(), d_host, sizeof(double) * q, hipMemcpyHostToDevice, s));
+        HINV_HIP(hipStreamSynchronize(s));
+    } else {
+        k_fill<<<ceil_div(q, kBlock), kBlock, 0, s>>>(q, 0.0, d.get());
+        HINV_LAUNCH_CHECK();
+    }
+}
+
+double* Problem::scratch(int which, int nc) {
+    if (which < 0 || which >= kScratch) fail(HINV_EINVAL, "internal: scratch index out of range");
+    if (nc > cap_) {
+        for (auto& w : w_) w.release();
+        for (auto& w : w_) w.ensure((size_t)n * nc);
+        cap_ = nc;
+    }
+    return w_[which].get();
+}
+
+double* Problem::obs_scratch(int nc) {
+    if (nc > qcap_) {
+        wq_.ensure((size_t)std::max(q, 1) * nc);
+        qcap_ = nc;
+    }
+    return wq_.get();
+}
+
+void Problem::forward(const double* m, double* u, SolveStats* st) {
+    hipStream_t s = ctx->stream;
+    HA->set_state_coefficient(m);
+    ha_is_lin = false;
+    double* rhs = scratch(0, 1);
+    k_forward_rhs<<<ceil_div(n, kBlock), kBlock, 0, s>>>(N, HA->weightsN(), rhs);
+    HINV_LAUNCH_CHECK();
+    HA->solve(1, rhs, n, u, n, precision, rtol, max_iter, st);
+    k_set_top<<<ceil_div(N + 1, kBlock), kBlock, 0, s>>>(N, u);
+    HINV_LAUNCH_CHECK();
+}
+
+void Problem::observe(const double* u, int ldu, int nc, double* out, int ldo, bool minus_data) {
+    if (q == 0) return;
+    k_obs_gather<<<grid2(q, nc), kBlock, 0, ctx->stream>>>(q, obs_node.get(), obs_w.get(), u, ldu,
+                                                           minus_data ? d.get() : nullptr, out, ldo);
+    HINV_LAUNCH_CHECK();
+}
+
+void Problem::cost(const double* m, const double* u, double* misfit, double* reg) {
+    double mis = 0.0;
+    if (q > 0) {
+        double* r = obs_scratch(1);
+        observe(u, n, 1, r, q, true);
+        double ss;
+        dev_dots(ctx, q, 1, r, q, r, q, &ss);
+        mis = 0.5 * ss / (sigma * sigma);
+    }
+    double* dm = scratch(0, 1);
+    double* Rdm = scratch(1, 1);
+    dev_copy(ctx, n, 1, m, n, dm, n);
+    k_add_scalar<<<ceil_div(n, kBlock), kBlock, 0, ctx->stream>>>(n, -m_prior, dm, n);
+    HINV_LAUNCH_CHECK();
+    prior_apply(1, dm, n, Rdm, n);
+    *misfit = mis;
+    *reg = 0.5 * dev_dot(ctx, n, dm, Rdm);
+}
+
+void Problem::gradient(const double* m, const double* u, double* p, double* g, SolveStats* st) {
+    hipStream_t s = ctx->stream;
+    HA->set_state_coefficient(m);
+    ha_is_lin = false;
+    double* rhs = scratch(0, 1);
+    k_fill<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, 0.0, rhs);
+    HINV_LAUNCH_CHECK();
+    if (q > 0) {
+        double* r = obs_scratch(1);
+        observe(u, n, 1, r, q, true);
+        k_obs_scatter<<<ceil_div(n_touch, kBlock), kBlock, 0, s>>>(
+            n_touch, t_node.get(), t_ptr.get(), t_ent.get(), obs_w.get(), r, q,
+            -1.0 / (sigma * sigma), rhs, n);
+        HINV_LAUNCH_CHECK();
+    }
+    HA->solve(1, rhs, n, p, n, precision, rtol, max_iter, st);
+    k_grad<<<ceil_div(n, kBlock), kBlock, 0, s>>>(N, HA->coefficient(), u, p, g);
+    HINV_LAUNCH_CHECK();
+    double* dm = scratch(1, 1);
+    dev_copy(ctx, n, 1, m, n, dm, n);
+    k_add_scalar<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, -m_prior, dm, n);
+    HINV_LAUNCH_CHECK();
+    prior_apply(1, dm, n, g, n, /*accumulate=*/true);
+}
+
+void Problem::linearize(const double* m, const double* u, const double* p) {
+    dev_copy(ctx, n, 1, m, n, m_lin.get(), n);
+    dev_copy(ctx, n, 1, u, n, u_lin.get(), n);
+    dev_copy(ctx, n, 1, p, n, p_lin.get(), n);
+    HA->set_state_coefficient(m_lin.get());
+    ha_is_lin = true;
+    linearized = true;
+}
+
+void Problem::ensure_lin_hierarchy() {
+    if (!linearized) fail(HINV_ESTATE, "Hessian action before hinv_linearize");
+    if (!ha_is_lin) {
+        HA->set_state_coefficient(m_lin.get());
+        ha_is_lin = true;
+    }
+}
+
+void Problem::inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st) {
+    ensure_lin_hierarchy();
+    double* rhs = scratch(0, nc);
+    k_sens<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(N, HA->coefficient(), mhat, ldm, u_lin.get(),
+                                                     -1.0, rhs, n);
+    HINV_LAUNCH_CHECK();
+    HA->solve(nc, rhs, n, uhat, ldu, precision, rtol, max_iter, st);
+}
+
+void Problem::inc_adjoint(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
+                          double* phat, int ldp, SolveStats* st) {
+    ensure_lin_hierarchy();
+    hipStream_t s = ctx->stream;
+    double* rhs = scratch(0, nc);
+    // -C(p) mhat (dropped by Gauss-Newton: the scale 0 zeroes the column)
+    k_sens<<<grid2(n, nc), kBlock, 0, s>>>(N, HA->coefficient(), mhat, ldm, p_lin.get(),
+                                           gn ? 0.0 : -1.0, rhs, n);
+    HINV_LAUNCH_CHECK();
+    if (q > 0) {
+        double* Bu = obs_scratch(nc);
+        observe(uhat, ldu, nc, Bu, q, false);
+        k_obs_scatter<<<grid2(n_touch, nc), kBlock, 0, s>>>(n_touch, t_node.get(), t_ptr.get(),
+                                                            t_ent.get(), obs_w.get(), Bu, q,
+                                                            -1.0 / (sigma * sigma), rhs, n);
+        HINV_LAUNCH_CHECK();
+    }
+    HA->solve(nc, rhs, n, phat, ldp, precision, rtol, max_iter, st);
+}
+
+void Problem::hessian(int mode, int nc, const double* mhat, int ldm, double* out, int ldo,
+                      SolveStats* st) {
+    const bool gn = mode == HINV_HESS_GN_FULL || mode == HINV_HESS_GN_MISFIT;
+    const bool with_prior = mode == HINV_HESS_FULL || mode == HINV_HESS_GN_FULL;
+    scratch(0, nc);
+    double* uh = scratch(1, nc);
+    double* ph = scratch(2, nc);
+    inc_forward(nc, mhat, ldm, uh, n, st);
+    inc_adjoint(nc, gn, mhat, ldm, uh, n, ph, n, st);
+    k_hess_out<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(N, HA->coefficient(), u_lin.get(),
+                                                         p_lin.get(), uh, n, ph, n, mhat, ldm, out,
+                                                         ldo, gn ? 1 : 0);
+    HINV_LAUNCH_CHECK();
+    if (with_prior) prior_apply(nc, mhat, ldm, out, ldo, true);
+}
+
+void Problem::mass_apply(int nc, const double* x, int ldx, double* y, int ldy) {
+    k_prior_apply<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(prior_op(N, 0.0, 1.0, 0.0), x, ldx, y,
+                                                            ldy, 0.0);
+    HINV_LAUNCH_CHECK();
+}
+
+void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx) {
+    // Chebyshev iteration (no inner products) on the Jacobi-scaled consistent
+    // mass matrix, whose spectrum lies in [1/2, 2] for P1 triangles.
+    hipStream_t s = ctx->stream;
+    const OpKA<double> M = prior_op(N, 0.0, 1.0, 0.0);
+    const double lo = 0.5, hi = 2.0;
+    const double theta = 0.5 * (hi + lo), dl = 0.5 * (hi - lo), sigma1 = theta / dl;
+    double* r = scratch(5, nc);
+    double* d0 = scratch(6, nc);
+    double* d1 = scratch(7, nc);
+    const dim3 g = grid2(n, nc);
+    if (ldx != n) fail(HINV_EINVAL, "mass_solve needs a packed output");
+    k_cheb_mass_init<<<g, kBlock, 0, s>>>(M, b, ldb, x, r, d0, n, 1.0 / theta);
+    HINV_LAUNCH_CHECK();
+    double rho = 1.0 / sigma1;
+    for (int it = 0; it < kMassCheb; ++it) {
+        const double rho_n = 1.0 / (2.0 * sigma1 - rho);
+        k_cheb_mass<<<g, kBlock, 0, s>>>(M, x, r, d0, d1, n, rho_n * rho, 2.0 * rho_n / dl);
+        HINV_LAUNCH_CHECK();
+        std::swap(d0, d1);
+        rho = rho_n;
+    }
+}
+
+void Problem::prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate) {
+    hipStream_t s = ctx->stream;
+    const OpKA<double> K = prior_op(N, gamma, delta, beta);
+    double* t1 = scratch(3, nc);
+    double* t2 = scratch(4, nc);
+    k_prior_apply<<<grid2(n, nc), kBlock, 0, s>>>(K, x, ldx, t1, n, 0.0);
+    HINV_LAUNCH_CHECK();
+    mass_solve(nc, t1, n, t2, n);
+    k_prior_apply<<<grid2(n, nc), kBlock, 0, s>>>(K, t2, n, y, ldy, accumulate ? 1.0 : 0.0);
+    HINV_LAUNCH_CHECK();
+}
+
+void Problem::prior_solve(int nc, const double* x, int ldx, double* y, int ldy, SolveStats* st) {
+    double* t1 = scratch(3, nc);
+    double* t2 = scratch(4, nc);
+    HK->solve(nc, x, ldx, t1, n, precision, rtol, max_iter, st);
+    mass_apply(nc, t1, n, t2, n);
+    HK->solve(nc, t2, n, y, ldy, precision, rtol, max_iter, st);
+}
+
+void Problem::prior_sample(int ns, const double* eta, int ldeta, double* out, int ldo,
+                           bool add_mean, SolveStats* st) {
+    double* t = scratch(3, ns);
+    k_mass_factor<<<grid2(n, ns), kBlock, 0, ctx->stream>>>(N, eta, ldeta, t, n);
+    HINV_LAUNCH_CHECK();
+    HK->solve(ns, t, n, out, ldo, precision, rtol, max_iter, st);
+    if (add_mean) {
+        k_add_scalar<<<grid2(n, ns), kBlock, 0, ctx->stream>>>(n, m_prior, out, ldo);
+        HINV_LAUNCH_CHECK();
+    }
+}
+
+}  // namespace hinv

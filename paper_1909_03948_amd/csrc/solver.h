@@ -1,0 +1,102 @@
+// Geometric-multigrid preconditioned CG on the structured mesh, batched over
+// right-hand sides, in FP64 or as FP32 PCG inside FP64 iterative refinement.
+#pragma once
+
+#include <memory>
+
+#include "common.h"
+
+namespace hinv {
+
+enum OpKind { kOpState = 0, kOpPrior = 1 };
+
+// One multigrid level.  For the state operator it holds the triangle
+// coefficients and the five-point weights in FP64 and FP32; the prior
+// operator needs nothing but N.
+struct Level {
+    int N = 0, n = 0;
+    DBuf<double> cT, wE64, wN64, dinv64;
+    DBuf<float> wE32, wN32, dinv32;
+};
+
+struct SolveStats {
+    int solves = 0, iterations = 0, refinements = 0, fallbacks = 0;
+    double max_relres = 0.0;
+    bool converged = true;
+    void add(const SolveStats& o) {
+        solves += o.solves;
+        iterations += o.iterations;
+        refinements += o.refinements;
+        fallbacks += o.fallbacks;
+        max_relres = o.max_relres > max_relres ? o.max_relres : max_relres;
+        converged = converged && o.converged;
+    }
+};
+
+// Per-precision scratch of the batched PCG (column-major, ld = level size).
+template <typename T>
+struct PcgWork {
+    int cap = 0;  // columns
+    DBuf<T> x, r, z, p, q;
+    std::vector<std::unique_ptr<DBuf<T>>> lb, lx, lt;  // per level b, x, t
+};
+
+struct ColState {
+    double bb;   // |b|^2 of the inner problem
+    double rz, pq, rr, tol2, alpha, beta;
+    double obb;  // |b|^2 of the outer (FP64) problem
+};
+
+class Hierarchy {
+  public:
+    Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp);
+    ~Hierarchy();
+    // State operator: builds all levels from the FP64 parameter field m (device).
+    void set_state_coefficient(const double* m);
+    // Solves A x = b for nc columns.  b and x: device FP64, column-major.
+    // Only the free rows of b are read; x is zero on Dirichlet rows.
+    void solve(int nc, const double* b, int ldb, double* x, int ldx, int precision, double rtol,
+               int max_iter, SolveStats* st);
+    // y = A x (FP64, masked to free rows).
+    void apply(int nc, const double* x, int ldx, double* y, int ldy);
+    // Level-0 triangle coefficients c_T (state operator only).
+    const double* coefficient() const { return lev_[0]->cT.get(); }
+    const double* weightsE() const { return lev_[0]->wE64.get(); }
+    const double* weightsN() const { return lev_[0]->wN64.get(); }
+    bool ready() const { return ready_; }
+    int N() const { return N_; }
+    int n() const { return n_; }
+    double inner_tol32 = 1e-5;  // FP32 inner relative tolerance of the refinement loop
+
+  private:
+    template <typename T>
+    void pcg(int nc, int max_iter, int* iters);
+    template <typename T>
+    void vcycle(int l, int nc);
+    template <typename T>
+    PcgWork<T>& work();
+    void ensure_cols(int nc);
+    void build_coarse();
+
+    Ctx* ctx_;
+    OpKind kind_;
+    int N_, n_;
+    PriorParams pp_;
+    bool ready_ = false;
+    std::vector<std::unique_ptr<Level>> lev_;
+    DBuf<double> cinv64_;
+    DBuf<float> cinv32_;
+    int nc_coarse_ = 0;
+    // refinement state
+    int cap_ = 0;
+    DBuf<double> x64_, r64_;
+    DBuf<double> partial_;
+    DBuf<ColState> st_;
+    DBuf<int> act_, oact_;
+    DBuf<double> colnorm_;  // per column |r| used to scale the inner right-hand side
+    int* host_flags_ = nullptr;
+    PcgWork<double> w64_;
+    PcgWork<float> w32_;
+};
+
+}  // namespace hinv

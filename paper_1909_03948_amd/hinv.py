@@ -1,0 +1,324 @@
+"""Thin Python binding of libhinv (C ABI in include/hinv.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+buffers are torch CUDA float64 tensors; a multivector of c columns is a tensor
+of shape (c, ld) whose rows are the columns (column-major with leading
+dimension ld = tensor.stride(0)).  The library must be built first
+(``python -m paper_1909_03948_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhinv.so")
+
+HINV_OK, HINV_EINVAL, HINV_ENOMEM, HINV_EHIP = 0, -1, -2, -3
+HINV_ENOCONV, HINV_ESTATE, HINV_ENEGEIG, HINV_EBREAK = -4, -5, -6, -7
+HESS_FULL, HESS_MISFIT, HESS_GN_FULL, HESS_GN_MISFIT = 0, 1, 2, 3
+PREC_FP64, PREC_FP32_IR = 0, 1
+TPROD_FP64, TPROD_BF16 = 0, 1
+NEWTON_MAXREC = 64
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("N", C.c_int), ("gamma", C.c_double), ("delta", C.c_double),
+                ("beta", C.c_double), ("m_prior", C.c_double), ("q", C.c_int),
+                ("obs_xy", C.POINTER(C.c_double)), ("d_obs", C.POINTER(C.c_double)),
+                ("sigma", C.c_double), ("precision", C.c_int), ("rtol", C.c_double),
+                ("max_iter", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("solves", C.c_int), ("iterations", C.c_int),
+                ("refinements", C.c_int), ("fallbacks", C.c_int), ("max_relres", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("rel_tol", C.c_double), ("abs_tol", C.c_double), ("max_iter", C.c_int),
+                ("max_backtrack", C.c_int), ("c_armijo", C.c_double), ("max_cg", C.c_int),
+                ("gauss_newton", C.c_int)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("converged", C.c_int),
+                ("hessian_applies", C.c_int),
+                ("cost", C.c_double * (NEWTON_MAXREC + 1)),
+                ("gnorm", C.c_double * (NEWTON_MAXREC + 1)),
+                ("cg_iters", C.c_int * NEWTON_MAXREC), ("alpha", C.c_double * NEWTON_MAXREC),
+                ("solves", SolveInfo)]
+
+    def as_dict(self):
+        it = self.iterations
+        return dict(status=self.status, iterations=it, converged=bool(self.converged),
+                    hessian_applies=self.hessian_applies,
+                    cost=list(self.cost[:it + 1]), gnorm=list(self.gnorm[:it + 1]),
+                    cg_iters=list(self.cg_iters[:it]), alpha=list(self.alpha[:it]),
+                    solves=self.solves.as_dict())
+
+
+EXPORTS = [
+    "hinv_ctx_create", "hinv_ctx_destroy", "hinv_ctx_set_stream", "hinv_last_error",
+    "hinv_status_string", "hinv_problem_create", "hinv_problem_destroy", "hinv_problem_size",
+    "hinv_set_data", "hinv_set_solver", "hinv_forward", "hinv_cost", "hinv_observe",
+    "hinv_gradient", "hinv_linearize", "hinv_inc_forward", "hinv_inc_adjoint",
+    "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_solve", "hinv_prior_sample",
+    "hinv_map_newton", "hinv_lowrank_eig", "hinv_posterior_sample",
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Loads libhinv and declares its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libhinv is not built ({path} missing); run "
+                           "`python -m paper_1909_03948_amd.build`")
+    lib = C.CDLL(path)
+    P, I, D, V = C.c_void_p, C.c_int, C.c_double, C.c_void_p
+    DP = C.POINTER(C.c_double)
+    sig = {
+        "hinv_ctx_create": [I, V, C.POINTER(P)],
+        "hinv_ctx_destroy": [P],
+        "hinv_ctx_set_stream": [P, V],
+        "hinv_last_error": [P],
+        "hinv_status_string": [I],
+        "hinv_problem_create": [P, C.POINTER(ProblemDesc), C.POINTER(P)],
+        "hinv_problem_destroy": [P],
+        "hinv_problem_size": [P, C.POINTER(I)],
+        "hinv_set_data": [P, DP, D],
+        "hinv_set_solver": [P, I, D, I],
+        "hinv_forward": [P, V, V, C.POINTER(SolveInfo)],
+        "hinv_cost": [P, V, V, DP, DP],
+        "hinv_observe": [P, V, V],
+        "hinv_gradient": [P, V, V, V, V, C.POINTER(SolveInfo)],
+        "hinv_linearize": [P, V, V, V],
+        "hinv_inc_forward": [P, I, V, I, V, I, C.POINTER(SolveInfo)],
+        "hinv_inc_adjoint": [P, I, I, V, I, V, I, V, I, C.POINTER(SolveInfo)],
+        "hinv_hessian_apply": [P, I, I, V, I, V, I, C.POINTER(SolveInfo)],
+        "hinv_prior_apply": [P, I, V, I, V, I],
+        "hinv_prior_solve": [P, I, V, I, V, I, C.POINTER(SolveInfo)],
+        "hinv_prior_sample": [P, I, V, I, V, I, C.POINTER(SolveInfo)],
+        "hinv_map_newton": [P, V, V, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)],
+        "hinv_lowrank_eig": [P, I, I, I, V, I, I, DP, V, I, C.POINTER(SolveInfo)],
+        "hinv_posterior_sample": [P, V, I, DP, V, I, I, V, I, V, I, C.POINTER(SolveInfo)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_char_p if name in ("hinv_last_error", "hinv_status_string") else C.c_int
+    _lib = lib
+    return lib
+
+
+class HinvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def _ptr(t):
+    """Device pointer of a CUDA float64 tensor whose last dimension is contiguous."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("expected a CUDA float64 tensor")
+    if t.dim() > 0 and t.numel() > 0 and t.stride(-1) != 1:
+        raise ValueError("last dimension must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _cols(t, n):
+    """(pointer, ncols, ld) of a multivector given as a (c, ld) or (n,) tensor."""
+    if t.numel() == 0:
+        return _ptr(t), 0, n
+    if t.dim() == 1:
+        if t.shape[0] < n:
+            raise ValueError("vector too short")
+        return _ptr(t), 1, max(n, t.shape[0])
+    if t.shape[1] < n:
+        raise ValueError("multivector rows shorter than n")
+    return _ptr(t), t.shape[0], t.stride(0)
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        rc = self.lib.hinv_ctx_create(device, C.c_void_p(stream), C.byref(h))
+        if rc != HINV_OK:
+            raise HinvError(rc, self.lib.hinv_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hinv_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self):
+        return self.lib.hinv_last_error(self.h).decode()
+
+
+class Problem:
+    """Binding of hinv_problem; method names follow the C functions."""
+
+    def __init__(self, ctx: Context, N, gamma, delta, obs_xy=None, d_obs=None, sigma=0.01,
+                 m_prior=-2.0, beta=float("nan"), precision=PREC_FP64, rtol=1e-10, max_iter=0):
+        self.ctx, self.lib = ctx, ctx.lib
+        xy = np.ascontiguousarray(np.zeros((0, 2)) if obs_xy is None else obs_xy, dtype=np.float64)
+        q = xy.shape[0]
+        self._xy = xy.reshape(-1)
+        self._d = None if d_obs is None else np.ascontiguousarray(d_obs, dtype=np.float64)
+        DP = C.POINTER(C.c_double)
+        desc = ProblemDesc(N=N, gamma=gamma, delta=delta, beta=beta, m_prior=m_prior, q=q,
+                           obs_xy=self._xy.ctypes.data_as(DP) if q else None,
+                           d_obs=self._d.ctypes.data_as(DP) if self._d is not None else None,
+                           sigma=sigma, precision=precision, rtol=rtol, max_iter=max_iter)
+        h = C.c_void_p()
+        self._check(self.lib.hinv_problem_create(ctx.h, C.byref(desc), C.byref(h)), allow=())
+        self.h = h
+        self.N, self.n, self.q = N, (N + 1) ** 2, q
+
+    def _check(self, rc, allow=(HINV_ENOCONV,)):
+        if rc != HINV_OK and rc not in allow:
+            raise HinvError(rc, self.ctx.error() or self.lib.hinv_status_string(rc).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hinv_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_data(self, d_obs=None, sigma=float("nan")):
+        DP = C.POINTER(C.c_double)
+        self._d = None if d_obs is None else np.ascontiguousarray(d_obs, dtype=np.float64)
+        p = self._d.ctypes.data_as(DP) if self._d is not None else None
+        self._check(self.lib.hinv_set_data(self.h, p, sigma), allow=())
+
+    def set_solver(self, precision, rtol, max_iter=0):
+        self._check(self.lib.hinv_set_solver(self.h, precision, rtol, max_iter), allow=())
+
+    def forward(self, m, u):
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_forward(self.h, _ptr(m), _ptr(u), C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def cost(self, m, u):
+        mis, reg = C.c_double(), C.c_double()
+        self._check(self.lib.hinv_cost(self.h, _ptr(m), _ptr(u), C.byref(mis), C.byref(reg)), allow=())
+        return mis.value, reg.value
+
+    def observe(self, u, Bu):
+        self._check(self.lib.hinv_observe(self.h, _ptr(u), _ptr(Bu)), allow=())
+
+    def gradient(self, m, u, p, g):
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_gradient(self.h, _ptr(m), _ptr(u), _ptr(p), _ptr(g), C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def linearize(self, m, u, p):
+        self._check(self.lib.hinv_linearize(self.h, _ptr(m), _ptr(u), _ptr(p)), allow=())
+
+    def inc_forward(self, mhat, uhat):
+        pm, nc, ldm = _cols(mhat, self.n)
+        pu, nc2, ldu = _cols(uhat, self.n)
+        assert nc == nc2
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_inc_forward(self.h, nc, pm, ldm, pu, ldu, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def inc_adjoint(self, mhat, uhat, phat, gauss_newton=False):
+        pm, nc, ldm = _cols(mhat, self.n)
+        pu, _, ldu = _cols(uhat, self.n)
+        pp, _, ldp = _cols(phat, self.n)
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_inc_adjoint(self.h, nc, int(gauss_newton), pm, ldm, pu, ldu,
+                                                   pp, ldp, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def hessian_apply(self, mode, mhat, out):
+        pm, nc, ldm = _cols(mhat, self.n)
+        po, nc2, ldo = _cols(out, self.n)
+        assert nc == nc2
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_hessian_apply(self.h, mode, nc, pm, ldm, po, ldo, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def prior_apply(self, x, y):
+        px, nc, ldx = _cols(x, self.n)
+        py, _, ldy = _cols(y, self.n)
+        self._check(self.lib.hinv_prior_apply(self.h, nc, px, ldx, py, ldy), allow=())
+
+    def prior_solve(self, x, y):
+        px, nc, ldx = _cols(x, self.n)
+        py, _, ldy = _cols(y, self.n)
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_prior_solve(self.h, nc, px, ldx, py, ldy, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def prior_sample(self, eta, out):
+        pe, ns, lde = _cols(eta, 6 * self.N * self.N)
+        po, _, ldo = _cols(out, self.n)
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_prior_sample(self.h, ns, pe, lde, po, ldo, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def map_newton(self, m_map, m0=None, rel_tol=1e-6, abs_tol=0.0, max_iter=50, max_backtrack=10,
+                   c_armijo=1e-4, max_cg=500, gauss_newton=False):
+        opts = NewtonOpts(rel_tol=rel_tol, abs_tol=abs_tol, max_iter=max_iter,
+                          max_backtrack=max_backtrack, c_armijo=c_armijo, max_cg=max_cg,
+                          gauss_newton=int(gauss_newton))
+        info = NewtonInfo()
+        rc = self.lib.hinv_map_newton(self.h, None if m0 is None else _ptr(m0), _ptr(m_map),
+                                      C.byref(opts), C.byref(info))
+        self._check(rc, allow=(HINV_ENOCONV, HINV_ESTATE))
+        return info.as_dict() | {"rc": rc}
+
+    def lowrank_eig(self, omega, k, V, mode=HESS_MISFIT, tprod=TPROD_FP64):
+        po, s, ldo = _cols(omega, self.n)
+        pv, kv, ldv = _cols(V, self.n)
+        assert kv >= k
+        lam = (C.c_double * k)()
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_lowrank_eig(self.h, mode, tprod, s, po, ldo, k, lam, pv, ldv,
+                                                   C.byref(info)))
+        return np.array(lam[:]), info.as_dict() | {"rc": rc}
+
+    def posterior_sample(self, m_map, lam, V, eta, out):
+        k = len(lam)
+        lam_arr = (C.c_double * max(k, 1))(*[float(x) for x in lam])
+        pv, _, ldv = _cols(V, self.n)
+        pe, ns, lde = _cols(eta, 6 * self.N * self.N)
+        po, _, ldo = _cols(out, self.n)
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_posterior_sample(self.h, _ptr(m_map), k, lam_arr, pv, ldv, ns,
+                                                        pe, lde, po, ldo, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+
+def default_beta(gamma, delta):
+    return math.sqrt(gamma * delta) / 1.42

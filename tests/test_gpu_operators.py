@@ -1,0 +1,162 @@
+"""GPU parity of the operators behind the C ABI against the FP64 oracle.
+
+Tolerance: relative 2-norm error <= 1e-8 for quantities that the GPU reaches
+by iterative solves to a 1e-10 relative residual (the oracle solves exactly);
+1e-12 for quantities without a solve (operator applies, cost).  Both solver
+precisions (FP64 and FP32 inside FP64 refinement) must meet the same bar.
+"""
+import numpy as np
+import pytest
+
+import synth
+from cases import col_rel, instance, rel
+from oracle import model
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hv = pytest.importorskip("paper_1909_03948_amd.hinv")
+
+PRECS = [hv.PREC_FP64, hv.PREC_FP32_IR]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] creating context", flush=True)
+    return hv.Context(0)
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def gpu_problem(ctx, prob, obs, precision=hv.PREC_FP64, **kw):
+    return hv.Problem(ctx, prob.N, prob.gamma, prob.delta, obs_xy=obs, d_obs=prob.d,
+                      sigma=prob.sigma, m_prior=prob.m_pr[0], beta=prob.beta,
+                      precision=precision, rtol=1e-10, **kw)
+
+
+def point(prob, N, seed=3):
+    return prob.m_pr + 0.7 * synth.smooth_field(N, seed=seed)
+
+
+@pytest.mark.parametrize("N,q", [(32, 100), (256, 400)])
+@pytest.mark.parametrize("prec", PRECS)
+def test_forward_cost_gradient(ctx, N, q, prec):
+    print(f"[gpu] forward/gradient N={N} prec={prec}", flush=True)
+    prob, m_true, obs = instance(N, q)
+    gp = gpu_problem(ctx, prob, obs, prec)
+    m = point(prob, N)
+    u_o = prob.forward(m)
+    p_o = prob.adjoint(m, u_o)
+    g_o = prob.gradient(m, u_o, p_o)
+    _, mis_o, reg_o = prob.cost(m, u_o)
+    md, ud, pd, gd = dev(m), dev(np.zeros(prob.n)), dev(np.zeros(prob.n)), dev(np.zeros(prob.n))
+    info = gp.forward(md, ud)
+    assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
+    assert rel(host(ud), u_o) < 1e-8
+    mis, reg = gp.cost(md, ud)
+    assert abs(mis - mis_o) <= 1e-8 * abs(mis_o)
+    assert abs(reg - reg_o) <= 1e-10 * abs(reg_o)
+    info = gp.gradient(md, ud, pd, gd)
+    assert info["rc"] == 0, info
+    assert rel(host(pd), p_o) < 1e-8
+    assert rel(host(gd), g_o) < 1e-8
+    # exact data-consistent cost at the truth: u(m_true) reproduces B u_true
+    Bu = dev(np.zeros(q))
+    gp.forward(dev(m_true), ud)
+    gp.observe(ud, Bu)
+    assert rel(host(Bu), prob.B @ prob.forward(m_true)) < 1e-9
+
+
+@pytest.mark.parametrize("N,q,nc", [(32, 100, 1), (32, 100, 7), (256, 400, 5)])
+@pytest.mark.parametrize("prec", PRECS)
+def test_hessian_modes(ctx, N, q, nc, prec):
+    print(f"[gpu] hessian N={N} nc={nc} prec={prec}", flush=True)
+    prob, _, obs = instance(N, q)
+    gp = gpu_problem(ctx, prob, obs, prec)
+    m = point(prob, N)
+    u = prob.forward(m)
+    p = prob.adjoint(m, u)
+    gp.linearize(dev(m), dev(u), dev(p))
+    ld = prob.n + 3  # padded leading dimension
+    mh = np.zeros((nc, ld))
+    mh[:, :prob.n] = synth.test_vectors(prob.n, nc, stream=21)
+    out = dev(np.full((nc, ld), 7.0))
+    for mode in (model.HESS_FULL, model.HESS_MISFIT, model.HESS_GN_FULL, model.HESS_GN_MISFIT):
+        info = gp.hessian_apply(mode, dev(mh), out)
+        assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
+        ref = np.array([prob.hessian_apply(m, u, p, mh[c, :prob.n], mode) for c in range(nc)])
+        res = host(out)
+        assert col_rel(res[:, :prob.n], ref) < 1e-8, mode
+        assert np.all(res[:, prob.n:] == 7.0)  # padding untouched
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_incremental_solves(ctx, prec):
+    N, q, nc = 32, 100, 3
+    prob, _, obs = instance(N, q)
+    gp = gpu_problem(ctx, prob, obs, prec)
+    m = point(prob, N)
+    u = prob.forward(m)
+    p = prob.adjoint(m, u)
+    gp.linearize(dev(m), dev(u), dev(p))
+    mh = synth.test_vectors(prob.n, nc, stream=22)
+    uh = dev(np.zeros((nc, prob.n)))
+    ph = dev(np.zeros((nc, prob.n)))
+    gp.inc_forward(dev(mh), uh)
+    uh_o = np.array([prob.inc_forward(m, u, v) for v in mh])
+    assert col_rel(host(uh), uh_o) < 1e-8
+    for gn in (False, True):
+        gp.inc_adjoint(dev(mh), uh, ph, gauss_newton=gn)
+        ph_o = np.array([prob.inc_adjoint(m, p, v, w, gauss_newton=gn) for v, w in zip(mh, uh_o)])
+        assert col_rel(host(ph), ph_o) < 1e-8
+
+
+@pytest.mark.parametrize("N", [4, 32, 256])
+def test_prior_apply_solve_sample(ctx, N):
+    print(f"[gpu] prior N={N}", flush=True)
+    prob, _, obs = instance(N, 10)
+    gp = gpu_problem(ctx, prob, obs)
+    nc = 4
+    x = synth.test_vectors(prob.n, nc, stream=23)
+    y = dev(np.zeros((nc, prob.n)))
+    gp.prior_apply(dev(x), y)
+    assert col_rel(host(y), np.array([prob.R_apply(v) for v in x])) < 1e-10
+    info = gp.prior_solve(dev(x), y)
+    assert info["rc"] == 0
+    assert col_rel(host(y), np.array([prob.R_solve(v) for v in x])) < 1e-8
+    eta = synth.white_noise(N, 3, stream=synth.STREAM_POST)
+    out = dev(np.zeros((3, prob.n)))
+    gp.prior_sample(dev(eta), out)
+    assert col_rel(host(out), np.array([prob.prior_sample(e) for e in eta])) < 1e-8
+
+
+def test_no_observations_and_empty_batches(ctx):
+    prob, _, _ = instance(8, 5)
+    gp = hv.Problem(ctx, 8, prob.gamma, prob.delta, obs_xy=None, sigma=0.01, beta=prob.beta)
+    m = point(prob, 8)
+    ud = dev(np.zeros(prob.n))
+    gp.forward(dev(m), ud)
+    ref = model.Problem(8, prob.gamma, prob.delta, beta=prob.beta).forward(m)
+    assert rel(host(ud), ref) < 1e-8
+    mis, reg = gp.cost(dev(m), ud)
+    assert mis == 0.0
+    empty = dev(np.zeros((0, prob.n)))
+    gp.prior_apply(empty, empty)
+
+
+def test_argument_errors(ctx):
+    prob, _, obs = instance(32, 100)
+    with pytest.raises(hv.HinvError) as e:
+        hv.Problem(ctx, 30, 0.1, 0.5, obs_xy=obs, sigma=0.01)
+    assert e.value.code == hv.HINV_EINVAL
+    gp = gpu_problem(ctx, prob, obs)
+    with pytest.raises(hv.HinvError) as e:
+        gp.hessian_apply(hv.HESS_FULL, dev(np.zeros(prob.n)), dev(np.zeros(prob.n)))
+    assert e.value.code == hv.HINV_ESTATE
