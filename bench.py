@@ -1,0 +1,178 @@
+"""Benchmark: Hessian-vector products/s at a 1e-10 residual and time to MAP +
+rank-k posterior, on one MI355X.
+
+One step = the whole hot path on the 256 x 256 Poisson coefficient-inversion
+workload (66 049 parameters, 400 observations, bilaplacian prior gamma = 0.1,
+delta = 0.5): inexact Newton-CG from the prior mean to |g| <= 1e-6 |g_0|, then
+the double-pass randomized eigensolver with k = 50, p = 20 (all 70 probe
+vectors in one batched multi-right-hand-side solve per pass).  Every state
+solve reaches a relative residual of 1e-10 (FP32 multigrid-PCG inside FP64
+refinement); the eigensolver's block product Q^T (A Q) runs on BF16 matrix
+cores with FP32 accumulation.
+
+value = Hessian-vector products completed in the timed steps / wall time
+(each Newton-CG Hessian action and each eigensolver column counts one).
+ms_per_step = time to MAP + rank-k posterior.  Inputs (probe matrix, data) are
+resident on the device before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+WORKLOAD = "poisson256"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def setup_gpu(cfg, precision, seed=synth.MASTER_SEED):
+    import torch
+    from paper_1909_03948_amd import hinv as hv
+    N, q = cfg["N"], cfg["q"]
+    n = (N + 1) ** 2
+    ctx = hv.Context(0)
+    obs = synth.obs_points(q, seed=seed)
+    prob = hv.Problem(ctx, N, cfg["gamma"], cfg["delta"], obs_xy=obs, d_obs=None, sigma=0.01,
+                      m_prior=cfg["m_prior"], precision=precision, rtol=1e-10)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    # synthetic truth: a prior draw; data = B u(m_true) + 1% noise (Sec. 5.1)
+    m_true = dev(np.zeros(n))
+    prob.prior_sample(dev(synth.white_noise(N, seed=seed)), m_true)
+    u_true = dev(np.zeros(n))
+    prob.forward(m_true, u_true)
+    Bu = dev(np.zeros(q))
+    prob.observe(u_true, Bu)
+    torch.cuda.synchronize()
+    sigma = 0.01 * float(u_true.abs().max())
+    d = Bu.cpu().numpy() + sigma * synth.obs_noise(q, seed=seed)
+    prob.set_data(d, sigma)
+    s = cfg["k"] + cfg["p"]
+    omega = dev(synth.omega(n, s, seed=seed))
+    torch.cuda.synchronize()
+    return ctx, prob, omega, dict(n=n, sigma=sigma)
+
+
+def run_step(prob, omega, cfg, tprod, m_map, V):
+    from paper_1909_03948_amd import hinv as hv
+    t0 = time.perf_counter()
+    ninfo = prob.map_newton(m_map, rel_tol=1e-6)
+    t1 = time.perf_counter()
+    lam, einfo = prob.lowrank_eig(omega, cfg["k"], V, mode=hv.HESS_MISFIT, tprod=tprod)
+    t2 = time.perf_counter()
+    s = cfg["k"] + cfg["p"]
+    hvps = ninfo["hessian_applies"] + 2 * s
+    return dict(hvps=hvps, newton_s=t1 - t0, eig_s=t2 - t1, newton=ninfo, eig=einfo, lam=lam)
+
+
+def cpu_baseline(cfg, budget_s=20.0):
+    """Oracle HVPs (misfit part) at the true parameter of the same workload,
+    factorization reused, until the time budget is spent."""
+    from oracle import model
+    N, q = cfg["N"], cfg["q"]
+    prob, m_true, _ = model.make_instance(dict(N=N, q=q, gamma=cfg["gamma"], delta=cfg["delta"],
+                                               m_prior=cfg["m_prior"]), synth.MASTER_SEED,
+                                          synth.white_noise(N)[0], synth.obs_points(q),
+                                          synth.obs_noise(q))
+    u = prob.forward(m_true)
+    p = prob.adjoint(m_true, u)
+    dirs = synth.test_vectors(prob.n, 64, stream=synth.STREAM_OMEGA)
+    prob.hessian_apply(m_true, u, p, dirs[0], model.HESS_MISFIT)  # factorization outside timing
+    count, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and count < len(dirs):
+        prob.hessian_apply(m_true, u, p, dirs[count], model.HESS_MISFIT)
+        count += 1
+    dt = time.perf_counter() - t0
+    return dict(value=count / dt, unit="HVP/s", cores=1, kind="oracle",
+                sample=f"{count} misfit Hessian actions of the {WORKLOAD} workload at the true "
+                       f"parameter, sparse LU of A(m) reused, {dt:.1f} s single-threaded SuperLU")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32ir", "fp64"], default="fp32ir")
+    ap.add_argument("--tprod", choices=["bf16", "fp64"], default="bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the hot path is a "
+                                   "single-GPU workload (multi-GPU sharding is design-only)",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1909_03948_amd import hinv as hv
+    cfg = synth.WORKLOADS[WORKLOAD]
+    prec = hv.PREC_FP32_IR if a.precision == "fp32ir" else hv.PREC_FP64
+    tprod = hv.TPROD_BF16 if a.tprod == "bf16" else hv.TPROD_FP64
+    log("setup", WORKLOAD, a.precision, a.tprod)
+    ctx, prob, omega, meta = setup_gpu(cfg, prec)
+    n = meta["n"]
+    m_map = torch.zeros(n, dtype=torch.float64, device="cuda")
+    V = torch.zeros((cfg["k"], n), dtype=torch.float64, device="cuda")
+    for w in range(a.warmup):
+        r = run_step(prob, omega, cfg, tprod, m_map, V)
+        log(f"warmup {w}: newton {r['newton_s']:.3f}s ({r['newton']['iterations']} it, "
+            f"{r['newton']['hessian_applies']} HVP) eig {r['eig_s']:.3f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for k in range(a.steps):
+        res.append(run_step(prob, omega, cfg, tprod, m_map, V))
+        log(f"step {k}: newton {res[-1]['newton_s']:.3f}s eig {res[-1]['eig_s']:.3f}s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    hvps = sum(r["hvps"] for r in res)
+    s = cfg["k"] + cfg["p"]
+    eig_s = sum(r["eig_s"] for r in res)
+    newton_s = sum(r["newton_s"] for r in res)
+    line = {
+        "metric": "Hessian-vector products/sec at 1e-10 residual; time to MAP + rank-k posterior",
+        "value": hvps / dt,
+        "unit": "HVP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32+fp64 refinement (bf16 block product)" if prec == hv.PREC_FP32_IR else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "N": cfg["N"], "n_params": n, "q": cfg["q"],
+                   "gamma": cfg["gamma"], "delta": cfg["delta"], "k": cfg["k"], "p": cfg["p"],
+                   "rtol": 1e-10, "newton_rel_tol": 1e-6, "precision": a.precision,
+                   "tprod": a.tprod},
+        "time_to_map_plus_posterior_s": dt / a.steps,
+        "newton_s_per_step": newton_s / a.steps,
+        "eigensolver_s_per_step": eig_s / a.steps,
+        "batched_hvp_per_s": 2 * s * a.steps / eig_s,
+        "newton_iterations": res[-1]["newton"]["iterations"],
+        "newton_hvps": res[-1]["newton"]["hessian_applies"],
+        "lambda_1": float(res[-1]["lam"][0]),
+        "lambda_k": float(res[-1]["lam"][-1]),
+    }
+    if not a.no_cpu_baseline:
+        log("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(cfg, a.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
