@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32ir", "fp64"], default="fp32ir")
+    ap.add_argument("--precision", choices=["auto", "fp32ir", "fp64"], default="auto")
     ap.add_argument("--tprod", choices=["bf16", "fp64"], default="bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -119,7 +119,7 @@ def main():
     import torch
     from paper_1909_03948_amd import hinv as hv
     cfg = synth.WORKLOADS[WORKLOAD]
-    prec = hv.PREC_FP32_IR if a.precision == "fp32ir" else hv.PREC_FP64
+    prec = {"auto": hv.PREC_AUTO, "fp32ir": hv.PREC_FP32_IR, "fp64": hv.PREC_FP64}[a.precision]
     tprod = hv.TPROD_BF16 if a.tprod == "bf16" else hv.TPROD_FP64
     log("setup", WORKLOAD, a.precision, a.tprod)
     ctx, prob, omega, meta = setup_gpu(cfg, prec)
@@ -153,7 +153,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32+fp64 refinement (bf16 block product)" if prec == hv.PREC_FP32_IR else "f64",
+        "dtype": {"auto": "f64 (single rhs) / f32 in f64 refinement (batched), bf16 block product",
+                  "fp32ir": "f32 in f64 refinement, bf16 block product",
+                  "fp64": "f64"}[a.precision] if a.tprod == "bf16" or a.precision != "fp64" else "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "N": cfg["N"], "n_params": n, "q": cfg["q"],
                    "gamma": cfg["gamma"], "delta": cfg["delta"], "k": cfg["k"], "p": cfg["p"],

@@ -74,6 +74,8 @@ extern "C" {
 /* solver precision */
 #define HINV_PREC_FP64     0  /* FP64 multigrid-preconditioned CG */
 #define HINV_PREC_FP32_IR  1  /* FP32 multigrid-PCG inside FP64 iterative refinement */
+#define HINV_PREC_AUTO     2  /* per call: FP64 below 8 right-hand sides (latency bound),
+                                 FP32_IR from 8 up (bandwidth bound) */
 
 /* precision of the T = Q^T (A Q) block product of the eigensolver */
 #define HINV_TPROD_FP64    0  /* FP64 matrix cores */

@@ -126,7 +126,7 @@ int hinv_problem_create(hinv_ctx* c, const hinv_problem_desc* d, hinv_problem** 
         REQUIRE(d->q >= 0, "q must be >= 0");
         REQUIRE(d->q == 0 || d->obs_xy, "obs_xy is required when q > 0");
         REQUIRE(d->sigma > 0, "sigma must be positive");
-        REQUIRE(d->precision == HINV_PREC_FP64 || d->precision == HINV_PREC_FP32_IR, "bad precision");
+        REQUIRE(d->precision >= HINV_PREC_FP64 && d->precision <= HINV_PREC_AUTO, "bad precision");
         REQUIRE(d->rtol > 0 && d->rtol < 1, "rtol must be in (0, 1)");
         for (int o = 0; o < d->q; ++o) {
             const double x = d->obs_xy[2 * o], y = d->obs_xy[2 * o + 1];
@@ -163,7 +163,7 @@ int hinv_set_data(hinv_problem* p, const double* d_obs, double sigma) {
 int hinv_set_solver(hinv_problem* p, int precision, double rtol, int max_iter) {
     if (!p) return HINV_EINVAL;
     return guarded(ctx_of(p), [&] {
-        REQUIRE(precision == HINV_PREC_FP64 || precision == HINV_PREC_FP32_IR, "bad precision");
+        REQUIRE(precision >= HINV_PREC_FP64 && precision <= HINV_PREC_AUTO, "bad precision");
         REQUIRE(rtol > 0 && rtol < 1, "rtol must be in (0, 1)");
         p->p->precision = precision;
         p->p->rtol = rtol;

@@ -74,6 +74,7 @@ struct Ctx {
 // ------------------------------------------------------------ constants ---
 constexpr int kBlock = 256;   // threads per workgroup for grid kernels
 constexpr int kCoarseMaxN = 8;  // coarsest multigrid level has N_c <= 8
+constexpr int kAutoBatch = 8;   // HINV_PREC_AUTO switches to FP32 refinement from this many columns
 
 // Chebyshev smoother: degree 2, targets the interval [0.5, 2] of the
 // Jacobi-scaled operator (2 bounds the spectrum by Gershgorin for both the

@@ -41,6 +41,10 @@ struct OpA {
     const T* dinv;  // 1 / diagonal on free nodes, 0 on Dirichlet nodes
     __device__ bool is_free(int, int j) const { return j > 0 && j < N; }
     __device__ T inv_diag(int, int, int k) const { return dinv[k]; }
+    // diagonal of a free row: sum of the four incident edge weights
+    __device__ T diag(int i, int, int k) const {
+        return (i < N ? wE[k] : (T)0) + (i > 0 ? wE[k - 1] : (T)0) + wN[k] + wN[k - N - 1];
+    }
     // Row k of A_FF applied to the vector given by xat(i, j, k); call on free nodes only.
     template <class F>
     __device__ T apply(int i, int j, int k, F xat) const {
@@ -80,6 +84,8 @@ template <typename T>
 struct OpKA {
     int N;
     double h, g, dl, bt;
+    // interior row (0 < i, j < N), identical at every interior node
+    T ic, iax, imass, idiag_inv;  // diagonal, axis neighbour, diagonal neighbour, 1/diagonal
     __device__ bool is_free(int, int) const { return true; }
     struct Row {
         double c, e, w, n, s, ne, sw;
@@ -106,11 +112,20 @@ struct OpKA {
               bt * (h / 3.0) * nbe;
         return r;
     }
-    __device__ T inv_diag(int i, int j, int) const { return (T)(1.0 / row(i, j).c); }
+    __device__ bool interior(int i, int j) const { return i > 0 && i < N && j > 0 && j < N; }
+    __device__ T inv_diag(int i, int j, int) const {
+        return interior(i, j) ? idiag_inv : (T)(1.0 / row(i, j).c);
+    }
+    __device__ T diag(int i, int j, int) const { return interior(i, j) ? ic : (T)row(i, j).c; }
     template <class F>
     __device__ T apply(int i, int j, int k, F xat) const {
-        const Row r = row(i, j);
         const int N1 = N + 1;
+        if (interior(i, j))
+            return ic * xat(i, j, k) +
+                   iax * (xat(i + 1, j, k + 1) + xat(i - 1, j, k - 1) + xat(i, j + 1, k + N1) +
+                          xat(i, j - 1, k - N1)) +
+                   imass * (xat(i + 1, j + 1, k + N1 + 1) + xat(i - 1, j - 1, k - N1 - 1));
+        const Row r = row(i, j);
         T acc = (T)r.c * xat(i, j, k);
         if (i < N) acc += (T)r.e * xat(i + 1, j, k + 1);
         if (i > 0) acc += (T)r.w * xat(i - 1, j, k - 1);
@@ -121,6 +136,26 @@ struct OpKA {
         return acc;
     }
 };
+
+// Builds the prior operator of a level with its interior row precomputed.
+template <typename T>
+__host__ __device__ inline OpKA<T> make_prior_op(int N, double g, double dl, double bt) {
+    OpKA<T> o;
+    o.N = N;
+    o.h = 1.0 / N;
+    o.g = g;
+    o.dl = dl;
+    o.bt = bt;
+    const double h2 = o.h * o.h;
+    // interior: axis edges touch 2 triangles (K weight 1, M entry h^2/12),
+    // diagonal neighbours h^2/12, 6 triangles (M diagonal h^2/2), no boundary term
+    const double c = g * 4.0 + dl * 6.0 * h2 / 12.0;
+    o.ic = (T)c;
+    o.iax = (T)(-g + dl * 2.0 * h2 / 24.0);
+    o.imass = (T)(dl * h2 / 12.0);
+    o.idiag_inv = (T)(1.0 / c);
+    return o;
+}
 
 // ------------------------------------------------------------ triangles ---
 // Node indices (a, r, b) of triangle s (0 lower, 1 upper) of cell (ci, cj).

@@ -1,0 +1,480 @@
+// Fused multigrid V-cycle and PCG kernels (included by solver.hip only).
+//
+// V-cycle, per level above the bottom (N_l > kBottomN), two LDS-tiled kernels:
+//   k_down: x2 = S(b) (two Chebyshev steps from zero), r = b - A x2, b_coarse = P^T r
+//   k_up:   x = x2 + P x_coarse, then two Chebyshev steps on A x = b
+// and one kernel for all levels with N_l <= kBottomN (one workgroup per column,
+// every vector in LDS, the coarsest level solved with its dense inverse).
+// PCG reductions finish in the producing kernel: the last workgroup of a column
+// to arrive sums the per-workgroup partials in a fixed order.
+#pragma once
+
+#include "grid.h"
+#include "solver.h"
+
+namespace hinv {
+
+// Tile sides: large tiles (less halo work) for batches, small tiles (more
+// workgroups) when few columns make the V-cycle latency bound.
+constexpr int kTCBig = 16, kTFBig = 32;      // coarse / fine nodes per tile side
+constexpr int kTCSmall = 8, kTFSmall = 16;
+constexpr int kSmallTileCols = 8;            // batches below this use the small tiles
+constexpr int kBottomN = 32;   // levels with N_l <= kBottomN run in the bottom kernel
+constexpr int kBottomNodes = 33 * 33 + 17 * 17 + 9 * 9;  // vector length of all bottom levels
+constexpr int kBottomLevels = 3;
+
+// Chebyshev degree-2 coefficients passed to the smoothing kernels.
+struct ChebCoef {
+    double inv_theta, theta, cA, cB, c1;  // pre: x = cA d0 + cB D^-1 r1; post: (1 + c1) d0 + cB D^-1 r1
+};
+
+// In-kernel reductions: every workgroup writes one partial sum per column to
+// part[col * stride + blk]; a later kernel (after the kernel boundary, so no
+// fences are needed) sums them in a fixed order.
+__device__ inline double partial_total(const double* part, int col, int stride, int nblk) {
+    __shared__ double ps[16];
+    __shared__ double tot;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)col * stride + b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) ps[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += ps[w];
+        tot = t;
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Partial-sum buffers of the PCG inner products ([ncols][stride] each).
+struct PcgRed {
+    double* rz;
+    double* pq;
+    double* rr;
+    int stride;
+    int nrz;  // number of partials of r^T z (workgroups of the last V-cycle kernel)
+    int nvec; // number of partials of p^T q and r^T r
+};
+
+// Workgroup sum with its own LDS slot; result valid in thread 0.
+__device__ inline double group_sum(double v) {
+    __shared__ double part[16];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += part[w];
+    return r;
+}
+
+// Convergence test at the start of a V-cycle: r^T r of the PCG update that
+// precedes it is summed from its partials; a column at its tolerance stops
+// (every workgroup reaches the same decision; workgroup 0 records it).
+__device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int* act, bool lead) {
+    const double rr = partial_total(red.rr, col, red.stride, red.nvec);
+    const ColState& c = st[col];
+    const bool done = rr <= c.tol2 * c.bb;
+    if (lead && threadIdx.x == 0) {
+        st[col].rr = rr;
+        if (done) act[col] = 0;
+    }
+    return done;
+}
+
+// --------------------------------------------------------------- k_down ---
+// Grid: (tiles over coarse x, tiles over coarse y, columns).  Coarse tile
+// [I0, I0+kTC) x [J0, J0+kTC) needs the fine residual on [2 I0 - 1, 2 I1 + 1],
+// hence x2 one node further out and b two nodes further out.
+template <typename T, class Op, int kTC>
+__global__ __launch_bounds__(256) void k_down(Op op, const T* __restrict__ b, T* __restrict__ x,
+                                              int ld, T* __restrict__ bc, int ldc, int dirichlet,
+                                              int* __restrict__ act, ChebCoef cc, PcgRed red,
+                                              ColState* __restrict__ st, int check) {
+    const int col = blockIdx.z;
+    if (act && !act[col]) return;
+    if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) return;
+    constexpr int TW = 2 * kTC + 5;
+    __shared__ T sb[TW * TW];
+    __shared__ T sx[TW * TW];
+    __shared__ T sr[TW * TW];
+    const int N = op.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
+    const int I0 = blockIdx.x * kTC, J0 = blockIdx.y * kTC;
+    const int I1 = min(I0 + kTC - 1, Nc), J1 = min(J0 + kTC - 1, Nc);
+    const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // global coordinates of local (0, 0)
+    const T* bcol = b + (size_t)col * ld;
+    T* xcol = x + (size_t)col * ld;
+    const T inv_theta = (T)cc.inv_theta, cA = (T)cc.cA, cB = (T)cc.cB;
+    auto in_dom = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
+    auto loc = [&](int i, int j) { return (j - oy) * TW + (i - ox); };
+    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
+        const int i = ox + t % TW, j = oy + t / TW;
+        sb[t] = in_dom(i, j) ? bcol[j * N1 + i] : (T)0;
+    }
+    __syncthreads();
+    // x2 on local [1, TW-1)^2; written to global on the owned fine nodes
+    const int own_i1 = min(2 * I1 + 1, N), own_j1 = min(2 * J1 + 1, N);
+    for (int t = threadIdx.x; t < (TW - 2) * (TW - 2); t += blockDim.x) {
+        const int i = ox + 1 + t % (TW - 2), j = oy + 1 + t / (TW - 2);
+        T v = 0;
+        if (in_dom(i, j) && op.is_free(i, j)) {
+            const int k = j * N1 + i;
+            auto d0 = [&](int ii, int jj, int kk) { return op.inv_diag(ii, jj, kk) * sb[loc(ii, jj)] * inv_theta; };
+            const T dk = d0(i, j, k);
+            const T r1 = sb[loc(i, j)] - op.apply(i, j, k, d0);
+            v = cA * dk + cB * op.inv_diag(i, j, k) * r1;
+        }
+        sx[loc(i, j)] = v;
+        if (i >= 2 * I0 && i <= own_i1 && j >= 2 * J0 && j <= own_j1) xcol[j * N1 + i] = v;
+    }
+    __syncthreads();
+    // residual on local [2, TW-2)^2
+    for (int t = threadIdx.x; t < (TW - 4) * (TW - 4); t += blockDim.x) {
+        const int i = ox + 2 + t % (TW - 4), j = oy + 2 + t / (TW - 4);
+        T v = 0;
+        if (in_dom(i, j) && op.is_free(i, j))
+            v = sb[loc(i, j)] - op.apply(i, j, j * N1 + i, [&](int ii, int jj, int) { return sx[loc(ii, jj)]; });
+        sr[loc(i, j)] = v;
+    }
+    __syncthreads();
+    // restriction P^T onto the coarse tile
+    T* bccol = bc + (size_t)col * ldc;
+    const int cw = I1 - I0 + 1, ch = J1 - J0 + 1;
+    for (int t = threadIdx.x; t < cw * ch; t += blockDim.x) {
+        const int I = I0 + t % cw, J = J0 + t / cw;
+        T v = 0;
+        if (!(dirichlet && (J == 0 || J == Nc))) {
+            const int i = 2 * I, j = 2 * J;
+            T s = 0;
+            if (i > 0) s += sr[loc(i - 1, j)];
+            if (i < N) s += sr[loc(i + 1, j)];
+            if (j > 0) s += sr[loc(i, j - 1)];
+            if (j < N) s += sr[loc(i, j + 1)];
+            if (i < N && j < N) s += sr[loc(i + 1, j + 1)];
+            if (i > 0 && j > 0) s += sr[loc(i - 1, j - 1)];
+            v = sr[loc(i, j)] + (T)0.5 * s;
+        }
+        bccol[J * Nc1 + I] = v;
+    }
+}
+
+// ----------------------------------------------------------------- k_up ---
+// Grid: (tiles over fine x, tiles over fine y, columns).  Fine tile O of
+// kTF x kTF nodes; x = x2 + P x_coarse is formed two nodes around O (x2 is
+// read from its own buffer: neighbouring workgroups write the output), the first
+// Chebyshev correction d0 one node around O.  Optionally writes the
+// workgroup's part of sum_k rv_k x_k (the PCG inner product r^T z).
+template <typename T, class Op, int kTF>
+__global__ __launch_bounds__(256) void k_up(Op op, const T* __restrict__ b, const T* __restrict__ x2,
+                                            T* __restrict__ x, int ld, const T* __restrict__ xc,
+                                            int ldc, int dirichlet,
+                                            const int* __restrict__ act, ChebCoef cc,
+                                            const T* __restrict__ rv, PcgRed red) {
+    const int col = blockIdx.z;
+    if (act && !act[col]) return;
+    constexpr int TW = kTF + 4;
+    __shared__ T sx[TW * TW];
+    __shared__ T sd[TW * TW];
+    const int N = op.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
+    const int i0 = blockIdx.x * kTF, j0 = blockIdx.y * kTF;
+    const int i1 = min(i0 + kTF - 1, N), j1 = min(j0 + kTF - 1, N);
+    const int ox = i0 - 2, oy = j0 - 2;
+    const T* bcol = b + (size_t)col * ld;
+    const T* x2col = x2 + (size_t)col * ld;
+    T* xcol = x + (size_t)col * ld;
+    const T* ccol = xc + (size_t)col * ldc;
+    const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
+    auto in_dom = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
+    auto loc = [&](int i, int j) { return (j - oy) * TW + (i - ox); };
+    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
+        const int i = ox + t % TW, j = oy + t / TW;
+        T v = 0;
+        if (in_dom(i, j) && !(dirichlet && (j == 0 || j == N))) {
+            const int I = i >> 1, J = j >> 1;
+            T p;
+            if (!(i & 1) && !(j & 1))
+                p = ccol[J * Nc1 + I];
+            else if (!(j & 1))
+                p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[J * Nc1 + I + 1]);
+            else if (!(i & 1))
+                p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[(J + 1) * Nc1 + I]);
+            else
+                p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[(J + 1) * Nc1 + I + 1]);
+            v = x2col[j * N1 + i] + p;
+        }
+        sx[t] = v;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < (TW - 2) * (TW - 2); t += blockDim.x) {
+        const int i = ox + 1 + t % (TW - 2), j = oy + 1 + t / (TW - 2);
+        T d = 0;
+        if (in_dom(i, j) && op.is_free(i, j)) {
+            const int k = j * N1 + i;
+            const T r0 = bcol[k] - op.apply(i, j, k, [&](int ii, int jj, int) { return sx[loc(ii, jj)]; });
+            d = op.inv_diag(i, j, k) * r0 * inv_theta;
+        }
+        sd[loc(i, j)] = d;
+    }
+    __syncthreads();
+    double dot = 0.0;
+    const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+    for (int t = threadIdx.x; t < w * h; t += blockDim.x) {
+        const int i = i0 + t % w, j = j0 + t / w;
+        const int k = j * N1 + i;
+        T v = sx[loc(i, j)];
+        if (op.is_free(i, j)) {
+            const T dk = sd[loc(i, j)];
+            const T di = op.inv_diag(i, j, k);
+            const T r1 = theta * dk * op.diag(i, j, k) - op.apply(i, j, k, [&](int ii, int jj, int) { return sd[loc(ii, jj)]; });
+            v = v + ((T)1 + c1) * dk + cB * di * r1;
+        }
+        xcol[k] = v;
+        if (rv) dot += (double)v * (double)rv[(size_t)col * ld + k];
+    }
+    if (rv) {
+        const double s = group_sum(dot);
+        if (threadIdx.x == 0) red.rz[(size_t)col * red.stride + blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// -------------------------------------------------------------- bottom ---
+// All levels with N_l <= kBottomN for one column in one workgroup.
+template <typename T>
+struct BottomArgs {
+    int nlev;                       // levels handled here (the last is the coarsest)
+    int N[kBottomLevels];
+    const T* wE[kBottomLevels];     // state operator coefficients (unused for the prior)
+    const T* wN[kBottomLevels];
+    const T* dinv[kBottomLevels];
+    const T* cinv;                  // dense inverse of the coarsest level
+    int nc;                         // its size
+    PriorParams pp;
+};
+
+template <typename T, int KIND>
+__device__ inline auto bottom_op(const BottomArgs<T>& a, int l) {
+    if constexpr (KIND == kOpState) {
+        OpA<T> o;
+        o.N = a.N[l];
+        o.wE = a.wE[l];
+        o.wN = a.wN[l];
+        o.dinv = a.dinv[l];
+        return o;
+    } else {
+        return make_prior_op<T>(a.N[l], a.pp.gamma, a.pp.delta, a.pp.beta);
+    }
+}
+
+// x_top = V-cycle(b_top) for every column (blockIdx.x = column).  b and x are
+// global level-Lb vectors.  When rv is given (the bottom is the whole
+// hierarchy), sum_k rv_k x_k is written as the single partial of r^T z.
+template <typename T, int KIND>
+__global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg,
+                                                 int ld, int* __restrict__ act, ChebCoef cc,
+                                                 const T* __restrict__ rv, PcgRed red,
+                                                 ColState* __restrict__ st, int check) {
+    const int col = blockIdx.x;
+    if (act && !act[col]) return;
+    if (check && column_done(red, col, st, act, true)) return;
+    __shared__ T sb[kBottomNodes], sx[kBottomNodes], st_[kBottomNodes];
+    int off[kBottomLevels];
+    {
+        int o = 0;
+        for (int l = 0; l < a.nlev; ++l) {
+            off[l] = o;
+            o += (a.N[l] + 1) * (a.N[l] + 1);
+        }
+    }
+    const int dir = KIND == kOpState;
+    const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cA = (T)cc.cA, cB = (T)cc.cB, c1 = (T)cc.c1;
+    const int n0 = (a.N[0] + 1) * (a.N[0] + 1);
+    for (int k = threadIdx.x; k < n0; k += blockDim.x) sb[k] = bg[(size_t)col * ld + k];
+    __syncthreads();
+    const int L = a.nlev - 1;
+    // ---- down
+    for (int l = 0; l < L; ++l) {
+        const auto op = bottom_op<T, KIND>(a, l);
+        const int N = a.N[l], N1 = N + 1, n = N1 * N1;
+        T* b = sb + off[l];
+        T* x = sx + off[l];
+        T* t = st_ + off[l];
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int i = k % N1, j = k / N1;
+            T v = 0;
+            if (op.is_free(i, j)) {
+                auto d0 = [&](int ii, int jj, int kk) { return op.inv_diag(ii, jj, kk) * b[kk] * inv_theta; };
+                const T dk = d0(i, j, k);
+                v = cA * dk + cB * op.inv_diag(i, j, k) * (b[k] - op.apply(i, j, k, d0));
+            }
+            x[k] = v;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int i = k % N1, j = k / N1;
+            T v = 0;
+            if (op.is_free(i, j)) v = b[k] - op.apply(i, j, k, [&](int, int, int kk) { return x[kk]; });
+            t[k] = v;
+        }
+        __syncthreads();
+        const int Nc = N / 2, Nc1 = Nc + 1;
+        T* bcn = sb + off[l + 1];
+        for (int K = threadIdx.x; K < Nc1 * Nc1; K += blockDim.x) {
+            const int I = K % Nc1, J = K / Nc1;
+            T v = 0;
+            if (!(dir && (J == 0 || J == Nc))) {
+                const int i = 2 * I, j = 2 * J, k = j * N1 + i;
+                T s = 0;
+                if (i > 0) s += t[k - 1];
+                if (i < N) s += t[k + 1];
+                if (j > 0) s += t[k - N1];
+                if (j < N) s += t[k + N1];
+                if (i < N && j < N) s += t[k + N1 + 1];
+                if (i > 0 && j > 0) s += t[k - N1 - 1];
+                v = t[k] + (T)0.5 * s;
+            }
+            bcn[K] = v;
+        }
+        __syncthreads();
+    }
+    // ---- coarsest: dense inverse, 12 threads per row
+    {
+        const T* b = sb + off[L];
+        T* x = sx + off[L];
+        T* tmp = st_;  // level-0 scratch is free here
+        constexpr int S = 12;
+        for (int t = threadIdx.x; t < a.nc * S; t += blockDim.x) {
+            const int r = t / S, part = t % S;
+            T s = 0;
+            for (int c = part; c < a.nc; c += S) s += a.cinv[r * a.nc + c] * b[c];
+            tmp[t] = s;
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < a.nc; r += blockDim.x) {
+            T s = 0;
+            for (int part = 0; part < S; ++part) s += tmp[r * S + part];
+            x[r] = s;
+        }
+        __syncthreads();
+    }
+    // ---- up
+    for (int l = L - 1; l >= 0; --l) {
+        const auto op = bottom_op<T, KIND>(a, l);
+        const int N = a.N[l], N1 = N + 1, n = N1 * N1, Nc1 = N / 2 + 1;
+        T* b = sb + off[l];
+        T* x = sx + off[l];
+        T* t = st_ + off[l];
+        const T* c = sx + off[l + 1];
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int i = k % N1, j = k / N1;
+            if (dir && (j == 0 || j == N)) continue;
+            const int I = i >> 1, J = j >> 1;
+            T p;
+            if (!(i & 1) && !(j & 1))
+                p = c[J * Nc1 + I];
+            else if (!(j & 1))
+                p = (T)0.5 * (c[J * Nc1 + I] + c[J * Nc1 + I + 1]);
+            else if (!(i & 1))
+                p = (T)0.5 * (c[J * Nc1 + I] + c[(J + 1) * Nc1 + I]);
+            else
+                p = (T)0.5 * (c[J * Nc1 + I] + c[(J + 1) * Nc1 + I + 1]);
+            x[k] += p;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int i = k % N1, j = k / N1;
+            T d = 0;
+            if (op.is_free(i, j))
+                d = op.inv_diag(i, j, k) * (b[k] - op.apply(i, j, k, [&](int, int, int kk) { return x[kk]; })) * inv_theta;
+            t[k] = d;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int i = k % N1, j = k / N1;
+            if (!op.is_free(i, j)) continue;
+            const T dk = t[k];
+            const T di = op.inv_diag(i, j, k);
+            const T r1 = theta * dk * op.diag(i, j, k) - op.apply(i, j, k, [&](int, int, int kk) { return t[kk]; });
+            x[k] += ((T)1 + c1) * dk + cB * di * r1;
+        }
+        __syncthreads();
+    }
+    double dot = 0.0;
+    for (int k = threadIdx.x; k < n0; k += blockDim.x) {
+        const T v = sx[k];
+        xg[(size_t)col * ld + k] = v;
+        if (rv) dot += (double)v * (double)rv[(size_t)col * ld + k];
+    }
+    if (rv) {
+        const double s = group_sum(dot);
+        if (threadIdx.x == 0) red.rz[(size_t)col * red.stride] = s;
+    }
+}
+
+// ------------------------------------------------------------------ PCG ---
+// p_new = z + beta p_old with beta = (r^T z) / rz_old (p_new = z on the first
+// iteration), q = A p_new, partials of p_new^T q.
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_pcg_apply(Op op, const T* __restrict__ z, const T* __restrict__ p_old,
+                                                   T* __restrict__ p_new, T* __restrict__ q, int ld,
+                                                   const int* __restrict__ act, const ColState* __restrict__ st,
+                                                   PcgRed red, int first) {
+    const int col = blockIdx.y;
+    if (!act[col]) return;
+    const int N = op.N, N1 = N + 1, n = N1 * N1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    T beta = 0;
+    if (!first) beta = (T)(partial_total(red.rz, col, red.stride, red.nrz) / st[col].rz);
+    const T* zc = z + (size_t)col * ld;
+    const T* pc = p_old + (size_t)col * ld;
+    auto pn = [&](int, int, int kk) { return first ? zc[kk] : zc[kk] + beta * pc[kk]; };
+    double dot = 0.0;
+    if (k < n) {
+        const int i = k % N1, j = k / N1;
+        const T pk = pn(i, j, k);
+        T v = 0;
+        if (op.is_free(i, j)) v = op.apply(i, j, k, pn);
+        p_new[(size_t)col * ld + k] = pk;
+        q[(size_t)col * ld + k] = v;
+        dot = (double)pk * (double)v;
+    }
+    const double s = group_sum(dot);
+    if (threadIdx.x == 0) red.pq[(size_t)col * red.stride + blockIdx.x] = s;
+}
+
+// alpha = (r^T z) / (p^T q); x += alpha p, r -= alpha q; partials of r^T r.
+// Workgroup 0 records rz (the next beta's denominator) and alpha; a column
+// with p^T q <= 0 (breakdown) stops.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_update(T* __restrict__ x, T* __restrict__ r,
+                                                    const T* __restrict__ p, const T* __restrict__ q,
+                                                    int ld, int n, int* __restrict__ act,
+                                                    ColState* __restrict__ st, PcgRed red) {
+    const int col = blockIdx.y;
+    if (!act[col]) return;
+    const double rz = partial_total(red.rz, col, red.stride, red.nrz);
+    const double pq = partial_total(red.pq, col, red.stride, red.nvec);
+    const double alpha = pq > 0.0 ? rz / pq : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ColState& c = st[col];
+        c.rz = rz;
+        c.pq = pq;
+        c.alpha = alpha;
+        if (!(pq > 0.0)) act[col] = 0;
+    }
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0;
+    if (k < n) {
+        const size_t o = (size_t)col * ld + k;
+        const T a = (T)alpha;
+        x[o] += a * p[o];
+        const T rv = r[o] - a * q[o];
+        r[o] = rv;
+        rr = (double)rv * (double)rv;
+    }
+    const double s = group_sum(rr);
+    if (threadIdx.x == 0) red.rr[(size_t)col * red.stride + blockIdx.x] = s;
+}
+
+}  // namespace hinv

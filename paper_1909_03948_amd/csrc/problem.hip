@@ -300,13 +300,7 @@ __global__ void k_dot_finish(const double* __restrict__ partial, int nblk, doubl
 }
 
 OpKA<double> prior_op(int N, double g, double dl, double bt) {
-    OpKA<double> op;
-    op.N = N;
-    op.h = 1.0 / N;
-    op.g = g;
-    op.dl = dl;
-    op.bt = bt;
-    return op;
+    return make_prior_op<double>(N, g, dl, bt);
 }
 
 // Chebyshev iteration count for M: error factor 2 (1/3)^K <= 2e-15.

@@ -37,7 +37,7 @@ struct SolveStats {
 template <typename T>
 struct PcgWork {
     int cap = 0;  // columns
-    DBuf<T> x, r, z, p, q;
+    DBuf<T> x, r, z, p, p2, q;
     std::vector<std::unique_ptr<DBuf<T>>> lb, lx, lt;  // per level b, x, t
 };
 
@@ -72,7 +72,8 @@ class Hierarchy {
     template <typename T>
     void pcg(int nc, int max_iter, int* iters);
     template <typename T>
-    void vcycle(int l, int nc);
+    void vcycle(int nc, int check);
+    struct PcgRed pcg_red(int nc) const;
     template <typename T>
     PcgWork<T>& work();
     void ensure_cols(int nc);
@@ -91,6 +92,8 @@ class Hierarchy {
     int cap_ = 0;
     DBuf<double> x64_, r64_;
     DBuf<double> partial_;
+    DBuf<double> pcg_part_;  // partial sums of r^T z, p^T q, r^T r per workgroup and column
+    int red_stride_ = 0;
     DBuf<ColState> st_;
     DBuf<int> act_, oact_;
     DBuf<double> colnorm_;  // per column |r| used to scale the inner right-hand side

@@ -19,11 +19,11 @@
 //   * precision: the outer loop is FP64 iterative refinement,
 //     r = b - A x in FP64, inner PCG in FP64 or FP32 on r / |r|, x += |r| d,
 //     until |r| <= rtol |b| per column.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 
-#include "grid.h"
-#include "solver.h"
+#include "mgkernels.h"
 
 namespace hinv {
 
@@ -130,145 +130,6 @@ __global__ void k_apply(Op op, const T* __restrict__ x, int ldx, T* __restrict__
     }
 }
 
-// Pre-smoothing from a zero initial guess (two Chebyshev steps in one pass):
-// d0 = D^-1 b / theta, r1 = b - A d0, x = (1 + rho1 rho0) d0 + (2 rho1 / delta) D^-1 r1.
-template <typename T, class Op>
-__global__ void k_smooth_pre(Op op, const T* __restrict__ b, T* __restrict__ x, int ld,
-                             const int* __restrict__ act, T cA, T cB, T inv_theta) {
-    if (act && !act[blockIdx.y]) return;
-    const int N = op.N, N1 = N + 1, n = N1 * N1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int i = k % N1, j = k / N1;
-    const T* bc = col(b, ld);
-    T* xc = col(x, ld);
-    if (!op.is_free(i, j)) {
-        xc[k] = 0;
-        return;
-    }
-    auto d0 = [&](int ii, int jj, int kk) { return op.inv_diag(ii, jj, kk) * bc[kk] * inv_theta; };
-    const T dk = d0(i, j, k);
-    const T r1 = bc[k] - op.apply(i, j, k, d0);
-    xc[k] = cA * dk + cB * op.inv_diag(i, j, k) * r1;
-}
-
-template <typename T, class Op>
-__global__ void k_residual(Op op, const T* __restrict__ b, const T* __restrict__ x,
-                           T* __restrict__ r, int ld, const int* __restrict__ act) {
-    if (act && !act[blockIdx.y]) return;
-    const int N = op.N, N1 = N + 1, n = N1 * N1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int i = k % N1, j = k / N1;
-    const T* bc = col(b, ld);
-    const T* xc = col(x, ld);
-    T v = 0;
-    if (op.is_free(i, j)) v = bc[k] - op.apply(i, j, k, [&](int, int, int kk) { return xc[kk]; });
-    col(r, ld)[k] = v;
-}
-
-// Restriction P^T: coarse node (I,J) gathers fine (2I,2J) with weight 1 and its
-// six P1 neighbours (2I+-1,2J), (2I,2J+-1), (2I+1,2J+1), (2I-1,2J-1) with 1/2.
-template <typename T>
-__global__ void k_restrict(int Nc, const T* __restrict__ rf, int ldf, T* __restrict__ bc,
-                           int ldc, int dirichlet, const int* __restrict__ act) {
-    if (act && !act[blockIdx.y]) return;
-    const int Nc1 = Nc + 1, nc = Nc1 * Nc1;
-    const int K = blockIdx.x * blockDim.x + threadIdx.x;
-    if (K >= nc) return;
-    const int I = K % Nc1, J = K / Nc1;
-    T* out = col(bc, ldc);
-    if (dirichlet && (J == 0 || J == Nc)) {
-        out[K] = 0;
-        return;
-    }
-    const int Nf = 2 * Nc, Nf1 = Nf + 1;
-    const T* f = col(rf, ldf);
-    const int i = 2 * I, j = 2 * J, k = j * Nf1 + i;
-    T s = 0;
-    if (i > 0) s += f[k - 1];
-    if (i < Nf) s += f[k + 1];
-    if (j > 0) s += f[k - Nf1];
-    if (j < Nf) s += f[k + Nf1];
-    if (i < Nf && j < Nf) s += f[k + Nf1 + 1];
-    if (i > 0 && j > 0) s += f[k - Nf1 - 1];
-    out[K] = f[k] + (T)0.5 * s;
-}
-
-// x_fine += P x_coarse (P1 interpolation on the nested meshes).
-template <typename T>
-__global__ void k_prolong_add(int Nc, const T* __restrict__ xc, int ldc, T* __restrict__ xf,
-                              int ldf, int dirichlet, const int* __restrict__ act) {
-    if (act && !act[blockIdx.y]) return;
-    const int Nf = 2 * Nc, Nf1 = Nf + 1, nf = Nf1 * Nf1, Nc1 = Nc + 1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nf) return;
-    const int i = k % Nf1, j = k / Nf1;
-    if (dirichlet && (j == 0 || j == Nf)) return;
-    const T* c = col(xc, ldc);
-    T v;
-    const int I = i >> 1, J = j >> 1;
-    if (!(i & 1) && !(j & 1))
-        v = c[J * Nc1 + I];
-    else if (!(j & 1))
-        v = (T)0.5 * (c[J * Nc1 + I] + c[J * Nc1 + I + 1]);
-    else if (!(i & 1))
-        v = (T)0.5 * (c[J * Nc1 + I] + c[(J + 1) * Nc1 + I]);
-    else
-        v = (T)0.5 * (c[J * Nc1 + I] + c[(J + 1) * Nc1 + I + 1]);
-    col(xf, ldf)[k] += v;
-}
-
-// Post-smoothing, first Chebyshev step: r0 = b - A x, d0 = D^-1 r0 / theta, x += d0; t = d0.
-template <typename T, class Op>
-__global__ void k_post1(Op op, const T* __restrict__ b, T* __restrict__ x, T* __restrict__ t,
-                        int ld, const int* __restrict__ act, T inv_theta) {
-    if (act && !act[blockIdx.y]) return;
-    const int N = op.N, N1 = N + 1, n = N1 * N1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int i = k % N1, j = k / N1;
-    const T* bc = col(b, ld);
-    const T* xc = col((const T*)x, ld);
-    T d = 0;
-    if (op.is_free(i, j)) {
-        const T r0 = bc[k] - op.apply(i, j, k, [&](int, int, int kk) { return xc[kk]; });
-        d = op.inv_diag(i, j, k) * r0 * inv_theta;
-    }
-    col(t, ld)[k] = d;
-}
-
-// Second step (x still holds the value before the first step): r1 = r0 - A d0 with
-// r0 = theta D d0, x2 = x + d0 + rho1 rho0 d0 + (2 rho1/delta) D^-1 r1.
-// Optionally accumulates sum_k rv_k x_k per column (r^T z of the PCG).
-template <typename T, class Op>
-__global__ void k_post2(Op op, T* __restrict__ x, const T* __restrict__ t, int ld,
-                        const int* __restrict__ act, T theta, T c1, T c2,
-                        const T* __restrict__ rv, double* __restrict__ partial) {
-    if (act && !act[blockIdx.y]) return;
-    const int N = op.N, N1 = N + 1, n = N1 * N1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const T* tc = col(t, ld);
-    T* xc = col(x, ld);
-    double dot = 0.0;
-    if (k < n) {
-        const int i = k % N1, j = k / N1;
-        if (op.is_free(i, j)) {
-            const T dk = tc[k];
-            const T di = op.inv_diag(i, j, k);
-            const T r0 = theta * dk / di;
-            const T r1 = r0 - op.apply(i, j, k, [&](int, int, int kk) { return tc[kk]; });
-            const T v = xc[k] + ((T)1 + c1) * dk + c2 * di * r1;
-            xc[k] = v;
-            if (rv) dot = (double)v * (double)col(rv, ld)[k];
-        }
-    }
-    if (partial) {
-        const double s = block_sum(dot);
-        if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
-    }
-}
-
 // ------------------------------------------------------------- coarse ---
 // Dense matrix of the coarsest operator; Dirichlet rows/columns become identity.
 template <class Op>
@@ -328,109 +189,6 @@ __global__ void k_cast_d2f(const double* a, float* b, int n) {
     if (k < n) b[k] = (float)a[k];
 }
 
-// x = Cinv b for the coarsest level, one workgroup per column.
-template <typename T>
-__global__ void k_coarse_solve(int nc, const T* __restrict__ cinv, const T* __restrict__ b,
-                               T* __restrict__ x, int ld, const int* __restrict__ act) {
-    if (act && !act[blockIdx.y]) return;
-    __shared__ T bs[128];
-    const T* bc = col(b, ld);
-    for (int k = threadIdx.x; k < nc; k += blockDim.x) bs[k] = bc[k];
-    __syncthreads();
-    for (int r = threadIdx.x; r < nc; r += blockDim.x) {
-        T s = 0;
-        for (int c = 0; c < nc; ++c) s += cinv[r * nc + c] * bs[c];
-        col(x, ld)[r] = s;
-    }
-}
-
-// ------------------------------------------------------------------ PCG ---
-// p = z + beta p (beta = 0 on the first iteration).
-template <typename T>
-__global__ void k_update_p(const T* __restrict__ z, T* __restrict__ p, int ld, int n,
-                           const int* __restrict__ act, const ColState* __restrict__ st,
-                           int first) {
-    if (!act[blockIdx.y]) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    T* pc = col(p, ld);
-    // p is not read on the first iteration: it may hold stale values
-    pc[k] = first ? col(z, ld)[k] : col(z, ld)[k] + (T)st[blockIdx.y].beta * pc[k];
-}
-
-// x += alpha p; r -= alpha q; partial |r|^2.
-template <typename T>
-__global__ void k_update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                            const T* __restrict__ q, int ld, int n, const int* __restrict__ act,
-                            const ColState* __restrict__ st, double* __restrict__ partial) {
-    if (!act[blockIdx.y]) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double rr = 0.0;
-    if (k < n) {
-        const T a = (T)st[blockIdx.y].alpha;
-        col(x, ld)[k] += a * col(p, ld)[k];
-        const T rv = col(r, ld)[k] - a * col(q, ld)[k];
-        col(r, ld)[k] = rv;
-        rr = (double)rv * (double)rv;
-    }
-    const double s = block_sum(rr);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
-}
-
-template <typename T>
-__global__ void k_dot(const T* __restrict__ a, const T* __restrict__ b, int ld, int n,
-                      const int* __restrict__ act, double* __restrict__ partial) {
-    if (act && !act[blockIdx.y]) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double v = 0.0;
-    if (k < n) v = (double)col(a, ld)[k] * (double)col(b, ld)[k];
-    const double s = block_sum(v);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
-}
-
-template <typename T>
-__global__ void k_zero(T* x, int ld, int n, const int* __restrict__ act) {
-    if (act && !act[blockIdx.y]) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) col(x, ld)[k] = 0;
-}
-
-// Column sums of the partials of one reduction, one workgroup per column.
-__device__ inline double column_total(const double* partial, int nblk) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[(size_t)blockIdx.x * nblk + b];
-    return block_sum(v);
-}
-
-enum FinKind { kFinRz0 = 0, kFinRz = 1, kFinAlpha = 2, kFinRr = 3 };
-
-__global__ void k_finalize(int kind, const double* __restrict__ partial, int nblk,
-                           ColState* __restrict__ st, int* __restrict__ act) {
-    if (!act[blockIdx.x]) return;
-    const double s = column_total(partial, nblk);
-    if (threadIdx.x != 0) return;
-    ColState& c = st[blockIdx.x];
-    switch (kind) {
-        case kFinRz0:
-            c.rz = s;
-            c.beta = 0.0;
-            break;
-        case kFinRz:
-            c.beta = s / c.rz;
-            c.rz = s;
-            break;
-        case kFinAlpha:
-            c.pq = s;
-            c.alpha = s > 0.0 ? c.rz / s : 0.0;
-            if (!(s > 0.0)) act[blockIdx.x] = 0;  // breakdown: stop this column
-            break;
-        case kFinRr:
-            c.rr = s;
-            if (s <= c.tol2 * c.bb) act[blockIdx.x] = 0;
-            break;
-    }
-}
-
 // --------------------------------------------------- FP64 refinement loop ---
 // r64 = masked b, x64 = 0, partial |r64|^2.
 template <class Op>
@@ -471,6 +229,13 @@ __global__ void k_ir_residual(Op op, const double* __restrict__ b, int ldb,
     }
     const double s = block_sum(v2);
     if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// Column sums of the partials of one reduction, one workgroup per column.
+__device__ inline double column_total(const double* partial, int nblk) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[(size_t)blockIdx.x * nblk + b];
+    return block_sum(v);
 }
 
 // Outer bookkeeping per column.  first: bb = s (|b|^2).  Always: rr = s;
@@ -546,13 +311,7 @@ OpA<T> make_opA(const Level& L) {
 
 template <typename T>
 OpKA<T> make_opKA(int N, const PriorParams& pp) {
-    OpKA<T> op;
-    op.N = N;
-    op.h = 1.0 / N;
-    op.g = pp.gamma;
-    op.dl = pp.delta;
-    op.bt = pp.beta;
-    return op;
+    return make_prior_op<T>(N, pp.gamma, pp.delta, pp.beta);
 }
 
 }  // namespace
@@ -662,7 +421,12 @@ void Hierarchy::ensure_cols(int nc) {
     const size_t n = n_;
     x64_.ensure(n * nc);
     r64_.ensure(n * nc);
-    partial_.ensure((size_t)ceil_div(n, kBlock) * nc);
+    // one partial per workgroup: vector kernels use ceil(n / kBlock) workgroups,
+    // the fine-level V-cycle kernel one per tile (the small tiles give the most)
+    const int tiles = ceil_div(N_ + 1, kTFSmall) * ceil_div(N_ + 1, kTFSmall);
+    red_stride_ = std::max(ceil_div(n, kBlock), tiles);
+    partial_.ensure((size_t)red_stride_ * nc);
+    pcg_part_.ensure((size_t)red_stride_ * nc * 3);
     st_.ensure(nc);
     act_.ensure(nc);
     oact_.ensure(nc);
@@ -679,6 +443,7 @@ static void ensure_work(PcgWork<T>& w, const std::vector<std::unique_ptr<Level>>
     w.r.ensure(n * nc);
     w.z.ensure(n * nc);
     w.p.ensure(n * nc);
+    w.p2.ensure(n * nc);
     w.q.ensure(n * nc);
     w.lb.clear();
     w.lx.clear();
@@ -697,108 +462,168 @@ static void ensure_work(PcgWork<T>& w, const std::vector<std::unique_ptr<Level>>
     w.cap = nc;
 }
 
+static ChebCoef cheb_coef() {
+    const double theta = 0.5 * (kChebHi + kChebLo), delta = 0.5 * (kChebHi - kChebLo);
+    const double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+    ChebCoef c;
+    c.inv_theta = 1.0 / theta;
+    c.theta = theta;
+    c.cA = 1.0 + rho1 * rho0;
+    c.cB = 2.0 * rho1 / delta;
+    c.c1 = rho1 * rho0;
+    return c;
+}
+
+// z = V-cycle(r) on the PCG vectors of precision T; the last kernel finishes
+// r^T z per column (beta, rz in ColState).
+PcgRed Hierarchy::pcg_red(int nc) const {
+    PcgRed r;
+    r.stride = red_stride_;
+    r.rz = pcg_part_.get();
+    r.pq = r.rz + (size_t)red_stride_ * cap_;
+    r.rr = r.pq + (size_t)red_stride_ * cap_;
+    int Lb = 0;
+    while (lev_[Lb]->N > kBottomN) ++Lb;
+    const int tf = nc < kSmallTileCols ? kTFSmall : kTFBig;
+    r.nrz = Lb == 0 ? 1 : ceil_div(lev_[0]->N + 1, tf) * ceil_div(lev_[0]->N + 1, tf);
+    r.nvec = ceil_div(n_, kBlock);
+    return r;
+}
+
 template <typename T>
-void Hierarchy::vcycle(int l, int nc) {
+void Hierarchy::vcycle(int nc, int check) {
     hipStream_t s = ctx_->stream;
     PcgWork<T>& w = work<T>();
     const int nlev = (int)lev_.size();
-    const Level& L = *lev_[l];
-    const int ld = L.n;
-    T* b = l == 0 ? w.r.get() : w.lb[l]->get();
-    T* x = l == 0 ? w.z.get() : w.lx[l]->get();
-    T* t = w.lt[l]->get();
-    const int* act = act_.get();
+    int Lb = 0;
+    while (lev_[Lb]->N > kBottomN) ++Lb;
+    int* act = act_.get();
     const int dir = kind_ == kOpState;
-    if (l == nlev - 1) {
-        const T* ci;
-        if constexpr (sizeof(T) == 8)
-            ci = cinv64_.get();
+    const ChebCoef cc = cheb_coef();
+    PcgRed red = pcg_red(nc);
+    const bool small = nc < kSmallTileCols;
+    auto bvec = [&](int l) { return l == 0 ? w.r.get() : w.lb[l]->get(); };
+    auto xout = [&](int l) { return l == 0 ? w.z.get() : w.lx[l]->get(); };
+    auto with_op = [&](int l, auto fn) {
+        if (kind_ == kOpState)
+            fn(make_opA<T>(*lev_[l]));
         else
-            ci = cinv32_.get();
-        k_coarse_solve<T><<<dim3(1, nc), 128, 0, s>>>(nc_coarse_, ci, b, x, ld, act);
-        HINV_LAUNCH_CHECK();
-        return;
-    }
-    static const Cheb ch;
-    const T inv_theta = (T)(1.0 / ch.theta);
-    const T cA = (T)(1.0 + ch.rho1 * ch.rho0), cB = (T)(2.0 * ch.rho1 / ch.delta);
-    const T c1 = (T)(ch.rho1 * ch.rho0), c2 = cB, theta = (T)ch.theta;
-    const dim3 g = grid2(L.n, nc);
-    auto run = [&](auto op) {
-        k_smooth_pre<T><<<g, kBlock, 0, s>>>(op, b, x, ld, act, cA, cB, inv_theta);
-        HINV_LAUNCH_CHECK();
-        k_residual<T><<<g, kBlock, 0, s>>>(op, b, x, t, ld, act);
-        HINV_LAUNCH_CHECK();
-        const Level& C = *lev_[l + 1];
-        k_restrict<T><<<grid2(C.n, nc), kBlock, 0, s>>>(C.N, t, ld, w.lb[l + 1]->get(), C.n, dir, act);
-        HINV_LAUNCH_CHECK();
-        vcycle<T>(l + 1, nc);
-        k_prolong_add<T><<<g, kBlock, 0, s>>>(C.N, w.lx[l + 1]->get(), C.n, x, ld, dir, act);
-        HINV_LAUNCH_CHECK();
-        k_post1<T><<<g, kBlock, 0, s>>>(op, b, x, t, ld, act, inv_theta);
-        HINV_LAUNCH_CHECK();
-        k_post2<T><<<g, kBlock, 0, s>>>(op, x, t, ld, act, theta, c1, c2,
-                                        l == 0 ? (const T*)b : (const T*)nullptr,
-                                        l == 0 ? partial_.get() : nullptr);
-        HINV_LAUNCH_CHECK();
+            fn(make_opKA<T>(lev_[l]->N, pp_));
     };
-    if (kind_ == kOpState)
-        run(make_opA<T>(L));
-    else
-        run(make_opKA<T>(L.N, pp_));
+    for (int l = 0; l < Lb; ++l) {
+        const Level& L = *lev_[l];
+        const Level& C = *lev_[l + 1];
+        with_op(l, [&](auto op) {
+            using Op = decltype(op);
+            const int chk = l == 0 ? check : 0;
+            if (small) {
+                const int tc = ceil_div(C.N + 1, kTCSmall);
+                k_down<T, Op, kTCSmall><<<dim3(tc, tc, nc), 256, 0, s>>>(
+                    op, bvec(l), w.lt[l]->get(), L.n, bvec(l + 1), C.n, dir, act, cc, red, st_.get(), chk);
+            } else {
+                const int tc = ceil_div(C.N + 1, kTCBig);
+                k_down<T, Op, kTCBig><<<dim3(tc, tc, nc), 256, 0, s>>>(
+                    op, bvec(l), w.lt[l]->get(), L.n, bvec(l + 1), C.n, dir, act, cc, red, st_.get(), chk);
+            }
+        });
+        HINV_LAUNCH_CHECK();
+    }
+    {
+        BottomArgs<T> a{};
+        a.nlev = nlev - Lb;
+        if (a.nlev > kBottomLevels) fail(HINV_EINVAL, "internal: too many bottom levels");
+        for (int l = 0; l < a.nlev; ++l) {
+            const Level& L = *lev_[Lb + l];
+            a.N[l] = L.N;
+            if (kind_ == kOpState) {
+                if constexpr (sizeof(T) == 8) {
+                    a.wE[l] = L.wE64.get();
+                    a.wN[l] = L.wN64.get();
+                    a.dinv[l] = L.dinv64.get();
+                } else {
+                    a.wE[l] = L.wE32.get();
+                    a.wN[l] = L.wN32.get();
+                    a.dinv[l] = L.dinv32.get();
+                }
+            }
+        }
+        if constexpr (sizeof(T) == 8)
+            a.cinv = cinv64_.get();
+        else
+            a.cinv = cinv32_.get();
+        a.nc = nc_coarse_;
+        a.pp = pp_;
+        const T* rv = Lb == 0 ? (const T*)w.r.get() : nullptr;
+        const int chk = Lb == 0 ? check : 0;
+        if (kind_ == kOpState)
+            k_bottom<T, kOpState><<<nc, 1024, 0, s>>>(a, bvec(Lb), xout(Lb), lev_[Lb]->n, act, cc, rv, red,
+                                                     st_.get(), chk);
+        else
+            k_bottom<T, kOpPrior><<<nc, 1024, 0, s>>>(a, bvec(Lb), xout(Lb), lev_[Lb]->n, act, cc, rv, red,
+                                                     st_.get(), chk);
+        HINV_LAUNCH_CHECK();
+    }
+    for (int l = Lb - 1; l >= 0; --l) {
+        const Level& L = *lev_[l];
+        const Level& C = *lev_[l + 1];
+        const T* rv = l == 0 ? (const T*)w.r.get() : nullptr;
+        with_op(l, [&](auto op) {
+            using Op = decltype(op);
+            if (small) {
+                const int tf = ceil_div(L.N + 1, kTFSmall);
+                k_up<T, Op, kTFSmall><<<dim3(tf, tf, nc), 256, 0, s>>>(
+                    op, bvec(l), w.lt[l]->get(), xout(l), L.n, xout(l + 1), C.n, dir, act, cc, rv, red);
+            } else {
+                const int tf = ceil_div(L.N + 1, kTFBig);
+                k_up<T, Op, kTFBig><<<dim3(tf, tf, nc), 256, 0, s>>>(
+                    op, bvec(l), w.lt[l]->get(), xout(l), L.n, xout(l + 1), C.n, dir, act, cc, rv, red);
+            }
+        });
+        HINV_LAUNCH_CHECK();
+    }
 }
 
 // Inner PCG on w.r (right-hand side, overwritten by the residual) -> w.x.
-// Column set: act_ (modified as columns converge); tolerances in st_.tol2, bb in st_.bb.
+// Columns: act_ (cleared on the device as columns converge); tolerances in
+// st_.tol2 relative to st_.bb.  The host checks for completion every few
+// iterations; kernels of finished columns return at once.
 template <typename T>
 void Hierarchy::pcg(int nc, int max_iter, int* iters) {
     hipStream_t s = ctx_->stream;
     PcgWork<T>& w = work<T>();
     const Level& L = *lev_[0];
     const int n = L.n, ld = n;
-    const int nblk = ceil_div(n, kBlock);
-    const dim3 g = grid2(n, nc);
+    const dim3 g(ceil_div(n, kBlock), nc);
     int* act = act_.get();
-    const bool single = lev_.size() == 1;
-    auto apply_dot = [&](auto op) {
-        k_apply<T><<<g, kBlock, 0, s>>>(op, (const T*)w.p.get(), ld, w.q.get(), ld, act, partial_.get());
-    };
-    // z = M r, rz
-    vcycle<T>(0, nc);
-    if (single) k_dot<T><<<g, kBlock, 0, s>>>(w.r.get(), w.z.get(), ld, n, act, partial_.get());
-    HINV_LAUNCH_CHECK();
-    k_finalize<<<nc, kBlock, 0, s>>>(kFinRz0, partial_.get(), nblk, st_.get(), act);
-    HINV_LAUNCH_CHECK();
-    k_update_p<T><<<g, kBlock, 0, s>>>(w.z.get(), w.p.get(), ld, n, act, st_.get(), 1);
-    HINV_LAUNCH_CHECK();
+    const PcgRed red = pcg_red(nc);
+    T* P[2] = {w.p.get(), w.p2.get()};
+    int cur = 0;
+    vcycle<T>(nc, 0);
     int it = 0;
-    for (; it < max_iter;) {
-        if (kind_ == kOpState)
-            apply_dot(make_opA<T>(L));
-        else
-            apply_dot(make_opKA<T>(L.N, pp_));
-        HINV_LAUNCH_CHECK();
-        k_finalize<<<nc, kBlock, 0, s>>>(kFinAlpha, partial_.get(), nblk, st_.get(), act);
-        HINV_LAUNCH_CHECK();
-        k_update_xr<T><<<g, kBlock, 0, s>>>(w.x.get(), w.r.get(), w.p.get(), w.q.get(), ld, n, act,
-                                            st_.get(), partial_.get());
-        HINV_LAUNCH_CHECK();
-        k_finalize<<<nc, kBlock, 0, s>>>(kFinRr, partial_.get(), nblk, st_.get(), act);
-        HINV_LAUNCH_CHECK();
-        ++it;
-        if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
+    while (it < max_iter) {
+        const int chunk = it == 0 ? 4 : 2;
+        for (int c = 0; c < chunk && it < max_iter; ++c) {
+            const int first = it == 0;
+            if (kind_ == kOpState)
+                k_pcg_apply<T><<<g, kBlock, 0, s>>>(make_opA<T>(L), w.z.get(), P[cur], P[1 - cur], w.q.get(),
+                                                    ld, act, st_.get(), red, first);
+            else
+                k_pcg_apply<T><<<g, kBlock, 0, s>>>(make_opKA<T>(L.N, pp_), w.z.get(), P[cur], P[1 - cur],
+                                                    w.q.get(), ld, act, st_.get(), red, first);
+            HINV_LAUNCH_CHECK();
+            k_pcg_update<T><<<g, kBlock, 0, s>>>(w.x.get(), w.r.get(), P[1 - cur], w.q.get(), ld, n, act,
+                                                 st_.get(), red);
+            HINV_LAUNCH_CHECK();
+            cur = 1 - cur;
+            ++it;
+            if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
+            vcycle<T>(nc, 1);
+        }
         HINV_HIP(hipMemcpyAsync(host_flags_, act, sizeof(int) * nc, hipMemcpyDeviceToHost, s));
         HINV_HIP(hipStreamSynchronize(s));
         int live = 0;
         for (int c = 0; c < nc; ++c) live += host_flags_[c];
         if (!live) break;
-        vcycle<T>(0, nc);
-        if (single) k_dot<T><<<g, kBlock, 0, s>>>(w.r.get(), w.z.get(), ld, n, act, partial_.get());
-        HINV_LAUNCH_CHECK();
-        k_finalize<<<nc, kBlock, 0, s>>>(kFinRz, partial_.get(), nblk, st_.get(), act);
-        HINV_LAUNCH_CHECK();
-        k_update_p<T><<<g, kBlock, 0, s>>>(w.z.get(), w.p.get(), ld, n, act, st_.get(), 0);
-        HINV_LAUNCH_CHECK();
     }
     *iters += it;
 }
@@ -820,6 +645,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     if (nc <= 0) return;
     hipStream_t s = ctx_->stream;
     ensure_cols(nc);
+    if (precision == HINV_PREC_AUTO) precision = nc >= kAutoBatch ? HINV_PREC_FP32_IR : HINV_PREC_FP64;
     const bool fp32 = precision == HINV_PREC_FP32_IR;
     if (fp32)
         ensure_work(w32_, lev_, nc);

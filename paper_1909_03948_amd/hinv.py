@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhinv.so")
 HINV_OK, HINV_EINVAL, HINV_ENOMEM, HINV_EHIP = 0, -1, -2, -3
 HINV_ENOCONV, HINV_ESTATE, HINV_ENEGEIG, HINV_EBREAK = -4, -5, -6, -7
 HESS_FULL, HESS_MISFIT, HESS_GN_FULL, HESS_GN_MISFIT = 0, 1, 2, 3
-PREC_FP64, PREC_FP32_IR = 0, 1
+PREC_FP64, PREC_FP32_IR, PREC_AUTO = 0, 1, 2
 TPROD_FP64, TPROD_BF16 = 0, 1
 NEWTON_MAXREC = 64
 

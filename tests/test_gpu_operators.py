@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 hv = pytest.importorskip("paper_1909_03948_amd.hinv")
 
-PRECS = [hv.PREC_FP64, hv.PREC_FP32_IR]
+PRECS = [hv.PREC_FP64, hv.PREC_FP32_IR, hv.PREC_AUTO]
 
 
 @pytest.fixture(scope="module")
