@@ -31,7 +31,11 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 WORKLOAD = "poisson256"
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_MFMA_PEAK_TFLOPS = 78.6   # dense FP64 matrix cores
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+TIMED_CLASSES = ["mg_down", "mg_up", "mg_bottom", "pcg_apply", "pcg_update", "gram"]
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
 def log(*a):
@@ -77,6 +81,50 @@ def run_step(prob, omega, cfg, tprod, m_map, V):
     return dict(hvps=hvps, newton_s=t1 - t0, eig_s=t2 - t1, newton=ninfo, eig=einfo, lam=lam)
 
 
+def kernel_source_hash():
+    """Hash of the kernel sources the traffic counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mgkernels.h", "grid.h"):
+        h.update(open(os.path.join(ROOT, "paper_1909_03948_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def roofline(ctx, steps, tprod):
+    """Per-class sampled event timings -> roofline of the dominant class."""
+    kern = {}
+    for name in TIMED_CLASSES:
+        r = ctx.kernel_timer_read(name)
+        if r["timed"] == 0:
+            continue
+        avg_ms = r["ms"] / r["timed"]
+        kern[name] = dict(launches=r["launches"], timed=r["timed"], avg_us=1e3 * avg_ms,
+                          est_total_ms=avg_ms * r["launches"],
+                          work_per_launch=r["work"] / r["timed"],
+                          rate=r["work"] / (r["ms"] * 1e-3) / 1e9)  # GB/s or GFLOP/s
+    if not kern:
+        return None, kern
+    dom = max(kern, key=lambda k: kern[k]["est_total_ms"])
+    k = kern[dom]
+    if dom == "gram":
+        peak = BF16_MFMA_PEAK_TFLOPS if tprod == "bf16" else FP64_MFMA_PEAK_TFLOPS
+        roof = dict(bound="mfma", achieved=k["rate"] / 1e3, peak=peak, unit="TFLOP/s",
+                    frac=k["rate"] / 1e3 / peak, traffic=None)
+    else:
+        roof = dict(bound="hbm", achieved=k["rate"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=k["rate"] / HBM_PEAK_GBS, traffic=None)
+    roof["kernel"] = dom
+    roof["avg_us"] = k["avg_us"]
+    roof["algorithmic_bytes_per_launch" if dom != "gram" else "flops_per_launch"] = k["work_per_launch"]
+    # HBM traffic from the committed counter summary, valid while the kernels are unchanged
+    if os.path.exists(PMC_FILE) and dom != "gram":
+        pmc = json.load(open(PMC_FILE))
+        ent = pmc.get("kernels", {}).get(dom)
+        if ent and ent.get("single_level") and pmc.get("source_hash") == kernel_source_hash():
+            roof["traffic"] = ent["hbm_bytes_per_launch"]
+    return roof, kern
+
+
 def cpu_baseline(cfg, budget_s=20.0):
     """Oracle HVPs (misfit part) at the true parameter of the same workload,
     factorization reused, until the time budget is spent."""
@@ -109,6 +157,8 @@ def main():
     ap.add_argument("--tprod", choices=["bf16", "fp64"], default="bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with a 256 MiB device copy (reference for HBM counters)")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -130,6 +180,8 @@ def main():
         r = run_step(prob, omega, cfg, tprod, m_map, V)
         log(f"warmup {w}: newton {r['newton_s']:.3f}s ({r['newton']['iterations']} it, "
             f"{r['newton']['hessian_applies']} HVP) eig {r['eig_s']:.3f}s")
+    for name in TIMED_CLASSES:
+        ctx.kernel_timer(name, True, 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = []
@@ -170,6 +222,19 @@ def main():
         "lambda_1": float(res[-1]["lam"][0]),
         "lambda_k": float(res[-1]["lam"][-1]),
     }
+    roof, kern = roofline(ctx, a.steps, a.tprod)
+    for name in TIMED_CLASSES:
+        ctx.kernel_timer(name, False, 16)
+    line["roofline"] = roof
+    line["kernels"] = kern
+    if a.calibration_copy:
+        # plain device copy of known size for scaling the HBM counters
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("calibration copy: 256 MiB read + 256 MiB written")
     if not a.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(cfg, a.cpu_budget)

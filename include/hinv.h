@@ -141,6 +141,25 @@ int hinv_ctx_set_stream(hinv_ctx* ctx, void* hip_stream);
 const char* hinv_last_error(const hinv_ctx* ctx);
 const char* hinv_status_string(int status);
 
+/* ---- kernel timing (roofline reports) ------------------------------------- */
+#define HINV_KCLASS_MG_DOWN     0  /* finest-level pre-smooth + residual + restriction */
+#define HINV_KCLASS_MG_UP       1  /* finest-level prolongation + post-smooth (+ r^T z) */
+#define HINV_KCLASS_MG_BOTTOM   2  /* all levels N <= 32, one workgroup per column */
+#define HINV_KCLASS_PCG_APPLY   3  /* p = z + beta p, q = A p */
+#define HINV_KCLASS_PCG_UPDATE  4  /* x += alpha p, r -= alpha q */
+#define HINV_KCLASS_GRAM        5  /* tall-skinny block product X^T Y on the matrix cores */
+/* Enables (enable = 1) or disables sampled timing of one kernel class: every
+ * `period`-th launch (period >= 1) is bracketed by HIP events on the context's
+ * stream, at most 2048 launches per class.  Enabling clears the record. */
+int hinv_ctx_kernel_timer(hinv_ctx* ctx, int kclass, int enable, int period);
+/* Synchronizes the stream and returns, for the timed launches of a class:
+ * their number, their summed duration (ms) and their summed algorithmic work
+ * (bytes moved for the stencil and vector kernels -- each array counted once
+ * per launch -- or flops for HINV_KCLASS_GRAM); `launches_total` is the number
+ * of launches of the class while enabled. */
+int hinv_ctx_kernel_timer_read(hinv_ctx* ctx, int kclass, int* timed, long* launches_total,
+                               double* total_ms, double* total_work);
+
 /* ---- problem -------------------------------------------------------------- */
 /* Builds mesh data, prior multigrid hierarchy and observation operator.
  * Observation points are located in their cells on the device; the host only

@@ -115,6 +115,50 @@ const char* hinv_last_error(const hinv_ctx* c) {
     return c->c.err.c_str();
 }
 
+int hinv_ctx_kernel_timer(hinv_ctx* c, int kclass, int enable, int period) {
+    if (!c) return HINV_EINVAL;
+    return guarded(&c->c, [&] {
+        REQUIRE(kclass >= 0 && kclass < hinv::KernelTimer::kClasses, "bad kernel class");
+        REQUIRE(period >= 1, "period must be >= 1");
+        auto& k = c->c.timer.cls[kclass];
+        if (enable && k.ev.empty()) {
+            k.ev.resize(2 * hinv::KernelTimer::kPool);
+            for (auto& e : k.ev) HINV_HIP(hipEventCreate(&e));
+            k.work.resize(hinv::KernelTimer::kPool);
+        }
+        k.on = enable != 0;
+        k.period = period;
+        if (enable) {
+            k.used = 0;
+            k.launches = 0;
+        }
+    });
+}
+
+int hinv_ctx_kernel_timer_read(hinv_ctx* c, int kclass, int* timed, long* launches_total,
+                               double* total_ms, double* total_work) {
+    if (!c || !timed || !launches_total || !total_ms || !total_work) return HINV_EINVAL;
+    return guarded(&c->c, [&] {
+        REQUIRE(kclass >= 0 && kclass < hinv::KernelTimer::kClasses, "bad kernel class");
+        auto& k = c->c.timer.cls[kclass];
+        HINV_HIP(hipStreamSynchronize(c->c.stream));
+        double ms = 0.0, work = 0.0;
+        int cnt = 0;
+        for (int i = 0; i < k.used; ++i) {
+            if (k.work[i] < 0) continue;  // launch of another level: not counted
+            float t = 0.f;
+            HINV_HIP(hipEventElapsedTime(&t, k.ev[2 * i], k.ev[2 * i + 1]));
+            ms += t;
+            work += k.work[i];
+            ++cnt;
+        }
+        *timed = cnt;
+        *launches_total = k.launches;
+        *total_ms = ms;
+        *total_work = work;
+    });
+}
+
 int hinv_problem_create(hinv_ctx* c, const hinv_problem_desc* d, hinv_problem** out) {
     if (!c || !d || !out) return HINV_EINVAL;
     *out = nullptr;

@@ -26,6 +26,19 @@ __global__ void k_add_vec(int n, const double* __restrict__ v, double* __restric
 
 double nrm(Ctx* c, int n, const double* x) { return std::sqrt(dev_dot(c, n, x, x)); }
 
+// Tightens the problem's solve tolerance for the lifetime of the guard.
+struct TolGuard {
+    Problem& P;
+    double saved;
+    TolGuard(Problem& p, double t) : P(p), saved(p.rtol) { P.rtol = std::min(P.rtol, t); }
+    ~TolGuard() { P.rtol = saved; }
+};
+
+// Forward and adjoint solves of the outer loop (two per Newton step) run to
+// this tolerance: near the minimizer the Armijo decrease and the gradient norm
+// fall below the noise that 1e-10 solves leave in J and g.
+constexpr double kOuterRtol = 1e-12;
+
 }  // namespace
 
 // ------------------------------------------------------------ Newton-CG ---
@@ -56,7 +69,10 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
         dev_copy(c, n, 1, m0, n, m, n);
     else
         dev_fill(c, n, P.m_prior, m);
-    P.forward(m, u, &st);
+    {
+        TolGuard tg(P, kOuterRtol);
+        P.forward(m, u, &st);
+    }
     double mis, reg;
     P.cost(m, u, &mis, &reg);
     double J = mis + reg;
@@ -67,7 +83,10 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
     int it = 0;
     bool have_grad_at_m = false;
     while (it < o.max_iter) {
-        P.gradient(m, u, p, g, &st);
+        {
+            TolGuard tg(P, kOuterRtol);
+            P.gradient(m, u, p, g, &st);
+        }
         have_grad_at_m = true;
         const double gn = nrm(c, n, g);
         info->gnorm[it] = gn;
@@ -115,7 +134,10 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
             dev_axpby(c, n, alpha, mh, 1.0, mt);
             // a trial point whose forward solve misses its tolerance is rejected
             SolveStats trial;
-            P.forward(mt, ut, &trial);
+            {
+                TolGuard tg(P, kOuterRtol);
+                P.forward(mt, ut, &trial);
+            }
             const bool solved = trial.converged;
             trial.converged = true;  // counted, but a failed trial does not fail the run
             st.add(trial);
@@ -143,6 +165,7 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
     info->iterations = it;
     // leave the problem linearized at the returned point
     if (!have_grad_at_m) {
+        TolGuard tg(P, kOuterRtol);
         P.gradient(m, u, p, g, &st);
         if (it <= HINV_NEWTON_MAXREC) info->gnorm[it] = nrm(c, n, g);
     }

@@ -64,11 +64,63 @@ struct DBuf {
     T* get() const { return p; }
 };
 
+// Sampled kernel timing: while a class is enabled, every `period`-th launch of
+// it is bracketed by HIP events on the launching stream, and the algorithmic
+// bytes (or flops) of that launch are recorded with it.
+struct KernelTimer {
+    static constexpr int kClasses = 8;
+    static constexpr int kPool = 2048;  // event pairs per class
+    struct Class {
+        bool on = false;
+        int period = 16;
+        long launches = 0;
+        std::vector<hipEvent_t> ev;  // 2 * kPool, created on enable
+        std::vector<double> work;    // per recorded pair
+        int used = 0;
+    } cls[kClasses];
+    bool paused = false;  // set while a graph is being captured
+    // Returns the event pair to record around this launch, or -1.
+    int begin(int c, hipStream_t s, double work) {
+        if (c < 0 || paused) return -1;
+        Class& k = cls[c];
+        if (!k.on) return -1;
+        const long idx = k.launches++;
+        if (idx % k.period || k.used >= kPool) return -1;
+        const int slot = k.used++;
+        k.work[slot] = work;
+        (void)hipEventRecord(k.ev[2 * slot], s);
+        return slot;
+    }
+    // Launches that ran inside a graph replay: counted, not timed.
+    void count_only(int c, long n) {
+        if (c >= 0 && cls[c].on) cls[c].launches += n;
+    }
+    void end(int c, int slot, hipStream_t s) {
+        if (c >= 0 && slot >= 0) (void)hipEventRecord(cls[c].ev[2 * slot + 1], s);
+    }
+    ~KernelTimer() {
+        for (auto& k : cls)
+            for (auto e : k.ev) (void)hipEventDestroy(e);
+    }
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
     DBuf<double> red;  // reduction scratch of the vector helpers
+    KernelTimer timer;
+};
+
+// Kernel classes of the timer (values of HINV_KCLASS_* in the public header).
+enum KClass { kKDown = 0, kKUp = 1, kKBottom = 2, kKPcgApply = 3, kKPcgUpdate = 4, kKGram = 5 };
+
+// RAII bracket of one launch (class -1: not timed).
+struct TimedLaunch {
+    Ctx* c;
+    int cls, slot;
+    TimedLaunch(Ctx* ctx, int k, double work) : c(ctx), cls(k), slot(ctx->timer.begin(k, ctx->stream, work)) {}
+    ~TimedLaunch() { c->timer.end(cls, slot, c->stream); }
 };
 
 // ------------------------------------------------------------ constants ---

@@ -346,6 +346,7 @@ void gram(Ctx* ctx, DenseWork& w, int n, int s1, int s2, const double* X, int ld
     int chunk = ceil_div(ceil_div(n, nsplit), unit) * unit;
     nsplit = ceil_div(n, chunk);
     w.part.ensure((size_t)nsplit * s1 * s2);
+    TimedLaunch tl(ctx, kKGram, 2.0 * n * s1 * s2);  // flops
     if (bf16)
         k_gram_bf16<<<dim3(tiles, nsplit), 256, 0, ctx->stream>>>(n, s1, s2, chunk, X, ldx, Y, ldy,
                                                                  w.part.get());

@@ -79,81 +79,98 @@ struct OpA {
 // M: P1 mass, |T|/12 (1 + delta_vw) per triangle, |T| = h^2/2; couples the
 //    four axis neighbours and the two diagonal neighbours (i+-1, j+-1).
 // M_boundary: (h/6) [[2,1],[1,2]] on every boundary edge.
-// Coefficients are computed on the fly from (i, j): no storage, no traffic.
+// Constant coefficients: the rows of the 9 node classes travel as kernel
+// arguments, so applying K_A reads no coefficient array.
+// Row of the prior operator: diagonal, the six neighbour couplings and 1/diagonal.
+template <typename T>
+struct KARow {
+    T c, e, w, n, s, ne, sw, dinv;
+};
+
+// The row of node (i, j) depends only on which sides of the square the node
+// lies on: 9 classes, class = ci + 3 cj with ci = 0 (interior column),
+// 1 (i = 0), 2 (i = N) and cj likewise for rows.
+__host__ __device__ inline int ka_class(int i, int j, int N) {
+    return (i == 0 ? 1 : (i == N ? 2 : 0)) + 3 * (j == 0 ? 1 : (j == N ? 2 : 0));
+}
+
+template <typename T, class F>
+__device__ inline T ka_apply(const KARow<T>& r, int N, int i, int j, int k, F xat) {
+    const int N1 = N + 1;
+    T acc = r.c * xat(i, j, k);
+    if (i < N) acc += r.e * xat(i + 1, j, k + 1);
+    if (i > 0) acc += r.w * xat(i - 1, j, k - 1);
+    if (j < N) acc += r.n * xat(i, j + 1, k + N1);
+    if (j > 0) acc += r.s * xat(i, j - 1, k - N1);
+    if (i < N && j < N) acc += r.ne * xat(i + 1, j + 1, k + N1 + 1);
+    if (i > 0 && j > 0) acc += r.sw * xat(i - 1, j - 1, k - N1 - 1);
+    return acc;
+}
+
+// Row tables travel by value (kernel arguments, constant-indexed per class).
 template <typename T>
 struct OpKA {
     int N;
-    double h, g, dl, bt;
-    // interior row (0 < i, j < N), identical at every interior node
-    T ic, iax, imass, idiag_inv;  // diagonal, axis neighbour, diagonal neighbour, 1/diagonal
+    KARow<T> rows[9];
     __device__ bool is_free(int, int) const { return true; }
-    struct Row {
-        double c, e, w, n, s, ne, sw;
-    };
-    __device__ Row row(int i, int j) const {
-        const double h2 = h * h;
-        const int hasE = i < N, hasW = i > 0, hasN = j < N, hasS = j > 0;
-        const int jin = (j < N) + (j > 0);  // triangles on a horizontal edge at row j
-        const int iin = (i < N) + (i > 0);  // triangles on a vertical edge at column i
-        const int bh = (j == 0 || j == N);  // horizontal edges at row j are boundary edges
-        const int bv = (i == 0 || i == N);  // vertical edges at column i are boundary edges
-        Row r;
-        const double eh = -g * 0.5 * jin + dl * jin * h2 / 24.0 + bt * (h / 6.0) * bh;
-        const double ev = -g * 0.5 * iin + dl * iin * h2 / 24.0 + bt * (h / 6.0) * bv;
-        r.e = hasE ? eh : 0.0;
-        r.w = hasW ? eh : 0.0;
-        r.n = hasN ? ev : 0.0;
-        r.s = hasS ? ev : 0.0;
-        r.ne = (hasE && hasN) ? dl * h2 / 12.0 : 0.0;
-        r.sw = (hasW && hasS) ? dl * h2 / 12.0 : 0.0;
-        const int ntri = 2 * (hasE && hasN) + (hasW && hasN) + (hasE && hasS) + 2 * (hasW && hasS);
-        const int nbe = bh * (hasE + hasW) + bv * (hasN + hasS);
-        r.c = g * 0.5 * (jin * (hasE + hasW) + iin * (hasN + hasS)) + dl * ntri * h2 / 12.0 +
-              bt * (h / 3.0) * nbe;
-        return r;
-    }
-    __device__ bool interior(int i, int j) const { return i > 0 && i < N && j > 0 && j < N; }
-    __device__ T inv_diag(int i, int j, int) const {
-        return interior(i, j) ? idiag_inv : (T)(1.0 / row(i, j).c);
-    }
-    __device__ T diag(int i, int j, int) const { return interior(i, j) ? ic : (T)row(i, j).c; }
+    __device__ T inv_diag(int i, int j, int) const { return rows[ka_class(i, j, N)].dinv; }
+    __device__ T diag(int i, int j, int) const { return rows[ka_class(i, j, N)].c; }
     template <class F>
     __device__ T apply(int i, int j, int k, F xat) const {
-        const int N1 = N + 1;
-        if (interior(i, j))
-            return ic * xat(i, j, k) +
-                   iax * (xat(i + 1, j, k + 1) + xat(i - 1, j, k - 1) + xat(i, j + 1, k + N1) +
-                          xat(i, j - 1, k - N1)) +
-                   imass * (xat(i + 1, j + 1, k + N1 + 1) + xat(i - 1, j - 1, k - N1 - 1));
-        const Row r = row(i, j);
-        T acc = (T)r.c * xat(i, j, k);
-        if (i < N) acc += (T)r.e * xat(i + 1, j, k + 1);
-        if (i > 0) acc += (T)r.w * xat(i - 1, j, k - 1);
-        if (j < N) acc += (T)r.n * xat(i, j + 1, k + N1);
-        if (j > 0) acc += (T)r.s * xat(i, j - 1, k - N1);
-        if (i < N && j < N) acc += (T)r.ne * xat(i + 1, j + 1, k + N1 + 1);
-        if (i > 0 && j > 0) acc += (T)r.sw * xat(i - 1, j - 1, k - N1 - 1);
-        return acc;
+        return ka_apply(rows[ka_class(i, j, N)], N, i, j, k, xat);
     }
 };
 
-// Builds the prior operator of a level with its interior row precomputed.
+// Same operator reading its row table through a pointer (e.g. staged in LDS).
 template <typename T>
-__host__ __device__ inline OpKA<T> make_prior_op(int N, double g, double dl, double bt) {
+struct OpKARef {
+    int N;
+    const KARow<T>* rows;
+    __device__ bool is_free(int, int) const { return true; }
+    __device__ T inv_diag(int i, int j, int) const { return rows[ka_class(i, j, N)].dinv; }
+    __device__ T diag(int i, int j, int) const { return rows[ka_class(i, j, N)].c; }
+    template <class F>
+    __device__ T apply(int i, int j, int k, F xat) const {
+        return ka_apply(rows[ka_class(i, j, N)], N, i, j, k, xat);
+    }
+};
+
+// Prior operator of a level: the 9 row classes from the element matrices.
+//   K (unit stiffness): an axis edge adjacent to t triangles has weight t/2;
+//   M: |T|/12 (1 + delta_vw) per triangle, |T| = h^2/2, so an axis edge adjacent
+//      to t triangles couples with t h^2/24, the diagonal edge (2 triangles) with
+//      h^2/12 and the diagonal is (number of incident triangles) h^2/12;
+//   M_boundary: (h/6) [[2,1],[1,2]] per boundary edge.
+template <typename T>
+inline OpKA<T> make_prior_op(int N, double g, double dl, double bt) {
     OpKA<T> o;
     o.N = N;
-    o.h = 1.0 / N;
-    o.g = g;
-    o.dl = dl;
-    o.bt = bt;
-    const double h2 = o.h * o.h;
-    // interior: axis edges touch 2 triangles (K weight 1, M entry h^2/12),
-    // diagonal neighbours h^2/12, 6 triangles (M diagonal h^2/2), no boundary term
-    const double c = g * 4.0 + dl * 6.0 * h2 / 12.0;
-    o.ic = (T)c;
-    o.iax = (T)(-g + dl * 2.0 * h2 / 24.0);
-    o.imass = (T)(dl * h2 / 12.0);
-    o.idiag_inv = (T)(1.0 / c);
+    const double h = 1.0 / N, h2 = h * h;
+    const int reps_i[3] = {N / 2, 0, N}, reps_j[3] = {N / 2, 0, N};
+    for (int cj = 0; cj < 3; ++cj)
+        for (int ci = 0; ci < 3; ++ci) {
+            const int i = reps_i[ci], j = reps_j[cj];
+            const int hasE = i < N, hasW = i > 0, hasN = j < N, hasS = j > 0;
+            const int jin = (j < N) + (j > 0);  // triangles on a horizontal edge at row j
+            const int iin = (i < N) + (i > 0);  // triangles on a vertical edge at column i
+            const int bh = (j == 0 || j == N);  // horizontal edges at row j are boundary edges
+            const int bv = (i == 0 || i == N);  // vertical edges at column i are boundary edges
+            const double eh = -g * 0.5 * jin + dl * jin * h2 / 24.0 + bt * (h / 6.0) * bh;
+            const double ev = -g * 0.5 * iin + dl * iin * h2 / 24.0 + bt * (h / 6.0) * bv;
+            const int ntri = 2 * (hasE && hasN) + (hasW && hasN) + (hasE && hasS) + 2 * (hasW && hasS);
+            const int nbe = bh * (hasE + hasW) + bv * (hasN + hasS);
+            const double c = g * 0.5 * (jin * (hasE + hasW) + iin * (hasN + hasS)) +
+                             dl * ntri * h2 / 12.0 + bt * (h / 3.0) * nbe;
+            KARow<T>& r = o.rows[ci + 3 * cj];
+            r.c = (T)c;
+            r.e = (T)(hasE ? eh : 0.0);
+            r.w = (T)(hasW ? eh : 0.0);
+            r.n = (T)(hasN ? ev : 0.0);
+            r.s = (T)(hasS ? ev : 0.0);
+            r.ne = (T)((hasE && hasN) ? dl * h2 / 12.0 : 0.0);
+            r.sw = (T)((hasW && hasS) ? dl * h2 / 12.0 : 0.0);
+            r.dinv = (T)(1.0 / c);
+        }
     return o;
 }
 

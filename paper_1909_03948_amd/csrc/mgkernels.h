@@ -250,20 +250,24 @@ struct BottomArgs {
     const T* dinv[kBottomLevels];
     const T* cinv;                  // dense inverse of the coarsest level
     int nc;                         // its size
-    PriorParams pp;
+    KARow<T> ka[kBottomLevels][9];  // prior operator rows of each level
 };
 
 template <typename T, int KIND>
-__device__ inline auto bottom_op(const BottomArgs<T>& a, int l) {
+__device__ inline auto bottom_op(const BottomArgs<T>& a, int l, const KARow<T>* lds_rows,
+                                 const T* cwE, const T* cwN, const T* cdinv, int off) {
     if constexpr (KIND == kOpState) {
-        OpA<T> o;
+        OpA<T> o;  // coefficients staged in LDS
         o.N = a.N[l];
-        o.wE = a.wE[l];
-        o.wN = a.wN[l];
-        o.dinv = a.dinv[l];
+        o.wE = cwE + off;
+        o.wN = cwN + off;
+        o.dinv = cdinv + off;
         return o;
     } else {
-        return make_prior_op<T>(a.N[l], a.pp.gamma, a.pp.delta, a.pp.beta);
+        OpKARef<T> o;
+        o.N = a.N[l];
+        o.rows = lds_rows + 9 * l;
+        return o;
     }
 }
 
@@ -279,6 +283,12 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
     if (act && !act[col]) return;
     if (check && column_done(red, col, st, act, true)) return;
     __shared__ T sb[kBottomNodes], sx[kBottomNodes], st_[kBottomNodes];
+    // state-operator coefficients of every bottom level (the prior needs only rows)
+    __shared__ T cwE[KIND == kOpState ? kBottomNodes : 1], cwN[KIND == kOpState ? kBottomNodes : 1],
+        cdinv[KIND == kOpState ? kBottomNodes : 1];
+    __shared__ KARow<T> rows[kBottomLevels * 9];
+    if (KIND == kOpPrior)
+        for (int t = threadIdx.x; t < a.nlev * 9; t += blockDim.x) rows[t] = a.ka[t / 9][t % 9];
     int off[kBottomLevels];
     {
         int o = 0;
@@ -287,6 +297,15 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
             o += (a.N[l] + 1) * (a.N[l] + 1);
         }
     }
+    if constexpr (KIND == kOpState)
+        for (int l = 0; l < a.nlev; ++l) {
+            const int nl = (a.N[l] + 1) * (a.N[l] + 1);
+            for (int k = threadIdx.x; k < nl; k += blockDim.x) {
+                cwE[off[l] + k] = a.wE[l][k];
+                cwN[off[l] + k] = a.wN[l][k];
+                cdinv[off[l] + k] = a.dinv[l][k];
+            }
+        }
     const int dir = KIND == kOpState;
     const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cA = (T)cc.cA, cB = (T)cc.cB, c1 = (T)cc.c1;
     const int n0 = (a.N[0] + 1) * (a.N[0] + 1);
@@ -295,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
     const int L = a.nlev - 1;
     // ---- down
     for (int l = 0; l < L; ++l) {
-        const auto op = bottom_op<T, KIND>(a, l);
+        const auto op = bottom_op<T, KIND>(a, l, rows, cwE, cwN, cdinv, off[l]);
         const int N = a.N[l], N1 = N + 1, n = N1 * N1;
         T* b = sb + off[l];
         T* x = sx + off[l];
@@ -360,7 +379,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
     }
     // ---- up
     for (int l = L - 1; l >= 0; --l) {
-        const auto op = bottom_op<T, KIND>(a, l);
+        const auto op = bottom_op<T, KIND>(a, l, rows, cwE, cwN, cdinv, off[l]);
         const int N = a.N[l], N1 = N + 1, n = N1 * N1, Nc1 = N / 2 + 1;
         T* b = sb + off[l];
         T* x = sx + off[l];

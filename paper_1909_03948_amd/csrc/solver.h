@@ -72,6 +72,11 @@ class Hierarchy {
     template <typename T>
     void pcg(int nc, int max_iter, int* iters);
     template <typename T>
+    void pcg_iteration(int nc, int cur, int first);
+    template <typename T>
+    hipGraphExec_t pcg_graph(int nc);
+    void drop_graphs();
+    template <typename T>
     void vcycle(int nc, int check);
     struct PcgRed pcg_red(int nc) const;
     template <typename T>
@@ -98,6 +103,10 @@ class Hierarchy {
     DBuf<int> act_, oact_;
     DBuf<double> colnorm_;  // per column |r| used to scale the inner right-hand side
     int* host_flags_ = nullptr;
+    hipStream_t gs_ = nullptr;             // private stream for graph capture
+    hipStream_t launch_stream_ = nullptr;  // stream the PCG kernels go to (capture or caller)
+    hipGraphExec_t gexec_[2] = {nullptr, nullptr};  // FP64 / FP32 two-iteration graphs
+    int gexec_nc_[2] = {0, 0};
     PcgWork<double> w64_;
     PcgWork<float> w32_;
 };

@@ -356,6 +356,8 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp)
     cinv64_.ensure((size_t)nc_coarse_ * nc_coarse_);
     cinv32_.ensure((size_t)nc_coarse_ * nc_coarse_);
     HINV_HIP(hipHostMalloc((void**)&host_flags_, sizeof(int) * 4096, hipHostMallocDefault));
+    HINV_HIP(hipStreamCreateWithFlags(&gs_, hipStreamNonBlocking));
+    launch_stream_ = ctx_->stream;
     if (kind_ == kOpPrior) {
         build_coarse();
         ready_ = true;
@@ -363,6 +365,8 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp)
 }
 
 Hierarchy::~Hierarchy() {
+    drop_graphs();
+    if (gs_) (void)hipStreamDestroy(gs_);
     if (host_flags_) (void)hipHostFree(host_flags_);
 }
 
@@ -418,6 +422,7 @@ PcgWork<float>& Hierarchy::work<float>() {
 
 void Hierarchy::ensure_cols(int nc) {
     if (nc <= cap_) return;
+    drop_graphs();
     const size_t n = n_;
     x64_.ensure(n * nc);
     r64_.ensure(n * nc);
@@ -492,7 +497,7 @@ PcgRed Hierarchy::pcg_red(int nc) const {
 
 template <typename T>
 void Hierarchy::vcycle(int nc, int check) {
-    hipStream_t s = ctx_->stream;
+    hipStream_t s = launch_stream_;
     PcgWork<T>& w = work<T>();
     const int nlev = (int)lev_.size();
     int Lb = 0;
@@ -513,6 +518,10 @@ void Hierarchy::vcycle(int nc, int check) {
     for (int l = 0; l < Lb; ++l) {
         const Level& L = *lev_[l];
         const Level& C = *lev_[l + 1];
+        // algorithmic bytes: read b, write x2 and b_coarse per column; the state
+        // operator's three coefficient arrays once per launch
+        const double bytes_down = sizeof(T) * ((double)nc * (2.0 * L.n + C.n) + (dir ? 3.0 * L.n : 0.0));
+        TimedLaunch tl(ctx_, l == 0 ? (int)kKDown : -1, bytes_down);
         with_op(l, [&](auto op) {
             using Op = decltype(op);
             const int chk = l == 0 ? check : 0;
@@ -552,9 +561,21 @@ void Hierarchy::vcycle(int nc, int check) {
         else
             a.cinv = cinv32_.get();
         a.nc = nc_coarse_;
-        a.pp = pp_;
+        if (kind_ == kOpPrior)
+            for (int l = 0; l < a.nlev; ++l) {
+                const OpKA<T> o = make_opKA<T>(a.N[l], pp_);
+                for (int c = 0; c < 9; ++c) a.ka[l][c] = o.rows[c];
+            }
         const T* rv = Lb == 0 ? (const T*)w.r.get() : nullptr;
         const int chk = Lb == 0 ? check : 0;
+        // per column: read b (and r for r^T z), write x; once per launch: the
+        // state coefficients of every bottom level and the dense coarse inverse
+        const double nb = (double)(lev_[Lb]->n);
+        double ncoef = 0.0;
+        for (int l = Lb; l < nlev; ++l) ncoef += lev_[l]->n;
+        TimedLaunch tl(ctx_, kKBottom,
+                       sizeof(T) * (nc * (2.0 * nb + (rv ? nb : 0.0)) + (dir ? 3.0 * ncoef : 0.0) +
+                                    (double)nc_coarse_ * nc_coarse_));
         if (kind_ == kOpState)
             k_bottom<T, kOpState><<<nc, 1024, 0, s>>>(a, bvec(Lb), xout(Lb), lev_[Lb]->n, act, cc, rv, red,
                                                      st_.get(), chk);
@@ -567,6 +588,10 @@ void Hierarchy::vcycle(int nc, int check) {
         const Level& L = *lev_[l];
         const Level& C = *lev_[l + 1];
         const T* rv = l == 0 ? (const T*)w.r.get() : nullptr;
+        // read b, x2, x_coarse (and r for r^T z), write x; coefficients once
+        const double bytes_up =
+            sizeof(T) * ((double)nc * ((rv ? 4.0 : 3.0) * L.n + C.n) + (dir ? 3.0 * L.n : 0.0));
+        TimedLaunch tl(ctx_, l == 0 ? (int)kKUp : -1, bytes_up);
         with_op(l, [&](auto op) {
             using Op = decltype(op);
             if (small) {
@@ -583,13 +608,11 @@ void Hierarchy::vcycle(int nc, int check) {
     }
 }
 
-// Inner PCG on w.r (right-hand side, overwritten by the residual) -> w.x.
-// Columns: act_ (cleared on the device as columns converge); tolerances in
-// st_.tol2 relative to st_.bb.  The host checks for completion every few
-// iterations; kernels of finished columns return at once.
+// One PCG iteration (apply, update, V-cycle) on launch_stream_: p moves from
+// P[cur] to P[1 - cur].
 template <typename T>
-void Hierarchy::pcg(int nc, int max_iter, int* iters) {
-    hipStream_t s = ctx_->stream;
+void Hierarchy::pcg_iteration(int nc, int cur, int first) {
+    hipStream_t s = launch_stream_;
     PcgWork<T>& w = work<T>();
     const Level& L = *lev_[0];
     const int n = L.n, ld = n;
@@ -597,28 +620,102 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
     int* act = act_.get();
     const PcgRed red = pcg_red(nc);
     T* P[2] = {w.p.get(), w.p2.get()};
-    int cur = 0;
+    {
+        // read z, p_old, write p_new, q; state coefficients once
+        TimedLaunch tl(ctx_, kKPcgApply,
+                       sizeof(T) * ((double)nc * 4.0 * n + (kind_ == kOpState ? 2.0 * n : 0.0)));
+        if (kind_ == kOpState)
+            k_pcg_apply<T><<<g, kBlock, 0, s>>>(make_opA<T>(L), w.z.get(), P[cur], P[1 - cur], w.q.get(), ld,
+                                                act, st_.get(), red, first);
+        else
+            k_pcg_apply<T><<<g, kBlock, 0, s>>>(make_opKA<T>(L.N, pp_), w.z.get(), P[cur], P[1 - cur],
+                                                w.q.get(), ld, act, st_.get(), red, first);
+        HINV_LAUNCH_CHECK();
+    }
+    {
+        TimedLaunch tl(ctx_, kKPcgUpdate, sizeof(T) * (double)nc * 6.0 * n);  // x, r in/out, p, q in
+        k_pcg_update<T><<<g, kBlock, 0, s>>>(w.x.get(), w.r.get(), P[1 - cur], w.q.get(), ld, n, act,
+                                             st_.get(), red);
+        HINV_LAUNCH_CHECK();
+    }
+    vcycle<T>(nc, 1);
+}
+
+// Graph of two PCG iterations starting from P[1] (captured once per precision
+// and column count; replayed on the caller's stream).
+template <typename T>
+hipGraphExec_t Hierarchy::pcg_graph(int nc) {
+    const int slot = sizeof(T) == 8 ? 0 : 1;
+    if (gexec_[slot] && gexec_nc_[slot] == nc) return gexec_[slot];
+    if (gexec_[slot]) {
+        HINV_HIP(hipGraphExecDestroy(gexec_[slot]));
+        gexec_[slot] = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    HINV_HIP(hipStreamBeginCapture(gs_, hipStreamCaptureModeRelaxed));
+    launch_stream_ = gs_;
+    ctx_->timer.paused = true;
+    try {
+        pcg_iteration<T>(nc, 1, 0);
+        pcg_iteration<T>(nc, 0, 0);
+    } catch (...) {
+        ctx_->timer.paused = false;
+        launch_stream_ = ctx_->stream;
+        (void)hipStreamEndCapture(gs_, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    ctx_->timer.paused = false;
+    launch_stream_ = ctx_->stream;
+    HINV_HIP(hipStreamEndCapture(gs_, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HINV_HIP(e);
+    gexec_[slot] = exec;
+    gexec_nc_[slot] = nc;
+    return exec;
+}
+
+void Hierarchy::drop_graphs() {
+    for (int i = 0; i < 2; ++i)
+        if (gexec_[i]) {
+            (void)hipGraphExecDestroy(gexec_[i]);
+            gexec_[i] = nullptr;
+        }
+}
+
+// Inner PCG on w.r (right-hand side, overwritten by the residual) -> w.x.
+// Columns: act_ (cleared on the device as columns converge); tolerances in
+// st_.tol2 relative to st_.bb.  The first iteration runs eagerly, the rest as
+// replays of a captured two-iteration graph; the host checks for completion
+// after each replay (kernels of finished columns return at once).
+template <typename T>
+void Hierarchy::pcg(int nc, int max_iter, int* iters) {
+    hipStream_t s = ctx_->stream;
+    launch_stream_ = s;
+    int* act = act_.get();
     vcycle<T>(nc, 0);
     int it = 0;
+    if (max_iter > 0) {
+        pcg_iteration<T>(nc, 0, 1);
+        it = 1;
+    }
+    const bool graphs = !std::getenv("HINV_NO_GRAPHS");
     while (it < max_iter) {
-        const int chunk = it == 0 ? 4 : 2;
-        for (int c = 0; c < chunk && it < max_iter; ++c) {
-            const int first = it == 0;
-            if (kind_ == kOpState)
-                k_pcg_apply<T><<<g, kBlock, 0, s>>>(make_opA<T>(L), w.z.get(), P[cur], P[1 - cur], w.q.get(),
-                                                    ld, act, st_.get(), red, first);
-            else
-                k_pcg_apply<T><<<g, kBlock, 0, s>>>(make_opKA<T>(L.N, pp_), w.z.get(), P[cur], P[1 - cur],
-                                                    w.q.get(), ld, act, st_.get(), red, first);
-            HINV_LAUNCH_CHECK();
-            k_pcg_update<T><<<g, kBlock, 0, s>>>(w.x.get(), w.r.get(), P[1 - cur], w.q.get(), ld, n, act,
-                                                 st_.get(), red);
-            HINV_LAUNCH_CHECK();
-            cur = 1 - cur;
-            ++it;
-            if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
-            vcycle<T>(nc, 1);
+        if (graphs && it + 2 <= max_iter) {
+            HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
+            it += 2;
+            // two iterations: two launches of each finest-level class
+            for (int k : {(int)kKDown, (int)kKUp, (int)kKBottom, (int)kKPcgApply, (int)kKPcgUpdate})
+                ctx_->timer.count_only(k, 2);
+        } else {
+            // odd tail: one eager iteration keeps the ping-pong parity at P[1]
+            pcg_iteration<T>(nc, 1, 0);
+            pcg_iteration<T>(nc, 0, 0);
+            it += 2;
         }
+        if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
         HINV_HIP(hipMemcpyAsync(host_flags_, act, sizeof(int) * nc, hipMemcpyDeviceToHost, s));
         HINV_HIP(hipStreamSynchronize(s));
         int live = 0;
@@ -647,6 +744,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     ensure_cols(nc);
     if (precision == HINV_PREC_AUTO) precision = nc >= kAutoBatch ? HINV_PREC_FP32_IR : HINV_PREC_FP64;
     const bool fp32 = precision == HINV_PREC_FP32_IR;
+    if ((fp32 ? w32_.cap : w64_.cap) < nc) drop_graphs();
     if (fp32)
         ensure_work(w32_, lev_, nc);
     else
@@ -699,6 +797,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
             if (stalled) {
                 use32 = false;
                 ++fallbacks;
+                if (w64_.cap < nc) drop_graphs();
                 ensure_work(w64_, lev_, nc);
                 // recompute the inner tolerances for FP64 from the current residuals
                 k_ir_finalize<<<nc, kBlock, 0, s>>>(0, partial_.get(), nblk, st_.get(), oact_.get(),

@@ -70,8 +70,11 @@ EXPORTS = [
     "hinv_set_data", "hinv_set_solver", "hinv_forward", "hinv_cost", "hinv_observe",
     "hinv_gradient", "hinv_linearize", "hinv_inc_forward", "hinv_inc_adjoint",
     "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_solve", "hinv_prior_sample",
-    "hinv_map_newton", "hinv_lowrank_eig", "hinv_posterior_sample",
+    "hinv_map_newton", "hinv_lowrank_eig", "hinv_posterior_sample", "hinv_ctx_kernel_timer",
+    "hinv_ctx_kernel_timer_read",
 ]
+
+KCLASS = {"mg_down": 0, "mg_up": 1, "mg_bottom": 2, "pcg_apply": 3, "pcg_update": 4, "gram": 5}
 
 _lib = None
 
@@ -112,6 +115,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_map_newton": [P, V, V, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)],
         "hinv_lowrank_eig": [P, I, I, I, V, I, I, DP, V, I, C.POINTER(SolveInfo)],
         "hinv_posterior_sample": [P, V, I, DP, V, I, I, V, I, V, I, C.POINTER(SolveInfo)],
+        "hinv_ctx_kernel_timer": [P, I, I, I],
+        "hinv_ctx_kernel_timer_read": [P, I, C.POINTER(I), C.POINTER(C.c_long), DP, DP],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -175,6 +180,20 @@ class Context:
 
     def error(self):
         return self.lib.hinv_last_error(self.h).decode()
+
+    def kernel_timer(self, name, enable=True, period=16):
+        rc = self.lib.hinv_ctx_kernel_timer(self.h, KCLASS[name], int(enable), period)
+        if rc != HINV_OK:
+            raise HinvError(rc, self.error())
+
+    def kernel_timer_read(self, name):
+        """dict(timed, launches, ms, work) of the sampled launches of a class."""
+        t, n, ms, w = C.c_int(), C.c_long(), C.c_double(), C.c_double()
+        rc = self.lib.hinv_ctx_kernel_timer_read(self.h, KCLASS[name], C.byref(t), C.byref(n),
+                                                 C.byref(ms), C.byref(w))
+        if rc != HINV_OK:
+            raise HinvError(rc, self.error())
+        return dict(timed=t.value, launches=n.value, ms=ms.value, work=w.value)
 
 
 class Problem:
