@@ -214,6 +214,16 @@ int hinv_prior_solve(hinv_problem* p, int nrhs, const double* x, int ldx, double
 int hinv_prior_sample(hinv_problem* p, int ns, const double* eta, int ldeta, double* out, int ldo,
                       hinv_solve_info* info);
 
+/* White noise for prior and posterior draws, generated on the device:
+ * eta[:, s] (ns columns of 6 N^2 N(0,1) values, leading dimension ld) for the
+ * samples first .. first+ns-1.  Philox4x64-10 (Salmon et al., SC'11) keyed by
+ * (seed, stream); sample S uses the stream words [S L, (S+1) L), L = 6 N^2,
+ * word w coming from counter block w / 4 + 1; Box-Muller on each word pair
+ * (w0, w1): u1 = ((w0 >> 11) + 1) 2^-53, u2 = (w1 >> 11) 2^-53,
+ * sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).  Any sample can be drawn alone. */
+int hinv_white_noise(hinv_problem* p, uint64_t seed, uint64_t stream, int64_t first, int ns,
+                     double* eta, int ld);
+
 /* ---- MAP point (Alg. 1) ---------------------------------------------------- */
 /* m0 may be NULL (start from m_pr).  opts may be NULL (defaults).  On return
  * the problem is linearized at m_map. */

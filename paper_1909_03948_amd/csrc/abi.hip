@@ -343,6 +343,17 @@ int hinv_prior_sample(hinv_problem* p, int ns, const double* eta, int ldeta, dou
     return rc != HINV_OK ? rc : conv_status(st);
 }
 
+int hinv_white_noise(hinv_problem* p, uint64_t seed, uint64_t stream, int64_t first, int ns,
+                     double* eta, int ld) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        const int N = p->p->N;
+        REQUIRE(ns >= 0 && first >= 0 && ld >= 6 * N * N, "bad size or leading dimension");
+        REQUIRE(ns == 0 || eta, "null output");
+        if (ns) p->p->white_noise(seed, stream, first, ns, eta, ld);
+    });
+}
+
 int hinv_map_newton(hinv_problem* p, const double* m0, double* m_map, const hinv_newton_opts* opts,
                     hinv_newton_info* info) {
     if (!p) return HINV_EINVAL;

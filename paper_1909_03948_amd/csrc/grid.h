@@ -33,12 +33,28 @@ __device__ inline double block_sum(double v) {
 // (i,j)-(i+1,j) = (c_lower(i,j) + c_upper(i,j-1)) / 2, wN[k] the weight of edge
 // (i,j)-(i,j+1) = (c_upper(i,j) + c_lower(i-1,j)) / 2 (absent triangles count
 // zero); the diagonal is the sum of the four incident edge weights.
+// Several instances of one mesh size can share a launch: their coefficient
+// arrays are stacked cs elements apart and column c belongs to instance
+// c / cpi (cs = 0: one instance).
 template <typename T>
 struct OpA {
     int N;
     const T* wE;
     const T* wN;
     const T* dinv;  // 1 / diagonal on free nodes, 0 on Dirichlet nodes
+    long long cs = 0;
+    int cpi = 1;
+    // the operator of the instance that owns column c
+    __device__ OpA at(int c) const {
+        OpA o = *this;
+        if (cs) {
+            const long long off = (long long)(c / cpi) * cs;
+            o.wE += off;
+            o.wN += off;
+            o.dinv += off;
+        }
+        return o;
+    }
     __device__ bool is_free(int, int j) const { return j > 0 && j < N; }
     __device__ T inv_diag(int, int, int k) const { return dinv[k]; }
     // diagonal of a free row: sum of the four incident edge weights
@@ -112,6 +128,7 @@ template <typename T>
 struct OpKA {
     int N;
     KARow<T> rows[9];
+    __device__ const OpKA& at(int) const { return *this; }
     __device__ bool is_free(int, int) const { return true; }
     __device__ T inv_diag(int i, int j, int) const { return rows[ka_class(i, j, N)].dinv; }
     __device__ T diag(int i, int j, int) const { return rows[ka_class(i, j, N)].c; }
@@ -121,11 +138,18 @@ struct OpKA {
     }
 };
 
-// Same operator reading its row table through a pointer (e.g. staged in LDS).
+// Same operator reading its row table through a pointer (staged in LDS, or in
+// global memory with 9 rows per stacked instance, column c -> instance c / cpi).
 template <typename T>
 struct OpKARef {
     int N;
     const KARow<T>* rows;
+    int cpi = 0;  // 0: one instance
+    __device__ OpKARef at(int c) const {
+        OpKARef o = *this;
+        if (cpi) o.rows += 9 * (c / cpi);
+        return o;
+    }
     __device__ bool is_free(int, int) const { return true; }
     __device__ T inv_diag(int i, int j, int) const { return rows[ka_class(i, j, N)].dinv; }
     __device__ T diag(int i, int j, int) const { return rows[ka_class(i, j, N)].c; }

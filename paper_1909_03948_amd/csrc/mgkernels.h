@@ -89,11 +89,12 @@ __device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int
 // [I0, I0+kTC) x [J0, J0+kTC) needs the fine residual on [2 I0 - 1, 2 I1 + 1],
 // hence x2 one node further out and b two nodes further out.
 template <typename T, class Op, int kTC>
-__global__ __launch_bounds__(256) void k_down(Op op, const T* __restrict__ b, T* __restrict__ x,
+__global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T* __restrict__ x,
                                               int ld, T* __restrict__ bc, int ldc, int dirichlet,
                                               int* __restrict__ act, ChebCoef cc, PcgRed red,
                                               ColState* __restrict__ st, int check) {
     const int col = blockIdx.z;
+    const auto& op = op_.at(col);  // operator of the instance owning this column
     if (act && !act[col]) return;
     if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) return;
     constexpr int TW = 2 * kTC + 5;
@@ -167,12 +168,13 @@ __global__ __launch_bounds__(256) void k_down(Op op, const T* __restrict__ b, T*
 // Chebyshev correction d0 one node around O.  Optionally writes the
 // workgroup's part of sum_k rv_k x_k (the PCG inner product r^T z).
 template <typename T, class Op, int kTF>
-__global__ __launch_bounds__(256) void k_up(Op op, const T* __restrict__ b, const T* __restrict__ x2,
+__global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, const T* __restrict__ x2,
                                             T* __restrict__ x, int ld, const T* __restrict__ xc,
                                             int ldc, int dirichlet,
                                             const int* __restrict__ act, ChebCoef cc,
                                             const T* __restrict__ rv, PcgRed red) {
     const int col = blockIdx.z;
+    const auto& op = op_.at(col);  // operator of the instance owning this column
     if (act && !act[col]) return;
     constexpr int TW = kTF + 4;
     __shared__ T sx[TW * TW];
@@ -251,6 +253,14 @@ struct BottomArgs {
     const T* cinv;                  // dense inverse of the coarsest level
     int nc;                         // its size
     KARow<T> ka[kBottomLevels][9];  // prior operator rows of each level
+    // stacked instances (cpi = 0: one instance): column c belongs to instance
+    // c / cpi, whose state coefficients of level l start cs[l] elements further,
+    // whose coarse inverse starts cinv_stride further and whose prior rows of
+    // level l are karows[l][9 inst .. 9 inst + 8]
+    int cpi;
+    long long cs[kBottomLevels];
+    long long cinv_stride;
+    const KARow<T>* karows[kBottomLevels];
 };
 
 template <typename T, int KIND>
@@ -287,8 +297,10 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
     __shared__ T cwE[KIND == kOpState ? kBottomNodes : 1], cwN[KIND == kOpState ? kBottomNodes : 1],
         cdinv[KIND == kOpState ? kBottomNodes : 1];
     __shared__ KARow<T> rows[kBottomLevels * 9];
+    const int inst = a.cpi ? col / a.cpi : 0;
     if (KIND == kOpPrior)
-        for (int t = threadIdx.x; t < a.nlev * 9; t += blockDim.x) rows[t] = a.ka[t / 9][t % 9];
+        for (int t = threadIdx.x; t < a.nlev * 9; t += blockDim.x)
+            rows[t] = a.cpi ? a.karows[t / 9][9 * inst + t % 9] : a.ka[t / 9][t % 9];
     int off[kBottomLevels];
     {
         int o = 0;
@@ -300,10 +312,11 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
     if constexpr (KIND == kOpState)
         for (int l = 0; l < a.nlev; ++l) {
             const int nl = (a.N[l] + 1) * (a.N[l] + 1);
+            const long long io = a.cpi ? inst * a.cs[l] : 0;
             for (int k = threadIdx.x; k < nl; k += blockDim.x) {
-                cwE[off[l] + k] = a.wE[l][k];
-                cwN[off[l] + k] = a.wN[l][k];
-                cdinv[off[l] + k] = a.dinv[l][k];
+                cwE[off[l] + k] = a.wE[l][io + k];
+                cwN[off[l] + k] = a.wN[l][io + k];
+                cdinv[off[l] + k] = a.dinv[l][io + k];
             }
         }
     const int dir = KIND == kOpState;
@@ -363,10 +376,11 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
         T* x = sx + off[L];
         T* tmp = st_;  // level-0 scratch is free here
         constexpr int S = 12;
+        const T* ci = a.cinv + (a.cpi ? inst * a.cinv_stride : 0);
         for (int t = threadIdx.x; t < a.nc * S; t += blockDim.x) {
             const int r = t / S, part = t % S;
             T s = 0;
-            for (int c = part; c < a.nc; c += S) s += a.cinv[r * a.nc + c] * b[c];
+            for (int c = part; c < a.nc; c += S) s += ci[r * a.nc + c] * b[c];
             tmp[t] = s;
         }
         __syncthreads();
@@ -435,11 +449,12 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
 // p_new = z + beta p_old with beta = (r^T z) / rz_old (p_new = z on the first
 // iteration), q = A p_new, partials of p_new^T q.
 template <typename T, class Op>
-__global__ __launch_bounds__(256) void k_pcg_apply(Op op, const T* __restrict__ z, const T* __restrict__ p_old,
+__global__ __launch_bounds__(256) void k_pcg_apply(Op op_, const T* __restrict__ z, const T* __restrict__ p_old,
                                                    T* __restrict__ p_new, T* __restrict__ q, int ld,
                                                    const int* __restrict__ act, const ColState* __restrict__ st,
                                                    PcgRed red, int first) {
     const int col = blockIdx.y;
+    const auto& op = op_.at(col);  // operator of the instance owning this column
     if (!act[col]) return;
     const int N = op.N, N1 = N + 1, n = N1 * N1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;

@@ -52,6 +52,7 @@ class Problem {
     void mass_solve(int nc, const double* x, int ldx, double* y, int ldy);
     void prior_sample(int ns, const double* eta, int ldeta, double* out, int ldo, bool add_mean,
                       SolveStats* st);
+    void white_noise(uint64_t seed, uint64_t stream, long long first, int ns, double* eta, int ld);
 
     // scratch of n x cap columns
     double* scratch(int which, int nc);

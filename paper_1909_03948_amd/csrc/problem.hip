@@ -299,6 +299,50 @@ __global__ void k_dot_finish(const double* __restrict__ partial, int nblk, doubl
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// ------------------------------------------------------------ white noise ---
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 64x64
+// multiplications with Weyl-sequence key increments.
+__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// Box-Muller on one word pair: u1 in (0, 1], u2 in [0, 1).
+__device__ inline void box_muller(uint64_t w0, uint64_t w1, double& z0, double& z1) {
+    const double u1 = ((double)(w0 >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(w1 >> 11) * 0x1.0p-53;
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// eta[:, s] for samples first .. first+ns-1: sample S takes the stream words
+// [S L, (S+1) L), word w from counter block w / 4 + 1 (L = 6 N^2, 4 | L).
+__global__ void k_white_noise(int L, uint64_t seed, uint64_t stream, long long first,
+                              double* __restrict__ eta, int ld) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;  // block within the sample
+    if (4 * b >= L) return;
+    const unsigned long long blk = (unsigned long long)(first + blockIdx.y) * (L / 4) + b + 1;
+    uint64_t c[4] = {blk, 0, 0, 0};
+    philox4x64_10(c, seed, stream);
+    double* e = eta + (size_t)blockIdx.y * ld + 4 * b;
+    box_muller(c[0], c[1], e[0], e[1]);
+    box_muller(c[2], c[3], e[2], e[3]);
+}
+
 OpKA<double> prior_op(int N, double g, double dl, double bt) {
     return make_prior_op<double>(N, g, dl, bt);
 }
@@ -598,6 +642,14 @@ void Problem::prior_solve(int nc, const double* x, int ldx, double* y, int ldy, 
     HK->solve(nc, x, ldx, t1, n, precision, rtol, max_iter, st);
     mass_apply(nc, t1, n, t2, n);
     HK->solve(nc, t2, n, y, ldy, precision, rtol, max_iter, st);
+}
+
+void Problem::white_noise(uint64_t seed, uint64_t stream, long long first, int ns, double* eta,
+                          int ld) {
+    const int L = 6 * N * N;
+    k_white_noise<<<dim3(ceil_div(L / 4, kBlock), ns), kBlock, 0, ctx->stream>>>(L, seed, stream, first,
+                                                                                  eta, ld);
+    HINV_LAUNCH_CHECK();
 }
 
 void Problem::prior_sample(int ns, const double* eta, int ldeta, double* out, int ldo,

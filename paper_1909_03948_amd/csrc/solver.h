@@ -5,6 +5,7 @@
 #include <memory>
 
 #include "common.h"
+#include "grid.h"
 
 namespace hinv {
 
@@ -47,12 +48,17 @@ struct ColState {
     double obb;  // |b|^2 of the outer (FP64) problem
 };
 
+// A hierarchy may stack ninst instances of one mesh size (their own state
+// coefficients, or their own prior parameters): a call with nc columns then
+// gives nc / ninst consecutive columns to each instance, in instance order.
 class Hierarchy {
   public:
-    Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp);
+    Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp, int ninst = 1,
+              const PriorParams* inst_pp = nullptr);
     ~Hierarchy();
-    // State operator: builds all levels from the FP64 parameter field m (device).
-    void set_state_coefficient(const double* m);
+    // State operator: builds all levels of instance inst from the FP64
+    // parameter field m (device).
+    void set_state_coefficient(const double* m, int inst = 0);
     // Solves A x = b for nc columns.  b and x: device FP64, column-major.
     // Only the free rows of b are read; x is zero on Dirichlet rows.
     void solve(int nc, const double* b, int ldb, double* x, int ldx, int precision, double rtol,
@@ -60,12 +66,15 @@ class Hierarchy {
     // y = A x (FP64, masked to free rows).
     void apply(int nc, const double* x, int ldx, double* y, int ldy);
     // Level-0 triangle coefficients c_T (state operator only).
-    const double* coefficient() const { return lev_[0]->cT.get(); }
-    const double* weightsE() const { return lev_[0]->wE64.get(); }
-    const double* weightsN() const { return lev_[0]->wN64.get(); }
+    const double* coefficient(int inst = 0) const {
+        return lev_[0]->cT.get() + (size_t)inst * 2 * N_ * N_;
+    }
+    const double* weightsE(int inst = 0) const { return lev_[0]->wE64.get() + (size_t)inst * n_; }
+    const double* weightsN(int inst = 0) const { return lev_[0]->wN64.get() + (size_t)inst * n_; }
     bool ready() const { return ready_; }
     int N() const { return N_; }
     int n() const { return n_; }
+    int ninst() const { return ninst_; }
     double inner_tol32 = 1e-5;  // FP32 inner relative tolerance of the refinement loop
 
   private:
@@ -82,13 +91,23 @@ class Hierarchy {
     template <typename T>
     PcgWork<T>& work();
     void ensure_cols(int nc);
-    void build_coarse();
+    void set_columns(int nc);
+    void build_coarse(int inst);
+    // calls fn with the operator of level l in precision T (all instances)
+    template <typename T, class F>
+    void with_op(int l, F fn);
 
     Ctx* ctx_;
     OpKind kind_;
     int N_, n_;
     PriorParams pp_;
     bool ready_ = false;
+    int ninst_ = 1;
+    int cpi_ = 1;  // columns per instance of the current call
+    std::vector<PriorParams> inst_pp_;
+    std::vector<char> inst_ready_;
+    DBuf<KARow<double>> karow64_;  // stacked prior rows: [level][instance][9]
+    DBuf<KARow<float>> karow32_;
     std::vector<std::unique_ptr<Level>> lev_;
     DBuf<double> cinv64_;
     DBuf<float> cinv32_;

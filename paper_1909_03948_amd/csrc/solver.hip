@@ -109,9 +109,10 @@ __global__ void k_weights(int N, const double* __restrict__ cT, double* wE64, do
 
 // ------------------------------------------------------------ operators ---
 template <typename T, class Op>
-__global__ void k_apply(Op op, const T* __restrict__ x, int ldx, T* __restrict__ y, int ldy,
+__global__ void k_apply(Op op_, const T* __restrict__ x, int ldx, T* __restrict__ y, int ldy,
                         const int* __restrict__ act, double* __restrict__ partial) {
     if (act && !act[blockIdx.y]) return;
+    const auto& op = op_.at(blockIdx.y);
     const int N = op.N, N1 = N + 1, n = N1 * N1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const T* xc = col(x, ldx);
@@ -192,8 +193,9 @@ __global__ void k_cast_d2f(const double* a, float* b, int n) {
 // --------------------------------------------------- FP64 refinement loop ---
 // r64 = masked b, x64 = 0, partial |r64|^2.
 template <class Op>
-__global__ void k_ir_init(Op op, const double* __restrict__ b, int ldb, double* __restrict__ x64,
+__global__ void k_ir_init(Op op_, const double* __restrict__ b, int ldb, double* __restrict__ x64,
                           double* __restrict__ r64, int ld, double* __restrict__ partial) {
+    const auto& op = op_.at(blockIdx.y);
     const int N1 = op.N + 1, n = N1 * N1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     double v2 = 0.0;
@@ -210,10 +212,11 @@ __global__ void k_ir_init(Op op, const double* __restrict__ b, int ldb, double* 
 
 // r64 = b - A x64 on active columns, partial |r64|^2.
 template <class Op>
-__global__ void k_ir_residual(Op op, const double* __restrict__ b, int ldb,
+__global__ void k_ir_residual(Op op_, const double* __restrict__ b, int ldb,
                               const double* __restrict__ x64, double* __restrict__ r64, int ld,
                               const int* __restrict__ act, double* __restrict__ partial) {
     if (!act[blockIdx.y]) return;
+    const auto& op = op_.at(blockIdx.y);
     const int N1 = op.N + 1, n = N1 * N1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     double v2 = 0.0;
@@ -293,18 +296,20 @@ __global__ void k_bb_init(ColState* st, int nc) {
     if (c < nc) st[c].bb = 1.0;
 }
 
+// State operator of level L for instance inst alone.
 template <typename T>
-OpA<T> make_opA(const Level& L) {
+OpA<T> make_opA(const Level& L, int inst = 0) {
     OpA<T> op;
     op.N = L.N;
+    const size_t off = (size_t)inst * L.n;
     if constexpr (sizeof(T) == 8) {
-        op.wE = L.wE64.get();
-        op.wN = L.wN64.get();
-        op.dinv = L.dinv64.get();
+        op.wE = L.wE64.get() + off;
+        op.wN = L.wN64.get() + off;
+        op.dinv = L.dinv64.get() + off;
     } else {
-        op.wE = L.wE32.get();
-        op.wN = L.wN32.get();
-        op.dinv = L.dinv32.get();
+        op.wE = L.wE32.get() + off;
+        op.wN = L.wN32.get() + off;
+        op.dinv = L.dinv32.get() + off;
     }
     return op;
 }
@@ -331,21 +336,28 @@ static void trace_cols(hipStream_t s, const char* tag, int it, const ColState* s
                      h[c].pq, h[c].rr, h[c].obb, h[c].tol2);
     std::fprintf(stderr, "\n");
 }
-Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp)
-    : ctx_(ctx), kind_(kind), N_(N), n_((N + 1) * (N + 1)), pp_(pp) {
+Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp, int ninst,
+                     const PriorParams* inst_pp)
+    : ctx_(ctx), kind_(kind), N_(N), n_((N + 1) * (N + 1)), pp_(pp), ninst_(ninst) {
+    if (ninst < 1) fail(HINV_EINVAL, "a hierarchy needs at least one instance");
+    inst_pp_.assign(ninst, pp);
+    if (inst_pp)
+        for (int i = 0; i < ninst; ++i) inst_pp_[i] = inst_pp[i];
+    inst_ready_.assign(ninst, 0);
+    const size_t ni = ninst;
     int Nl = N;
     while (true) {
         auto L = std::make_unique<Level>();
         L->N = Nl;
         L->n = (Nl + 1) * (Nl + 1);
         if (kind_ == kOpState) {
-            L->cT.ensure((size_t)2 * Nl * Nl);
-            L->wE64.ensure(L->n);
-            L->wN64.ensure(L->n);
-            L->dinv64.ensure(L->n);
-            L->wE32.ensure(L->n);
-            L->wN32.ensure(L->n);
-            L->dinv32.ensure(L->n);
+            L->cT.ensure(ni * 2 * Nl * Nl);
+            L->wE64.ensure(ni * L->n);
+            L->wN64.ensure(ni * L->n);
+            L->dinv64.ensure(ni * L->n);
+            L->wE32.ensure(ni * L->n);
+            L->wN32.ensure(ni * L->n);
+            L->dinv32.ensure(ni * L->n);
         }
         lev_.push_back(std::move(L));
         if (Nl <= kCoarseMaxN || (Nl & 1)) break;
@@ -353,13 +365,36 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp)
     }
     nc_coarse_ = lev_.back()->n;
     if (nc_coarse_ > 128) fail(HINV_EINVAL, "coarsest multigrid level too large (N must be a power of two)");
-    cinv64_.ensure((size_t)nc_coarse_ * nc_coarse_);
-    cinv32_.ensure((size_t)nc_coarse_ * nc_coarse_);
+    cinv64_.ensure(ni * nc_coarse_ * nc_coarse_);
+    cinv32_.ensure(ni * nc_coarse_ * nc_coarse_);
     HINV_HIP(hipHostMalloc((void**)&host_flags_, sizeof(int) * 4096, hipHostMallocDefault));
     HINV_HIP(hipStreamCreateWithFlags(&gs_, hipStreamNonBlocking));
     launch_stream_ = ctx_->stream;
     if (kind_ == kOpPrior) {
-        build_coarse();
+        if (ninst_ > 1) {
+            // row tables of every level and instance, [level][instance][class]
+            const size_t nl = lev_.size();
+            std::vector<KARow<double>> h64(nl * ni * 9);
+            std::vector<KARow<float>> h32(nl * ni * 9);
+            for (size_t l = 0; l < nl; ++l)
+                for (size_t i = 0; i < ni; ++i) {
+                    const PriorParams& q = inst_pp_[i];
+                    const OpKA<double> o64 = make_prior_op<double>(lev_[l]->N, q.gamma, q.delta, q.beta);
+                    const OpKA<float> o32 = make_prior_op<float>(lev_[l]->N, q.gamma, q.delta, q.beta);
+                    for (int c = 0; c < 9; ++c) {
+                        h64[(l * ni + i) * 9 + c] = o64.rows[c];
+                        h32[(l * ni + i) * 9 + c] = o32.rows[c];
+                    }
+                }
+            karow64_.ensure(h64.size());
+            karow32_.ensure(h32.size());
+            HINV_HIP(hipMemcpyAsync(karow64_.get(), h64.data(), sizeof(KARow<double>) * h64.size(),
+                                    hipMemcpyHostToDevice, ctx_->stream));
+            HINV_HIP(hipMemcpyAsync(karow32_.get(), h32.data(), sizeof(KARow<float>) * h32.size(),
+                                    hipMemcpyHostToDevice, ctx_->stream));
+            HINV_HIP(hipStreamSynchronize(ctx_->stream));
+        }
+        for (int i = 0; i < ninst_; ++i) build_coarse(i);
         ready_ = true;
     }
 }
@@ -370,45 +405,85 @@ Hierarchy::~Hierarchy() {
     if (host_flags_) (void)hipHostFree(host_flags_);
 }
 
-void Hierarchy::build_coarse() {
+void Hierarchy::build_coarse(int inst) {
     hipStream_t s = ctx_->stream;
     const int nc = nc_coarse_;
     const Level& L = *lev_.back();
     const int tot = nc * nc;
+    double* c64 = cinv64_.get() + (size_t)inst * tot;
     if (kind_ == kOpState)
-        k_coarse_matrix<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(make_opA<double>(L), cinv64_.get());
+        k_coarse_matrix<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(make_opA<double>(L, inst), c64);
     else
-        k_coarse_matrix<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(make_opKA<double>(L.N, pp_),
-                                                                  cinv64_.get());
+        k_coarse_matrix<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(
+            make_prior_op<double>(L.N, inst_pp_[inst].gamma, inst_pp_[inst].delta, inst_pp_[inst].beta), c64);
     HINV_LAUNCH_CHECK();
     const size_t shm = sizeof(double) * ((size_t)nc * nc + 2 * nc);
-    k_gauss_jordan<<<1, 1024, shm, s>>>(nc, cinv64_.get());
+    k_gauss_jordan<<<1, 1024, shm, s>>>(nc, c64);
     HINV_LAUNCH_CHECK();
-    k_cast_d2f<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(cinv64_.get(), cinv32_.get(), tot);
+    k_cast_d2f<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(c64, cinv32_.get() + (size_t)inst * tot, tot);
     HINV_LAUNCH_CHECK();
 }
 
-void Hierarchy::set_state_coefficient(const double* m) {
+void Hierarchy::set_state_coefficient(const double* m, int inst) {
     if (kind_ != kOpState) fail(HINV_EINVAL, "set_state_coefficient on a prior hierarchy");
+    if (inst < 0 || inst >= ninst_) fail(HINV_EINVAL, "instance index out of range");
     hipStream_t s = ctx_->stream;
     const int N = lev_[0]->N;
-    k_coef_fine<<<ceil_div(2 * N * N, kBlock), kBlock, 0, s>>>(N, m, lev_[0]->cT.get());
+    auto cT = [&](int l) { return lev_[l]->cT.get() + (size_t)inst * 2 * lev_[l]->N * lev_[l]->N; };
+    k_coef_fine<<<ceil_div(2 * N * N, kBlock), kBlock, 0, s>>>(N, m, cT(0));
     HINV_LAUNCH_CHECK();
     for (size_t l = 0; l < lev_.size(); ++l) {
         Level& L = *lev_[l];
+        const size_t o = (size_t)inst * L.n;
         if (l > 0) {
-            k_coarsen<<<ceil_div(2 * L.N * L.N, kBlock), kBlock, 0, s>>>(L.N, lev_[l - 1]->cT.get(),
-                                                                         L.cT.get());
+            k_coarsen<<<ceil_div(2 * L.N * L.N, kBlock), kBlock, 0, s>>>(L.N, cT(l - 1), cT(l));
             HINV_LAUNCH_CHECK();
         }
-        k_weights<<<ceil_div(L.n, kBlock), kBlock, 0, s>>>(L.N, L.cT.get(), L.wE64.get(),
-                                                           L.wN64.get(), L.dinv64.get(),
-                                                           L.wE32.get(), L.wN32.get(),
-                                                           L.dinv32.get());
+        k_weights<<<ceil_div(L.n, kBlock), kBlock, 0, s>>>(L.N, cT(l), L.wE64.get() + o,
+                                                           L.wN64.get() + o, L.dinv64.get() + o,
+                                                           L.wE32.get() + o, L.wN32.get() + o,
+                                                           L.dinv32.get() + o);
         HINV_LAUNCH_CHECK();
     }
-    build_coarse();
+    build_coarse(inst);
+    inst_ready_[inst] = 1;
     ready_ = true;
+    for (int i = 0; i < ninst_; ++i) ready_ = ready_ && inst_ready_[i];
+}
+
+template <typename T, class F>
+void Hierarchy::with_op(int l, F fn) {
+    const Level& L = *lev_[l];
+    if (kind_ == kOpState) {
+        OpA<T> o = make_opA<T>(L);
+        if (ninst_ > 1) {
+            o.cs = L.n;
+            o.cpi = cpi_;
+        }
+        fn(o);
+    } else if (ninst_ == 1) {
+        fn(make_opKA<T>(L.N, pp_));
+    } else {
+        OpKARef<T> o;
+        o.N = L.N;
+        o.cpi = cpi_;
+        const size_t off = (size_t)l * ninst_ * 9;
+        if constexpr (sizeof(T) == 8)
+            o.rows = karow64_.get() + off;
+        else
+            o.rows = karow32_.get() + off;
+        fn(o);
+    }
+}
+
+// Columns of a call: with stacked instances, nc / ninst consecutive columns each.
+void Hierarchy::set_columns(int nc) {
+    if (ninst_ == 1) {
+        cpi_ = 1;
+        return;
+    }
+    if (nc % ninst_) fail(HINV_EINVAL, "column count must be a multiple of the number of instances");
+    cpi_ = nc / ninst_;
 }
 
 template <>
@@ -509,20 +584,15 @@ void Hierarchy::vcycle(int nc, int check) {
     const bool small = nc < kSmallTileCols;
     auto bvec = [&](int l) { return l == 0 ? w.r.get() : w.lb[l]->get(); };
     auto xout = [&](int l) { return l == 0 ? w.z.get() : w.lx[l]->get(); };
-    auto with_op = [&](int l, auto fn) {
-        if (kind_ == kOpState)
-            fn(make_opA<T>(*lev_[l]));
-        else
-            fn(make_opKA<T>(lev_[l]->N, pp_));
-    };
     for (int l = 0; l < Lb; ++l) {
         const Level& L = *lev_[l];
         const Level& C = *lev_[l + 1];
         // algorithmic bytes: read b, write x2 and b_coarse per column; the state
-        // operator's three coefficient arrays once per launch
-        const double bytes_down = sizeof(T) * ((double)nc * (2.0 * L.n + C.n) + (dir ? 3.0 * L.n : 0.0));
+        // operator's three coefficient arrays once per launch and instance
+        const double bytes_down =
+            sizeof(T) * ((double)nc * (2.0 * L.n + C.n) + (dir ? 3.0 * L.n * ninst_ : 0.0));
         TimedLaunch tl(ctx_, l == 0 ? (int)kKDown : -1, bytes_down);
-        with_op(l, [&](auto op) {
+        with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
             const int chk = l == 0 ? check : 0;
             if (small) {
@@ -561,11 +631,23 @@ void Hierarchy::vcycle(int nc, int check) {
         else
             a.cinv = cinv32_.get();
         a.nc = nc_coarse_;
-        if (kind_ == kOpPrior)
+        if (kind_ == kOpPrior && ninst_ == 1)
             for (int l = 0; l < a.nlev; ++l) {
                 const OpKA<T> o = make_opKA<T>(a.N[l], pp_);
                 for (int c = 0; c < 9; ++c) a.ka[l][c] = o.rows[c];
             }
+        if (ninst_ > 1) {
+            a.cpi = cpi_;
+            a.cinv_stride = (long long)nc_coarse_ * nc_coarse_;
+            for (int l = 0; l < a.nlev; ++l) {
+                a.cs[l] = lev_[Lb + l]->n;
+                const size_t off = (size_t)(Lb + l) * ninst_ * 9;
+                if constexpr (sizeof(T) == 8)
+                    a.karows[l] = karow64_.get() ? karow64_.get() + off : nullptr;
+                else
+                    a.karows[l] = karow32_.get() ? karow32_.get() + off : nullptr;
+            }
+        }
         const T* rv = Lb == 0 ? (const T*)w.r.get() : nullptr;
         const int chk = Lb == 0 ? check : 0;
         // per column: read b (and r for r^T z), write x; once per launch: the
@@ -574,8 +656,8 @@ void Hierarchy::vcycle(int nc, int check) {
         double ncoef = 0.0;
         for (int l = Lb; l < nlev; ++l) ncoef += lev_[l]->n;
         TimedLaunch tl(ctx_, kKBottom,
-                       sizeof(T) * (nc * (2.0 * nb + (rv ? nb : 0.0)) + (dir ? 3.0 * ncoef : 0.0) +
-                                    (double)nc_coarse_ * nc_coarse_));
+                       sizeof(T) * (nc * (2.0 * nb + (rv ? nb : 0.0)) +
+                                    ninst_ * ((dir ? 3.0 * ncoef : 0.0) + (double)nc_coarse_ * nc_coarse_)));
         if (kind_ == kOpState)
             k_bottom<T, kOpState><<<nc, 1024, 0, s>>>(a, bvec(Lb), xout(Lb), lev_[Lb]->n, act, cc, rv, red,
                                                      st_.get(), chk);
@@ -588,11 +670,11 @@ void Hierarchy::vcycle(int nc, int check) {
         const Level& L = *lev_[l];
         const Level& C = *lev_[l + 1];
         const T* rv = l == 0 ? (const T*)w.r.get() : nullptr;
-        // read b, x2, x_coarse (and r for r^T z), write x; coefficients once
+        // read b, x2, x_coarse (and r for r^T z), write x; coefficients once per instance
         const double bytes_up =
-            sizeof(T) * ((double)nc * ((rv ? 4.0 : 3.0) * L.n + C.n) + (dir ? 3.0 * L.n : 0.0));
+            sizeof(T) * ((double)nc * ((rv ? 4.0 : 3.0) * L.n + C.n) + (dir ? 3.0 * L.n * ninst_ : 0.0));
         TimedLaunch tl(ctx_, l == 0 ? (int)kKUp : -1, bytes_up);
-        with_op(l, [&](auto op) {
+        with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
             if (small) {
                 const int tf = ceil_div(L.N + 1, kTFSmall);
@@ -621,15 +703,13 @@ void Hierarchy::pcg_iteration(int nc, int cur, int first) {
     const PcgRed red = pcg_red(nc);
     T* P[2] = {w.p.get(), w.p2.get()};
     {
-        // read z, p_old, write p_new, q; state coefficients once
+        // read z, p_old, write p_new, q; state coefficients once per instance
         TimedLaunch tl(ctx_, kKPcgApply,
-                       sizeof(T) * ((double)nc * 4.0 * n + (kind_ == kOpState ? 2.0 * n : 0.0)));
-        if (kind_ == kOpState)
-            k_pcg_apply<T><<<g, kBlock, 0, s>>>(make_opA<T>(L), w.z.get(), P[cur], P[1 - cur], w.q.get(), ld,
-                                                act, st_.get(), red, first);
-        else
-            k_pcg_apply<T><<<g, kBlock, 0, s>>>(make_opKA<T>(L.N, pp_), w.z.get(), P[cur], P[1 - cur],
-                                                w.q.get(), ld, act, st_.get(), red, first);
+                       sizeof(T) * ((double)nc * 4.0 * n + (kind_ == kOpState ? 2.0 * n * ninst_ : 0.0)));
+        with_op<T>(0, [&](auto op) {
+            k_pcg_apply<T><<<g, kBlock, 0, s>>>(op, w.z.get(), P[cur], P[1 - cur], w.q.get(), ld, act,
+                                                st_.get(), red, first);
+        });
         HINV_LAUNCH_CHECK();
     }
     {
@@ -727,12 +807,13 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
 
 void Hierarchy::apply(int nc, const double* x, int ldx, double* y, int ldy) {
     if (!ready_) fail(HINV_ESTATE, "operator used before its coefficient was set");
+    if (nc <= 0) return;
     hipStream_t s = ctx_->stream;
+    set_columns(nc);
     const dim3 g = grid2(n_, nc);
-    if (kind_ == kOpState)
-        k_apply<double><<<g, kBlock, 0, s>>>(make_opA<double>(*lev_[0]), x, ldx, y, ldy, nullptr, nullptr);
-    else
-        k_apply<double><<<g, kBlock, 0, s>>>(make_opKA<double>(N_, pp_), x, ldx, y, ldy, nullptr, nullptr);
+    with_op<double>(0, [&](auto op) {
+        k_apply<double><<<g, kBlock, 0, s>>>(op, x, ldx, y, ldy, nullptr, nullptr);
+    });
     HINV_LAUNCH_CHECK();
 }
 
@@ -741,6 +822,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     if (!ready_) fail(HINV_ESTATE, "solve before the operator coefficient was set");
     if (nc <= 0) return;
     hipStream_t s = ctx_->stream;
+    set_columns(nc);
     ensure_cols(nc);
     if (precision == HINV_PREC_AUTO) precision = nc >= kAutoBatch ? HINV_PREC_FP32_IR : HINV_PREC_FP64;
     const bool fp32 = precision == HINV_PREC_FP32_IR;
@@ -751,7 +833,6 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
         ensure_work(w64_, lev_, nc);
     const int n = n_, ld = n, nblk = ceil_div(n, kBlock);
     const dim3 g = grid2(n, nc);
-    const Level& L0 = *lev_[0];
     auto launch_init = [&](auto op) {
         k_ir_init<<<g, kBlock, 0, s>>>(op, b, ldb, x64_.get(), r64_.get(), ld, partial_.get());
     };
@@ -759,10 +840,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
         k_ir_residual<<<g, kBlock, 0, s>>>(op, b, ldb, x64_.get(), r64_.get(), ld, oact_.get(),
                                            partial_.get());
     };
-    if (kind_ == kOpState)
-        launch_init(make_opA<double>(L0));
-    else
-        launch_init(make_opKA<double>(N_, pp_));
+    with_op<double>(0, launch_init);
     HINV_LAUNCH_CHECK();
     const double floor32 = inner_tol32, floor64 = 1e-14;
     k_ir_finalize<<<nc, kBlock, 0, s>>>(1, partial_.get(), nblk, st_.get(), oact_.get(),
@@ -825,10 +903,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
                                                      colnorm_.get());
         }
         HINV_LAUNCH_CHECK();
-        if (kind_ == kOpState)
-            launch_res(make_opA<double>(L0));
-        else
-            launch_res(make_opKA<double>(N_, pp_));
+        with_op<double>(0, launch_res);
         HINV_LAUNCH_CHECK();
         k_ir_finalize<<<nc, kBlock, 0, s>>>(0, partial_.get(), nblk, st_.get(), oact_.get(),
                                             colnorm_.get(), rtol, use32 ? floor32 : floor64);

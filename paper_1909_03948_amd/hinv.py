@@ -71,7 +71,7 @@ EXPORTS = [
     "hinv_gradient", "hinv_linearize", "hinv_inc_forward", "hinv_inc_adjoint",
     "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_solve", "hinv_prior_sample",
     "hinv_map_newton", "hinv_lowrank_eig", "hinv_posterior_sample", "hinv_ctx_kernel_timer",
-    "hinv_ctx_kernel_timer_read",
+    "hinv_ctx_kernel_timer_read", "hinv_white_noise",
 ]
 
 KCLASS = {"mg_down": 0, "mg_up": 1, "mg_bottom": 2, "pcg_apply": 3, "pcg_update": 4, "gram": 5}
@@ -116,6 +116,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_lowrank_eig": [P, I, I, I, V, I, I, DP, V, I, C.POINTER(SolveInfo)],
         "hinv_posterior_sample": [P, V, I, DP, V, I, I, V, I, V, I, C.POINTER(SolveInfo)],
         "hinv_ctx_kernel_timer": [P, I, I, I],
+        "hinv_white_noise": [P, C.c_uint64, C.c_uint64, C.c_int64, I, V, I],
         "hinv_ctx_kernel_timer_read": [P, I, C.POINTER(I), C.POINTER(C.c_long), DP, DP],
     }
     for name, args in sig.items():
@@ -305,6 +306,10 @@ class Problem:
         info = SolveInfo()
         rc = self._check(self.lib.hinv_prior_sample(self.h, ns, pe, lde, po, ldo, C.byref(info)))
         return info.as_dict() | {"rc": rc}
+
+    def white_noise(self, seed, stream, first, eta):
+        pe, ns, lde = _cols(eta, 6 * self.N * self.N)
+        self._check(self.lib.hinv_white_noise(self.h, seed, stream, first, ns, pe, lde), allow=())
 
     def map_newton(self, m_map, m0=None, rel_tol=1e-6, abs_tol=0.0, max_iter=50, max_backtrack=10,
                    c_armijo=1e-4, max_cg=500, gauss_newton=False):

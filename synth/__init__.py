@@ -28,6 +28,7 @@ STREAM_OBS_NOISE = 2  # observation noise
 STREAM_OMEGA = 3      # Gaussian probe matrix of the randomized eigensolver
 STREAM_POST = 4       # white noise of posterior samples
 STREAM_TEST = 7       # generic test vectors (directions, right-hand sides)
+STREAM_SAMPLE = 8     # sampled output indices and random functionals of large tests
 
 # Synthetic workloads shaped like the paper's Poisson example, scaled up.
 WORKLOADS = {
@@ -57,6 +58,34 @@ def white_noise(N: int, ns: int = 1, seed: int = MASTER_SEED,
     return _gen(seed, stream).standard_normal((ns, n_noise(N)))
 
 
+def philox_white_noise(N: int, ns: int, seed: int = MASTER_SEED, stream: int = STREAM_POST,
+                       first: int = 0) -> np.ndarray:
+    """(ns, 6 N^2) standard normals from Philox4x64-10 with Box-Muller.
+
+    Counter-based, so any sample can be drawn without the ones before it:
+    sample s uses the words [s L, (s+1) L) of the Philox4x64-10 stream keyed by
+    (seed, stream), L = 6 N^2; word w comes from counter block w // 4 + 1 (the
+    stream NumPy's ``Philox`` produces).  Each word pair (w0, w1) gives
+    u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1], u2 = (w1 >> 11) 2^-53 in [0, 1) and
+    the normals sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) (Box-Muller).
+    The device generator of the library follows the same definition.
+    """
+    L = n_noise(N)
+    if L % 4:
+        raise ValueError("6 N^2 must be a multiple of 4 (N even)")
+    out = np.empty((ns, L))
+    key = (int(seed) & ((1 << 64) - 1)) | ((int(stream) & ((1 << 64) - 1)) << 64)
+    for s in range(ns):
+        g = np.random.Philox(key=key, counter=[(first + s) * (L // 4), 0, 0, 0])
+        w = g.random_raw(L)
+        u1 = ((w[0::2] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+        u2 = (w[1::2] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        r = np.sqrt(-2.0 * np.log(u1))
+        out[s, 0::2] = r * np.cos(2.0 * np.pi * u2)
+        out[s, 1::2] = r * np.sin(2.0 * np.pi * u2)
+    return out
+
+
 def obs_points(q: int, seed: int = MASTER_SEED, lo: float = 0.05,
                hi: float = 0.95) -> np.ndarray:
     """(q, 2) locations drawn uniformly in [lo, hi]^2."""
@@ -77,6 +106,11 @@ def test_vectors(n: int, b: int, seed: int = MASTER_SEED,
                  stream: int = STREAM_TEST, scale: float = 1.0) -> np.ndarray:
     """(b, n) i.i.d. N(0, scale^2) vectors for directions and right-hand sides."""
     return scale * _gen(seed, stream).standard_normal((b, n))
+
+
+def sample_indices(n: int, count: int, seed: int = MASTER_SEED) -> np.ndarray:
+    """Sorted distinct indices in [0, n), drawn uniformly (sampled outputs of large tests)."""
+    return np.sort(_gen(seed, STREAM_SAMPLE).choice(n, size=min(count, n), replace=False))
 
 
 def smooth_field(N: int, seed: int = MASTER_SEED, stream: int = STREAM_TEST,

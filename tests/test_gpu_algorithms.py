@@ -140,3 +140,32 @@ def test_posterior_samples(ctx, map32):
     with pytest.raises(hv.HinvError) as e:
         gp.posterior_sample(dev(m), np.array([-1.5]), dev(V.T[:1]), dev(eta), out)
     assert e.value.code == hv.HINV_ENEGEIG
+
+
+@pytest.mark.parametrize("N,first,ns", [(32, 0, 3), (256, 17, 2)])
+def test_device_white_noise_matches_counter_definition(ctx, N, first, ns):
+    prob, _, obs = instance(N, 10)
+    gp = gpu_problem(ctx, prob, obs)
+    eta = dev(np.zeros((ns, 6 * N * N)))
+    gp.white_noise(1909, synth.STREAM_POST, first, eta)
+    ref = synth.philox_white_noise(N, ns, seed=1909, stream=synth.STREAM_POST, first=first)
+    assert np.max(np.abs(host(eta) - ref)) < 1e-13
+
+
+def test_posterior_samples_from_device_noise(ctx, map32):
+    prob, obs, m = map32
+    k, ns = 12, 4
+    u = prob.forward(m)
+    adj = prob.adjoint(m, u)
+    Om = synth.omega(prob.n, k + 8)
+    A = lambda v: prob.hessian_apply(m, u, adj, v, model.HESS_GN_MISFIT)
+    lam, V, _ = lowrank.double_pass(A, prob.R_apply, prob.R_solve, Om.T, k)
+    eta_o = synth.philox_white_noise(32, ns, seed=5, stream=synth.STREAM_POST, first=100)
+    ref = np.array([m + lowrank.posterior_sample_update(prob.KA_solve(prob.CM @ e), V, lam, prob.R_apply)
+                    for e in eta_o])
+    gp = gpu_problem(ctx, prob, obs)
+    eta = dev(np.zeros((ns, 6 * 32 * 32)))
+    gp.white_noise(5, synth.STREAM_POST, 100, eta)
+    out = dev(np.zeros((ns, prob.n)))
+    gp.posterior_sample(dev(m), lam, dev(V.T), eta, out)
+    assert col_rel(host(out), ref) < 1e-8
