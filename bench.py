@@ -19,6 +19,12 @@ resident on the device before timing starts.
 parameters, 2 000 observations, gamma = 0.05, delta = 1, k = 200, p = 20): the
 same step followed by 1 000 posterior samples through the low-rank update,
 their white noise drawn on the device by the counter-based generator.
+
+``--workload uneven64`` runs 64 independent inversions with mesh sizes drawn
+from {64, 128, 256, 512}, their own prior parameters, observations and true
+fields: one step is the double pass (k = 50, p = 20) of every instance at its
+true parameter through the batch (one multi-right-hand-side solve per mesh
+size), and the same work instance by instance is timed beside it.
 """
 from __future__ import annotations
 
@@ -165,12 +171,114 @@ def cpu_baseline(cfg, workload, budget_s=20.0):
                        f"parameter, sparse LU of A(m) reused, {dt:.1f} s single-threaded SuperLU")
 
 
+def run_uneven(a):
+    """Uneven batch: 64 instances, double pass k = 50, p = 20 for all of them."""
+    import torch
+    from paper_1909_03948_amd import hinv as hv
+    specs = synth.uneven_batch(64)
+    k, p = 50, 20
+    s = k + p
+    prec = {"auto": hv.PREC_AUTO, "fp32ir": hv.PREC_FP32_IR, "fp64": hv.PREC_FP64}[a.precision]
+    tprod = hv.TPROD_BF16 if a.tprod == "bf16" else hv.TPROD_FP64
+    ctx = hv.Context(0)
+    probs, omegas, Vs = [], [], []
+    log("setup: 64 instances, sizes", sorted({sp["N"] for sp in specs}))
+    for sp in specs:
+        N, q, seed = sp["N"], sp["q"], sp["seed"]
+        n = (N + 1) ** 2
+        gp = hv.Problem(ctx, N, sp["gamma"], sp["delta"], obs_xy=synth.obs_points(q, seed=seed),
+                        d_obs=None, sigma=0.01, m_prior=sp["m_prior"], precision=prec, rtol=1e-10)
+        z = lambda *shape: torch.zeros(shape, dtype=torch.float64, device="cuda")
+        eta = z(1, 6 * N * N)
+        gp.white_noise(seed, synth.STREAM_TRUTH, 0, eta)
+        m_true, u, pp, g, Bu = z(n), z(n), z(n), z(n), z(q)
+        gp.prior_sample(eta, m_true)
+        gp.forward(m_true, u)
+        gp.observe(u, Bu)
+        torch.cuda.synchronize()
+        sigma = 0.01 * float(u.abs().max())
+        gp.set_data(Bu.cpu().numpy() + sigma * synth.obs_noise(q, seed=seed), sigma)
+        gp.gradient(m_true, u, pp, g)
+        gp.linearize(m_true, u, pp)
+        probs.append(gp)
+        omegas.append(torch.as_tensor(synth.omega(n, s, seed=seed), device="cuda"))
+        Vs.append(z(k, n))
+    batch = hv.Batch(ctx, probs)
+    torch.cuda.synchronize()
+    hvps = 64 * 2 * s
+
+    def batched():
+        lam, info = batch.lowrank_eig(omegas, k, Vs, mode=hv.HESS_MISFIT, tprod=tprod)
+        assert info["rc"] == 0, info
+        return lam
+
+    def sequential():
+        lam = np.zeros((64, k))
+        for i, gp in enumerate(probs):
+            lam[i], info = gp.lowrank_eig(omegas[i], k, Vs[i], mode=hv.HESS_MISFIT, tprod=tprod)
+            assert info["rc"] == 0, info
+        return lam
+
+    for w in range(a.warmup):
+        t0 = time.perf_counter()
+        lam_b = batched()
+        t1 = time.perf_counter()
+        lam_s = sequential()
+        t2 = time.perf_counter()
+        log(f"warmup {w}: batched {t1 - t0:.3f}s sequential {t2 - t1:.3f}s")
+    for name in TIMED_CLASSES:
+        ctx.kernel_timer(name, True, 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(a.steps):
+        lam_b = batched()
+        log(f"step {st}: batched done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    roof, kern = roofline(ctx, a.steps, a.tprod)
+    for name in TIMED_CLASSES:
+        ctx.kernel_timer(name, False, 16)
+    t2 = time.perf_counter()
+    for st in range(a.steps):
+        lam_s = sequential()
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t2
+    rel = np.max(np.abs(lam_b - lam_s) / np.abs(lam_s[:, :1]))
+    sizes = {}
+    for sp in specs:
+        sizes[sp["N"]] = sizes.get(sp["N"], 0) + 1
+    line = {
+        "metric": "Hessian-vector products/sec at 1e-10 residual (uneven batch of 64 double passes)",
+        "value": hvps * a.steps / dt,
+        "unit": "HVP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 in f64 refinement" + (", bf16 block product" if a.tprod == "bf16" else ""),
+        "data": "synthetic",
+        "config": {"workload": "uneven64", "instances": 64, "mesh_sizes": {str(kk): v for kk, v in sorted(sizes.items())},
+                   "sum_n": int(sum((sp["N"] + 1) ** 2 for sp in specs)), "k": k, "p": p,
+                   "rtol": 1e-10, "linearization": "true parameter", "precision": a.precision,
+                   "tprod": a.tprod},
+        "sequential_hvp_per_s": hvps * a.steps / dts,
+        "batched_over_sequential": dts / dt,
+        "max_eig_diff_batched_vs_sequential": float(rel),
+        "roofline": roof,
+        "kernels": kern,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["poisson256", "poisson1024"], default=WORKLOAD)
+    ap.add_argument("--workload", choices=["poisson256", "poisson1024", "uneven64"], default=WORKLOAD)
     ap.add_argument("--samples", type=int, default=1000,
                     help="posterior samples per step (poisson1024 only)")
     ap.add_argument("--precision", choices=["auto", "fp32ir", "fp64"], default="auto")
@@ -186,6 +294,9 @@ def main():
                                    "single-GPU workload (multi-GPU sharding is design-only)",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.workload == "uneven64":
+        run_uneven(a)
+        return
     import torch
     from paper_1909_03948_amd import hinv as hv
     workload = a.workload

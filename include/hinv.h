@@ -83,6 +83,7 @@ extern "C" {
 
 typedef struct hinv_ctx hinv_ctx;
 typedef struct hinv_problem hinv_problem;
+typedef struct hinv_batch hinv_batch;
 
 typedef struct {
     int    N;          /* cells per side, a power of two >= 4 */
@@ -242,6 +243,32 @@ int hinv_lowrank_eig(hinv_problem* p, int mode, int tprod, int s, const double* 
 int hinv_posterior_sample(hinv_problem* p, const double* m_map, int k, const double* lambda_host,
                           const double* V, int ldv, int ns, const double* eta, int ldeta,
                           double* out, int ldo, hinv_solve_info* info);
+
+/* ---- batches of independent inversions ------------------------------------ */
+/* Many independent problems (own mesh size N_i, prior gamma_i / delta_i / beta_i,
+ * observations and linearization point) whose Hessian actions and double
+ * passes advance together.  Problems of one mesh size share a stacked
+ * multigrid hierarchy: every solve of a Hessian action (two per column, App. A)
+ * and every prior solve runs once per mesh size with the columns of all its
+ * problems in one multi-right-hand-side PCG.  The solver settings are those of
+ * probs[0], with the smallest rtol and largest max_iter of all members.
+ * The problems must stay alive, on this context, while the batch exists; a
+ * problem may appear once.  Columns per mesh size (members x nrhs, or
+ * members x s) are limited to 4096. */
+int hinv_batch_create(hinv_ctx* ctx, int nprob, hinv_problem* const* probs, hinv_batch** out);
+int hinv_batch_destroy(hinv_batch* b);
+/* out[i] (device, n_i x nrhs, leading dimension n_i) = H_i mhat[i] for every
+ * problem i, at its current linearization point (HINV_ESTATE if a problem is
+ * not linearized).  mhat, out: HOST arrays of nprob device pointers.  Modes as
+ * in hinv_hessian_apply (Sec. 4.1, App. A). */
+int hinv_batch_hessian_apply(hinv_batch* b, int mode, int nrhs, const double* const* mhat,
+                             double* const* out, hinv_solve_info* info);
+/* Double pass (Alg. 2 with Alg. 4) for every problem with s probe vectors and
+ * rank k: omega[i] (device, n_i x s, ld n_i), V[i] (device, n_i x k, ld n_i),
+ * lambda_host (HOST, nprob x k, row i = problem i, descending).  Mode and
+ * tprod as in hinv_lowrank_eig. */
+int hinv_batch_lowrank_eig(hinv_batch* b, int mode, int tprod, int s, const double* const* omega,
+                           int k, double* lambda_host, double* const* V, hinv_solve_info* info);
 
 #ifdef __cplusplus
 }

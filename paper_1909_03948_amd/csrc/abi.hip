@@ -1,10 +1,14 @@
 // extern "C" entry points of libhinv (declared and documented in include/hinv.h).
 // Each entry validates its arguments, runs the operation on the context's
 // stream and turns internal errors into status codes.
+#include <algorithm>
 #include <cmath>
+#include <map>
 #include <new>
+#include <vector>
 
 #include "algos.h"
+#include "batch.h"
 #include "problem.h"
 
 struct hinv_ctx {
@@ -14,6 +18,13 @@ struct hinv_ctx {
 struct hinv_problem {
     hinv_ctx* owner;
     std::unique_ptr<hinv::Problem> p;
+};
+
+struct hinv_batch {
+    hinv_ctx* owner;
+    std::vector<hinv_problem*> probs;
+    std::unique_ptr<hinv::Batch> b;
+    int max_group = 0;  // members of the largest mesh-size group
 };
 
 namespace {
@@ -413,6 +424,79 @@ int hinv_posterior_sample(hinv_problem* p, const double* m_map, int k, const dou
     });
     fill_info(info, st);
     return rc != HINV_OK ? rc : conv_status(st);
+}
+
+// ------------------------------------------------------------- batches ---
+int hinv_batch_create(hinv_ctx* c, int nprob, hinv_problem* const* probs, hinv_batch** out) {
+    if (!c || !out) return HINV_EINVAL;
+    *out = nullptr;
+    return guarded(&c->c, [&] {
+        REQUIRE(nprob >= 1 && nprob <= 4096, "nprob must be in [1, 4096]");
+        REQUIRE(probs, "null problem list");
+        std::vector<hinv::Problem*> ps;
+        std::map<int, int> count;
+        for (int i = 0; i < nprob; ++i) {
+            REQUIRE(probs[i] && probs[i]->owner == c, "every problem must belong to this context");
+            for (int j = 0; j < i; ++j) REQUIRE(probs[j] != probs[i], "a problem appears twice");
+            ps.push_back(probs[i]->p.get());
+            ++count[probs[i]->p->N];
+        }
+        set_device(&c->c);
+        auto hb = std::make_unique<hinv_batch>();
+        hb->owner = c;
+        hb->probs.assign(probs, probs + nprob);
+        for (auto& kv : count) hb->max_group = std::max(hb->max_group, kv.second);
+        hb->b = std::make_unique<hinv::Batch>(&c->c, nprob, ps.data());
+        *out = hb.release();
+    });
+}
+
+int hinv_batch_destroy(hinv_batch* b) {
+    if (!b) return HINV_EINVAL;
+    delete b;
+    return HINV_OK;
+}
+
+int hinv_batch_hessian_apply(hinv_batch* b, int mode, int nrhs, const double* const* mhat,
+                             double* const* out, hinv_solve_info* info) {
+    if (!b) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(&b->owner->c, [&] {
+        REQUIRE(mode >= HINV_HESS_FULL && mode <= HINV_HESS_GN_MISFIT, "bad Hessian mode");
+        REQUIRE(nrhs >= 0, "nrhs must be >= 0");
+        REQUIRE((long long)nrhs * b->max_group <= 4096,
+                "nrhs times the largest mesh-size group must not exceed 4096 columns");
+        if (nrhs == 0) return;
+        REQUIRE(mhat && out, "null pointer list");
+        for (size_t i = 0; i < b->probs.size(); ++i) REQUIRE(mhat[i] && out[i], "null vector");
+        b->b->hessian(mode, nrhs, mhat, out, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_batch_lowrank_eig(hinv_batch* b, int mode, int tprod, int s, const double* const* omega,
+                           int k, double* lambda_host, double* const* V, hinv_solve_info* info) {
+    if (!b) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int status = HINV_OK;
+    int rc = guarded(&b->owner->c, [&] {
+        REQUIRE(mode == HINV_HESS_MISFIT || mode == HINV_HESS_GN_MISFIT, "mode must be a misfit mode");
+        REQUIRE(tprod == HINV_TPROD_FP64 || tprod == HINV_TPROD_BF16, "bad block-product precision");
+        int nmin = 1 << 30;
+        for (auto* p : b->probs) nmin = std::min(nmin, p->p->n);
+        REQUIRE(s >= 1 && s <= 512 && s <= nmin, "probe count s must be in [1, min(512, n_i)]");
+        REQUIRE((long long)s * b->max_group <= 4096,
+                "s times the largest mesh-size group must not exceed 4096 columns");
+        REQUIRE(k >= 1 && k <= s, "k must be in [1, s]");
+        REQUIRE(omega && lambda_host && V, "null argument");
+        for (size_t i = 0; i < b->probs.size(); ++i) REQUIRE(omega[i] && V[i], "null vector");
+        status = b->b->lowrank_eig(mode, tprod, s, omega, k, lambda_host, V, &st);
+    });
+    fill_info(info, st);
+    if (rc != HINV_OK) return rc;
+    if (status != HINV_OK) return status;
+    return conv_status(st);
 }
 
 }  // extern "C"

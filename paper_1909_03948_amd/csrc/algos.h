@@ -14,6 +14,14 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
 int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int ldo, int k,
                 double* lambda_host, double* V, int ldv, SolveStats* st);
 
+// The two dense stages of the double pass for one instance (used by batches).
+struct DenseWork;
+int precholqr(Problem& P, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
+              double* Ri);
+void rayleigh_ritz(Problem& P, DenseWork& dw, int s, int k, int tprod, const double* Q,
+                   const double* AQ, double* T, double* S, double* lam, double* V, int ldv,
+                   double* lambda_host);
+
 // Posterior samples through the low-rank update (Sec. 4.3.2).
 void posterior_sample(Problem& P, const double* m_map, int k, const double* lambda_host,
                       const double* V, int ldv, int ns, const double* eta, int ldeta, double* out,

@@ -208,9 +208,37 @@ bool orthonormalize(Ctx* c, DenseWork& w, int n, int s, double* Y, double* tmp, 
 
 }  // namespace
 
+// PreCholQR (Algorithm 4) on Y (n x s): Z = qr(Y), Zbar = B Z, R_Z = chol(Z^T Zbar),
+// Q = Z R_Z^-1 written to Q.  Y is overwritten by Z; Zb is scratch.
+int precholqr(Problem& P, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
+              double* Ri) {
+    Ctx* c = P.ctx;
+    const int n = P.n;
+    if (!orthonormalize(c, dw, n, s, Y, Q, G, Ri)) return HINV_EBREAK;  // Y <- Z
+    P.prior_apply(s, Y, n, Zb, n);                                       // Zbar = B Z
+    gram(c, dw, n, s, s, Y, n, Zb, n, G, s);                             // Z^T Zbar
+    if (!cholesky_upper(c, dw, s, G, s, 0.0)) return HINV_EBREAK;        // R_Z
+    tri_inverse_upper(c, s, G, s, Ri, s);
+    gemm_tall(c, n, s, s, 1.0, Y, n, Ri, s, 0.0, Q, n);                  // Q = Z R_Z^-1
+    return HINV_OK;
+}
+
+// Rayleigh-Ritz step of Algorithm 2: T = Q^T (A Q), T = S Lambda S^T (descending),
+// V = Q S_k, Lambda_k to the host (synchronizes the stream).
+void rayleigh_ritz(Problem& P, DenseWork& dw, int s, int k, int tprod, const double* Q,
+                   const double* AQ, double* T, double* S, double* lam, double* V, int ldv,
+                   double* lambda_host) {
+    Ctx* c = P.ctx;
+    const int n = P.n;
+    gram(c, dw, n, s, s, Q, n, AQ, n, T, s, tprod == HINV_TPROD_BF16);
+    sym_eig(c, dw, s, T, s, S, s, lam);
+    gemm_tall(c, n, s, k, 1.0, Q, n, S, s, 0.0, V, ldv);
+    HINV_HIP(hipMemcpyAsync(lambda_host, lam, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    HINV_HIP(hipStreamSynchronize(c->stream));
+}
+
 int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int ldo, int k,
                 double* lambda_host, double* V, int ldv, SolveStats* st) {
-    Ctx* c = P.ctx;
     const int n = P.n;
     DBuf<double> big, small;
     big.ensure((size_t)n * s * 3);
@@ -227,20 +255,11 @@ int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int
     // pass 1: Ybar = A Omega, Y = B^-1 Ybar  (A = H_misfit, B = R)
     P.hessian(mode, s, omega, ldo, W, n, st);
     P.prior_solve(s, W, n, Y, n, st);
-    // PreCholQR (Algorithm 4)
-    if (!orthonormalize(c, dw, n, s, Y, W, G, Ri)) return HINV_EBREAK;  // Y <- Z
-    P.prior_apply(s, Y, n, Zb, n);                                         // Zbar = B Z
-    gram(c, dw, n, s, s, Y, n, Zb, n, G, s);                               // Z^T Zbar
-    if (!cholesky_upper(c, dw, s, G, s, 0.0)) return HINV_EBREAK;          // R_Z
-    tri_inverse_upper(c, s, G, s, Ri, s);
-    gemm_tall(c, n, s, s, 1.0, Y, n, Ri, s, 0.0, W, n);                    // Q = Z R_Z^-1
+    const int rc = precholqr(P, dw, s, Y, Zb, W, G, Ri);  // Q in W
+    if (rc != HINV_OK) return rc;
     // pass 2: T = Q^T A Q
     P.hessian(mode, s, W, n, Zb, n, st);
-    gram(c, dw, n, s, s, W, n, Zb, n, T, s, tprod == HINV_TPROD_BF16);
-    sym_eig(c, dw, s, T, s, S, s, lam);
-    gemm_tall(c, n, s, k, 1.0, W, n, S, s, 0.0, V, ldv);                   // V = Q S_k
-    HINV_HIP(hipMemcpyAsync(lambda_host, lam, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
-    HINV_HIP(hipStreamSynchronize(c->stream));
+    rayleigh_ritz(P, dw, s, k, tprod, W, Zb, T, S, lam, V, ldv, lambda_host);
     return HINV_OK;
 }
 

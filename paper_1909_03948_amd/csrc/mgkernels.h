@@ -55,7 +55,8 @@ struct PcgRed {
     double* rr;
     int stride;
     int nrz;  // number of partials of r^T z (workgroups of the last V-cycle kernel)
-    int nvec; // number of partials of p^T q and r^T r
+    int nvec; // number of partials of p^T q and r^T r (workgroups of the PCG vector kernels)
+    int per;  // consecutive blocks of kBlock nodes per workgroup in the PCG vector kernels
 };
 
 // Workgroup sum with its own LDS slot; result valid in thread 0.
@@ -457,21 +458,22 @@ __global__ __launch_bounds__(256) void k_pcg_apply(Op op_, const T* __restrict__
     const auto& op = op_.at(col);  // operator of the instance owning this column
     if (!act[col]) return;
     const int N = op.N, N1 = N + 1, n = N1 * N1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     T beta = 0;
     if (!first) beta = (T)(partial_total(red.rz, col, red.stride, red.nrz) / st[col].rz);
     const T* zc = z + (size_t)col * ld;
     const T* pc = p_old + (size_t)col * ld;
     auto pn = [&](int, int, int kk) { return first ? zc[kk] : zc[kk] + beta * pc[kk]; };
     double dot = 0.0;
-    if (k < n) {
+    for (int e = 0; e < red.per; ++e) {
+        const int k = (blockIdx.x * red.per + e) * blockDim.x + threadIdx.x;
+        if (k >= n) break;
         const int i = k % N1, j = k / N1;
         const T pk = pn(i, j, k);
         T v = 0;
         if (op.is_free(i, j)) v = op.apply(i, j, k, pn);
         p_new[(size_t)col * ld + k] = pk;
         q[(size_t)col * ld + k] = v;
-        dot = (double)pk * (double)v;
+        dot += (double)pk * (double)v;
     }
     const double s = group_sum(dot);
     if (threadIdx.x == 0) red.pq[(size_t)col * red.stride + blockIdx.x] = s;
@@ -497,15 +499,16 @@ __global__ __launch_bounds__(256) void k_pcg_update(T* __restrict__ x, T* __rest
         c.alpha = alpha;
         if (!(pq > 0.0)) act[col] = 0;
     }
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     double rr = 0.0;
-    if (k < n) {
+    const T a = (T)alpha;
+    for (int e = 0; e < red.per; ++e) {
+        const int k = (blockIdx.x * red.per + e) * blockDim.x + threadIdx.x;
+        if (k >= n) break;
         const size_t o = (size_t)col * ld + k;
-        const T a = (T)alpha;
         x[o] += a * p[o];
         const T rv = r[o] - a * q[o];
         r[o] = rv;
-        rr = (double)rv * (double)rv;
+        rr += (double)rv * (double)rv;
     }
     const double s = group_sum(rr);
     if (threadIdx.x == 0) red.rr[(size_t)col * red.stride + blockIdx.x] = s;

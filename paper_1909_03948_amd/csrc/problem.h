@@ -32,6 +32,7 @@ class Problem {
     DBuf<double> m_lin, u_lin, p_lin;
     bool linearized = false;
     bool ha_is_lin = false;
+    long long lin_version = 0;  // counts linearizations (batches track it)
 
     void set_data(const double* d_host, double sig);
 
@@ -46,6 +47,12 @@ class Problem {
                      double* phat, int ldp, SolveStats* st);
     void hessian(int mode, int nc, const double* mhat, int ldm, double* out, int ldo,
                  SolveStats* st);
+    // the three stages of a Hessian action around the two solves
+    void inc_forward_rhs(int nc, const double* mhat, int ldm, double* rhs, int ldr);
+    void inc_adjoint_rhs(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
+                         double* rhs, int ldr);
+    void hess_output(int mode, int nc, const double* mhat, int ldm, const double* uh, int ldu,
+                     const double* ph, int ldp, double* out, int ldo);
     void prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate = false);
     void prior_solve(int nc, const double* x, int ldx, double* y, int ldy, SolveStats* st);
     void mass_apply(int nc, const double* x, int ldx, double* y, int ldy);

@@ -539,6 +539,7 @@ void Problem::linearize(const double* m, const double* u, const double* p) {
     HA->set_state_coefficient(m_lin.get());
     ha_is_lin = true;
     linearized = true;
+    ++lin_version;
 }
 
 void Problem::ensure_lin_hierarchy() {
@@ -549,49 +550,68 @@ void Problem::ensure_lin_hierarchy() {
     }
 }
 
-void Problem::inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st) {
+// Right-hand side -[C(u) mhat]_F of the incremental forward problem.
+void Problem::inc_forward_rhs(int nc, const double* mhat, int ldm, double* rhs, int ldr) {
     ensure_lin_hierarchy();
-    double* rhs = scratch(0, nc);
     k_sens<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(N, HA->coefficient(), mhat, ldm, u_lin.get(),
-                                                     -1.0, rhs, n);
+                                                     -1.0, rhs, ldr);
     HINV_LAUNCH_CHECK();
-    HA->solve(nc, rhs, n, uhat, ldu, precision, rtol, max_iter, st);
 }
 
-void Problem::inc_adjoint(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
-                          double* phat, int ldp, SolveStats* st) {
+// Right-hand side -[B^T B uhat / sigma^2 + C(p) mhat]_F of the incremental
+// adjoint problem (Gauss-Newton drops C(p) mhat).
+void Problem::inc_adjoint_rhs(int nc, bool gn, const double* mhat, int ldm, const double* uhat,
+                              int ldu, double* rhs, int ldr) {
     ensure_lin_hierarchy();
     hipStream_t s = ctx->stream;
-    double* rhs = scratch(0, nc);
-    // -C(p) mhat (dropped by Gauss-Newton: the scale 0 zeroes the column)
+    // the scale 0 zeroes the column under Gauss-Newton
     k_sens<<<grid2(n, nc), kBlock, 0, s>>>(N, HA->coefficient(), mhat, ldm, p_lin.get(),
-                                           gn ? 0.0 : -1.0, rhs, n);
+                                           gn ? 0.0 : -1.0, rhs, ldr);
     HINV_LAUNCH_CHECK();
     if (q > 0) {
         double* Bu = obs_scratch(nc);
         observe(uhat, ldu, nc, Bu, q, false);
         k_obs_scatter<<<grid2(n_touch, nc), kBlock, 0, s>>>(n_touch, t_node.get(), t_ptr.get(),
                                                             t_ent.get(), obs_w.get(), Bu, q,
-                                                            -1.0 / (sigma * sigma), rhs, n);
+                                                            -1.0 / (sigma * sigma), rhs, ldr);
         HINV_LAUNCH_CHECK();
     }
+}
+
+// Hessian action from the incremental states (and R mhat for the full modes).
+void Problem::hess_output(int mode, int nc, const double* mhat, int ldm, const double* uh, int ldu,
+                          const double* ph, int ldp, double* out, int ldo) {
+    const bool gn = mode == HINV_HESS_GN_FULL || mode == HINV_HESS_GN_MISFIT;
+    const bool with_prior = mode == HINV_HESS_FULL || mode == HINV_HESS_GN_FULL;
+    k_hess_out<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(N, HA->coefficient(), u_lin.get(),
+                                                         p_lin.get(), uh, ldu, ph, ldp, mhat, ldm,
+                                                         out, ldo, gn ? 1 : 0);
+    HINV_LAUNCH_CHECK();
+    if (with_prior) prior_apply(nc, mhat, ldm, out, ldo, true);
+}
+
+void Problem::inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st) {
+    double* rhs = scratch(0, nc);
+    inc_forward_rhs(nc, mhat, ldm, rhs, n);
+    HA->solve(nc, rhs, n, uhat, ldu, precision, rtol, max_iter, st);
+}
+
+void Problem::inc_adjoint(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
+                          double* phat, int ldp, SolveStats* st) {
+    double* rhs = scratch(0, nc);
+    inc_adjoint_rhs(nc, gn, mhat, ldm, uhat, ldu, rhs, n);
     HA->solve(nc, rhs, n, phat, ldp, precision, rtol, max_iter, st);
 }
 
 void Problem::hessian(int mode, int nc, const double* mhat, int ldm, double* out, int ldo,
                       SolveStats* st) {
     const bool gn = mode == HINV_HESS_GN_FULL || mode == HINV_HESS_GN_MISFIT;
-    const bool with_prior = mode == HINV_HESS_FULL || mode == HINV_HESS_GN_FULL;
     scratch(0, nc);
     double* uh = scratch(1, nc);
     double* ph = scratch(2, nc);
     inc_forward(nc, mhat, ldm, uh, n, st);
     inc_adjoint(nc, gn, mhat, ldm, uh, n, ph, n, st);
-    k_hess_out<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(N, HA->coefficient(), u_lin.get(),
-                                                         p_lin.get(), uh, n, ph, n, mhat, ldm, out,
-                                                         ldo, gn ? 1 : 0);
-    HINV_LAUNCH_CHECK();
-    if (with_prior) prior_apply(nc, mhat, ldm, out, ldo, true);
+    hess_output(mode, nc, mhat, ldm, uh, n, ph, n, out, ldo);
 }
 
 void Problem::mass_apply(int nc, const double* x, int ldx, double* y, int ldy) {

@@ -566,7 +566,12 @@ PcgRed Hierarchy::pcg_red(int nc) const {
     while (lev_[Lb]->N > kBottomN) ++Lb;
     const int tf = nc < kSmallTileCols ? kTFSmall : kTFBig;
     r.nrz = Lb == 0 ? 1 : ceil_div(lev_[0]->N + 1, tf) * ceil_div(lev_[0]->N + 1, tf);
-    r.nvec = ceil_div(n_, kBlock);
+    // Batched calls give each workgroup of the PCG vector kernels several blocks
+    // of nodes: every workgroup sums all partials of its column, so their number
+    // must stay small next to the work per workgroup.
+    const int nb = ceil_div(n_, kBlock);
+    r.per = nc < kSmallTileCols ? 1 : std::min(16, std::max(1, ceil_div(nb, 64)));
+    r.nvec = ceil_div(n_, kBlock * r.per);
     return r;
 }
 
@@ -698,9 +703,9 @@ void Hierarchy::pcg_iteration(int nc, int cur, int first) {
     PcgWork<T>& w = work<T>();
     const Level& L = *lev_[0];
     const int n = L.n, ld = n;
-    const dim3 g(ceil_div(n, kBlock), nc);
     int* act = act_.get();
     const PcgRed red = pcg_red(nc);
+    const dim3 g(red.nvec, nc);
     T* P[2] = {w.p.get(), w.p2.get()};
     {
         // read z, p_old, write p_new, q; state coefficients once per instance

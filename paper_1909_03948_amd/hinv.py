@@ -71,7 +71,8 @@ EXPORTS = [
     "hinv_gradient", "hinv_linearize", "hinv_inc_forward", "hinv_inc_adjoint",
     "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_solve", "hinv_prior_sample",
     "hinv_map_newton", "hinv_lowrank_eig", "hinv_posterior_sample", "hinv_ctx_kernel_timer",
-    "hinv_ctx_kernel_timer_read", "hinv_white_noise",
+    "hinv_ctx_kernel_timer_read", "hinv_white_noise", "hinv_batch_create", "hinv_batch_destroy",
+    "hinv_batch_hessian_apply", "hinv_batch_lowrank_eig",
 ]
 
 KCLASS = {"mg_down": 0, "mg_up": 1, "mg_bottom": 2, "pcg_apply": 3, "pcg_update": 4, "gram": 5}
@@ -118,6 +119,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_ctx_kernel_timer": [P, I, I, I],
         "hinv_white_noise": [P, C.c_uint64, C.c_uint64, C.c_int64, I, V, I],
         "hinv_ctx_kernel_timer_read": [P, I, C.POINTER(I), C.POINTER(C.c_long), DP, DP],
+        "hinv_batch_create": [P, I, C.POINTER(P), C.POINTER(P)],
+        "hinv_batch_destroy": [P],
+        "hinv_batch_hessian_apply": [P, I, I, C.POINTER(V), C.POINTER(V), C.POINTER(SolveInfo)],
+        "hinv_batch_lowrank_eig": [P, I, I, I, C.POINTER(V), I, DP, C.POINTER(V),
+                                   C.POINTER(SolveInfo)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -342,6 +348,63 @@ class Problem:
         rc = self._check(self.lib.hinv_posterior_sample(self.h, _ptr(m_map), k, lam_arr, pv, ldv, ns,
                                                         pe, lde, po, ldo, C.byref(info)))
         return info.as_dict() | {"rc": rc}
+
+
+class Batch:
+    """Binding of hinv_batch: independent problems advanced together.  Vectors
+    are given per problem as (c, n_i) CUDA float64 tensors (row = column of the
+    C multivector, rows contiguous and packed)."""
+
+    def __init__(self, ctx: Context, problems):
+        self.ctx, self.lib = ctx, ctx.lib
+        self.problems = list(problems)  # keeps the problems alive
+        arr = (C.c_void_p * len(self.problems))(*[p.h.value for p in self.problems])
+        h = C.c_void_p()
+        rc = self.lib.hinv_batch_create(ctx.h, len(self.problems), arr, C.byref(h))
+        if rc != HINV_OK:
+            raise HinvError(rc, ctx.error() or self.lib.hinv_status_string(rc).decode())
+        self.h = h
+
+    def _check(self, rc, allow=(HINV_ENOCONV,)):
+        if rc != HINV_OK and rc not in allow:
+            raise HinvError(rc, self.ctx.error() or self.lib.hinv_status_string(rc).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hinv_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, ts, ncol):
+        if len(ts) != len(self.problems):
+            raise ValueError("one tensor per problem")
+        out = []
+        for t, p in zip(ts, self.problems):
+            if t.dim() != 2 or t.shape[0] < ncol or t.shape[1] != p.n or (t.numel() and t.stride(0) != p.n):
+                raise ValueError("expected a packed (c, n_i) tensor per problem")
+            out.append(_ptr(t).value)
+        return (C.c_void_p * len(out))(*out)
+
+    def hessian_apply(self, mode, mhats, outs):
+        nrhs = mhats[0].shape[0]
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_batch_hessian_apply(self.h, mode, nrhs, self._ptrs(mhats, nrhs),
+                                                           self._ptrs(outs, nrhs), C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def lowrank_eig(self, omegas, k, Vs, mode=HESS_MISFIT, tprod=TPROD_FP64):
+        s = omegas[0].shape[0]
+        lam = (C.c_double * (k * len(self.problems)))()
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_batch_lowrank_eig(self.h, mode, tprod, s, self._ptrs(omegas, s), k,
+                                                         lam, self._ptrs(Vs, k), C.byref(info)))
+        return np.array(lam[:]).reshape(len(self.problems), k), info.as_dict() | {"rc": rc}
 
 
 def default_beta(gamma, delta):

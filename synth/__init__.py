@@ -29,6 +29,7 @@ STREAM_OMEGA = 3      # Gaussian probe matrix of the randomized eigensolver
 STREAM_POST = 4       # white noise of posterior samples
 STREAM_TEST = 7       # generic test vectors (directions, right-hand sides)
 STREAM_SAMPLE = 8     # sampled output indices and random functionals of large tests
+STREAM_BATCH = 9      # sizes and prior parameters of the uneven batch
 
 # Synthetic workloads shaped like the paper's Poisson example, scaled up.
 WORKLOADS = {
@@ -36,6 +37,20 @@ WORKLOADS = {
     "poisson256": dict(N=256, q=400, gamma=0.1, delta=0.5, m_prior=-2.0, k=50, p=20),
     "poisson1024": dict(N=1024, q=2000, gamma=0.05, delta=1.0, m_prior=-2.0, k=200, p=20),
 }
+
+
+def uneven_batch(count: int = 64, seed: int = MASTER_SEED, sizes=(64, 128, 256, 512),
+                 q_range=(100, 1000), gamma_range=(0.05, 0.2), delta_range=(0.5, 2.0)) -> list:
+    """Instances of the uneven batch: mesh size uniform over ``sizes``, gamma and
+    delta uniform over their ranges, q uniform over the integers in q_range;
+    instance i draws its own true field and data with seed + i."""
+    g = _gen(seed, STREAM_BATCH)
+    Ns = g.choice(np.asarray(sizes), size=count)
+    gam = g.uniform(*gamma_range, size=count)
+    dl = g.uniform(*delta_range, size=count)
+    qs = g.integers(q_range[0], q_range[1] + 1, size=count)
+    return [dict(N=int(Ns[i]), q=int(qs[i]), gamma=float(gam[i]), delta=float(dl[i]), m_prior=-2.0,
+                 seed=seed + i) for i in range(count)]
 
 
 def _gen(seed: int, stream: int) -> np.random.Generator:
