@@ -84,6 +84,7 @@ extern "C" {
 typedef struct hinv_ctx hinv_ctx;
 typedef struct hinv_problem hinv_problem;
 typedef struct hinv_batch hinv_batch;
+typedef struct hinv_cnn hinv_cnn;
 
 typedef struct {
     int    N;          /* cells per side, a power of two >= 4 */
@@ -269,6 +270,70 @@ int hinv_batch_hessian_apply(hinv_batch* b, int mode, int nrhs, const double* co
  * tprod as in hinv_lowrank_eig. */
 int hinv_batch_lowrank_eig(hinv_batch* b, int mode, int tprod, int s, const double* const* omega,
                            int k, double* lambda_host, double* const* V, hinv_solve_info* info);
+
+/* ---- state operator at the linearization point ------------------------------ */
+/* y = A(m) x restricted to the free rows (zero on the Dirichlet rows y = 0, 1):
+ * the stiffness of the weak form (Sec. 5.1) with coefficient e^m, m the
+ * linearization point.  Device, column-major, ld >= n. */
+int hinv_state_apply(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy);
+/* A(m) x = b on the free rows (Dirichlet entries of x are zero) by multigrid
+ * PCG with the problem's precision and tolerance. */
+int hinv_state_solve(hinv_problem* p, int nrhs, const double* b, int ldb, double* x, int ldx,
+                     hinv_solve_info* info);
+
+typedef struct hinv_fcg_info {
+    int status;               /* HINV_OK or HINV_ENOCONV */
+    int iterations;           /* flexible-CG iterations */
+    int fallback;             /* 1: stalled, multigrid PCG finished the solve */
+    int fallback_iterations;  /* PCG iterations of the fallback */
+    double relres;            /* final |b - A x| / |b| (recomputed) */
+} hinv_fcg_info;
+
+/* Flexible CG (Notay, SIAM J. Sci. Comput. 2000) on A(m) x = b, one
+ * right-hand side, FP64: each new direction is A-orthogonalized against the
+ * last `truncation` directions (1..32).  Preconditioner: one multigrid V-cycle
+ * z = V(r), and when net is not NULL the network's correction of the residual
+ * t = r - A z that the V-cycle leaves, c = s y(t / s, m, mask) with s the rms
+ * of t, added at the step that minimizes the A-norm of the remaining error:
+ * z += omega c, omega = c^T t / c^T A c (skipped unless positive).  Less than a 10x residual drop over 20 iterations hands the rest to
+ * multigrid PCG.  b, x: device vectors of length n. */
+int hinv_state_solve_fcg(hinv_problem* p, hinv_cnn* net, const double* b, double* x, double rtol,
+                         int max_iter, int truncation, hinv_fcg_info* info);
+
+/* ---- learned correction: residual CNN ------------------------------------- */
+/* Six 3x3 convolutions with zero padding (3 -> 32, four residual 32 -> 32 with
+ * ReLU, 32 -> 1), BF16 weights and activations on the matrix cores, FP32
+ * accumulation, FP32 master parameters and Adam (beta 0.9 / 0.999, eps 1e-8).
+ * Parameters are packed per layer as W[c_out][c_in][3][3] then b[c_out]; a new
+ * network has all parameters zero. */
+int hinv_cnn_create(hinv_ctx* ctx, hinv_cnn** out);
+int hinv_cnn_destroy(hinv_cnn* net);
+int hinv_cnn_param_count(void);
+int hinv_cnn_set_params(hinv_cnn* net, const float* host, int count); /* resets Adam */
+int hinv_cnn_get_params(hinv_cnn* net, float* host, int count);
+/* in: device FP32 [B][3][S][S] (channel, row, column); out: device FP32 [B][S][S]. */
+int hinv_cnn_forward(hinv_cnn* net, int B, int S, const float* in, float* out);
+/* Loss and its gradient; grad_host (HOST, may be NULL) receives the gradient in
+ * the packed layout.  tchan = 1: target device FP32 [B][S][S], loss = mean over
+ * the batch of |y - t|^2 / |t|^2.  tchan = 4: target [B][4][S][S] =
+ * (t, wE, wN, diag), loss = mean of d^T A d / t^T A t with d = (y - t) on the
+ * free nodes (input channel 2) and A the 5-point stencil with east / north
+ * edge weights wE, wN and diagonal diag (neighbours outside the image zero). */
+int hinv_cnn_gradient(hinv_cnn* net, int B, int S, const float* in, const float* target, int tchan,
+                      double* loss, float* grad_host);
+/* gradient and one Adam step with learning rate lr; loss before the step. */
+int hinv_cnn_train_step(hinv_cnn* net, int B, int S, const float* in, const float* target, int tchan,
+                        float lr, double* loss);
+/* npairs training pairs from the problem's incremental forward solves at its
+ * linearization point (App. A): b = -C(u) mhat for random mhat, x_k after
+ * k = 0..7 multigrid-PCG iterations, r = b - A x_k, r' = r - A V(r),
+ * e' = A^-1 r'.  Each pair is cut to a crop x crop window at a seeded position
+ * and scaled by the rms s of r' there: in[i] = (r' / s, m, free mask)
+ * (device FP32 [npairs][3][crop][crop]), target[i] = (e' / s, wE, wN, diag)
+ * ([npairs][4][crop][crop]: the stencil of A(m) on the window, for the energy
+ * loss). */
+int hinv_cnn_harvest(hinv_problem* p, int npairs, uint64_t seed, int crop, float* in, float* target,
+                     hinv_solve_info* info);
 
 #ifdef __cplusplus
 }

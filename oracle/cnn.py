@@ -11,7 +11,10 @@ conv is cross-correlation: conv(x, W)[o, i, j] = sum_{c, a, b} W[o, c, a, b]
 x[c, i + a - 1, j + b - 1] with x = 0 outside the image.  Images are indexed
 [row j][column i] = node (i, j) of the mesh.
 
-Loss over a batch: mean over samples of |y - t|^2 / |t|^2 (relative L2).
+Loss over a batch: mean over samples of |y - t|^2 / |t|^2 (relative L2), or of
+(y - t)^T A (y - t) / t^T A t (relative energy norm) with A the 5-point stencil
+of the state operator given beside the target and the free-node mask of the
+input.
 Training: Adam (Kingma and Ba, 2015) with beta1 = 0.9, beta2 = 0.999,
 eps = 1e-8 and bias correction.
 
@@ -111,7 +114,8 @@ def forward(theta, x, round_bf16: bool = False, shapes=None):
     """Network output y (B, 1, H, W) and the cache of the backward pass.
 
     round_bf16: weights and every convolution input rounded to bf16 (the
-    values the device network multiplies; sums stay exact here)."""
+    values the device network multiplies; sums stay exact here).  In the
+    gradient the output gradient of every convolution is rounded likewise."""
     layers = unpack(np.asarray(theta, dtype=float), shapes)
     rnd = bf16 if round_bf16 else (lambda v: v)
     cache = []
@@ -139,18 +143,49 @@ def loss(y, t):
     return L, gy
 
 
+def stencil_apply(v, wE, wN, diag):
+    """(A v) on an image: 5-point operator with edge weights wE (to the east
+    neighbour), wN (to the north neighbour) and diagonal diag; neighbours
+    outside the image count zero.  Arrays (..., H, W) indexed [row][column]."""
+    Av = diag * v
+    Av[..., :, :-1] -= wE[..., :, :-1] * v[..., :, 1:]
+    Av[..., :, 1:] -= wE[..., :, :-1] * v[..., :, :-1]
+    Av[..., :-1, :] -= wN[..., :-1, :] * v[..., 1:, :]
+    Av[..., 1:, :] -= wN[..., :-1, :] * v[..., :-1, :]
+    return Av
+
+
+def energy_loss(y, t4, mask):
+    """mean_b (d^T A d) / (t^T A t), d = (y - t) * mask, with A the 5-point
+    stencil of t4[:, 1:4] = (wE, wN, diag); and its gradient w.r.t. y."""
+    B = y.shape[0]
+    t = t4[:, 0:1]
+    wE, wN, dg = t4[:, 1:2], t4[:, 2:3], t4[:, 3:4]
+    d = (y - t) * mask
+    tm = t * mask
+    Ad = stencil_apply(d, wE, wN, dg) * mask
+    At = stencil_apply(tm, wE, wN, dg) * mask
+    num = (d * Ad).reshape(B, -1).sum(axis=1)
+    den = (tm * At).reshape(B, -1).sum(axis=1)
+    L = float(np.mean(num / den))
+    gy = 2.0 * Ad / (den[:, None, None, None] * B)
+    return L, gy
+
+
 def gradient(theta, x, t, round_bf16: bool = False, shapes=None):
-    """Loss and its gradient (packed like theta)."""
+    """Loss and its gradient (packed like theta).  t: (B, 1, H, W) for the
+    relative L2 loss, (B, 4, H, W) = (target, wE, wN, diag) for the relative
+    energy norm with the free-node mask taken from input channel 2."""
     layers = unpack(np.asarray(theta, dtype=float), shapes)
     rnd = bf16 if round_bf16 else (lambda v: v)
     y, cache = forward(theta, x, round_bf16, shapes)
-    L, g = loss(y, t)
+    L, g = loss(y, t) if t.shape[1] == 1 else energy_loss(y, t, x[:, 2:3])
     grads = [None] * len(layers)
     # g holds dL/dh of the current layer's output
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
         inp, z = cache[li]
-        gz = g if li == len(layers) - 1 else g * (z > 0)
+        gz = rnd(g if li == len(layers) - 1 else g * (z > 0))
         gx, gW, gb = conv_backward(inp, rnd(W), gz)
         grads[li] = (gW, gb)
         if li > 0:

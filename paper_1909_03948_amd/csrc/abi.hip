@@ -9,6 +9,8 @@
 
 #include "algos.h"
 #include "batch.h"
+#include "cnn.h"
+#include "fcg.h"
 #include "problem.h"
 
 struct hinv_ctx {
@@ -18,6 +20,11 @@ struct hinv_ctx {
 struct hinv_problem {
     hinv_ctx* owner;
     std::unique_ptr<hinv::Problem> p;
+};
+
+struct hinv_cnn {
+    hinv_ctx* owner;
+    std::unique_ptr<hinv::Cnn> net;
 };
 
 struct hinv_batch {
@@ -497,6 +504,146 @@ int hinv_batch_lowrank_eig(hinv_batch* b, int mode, int tprod, int s, const doub
     if (rc != HINV_OK) return rc;
     if (status != HINV_OK) return status;
     return conv_status(st);
+}
+
+// ------------------------------------------------- state-operator solves ---
+int hinv_state_apply(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(nrhs >= 0 && ldx >= n && ldy >= n, "bad size or leading dimension");
+        REQUIRE(nrhs == 0 || (x && y), "null vector");
+        REQUIRE(p->p->linearized, "state operator used before hinv_linearize");
+        if (!nrhs) return;
+        p->p->ensure_lin_hierarchy();
+        p->p->HA->apply(nrhs, x, ldx, y, ldy);
+    });
+}
+
+int hinv_state_solve(hinv_problem* p, int nrhs, const double* b, int ldb, double* x, int ldx,
+                     hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(nrhs >= 0 && ldb >= n && ldx >= n, "bad size or leading dimension");
+        REQUIRE(nrhs == 0 || (b && x), "null vector");
+        REQUIRE(p->p->linearized, "state operator used before hinv_linearize");
+        if (!nrhs) return;
+        hinv::Problem& P = *p->p;
+        P.ensure_lin_hierarchy();
+        P.HA->solve(nrhs, b, ldb, x, ldx, P.precision, P.rtol, P.max_iter, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
+int hinv_state_solve_fcg(hinv_problem* p, hinv_cnn* net, const double* b, double* x, double rtol,
+                         int max_iter, int truncation, hinv_fcg_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::FcgStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        REQUIRE(b && x, "null vector");
+        REQUIRE(rtol > 0 && rtol < 1, "rtol must be in (0, 1)");
+        REQUIRE(max_iter >= 1, "max_iter must be >= 1");
+        REQUIRE(truncation >= 1 && truncation <= 32, "truncation must be in [1, 32]");
+        REQUIRE(!net || net->owner == p->owner, "network and problem must share the context");
+        REQUIRE(p->p->linearized, "state operator used before hinv_linearize");
+        hinv::state_solve_fcg(*p->p, net ? net->net.get() : nullptr, b, x, rtol, max_iter, truncation, &st);
+    });
+    if (info) {
+        info->status = st.converged ? HINV_OK : HINV_ENOCONV;
+        info->iterations = st.iterations;
+        info->fallback = st.fallback;
+        info->fallback_iterations = st.fallback_iterations;
+        info->relres = st.relres;
+    }
+    if (rc != HINV_OK) return rc;
+    return st.converged ? HINV_OK : HINV_ENOCONV;
+}
+
+// ------------------------------------------------------------- network ---
+int hinv_cnn_create(hinv_ctx* c, hinv_cnn** out) {
+    if (!c || !out) return HINV_EINVAL;
+    *out = nullptr;
+    return guarded(&c->c, [&] {
+        set_device(&c->c);
+        auto h = std::make_unique<hinv_cnn>();
+        h->owner = c;
+        h->net = std::make_unique<hinv::Cnn>(&c->c);
+        *out = h.release();
+    });
+}
+
+int hinv_cnn_destroy(hinv_cnn* net) {
+    if (!net) return HINV_EINVAL;
+    delete net;
+    return HINV_OK;
+}
+
+int hinv_cnn_param_count(void) { return hinv::Cnn::nparams(); }
+
+int hinv_cnn_set_params(hinv_cnn* net, const float* host, int count) {
+    if (!net) return HINV_EINVAL;
+    return guarded(&net->owner->c, [&] {
+        REQUIRE(host && count == hinv::Cnn::nparams(), "parameter count mismatch");
+        net->net->set_params(host);
+    });
+}
+
+int hinv_cnn_get_params(hinv_cnn* net, float* host, int count) {
+    if (!net) return HINV_EINVAL;
+    return guarded(&net->owner->c, [&] {
+        REQUIRE(host && count == hinv::Cnn::nparams(), "parameter count mismatch");
+        net->net->get_params(host);
+    });
+}
+
+int hinv_cnn_forward(hinv_cnn* net, int B, int S, const float* in, float* out) {
+    if (!net) return HINV_EINVAL;
+    return guarded(&net->owner->c, [&] {
+        REQUIRE(B >= 1 && S >= 1 && S <= 8193 && (long long)B * S * S <= (1LL << 28), "bad image batch size");
+        REQUIRE(in && out, "null image");
+        net->net->forward(B, S, in, out);
+    });
+}
+
+int hinv_cnn_gradient(hinv_cnn* net, int B, int S, const float* in, const float* target, int tchan,
+                      double* loss, float* grad_host) {
+    if (!net) return HINV_EINVAL;
+    return guarded(&net->owner->c, [&] {
+        REQUIRE(B >= 1 && S >= 1 && S <= 8193 && (long long)B * S * S <= (1LL << 26), "bad image batch size");
+        REQUIRE(tchan == 1 || tchan == 4, "target channels must be 1 or 4");
+        REQUIRE(in && target && loss, "null argument");
+        *loss = net->net->gradient(B, S, in, target, tchan, grad_host);
+    });
+}
+
+int hinv_cnn_train_step(hinv_cnn* net, int B, int S, const float* in, const float* target, int tchan,
+                        float lr, double* loss) {
+    if (!net) return HINV_EINVAL;
+    return guarded(&net->owner->c, [&] {
+        REQUIRE(B >= 1 && S >= 1 && S <= 8193 && (long long)B * S * S <= (1LL << 26), "bad image batch size");
+        REQUIRE(tchan == 1 || tchan == 4, "target channels must be 1 or 4");
+        REQUIRE(in && target && loss, "null argument");
+        REQUIRE(lr > 0 && std::isfinite(lr), "learning rate must be positive");
+        *loss = net->net->train_step(B, S, in, target, tchan, lr);
+    });
+}
+
+int hinv_cnn_harvest(hinv_problem* p, int npairs, uint64_t seed, int crop, float* in, float* target,
+                     hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        REQUIRE(npairs >= 0, "npairs must be >= 0");
+        REQUIRE(crop >= 3 && crop <= p->p->N + 1, "crop must be in [3, N + 1]");
+        REQUIRE(npairs == 0 || (in && target), "null output");
+        REQUIRE(p->p->linearized, "harvest before hinv_linearize");
+        if (npairs) hinv::cnn_harvest(*p->p, npairs, seed, crop, in, target, &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
 }
 
 }  // extern "C"

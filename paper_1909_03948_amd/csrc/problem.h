@@ -65,8 +65,10 @@ class Problem {
     double* scratch(int which, int nc);
     double* obs_scratch(int nc);
 
-  private:
+    // A(m_lin) rebuilt in HA if a solve at another parameter replaced it
     void ensure_lin_hierarchy();
+
+  private:
     static constexpr int kScratch = 8;
     int cap_ = 0;
     DBuf<double> w_[kScratch];

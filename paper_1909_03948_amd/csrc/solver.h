@@ -65,12 +65,15 @@ class Hierarchy {
                int max_iter, SolveStats* st);
     // y = A x (FP64, masked to free rows).
     void apply(int nc, const double* x, int ldx, double* y, int ldy);
+    // z = one V-cycle (FP64) applied to r, zero on Dirichlet rows.
+    void precondition(int nc, const double* r, int ldr, double* z, int ldz);
     // Level-0 triangle coefficients c_T (state operator only).
     const double* coefficient(int inst = 0) const {
         return lev_[0]->cT.get() + (size_t)inst * 2 * N_ * N_;
     }
     const double* weightsE(int inst = 0) const { return lev_[0]->wE64.get() + (size_t)inst * n_; }
     const double* weightsN(int inst = 0) const { return lev_[0]->wN64.get() + (size_t)inst * n_; }
+    const double* inv_diag(int inst = 0) const { return lev_[0]->dinv64.get() + (size_t)inst * n_; }
     bool ready() const { return ready_; }
     int N() const { return N_; }
     int n() const { return n_; }

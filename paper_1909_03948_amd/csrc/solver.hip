@@ -291,6 +291,22 @@ __global__ void k_copy_cols(const double* __restrict__ a, int lda, double* __res
     if (k < n) col(b, ldb)[k] = col(a, lda)[k];
 }
 
+// dst = src on free rows, 0 on Dirichlet rows.
+template <class Op>
+__global__ void k_masked_copy(Op op_, const double* __restrict__ src, int lds, double* __restrict__ dst,
+                              int ldd) {
+    const auto& op = op_.at(blockIdx.y);
+    const int N1 = op.N + 1, n = N1 * N1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    col(dst, ldd)[k] = op.is_free(k % N1, k / N1) ? col(src, lds)[k] : 0.0;
+}
+
+__global__ void k_fill_int(int n, int v, int* __restrict__ a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
 __global__ void k_bb_init(ColState* st, int nc) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < nc) st[c].bb = 1.0;
@@ -818,6 +834,29 @@ void Hierarchy::apply(int nc, const double* x, int ldx, double* y, int ldy) {
     const dim3 g = grid2(n_, nc);
     with_op<double>(0, [&](auto op) {
         k_apply<double><<<g, kBlock, 0, s>>>(op, x, ldx, y, ldy, nullptr, nullptr);
+    });
+    HINV_LAUNCH_CHECK();
+}
+
+void Hierarchy::precondition(int nc, const double* r, int ldr, double* z, int ldz) {
+    if (!ready_) fail(HINV_ESTATE, "operator used before its coefficient was set");
+    if (nc <= 0) return;
+    hipStream_t s = ctx_->stream;
+    set_columns(nc);
+    ensure_cols(nc);
+    if (w64_.cap < nc) drop_graphs();
+    ensure_work(w64_, lev_, nc);
+    const dim3 g = grid2(n_, nc);
+    with_op<double>(0, [&](auto op) {
+        k_masked_copy<<<g, kBlock, 0, s>>>(op, r, ldr, w64_.r.get(), n_);
+    });
+    HINV_LAUNCH_CHECK();
+    k_fill_int<<<ceil_div(nc, 64), 64, 0, s>>>(nc, 1, act_.get());
+    HINV_LAUNCH_CHECK();
+    launch_stream_ = s;
+    vcycle<double>(nc, 0);
+    with_op<double>(0, [&](auto op) {
+        k_masked_copy<<<g, kBlock, 0, s>>>(op, w64_.z.get(), n_, z, ldz);
     });
     HINV_LAUNCH_CHECK();
 }

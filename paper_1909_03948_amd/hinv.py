@@ -25,6 +25,14 @@ TPROD_FP64, TPROD_BF16 = 0, 1
 NEWTON_MAXREC = 64
 
 
+class FcgInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("fallback", C.c_int),
+                ("fallback_iterations", C.c_int), ("relres", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ProblemDesc(C.Structure):
     _fields_ = [("N", C.c_int), ("gamma", C.c_double), ("delta", C.c_double),
                 ("beta", C.c_double), ("m_prior", C.c_double), ("q", C.c_int),
@@ -72,7 +80,10 @@ EXPORTS = [
     "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_solve", "hinv_prior_sample",
     "hinv_map_newton", "hinv_lowrank_eig", "hinv_posterior_sample", "hinv_ctx_kernel_timer",
     "hinv_ctx_kernel_timer_read", "hinv_white_noise", "hinv_batch_create", "hinv_batch_destroy",
-    "hinv_batch_hessian_apply", "hinv_batch_lowrank_eig",
+    "hinv_batch_hessian_apply", "hinv_batch_lowrank_eig", "hinv_state_apply", "hinv_state_solve",
+    "hinv_state_solve_fcg", "hinv_cnn_create", "hinv_cnn_destroy", "hinv_cnn_param_count",
+    "hinv_cnn_set_params", "hinv_cnn_get_params", "hinv_cnn_forward", "hinv_cnn_gradient",
+    "hinv_cnn_train_step", "hinv_cnn_harvest",
 ]
 
 KCLASS = {"mg_down": 0, "mg_up": 1, "mg_bottom": 2, "pcg_apply": 3, "pcg_update": 4, "gram": 5}
@@ -91,6 +102,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib = C.CDLL(path)
     P, I, D, V = C.c_void_p, C.c_int, C.c_double, C.c_void_p
     DP = C.POINTER(C.c_double)
+    FP = C.POINTER(C.c_float)
     sig = {
         "hinv_ctx_create": [I, V, C.POINTER(P)],
         "hinv_ctx_destroy": [P],
@@ -124,6 +136,18 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_batch_hessian_apply": [P, I, I, C.POINTER(V), C.POINTER(V), C.POINTER(SolveInfo)],
         "hinv_batch_lowrank_eig": [P, I, I, I, C.POINTER(V), I, DP, C.POINTER(V),
                                    C.POINTER(SolveInfo)],
+        "hinv_state_apply": [P, I, V, I, V, I],
+        "hinv_state_solve": [P, I, V, I, V, I, C.POINTER(SolveInfo)],
+        "hinv_state_solve_fcg": [P, P, V, V, D, I, I, C.POINTER(FcgInfo)],
+        "hinv_cnn_create": [P, C.POINTER(P)],
+        "hinv_cnn_destroy": [P],
+        "hinv_cnn_param_count": [],
+        "hinv_cnn_set_params": [P, FP, I],
+        "hinv_cnn_get_params": [P, FP, I],
+        "hinv_cnn_forward": [P, I, I, V, V],
+        "hinv_cnn_gradient": [P, I, I, V, V, I, DP, FP],
+        "hinv_cnn_train_step": [P, I, I, V, V, I, C.c_float, DP],
+        "hinv_cnn_harvest": [P, I, C.c_uint64, I, V, V, C.POINTER(SolveInfo)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -328,6 +352,33 @@ class Problem:
         self._check(rc, allow=(HINV_ENOCONV, HINV_ESTATE))
         return info.as_dict() | {"rc": rc}
 
+    def state_apply(self, x, y):
+        px, nc, ldx = _cols(x, self.n)
+        py, _, ldy = _cols(y, self.n)
+        self._check(self.lib.hinv_state_apply(self.h, nc, px, ldx, py, ldy), allow=())
+
+    def state_solve(self, b, x):
+        pb, nc, ldb = _cols(b, self.n)
+        px, _, ldx = _cols(x, self.n)
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_state_solve(self.h, nc, pb, ldb, px, ldx, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def state_solve_fcg(self, b, x, net=None, rtol=1e-10, max_iter=200, truncation=1):
+        info = FcgInfo()
+        rc = self._check(self.lib.hinv_state_solve_fcg(self.h, None if net is None else net.h, _ptr(b), _ptr(x),
+                                                       rtol, max_iter, truncation, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
+    def cnn_harvest(self, npairs, seed, crop, inp, target):
+        """inp: CUDA float32 (npairs, 3, crop, crop); target: (npairs, 4, crop, crop)."""
+        _fcheck(inp, (npairs, 3, crop, crop))
+        _fcheck(target, (npairs, 4, crop, crop))
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_cnn_harvest(self.h, npairs, seed, crop, C.c_void_p(inp.data_ptr()),
+                                                   C.c_void_p(target.data_ptr()), C.byref(info)))
+        return info.as_dict() | {"rc": rc}
+
     def lowrank_eig(self, omega, k, V, mode=HESS_MISFIT, tprod=TPROD_FP64):
         po, s, ldo = _cols(omega, self.n)
         pv, kv, ldv = _cols(V, self.n)
@@ -348,6 +399,91 @@ class Problem:
         rc = self._check(self.lib.hinv_posterior_sample(self.h, _ptr(m_map), k, lam_arr, pv, ldv, ns,
                                                         pe, lde, po, ldo, C.byref(info)))
         return info.as_dict() | {"rc": rc}
+
+
+def _fcheck(t, shape):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError("expected a CUDA float32 tensor")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous tensor of shape {shape}")
+
+
+class Cnn:
+    """Binding of hinv_cnn (the residual CNN of the learned correction).
+    Images: CUDA float32 tensors, input (B, 3, S, S), output / target (B, S, S)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx, self.lib = ctx, ctx.lib
+        h = C.c_void_p()
+        rc = self.lib.hinv_cnn_create(ctx.h, C.byref(h))
+        if rc != HINV_OK:
+            raise HinvError(rc, ctx.error() or self.lib.hinv_status_string(rc).decode())
+        self.h = h
+        self.nparams = self.lib.hinv_cnn_param_count()
+
+    def _check(self, rc):
+        if rc != HINV_OK:
+            raise HinvError(rc, self.ctx.error() or self.lib.hinv_status_string(rc).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hinv_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        if a.size != self.nparams:
+            raise ValueError("parameter count mismatch")
+        self._check(self.lib.hinv_cnn_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+    def get_params(self):
+        a = np.zeros(self.nparams, dtype=np.float32)
+        self._check(self.lib.hinv_cnn_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def forward(self, inp, out):
+        B, S = inp.shape[0], inp.shape[-1]
+        _fcheck(inp, (B, 3, S, S))
+        _fcheck(out, (B, S, S))
+        self._check(self.lib.hinv_cnn_forward(self.h, B, S, C.c_void_p(inp.data_ptr()), C.c_void_p(out.data_ptr())))
+
+    @staticmethod
+    def _tchan(target, B, S):
+        if target.dim() == 3:
+            _fcheck(target, (B, S, S))
+            return 1
+        _fcheck(target, (B, 4, S, S))
+        return 4
+
+    def gradient(self, inp, target):
+        """target (B, S, S): relative L2 loss; (B, 4, S, S) = (t, wE, wN, diag):
+        relative energy norm."""
+        B, S = inp.shape[0], inp.shape[-1]
+        _fcheck(inp, (B, 3, S, S))
+        tc = self._tchan(target, B, S)
+        g = np.zeros(self.nparams, dtype=np.float32)
+        L = C.c_double()
+        self._check(self.lib.hinv_cnn_gradient(self.h, B, S, C.c_void_p(inp.data_ptr()),
+                                               C.c_void_p(target.data_ptr()), tc, C.byref(L),
+                                               g.ctypes.data_as(C.POINTER(C.c_float))))
+        return L.value, g
+
+    def train_step(self, inp, target, lr):
+        B, S = inp.shape[0], inp.shape[-1]
+        _fcheck(inp, (B, 3, S, S))
+        tc = self._tchan(target, B, S)
+        L = C.c_double()
+        self._check(self.lib.hinv_cnn_train_step(self.h, B, S, C.c_void_p(inp.data_ptr()),
+                                                 C.c_void_p(target.data_ptr()), tc, float(lr), C.byref(L)))
+        return L.value
 
 
 class Batch:

@@ -49,6 +49,44 @@ def test_gradient_matches_finite_differences():
         assert abs(fd - grad[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, grad[idx])
 
 
+def test_energy_gradient_matches_finite_differences():
+    g = rng(12)
+    theta = cnn.init_params(g, SMALL, scale=1.5)
+    theta += 0.05 * g.standard_normal(theta.size)
+    x = g.standard_normal((2, 3, 6, 5))
+    x[:, 2] = (g.random((2, 6, 5)) > 0.2).astype(float)  # free-node mask
+    t = np.concatenate([g.standard_normal((2, 1, 6, 5)), 0.5 + g.random((2, 2, 6, 5)),
+                        np.zeros((2, 1, 6, 5))], axis=1)
+    t[:, 3] = 2.5 + g.random((2, 6, 5))  # diagonally dominant: positive definite
+    L, grad = cnn.gradient(theta, x, t, shapes=SMALL)
+    eps = 1e-6
+    for idx in g.choice(theta.size, size=25, replace=False):
+        e = np.zeros_like(theta)
+        e[idx] = eps
+        Lp, _ = cnn.energy_loss(cnn.forward(theta + e, x, shapes=SMALL)[0], t, x[:, 2:3])
+        Lm, _ = cnn.energy_loss(cnn.forward(theta - e, x, shapes=SMALL)[0], t, x[:, 2:3])
+        fd = (Lp - Lm) / (2 * eps)
+        assert abs(fd - grad[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, grad[idx])
+
+
+def test_stencil_is_the_assembled_matrix():
+    """stencil_apply equals the sparse 5-point matrix built edge by edge."""
+    g = rng(13)
+    H, W = 5, 4
+    wE, wN = g.random((H, W)), g.random((H, W))
+    dg = 3.0 + g.random((H, W))
+    A = np.diag(dg.reshape(-1))
+    idx = lambda r, c: r * W + c
+    for r in range(H):
+        for c in range(W):
+            if c + 1 < W:
+                A[idx(r, c), idx(r, c + 1)] = A[idx(r, c + 1), idx(r, c)] = -wE[r, c]
+            if r + 1 < H:
+                A[idx(r, c), idx(r + 1, c)] = A[idx(r + 1, c), idx(r, c)] = -wN[r, c]
+    v = g.standard_normal((H, W))
+    np.testing.assert_allclose(cnn.stencil_apply(v, wE, wN, dg).reshape(-1), A @ v.reshape(-1), rtol=1e-13)
+
+
 def test_first_adam_step():
     g = rng(3)
     th = g.standard_normal(50)
