@@ -20,6 +20,12 @@ parameters, 2 000 observations, gamma = 0.05, delta = 1, k = 200, p = 20): the
 same step followed by 1 000 posterior samples through the low-rank update,
 their white noise drawn on the device by the counter-based generator.
 
+``--workload learned1024`` runs the learned correction on the 1024 x 1024
+problem: 20 000 training pairs harvested from the incremental solves of 50
+seeded true fields, the residual CNN trained on the device, then flexible CG
+with and without it against multigrid PCG at a 1e-10 relative residual on a
+held-out field (iterations and wall time).
+
 ``--workload uneven64`` runs 64 independent inversions with mesh sizes drawn
 from {64, 128, 256, 512}, their own prior parameters, observations and true
 fields: one step is the double pass (k = 50, p = 20) of every instance at its
@@ -273,12 +279,116 @@ def run_uneven(a):
     print(json.dumps(line), flush=True)
 
 
+def run_learned(a):
+    """Learned correction on the 1024 x 1024 problem (harvest, train, compare)."""
+    import torch
+    from oracle import cnn as ocnn  # parameter initialisation only (He normal)
+    from paper_1909_03948_amd import hinv as hv
+    cfg = synth.WORKLOADS["poisson1024"]
+    N, q = cfg["N"], cfg["q"]
+    n = (N + 1) ** 2
+    fields, ppf, crop, steps, B, lr0 = 50, 400, 64, 4000, 32, 2e-3
+    ctx = hv.Context(0)
+
+    def field(seed):
+        gp = hv.Problem(ctx, N, cfg["gamma"], cfg["delta"], obs_xy=synth.obs_points(q, seed=seed), d_obs=None,
+                        sigma=0.01, m_prior=cfg["m_prior"], precision=hv.PREC_AUTO, rtol=1e-10)
+        z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+        eta = z(1, 6 * N * N)
+        gp.white_noise(seed, synth.STREAM_TRUTH, 0, eta)
+        m, u, pp, g, Bu = z(n), z(n), z(n), z(n), z(q)
+        gp.prior_sample(eta, m)
+        gp.forward(m, u)
+        gp.observe(u, Bu)
+        torch.cuda.synchronize()
+        sig = 0.01 * float(u.abs().max())
+        gp.set_data(Bu.cpu().numpy() + sig * synth.obs_noise(q, seed=seed), sig)
+        gp.gradient(m, u, pp, g)
+        gp.linearize(m, u, pp)
+        return gp
+
+    X = torch.zeros((fields * ppf, 3, crop, crop), dtype=torch.float32, device="cuda")
+    T = torch.zeros((fields * ppf, 4, crop, crop), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    for f in range(fields):
+        gp = field(10000 + f)
+        gp.cnn_harvest(ppf, 77 + f, crop, X[f * ppf:(f + 1) * ppf], T[f * ppf:(f + 1) * ppf])
+        del gp
+        if f % 10 == 9:
+            log(f"harvested {(f + 1) * ppf} pairs, {time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    harvest_s = time.perf_counter() - t0
+    net = hv.Cnn(ctx)
+    net.set_params(ocnn.init_params(np.random.default_rng(0)))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    t0 = time.perf_counter()
+    losses = []
+    for st in range(steps):
+        idx = torch.randint(0, X.shape[0], (B,), device="cuda", generator=gen)
+        lr = lr0 * 0.5 * (1.0 + np.cos(np.pi * st / steps))
+        losses.append(net.train_step(X[idx].contiguous(), T[idx].contiguous(), lr))
+        if st % 1000 == 0:
+            log(f"train step {st}: energy loss {losses[-1]:.4f}")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    gp = field(10000 + fields)  # held out
+    Xh = torch.zeros((256, 3, crop, crop), dtype=torch.float32, device="cuda")
+    Th = torch.zeros((256, 4, crop, crop), dtype=torch.float32, device="cuda")
+    gp.cnn_harvest(256, 5, crop, Xh, Th)
+    held = float(np.mean([net.gradient(Xh[i:i + 32].contiguous(), Th[i:i + 32].contiguous())[0]
+                          for i in range(0, 256, 32)]))
+    gp.set_solver(hv.PREC_FP64, 1e-10)
+    res = {"fcg_plain": [], "fcg_learned": [], "mg_pcg": []}
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for trial in range(a.steps + a.warmup):
+        b = torch.as_tensor(synth.test_vectors(n, 1, stream=70 + trial)[0], device="cuda")
+        for key, fn in (("fcg_plain", lambda: gp.state_solve_fcg(b, x, None, 1e-10, 300)),
+                        ("fcg_learned", lambda: gp.state_solve_fcg(b, x, net, 1e-10, 300)),
+                        ("mg_pcg", lambda: gp.state_solve(b, x))):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            info = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            if trial >= a.warmup:
+                res[key].append((info["iterations"], 1e3 * dt, info.get("fallback", 0),
+                                 info.get("relres", info.get("max_relres"))))
+    summ = {k: {"iterations": float(np.mean([r[0] for r in v])), "ms": float(np.mean([r[1] for r in v])),
+                "fallbacks": int(sum(r[2] for r in v)), "max_relres": float(max(r[3] for r in v))}
+            for k, v in res.items()}
+    line = {
+        "metric": "state solves at 1e-10 relative residual on the 1024x1024 problem: flexible CG with the "
+                  "learned correction vs without it vs multigrid PCG (iterations, ms per solve)",
+        "value": summ["fcg_learned"]["ms"],
+        "unit": "ms/solve",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": summ["fcg_learned"]["ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 solve, bf16 network with f32 accumulation",
+        "data": "synthetic",
+        "config": {"workload": "learned1024", "N": N, "fields": fields, "pairs": fields * ppf, "crop": crop,
+                   "train_steps": steps, "batch": B, "lr": lr0, "loss": "relative energy norm"},
+        "harvest_s": harvest_s,
+        "train_s": train_s,
+        "final_train_loss": float(np.mean(losses[-50:])),
+        "heldout_energy_loss": held,
+        "solvers": summ,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["poisson256", "poisson1024", "uneven64"], default=WORKLOAD)
+    ap.add_argument("--workload", choices=["poisson256", "poisson1024", "uneven64", "learned1024"],
+                    default=WORKLOAD)
     ap.add_argument("--samples", type=int, default=1000,
                     help="posterior samples per step (poisson1024 only)")
     ap.add_argument("--precision", choices=["auto", "fp32ir", "fp64"], default="auto")
@@ -296,6 +406,9 @@ def main():
         sys.exit(2)
     if a.workload == "uneven64":
         run_uneven(a)
+        return
+    if a.workload == "learned1024":
+        run_learned(a)
         return
     import torch
     from paper_1909_03948_amd import hinv as hv
