@@ -104,6 +104,9 @@ def run_step(prob, omega, cfg, tprod, m_map, V, samples=None):
             prob.posterior_sample(m_map, lam, V, eta[:c], out[:c])
         torch.cuda.synchronize()
     t3 = time.perf_counter()
+    if not ninfo["converged"]:
+        log(f"WARNING: Newton did not reach its tolerance (status {ninfo['status']}, "
+            f"{ninfo['iterations']} iterations)")
     s = cfg["k"] + cfg["p"]
     hvps = ninfo["hessian_applies"] + 2 * s
     return dict(hvps=hvps, newton_s=t1 - t0, eig_s=t2 - t1, sample_s=t3 - t2, newton=ninfo,
@@ -473,6 +476,7 @@ def main():
         "eigensolver_s_per_step": eig_s / a.steps,
         "batched_hvp_per_s": 2 * s * a.steps / eig_s,
         "newton_iterations": res[-1]["newton"]["iterations"],
+        "newton_converged": all(r["newton"]["converged"] for r in res),
         "newton_hvps": res[-1]["newton"]["hessian_applies"],
         "lambda_1": float(res[-1]["lam"][0]),
         "lambda_k": float(res[-1]["lam"][-1]),

@@ -117,7 +117,9 @@ typedef struct {
     int    max_backtrack;/* Armijo backtracking steps (default 10) */
     double c_armijo;     /* Armijo constant (default 1e-4) */
     int    max_cg;       /* CG iterations per Newton step (default 500) */
-    int    gauss_newton; /* 1: Gauss-Newton Hessian in the CG */
+    int    gn_iters;     /* the first gn_iters Newton steps use the Gauss-Newton Hessian,
+                            the later ones the full Hessian (default 5; >= max_iter:
+                            Gauss-Newton throughout) */
 } hinv_newton_opts;
 
 #define HINV_NEWTON_MAXREC 64

@@ -12,7 +12,11 @@ Readings where the paper is silent or degenerate:
   or at non-positive curvature (Steihaug): at the first iteration the
   preconditioned steepest-descent direction is taken, later the current iterate;
 * Armijo constant c = 1e-4 (the paper's interval is [1e-5, 1e-4]), step halving,
-  at most 10 backtracks, at most 50 Newton and 500 CG iterations.
+  at most 10 backtracks, at most 50 Newton and 500 CG iterations;
+* the first gn_iters = 5 steps use the Gauss-Newton Hessian (positive
+  semidefinite misfit part, the alternative the paper names where the full
+  Hessian is not positive definite), later steps the full Hessian, which keeps
+  the local superlinear convergence.
 """
 from __future__ import annotations
 
@@ -22,14 +26,13 @@ from .model import HESS_FULL, HESS_GN_FULL
 
 
 def newton_cg(prob, m0=None, rel_tol=1e-6, abs_tol=0.0, max_iter=50, max_backtrack=10,
-              c_armijo=1e-4, max_cg=500, gauss_newton=False, verbose=False):
+              c_armijo=1e-4, max_cg=500, gn_iters=5, verbose=False):
     """Returns (m, info) with info = dict(iters, cost, gnorm, cg_iters, alphas, converged, reason)."""
     m = prob.m_pr.copy() if m0 is None else np.array(m0, dtype=float)
     u = prob.forward(m)
     J, _, _ = prob.cost(m, u)
     info = dict(cost=[J], gnorm=[], cg_iters=[], alphas=[], converged=False, reason="max_iter")
     g0norm = None
-    mode = HESS_GN_FULL if gauss_newton else HESS_FULL
     i = 0
     while i < max_iter:
         p = prob.adjoint(m, u)
@@ -43,6 +46,7 @@ def newton_cg(prob, m0=None, rel_tol=1e-6, abs_tol=0.0, max_iter=50, max_backtra
             info["reason"] = "gradient"
             break
         eta = min(0.5, np.sqrt(gnorm / g0norm))
+        mode = HESS_GN_FULL if i < gn_iters else HESS_FULL
 
         # --- CG with Steihaug and Eisenstat-Walker termination ---
         def H(v):

@@ -385,10 +385,10 @@ int hinv_map_newton(hinv_problem* p, const double* m0, double* m_map, const hinv
         o.max_backtrack = 10;
         o.c_armijo = 1e-4;
         o.max_cg = 500;
-        o.gauss_newton = 0;
+        o.gn_iters = 5;
         if (opts) o = *opts;
         REQUIRE(o.max_iter >= 0 && o.max_iter <= HINV_NEWTON_MAXREC, "max_iter out of range");
-        REQUIRE(o.max_backtrack >= 0 && o.max_cg >= 1, "bad Newton options");
+        REQUIRE(o.max_backtrack >= 0 && o.max_cg >= 1 && o.gn_iters >= 0, "bad Newton options");
         hinv_newton_info tmp;
         status = hinv::map_newton(*p->p, m0, m_map, o, info ? info : &tmp);
     });

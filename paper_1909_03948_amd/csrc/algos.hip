@@ -77,7 +77,6 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
     P.cost(m, u, &mis, &reg);
     double J = mis + reg;
     info->cost[0] = J;
-    const int hmode = o.gauss_newton ? HINV_HESS_GN_FULL : HINV_HESS_FULL;
     double g0 = -1.0;
     int status = HINV_ENOCONV;
     int it = 0;
@@ -97,6 +96,9 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
             break;
         }
         const double eta = std::min(0.5, std::sqrt(gn / g0));
+        // Gauss-Newton Hessian (positive semidefinite misfit part) for the first
+        // steps, where the full Hessian can be indefinite; the full Hessian after
+        const int hmode = it < o.gn_iters ? HINV_HESS_GN_FULL : HINV_HESS_FULL;
         P.linearize(m, u, p);
         // --- CG on H mhat = -g ---
         dev_fill(c, n, 0.0, mh);

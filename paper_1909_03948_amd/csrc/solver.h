@@ -95,6 +95,17 @@ class Hierarchy {
     PcgWork<T>& work();
     void ensure_cols(int nc);
     void set_columns(int nc);
+    // Launch shape of the batched kernels: V-cycle tiles (small: 8 / 16 nodes
+    // per coarse / fine side, else 16 / 32) and node blocks per workgroup of
+    // the PCG vector kernels.  Chosen by timing on the first call of each
+    // (column count, precision); HINV_AUTOTUNE=0 uses the fixed rule instead.
+    struct LaunchShape {
+        bool small;
+        int per;
+    };
+    LaunchShape default_shape(int nc) const;
+    template <typename T>
+    void tune_shape(int nc);
     void build_coarse(int inst);
     // calls fn with the operator of level l in precision T (all instances)
     template <typename T, class F>
@@ -107,6 +118,8 @@ class Hierarchy {
     bool ready_ = false;
     int ninst_ = 1;
     int cpi_ = 1;  // columns per instance of the current call
+    LaunchShape shape_{true, 1};  // launch shape of the current call
+    std::vector<std::pair<long long, LaunchShape>> tuned_;  // (nc * 2 + fp32, shape)
     std::vector<PriorParams> inst_pp_;
     std::vector<char> inst_ready_;
     DBuf<KARow<double>> karow64_;  // stacked prior rows: [level][instance][9]

@@ -580,15 +580,103 @@ PcgRed Hierarchy::pcg_red(int nc) const {
     r.rr = r.pq + (size_t)red_stride_ * cap_;
     int Lb = 0;
     while (lev_[Lb]->N > kBottomN) ++Lb;
-    const int tf = nc < kSmallTileCols ? kTFSmall : kTFBig;
+    (void)nc;
+    const int tf = shape_.small ? kTFSmall : kTFBig;
     r.nrz = Lb == 0 ? 1 : ceil_div(lev_[0]->N + 1, tf) * ceil_div(lev_[0]->N + 1, tf);
-    // Batched calls give each workgroup of the PCG vector kernels several blocks
-    // of nodes: every workgroup sums all partials of its column, so their number
-    // must stay small next to the work per workgroup.
-    const int nb = ceil_div(n_, kBlock);
-    r.per = nc < kSmallTileCols ? 1 : std::min(16, std::max(1, ceil_div(nb, 64)));
+    r.per = shape_.per;
     r.nvec = ceil_div(n_, kBlock * r.per);
     return r;
+}
+
+// Fixed rule: small tiles below kSmallTileCols columns (more workgroups when
+// few columns make the V-cycle latency bound); batched calls give each
+// workgroup of the PCG vector kernels several node blocks, since every
+// workgroup sums all partials of its column.
+Hierarchy::LaunchShape Hierarchy::default_shape(int nc) const {
+    const int nb = ceil_div(n_, kBlock);
+    LaunchShape sh;
+    sh.small = nc < kSmallTileCols;
+    sh.per = nc < kSmallTileCols ? 1 : std::min(16, std::max(1, ceil_div(nb, 64)));
+    return sh;
+}
+
+// Times the candidate shapes on the call's own right-hand sides (w.r is set):
+// the V-cycle with each tile size, then the PCG apply kernel (first-iteration
+// form, whose outputs the first real iteration rewrites) with 1, 4 and 16 node
+// blocks per workgroup.  Both are pure functions of their inputs here.
+template <typename T>
+void Hierarchy::tune_shape(int nc) {
+    const long long key = 2LL * nc + (sizeof(T) == 4);
+    for (const auto& kv : tuned_)
+        if (kv.first == key) {
+            shape_ = kv.second;
+            return;
+        }
+    shape_ = default_shape(nc);
+    // HINV_SHAPE=<s|l><per> forces a shape (tests of every launch path)
+    if (const char* f = std::getenv("HINV_SHAPE")) {
+        if ((f[0] == 's' || f[0] == 'l') && std::atoi(f + 1) >= 1) {
+            shape_.small = f[0] == 's';
+            shape_.per = std::min(64, std::atoi(f + 1));
+            return;
+        }
+    }
+    const char* env = std::getenv("HINV_AUTOTUNE");
+    if (env && env[0] == '0') return;
+    hipStream_t s = ctx_->stream;
+    launch_stream_ = s;
+    hipEvent_t e0, e1;
+    HINV_HIP(hipEventCreate(&e0));
+    HINV_HIP(hipEventCreate(&e1));
+    const bool timer_was = ctx_->timer.paused;
+    ctx_->timer.paused = true;
+    auto timed = [&](auto fn) {
+        fn();  // warm
+        HINV_HIP(hipEventRecord(e0, s));
+        fn();
+        HINV_HIP(hipEventRecord(e1, s));
+        HINV_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HINV_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return ms;
+    };
+    LaunchShape best = shape_;
+    float best_ms = 1e30f;
+    for (bool small : {true, false}) {
+        shape_.small = small;
+        const float ms = timed([&] { vcycle<T>(nc, 0); });
+        if (ms < best_ms) {
+            best_ms = ms;
+            best.small = small;
+        }
+    }
+    shape_.small = best.small;
+    PcgWork<T>& w = work<T>();
+    const int n = n_;
+    best_ms = 1e30f;
+    for (int per : {1, 4, 16}) {
+        shape_.per = per;
+        const PcgRed red = pcg_red(nc);
+        const float ms = timed([&] {
+            with_op<T>(0, [&](auto op) {
+                k_pcg_apply<T><<<dim3(red.nvec, nc), kBlock, 0, s>>>(op, w.z.get(), w.p.get(), w.p2.get(),
+                                                                     w.q.get(), n, act_.get(), st_.get(), red, 1);
+            });
+            HINV_LAUNCH_CHECK();
+        });
+        if (ms < best_ms) {
+            best_ms = ms;
+            best.per = per;
+        }
+    }
+    ctx_->timer.paused = timer_was;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    shape_ = best;
+    tuned_.push_back({key, best});
+    if (std::getenv("HINV_TRACE_SHAPES"))
+        std::fprintf(stderr, "[hinv] launch shape N=%d nc=%d %s: %s tiles, %d node blocks per workgroup\n", N_, nc,
+                     sizeof(T) == 8 ? "fp64" : "fp32", best.small ? "small" : "large", best.per);
 }
 
 template <typename T>
@@ -602,7 +690,7 @@ void Hierarchy::vcycle(int nc, int check) {
     const int dir = kind_ == kOpState;
     const ChebCoef cc = cheb_coef();
     PcgRed red = pcg_red(nc);
-    const bool small = nc < kSmallTileCols;
+    const bool small = shape_.small;
     auto bvec = [&](int l) { return l == 0 ? w.r.get() : w.lb[l]->get(); };
     auto xout = [&](int l) { return l == 0 ? w.z.get() : w.lx[l]->get(); };
     for (int l = 0; l < Lb; ++l) {
@@ -796,6 +884,7 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
     hipStream_t s = ctx_->stream;
     launch_stream_ = s;
     int* act = act_.get();
+    tune_shape<T>(nc);
     vcycle<T>(nc, 0);
     int it = 0;
     if (max_iter > 0) {
@@ -854,6 +943,7 @@ void Hierarchy::precondition(int nc, const double* r, int ldr, double* z, int ld
     k_fill_int<<<ceil_div(nc, 64), 64, 0, s>>>(nc, 1, act_.get());
     HINV_LAUNCH_CHECK();
     launch_stream_ = s;
+    tune_shape<double>(nc);
     vcycle<double>(nc, 0);
     with_op<double>(0, [&](auto op) {
         k_masked_copy<<<g, kBlock, 0, s>>>(op, w64_.z.get(), n_, z, ldz);

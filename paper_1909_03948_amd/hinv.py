@@ -52,7 +52,7 @@ class SolveInfo(C.Structure):
 class NewtonOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("abs_tol", C.c_double), ("max_iter", C.c_int),
                 ("max_backtrack", C.c_int), ("c_armijo", C.c_double), ("max_cg", C.c_int),
-                ("gauss_newton", C.c_int)]
+                ("gn_iters", C.c_int)]
 
 
 class NewtonInfo(C.Structure):
@@ -342,10 +342,10 @@ class Problem:
         self._check(self.lib.hinv_white_noise(self.h, seed, stream, first, ns, pe, lde), allow=())
 
     def map_newton(self, m_map, m0=None, rel_tol=1e-6, abs_tol=0.0, max_iter=50, max_backtrack=10,
-                   c_armijo=1e-4, max_cg=500, gauss_newton=False):
+                   c_armijo=1e-4, max_cg=500, gn_iters=5):
         opts = NewtonOpts(rel_tol=rel_tol, abs_tol=abs_tol, max_iter=max_iter,
                           max_backtrack=max_backtrack, c_armijo=c_armijo, max_cg=max_cg,
-                          gauss_newton=int(gauss_newton))
+                          gn_iters=int(gn_iters))
         info = NewtonInfo()
         rc = self.lib.hinv_map_newton(self.h, None if m0 is None else _ptr(m0), _ptr(m_map),
                                       C.byref(opts), C.byref(info))

@@ -160,3 +160,27 @@ def test_argument_errors(ctx):
     with pytest.raises(hv.HinvError) as e:
         gp.hessian_apply(hv.HESS_FULL, dev(np.zeros(prob.n)), dev(np.zeros(prob.n)))
     assert e.value.code == hv.HINV_ESTATE
+
+
+@pytest.mark.parametrize("autotune,shape", [("0", None), ("1", None), ("1", "s4"), ("1", "l16"), ("1", "l1")])
+def test_launch_shape_paths(ctx, autotune, shape, monkeypatch):
+    """Tuned, fixed and forced launch shapes (tile size, node blocks per
+    workgroup) give the same Hessian actions to the parity bar (the choice
+    itself is a performance matter and not pinned)."""
+    monkeypatch.setenv("HINV_AUTOTUNE", autotune)
+    if shape:
+        monkeypatch.setenv("HINV_SHAPE", shape)
+    N, q = 256, 400
+    prob, _, obs = instance(N, q)
+    gp = gpu_problem(ctx, prob, obs, hv.PREC_AUTO)
+    m = point(prob, N)
+    u = prob.forward(m)
+    p = prob.adjoint(m, u)
+    gp.linearize(dev(m), dev(u), dev(p))
+    for nc in (1, 9):
+        mh = synth.test_vectors(prob.n, nc, stream=24)
+        out = dev(np.zeros((nc, prob.n)))
+        info = gp.hessian_apply(model.HESS_GN_MISFIT, dev(mh), out)
+        assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
+        ref = np.array([prob.hessian_apply(m, u, p, v, model.HESS_GN_MISFIT) for v in mh[:2]])
+        assert col_rel(host(out)[:2], ref) < 1e-8
