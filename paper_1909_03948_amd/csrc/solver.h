@@ -120,6 +120,7 @@ class Hierarchy {
     int cpi_ = 1;  // columns per instance of the current call
     LaunchShape shape_{true, 1};  // launch shape of the current call
     std::vector<std::pair<long long, LaunchShape>> tuned_;  // (nc * 2 + fp32, shape)
+    std::vector<std::pair<long long, int>> last_iters_;    // (nc * 2 + fp32, PCG iterations)
     std::vector<PriorParams> inst_pp_;
     std::vector<char> inst_ready_;
     DBuf<KARow<double>> karow64_;  // stacked prior rows: [level][instance][9]

@@ -892,13 +892,23 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
         it = 1;
     }
     const bool graphs = !std::getenv("HINV_NO_GRAPHS");
+    // the previous call with this shape took `expect` iterations: replay up to
+    // one short of that before the first completion check (kernels of finished
+    // columns return at once, so a late check costs launches, not work)
+    const long long key = 2LL * nc + (sizeof(T) == 4);
+    int expect = 0;
+    for (const auto& kv : last_iters_)
+        if (kv.first == key) expect = kv.second;
     while (it < max_iter) {
-        if (graphs && it + 2 <= max_iter) {
-            HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
-            it += 2;
-            // two iterations: two launches of each finest-level class
+        int reps = 1;
+        if (expect - 1 > it + 2) reps = (expect - 1 - it) / 2;
+        while (reps > 0 && it + 2 * reps > max_iter) --reps;
+        if (graphs && reps > 0) {
+            for (int rep = 0; rep < reps; ++rep) HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
+            it += 2 * reps;
+            // two iterations per replay: two launches of each finest-level class
             for (int k : {(int)kKDown, (int)kKUp, (int)kKBottom, (int)kKPcgApply, (int)kKPcgUpdate})
-                ctx_->timer.count_only(k, 2);
+                ctx_->timer.count_only(k, 2 * reps);
         } else {
             // odd tail: one eager iteration keeps the ping-pong parity at P[1]
             pcg_iteration<T>(nc, 1, 0);
@@ -913,6 +923,13 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
         if (!live) break;
     }
     *iters += it;
+    bool found = false;
+    for (auto& kv : last_iters_)
+        if (kv.first == key) {
+            kv.second = it;
+            found = true;
+        }
+    if (!found) last_iters_.push_back({key, it});
 }
 
 void Hierarchy::apply(int nc, const double* x, int ldx, double* y, int ldy) {
@@ -988,8 +1005,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     bool converged = false;
     while (true) {
         HINV_HIP(hipMemcpyAsync(host_flags_, oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToHost, s));
-        if (use32)
-            HINV_HIP(hipMemcpyAsync(hst.data(), st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
+        HINV_HIP(hipMemcpyAsync(hst.data(), st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
         HINV_HIP(hipStreamSynchronize(s));
         int live = 0;
         for (int c = 0; c < nc; ++c) live += host_flags_[c];
@@ -1047,13 +1063,11 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     }
     k_copy_cols<<<g, kBlock, 0, s>>>(x64_.get(), ld, x, ldx, n);
     HINV_LAUNCH_CHECK();
-    // final relative residuals
-    std::vector<ColState> hs(nc);
-    HINV_HIP(hipMemcpyAsync(hs.data(), st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
-    HINV_HIP(hipStreamSynchronize(s));
+    // final relative residuals: the column states read with the last flags
+    // (no refinement step ran after that read)
     double worst = 0.0;
     for (int c = 0; c < nc; ++c) {
-        const double rel = hs[c].obb > 0 ? std::sqrt(hs[c].rr / hs[c].obb) : 0.0;
+        const double rel = hst[c].obb > 0 ? std::sqrt(hst[c].rr / hst[c].obb) : 0.0;
         worst = rel > worst ? rel : worst;
     }
     if (stats) {
