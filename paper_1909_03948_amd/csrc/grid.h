@@ -89,6 +89,79 @@ struct OpA {
     }
 };
 
+// The state operator of one LDS tile: weights and 1/diagonal staged for the
+// tile's nodes (local index (j - oy) TW + (i - ox)); same rows as OpA.  Used
+// only on nodes whose west and south neighbours lie in the tile.
+template <typename T>
+struct OpATile {
+    int N, ox, oy, TW;
+    const T* wE;
+    const T* wN;
+    const T* dinv;
+    __device__ int li(int i, int j) const { return (j - oy) * TW + (i - ox); }
+    __device__ bool is_free(int, int j) const { return j > 0 && j < N; }
+    __device__ T inv_diag(int i, int j, int) const { return dinv[li(i, j)]; }
+    __device__ T diag(int i, int j, int) const {
+        const int l = li(i, j);
+        return (i < N ? wE[l] : (T)0) + (i > 0 ? wE[l - 1] : (T)0) + wN[l] + wN[l - TW];
+    }
+    template <class F>
+    __device__ T apply(int i, int j, int k, F xat) const {
+        const int l = li(i, j), N1 = N + 1;
+        T s = 0, d = 0;
+        if (i < N) {
+            const T w = wE[l];
+            d += w;
+            s += w * xat(i + 1, j, k + 1);
+        }
+        if (i > 0) {
+            const T w = wE[l - 1];
+            d += w;
+            s += w * xat(i - 1, j, k - 1);
+        }
+        {
+            const T w = wN[l];
+            d += w;
+            if (j + 1 < N) s += w * xat(i, j + 1, k + N1);
+        }
+        {
+            const T w = wN[l - TW];
+            d += w;
+            if (j - 1 > 0) s += w * xat(i, j - 1, k - N1);
+        }
+        return d * xat(i, j, k) - s;
+    }
+};
+
+// Tile view of an operator: the state operator reads the staged LDS arrays;
+// the prior operator (constant rows) is used as it is.
+template <typename T>
+__device__ inline OpATile<T> tile_op(const OpA<T>& op, const T* cwE, const T* cwN, const T* cdinv, int ox,
+                                     int oy, int TW) {
+    return OpATile<T>{op.N, ox, oy, TW, cwE, cwN, cdinv};
+}
+template <class Op>
+__device__ inline const Op& tile_op(const Op& op, const void*, const void*, const void*, int, int, int) {
+    return op;
+}
+
+// Stages the state operator's coefficients of the TW x TW tile at (ox, oy)
+// (zero outside the mesh); nothing for the prior operator.
+template <typename T>
+__device__ inline void stage_coefficients(const OpA<T>& op, T* cwE, T* cwN, T* cdinv, int ox, int oy, int TW) {
+    const int N = op.N, N1 = N + 1;
+    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
+        const int i = ox + t % TW, j = oy + t / TW;
+        const bool in = i >= 0 && i <= N && j >= 0 && j <= N;
+        const int k = j * N1 + i;
+        cwE[t] = in ? op.wE[k] : (T)0;
+        cwN[t] = in ? op.wN[k] : (T)0;
+        cdinv[t] = in ? op.dinv[k] : (T)0;
+    }
+}
+template <class Op, typename T>
+__device__ inline void stage_coefficients(const Op&, T*, T*, T*, int, int, int) {}
+
 // ------------------------------------------------------- prior operator ---
 // K_A = g K + dl M + bt M_boundary with Theta = I (every node is a dof).
 // K: unit five-point stiffness (edge weight = number of adjacent triangles / 2).

@@ -85,6 +85,13 @@ __device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int
     return done;
 }
 
+// The state operator's coefficients are staged in LDS per tile; the prior
+// operator has none.
+template <class Op>
+constexpr bool kStagesCoef = false;
+template <typename T>
+constexpr bool kStagesCoef<OpA<T>> = true;
+
 // --------------------------------------------------------------- k_down ---
 // Grid: (tiles over coarse x, tiles over coarse y, columns).  Coarse tile
 // [I0, I0+kTC) x [J0, J0+kTC) needs the fine residual on [2 I0 - 1, 2 I1 + 1],
@@ -93,29 +100,43 @@ template <typename T, class Op, int kTC>
 __global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T* __restrict__ x,
                                               int ld, T* __restrict__ bc, int ldc, int dirichlet,
                                               int* __restrict__ act, ChebCoef cc, PcgRed red,
-                                              ColState* __restrict__ st, int check) {
-    const int col = blockIdx.z;
-    const auto& op = op_.at(col);  // operator of the instance owning this column
-    if (act && !act[col]) return;
-    if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) return;
+                                              ColState* __restrict__ st, int check, int nc, int cb) {
     constexpr int TW = 2 * kTC + 5;
+    constexpr int TC = kStagesCoef<Op> ? TW * TW : 1;
     __shared__ T sb[TW * TW];
     __shared__ T sx[TW * TW];
     __shared__ T sr[TW * TW];
-    const int N = op.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
+    __shared__ T cwE[TC], cwN[TC], cdinv[TC];
+    const int N = op_.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
     const int I0 = blockIdx.x * kTC, J0 = blockIdx.y * kTC;
     const int I1 = min(I0 + kTC - 1, Nc), J1 = min(J0 + kTC - 1, Nc);
     const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // global coordinates of local (0, 0)
-    const T* bcol = b + (size_t)col * ld;
-    T* xcol = x + (size_t)col * ld;
     const T inv_theta = (T)cc.inv_theta, cA = (T)cc.cA, cB = (T)cc.cB;
     auto in_dom = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
     auto loc = [&](int i, int j) { return (j - oy) * TW + (i - ox); };
+    const void* staged = nullptr;  // coefficients in LDS belong to this instance
+    // the workgroup sweeps cb consecutive columns: the coefficient tile is
+    // staged once per instance
+    const int c_end = min(nc, (int)(blockIdx.z + 1) * cb);
+    for (int col = blockIdx.z * cb; col < c_end; ++col) {
+    if (act && !act[col]) continue;
+    if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) continue;
+    const auto& op_g = op_.at(col);  // operator of the instance owning this column
+    const T* bcol = b + (size_t)col * ld;
+    T* xcol = x + (size_t)col * ld;
+    __syncthreads();  // the previous column's LDS reads are done
     for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
         const int i = ox + t % TW, j = oy + t / TW;
         sb[t] = in_dom(i, j) ? bcol[j * N1 + i] : (T)0;
     }
+    if constexpr (kStagesCoef<Op>) {
+        if (op_g.wE != staged) {
+            stage_coefficients(op_g, cwE, cwN, cdinv, ox, oy, TW);
+            staged = op_g.wE;
+        }
+    }
     __syncthreads();
+    const auto& op = tile_op(op_g, cwE, cwN, cdinv, ox, oy, TW);
     // x2 on local [1, TW-1)^2; written to global on the owned fine nodes
     const int own_i1 = min(2 * I1 + 1, N), own_j1 = min(2 * J1 + 1, N);
     for (int t = threadIdx.x; t < (TW - 2) * (TW - 2); t += blockDim.x) {
@@ -160,6 +181,7 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T
         }
         bccol[J * Nc1 + I] = v;
     }
+    }  // columns
 }
 
 // ----------------------------------------------------------------- k_up ---
@@ -173,24 +195,29 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
                                             T* __restrict__ x, int ld, const T* __restrict__ xc,
                                             int ldc, int dirichlet,
                                             const int* __restrict__ act, ChebCoef cc,
-                                            const T* __restrict__ rv, PcgRed red) {
-    const int col = blockIdx.z;
-    const auto& op = op_.at(col);  // operator of the instance owning this column
-    if (act && !act[col]) return;
+                                            const T* __restrict__ rv, PcgRed red, int nc, int cb) {
     constexpr int TW = kTF + 4;
+    constexpr int TC = kStagesCoef<Op> ? TW * TW : 1;
     __shared__ T sx[TW * TW];
     __shared__ T sd[TW * TW];
-    const int N = op.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
+    __shared__ T cwE[TC], cwN[TC], cdinv[TC];
+    const int N = op_.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
     const int i0 = blockIdx.x * kTF, j0 = blockIdx.y * kTF;
     const int i1 = min(i0 + kTF - 1, N), j1 = min(j0 + kTF - 1, N);
     const int ox = i0 - 2, oy = j0 - 2;
+    const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
+    auto in_dom = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
+    auto loc = [&](int i, int j) { return (j - oy) * TW + (i - ox); };
+    const void* staged = nullptr;  // coefficients in LDS belong to this instance
+    const int c_end = min(nc, (int)(blockIdx.z + 1) * cb);
+    for (int col = blockIdx.z * cb; col < c_end; ++col) {
+    if (act && !act[col]) continue;
+    const auto& op_g = op_.at(col);  // operator of the instance owning this column
     const T* bcol = b + (size_t)col * ld;
     const T* x2col = x2 + (size_t)col * ld;
     T* xcol = x + (size_t)col * ld;
     const T* ccol = xc + (size_t)col * ldc;
-    const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
-    auto in_dom = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
-    auto loc = [&](int i, int j) { return (j - oy) * TW + (i - ox); };
+    __syncthreads();  // the previous column's LDS reads are done
     for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
         const int i = ox + t % TW, j = oy + t / TW;
         T v = 0;
@@ -209,7 +236,14 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
         }
         sx[t] = v;
     }
+    if constexpr (kStagesCoef<Op>) {
+        if (op_g.wE != staged) {
+            stage_coefficients(op_g, cwE, cwN, cdinv, ox, oy, TW);
+            staged = op_g.wE;
+        }
+    }
     __syncthreads();
+    const auto& op = tile_op(op_g, cwE, cwN, cdinv, ox, oy, TW);
     for (int t = threadIdx.x; t < (TW - 2) * (TW - 2); t += blockDim.x) {
         const int i = ox + 1 + t % (TW - 2), j = oy + 1 + t / (TW - 2);
         T d = 0;
@@ -240,6 +274,7 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
         const double s = group_sum(dot);
         if (threadIdx.x == 0) red.rz[(size_t)col * red.stride + blockIdx.y * gridDim.x + blockIdx.x] = s;
     }
+    }  // columns
 }
 
 // -------------------------------------------------------------- bottom ---

@@ -96,12 +96,14 @@ class Hierarchy {
     void ensure_cols(int nc);
     void set_columns(int nc);
     // Launch shape of the batched kernels: V-cycle tiles (small: 8 / 16 nodes
-    // per coarse / fine side, else 16 / 32) and node blocks per workgroup of
-    // the PCG vector kernels.  Chosen by timing on the first call of each
+    // per coarse / fine side, else 16 / 32), columns per V-cycle workgroup
+    // (the coefficient tile is staged once for them) and node blocks per
+    // workgroup of the PCG vector kernels.  Chosen by timing on the first call of each
     // (column count, precision); HINV_AUTOTUNE=0 uses the fixed rule instead.
     struct LaunchShape {
         bool small;
         int per;
+        int cb;  // columns per workgroup of the V-cycle kernels
     };
     LaunchShape default_shape(int nc) const;
     template <typename T>
@@ -118,7 +120,7 @@ class Hierarchy {
     bool ready_ = false;
     int ninst_ = 1;
     int cpi_ = 1;  // columns per instance of the current call
-    LaunchShape shape_{true, 1};  // launch shape of the current call
+    LaunchShape shape_{true, 1, 1};  // launch shape of the current call
     std::vector<std::pair<long long, LaunchShape>> tuned_;  // (nc * 2 + fp32, shape)
     std::vector<std::pair<long long, int>> last_iters_;    // (nc * 2 + fp32, PCG iterations)
     std::vector<PriorParams> inst_pp_;

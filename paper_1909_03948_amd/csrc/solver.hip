@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 #include "mgkernels.h"
 
@@ -597,6 +598,7 @@ Hierarchy::LaunchShape Hierarchy::default_shape(int nc) const {
     LaunchShape sh;
     sh.small = nc < kSmallTileCols;
     sh.per = nc < kSmallTileCols ? 1 : std::min(16, std::max(1, ceil_div(nb, 64)));
+    sh.cb = 1;
     return sh;
 }
 
@@ -613,11 +615,14 @@ void Hierarchy::tune_shape(int nc) {
             return;
         }
     shape_ = default_shape(nc);
-    // HINV_SHAPE=<s|l><per> forces a shape (tests of every launch path)
+    // HINV_SHAPE forces a shape (tests of every launch path)
     if (const char* f = std::getenv("HINV_SHAPE")) {
+        // HINV_SHAPE=<s|l><per>[c<cb>]
         if ((f[0] == 's' || f[0] == 'l') && std::atoi(f + 1) >= 1) {
             shape_.small = f[0] == 's';
             shape_.per = std::min(64, std::atoi(f + 1));
+            const char* c = std::strchr(f, 'c');
+            shape_.cb = c ? std::max(1, std::min(64, std::atoi(c + 1))) : 1;
             return;
         }
     }
@@ -642,15 +647,20 @@ void Hierarchy::tune_shape(int nc) {
     };
     LaunchShape best = shape_;
     float best_ms = 1e30f;
-    for (bool small : {true, false}) {
-        shape_.small = small;
-        const float ms = timed([&] { vcycle<T>(nc, 0); });
-        if (ms < best_ms) {
-            best_ms = ms;
-            best.small = small;
+    for (bool small : {true, false})
+        for (int cb : {1, 2, 4, 8}) {
+            if (cb > 1 && nc < kSmallTileCols) continue;
+            shape_.small = small;
+            shape_.cb = cb;
+            const float ms = timed([&] { vcycle<T>(nc, 0); });
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.small = small;
+                best.cb = cb;
+            }
         }
-    }
     shape_.small = best.small;
+    shape_.cb = best.cb;
     PcgWork<T>& w = work<T>();
     const int n = n_;
     best_ms = 1e30f;
@@ -675,8 +685,9 @@ void Hierarchy::tune_shape(int nc) {
     shape_ = best;
     tuned_.push_back({key, best});
     if (std::getenv("HINV_TRACE_SHAPES"))
-        std::fprintf(stderr, "[hinv] launch shape N=%d nc=%d %s: %s tiles, %d node blocks per workgroup\n", N_, nc,
-                     sizeof(T) == 8 ? "fp64" : "fp32", best.small ? "small" : "large", best.per);
+        std::fprintf(stderr, "[hinv] launch shape N=%d nc=%d %s: %s tiles, %d columns per V-cycle workgroup, "
+                     "%d node blocks per workgroup\n", N_, nc, sizeof(T) == 8 ? "fp64" : "fp32",
+                     best.small ? "small" : "large", best.cb, best.per);
 }
 
 template <typename T>
@@ -704,14 +715,15 @@ void Hierarchy::vcycle(int nc, int check) {
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
             const int chk = l == 0 ? check : 0;
+            const int cb = shape_.cb, gz = ceil_div(nc, cb);
             if (small) {
                 const int tc = ceil_div(C.N + 1, kTCSmall);
-                k_down<T, Op, kTCSmall><<<dim3(tc, tc, nc), 256, 0, s>>>(
-                    op, bvec(l), w.lt[l]->get(), L.n, bvec(l + 1), C.n, dir, act, cc, red, st_.get(), chk);
+                k_down<T, Op, kTCSmall><<<dim3(tc, tc, gz), 256, 0, s>>>(
+                    op, bvec(l), w.lt[l]->get(), L.n, bvec(l + 1), C.n, dir, act, cc, red, st_.get(), chk, nc, cb);
             } else {
                 const int tc = ceil_div(C.N + 1, kTCBig);
-                k_down<T, Op, kTCBig><<<dim3(tc, tc, nc), 256, 0, s>>>(
-                    op, bvec(l), w.lt[l]->get(), L.n, bvec(l + 1), C.n, dir, act, cc, red, st_.get(), chk);
+                k_down<T, Op, kTCBig><<<dim3(tc, tc, gz), 256, 0, s>>>(
+                    op, bvec(l), w.lt[l]->get(), L.n, bvec(l + 1), C.n, dir, act, cc, red, st_.get(), chk, nc, cb);
             }
         });
         HINV_LAUNCH_CHECK();
@@ -785,14 +797,15 @@ void Hierarchy::vcycle(int nc, int check) {
         TimedLaunch tl(ctx_, l == 0 ? (int)kKUp : -1, bytes_up);
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
+            const int cb = shape_.cb, gz = ceil_div(nc, cb);
             if (small) {
                 const int tf = ceil_div(L.N + 1, kTFSmall);
-                k_up<T, Op, kTFSmall><<<dim3(tf, tf, nc), 256, 0, s>>>(
-                    op, bvec(l), w.lt[l]->get(), xout(l), L.n, xout(l + 1), C.n, dir, act, cc, rv, red);
+                k_up<T, Op, kTFSmall><<<dim3(tf, tf, gz), 256, 0, s>>>(
+                    op, bvec(l), w.lt[l]->get(), xout(l), L.n, xout(l + 1), C.n, dir, act, cc, rv, red, nc, cb);
             } else {
                 const int tf = ceil_div(L.N + 1, kTFBig);
-                k_up<T, Op, kTFBig><<<dim3(tf, tf, nc), 256, 0, s>>>(
-                    op, bvec(l), w.lt[l]->get(), xout(l), L.n, xout(l + 1), C.n, dir, act, cc, rv, red);
+                k_up<T, Op, kTFBig><<<dim3(tf, tf, gz), 256, 0, s>>>(
+                    op, bvec(l), w.lt[l]->get(), xout(l), L.n, xout(l + 1), C.n, dir, act, cc, rv, red, nc, cb);
             }
         });
         HINV_LAUNCH_CHECK();

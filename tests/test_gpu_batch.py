@@ -60,8 +60,12 @@ def test_batch_requires_linearization(batch_setup):
     assert e.value.code == hv.HINV_ESTATE
 
 
-@pytest.mark.parametrize("nrhs", [1, 3])
-def test_batch_hessian_all_modes(batch_setup, nrhs):
+@pytest.mark.parametrize("nrhs,shape", [(1, None), (3, None), (3, "l4c4"), (3, "s1c2")])
+def test_batch_hessian_all_modes(batch_setup, nrhs, shape, monkeypatch):
+    """Column blocks of 4 / 2 with 3 columns per problem straddle problems of a
+    stacked hierarchy (their coefficient tiles are staged again)."""
+    if shape:
+        monkeypatch.setenv("HINV_SHAPE", shape)
     ctx, insts, gps = batch_setup
     for (prob, m, u, p), gp in zip(insts, gps):
         gp.linearize(dev(m), dev(u), dev(p))

@@ -162,7 +162,8 @@ def test_argument_errors(ctx):
     assert e.value.code == hv.HINV_ESTATE
 
 
-@pytest.mark.parametrize("autotune,shape", [("0", None), ("1", None), ("1", "s4"), ("1", "l16"), ("1", "l1")])
+@pytest.mark.parametrize("autotune,shape", [("0", None), ("1", None), ("1", "s4"), ("1", "l16"), ("1", "l1"),
+                                            ("1", "l4c4"), ("1", "s1c3"), ("1", "l16c8")])
 def test_launch_shape_paths(ctx, autotune, shape, monkeypatch):
     """Tuned, fixed and forced launch shapes (tile size, node blocks per
     workgroup) give the same Hessian actions to the parity bar (the choice
