@@ -89,79 +89,6 @@ struct OpA {
     }
 };
 
-// The state operator of one LDS tile: weights and 1/diagonal staged for the
-// tile's nodes (local index (j - oy) TW + (i - ox)); same rows as OpA.  Used
-// only on nodes whose west and south neighbours lie in the tile.
-template <typename T>
-struct OpATile {
-    int N, ox, oy, TW;
-    const T* wE;
-    const T* wN;
-    const T* dinv;
-    __device__ int li(int i, int j) const { return (j - oy) * TW + (i - ox); }
-    __device__ bool is_free(int, int j) const { return j > 0 && j < N; }
-    __device__ T inv_diag(int i, int j, int) const { return dinv[li(i, j)]; }
-    __device__ T diag(int i, int j, int) const {
-        const int l = li(i, j);
-        return (i < N ? wE[l] : (T)0) + (i > 0 ? wE[l - 1] : (T)0) + wN[l] + wN[l - TW];
-    }
-    template <class F>
-    __device__ T apply(int i, int j, int k, F xat) const {
-        const int l = li(i, j), N1 = N + 1;
-        T s = 0, d = 0;
-        if (i < N) {
-            const T w = wE[l];
-            d += w;
-            s += w * xat(i + 1, j, k + 1);
-        }
-        if (i > 0) {
-            const T w = wE[l - 1];
-            d += w;
-            s += w * xat(i - 1, j, k - 1);
-        }
-        {
-            const T w = wN[l];
-            d += w;
-            if (j + 1 < N) s += w * xat(i, j + 1, k + N1);
-        }
-        {
-            const T w = wN[l - TW];
-            d += w;
-            if (j - 1 > 0) s += w * xat(i, j - 1, k - N1);
-        }
-        return d * xat(i, j, k) - s;
-    }
-};
-
-// Tile view of an operator: the state operator reads the staged LDS arrays;
-// the prior operator (constant rows) is used as it is.
-template <typename T>
-__device__ inline OpATile<T> tile_op(const OpA<T>& op, const T* cwE, const T* cwN, const T* cdinv, int ox,
-                                     int oy, int TW) {
-    return OpATile<T>{op.N, ox, oy, TW, cwE, cwN, cdinv};
-}
-template <class Op>
-__device__ inline const Op& tile_op(const Op& op, const void*, const void*, const void*, int, int, int) {
-    return op;
-}
-
-// Stages the state operator's coefficients of the TW x TW tile at (ox, oy)
-// (zero outside the mesh); nothing for the prior operator.
-template <typename T>
-__device__ inline void stage_coefficients(const OpA<T>& op, T* cwE, T* cwN, T* cdinv, int ox, int oy, int TW) {
-    const int N = op.N, N1 = N + 1;
-    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
-        const int i = ox + t % TW, j = oy + t / TW;
-        const bool in = i >= 0 && i <= N && j >= 0 && j <= N;
-        const int k = j * N1 + i;
-        cwE[t] = in ? op.wE[k] : (T)0;
-        cwN[t] = in ? op.wN[k] : (T)0;
-        cdinv[t] = in ? op.dinv[k] : (T)0;
-    }
-}
-template <class Op, typename T>
-__device__ inline void stage_coefficients(const Op&, T*, T*, T*, int, int, int) {}
-
 // ------------------------------------------------------- prior operator ---
 // K_A = g K + dl M + bt M_boundary with Theta = I (every node is a dof).
 // K: unit five-point stiffness (edge weight = number of adjacent triangles / 2).
@@ -269,6 +196,91 @@ inline OpKA<T> make_prior_op(int N, double g, double dl, double bt) {
             r.dinv = (T)(1.0 / c);
         }
     return o;
+}
+
+// ---------------------------------------------------------- tile stencil ---
+// Both operators are symmetric with couplings to the east, north and (prior
+// only) north-east neighbours, so an LDS tile of either is five arrays per
+// node: diagonal c, east e, north n, north-east g and 1/diagonal dv, with
+//   (A x)_l = c_l x_l + e_l x_{l+1} + e_{l-1} x_{l-1} + n_l x_{l+TW} + n_{l-TW} x_{l-TW}
+//             + g_l x_{l+TW+1} + g_{l-TW-1} x_{l-TW-1}
+// (l = local index, TW = tile width).  Absent neighbours carry zero
+// couplings, nodes outside the mesh are zero everywhere, and dv is zero on
+// Dirichlet rows, so the tile stencil needs no boundary branches: the vectors
+// it is applied to are zero on Dirichlet rows.
+template <class Op>
+constexpr bool kNorthEast = true;  // the prior operator couples (i+1, j+1)
+template <typename T>
+constexpr bool kNorthEast<OpA<T>> = false;
+
+template <typename T>
+struct TileStencil {
+    T* c;
+    T* e;
+    T* n;
+    T* g;   // unused (size 1) for the state operator
+    T* dv;
+};
+
+// Stages the rows of the TW x TW tile whose local (0, 0) is node (ox, oy).
+template <typename T>
+__device__ inline void stage_stencil(const OpA<T>& op, const TileStencil<T>& s, int ox, int oy, int TW) {
+    const int N = op.N, N1 = N + 1;
+    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
+        const int i = ox + t % TW, j = oy + t / TW;
+        T c = 0, e = 0, n = 0, dv = 0;
+        if (i >= 0 && i <= N && j >= 0 && j <= N) {
+            const int k = j * N1 + i;
+            const T wE = op.wE[k], wN = op.wN[k];
+            c = wE + wN + (i > 0 ? op.wE[k - 1] : (T)0) + (j > 0 ? op.wN[k - N1] : (T)0);
+            e = -wE;
+            n = -wN;
+            dv = op.dinv[k];
+        }
+        s.c[t] = c;
+        s.e[t] = e;
+        s.n[t] = n;
+        s.dv[t] = dv;
+    }
+}
+
+template <typename T, class OpK>
+__device__ inline void stage_stencil(const OpK& op, const TileStencil<T>& s, int ox, int oy, int TW) {
+    const int N = op.N;
+    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
+        const int i = ox + t % TW, j = oy + t / TW;
+        T c = 0, e = 0, n = 0, g = 0, dv = 0;
+        if (i >= 0 && i <= N && j >= 0 && j <= N) {
+            const KARow<T>& r = op.rows[ka_class(i, j, N)];
+            c = r.c;
+            e = r.e;
+            n = r.n;
+            g = r.ne;
+            dv = r.dinv;
+        }
+        s.c[t] = c;
+        s.e[t] = e;
+        s.n[t] = n;
+        s.g[t] = g;
+        s.dv[t] = dv;
+    }
+}
+
+// Identifies the problem instance an operator belongs to (stacked
+// hierarchies): a staged tile is reused while the key stays the same.
+template <typename T>
+__device__ inline const void* instance_key(const OpA<T>& o) { return o.wE; }
+template <typename T>
+__device__ inline const void* instance_key(const OpKARef<T>& o) { return o.rows; }
+template <typename T>
+__device__ inline const void* instance_key(const OpKA<T>&) { return reinterpret_cast<const void*>(1); }
+
+// (A v)_l on a staged tile; l must have all eight neighbours inside the tile.
+template <bool NE, typename T>
+__device__ inline T tile_apply(const TileStencil<T>& s, int TW, int l, const T* v) {
+    T a = s.c[l] * v[l] + s.e[l] * v[l + 1] + s.e[l - 1] * v[l - 1] + s.n[l] * v[l + TW] + s.n[l - TW] * v[l - TW];
+    if constexpr (NE) a += s.g[l] * v[l + TW + 1] + s.g[l - TW - 1] * v[l - TW - 1];
+    return a;
 }
 
 // ------------------------------------------------------------ triangles ---

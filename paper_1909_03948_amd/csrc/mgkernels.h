@@ -85,110 +85,99 @@ __device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int
     return done;
 }
 
-// The state operator's coefficients are staged in LDS per tile; the prior
-// operator has none.
-template <class Op>
-constexpr bool kStagesCoef = false;
-template <typename T>
-constexpr bool kStagesCoef<OpA<T>> = true;
-
 // --------------------------------------------------------------- k_down ---
-// Grid: (tiles over coarse x, tiles over coarse y, columns).  Coarse tile
-// [I0, I0+kTC) x [J0, J0+kTC) needs the fine residual on [2 I0 - 1, 2 I1 + 1],
-// hence x2 one node further out and b two nodes further out.
+// Grid: (tiles over coarse x, tiles over coarse y, column blocks).  Coarse
+// tile [I0, I0+kTC) x [J0, J0+kTC) needs the fine residual on
+// [2 I0 - 1, 2 I1 + 1], hence x2 one node further out and b two nodes further
+// out.  The operator rows of the tile are staged once per problem instance;
+// the workgroup then sweeps cb consecutive columns.
 template <typename T, class Op, int kTC>
 __global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T* __restrict__ x,
                                               int ld, T* __restrict__ bc, int ldc, int dirichlet,
                                               int* __restrict__ act, ChebCoef cc, PcgRed red,
                                               ColState* __restrict__ st, int check, int nc, int cb) {
-    constexpr int TW = 2 * kTC + 5;
-    constexpr int TC = kStagesCoef<Op> ? TW * TW : 1;
-    __shared__ T sb[TW * TW];
-    __shared__ T sx[TW * TW];
-    __shared__ T sr[TW * TW];
-    __shared__ T cwE[TC], cwN[TC], cdinv[TC];
+    constexpr int TW = 2 * kTC + 5, NN = TW * TW;
+    constexpr bool NE = kNorthEast<Op>;
+    __shared__ T sb[NN], sx[NN], sr[NN];
+    __shared__ T tc[NN], te[NN], tn[NN], tdv[NN], tg[NE ? NN : 1];
+    const TileStencil<T> ts{tc, te, tn, tg, tdv};
     const int N = op_.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
     const int I0 = blockIdx.x * kTC, J0 = blockIdx.y * kTC;
     const int I1 = min(I0 + kTC - 1, Nc), J1 = min(J0 + kTC - 1, Nc);
     const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // global coordinates of local (0, 0)
     const T inv_theta = (T)cc.inv_theta, cA = (T)cc.cA, cB = (T)cc.cB;
-    auto in_dom = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
-    auto loc = [&](int i, int j) { return (j - oy) * TW + (i - ox); };
-    const void* staged = nullptr;  // coefficients in LDS belong to this instance
-    // the workgroup sweeps cb consecutive columns: the coefficient tile is
-    // staged once per instance
+    const int own_i1 = min(2 * I1 + 1, N), own_j1 = min(2 * J1 + 1, N);
+    const void* staged = nullptr;  // the staged rows belong to this instance
     const int c_end = min(nc, (int)(blockIdx.z + 1) * cb);
     for (int col = blockIdx.z * cb; col < c_end; ++col) {
-    if (act && !act[col]) continue;
-    if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) continue;
-    const auto& op_g = op_.at(col);  // operator of the instance owning this column
-    const T* bcol = b + (size_t)col * ld;
-    T* xcol = x + (size_t)col * ld;
-    __syncthreads();  // the previous column's LDS reads are done
-    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
-        const int i = ox + t % TW, j = oy + t / TW;
-        sb[t] = in_dom(i, j) ? bcol[j * N1 + i] : (T)0;
-    }
-    if constexpr (kStagesCoef<Op>) {
-        if (op_g.wE != staged) {
-            stage_coefficients(op_g, cwE, cwN, cdinv, ox, oy, TW);
-            staged = op_g.wE;
+        if (act && !act[col]) continue;
+        if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) continue;
+        const auto& op = op_.at(col);  // operator of the instance owning this column
+        const T* bcol = b + (size_t)col * ld;
+        T* xcol = x + (size_t)col * ld;
+        __syncthreads();  // the previous column's LDS reads are done
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) {
+            const int i = ox + t % TW, j = oy + t / TW;
+            sb[t] = (i >= 0 && i <= N && j >= 0 && j <= N) ? bcol[j * N1 + i] : (T)0;
+        }
+        if (instance_key(op) != staged) {
+            stage_stencil(op, ts, ox, oy, TW);
+            staged = instance_key(op);
+        }
+        __syncthreads();
+        // d0 = D^-1 b / theta on the whole tile (zero off the free nodes)
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) sr[t] = tdv[t] * sb[t] * inv_theta;
+        __syncthreads();
+        // x2 = cA d0 + cB D^-1 (b - A d0) on local [1, TW-1)^2; owned nodes to global
+        {
+            constexpr int W = TW - 2;
+            for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+                const int il = 1 + t % W, jl = 1 + t / W, l = jl * TW + il;
+                const T v = cA * sr[l] + cB * tdv[l] * (sb[l] - tile_apply<NE>(ts, TW, l, sr));
+                sx[l] = v;
+                const int i = ox + il, j = oy + jl;
+                if (i >= 2 * I0 && i <= own_i1 && j >= 2 * J0 && j <= own_j1) xcol[j * N1 + i] = v;
+            }
+        }
+        __syncthreads();
+        // residual b - A x2 on the free nodes of local [2, TW-2)^2
+        {
+            constexpr int W = TW - 4;
+            for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+                const int l = (2 + t / W) * TW + 2 + t % W;
+                const T v = sb[l] - tile_apply<NE>(ts, TW, l, sx);
+                sr[l] = tdv[l] != (T)0 ? v : (T)0;
+            }
+        }
+        __syncthreads();
+        // restriction P^T onto the coarse tile
+        T* bccol = bc + (size_t)col * ldc;
+        const int cw = I1 - I0 + 1, ch = J1 - J0 + 1;
+        auto res = [&](int i, int j) { return sr[(j - oy) * TW + (i - ox)]; };
+        for (int t = threadIdx.x; t < cw * ch; t += blockDim.x) {
+            const int I = I0 + t % cw, J = J0 + t / cw;
+            T v = 0;
+            if (!(dirichlet && (J == 0 || J == Nc))) {
+                const int i = 2 * I, j = 2 * J;
+                T sm = 0;
+                if (i > 0) sm += res(i - 1, j);
+                if (i < N) sm += res(i + 1, j);
+                if (j > 0) sm += res(i, j - 1);
+                if (j < N) sm += res(i, j + 1);
+                if (i < N && j < N) sm += res(i + 1, j + 1);
+                if (i > 0 && j > 0) sm += res(i - 1, j - 1);
+                v = res(i, j) + (T)0.5 * sm;
+            }
+            bccol[J * Nc1 + I] = v;
         }
     }
-    __syncthreads();
-    const auto& op = tile_op(op_g, cwE, cwN, cdinv, ox, oy, TW);
-    // x2 on local [1, TW-1)^2; written to global on the owned fine nodes
-    const int own_i1 = min(2 * I1 + 1, N), own_j1 = min(2 * J1 + 1, N);
-    for (int t = threadIdx.x; t < (TW - 2) * (TW - 2); t += blockDim.x) {
-        const int i = ox + 1 + t % (TW - 2), j = oy + 1 + t / (TW - 2);
-        T v = 0;
-        if (in_dom(i, j) && op.is_free(i, j)) {
-            const int k = j * N1 + i;
-            auto d0 = [&](int ii, int jj, int kk) { return op.inv_diag(ii, jj, kk) * sb[loc(ii, jj)] * inv_theta; };
-            const T dk = d0(i, j, k);
-            const T r1 = sb[loc(i, j)] - op.apply(i, j, k, d0);
-            v = cA * dk + cB * op.inv_diag(i, j, k) * r1;
-        }
-        sx[loc(i, j)] = v;
-        if (i >= 2 * I0 && i <= own_i1 && j >= 2 * J0 && j <= own_j1) xcol[j * N1 + i] = v;
-    }
-    __syncthreads();
-    // residual on local [2, TW-2)^2
-    for (int t = threadIdx.x; t < (TW - 4) * (TW - 4); t += blockDim.x) {
-        const int i = ox + 2 + t % (TW - 4), j = oy + 2 + t / (TW - 4);
-        T v = 0;
-        if (in_dom(i, j) && op.is_free(i, j))
-            v = sb[loc(i, j)] - op.apply(i, j, j * N1 + i, [&](int ii, int jj, int) { return sx[loc(ii, jj)]; });
-        sr[loc(i, j)] = v;
-    }
-    __syncthreads();
-    // restriction P^T onto the coarse tile
-    T* bccol = bc + (size_t)col * ldc;
-    const int cw = I1 - I0 + 1, ch = J1 - J0 + 1;
-    for (int t = threadIdx.x; t < cw * ch; t += blockDim.x) {
-        const int I = I0 + t % cw, J = J0 + t / cw;
-        T v = 0;
-        if (!(dirichlet && (J == 0 || J == Nc))) {
-            const int i = 2 * I, j = 2 * J;
-            T s = 0;
-            if (i > 0) s += sr[loc(i - 1, j)];
-            if (i < N) s += sr[loc(i + 1, j)];
-            if (j > 0) s += sr[loc(i, j - 1)];
-            if (j < N) s += sr[loc(i, j + 1)];
-            if (i < N && j < N) s += sr[loc(i + 1, j + 1)];
-            if (i > 0 && j > 0) s += sr[loc(i - 1, j - 1)];
-            v = sr[loc(i, j)] + (T)0.5 * s;
-        }
-        bccol[J * Nc1 + I] = v;
-    }
-    }  // columns
 }
 
 // ----------------------------------------------------------------- k_up ---
-// Grid: (tiles over fine x, tiles over fine y, columns).  Fine tile O of
+// Grid: (tiles over fine x, tiles over fine y, column blocks).  Fine tile O of
 // kTF x kTF nodes; x = x2 + P x_coarse is formed two nodes around O (x2 is
-// read from its own buffer: neighbouring workgroups write the output), the first
-// Chebyshev correction d0 one node around O.  Optionally writes the
+// read from its own buffer: neighbouring workgroups write the output), b and
+// the first Chebyshev correction d0 one node around O.  Optionally writes the
 // workgroup's part of sum_k rv_k x_k (the PCG inner product r^T z).
 template <typename T, class Op, int kTF>
 __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, const T* __restrict__ x2,
@@ -196,85 +185,79 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
                                             int ldc, int dirichlet,
                                             const int* __restrict__ act, ChebCoef cc,
                                             const T* __restrict__ rv, PcgRed red, int nc, int cb) {
-    constexpr int TW = kTF + 4;
-    constexpr int TC = kStagesCoef<Op> ? TW * TW : 1;
-    __shared__ T sx[TW * TW];
-    __shared__ T sd[TW * TW];
-    __shared__ T cwE[TC], cwN[TC], cdinv[TC];
-    const int N = op_.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
+    constexpr int TW = kTF + 4, NN = TW * TW;
+    constexpr bool NE = kNorthEast<Op>;
+    __shared__ T sx[NN], sd[NN], sb[NN];
+    __shared__ T tc[NN], te[NN], tn[NN], tdv[NN], tg[NE ? NN : 1];
+    const TileStencil<T> ts{tc, te, tn, tg, tdv};
+    const int N = op_.N, N1 = N + 1, Nc1 = N / 2 + 1;
     const int i0 = blockIdx.x * kTF, j0 = blockIdx.y * kTF;
     const int i1 = min(i0 + kTF - 1, N), j1 = min(j0 + kTF - 1, N);
     const int ox = i0 - 2, oy = j0 - 2;
     const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
-    auto in_dom = [&](int i, int j) { return i >= 0 && i <= N && j >= 0 && j <= N; };
-    auto loc = [&](int i, int j) { return (j - oy) * TW + (i - ox); };
-    const void* staged = nullptr;  // coefficients in LDS belong to this instance
+    const void* staged = nullptr;
     const int c_end = min(nc, (int)(blockIdx.z + 1) * cb);
     for (int col = blockIdx.z * cb; col < c_end; ++col) {
-    if (act && !act[col]) continue;
-    const auto& op_g = op_.at(col);  // operator of the instance owning this column
-    const T* bcol = b + (size_t)col * ld;
-    const T* x2col = x2 + (size_t)col * ld;
-    T* xcol = x + (size_t)col * ld;
-    const T* ccol = xc + (size_t)col * ldc;
-    __syncthreads();  // the previous column's LDS reads are done
-    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
-        const int i = ox + t % TW, j = oy + t / TW;
-        T v = 0;
-        if (in_dom(i, j) && !(dirichlet && (j == 0 || j == N))) {
-            const int I = i >> 1, J = j >> 1;
-            T p;
-            if (!(i & 1) && !(j & 1))
-                p = ccol[J * Nc1 + I];
-            else if (!(j & 1))
-                p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[J * Nc1 + I + 1]);
-            else if (!(i & 1))
-                p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[(J + 1) * Nc1 + I]);
-            else
-                p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[(J + 1) * Nc1 + I + 1]);
-            v = x2col[j * N1 + i] + p;
+        if (act && !act[col]) continue;
+        const auto& op = op_.at(col);  // operator of the instance owning this column
+        const T* bcol = b + (size_t)col * ld;
+        const T* x2col = x2 + (size_t)col * ld;
+        T* xcol = x + (size_t)col * ld;
+        const T* ccol = xc + (size_t)col * ldc;
+        __syncthreads();  // the previous column's LDS reads are done
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) {
+            const int i = ox + t % TW, j = oy + t / TW;
+            T v = 0, bv = 0;
+            if (i >= 0 && i <= N && j >= 0 && j <= N) {
+                bv = bcol[j * N1 + i];
+                if (!(dirichlet && (j == 0 || j == N))) {
+                    const int I = i >> 1, J = j >> 1;
+                    T p;
+                    if (!(i & 1) && !(j & 1))
+                        p = ccol[J * Nc1 + I];
+                    else if (!(j & 1))
+                        p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[J * Nc1 + I + 1]);
+                    else if (!(i & 1))
+                        p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[(J + 1) * Nc1 + I]);
+                    else
+                        p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[(J + 1) * Nc1 + I + 1]);
+                    v = x2col[j * N1 + i] + p;
+                }
+            }
+            sx[t] = v;
+            sb[t] = bv;
         }
-        sx[t] = v;
-    }
-    if constexpr (kStagesCoef<Op>) {
-        if (op_g.wE != staged) {
-            stage_coefficients(op_g, cwE, cwN, cdinv, ox, oy, TW);
-            staged = op_g.wE;
+        if (instance_key(op) != staged) {
+            stage_stencil(op, ts, ox, oy, TW);
+            staged = instance_key(op);
+        }
+        __syncthreads();
+        // d0 = D^-1 (b - A x) / theta on local [1, TW-1)^2 (zero off the free nodes)
+        {
+            constexpr int W = TW - 2;
+            for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+                const int l = (1 + t / W) * TW + 1 + t % W;
+                sd[l] = tdv[l] * (sb[l] - tile_apply<NE>(ts, TW, l, sx)) * inv_theta;
+            }
+        }
+        __syncthreads();
+        // x += (1 + c1) d0 + cB D^-1 r1 on O with r1 = r0 - A d0 = theta D d0 - A d0
+        double dot = 0.0;
+        const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+        for (int t = threadIdx.x; t < w * h; t += blockDim.x) {
+            const int i = i0 + t % w, j = j0 + t / w;
+            const int l = (j - oy) * TW + (i - ox), k = j * N1 + i;
+            const T dk = sd[l];
+            const T r1 = theta * dk * tc[l] - tile_apply<NE>(ts, TW, l, sd);
+            const T v = sx[l] + ((T)1 + c1) * dk + cB * tdv[l] * r1;
+            xcol[k] = v;
+            if (rv) dot += (double)v * (double)rv[(size_t)col * ld + k];
+        }
+        if (rv) {
+            const double sm = group_sum(dot);
+            if (threadIdx.x == 0) red.rz[(size_t)col * red.stride + blockIdx.y * gridDim.x + blockIdx.x] = sm;
         }
     }
-    __syncthreads();
-    const auto& op = tile_op(op_g, cwE, cwN, cdinv, ox, oy, TW);
-    for (int t = threadIdx.x; t < (TW - 2) * (TW - 2); t += blockDim.x) {
-        const int i = ox + 1 + t % (TW - 2), j = oy + 1 + t / (TW - 2);
-        T d = 0;
-        if (in_dom(i, j) && op.is_free(i, j)) {
-            const int k = j * N1 + i;
-            const T r0 = bcol[k] - op.apply(i, j, k, [&](int ii, int jj, int) { return sx[loc(ii, jj)]; });
-            d = op.inv_diag(i, j, k) * r0 * inv_theta;
-        }
-        sd[loc(i, j)] = d;
-    }
-    __syncthreads();
-    double dot = 0.0;
-    const int w = i1 - i0 + 1, h = j1 - j0 + 1;
-    for (int t = threadIdx.x; t < w * h; t += blockDim.x) {
-        const int i = i0 + t % w, j = j0 + t / w;
-        const int k = j * N1 + i;
-        T v = sx[loc(i, j)];
-        if (op.is_free(i, j)) {
-            const T dk = sd[loc(i, j)];
-            const T di = op.inv_diag(i, j, k);
-            const T r1 = theta * dk * op.diag(i, j, k) - op.apply(i, j, k, [&](int ii, int jj, int) { return sd[loc(ii, jj)]; });
-            v = v + ((T)1 + c1) * dk + cB * di * r1;
-        }
-        xcol[k] = v;
-        if (rv) dot += (double)v * (double)rv[(size_t)col * ld + k];
-    }
-    if (rv) {
-        const double s = group_sum(dot);
-        if (threadIdx.x == 0) red.rz[(size_t)col * red.stride + blockIdx.y * gridDim.x + blockIdx.x] = s;
-    }
-    }  // columns
 }
 
 // -------------------------------------------------------------- bottom ---

@@ -905,16 +905,20 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
         it = 1;
     }
     const bool graphs = !std::getenv("HINV_NO_GRAPHS");
-    // the previous call with this shape took `expect` iterations: replay up to
-    // one short of that before the first completion check (kernels of finished
-    // columns return at once, so a late check costs launches, not work)
+    // Replays before the first completion check follow an estimate of the
+    // iteration count kept per shape (kernels of finished columns return at
+    // once, so a late check costs launches, not work).  The estimate must not
+    // grow from the iterations replayed past convergence: when the first
+    // check already finds every column done, the next call checks two
+    // iterations earlier; at most 12 iterations run between checks.
     const long long key = 2LL * nc + (sizeof(T) == 4);
     int expect = 0;
     for (const auto& kv : last_iters_)
         if (kv.first == key) expect = kv.second;
+    bool first_check = true, done_at_first = false;
     while (it < max_iter) {
         int reps = 1;
-        if (expect - 1 > it + 2) reps = (expect - 1 - it) / 2;
+        if (first_check && expect - 1 > it + 2) reps = std::min(6, (expect - 1 - it) / 2);
         while (reps > 0 && it + 2 * reps > max_iter) --reps;
         if (graphs && reps > 0) {
             for (int rep = 0; rep < reps; ++rep) HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
@@ -933,16 +937,21 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
         HINV_HIP(hipStreamSynchronize(s));
         int live = 0;
         for (int c = 0; c < nc; ++c) live += host_flags_[c];
-        if (!live) break;
+        if (!live) {
+            done_at_first = first_check;
+            break;
+        }
+        first_check = false;
     }
     *iters += it;
+    const int next = done_at_first ? std::max(1, it - 2) : it;
     bool found = false;
     for (auto& kv : last_iters_)
         if (kv.first == key) {
-            kv.second = it;
+            kv.second = next;
             found = true;
         }
-    if (!found) last_iters_.push_back({key, it});
+    if (!found) last_iters_.push_back({key, next});
 }
 
 void Hierarchy::apply(int nc, const double* x, int ldx, double* y, int ldy) {

@@ -131,3 +131,50 @@ def test_batch_column_limit(batch_setup):
     with pytest.raises(hv.HinvError) as e:
         b.hessian_apply(hv.HESS_MISFIT, mh, mh)
     assert e.value.code == hv.HINV_EINVAL
+
+
+# meshes above the one-workgroup bottom (N > 32): the fused down/up V-cycle
+# kernels run on stacked problems; two instances share N = 64
+SPECS_LARGE = [(64, 120, 0.1, 0.8, 21), (128, 200, 0.06, 1.2, 22), (64, 80, 0.15, 0.6, 23)]
+
+
+@pytest.fixture(scope="module")
+def batch_large():
+    print("[gpu-batch] large setup", flush=True)
+    ctx = hv.Context(0)
+    insts, gps = [], []
+    for N, q, g, d, seed in SPECS_LARGE:
+        prob, _, obs = instance(N, q, g, d, seed)
+        m = prob.m_pr + 0.6 * synth.smooth_field(N, seed=seed)
+        u = prob.forward(m)
+        p = prob.adjoint(m, u)
+        gp = hv.Problem(ctx, N, g, d, obs_xy=obs, d_obs=prob.d, sigma=prob.sigma,
+                        m_prior=prob.m_pr[0], beta=prob.beta, precision=hv.PREC_AUTO, rtol=1e-10)
+        gp.linearize(dev(m), dev(u), dev(p))
+        insts.append((prob, m, u, p))
+        gps.append(gp)
+    return ctx, insts, gps
+
+
+@pytest.mark.parametrize("shape", [None, "l4c4", "s1c3", "l16c8"])
+def test_batch_hessian_stacked_large(batch_large, shape, monkeypatch):
+    """Four columns per problem (FP32 refinement on the stacked N = 64 pair);
+    column blocks of 3 and 8 straddle the two stacked problems.  Repeated calls
+    check that the per-shape iteration estimate of the inner solves does not
+    drift (every call converges to the requested tolerance)."""
+    if shape:
+        monkeypatch.setenv("HINV_SHAPE", shape)
+    ctx, insts, gps = batch_large
+    b = hv.Batch(ctx, gps)
+    nrhs = 4
+    mh = [synth.test_vectors(prob.n, nrhs, stream=70 + i) for i, (prob, *_) in enumerate(insts)]
+    outs = [dev(np.zeros((nrhs, prob.n))) for prob, *_ in insts]
+    for mode in (hv.HESS_MISFIT, hv.HESS_FULL):
+        refs = [np.array([prob.hessian_apply(m, u, p, v, mode) for v in mh[i]])
+                for i, (prob, m, u, p) in enumerate(insts)]
+        for rep in range(3):
+            print(f"[gpu-batch] large shape={shape} mode={mode} call {rep}", flush=True)
+            info = b.hessian_apply(mode, [dev(x) for x in mh], outs)
+            assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
+            for i in range(len(insts)):
+                assert col_rel(host(outs[i]), refs[i]) < 1e-8, (i, mode, rep)
