@@ -113,16 +113,7 @@ def run_step(prob, omega, cfg, tprod, m_map, V, samples=None):
                 eig=einfo, lam=lam)
 
 
-def kernel_source_hash():
-    """Hash of the kernel sources the traffic counters were taken on."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("mgkernels.h", "grid.h"):
-        h.update(open(os.path.join(ROOT, "paper_1909_03948_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
-def roofline(ctx, steps, tprod):
+def roofline(ctx, steps, tprod, workload):
     """Per-class sampled event timings -> roofline of the dominant class."""
     kern = {}
     for name in TIMED_CLASSES:
@@ -148,11 +139,14 @@ def roofline(ctx, steps, tprod):
     roof["kernel"] = dom
     roof["avg_us"] = k["avg_us"]
     roof["algorithmic_bytes_per_launch" if dom != "gram" else "flops_per_launch"] = k["work_per_launch"]
-    # HBM traffic from the committed counter summary, valid while the kernels are unchanged
+    # HBM bytes per launch from the committed counter summary of this workload,
+    # valid while the kernel sources are those the counters were taken on
     if os.path.exists(PMC_FILE) and dom != "gram":
-        pmc = json.load(open(PMC_FILE))
-        ent = pmc.get("kernels", {}).get(dom)
-        if ent and ent.get("single_level") and pmc.get("source_hash") == kernel_source_hash():
+        from paper_1909_03948_amd.profile_summary import kernel_source_hash
+        wl = json.load(open(PMC_FILE)).get("workloads", {}).get(workload, {})
+        ent = wl.get("kernels", {}).get(dom)
+        src = os.path.join(ROOT, "paper_1909_03948_amd")
+        if ent and wl.get("source_hash") == kernel_source_hash(src):
             roof["traffic"] = ent["hbm_bytes_per_launch"]
     return roof, kern
 
@@ -244,7 +238,7 @@ def run_uneven(a):
         log(f"step {st}: batched done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    roof, kern = roofline(ctx, a.steps, a.tprod)
+    roof, kern = roofline(ctx, a.steps, a.tprod, "uneven64")
     for name in TIMED_CLASSES:
         ctx.kernel_timer(name, False, 16)
     t2 = time.perf_counter()
@@ -486,7 +480,7 @@ def main():
         line["posterior_samples_per_s"] = a.samples * a.steps / sample_s
         line["value"] = hvps / (dt - sample_s)
         line["metric"] += " (HVP/s over the MAP + eigensolver part; samples timed separately)"
-    roof, kern = roofline(ctx, a.steps, a.tprod)
+    roof, kern = roofline(ctx, a.steps, a.tprod, workload)
     for name in TIMED_CLASSES:
         ctx.kernel_timer(name, False, 16)
     line["roofline"] = roof

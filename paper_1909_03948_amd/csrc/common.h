@@ -8,6 +8,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdint>
@@ -64,9 +65,11 @@ struct DBuf {
     T* get() const { return p; }
 };
 
-// Sampled kernel timing: while a class is enabled, every `period`-th launch of
-// it is bracketed by HIP events on the launching stream, and the algorithmic
-// bytes (or flops) of that launch are recorded with it.
+// Sampled kernel timing: while a class is enabled, every `period`-th eagerly
+// launched kernel of it (every one while `force` is set) carries an event pair
+// in its own dispatch (hipExtLaunchKernelGGL), so the pair brackets the
+// kernel's execution alone, and the algorithmic bytes (or flops) of that
+// launch are recorded with it.
 struct KernelTimer {
     static constexpr int kClasses = 8;
     static constexpr int kPool = 2048;  // event pairs per class
@@ -79,24 +82,26 @@ struct KernelTimer {
         int used = 0;
     } cls[kClasses];
     bool paused = false;  // set while a graph is being captured
-    // Returns the event pair to record around this launch, or -1.
-    int begin(int c, hipStream_t s, double work) {
+    bool force = false;   // sample every launch (not every period-th)
+    bool any_on() const {
+        for (const auto& k : cls)
+            if (k.on) return true;
+        return false;
+    }
+    // Returns the event-pair slot this launch carries, or -1.
+    int sample(int c, double work) {
         if (c < 0 || paused) return -1;
         Class& k = cls[c];
         if (!k.on) return -1;
         const long idx = k.launches++;
-        if (idx % k.period || k.used >= kPool) return -1;
+        if ((!force && idx % k.period) || k.used >= kPool) return -1;
         const int slot = k.used++;
         k.work[slot] = work;
-        (void)hipEventRecord(k.ev[2 * slot], s);
         return slot;
     }
     // Launches that ran inside a graph replay: counted, not timed.
     void count_only(int c, long n) {
         if (c >= 0 && cls[c].on) cls[c].launches += n;
-    }
-    void end(int c, int slot, hipStream_t s) {
-        if (c >= 0 && slot >= 0) (void)hipEventRecord(cls[c].ev[2 * slot + 1], s);
     }
     ~KernelTimer() {
         for (auto& k : cls)
@@ -115,17 +120,24 @@ struct Ctx {
 // Kernel classes of the timer (values of HINV_KCLASS_* in the public header).
 enum KClass { kKDown = 0, kKUp = 1, kKBottom = 2, kKPcgApply = 3, kKPcgUpdate = 4, kKGram = 5 };
 
-// RAII bracket of one launch (class -1: not timed).
-struct TimedLaunch {
-    Ctx* c;
-    int cls, slot;
-    TimedLaunch(Ctx* ctx, int k, double work) : c(ctx), cls(k), slot(ctx->timer.begin(k, ctx->stream, work)) {}
-    ~TimedLaunch() { c->timer.end(cls, slot, c->stream); }
-};
+// Launch of a timed class (-1: untimed): a sampled launch carries the class's
+// next event pair in its dispatch.
+template <typename F, typename... Args>
+inline void timed_launch(Ctx* ctx, int cls, double work, F kernel, dim3 grid, dim3 block,
+                         hipStream_t s, Args... args) {
+    const int slot = ctx->timer.sample(cls, work);
+    if (slot >= 0) {
+        auto& k = ctx->timer.cls[cls];
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, k.ev[2 * slot], k.ev[2 * slot + 1], 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    }
+}
 
 // ------------------------------------------------------------ constants ---
 constexpr int kBlock = 256;   // threads per workgroup for grid kernels
 constexpr int kCoarseMaxN = 8;  // coarsest multigrid level has N_c <= 8
+constexpr int kMaxVecPartials = 512;  // partial sums per column of the PCG vector kernels
 constexpr int kAutoBatch = 8;   // HINV_PREC_AUTO switches to FP32 refinement from this many columns
 
 // Chebyshev smoother: degree 2, targets the interval [0.5, 2] of the

@@ -28,71 +28,103 @@ __device__ inline short to_bf16(double x) {
     return (short)(u >> 16);
 }
 
-constexpr int kWaves = 4;  // waves per workgroup in the block-product kernels
+// Block products: a workgroup of kBlkWaves waves owns a 128 x 128 block of the
+// output; wave w computes its rows [16 w, 16 w + 16) against all 128 columns
+// (kBlkTiles matrix-core tiles sharing one operand), so each column of X and
+// Y is read by ceil(s / 128) workgroups instead of ceil(s / 16).
+constexpr int kBlkWaves = 8, kBlkTiles = 8, kBlk = 128;
 
-// Split-K Gram: grid.x = output tile (16 x 16), grid.y = K chunk.
-// Each of the 4 waves walks every 4th group of 4 rows of the chunk.
-__global__ __launch_bounds__(256) void k_gram_f64(int n, int s1, int s2, int chunk,
+// Split-K Gram C = X^T Y: grid.x = output block, grid.y = K chunk.
+__global__ __launch_bounds__(512) void k_gram_f64(int n, int s1, int s2, int chunk,
                                                   const double* __restrict__ X, int ldx,
                                                   const double* __restrict__ Y, int ldy,
                                                   double* __restrict__ part) {
-    const int tiles_i = (s1 + 15) / 16;
-    const int ti = blockIdx.x % tiles_i, tj = blockIdx.x / tiles_i;
+    const int blocks_i = (s1 + kBlk - 1) / kBlk;
+    const int bi = blockIdx.x % blocks_i, bj = blockIdx.x / blocks_i;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = ti * 16 + (lane & 15), j = tj * 16 + (lane & 15);
+    const int i = bi * kBlk + wave * 16 + (lane & 15);
+    if (bi * kBlk + wave * 16 >= s1) return;  // no rows for this wave (no barrier below)
     const int kr = lane >> 4;
     const int k_begin = blockIdx.y * chunk;
     const int k_end = min(n, k_begin + chunk);
-    d4_t acc = {0.0, 0.0, 0.0, 0.0};
     const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
-    const double* yc = Y + (size_t)(j < s2 ? j : 0) * ldy;
-    for (int k0 = k_begin + wave * 4; k0 < k_end; k0 += 4 * kWaves) {
-        const int k = k0 + kr;
-        const double a = (i < s1 && k < k_end) ? xc[k] : 0.0;
-        const double b = (j < s2 && k < k_end) ? yc[k] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    const double* yc[kBlkTiles];
+    bool jv[kBlkTiles];
+    d4_t acc[kBlkTiles];
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t) {
+        const int j = bj * kBlk + t * 16 + (lane & 15);
+        jv[t] = j < s2;
+        yc[t] = Y + (size_t)(jv[t] ? j : 0) * ldy;
+        acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
     }
-    __shared__ double red[kWaves][16][16];
-    for (int v = 0; v < 4; ++v) red[wave][4 * v + (lane >> 4)][lane & 15] = acc[v];
-    __syncthreads();
-    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;  // 256 threads = 16 x 16
-    double sum = 0.0;
-    for (int w = 0; w < kWaves; ++w) sum += red[w][r][c];
-    const int gi = ti * 16 + r, gj = tj * 16 + c;
-    if (gi < s1 && gj < s2) part[((size_t)blockIdx.y * s2 + gj) * s1 + gi] = sum;
+    for (int k0 = k_begin; k0 < k_end; k0 += 4) {
+        const int k = k0 + kr;
+        const bool kv = k < k_end;
+        const double a = (i < s1 && kv) ? xc[k] : 0.0;
+#pragma unroll
+        for (int t = 0; t < kBlkTiles; ++t) {
+            const double b = (jv[t] && kv) ? yc[t][k] : 0.0;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t)
+        for (int v = 0; v < 4; ++v) {
+            const int gi = bi * kBlk + wave * 16 + 4 * v + (lane >> 4);
+            const int gj = bj * kBlk + t * 16 + (lane & 15);
+            if (gi < s1 && gj < s2) part[((size_t)blockIdx.y * s2 + gj) * s1 + gi] = acc[t][v];
+        }
 }
 
-__global__ __launch_bounds__(256) void k_gram_bf16(int n, int s1, int s2, int chunk,
+__global__ __launch_bounds__(512) void k_gram_bf16(int n, int s1, int s2, int chunk,
                                                    const double* __restrict__ X, int ldx,
                                                    const double* __restrict__ Y, int ldy,
                                                    double* __restrict__ part) {
-    const int tiles_i = (s1 + 15) / 16;
-    const int ti = blockIdx.x % tiles_i, tj = blockIdx.x / tiles_i;
+    const int blocks_i = (s1 + kBlk - 1) / kBlk;
+    const int bi = blockIdx.x % blocks_i, bj = blockIdx.x / blocks_i;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = ti * 16 + (lane & 15), j = tj * 16 + (lane & 15);
+    const int i = bi * kBlk + wave * 16 + (lane & 15);
+    if (bi * kBlk + wave * 16 >= s1) return;  // no rows for this wave (no barrier below)
     const int kq = (lane >> 4) * 4;
     const int k_begin = blockIdx.y * chunk;
     const int k_end = min(n, k_begin + chunk);
-    f4_t acc = {0.f, 0.f, 0.f, 0.f};
     const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
-    const double* yc = Y + (size_t)(j < s2 ? j : 0) * ldy;
-    for (int k0 = k_begin + wave * 16; k0 < k_end; k0 += 16 * kWaves) {
-        s4_t a, b;
+    const double* yc[kBlkTiles];
+    bool jv[kBlkTiles];
+    f4_t acc[kBlkTiles];
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t) {
+        const int j = bj * kBlk + t * 16 + (lane & 15);
+        jv[t] = j < s2;
+        yc[t] = Y + (size_t)(jv[t] ? j : 0) * ldy;
+        acc[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int k0 = k_begin; k0 < k_end; k0 += 16) {
+        s4_t a;
+#pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int k = k0 + kq + e;
             a[e] = to_bf16((i < s1 && k < k_end) ? xc[k] : 0.0);
-            b[e] = to_bf16((j < s2 && k < k_end) ? yc[k] : 0.0);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < kBlkTiles; ++t) {
+            s4_t b;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = k0 + kq + e;
+                b[e] = to_bf16((jv[t] && k < k_end) ? yc[t][k] : 0.0);
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
     }
-    __shared__ float red[kWaves][16][16];
-    for (int v = 0; v < 4; ++v) red[wave][4 * (lane >> 4) + v][lane & 15] = acc[v];
-    __syncthreads();
-    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
-    double sum = 0.0;
-    for (int w = 0; w < kWaves; ++w) sum += (double)red[w][r][c];
-    const int gi = ti * 16 + r, gj = tj * 16 + c;
-    if (gi < s1 && gj < s2) part[((size_t)blockIdx.y * s2 + gj) * s1 + gi] = sum;
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t)
+        for (int v = 0; v < 4; ++v) {
+            const int gi = bi * kBlk + wave * 16 + 4 * (lane >> 4) + v;
+            const int gj = bj * kBlk + t * 16 + (lane & 15);
+            if (gi < s1 && gj < s2) part[((size_t)blockIdx.y * s2 + gj) * s1 + gi] = (double)acc[t][v];
+        }
 }
 
 __global__ void k_gram_reduce(int s1, int s2, int nsplit, const double* __restrict__ part,
@@ -105,30 +137,42 @@ __global__ void k_gram_reduce(int s1, int s2, int nsplit, const double* __restri
     C[i + (size_t)j * ldc] = s;
 }
 
-// C = alpha X B + beta C; grid.x: 16-row strips (4 per workgroup), grid.y: 16-column tiles.
-__global__ __launch_bounds__(256) void k_gemm_tall(int n, int s, int t, double alpha,
+// C = alpha X B + beta C (X: n x s, B: s x t).  grid.x: strips of 16
+// kBlkWaves rows (one 16-row strip per wave), grid.y: 128-column blocks; a
+// wave computes its 16 rows against the block's kBlkTiles column tiles, so
+// X is read once per column block.
+__global__ __launch_bounds__(512) void k_gemm_tall(int n, int s, int t, double alpha,
                                                    const double* __restrict__ X, int ldx,
                                                    const double* __restrict__ B, int ldb,
                                                    double beta, double* __restrict__ C, int ldc) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = (blockIdx.x * kWaves + wave) * 16;
+    const int r0 = (blockIdx.x * kBlkWaves + wave) * 16;
     if (r0 >= n) return;
-    const int c0 = blockIdx.y * 16;
-    const int row = r0 + (lane & 15), colb = c0 + (lane & 15), kr = lane >> 4;
-    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    const int c0 = blockIdx.y * kBlk;
+    const int row = r0 + (lane & 15), kr = lane >> 4;
+    d4_t acc[kBlkTiles];
+#pragma unroll
+    for (int tt = 0; tt < kBlkTiles; ++tt) acc[tt] = d4_t{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < s; k0 += 4) {
         const int k = k0 + kr;
         const double a = (row < n && k < s) ? X[(size_t)k * ldx + row] : 0.0;
-        const double b = (colb < t && k < s) ? B[k + (size_t)colb * ldb] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int tt = 0; tt < kBlkTiles; ++tt) {
+            const int colb = c0 + tt * 16 + (lane & 15);
+            const double b = (colb < t && k < s) ? B[k + (size_t)colb * ldb] : 0.0;
+            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[tt], 0, 0, 0);
+        }
     }
-    const int cc = c0 + (lane & 15);
-    if (cc >= t) return;
-    for (int v = 0; v < 4; ++v) {
-        const int rr = r0 + 4 * v + (lane >> 4);
-        if (rr < n) {
-            double* dst = C + (size_t)cc * ldc + rr;
-            *dst = alpha * acc[v] + (beta != 0.0 ? beta * *dst : 0.0);
+#pragma unroll
+    for (int tt = 0; tt < kBlkTiles; ++tt) {
+        const int cc = c0 + tt * 16 + (lane & 15);
+        if (cc >= t) continue;
+        for (int v = 0; v < 4; ++v) {
+            const int rr = r0 + 4 * v + (lane >> 4);
+            if (rr < n) {
+                double* dst = C + (size_t)cc * ldc + rr;
+                *dst = alpha * acc[tt][v] + (beta != 0.0 ? beta * *dst : 0.0);
+            }
         }
     }
 }
@@ -186,7 +230,10 @@ __global__ void k_tri_inverse(int s, const double* __restrict__ R, int ldr, doub
     }
 }
 
-// Parallel cyclic Jacobi (round-robin pairing), one workgroup.
+// Parallel cyclic Jacobi (round-robin pairing), one workgroup.  Stops when
+// the off-diagonal Frobenius norm is below 1e-12 of the total, or, once it is
+// below 1e-8, when a sweep no longer halves it (rounding in the rotations
+// keeps it near s eps |T|, so a fixed tighter bound may never be met).
 __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restrict__ S, int lds,
                          int max_sweeps) {
     const int m = s + (s & 1);
@@ -194,6 +241,7 @@ __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restr
     __shared__ double cs[256], sn[256];
     __shared__ int pp[256], qq[256];
     __shared__ double offn, totn;
+    double prev = -1.0;  // off-diagonal norm^2 of the previous sweep
     __shared__ double wsum[32];
     // symmetrize, S = I
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
@@ -234,7 +282,9 @@ __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restr
             totn = st;
         }
         __syncthreads();
-        if (offn <= 1e-30 * totn || totn == 0.0) break;
+        if (offn <= 1e-24 * totn || totn == 0.0) break;
+        if (prev >= 0.0 && offn <= 1e-16 * totn && offn > 0.25 * prev) break;
+        prev = offn;
         for (int step = 0; step < m - 1; ++step) {
             for (int k = threadIdx.x; k < np; k += blockDim.x) {
                 int p, q;
@@ -276,9 +326,9 @@ __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restr
                 T[q + (size_t)c * ldt] = sn[k] * tp + cs[k] * tq;
             }
             __syncthreads();
-            // columns p, q  <- T J, S J
+            // columns p, q  <- T J, S J (consecutive threads on consecutive rows)
             for (int id = threadIdx.x; id < np * s; id += blockDim.x) {
-                const int k = id % np, r = id / np;
+                const int r = id % s, k = id / s;
                 const int p = pp[k], q = qq[k];
                 if (q >= s) continue;
                 const double tp = T[r + (size_t)p * ldt], tq = T[r + (size_t)q * ldt];
@@ -340,19 +390,20 @@ __global__ void k_scale_rows(int s, int t, const double* __restrict__ d, double*
 
 void gram(Ctx* ctx, DenseWork& w, int n, int s1, int s2, const double* X, int ldx, const double* Y,
           int ldy, double* C, int ldc, bool bf16) {
-    const int tiles = ((s1 + 15) / 16) * ((s2 + 15) / 16);
-    const int unit = bf16 ? 16 * kWaves : 4 * kWaves;
-    int nsplit = std::max(1, std::min(ceil_div(4096, 4 * tiles), ceil_div(n, 4 * unit)));
-    int chunk = ceil_div(ceil_div(n, nsplit), unit) * unit;
+    const int blocks = ((s1 + kBlk - 1) / kBlk) * ((s2 + kBlk - 1) / kBlk);
+    // K split: about 2048 workgroups, chunks of at least 256 rows (a multiple
+    // of the 16-row matrix-core step)
+    int nsplit = std::max(1, std::min(ceil_div(2048, blocks), ceil_div(n, 256)));
+    const int chunk = ceil_div(ceil_div(n, nsplit), 16) * 16;
     nsplit = ceil_div(n, chunk);
     w.part.ensure((size_t)nsplit * s1 * s2);
-    TimedLaunch tl(ctx, kKGram, 2.0 * n * s1 * s2);  // flops
+    const double flops = 2.0 * n * s1 * s2;
     if (bf16)
-        k_gram_bf16<<<dim3(tiles, nsplit), 256, 0, ctx->stream>>>(n, s1, s2, chunk, X, ldx, Y, ldy,
-                                                                 w.part.get());
+        timed_launch(ctx, kKGram, flops, k_gram_bf16, dim3(blocks, nsplit), dim3(64 * kBlkWaves), ctx->stream,
+                     n, s1, s2, chunk, X, ldx, Y, ldy, w.part.get());
     else
-        k_gram_f64<<<dim3(tiles, nsplit), 256, 0, ctx->stream>>>(n, s1, s2, chunk, X, ldx, Y, ldy,
-                                                                w.part.get());
+        timed_launch(ctx, kKGram, flops, k_gram_f64, dim3(blocks, nsplit), dim3(64 * kBlkWaves), ctx->stream,
+                     n, s1, s2, chunk, X, ldx, Y, ldy, w.part.get());
     HINV_LAUNCH_CHECK();
     k_gram_reduce<<<ceil_div(s1 * s2, 256), 256, 0, ctx->stream>>>(s1, s2, nsplit, w.part.get(), C, ldc);
     HINV_LAUNCH_CHECK();
@@ -361,8 +412,8 @@ void gram(Ctx* ctx, DenseWork& w, int n, int s1, int s2, const double* X, int ld
 void gemm_tall(Ctx* ctx, int n, int s, int t, double alpha, const double* X, int ldx,
                const double* B, int ldb, double beta, double* C, int ldc) {
     if (n <= 0 || t <= 0) return;
-    const dim3 g(ceil_div(ceil_div(n, 16), kWaves), ceil_div(t, 16));
-    k_gemm_tall<<<g, 256, 0, ctx->stream>>>(n, s, t, alpha, X, ldx, B, ldb, beta, C, ldc);
+    const dim3 g(ceil_div(ceil_div(n, 16), kBlkWaves), ceil_div(t, kBlk));
+    k_gemm_tall<<<g, 64 * kBlkWaves, 0, ctx->stream>>>(n, s, t, alpha, X, ldx, B, ldb, beta, C, ldc);
     HINV_LAUNCH_CHECK();
 }
 

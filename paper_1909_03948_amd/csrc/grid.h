@@ -222,44 +222,58 @@ struct TileStencil {
     T* dv;
 };
 
-// Stages the rows of the TW x TW tile whose local (0, 0) is node (ox, oy).
-template <typename T>
-__device__ inline void stage_stencil(const OpA<T>& op, const TileStencil<T>& s, int ox, int oy, int TW) {
+// Stages the rows of the TW x TW tile whose local (0, 0) is node (ox, oy),
+// NT threads.  Every global load of a thread is issued before its first LDS
+// store, so the load latencies of its NT-strided elements overlap.
+template <int TW, int NT, typename T>
+__device__ inline void stage_stencil(const OpA<T>& op, const TileStencil<T>& s, int ox, int oy) {
+    constexpr int NN = TW * TW, E = (NN + NT - 1) / NT;
     const int N = op.N, N1 = N + 1;
-    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
+    T we[E], wn[E], ww[E], ws[E], dv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + e * NT;
         const int i = ox + t % TW, j = oy + t / TW;
-        T c = 0, e = 0, n = 0, dv = 0;
-        if (i >= 0 && i <= N && j >= 0 && j <= N) {
-            const int k = j * N1 + i;
-            const T wE = op.wE[k], wN = op.wN[k];
-            c = wE + wN + (i > 0 ? op.wE[k - 1] : (T)0) + (j > 0 ? op.wN[k - N1] : (T)0);
-            e = -wE;
-            n = -wN;
-            dv = op.dinv[k];
+        const bool in = t < NN && i >= 0 && i <= N && j >= 0 && j <= N;
+        const int k = j * N1 + i;
+        we[e] = in ? op.wE[k] : (T)0;
+        wn[e] = in ? op.wN[k] : (T)0;
+        ww[e] = in && i > 0 ? op.wE[k - 1] : (T)0;
+        ws[e] = in && j > 0 ? op.wN[k - N1] : (T)0;
+        dv[e] = in ? op.dinv[k] : (T)0;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + e * NT;
+        if (t < NN) {
+            s.c[t] = we[e] + wn[e] + ww[e] + ws[e];
+            s.e[t] = -we[e];
+            s.n[t] = -wn[e];
+            s.dv[t] = dv[e];
         }
-        s.c[t] = c;
-        s.e[t] = e;
-        s.n[t] = n;
-        s.dv[t] = dv;
     }
 }
 
-template <typename T, class OpK>
-__device__ inline void stage_stencil(const OpK& op, const TileStencil<T>& s, int ox, int oy, int TW) {
+template <int TW, int NT, typename T, class OpK>
+__device__ inline void stage_stencil(const OpK& op, const TileStencil<T>& s, int ox, int oy) {
+    constexpr int NN = TW * TW, E = (NN + NT - 1) / NT;
     const int N = op.N;
-    for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + e * NT;
+        if (t >= NN) break;
         const int i = ox + t % TW, j = oy + t / TW;
-        T c = 0, e = 0, n = 0, g = 0, dv = 0;
+        T c = 0, ee = 0, n = 0, g = 0, dv = 0;
         if (i >= 0 && i <= N && j >= 0 && j <= N) {
             const KARow<T>& r = op.rows[ka_class(i, j, N)];
             c = r.c;
-            e = r.e;
+            ee = r.e;
             n = r.n;
             g = r.ne;
             dv = r.dinv;
         }
         s.c[t] = c;
-        s.e[t] = e;
+        s.e[t] = ee;
         s.n[t] = n;
         s.g[t] = g;
         s.dv[t] = dv;

@@ -31,11 +31,19 @@ struct ChebCoef {
 // In-kernel reductions: every workgroup writes one partial sum per column to
 // part[col * stride + blk]; a later kernel (after the kernel boundary, so no
 // fences are needed) sums them in a fixed order.
-__device__ inline double partial_total(const double* part, int col, int stride, int nblk) {
+// First phase: this thread's strided share of the partials (loads only, so
+// that a kernel can issue them together with its other loads).
+__device__ inline double partial_share(const double* part, int col, int stride, int nblk) {
+    double s = 0.0;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)col * stride + b];
+    return s;
+}
+
+// Second phase: the workgroup total of the shares, returned to every thread.
+__device__ inline double share_total(double s) {
     __shared__ double ps[16];
     __shared__ double tot;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)col * stride + b];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) ps[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -48,6 +56,10 @@ __device__ inline double partial_total(const double* part, int col, int stride, 
     return tot;
 }
 
+__device__ inline double partial_total(const double* part, int col, int stride, int nblk) {
+    return share_total(partial_share(part, col, stride, nblk));
+}
+
 // Partial-sum buffers of the PCG inner products ([ncols][stride] each).
 struct PcgRed {
     double* rz;
@@ -56,8 +68,13 @@ struct PcgRed {
     int stride;
     int nrz;  // number of partials of r^T z (workgroups of the last V-cycle kernel)
     int nvec; // number of partials of p^T q and r^T r (workgroups of the PCG vector kernels)
-    int per;  // consecutive blocks of kBlock nodes per workgroup in the PCG vector kernels
+    int per;  // consecutive blocks of 256 nodes per workgroup in the PCG vector kernels
 };
+
+// Threads per workgroup of the PCG vector kernels: 256 per node block up to
+// 1024, so a workgroup covers its 256 per nodes in at most kVecNodes passes.
+__host__ __device__ inline int vec_threads(int per) { return per >= 4 ? 1024 : 256 * per; }
+constexpr int kVecNodes = 4;
 
 // Workgroup sum with its own LDS slot; result valid in thread 0.
 __device__ inline double group_sum(double v) {
@@ -107,22 +124,33 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T
     const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // global coordinates of local (0, 0)
     const T inv_theta = (T)cc.inv_theta, cA = (T)cc.cA, cB = (T)cc.cB;
     const int own_i1 = min(2 * I1 + 1, N), own_j1 = min(2 * J1 + 1, N);
+    constexpr int E = (NN + 255) / 256;  // tile elements per thread
     const void* staged = nullptr;  // the staged rows belong to this instance
     const int c_end = min(nc, (int)(blockIdx.z + 1) * cb);
     for (int col = blockIdx.z * cb; col < c_end; ++col) {
         if (act && !act[col]) continue;
-        if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) continue;
         const auto& op = op_.at(col);  // operator of the instance owning this column
         const T* bcol = b + (size_t)col * ld;
         T* xcol = x + (size_t)col * ld;
-        __syncthreads();  // the previous column's LDS reads are done
-        for (int t = threadIdx.x; t < NN; t += blockDim.x) {
+        // loads first: b, then the operator rows, then the convergence test,
+        // so that their latencies overlap
+        T vb[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + 256 * e;
             const int i = ox + t % TW, j = oy + t / TW;
-            sb[t] = (i >= 0 && i <= N && j >= 0 && j <= N) ? bcol[j * N1 + i] : (T)0;
+            vb[e] = (t < NN && i >= 0 && i <= N && j >= 0 && j <= N) ? bcol[j * N1 + i] : (T)0;
         }
+        __syncthreads();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
-            stage_stencil(op, ts, ox, oy, TW);
+            stage_stencil<TW, 256>(op, ts, ox, oy);
             staged = instance_key(op);
+        }
+        if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) continue;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + 256 * e;
+            if (t < NN) sb[t] = vb[e];
         }
         __syncthreads();
         // d0 = D^-1 b / theta on the whole tile (zero off the free nodes)
@@ -195,6 +223,7 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
     const int i1 = min(i0 + kTF - 1, N), j1 = min(j0 + kTF - 1, N);
     const int ox = i0 - 2, oy = j0 - 2;
     const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
+    constexpr int E = (NN + 255) / 256;  // tile elements per thread
     const void* staged = nullptr;
     const int c_end = min(nc, (int)(blockIdx.z + 1) * cb);
     for (int col = blockIdx.z * cb; col < c_end; ++col) {
@@ -204,32 +233,38 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
         const T* x2col = x2 + (size_t)col * ld;
         T* xcol = x + (size_t)col * ld;
         const T* ccol = xc + (size_t)col * ldc;
-        __syncthreads();  // the previous column's LDS reads are done
-        for (int t = threadIdx.x; t < NN; t += blockDim.x) {
+        // loads first (b, x2 and the two coarse values of the prolongation,
+        // then the operator rows) so that their latencies overlap.  P x_c at
+        // (i, j): the coarse node (i/2, j/2) when both are even, else the mean
+        // of the two coarse ends of the fine edge through (i, j).
+        T vb[E], vx[E], pc0[E], pc1[E];
+        bool even[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + 256 * e;
             const int i = ox + t % TW, j = oy + t / TW;
-            T v = 0, bv = 0;
-            if (i >= 0 && i <= N && j >= 0 && j <= N) {
-                bv = bcol[j * N1 + i];
-                if (!(dirichlet && (j == 0 || j == N))) {
-                    const int I = i >> 1, J = j >> 1;
-                    T p;
-                    if (!(i & 1) && !(j & 1))
-                        p = ccol[J * Nc1 + I];
-                    else if (!(j & 1))
-                        p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[J * Nc1 + I + 1]);
-                    else if (!(i & 1))
-                        p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[(J + 1) * Nc1 + I]);
-                    else
-                        p = (T)0.5 * (ccol[J * Nc1 + I] + ccol[(J + 1) * Nc1 + I + 1]);
-                    v = x2col[j * N1 + i] + p;
-                }
-            }
-            sx[t] = v;
-            sb[t] = bv;
+            const bool in = t < NN && i >= 0 && i <= N && j >= 0 && j <= N;
+            const bool fr = in && !(dirichlet && (j == 0 || j == N));
+            const int I = i >> 1, J = j >> 1;
+            const int a0 = J * Nc1 + I, a1 = (J + (j & 1)) * Nc1 + I + (i & 1);
+            vb[e] = in ? bcol[j * N1 + i] : (T)0;
+            vx[e] = fr ? x2col[j * N1 + i] : (T)0;
+            pc0[e] = fr ? ccol[a0] : (T)0;
+            pc1[e] = fr ? ccol[a1] : (T)0;
+            even[e] = !((i | j) & 1);
         }
+        __syncthreads();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
-            stage_stencil(op, ts, ox, oy, TW);
+            stage_stencil<TW, 256>(op, ts, ox, oy);
             staged = instance_key(op);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + 256 * e;
+            if (t < NN) {
+                sx[t] = vx[e] + (even[e] ? pc0[e] : (T)0.5 * (pc0[e] + pc1[e]));
+                sb[t] = vb[e];
+            }
         }
         __syncthreads();
         // d0 = D^-1 (b - A x) / theta on local [1, TW-1)^2 (zero off the free nodes)
@@ -320,28 +355,61 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
     if (KIND == kOpPrior)
         for (int t = threadIdx.x; t < a.nlev * 9; t += blockDim.x)
             rows[t] = a.cpi ? a.karows[t / 9][9 * inst + t % 9] : a.ka[t / 9][t % 9];
-    int off[kBottomLevels];
+    int off[kBottomLevels + 1];
     {
         int o = 0;
-        for (int l = 0; l < a.nlev; ++l) {
+        for (int l = 0; l < kBottomLevels; ++l) {
             off[l] = o;
-            o += (a.N[l] + 1) * (a.N[l] + 1);
+            if (l < a.nlev) o += (a.N[l] + 1) * (a.N[l] + 1);
+        }
+        off[kBottomLevels] = o;
+    }
+    const int n0 = (a.N[0] + 1) * (a.N[0] + 1);
+    // Every global load is issued before the first LDS store: b, the state
+    // coefficients of the bottom levels (all levels concatenated, node t of
+    // the concatenation), and this thread's part of the dense coarse inverse
+    // (row t / S, entries t % S, t % S + S, ...; at most kCU of them).
+    constexpr int EB = (kBottomNodes + 1023) / 1024, S = 12, kCU = 8;
+    T vb[EB], vE[EB], vN[EB], vD[EB];
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+        const int t = threadIdx.x + 1024 * e;
+        vb[e] = t < n0 ? bg[(size_t)col * ld + t] : (T)0;
+        if constexpr (KIND == kOpState) {
+            const int l = (t >= off[1]) + (t >= off[2]);
+            const bool in = t < off[kBottomLevels];
+            const long long cs = l == 0 ? a.cs[0] : (l == 1 ? a.cs[1] : a.cs[2]);
+            const int ol = l == 0 ? 0 : (l == 1 ? off[1] : off[2]);
+            const long long at = (a.cpi ? inst * cs : 0) + (t - ol);
+            const T* pE = l == 0 ? a.wE[0] : (l == 1 ? a.wE[1] : a.wE[2]);
+            const T* pN = l == 0 ? a.wN[0] : (l == 1 ? a.wN[1] : a.wN[2]);
+            const T* pD = l == 0 ? a.dinv[0] : (l == 1 ? a.dinv[1] : a.dinv[2]);
+            vE[e] = in ? pE[at] : (T)0;
+            vN[e] = in ? pN[at] : (T)0;
+            vD[e] = in ? pD[at] : (T)0;
         }
     }
-    if constexpr (KIND == kOpState)
-        for (int l = 0; l < a.nlev; ++l) {
-            const int nl = (a.N[l] + 1) * (a.N[l] + 1);
-            const long long io = a.cpi ? inst * a.cs[l] : 0;
-            for (int k = threadIdx.x; k < nl; k += blockDim.x) {
-                cwE[off[l] + k] = a.wE[l][io + k];
-                cwN[off[l] + k] = a.wN[l][io + k];
-                cdinv[off[l] + k] = a.dinv[l][io + k];
+    const T* ci = a.cinv + (a.cpi ? inst * a.cinv_stride : 0);
+    const int cr = threadIdx.x / S, cpart = threadIdx.x % S;
+    T cv[kCU];
+#pragma unroll
+    for (int u = 0; u < kCU; ++u) {
+        const int c = cpart + u * S;
+        cv[u] = (cr < a.nc && c < a.nc) ? ci[cr * a.nc + c] : (T)0;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+        const int t = threadIdx.x + 1024 * e;
+        if (t < n0) sb[t] = vb[e];
+        if constexpr (KIND == kOpState)
+            if (t < off[kBottomLevels]) {
+                cwE[t] = vE[e];
+                cwN[t] = vN[e];
+                cdinv[t] = vD[e];
             }
-        }
+    }
     const int dir = KIND == kOpState;
     const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cA = (T)cc.cA, cB = (T)cc.cB, c1 = (T)cc.c1;
-    const int n0 = (a.N[0] + 1) * (a.N[0] + 1);
-    for (int k = threadIdx.x; k < n0; k += blockDim.x) sb[k] = bg[(size_t)col * ld + k];
     __syncthreads();
     const int L = a.nlev - 1;
     // ---- down
@@ -389,18 +457,19 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
         }
         __syncthreads();
     }
-    // ---- coarsest: dense inverse, 12 threads per row
+    // ---- coarsest: dense inverse, S threads per row (entries prefetched in cv)
     {
         const T* b = sb + off[L];
         T* x = sx + off[L];
         T* tmp = st_;  // level-0 scratch is free here
-        constexpr int S = 12;
-        const T* ci = a.cinv + (a.cpi ? inst * a.cinv_stride : 0);
-        for (int t = threadIdx.x; t < a.nc * S; t += blockDim.x) {
-            const int r = t / S, part = t % S;
+        if (cr < a.nc) {
             T s = 0;
-            for (int c = part; c < a.nc; c += S) s += ci[r * a.nc + c] * b[c];
-            tmp[t] = s;
+#pragma unroll
+            for (int u = 0; u < kCU; ++u) {
+                const int c = cpart + u * S;
+                if (c < a.nc) s += cv[u] * b[c];
+            }
+            tmp[threadIdx.x] = s;
         }
         __syncthreads();
         for (int r = threadIdx.x; r < a.nc; r += blockDim.x) {
@@ -465,50 +534,92 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
 }
 
 // ------------------------------------------------------------------ PCG ---
+// Workgroup blockIdx.x covers nodes [256 per x, 256 per (x + 1)) of column
+// blockIdx.y with vec_threads(per) threads, at most kVecNodes nodes a thread.
+
 // p_new = z + beta p_old with beta = (r^T z) / rz_old (p_new = z on the first
-// iteration), q = A p_new, partials of p_new^T q.
+// iteration), q = A p_new = A z + beta A p_old, partials of p_new^T q.  The
+// loads of z, p_old (with the operator rows) and of the r^T z partials are
+// all issued before the reduction.  Workgroup 0 records r^T z for the update
+// kernel, which then reads one value instead of the partials.
 template <typename T, class Op>
-__global__ __launch_bounds__(256) void k_pcg_apply(Op op_, const T* __restrict__ z, const T* __restrict__ p_old,
-                                                   T* __restrict__ p_new, T* __restrict__ q, int ld,
-                                                   const int* __restrict__ act, const ColState* __restrict__ st,
-                                                   PcgRed red, int first) {
+__global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict__ z, const T* __restrict__ p_old,
+                                                    T* __restrict__ p_new, T* __restrict__ q, int ld,
+                                                    const int* __restrict__ act, ColState* __restrict__ st,
+                                                    PcgRed red, int first) {
     const int col = blockIdx.y;
     const auto& op = op_.at(col);  // operator of the instance owning this column
     if (!act[col]) return;
     const int N = op.N, N1 = N + 1, n = N1 * N1;
-    T beta = 0;
-    if (!first) beta = (T)(partial_total(red.rz, col, red.stride, red.nrz) / st[col].rz);
+    const bool need_rz = !first || blockIdx.x == 0;  // uniform in the workgroup
+    const double srz = need_rz ? partial_share(red.rz, col, red.stride, red.nrz) : 0.0;
     const T* zc = z + (size_t)col * ld;
     const T* pc = p_old + (size_t)col * ld;
-    auto pn = [&](int, int, int kk) { return first ? zc[kk] : zc[kk] + beta * pc[kk]; };
-    double dot = 0.0;
-    for (int e = 0; e < red.per; ++e) {
-        const int k = (blockIdx.x * red.per + e) * blockDim.x + threadIdx.x;
-        if (k >= n) break;
-        const int i = k % N1, j = k / N1;
-        const T pk = pn(i, j, k);
-        T v = 0;
-        if (op.is_free(i, j)) v = op.apply(i, j, k, pn);
-        p_new[(size_t)col * ld + k] = pk;
-        q[(size_t)col * ld + k] = v;
-        dot += (double)pk * (double)v;
+    const int k0 = blockIdx.x * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
+    T zk[kVecNodes], pk[kVecNodes], az[kVecNodes], ap[kVecNodes];
+#pragma unroll
+    for (int e = 0; e < kVecNodes; ++e) {
+        const int k = k0 + e * blockDim.x + threadIdx.x;
+        zk[e] = pk[e] = az[e] = ap[e] = 0;
+        if (k < k1) {
+            const int i = k % N1, j = k / N1;
+            zk[e] = zc[k];
+            if (!first) pk[e] = pc[k];
+            if (op.is_free(i, j)) {
+                az[e] = op.apply(i, j, k, [&](int, int, int kk) { return zc[kk]; });
+                if (!first) ap[e] = op.apply(i, j, k, [&](int, int, int kk) { return pc[kk]; });
+            }
+        }
     }
-    const double s = group_sum(dot);
-    if (threadIdx.x == 0) red.pq[(size_t)col * red.stride + blockIdx.x] = s;
+    T beta = 0;
+    if (need_rz) {
+        const double rz = share_total(srz);
+        if (!first) beta = (T)(rz / st[col].rz);
+        if (blockIdx.x == 0 && threadIdx.x == 0) st[col].rz_new = rz;
+    }
+    double dot = 0.0;
+#pragma unroll
+    for (int e = 0; e < kVecNodes; ++e) {
+        const int k = k0 + e * blockDim.x + threadIdx.x;
+        if (k < k1) {
+            const T pn = first ? zk[e] : zk[e] + beta * pk[e];
+            const T v = first ? az[e] : az[e] + beta * ap[e];
+            p_new[(size_t)col * ld + k] = pn;
+            q[(size_t)col * ld + k] = v;
+            dot += (double)pn * (double)v;
+        }
+    }
+    const double sm = group_sum(dot);
+    if (threadIdx.x == 0) red.pq[(size_t)col * red.stride + blockIdx.x] = sm;
 }
 
 // alpha = (r^T z) / (p^T q); x += alpha p, r -= alpha q; partials of r^T r.
 // Workgroup 0 records rz (the next beta's denominator) and alpha; a column
 // with p^T q <= 0 (breakdown) stops.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pcg_update(T* __restrict__ x, T* __restrict__ r,
-                                                    const T* __restrict__ p, const T* __restrict__ q,
-                                                    int ld, int n, int* __restrict__ act,
-                                                    ColState* __restrict__ st, PcgRed red) {
+__global__ __launch_bounds__(1024) void k_pcg_update(T* __restrict__ x, T* __restrict__ r,
+                                                     const T* __restrict__ p, const T* __restrict__ q,
+                                                     int ld, int n, int* __restrict__ act,
+                                                     ColState* __restrict__ st, PcgRed red) {
     const int col = blockIdx.y;
     if (!act[col]) return;
-    const double rz = partial_total(red.rz, col, red.stride, red.nrz);
-    const double pq = partial_total(red.pq, col, red.stride, red.nvec);
+    const double spq = partial_share(red.pq, col, red.stride, red.nvec);
+    const int k0 = blockIdx.x * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
+    T xk[kVecNodes], rk[kVecNodes], pk[kVecNodes], qk[kVecNodes];
+#pragma unroll
+    for (int e = 0; e < kVecNodes; ++e) {
+        const int k = k0 + e * blockDim.x + threadIdx.x;
+        const size_t o = (size_t)col * ld + k;
+        xk[e] = rk[e] = pk[e] = qk[e] = 0;
+        if (k < k1) {
+            xk[e] = x[o];
+            rk[e] = r[o];
+            pk[e] = p[o];
+            qk[e] = q[o];
+        }
+    }
+    const double rz = st[col].rz_new;
+    const double pq = share_total(spq);
     const double alpha = pq > 0.0 ? rz / pq : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ColState& c = st[col];
@@ -519,14 +630,16 @@ __global__ __launch_bounds__(256) void k_pcg_update(T* __restrict__ x, T* __rest
     }
     double rr = 0.0;
     const T a = (T)alpha;
-    for (int e = 0; e < red.per; ++e) {
-        const int k = (blockIdx.x * red.per + e) * blockDim.x + threadIdx.x;
-        if (k >= n) break;
-        const size_t o = (size_t)col * ld + k;
-        x[o] += a * p[o];
-        const T rv = r[o] - a * q[o];
-        r[o] = rv;
-        rr += (double)rv * (double)rv;
+#pragma unroll
+    for (int e = 0; e < kVecNodes; ++e) {
+        const int k = k0 + e * blockDim.x + threadIdx.x;
+        if (k < k1) {
+            const size_t o = (size_t)col * ld + k;
+            x[o] = xk[e] + a * pk[e];
+            const T rv = rk[e] - a * qk[e];
+            r[o] = rv;
+            rr += (double)rv * (double)rv;
+        }
     }
     const double s = group_sum(rr);
     if (threadIdx.x == 0) red.rr[(size_t)col * red.stride + blockIdx.x] = s;

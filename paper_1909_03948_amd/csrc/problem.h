@@ -69,7 +69,7 @@ class Problem {
     void ensure_lin_hierarchy();
 
   private:
-    static constexpr int kScratch = 8;
+    static constexpr int kScratch = 9;
     int cap_ = 0;
     DBuf<double> w_[kScratch];
     int qcap_ = 0;

@@ -231,36 +231,106 @@ __global__ void k_prior_apply(OpKA<double> op, const double* __restrict__ x, int
     yc[k] = v;
 }
 
-// One Chebyshev step for M x = b with the Jacobi-scaled spectrum in [1/2, 2]:
-// r <- r - M d, x <- x + d, dn = c1 d + c2 D^-1 r.
-__global__ void k_cheb_mass(OpKA<double> op, double* __restrict__ x, double* __restrict__ r,
-                            const double* __restrict__ d, double* __restrict__ dn, int ld,
-                            double c1, double c2) {
-    const int N1 = op.N + 1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N1 * N1) return;
-    const int i = k % N1, j = k / N1;
-    const double* dc = colp(d, ld);
-    const double Md = op.apply(i, j, k, [&](int, int, int kk) { return dc[kk]; });
-    double* rc = colp(r, ld);
-    const double rn = rc[k] - Md;
-    rc[k] = rn;
-    colp(x, ld)[k] += dc[k];
-    colp(dn, ld)[k] = c1 * dc[k] + c2 * op.inv_diag(i, j, k) * rn;
-}
+// Chebyshev iteration for M x = b with the Jacobi-scaled spectrum in [1/2, 2]
+// (x = 0, r = b, d = D^-1 b / theta; then per step r <- r - M d, x <- x + d,
+// d <- c1 d + c2 D^-1 r), kMassSteps steps per launch on LDS tiles: a
+// workgroup owns T x T nodes (T = 32, or 16 when the 32-tiles would leave
+// most of the GPU idle) and holds r and d on a halo of kMassSteps rings, so
+// step s updates the tile shrunk by s + 1 rings from values it holds.  The
+// next launch reads the other copy of r and d (the halos of a tile are owned
+// by its neighbours).
+constexpr int kMassSteps = 8;
+struct MassSteps {
+    double c1[kMassSteps], c2[kMassSteps];
+};
 
-// x = 0, r = b, d = D^-1 b / theta.
-__global__ void k_cheb_mass_init(OpKA<double> op, const double* __restrict__ b, int ldb,
-                                 double* __restrict__ x, double* __restrict__ r,
-                                 double* __restrict__ d, int ld, double inv_theta) {
-    const int N1 = op.N + 1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N1 * N1) return;
-    const int i = k % N1, j = k / N1;
-    const double bv = colp(b, ldb)[k];
-    colp(x, ld)[k] = 0.0;
-    colp(r, ld)[k] = bv;
-    colp(d, ld)[k] = op.inv_diag(i, j, k) * bv * inv_theta;
+template <int T>
+__global__ __launch_bounds__(256) void k_cheb_mass(OpKA<double> op, const double* __restrict__ b, int ldb,
+                                                   double* __restrict__ x, const double* __restrict__ r_in,
+                                                   const double* __restrict__ d_in, double* __restrict__ r_out,
+                                                   double* __restrict__ d_out, int ld, MassSteps cs, int first,
+                                                   double inv_theta) {
+    constexpr int H = kMassSteps, W = T + 2 * H, NN = W * W, E = (NN + 255) / 256;
+    constexpr int OWN = (T * T + 255) / 256;
+    __shared__ double sr[NN], sd[NN];
+    const int N = op.N, N1 = N + 1;
+    const int ox = blockIdx.x * T - H, oy = blockIdx.y * T - H;  // node of local (0, 0)
+    const size_t co = (size_t)blockIdx.z * ld;
+    // loads first (r and d, or b on the first launch; x of the owned nodes)
+    double vr[E], vd[E], vx[OWN];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + 256 * e;
+        const int i = ox + t % W, j = oy + t / W;
+        const bool in = t < NN && i >= 0 && i <= N && j >= 0 && j <= N;
+        const int k = j * N1 + i;
+        vr[e] = vd[e] = 0.0;
+        if (in) {
+            if (first) {
+                const double bv = b[(size_t)blockIdx.z * ldb + k];
+                vr[e] = bv;
+                vd[e] = op.inv_diag(i, j, k) * bv * inv_theta;
+            } else {
+                vr[e] = r_in[co + k];
+                vd[e] = d_in[co + k];
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) {
+        const int t = threadIdx.x + 256 * o;
+        const int i = ox + H + t % T, j = oy + H + t / T;
+        vx[o] = (!first && t < T * T && i <= N && j <= N) ? x[co + j * N1 + i] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + 256 * e;
+        if (t < NN) {
+            sr[t] = vr[e];
+            sd[t] = vd[e];
+        }
+    }
+    __syncthreads();
+    for (int st = 0; st < H; ++st) {
+        const int lo = st + 1, w = W - 2 * lo;  // region [lo, W - lo)^2
+        // r <- r - M d on the region (each r read and written by one thread);
+        // x <- x + d on the owned nodes, before d changes
+        for (int t = threadIdx.x; t < w * w; t += 256) {
+            const int li = lo + t % w, lj = lo + t / w, i = ox + li, j = oy + lj;
+            if (i < 0 || i > N || j < 0 || j > N) continue;
+            const int l = lj * W + li;
+            const double Md = op.apply(i, j, j * N1 + i, [&](int ii, int jj, int) {
+                return sd[(jj - oy) * W + (ii - ox)];
+            });
+            sr[l] = sr[l] - Md;
+        }
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            const int t = threadIdx.x + 256 * o;
+            if (t < T * T) vx[o] += sd[(H + t / T) * W + H + t % T];
+        }
+        __syncthreads();
+        const double c1 = cs.c1[st], c2 = cs.c2[st];
+        for (int t = threadIdx.x; t < w * w; t += 256) {
+            const int li = lo + t % w, lj = lo + t / w, i = ox + li, j = oy + lj;
+            if (i < 0 || i > N || j < 0 || j > N) continue;
+            const int l = lj * W + li;
+            sd[l] = c1 * sd[l] + c2 * op.inv_diag(i, j, j * N1 + i) * sr[l];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) {
+        const int t = threadIdx.x + 256 * o;
+        const int i = ox + H + t % T, j = oy + H + t / T;
+        if (t < T * T && i <= N && j <= N) {
+            const int l = (H + t / T) * W + H + t % T;
+            const size_t k = co + j * N1 + i;
+            x[k] = vx[o];
+            r_out[k] = sr[l];
+            d_out[k] = sd[l];
+        }
+    }
 }
 
 __global__ void k_add_scalar(int n, double v, double* __restrict__ x, int ld) {
@@ -349,6 +419,7 @@ OpKA<double> prior_op(int N, double g, double dl, double bt) {
 
 // Chebyshev iteration count for M: error factor 2 (1/3)^K <= 2e-15.
 constexpr int kMassCheb = 32;
+static_assert(kMassCheb % kMassSteps == 0, "mass Chebyshev steps come in whole launches");
 
 }  // namespace
 
@@ -627,20 +698,29 @@ void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx) {
     const OpKA<double> M = prior_op(N, 0.0, 1.0, 0.0);
     const double lo = 0.5, hi = 2.0;
     const double theta = 0.5 * (hi + lo), dl = 0.5 * (hi - lo), sigma1 = theta / dl;
-    double* r = scratch(5, nc);
-    double* d0 = scratch(6, nc);
-    double* d1 = scratch(7, nc);
-    const dim3 g = grid2(n, nc);
+    double* r[2] = {scratch(5, nc), scratch(8, nc)};
+    double* d[2] = {scratch(6, nc), scratch(7, nc)};
     if (ldx != n) fail(HINV_EINVAL, "mass_solve needs a packed output");
-    k_cheb_mass_init<<<g, kBlock, 0, s>>>(M, b, ldb, x, r, d0, n, 1.0 / theta);
-    HINV_LAUNCH_CHECK();
+    if (nc > 65535) fail(HINV_EINVAL, "mass_solve: at most 65535 columns per call");
+    const bool small = (long long)ceil_div(N + 1, 32) * ceil_div(N + 1, 32) * nc < 512;
+    const int tiles = ceil_div(N + 1, small ? 16 : 32);
     double rho = 1.0 / sigma1;
-    for (int it = 0; it < kMassCheb; ++it) {
-        const double rho_n = 1.0 / (2.0 * sigma1 - rho);
-        k_cheb_mass<<<g, kBlock, 0, s>>>(M, x, r, d0, d1, n, rho_n * rho, 2.0 * rho_n / dl);
+    for (int launch = 0; launch < kMassCheb / kMassSteps; ++launch) {
+        MassSteps cs;
+        for (int st = 0; st < kMassSteps; ++st) {
+            const double rho_n = 1.0 / (2.0 * sigma1 - rho);
+            cs.c1[st] = rho_n * rho;
+            cs.c2[st] = 2.0 * rho_n / dl;
+            rho = rho_n;
+        }
+        const int in = launch & 1;
+        if (small)
+            k_cheb_mass<16><<<dim3(tiles, tiles, nc), 256, 0, s>>>(M, b, ldb, x, r[in], d[in], r[1 - in],
+                                                                   d[1 - in], n, cs, launch == 0, 1.0 / theta);
+        else
+            k_cheb_mass<32><<<dim3(tiles, tiles, nc), 256, 0, s>>>(M, b, ldb, x, r[in], d[in], r[1 - in],
+                                                                   d[1 - in], n, cs, launch == 0, 1.0 / theta);
         HINV_LAUNCH_CHECK();
-        std::swap(d0, d1);
-        rho = rho_n;
     }
 }
 

@@ -45,6 +45,7 @@ struct PcgWork {
 struct ColState {
     double bb;   // |b|^2 of the inner problem
     double rz, pq, rr, tol2, alpha, beta;
+    double rz_new;  // r^T z of the current iteration, summed once by the PCG apply kernel
     double obb;  // |b|^2 of the outer (FP64) problem
 };
 
@@ -87,6 +88,10 @@ class Hierarchy {
     void pcg_iteration(int nc, int cur, int first);
     template <typename T>
     hipGraphExec_t pcg_graph(int nc);
+    template <typename T>
+    hipGraphExec_t prologue_graph(int nc);
+    template <typename T>
+    hipGraphExec_t capture(int nc, bool prologue);
     void drop_graphs();
     template <typename T>
     void vcycle(int nc, int check);
@@ -101,11 +106,14 @@ class Hierarchy {
     // workgroup of the PCG vector kernels.  Chosen by timing on the first call of each
     // (column count, precision); HINV_AUTOTUNE=0 uses the fixed rule instead.
     struct LaunchShape {
-        bool small;
+        bool small;         // small tiles on every level
+        int small_max = 0;  // otherwise small tiles on the levels with N_l <= small_max
         int per;
         int cb;  // columns per workgroup of the V-cycle kernels
     };
+    bool small_tiles(int l) const { return shape_.small || lev_[l]->N <= shape_.small_max; }
     LaunchShape default_shape(int nc) const;
+    int min_per() const;
     template <typename T>
     void tune_shape(int nc);
     void build_coarse(int inst);
@@ -145,6 +153,9 @@ class Hierarchy {
     hipStream_t launch_stream_ = nullptr;  // stream the PCG kernels go to (capture or caller)
     hipGraphExec_t gexec_[2] = {nullptr, nullptr};  // FP64 / FP32 two-iteration graphs
     int gexec_nc_[2] = {0, 0};
+    hipGraphExec_t gpro_[2] = {nullptr, nullptr};   // FP64 / FP32 prologue graphs (V-cycle, first iteration)
+    int gpro_nc_[2] = {0, 0};
+    long solves_ = 0;  // inner solves so far (every 16th runs its prologue eagerly while timing)
     PcgWork<double> w64_;
     PcgWork<float> w32_;
 };
