@@ -20,7 +20,7 @@ constexpr int kTCBig = 16, kTFBig = 32;      // coarse / fine nodes per tile sid
 constexpr int kTCSmall = 8, kTFSmall = 16;
 constexpr int kSmallTileCols = 8;            // batches below this use the small tiles
 constexpr int kBottomN = 32;   // levels with N_l <= kBottomN run in the bottom kernel
-constexpr int kBottomNodes = 33 * 33 + 17 * 17 + 9 * 9;  // vector length of all bottom levels
+constexpr int kBottomNodes = 33 * 33 + 17 * 17 + 9 * 9;  // nodes of all bottom levels
 constexpr int kBottomLevels = 3;
 
 // Chebyshev degree-2 coefficients passed to the smoothing kernels.
@@ -317,70 +317,79 @@ struct BottomArgs {
     const KARow<T>* karows[kBottomLevels];
 };
 
-template <typename T, int KIND>
-__device__ inline auto bottom_op(const BottomArgs<T>& a, int l, const KARow<T>* lds_rows,
-                                 const T* cwE, const T* cwN, const T* cdinv, int off) {
-    if constexpr (KIND == kOpState) {
-        OpA<T> o;  // coefficients staged in LDS
-        o.N = a.N[l];
-        o.wE = cwE + off;
-        o.wN = cwN + off;
-        o.dinv = cdinv + off;
-        return o;
-    } else {
-        OpKARef<T> o;
-        o.N = a.N[l];
-        o.rows = lds_rows + 9 * l;
-        return o;
-    }
-}
+// Bottom levels in LDS with a ring of zeros around each level (padded width
+// P_l = N_l + 3): the tile stencil applies without boundary branches, and
+// Dirichlet rows are masked by their zero inverse diagonal.
+constexpr int kBottomPadded = 35 * 35 + 19 * 19 + 11 * 11;
+
+// q / d for 0 <= q < 2^16 and 1 <= d <= 64 by a float reciprocal: (q + 1/2) / d
+// lies at least 1 / (2 d) from an integer and the float product errs by less
+// than 2^-20 (q / d), so the truncation is exact (integer division is a long
+// instruction sequence on the vector ALU).
+__device__ inline int small_div(int q, float inv_d) { return (int)(((float)q + 0.5f) * inv_d); }
 
 // x_top = V-cycle(b_top) for every column (blockIdx.x = column).  b and x are
 // global level-Lb vectors.  When rv is given (the bottom is the whole
 // hierarchy), sum_k rv_k x_k is written as the single partial of r^T z.
+// Each thread keeps, per level, the padded positions of its nodes (node
+// q = threadIdx.x + 1024 s of the level), the fine position under a coarse
+// node and the two coarse ends used by the prolongation.
 template <typename T, int KIND>
 __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg,
                                                  int ld, int* __restrict__ act, ChebCoef cc,
                                                  const T* __restrict__ rv, PcgRed red,
                                                  ColState* __restrict__ st, int check) {
+    constexpr bool NE = KIND == kOpPrior;
+    constexpr int PN = kBottomPadded, NT = 1024, NS = 2, LV = kBottomLevels;
     const int col = blockIdx.x;
     if (act && !act[col]) return;
     if (check && column_done(red, col, st, act, true)) return;
-    __shared__ T sb[kBottomNodes], sx[kBottomNodes], st_[kBottomNodes];
-    // state-operator coefficients of every bottom level (the prior needs only rows)
-    __shared__ T cwE[KIND == kOpState ? kBottomNodes : 1], cwN[KIND == kOpState ? kBottomNodes : 1],
-        cdinv[KIND == kOpState ? kBottomNodes : 1];
-    __shared__ KARow<T> rows[kBottomLevels * 9];
+    __shared__ T sb[PN], sx[PN], sw[PN];  // right-hand side, iterate, work vector
+    __shared__ T tc[PN], te[PN], tn[PN], tdv[PN], tg[NE ? PN : 1];
+    __shared__ KARow<T> rows[LV * 9];
     const int inst = a.cpi ? col / a.cpi : 0;
-    if (KIND == kOpPrior)
-        for (int t = threadIdx.x; t < a.nlev * 9; t += blockDim.x)
-            rows[t] = a.cpi ? a.karows[t / 9][9 * inst + t % 9] : a.ka[t / 9][t % 9];
-    int off[kBottomLevels + 1];
+    const int L = a.nlev - 1;  // the coarsest level, solved with its dense inverse
+    int Nl[LV], Pl[LV], po[LV], uo[LV + 1];
     {
-        int o = 0;
-        for (int l = 0; l < kBottomLevels; ++l) {
-            off[l] = o;
-            if (l < a.nlev) o += (a.N[l] + 1) * (a.N[l] + 1);
+        int p = 0, u = 0;
+#pragma unroll
+        for (int l = 0; l < LV; ++l) {
+            const int n = l < a.nlev ? a.N[l] : 0;
+            Nl[l] = n;
+            Pl[l] = n + 3;
+            po[l] = p;
+            uo[l] = u;
+            if (l < a.nlev) {
+                p += (n + 3) * (n + 3);
+                u += (n + 1) * (n + 1);
+            }
         }
-        off[kBottomLevels] = o;
+        uo[LV] = u;
     }
-    const int n0 = (a.N[0] + 1) * (a.N[0] + 1);
-    // Every global load is issued before the first LDS store: b, the state
-    // coefficients of the bottom levels (all levels concatenated, node t of
-    // the concatenation), and this thread's part of the dense coarse inverse
-    // (row t / S, entries t % S, t % S + S, ...; at most kCU of them).
-    constexpr int EB = (kBottomNodes + 1023) / 1024, S = 12, kCU = 8;
+    const int n0 = uo[1];
+    // ---- loads: b, the state coefficients (unpadded concatenation of the
+    // levels), this thread's part of the dense coarse inverse
+    constexpr int EB = (kBottomNodes + NT - 1) / NT, S = 12, kCU = 8;
     T vb[EB], vE[EB], vN[EB], vD[EB];
+    int vp[EB], vlev[EB], vi[EB], vj[EB];
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-        const int t = threadIdx.x + 1024 * e;
+        const int t = threadIdx.x + NT * e;
+        const int l = (t >= uo[1]) + (t >= uo[2]);
+        const bool in = t < uo[LV];
+        const int q = t - (l == 0 ? 0 : (l == 1 ? uo[1] : uo[2]));
+        const int N1 = (l == 0 ? Nl[0] : (l == 1 ? Nl[1] : Nl[2])) + 1;
+        const int j = small_div(q, 1.0f / (float)N1);
+        const int P = N1 + 2, i = q - j * N1;
+        vlev[e] = l;
+        vi[e] = i;
+        vj[e] = j;
+        vp[e] = in ? (l == 0 ? po[0] : (l == 1 ? po[1] : po[2])) + (j + 1) * P + i + 1 : -1;
         vb[e] = t < n0 ? bg[(size_t)col * ld + t] : (T)0;
+        vE[e] = vN[e] = vD[e] = 0;
         if constexpr (KIND == kOpState) {
-            const int l = (t >= off[1]) + (t >= off[2]);
-            const bool in = t < off[kBottomLevels];
             const long long cs = l == 0 ? a.cs[0] : (l == 1 ? a.cs[1] : a.cs[2]);
-            const int ol = l == 0 ? 0 : (l == 1 ? off[1] : off[2]);
-            const long long at = (a.cpi ? inst * cs : 0) + (t - ol);
+            const long long at = (a.cpi ? inst * cs : 0) + q;
             const T* pE = l == 0 ? a.wE[0] : (l == 1 ? a.wE[1] : a.wE[2]);
             const T* pN = l == 0 ? a.wN[0] : (l == 1 ? a.wN[1] : a.wN[2]);
             const T* pD = l == 0 ? a.dinv[0] : (l == 1 ? a.dinv[1] : a.dinv[2]);
@@ -397,139 +406,190 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
         const int c = cpart + u * S;
         cv[u] = (cr < a.nc && c < a.nc) ? ci[cr * a.nc + c] : (T)0;
     }
+    // ---- per-thread geometry: node positions, restriction and prolongation
+    int pi[LV][NS], fi[LV][NS], ca0[LV][NS], ca1[LV][NS];
+    bool ev[LV][NS];
+#pragma unroll
+    for (int l = 0; l < LV; ++l)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int q = threadIdx.x + NT * s;
+            const int N1 = Nl[l] + 1, P = Pl[l];
+            const bool in = l < a.nlev && q < N1 * N1;
+            const int jq = small_div(q, 1.0f / (float)N1);
+            const int i = in ? q - jq * N1 : 0, j = in ? jq : 0;
+            pi[l][s] = in ? po[l] + (j + 1) * P + i + 1 : -1;
+            fi[l][s] = (in && l > 0) ? po[l - 1] + (2 * j + 1) * Pl[l - 1] + 2 * i + 1 : -1;
+            if (l + 1 < LV) {
+                const int I = i >> 1, J = j >> 1, Pc = Pl[l + 1];
+                ca0[l][s] = po[l + 1] + (J + 1) * Pc + I + 1;
+                ca1[l][s] = po[l + 1] + (J + 1 + (j & 1)) * Pc + I + 1 + (i & 1);
+                ev[l][s] = !((i | j) & 1);
+            } else {
+                ca0[l][s] = ca1[l][s] = 0;
+                ev[l][s] = true;
+            }
+        }
+    // ---- LDS: zeros everywhere (the rings stay zero), then the interiors
+    if constexpr (KIND == kOpPrior)
+        for (int t = threadIdx.x; t < a.nlev * 9; t += NT)
+            rows[t] = a.cpi ? a.karows[t / 9][9 * inst + t % 9] : a.ka[t / 9][t % 9];
+    for (int q = threadIdx.x; q < PN; q += NT) {
+        sb[q] = sx[q] = sw[q] = tc[q] = te[q] = tn[q] = tdv[q] = (T)0;
+        if constexpr (NE) tg[q] = (T)0;
+    }
+    __syncthreads();
+    const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cA = (T)cc.cA, cB = (T)cc.cB, c1 = (T)cc.c1;
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-        const int t = threadIdx.x + 1024 * e;
-        if (t < n0) sb[t] = vb[e];
-        if constexpr (KIND == kOpState)
-            if (t < off[kBottomLevels]) {
-                cwE[t] = vE[e];
-                cwN[t] = vN[e];
-                cdinv[t] = vD[e];
-            }
+        const int p = vp[e];
+        if (p < 0) continue;
+        if constexpr (KIND == kOpState) {
+            te[p] = -vE[e];
+            tn[p] = -vN[e];
+            tdv[p] = vD[e];
+        } else {
+            const int l = vlev[e];
+            const KARow<T>& r = rows[9 * l + ka_class(vi[e], vj[e], l == 0 ? Nl[0] : (l == 1 ? Nl[1] : Nl[2]))];
+            tc[p] = r.c;
+            te[p] = r.e;
+            tn[p] = r.n;
+            tg[p] = r.ne;
+            tdv[p] = r.dinv;
+            vD[e] = r.dinv;
+        }
+        if (threadIdx.x + NT * e < n0) {
+            sb[p] = vb[e];
+            sw[p] = vD[e] * vb[e] * inv_theta;  // d0 of the first smoothing step
+        }
     }
-    const int dir = KIND == kOpState;
-    const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cA = (T)cc.cA, cB = (T)cc.cB, c1 = (T)cc.c1;
+    if constexpr (KIND == kOpState) {
+        __syncthreads();
+        // diagonal: the sum of the four incident edge weights
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int p = vp[e];
+            if (p < 0) continue;
+            const int P = (vlev[e] == 0 ? Pl[0] : (vlev[e] == 1 ? Pl[1] : Pl[2]));
+            tc[p] = -(te[p] + te[p - 1] + tn[p] + tn[p - P]);
+        }
+    }
     __syncthreads();
-    const int L = a.nlev - 1;
     // ---- down
-    for (int l = 0; l < L; ++l) {
-        const auto op = bottom_op<T, KIND>(a, l, rows, cwE, cwN, cdinv, off[l]);
-        const int N = a.N[l], N1 = N + 1, n = N1 * N1;
-        T* b = sb + off[l];
-        T* x = sx + off[l];
-        T* t = st_ + off[l];
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            const int i = k % N1, j = k / N1;
-            T v = 0;
-            if (op.is_free(i, j)) {
-                auto d0 = [&](int ii, int jj, int kk) { return op.inv_diag(ii, jj, kk) * b[kk] * inv_theta; };
-                const T dk = d0(i, j, k);
-                v = cA * dk + cB * op.inv_diag(i, j, k) * (b[k] - op.apply(i, j, k, d0));
-            }
-            x[k] = v;
+#pragma unroll
+    for (int l = 0; l < LV - 1; ++l) {
+        if (l >= L) break;
+        const int P = Pl[l];
+        const TileStencil<T> ts{tc, te, tn, tg, tdv};
+        // x2 = cA d0 + cB D^-1 (b - A d0), d0 in sw
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int p = pi[l][s];
+            if (p >= 0) sx[p] = cA * sw[p] + cB * tdv[p] * (sb[p] - tile_apply<NE>(ts, P, p, sw));
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            const int i = k % N1, j = k / N1;
-            T v = 0;
-            if (op.is_free(i, j)) v = b[k] - op.apply(i, j, k, [&](int, int, int kk) { return x[kk]; });
-            t[k] = v;
+        // residual b - A x2 on the free nodes, into sw
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int p = pi[l][s];
+            if (p >= 0) {
+                const T v = sb[p] - tile_apply<NE>(ts, P, p, sx);
+                sw[p] = tdv[p] != (T)0 ? v : (T)0;
+            }
         }
         __syncthreads();
-        const int Nc = N / 2, Nc1 = Nc + 1;
-        T* bcn = sb + off[l + 1];
-        for (int K = threadIdx.x; K < Nc1 * Nc1; K += blockDim.x) {
-            const int I = K % Nc1, J = K / Nc1;
+        // restriction P^T to level l + 1, and its first smoothing correction d0
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int pc = pi[l + 1][s];
+            if (pc < 0) continue;
+            const int f = fi[l + 1][s];
             T v = 0;
-            if (!(dir && (J == 0 || J == Nc))) {
-                const int i = 2 * I, j = 2 * J, k = j * N1 + i;
-                T s = 0;
-                if (i > 0) s += t[k - 1];
-                if (i < N) s += t[k + 1];
-                if (j > 0) s += t[k - N1];
-                if (j < N) s += t[k + N1];
-                if (i < N && j < N) s += t[k + N1 + 1];
-                if (i > 0 && j > 0) s += t[k - N1 - 1];
-                v = t[k] + (T)0.5 * s;
-            }
-            bcn[K] = v;
+            if (tdv[pc] != (T)0)
+                v = sw[f] + (T)0.5 * (sw[f - 1] + sw[f + 1] + sw[f - P] + sw[f + P] + sw[f + P + 1] + sw[f - P - 1]);
+            sb[pc] = v;
+            sw[pc] = tdv[pc] * v * inv_theta;
         }
         __syncthreads();
     }
     // ---- coarsest: dense inverse, S threads per row (entries prefetched in cv)
     {
-        const T* b = sb + off[L];
-        T* x = sx + off[L];
-        T* tmp = st_;  // level-0 scratch is free here
+        const int N1 = (L == 0 ? Nl[0] : (L == 1 ? Nl[1] : Nl[2])) + 1;
+        const int P = N1 + 2, o = L == 0 ? po[0] : (L == 1 ? po[1] : po[2]);
+        T* tmp = sw;  // the work vector is free here (the dense solve reads b only); 12 * 81 <= PN
+        const float inv_n1 = 1.0f / (float)N1;
         if (cr < a.nc) {
             T s = 0;
+            // entry c = cpart + u S at (c mod N1, c / N1), stepped without dividing
+            int jc = small_div(cpart, inv_n1), ic = cpart - jc * N1;
 #pragma unroll
             for (int u = 0; u < kCU; ++u) {
                 const int c = cpart + u * S;
-                if (c < a.nc) s += cv[u] * b[c];
+                if (c < a.nc) s += cv[u] * sb[o + (jc + 1) * P + ic + 1];
+                ic += S;
+                while (ic >= N1) {
+                    ic -= N1;
+                    ++jc;
+                }
             }
             tmp[threadIdx.x] = s;
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < a.nc; r += blockDim.x) {
+        for (int r = threadIdx.x; r < a.nc; r += NT) {
             T s = 0;
             for (int part = 0; part < S; ++part) s += tmp[r * S + part];
-            x[r] = s;
+            const int jr = small_div(r, inv_n1);
+            sx[o + (jr + 1) * P + r - jr * N1 + 1] = s;
         }
         __syncthreads();
     }
     // ---- up
-    for (int l = L - 1; l >= 0; --l) {
-        const auto op = bottom_op<T, KIND>(a, l, rows, cwE, cwN, cdinv, off[l]);
-        const int N = a.N[l], N1 = N + 1, n = N1 * N1, Nc1 = N / 2 + 1;
-        T* b = sb + off[l];
-        T* x = sx + off[l];
-        T* t = st_ + off[l];
-        const T* c = sx + off[l + 1];
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            const int i = k % N1, j = k / N1;
-            if (dir && (j == 0 || j == N)) continue;
-            const int I = i >> 1, J = j >> 1;
-            T p;
-            if (!(i & 1) && !(j & 1))
-                p = c[J * Nc1 + I];
-            else if (!(j & 1))
-                p = (T)0.5 * (c[J * Nc1 + I] + c[J * Nc1 + I + 1]);
-            else if (!(i & 1))
-                p = (T)0.5 * (c[J * Nc1 + I] + c[(J + 1) * Nc1 + I]);
-            else
-                p = (T)0.5 * (c[J * Nc1 + I] + c[(J + 1) * Nc1 + I + 1]);
-            x[k] += p;
+#pragma unroll
+    for (int l = LV - 2; l >= 0; --l) {
+        if (l >= L) continue;
+        const int P = Pl[l];
+        const TileStencil<T> ts{tc, te, tn, tg, tdv};
+        // x += P x_coarse on the free nodes
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int p = pi[l][s];
+            if (p >= 0 && tdv[p] != (T)0)
+                sx[p] += ev[l][s] ? sx[ca0[l][s]] : (T)0.5 * (sx[ca0[l][s]] + sx[ca1[l][s]]);
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            const int i = k % N1, j = k / N1;
-            T d = 0;
-            if (op.is_free(i, j))
-                d = op.inv_diag(i, j, k) * (b[k] - op.apply(i, j, k, [&](int, int, int kk) { return x[kk]; })) * inv_theta;
-            t[k] = d;
+        // d0 = D^-1 (b - A x) / theta
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int p = pi[l][s];
+            if (p >= 0) sw[p] = tdv[p] * (sb[p] - tile_apply<NE>(ts, P, p, sx)) * inv_theta;
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            const int i = k % N1, j = k / N1;
-            if (!op.is_free(i, j)) continue;
-            const T dk = t[k];
-            const T di = op.inv_diag(i, j, k);
-            const T r1 = theta * dk * op.diag(i, j, k) - op.apply(i, j, k, [&](int, int, int kk) { return t[kk]; });
-            x[k] += ((T)1 + c1) * dk + cB * di * r1;
+        // x += (1 + c1) d0 + cB D^-1 r1 with r1 = theta D d0 - A d0
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int p = pi[l][s];
+            if (p >= 0) {
+                const T dk = sw[p];
+                const T r1 = theta * dk * tc[p] - tile_apply<NE>(ts, P, p, sw);
+                sx[p] += ((T)1 + c1) * dk + cB * tdv[p] * r1;
+            }
         }
         __syncthreads();
     }
     double dot = 0.0;
-    for (int k = threadIdx.x; k < n0; k += blockDim.x) {
-        const T v = sx[k];
-        xg[(size_t)col * ld + k] = v;
-        if (rv) dot += (double)v * (double)rv[(size_t)col * ld + k];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int q = threadIdx.x + NT * s;
+        const int p = pi[0][s];
+        if (p >= 0) {
+            const T v = sx[p];
+            xg[(size_t)col * ld + q] = v;
+            if (rv) dot += (double)v * (double)rv[(size_t)col * ld + q];
+        }
     }
     if (rv) {
-        const double s = group_sum(dot);
-        if (threadIdx.x == 0) red.rz[(size_t)col * red.stride] = s;
+        const double sm = group_sum(dot);
+        if (threadIdx.x == 0) red.rz[(size_t)col * red.stride] = sm;
     }
 }
 

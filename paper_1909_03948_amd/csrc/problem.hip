@@ -292,17 +292,20 @@ __global__ __launch_bounds__(256) void k_cheb_mass(OpKA<double> op, const double
     }
     __syncthreads();
     for (int st = 0; st < H; ++st) {
-        const int lo = st + 1, w = W - 2 * lo;  // region [lo, W - lo)^2
+        const int lo = st + 1, hi = W - lo;  // region [lo, hi)^2
         // r <- r - M d on the region (each r read and written by one thread);
-        // x <- x + d on the owned nodes, before d changes
-        for (int t = threadIdx.x; t < w * w; t += 256) {
-            const int li = lo + t % w, lj = lo + t / w, i = ox + li, j = oy + lj;
+        // x <- x + d on the owned nodes, before d changes.  The loops walk the
+        // whole tile (compile-time width) and skip what lies outside.
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + 256 * e;
+            const int li = t % W, lj = t / W, i = ox + li, j = oy + lj;
+            if (t >= NN || li < lo || li >= hi || lj < lo || lj >= hi) continue;
             if (i < 0 || i > N || j < 0 || j > N) continue;
-            const int l = lj * W + li;
             const double Md = op.apply(i, j, j * N1 + i, [&](int ii, int jj, int) {
                 return sd[(jj - oy) * W + (ii - ox)];
             });
-            sr[l] = sr[l] - Md;
+            sr[t] = sr[t] - Md;
         }
 #pragma unroll
         for (int o = 0; o < OWN; ++o) {
@@ -311,11 +314,13 @@ __global__ __launch_bounds__(256) void k_cheb_mass(OpKA<double> op, const double
         }
         __syncthreads();
         const double c1 = cs.c1[st], c2 = cs.c2[st];
-        for (int t = threadIdx.x; t < w * w; t += 256) {
-            const int li = lo + t % w, lj = lo + t / w, i = ox + li, j = oy + lj;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + 256 * e;
+            const int li = t % W, lj = t / W, i = ox + li, j = oy + lj;
+            if (t >= NN || li < lo || li >= hi || lj < lo || lj >= hi) continue;
             if (i < 0 || i > N || j < 0 || j > N) continue;
-            const int l = lj * W + li;
-            sd[l] = c1 * sd[l] + c2 * op.inv_diag(i, j, j * N1 + i) * sr[l];
+            sd[t] = c1 * sd[t] + c2 * op.inv_diag(i, j, j * N1 + i) * sr[t];
         }
         __syncthreads();
     }
