@@ -686,6 +686,7 @@ __global__ __launch_bounds__(1024) void k_pcg_update(T* __restrict__ x, T* __res
         c.rz = rz;
         c.pq = pq;
         c.alpha = alpha;
+        c.its += 1.0;
         if (!(pq > 0.0)) act[col] = 0;
     }
     double rr = 0.0;

@@ -47,6 +47,7 @@ struct ColState {
     double rz, pq, rr, tol2, alpha, beta;
     double rz_new;  // r^T z of the current iteration, summed once by the PCG apply kernel
     double obb;  // |b|^2 of the outer (FP64) problem
+    double its;  // PCG iterations this column has taken in the current inner solve
 };
 
 // A hierarchy may stack ninst instances of one mesh size (their own state

@@ -310,7 +310,10 @@ __global__ void k_fill_int(int n, int v, int* __restrict__ a) {
 
 __global__ void k_bb_init(ColState* st, int nc) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < nc) st[c].bb = 1.0;
+    if (c < nc) {
+        st[c].bb = 1.0;
+        st[c].its = 0.0;
+    }
 }
 
 // State operator of level L for instance inst alone.
@@ -1001,20 +1004,21 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
         }
         ctx_->timer.force = false;
     }
-    // Replays before the first completion check follow an estimate of the
-    // iteration count kept per shape (kernels of finished columns return at
-    // once, so a late check costs launches, not work).  The estimate must not
-    // grow from the iterations replayed past convergence: when the first
-    // check already finds every column done, the next call checks two
-    // iterations earlier; at most 12 iterations run between checks.
+    // Replays before the first completion check follow the iteration count of
+    // the last solve of this shape: the columns count their own iterations in
+    // the column state, so the estimate is the slowest column's count, not the
+    // replays (kernels of finished columns return at once, so a late check
+    // costs launches, not work).  At most 12 iterations run before the first
+    // check, 2 between later ones.
     const long long key = 2LL * nc + (sizeof(T) == 4);
     int expect = 0;
     for (const auto& kv : last_iters_)
         if (kv.first == key) expect = kv.second;
-    bool first_check = true, done_at_first = false;
+    bool first_check = true;
+    std::vector<ColState> hst(nc);
     while (it < max_iter) {
         int reps = 1;
-        if (first_check && expect - 1 > it + 2) reps = std::min(6, (expect - 1 - it) / 2);
+        if (first_check && expect > it + 2) reps = std::min(6, (expect - it + 1) / 2);
         while (reps > 0 && it + 2 * reps > max_iter) --reps;
         if (graphs && reps > 0) {
             for (int rep = 0; rep < reps; ++rep) HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
@@ -1030,24 +1034,24 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
         }
         if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
         HINV_HIP(hipMemcpyAsync(host_flags_, act, sizeof(int) * nc, hipMemcpyDeviceToHost, s));
+        HINV_HIP(hipMemcpyAsync(hst.data(), st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
         HINV_HIP(hipStreamSynchronize(s));
+        first_check = false;
         int live = 0;
         for (int c = 0; c < nc; ++c) live += host_flags_[c];
-        if (!live) {
-            done_at_first = first_check;
-            break;
-        }
-        first_check = false;
+        if (!live) break;
     }
-    *iters += it;
-    const int next = done_at_first ? std::max(1, it - 2) : it;
+    int taken = 0;
+    for (int c = 0; c < nc; ++c) taken = std::max(taken, (int)hst[c].its);
+    if (first_check) taken = it;  // no completion check ran
+    *iters += taken;
     bool found = false;
     for (auto& kv : last_iters_)
         if (kv.first == key) {
-            kv.second = next;
+            kv.second = taken;
             found = true;
         }
-    if (!found) last_iters_.push_back({key, next});
+    if (!found) last_iters_.push_back({key, taken});
 }
 
 void Hierarchy::apply(int nc, const double* x, int ldx, double* y, int ldy) {
