@@ -123,18 +123,35 @@ __device__ inline T ka_apply(const KARow<T>& r, int N, int i, int j, int k, F xa
     return acc;
 }
 
-// Row tables travel by value (kernel arguments, constant-indexed per class).
+// Row tables travel by value (kernel arguments).  Interior nodes (class 0,
+// all but the boundary) read row 0 at a constant index, which the compiler
+// keeps in scalar registers; only boundary nodes index the table per lane.
 template <typename T>
 struct OpKA {
     int N;
     KARow<T> rows[9];
     __device__ const OpKA& at(int) const { return *this; }
     __device__ bool is_free(int, int) const { return true; }
-    __device__ T inv_diag(int i, int j, int) const { return rows[ka_class(i, j, N)].dinv; }
-    __device__ T diag(int i, int j, int) const { return rows[ka_class(i, j, N)].c; }
+    __device__ T inv_diag(int i, int j, int) const {
+        const int c = ka_class(i, j, N);
+        return c == 0 ? rows[0].dinv : rows[c].dinv;
+    }
+    __device__ T diag(int i, int j, int) const {
+        const int c = ka_class(i, j, N);
+        return c == 0 ? rows[0].c : rows[c].c;
+    }
     template <class F>
     __device__ T apply(int i, int j, int k, F xat) const {
-        return ka_apply(rows[ka_class(i, j, N)], N, i, j, k, xat);
+        const int c = ka_class(i, j, N);
+        if (c == 0) {
+            // interior: all six neighbours exist
+            const int N1 = N + 1;
+            const KARow<T>& r = rows[0];
+            return r.c * xat(i, j, k) + r.e * xat(i + 1, j, k + 1) + r.w * xat(i - 1, j, k - 1) +
+                   r.n * xat(i, j + 1, k + N1) + r.s * xat(i, j - 1, k - N1) +
+                   r.ne * xat(i + 1, j + 1, k + N1 + 1) + r.sw * xat(i - 1, j - 1, k - N1 - 1);
+        }
+        return ka_apply(rows[c], N, i, j, k, xat);
     }
 };
 
