@@ -162,7 +162,7 @@ def cpu_baseline(cfg, workload, budget_s=20.0):
                                           synth.obs_noise(q))
     u = prob.forward(m_true)
     p = prob.adjoint(m_true, u)
-    dirs = synth.test_vectors(prob.n, 64, stream=synth.STREAM_OMEGA)
+    dirs = synth.test_vectors(prob.n, 160, stream=synth.STREAM_OMEGA)
     prob.hessian_apply(m_true, u, p, dirs[0], model.HESS_MISFIT)  # factorization outside timing
     count, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < budget_s and count < len(dirs):

@@ -66,10 +66,11 @@ struct DBuf {
 };
 
 // Sampled kernel timing: while a class is enabled, every `period`-th eagerly
-// launched kernel of it (every one while `force` is set) carries an event pair
-// in its own dispatch (hipExtLaunchKernelGGL), so the pair brackets the
-// kernel's execution alone, and the algorithmic bytes (or flops) of that
-// launch are recorded with it.
+// launched kernel of it (every one while `force` is set: the solver forces
+// two warm iterations of every 16th solve) carries an event pair in its own
+// dispatch (hipExtLaunchKernelGGL), so the pair brackets the kernel's
+// execution alone, and the algorithmic bytes (or flops) of that launch are
+// recorded with it.
 struct KernelTimer {
     static constexpr int kClasses = 8;
     static constexpr int kPool = 2048;  // event pairs per class
