@@ -1,0 +1,93 @@
+"""Host logic of the profile summarizer: the finest-level selection of the
+V-cycle classes in dispatch order, per-class averages, and the scaling of
+the counters by the closing device copy (synthetic rocprofv3 CSVs)."""
+import csv
+import json
+
+from paper_1909_03948_amd import profile_summary as ps
+
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def _cycle():
+    # one V-cycle over two levels above the bottom, then the PCG vector kernels
+    return ["void hinv::k_down<double, hinv::OpA<double>, 8>(...)",
+            "void hinv::k_down<double, hinv::OpA<double>, 8>(...)",
+            "void hinv::k_bottom<double, 0>(...)",
+            "void hinv::k_up<double, hinv::OpA<double>, 16>(...)",
+            "void hinv::k_up<double, hinv::OpA<double>, 16>(...)",
+            "void hinv::k_pcg_apply<double, hinv::OpA<double> >(...)",
+            "void hinv::k_pcg_update<double>(...)"]
+
+
+def test_finest_mask_picks_first_down_and_last_up():
+    names = _cycle() * 2
+    cls = [ps.kernel_class(n) for n in names]
+    mask = ps.finest_mask(cls)
+    picked = [(c, i % 7) for i, (c, m) in enumerate(zip(cls, mask)) if m]
+    assert picked == [("mg_down", 0), ("mg_bottom", 2), ("mg_up", 4), ("pcg_apply", 5), ("pcg_update", 6)] * 2
+
+
+def test_trace_summary_averages_finest_dispatches(tmp_path):
+    names = _cycle() * 3
+    # durations: finest down 10, coarse down 4, bottom 8, coarse up 3, finest up 9, apply 6, update 5 (ns x 1000)
+    dur = [10, 4, 8, 3, 9, 6, 5] * 3
+    with open(tmp_path / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        t = 0
+        for i, (n, d) in enumerate(zip(names, dur)):
+            w.writerow([i + 1, n, t, t + 1000 * d])
+            t += 1000 * d + 500
+    res = ps.summarize_trace(str(tmp_path))
+    assert res["dispatches"] == 21
+    c = res["classes"]
+    assert c["mg_down"]["dispatches"] == 3 and abs(c["mg_down"]["avg_us"] - 10.0) < 1e-9
+    assert c["mg_up"]["dispatches"] == 3 and abs(c["mg_up"]["avg_us"] - 9.0) < 1e-9
+    assert abs(c["mg_bottom"]["avg_us"] - 8.0) < 1e-9 and abs(c["pcg_update"]["avg_us"] - 5.0) < 1e-9
+    assert abs(res["total_ms"] - sum(dur) * 1e-3) < 1e-9
+
+
+def _counter_csv(path, counter, values, copy_kib):
+    names = _cycle()
+    with open(path / "run_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (n, v) in enumerate(zip(names, values)):
+            w.writerow([i + 1, n, counter, v])
+        w.writerow([len(names) + 1, COPY, counter, 7.0])  # an earlier small copy is ignored
+        w.writerow([len(names) + 2, "void hinv::k_pcg_update<double>(...)", counter, 100.0])
+        w.writerow([len(names) + 3, COPY, counter, copy_kib])
+
+
+def test_traffic_scales_by_the_closing_copy(tmp_path):
+    fdir, wdir = tmp_path / "f", tmp_path / "w"
+    fdir.mkdir()
+    wdir.mkdir()
+    # FETCH counts half the bytes (as the hardware counter does), WRITE all of them
+    _counter_csv(fdir, "FETCH_SIZE", [50, 20, 3, 10, 40, 30, 60], 131072.0)
+    _counter_csv(wdir, "WRITE_SIZE", [25, 9, 1, 5, 30, 20, 40], 262144.0)
+    fe, wr = ps.summarize_pmc(str(fdir)), ps.summarize_pmc(str(wdir))
+    assert fe["copy_kib"] == 131072.0 and wr["copy_kib"] == 262144.0
+    assert fe["classes"]["mg_down"]["kib_per_dispatch"] == 50
+    assert fe["classes"]["pcg_update"]["kib_per_dispatch"] == 80  # (60 + 100) / 2
+    json.dump(fe, open(tmp_path / "fe.json", "w"))
+    json.dump(wr, open(tmp_path / "wr.json", "w"))
+    out = tmp_path / "traffic.json"
+    ent = ps.merge_traffic(str(tmp_path / "fe.json"), str(tmp_path / "wr.json"), "w1", str(out))
+    assert abs(ent["calibration"]["fetch_factor"] - 2.0) < 1e-12
+    assert abs(ent["calibration"]["write_factor"] - 1.0) < 1e-12
+    up = ent["kernels"]["mg_up"]
+    assert abs(up["hbm_bytes_per_launch"] - (40 * 2 + 30) * 1024) < 1e-6
+    assert json.load(open(out))["workloads"]["w1"]["source_hash"] == ent["source_hash"]
+
+
+def test_small_quotient_by_float_reciprocal_is_exact():
+    # the bottom kernel divides node indices q < 2^16 by level widths d <= 64
+    # as (q + 1/2) * (1/d) in single precision, truncated
+    import numpy as np
+    q = np.arange(1 << 16, dtype=np.int64)
+    for d in range(1, 65):
+        inv = np.float32(1.0) / np.float32(d)
+        got = ((q.astype(np.float32) + np.float32(0.5)) * inv).astype(np.int64)
+        assert np.array_equal(got, q // d), d
