@@ -291,7 +291,42 @@ __global__ __launch_bounds__(256) void k_cheb_mass(OpKA<double> op, const double
         }
     }
     __syncthreads();
-    for (int st = 0; st < H; ++st) {
+    // Tiles strictly inside the mesh (every node 1 <= i, j <= N - 1) have the
+    // interior row everywhere: its seven couplings stay in scalar registers.
+    const bool inner = ox >= 1 && oy >= 1 && ox + W <= N && oy + W <= N;
+    if (inner) {
+        const KARow<double>& q0 = op.rows[0];
+        const double mc = q0.c, me = q0.e, mw = q0.w, mn = q0.n, ms = q0.s, mne = q0.ne, msw = q0.sw;
+        const double mdv = q0.dinv;
+        for (int st = 0; st < H; ++st) {
+            const int lo = st + 1, hi = W - lo;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int t = threadIdx.x + 256 * e;
+                const int li = t % W, lj = t / W;
+                if (t >= NN || li < lo || li >= hi || lj < lo || lj >= hi) continue;
+                const double Md = mc * sd[t] + me * sd[t + 1] + mw * sd[t - 1] + mn * sd[t + W] + ms * sd[t - W] +
+                                  mne * sd[t + W + 1] + msw * sd[t - W - 1];
+                sr[t] = sr[t] - Md;
+            }
+#pragma unroll
+            for (int o = 0; o < OWN; ++o) {
+                const int t = threadIdx.x + 256 * o;
+                if (t < T * T) vx[o] += sd[(H + t / T) * W + H + t % T];
+            }
+            __syncthreads();
+            const double c1 = cs.c1[st], c2 = cs.c2[st];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int t = threadIdx.x + 256 * e;
+                const int li = t % W, lj = t / W;
+                if (t >= NN || li < lo || li >= hi || lj < lo || lj >= hi) continue;
+                sd[t] = c1 * sd[t] + c2 * mdv * sr[t];
+            }
+            __syncthreads();
+        }
+    }
+    for (int st = 0; !inner && st < H; ++st) {
         const int lo = st + 1, hi = W - lo;  // region [lo, hi)^2
         // r <- r - M d on the region (each r read and written by one thread);
         // x <- x + d on the owned nodes, before d changes.  The loops walk the

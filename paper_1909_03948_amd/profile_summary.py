@@ -40,6 +40,7 @@ def kernel_class(name):
 
 
 def short(name):
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0].replace("void ", "").replace("hinv::", "").strip()
 
 

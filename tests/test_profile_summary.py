@@ -91,3 +91,8 @@ def test_small_quotient_by_float_reciprocal_is_exact():
         inv = np.float32(1.0) / np.float32(d)
         got = ((q.astype(np.float32) + np.float32(0.5)) * inv).astype(np.int64)
         assert np.array_equal(got, q // d), d
+
+
+def test_short_names_keep_helper_kernels():
+    assert ps.short("void hinv::(anonymous namespace)::k_cheb_mass<32>(hinv::OpKA<double>, int)") == "k_cheb_mass<32>"
+    assert ps.short("void hinv::k_up<float, hinv::OpA<float>, 16>(hinv::OpA<float>)") == "k_up<float, OpA<float>, 16>"
