@@ -138,7 +138,7 @@ inline void timed_launch(Ctx* ctx, int cls, double work, F kernel, dim3 grid, di
 // ------------------------------------------------------------ constants ---
 constexpr int kBlock = 256;   // threads per workgroup for grid kernels
 constexpr int kCoarseMaxN = 8;  // coarsest multigrid level has N_c <= 8
-constexpr int kMaxVecPartials = 512;  // partial sums per column of the PCG vector kernels
+constexpr int kMaxVecPartials = 520;  // partial sums per column of the PCG vector kernels
 constexpr int kAutoBatch = 8;   // HINV_PREC_AUTO switches to FP32 refinement from this many columns
 
 // Chebyshev smoother: degree 2, targets the interval [0.5, 2] of the

@@ -610,17 +610,19 @@ Hierarchy::LaunchShape Hierarchy::default_shape(int nc) const {
 
 // Every workgroup of the kernels after a reduction sums all of its partials,
 // so their count enters squared: the PCG vector kernels keep it at or below
-// kMaxVecPartials by giving each workgroup 1, 4 or 16 node blocks.
+// kMaxVecPartials by giving each workgroup 1, 4, 8 or 16 node blocks (the
+// tuner, which times the apply kernel alone, would otherwise pick more
+// workgroups than pay inside the iteration).
 int Hierarchy::min_per() const {
     const int nb = ceil_div(n_, kBlock);
-    for (int per : {1, 4, 16})
+    for (int per : {1, 4, 8, 16})
         if (ceil_div(nb, per) <= kMaxVecPartials) return per;
     return 16;
 }
 
 // Times the candidate shapes on the call's own right-hand sides (w.r is set):
 // the V-cycle with each tile choice, then the PCG apply kernel in its general
-// form (beta from the r^T z partials) with 1, 4 and 16 node blocks per
+// form (beta from the r^T z partials) with 1, 4, 8 and 16 node blocks per
 // workgroup.  Neither touches the solve's state: the apply kernel's outputs
 // (p_new, q, the recorded r^T z) are rewritten by the first real iteration.
 template <typename T>
@@ -696,7 +698,7 @@ void Hierarchy::tune_shape(int nc) {
     PcgWork<T>& w = work<T>();
     const int n = n_;
     best_ms = 1e30f;
-    for (int per : {1, 4, 16}) {
+    for (int per : {1, 4, 8, 16}) {
         if (per < min_per()) continue;
         shape_.per = per;
         const PcgRed red = pcg_red(nc);
