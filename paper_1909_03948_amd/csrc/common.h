@@ -115,7 +115,15 @@ struct Ctx {
     hipStream_t stream = nullptr;
     std::string err;
     DBuf<double> red;  // reduction scratch of the vector helpers
+    double* host_red = nullptr;  // pinned landing buffer of their results (kHostRed doubles)
+    static constexpr int kHostRed = 4096;
     KernelTimer timer;
+    Ctx() = default;
+    Ctx(const Ctx&) = delete;
+    Ctx& operator=(const Ctx&) = delete;
+    ~Ctx() {
+        if (host_red) (void)hipHostFree(host_red);
+    }
 };
 
 // Kernel classes of the timer (values of HINV_KCLASS_* in the public header).

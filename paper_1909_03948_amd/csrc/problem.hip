@@ -473,8 +473,16 @@ void dev_dots(Ctx* ctx, int n, int nc, const double* a, int lda, const double* b
     double* out = ctx->red.get() + (size_t)nblk * nc;
     k_dot_finish<<<nc, kBlock, 0, ctx->stream>>>(ctx->red.get(), nblk, out);
     HINV_LAUNCH_CHECK();
-    HINV_HIP(hipMemcpyAsync(host_out, out, sizeof(double) * nc, hipMemcpyDeviceToHost, ctx->stream));
-    HINV_HIP(hipStreamSynchronize(ctx->stream));
+    // through pinned memory: a pageable destination adds a staging copy to
+    // every read-back of the Newton-CG loop
+    if (!ctx->host_red) HINV_HIP(hipHostMalloc((void**)&ctx->host_red, sizeof(double) * Ctx::kHostRed,
+                                               hipHostMallocDefault));
+    for (int c0 = 0; c0 < nc; c0 += Ctx::kHostRed) {
+        const int m = std::min(Ctx::kHostRed, nc - c0);
+        HINV_HIP(hipMemcpyAsync(ctx->host_red, out + c0, sizeof(double) * m, hipMemcpyDeviceToHost, ctx->stream));
+        HINV_HIP(hipStreamSynchronize(ctx->stream));
+        std::memcpy(host_out + c0, ctx->host_red, sizeof(double) * m);
+    }
 }
 
 double dev_dot(Ctx* ctx, int n, const double* a, const double* b) {

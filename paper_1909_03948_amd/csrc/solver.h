@@ -150,6 +150,7 @@ class Hierarchy {
     DBuf<int> act_, oact_;
     DBuf<double> colnorm_;  // per column |r| used to scale the inner right-hand side
     int* host_flags_ = nullptr;
+    ColState* host_st_ = nullptr;  // pinned: column states read by the refinement loop [0, 4096) and PCG [4096, 8192)
     hipStream_t gs_ = nullptr;             // private stream for graph capture
     hipStream_t launch_stream_ = nullptr;  // stream the PCG kernels go to (capture or caller)
     hipGraphExec_t gexec_[2] = {nullptr, nullptr};  // FP64 / FP32 two-iteration graphs

@@ -390,6 +390,7 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp, int ninst,
     cinv64_.ensure(ni * nc_coarse_ * nc_coarse_);
     cinv32_.ensure(ni * nc_coarse_ * nc_coarse_);
     HINV_HIP(hipHostMalloc((void**)&host_flags_, sizeof(int) * 4096, hipHostMallocDefault));
+    HINV_HIP(hipHostMalloc((void**)&host_st_, sizeof(ColState) * 2 * 4096, hipHostMallocDefault));
     HINV_HIP(hipStreamCreateWithFlags(&gs_, hipStreamNonBlocking));
     launch_stream_ = ctx_->stream;
     if (kind_ == kOpPrior) {
@@ -425,6 +426,7 @@ Hierarchy::~Hierarchy() {
     drop_graphs();
     if (gs_) (void)hipStreamDestroy(gs_);
     if (host_flags_) (void)hipHostFree(host_flags_);
+    if (host_st_) (void)hipHostFree(host_st_);
 }
 
 void Hierarchy::build_coarse(int inst) {
@@ -1017,7 +1019,7 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
     for (const auto& kv : last_iters_)
         if (kv.first == key) expect = kv.second;
     bool first_check = true;
-    std::vector<ColState> hst(nc);
+    ColState* hst = host_st_ + 4096;  // pinned, so the read-back needs no staging copy
     while (it < max_iter) {
         int reps = 1;
         if (first_check && expect > it + 2) reps = std::min(6, (expect - it + 1) / 2);
@@ -1049,7 +1051,7 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
         }
         if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
         HINV_HIP(hipMemcpyAsync(host_flags_, act, sizeof(int) * nc, hipMemcpyDeviceToHost, s));
-        HINV_HIP(hipMemcpyAsync(hst.data(), st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
+        HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
         HINV_HIP(hipStreamSynchronize(s));
         first_check = false;
         int live = 0;
@@ -1138,14 +1140,14 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     const int max_outer = fp32 ? 16 : 4;
     bool use32 = fp32;
     std::vector<double> prev_rr(nc, INFINITY);  // unknown before the first pass
-    std::vector<ColState> hst(nc);
+    ColState* hst = host_st_;  // pinned, so the read-backs need no staging copy
     bool converged = false;
     while (true) {
         // the first pass starts without reading the flags back: its kernels
         // skip the columns that are already converged (b = 0)
         if (outer > 0) {
             HINV_HIP(hipMemcpyAsync(host_flags_, oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToHost, s));
-            HINV_HIP(hipMemcpyAsync(hst.data(), st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
+            HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
             HINV_HIP(hipStreamSynchronize(s));
             int live = 0;
             for (int c = 0; c < nc; ++c) live += host_flags_[c];
@@ -1156,7 +1158,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
         }
         if (outer >= max_outer || iters >= max_iter) {
             if (outer == 0) {
-                HINV_HIP(hipMemcpyAsync(hst.data(), st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
+                HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
                 HINV_HIP(hipStreamSynchronize(s));
             }
             break;
