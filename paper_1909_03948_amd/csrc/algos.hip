@@ -26,6 +26,40 @@ __global__ void k_add_vec(int n, const double* __restrict__ v, double* __restric
 
 double nrm(Ctx* c, int n, const double* x) { return std::sqrt(dev_dot(c, n, x, x)); }
 
+// Scalars of the Newton-CG loop kept on the device (slots of cgs): 0 = r^T z,
+// 1 = d^T H d, 2 = alpha, 3 = 1 when d^T H d <= 0, 4 = |r|^2, 5 = new r^T z.
+// Only slots 3 and 4 travel to the host, once per CG iteration.
+__global__ void k_cg_alpha(double* __restrict__ cgs) {
+    if (threadIdx.x == 0) {
+        const double dHd = cgs[1];
+        const bool ok = dHd > 0.0;
+        cgs[2] = ok ? cgs[0] / dHd : 0.0;
+        cgs[3] = ok ? 0.0 : 1.0;
+    }
+}
+
+// mhat += alpha d, r -= alpha H d (alpha = 0 after non-positive curvature)
+__global__ void k_cg_step(int n, const double* __restrict__ cgs, const double* __restrict__ d,
+                          const double* __restrict__ Hd, double* __restrict__ mh, double* __restrict__ r) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double alpha = cgs[2];
+    mh[k] = alpha * d[k] + 1.0 * mh[k];
+    r[k] = -alpha * Hd[k] + 1.0 * r[k];
+}
+
+// d = z + beta d with beta = (new r^T z) / (r^T z)
+__global__ void k_cg_dir(int n, const double* __restrict__ cgs, const double* __restrict__ z,
+                         double* __restrict__ d) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    d[k] = 1.0 * z[k] + (cgs[5] / cgs[0]) * d[k];
+}
+
+__global__ void k_cg_roll(double* __restrict__ cgs) {
+    if (threadIdx.x == 0) cgs[0] = cgs[5];
+}
+
 // Tightens the problem's solve tolerance for the lifetime of the guard.
 struct TolGuard {
     Problem& P;
@@ -53,6 +87,11 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
     std::memset(info, 0, sizeof(*info));
     DBuf<double> buf;
     buf.ensure((size_t)n * 10);
+    DBuf<double> cgsb;
+    cgsb.ensure(8);
+    double* cgs = cgsb.get();
+    if (!c->host_red)
+        HINV_HIP(hipHostMalloc((void**)&c->host_red, sizeof(double) * Ctx::kHostRed, hipHostMallocDefault));
     double* m = m_map;
     double* u = buf.get();
     double* p = u + n;
@@ -106,25 +145,31 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
         dev_axpby(c, n, 0.0, g, -1.0, r);  // r = -g
         P.prior_solve(1, r, n, z, n, &st);
         dev_copy(c, n, 1, z, n, d, n);
-        double rz = dev_dot(c, n, r, z);
+        dev_dot_to(c, n, r, z, cgs);  // r^T z
         int ncg = 0;
+        const int nb = ceil_div(n, kBlock);
         for (int k = 0; k < o.max_cg; ++k) {
             P.hessian(hmode, 1, d, n, Hd, n, &st);
             ++info->hessian_applies;
             ++ncg;
-            const double dHd = dev_dot(c, n, d, Hd);
-            if (!(dHd > 0.0)) {
+            dev_dot_to(c, n, d, Hd, cgs + 1);
+            k_cg_alpha<<<1, 64, 0, c->stream>>>(cgs);
+            k_cg_step<<<nb, kBlock, 0, c->stream>>>(n, cgs, d, Hd, mh, r);
+            dev_dot_to(c, n, r, r, cgs + 4);
+            HINV_LAUNCH_CHECK();
+            HINV_HIP(hipMemcpyAsync(c->host_red, cgs + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HINV_HIP(hipStreamSynchronize(c->stream));
+            if (c->host_red[0] != 0.0) {
+                // non-positive curvature: the step above used alpha = 0
                 if (k == 0) dev_copy(c, n, 1, d, n, mh, n);
                 break;
             }
-            const double alpha = rz / dHd;
-            dev_axpby(c, n, alpha, d, 1.0, mh);
-            dev_axpby(c, n, -alpha, Hd, 1.0, r);
-            if (nrm(c, n, r) <= eta * gn) break;
+            if (std::sqrt(c->host_red[1]) <= eta * gn) break;
             P.prior_solve(1, r, n, z, n, &st);
-            const double rzn = dev_dot(c, n, r, z);
-            dev_axpby(c, n, 1.0, z, rzn / rz, d);  // d = z + beta d
-            rz = rzn;
+            dev_dot_to(c, n, r, z, cgs + 5);
+            k_cg_dir<<<nb, kBlock, 0, c->stream>>>(n, cgs, z, d);  // d = z + beta d
+            k_cg_roll<<<1, 64, 0, c->stream>>>(cgs);
+            HINV_LAUNCH_CHECK();
         }
         info->cg_iters[it] = ncg;
         // --- Armijo backtracking ---

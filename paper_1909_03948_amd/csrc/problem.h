@@ -79,6 +79,7 @@ class Problem {
 
 // ---- device vector helpers (FP64, single stream) ---------------------------
 double dev_dot(Ctx* ctx, int n, const double* a, const double* b);
+void dev_dot_to(Ctx* ctx, int n, const double* a, const double* b, double* out);  // a^T b into device *out
 void dev_dots(Ctx* ctx, int n, int nc, const double* a, int lda, const double* b, int ldb,
               double* host_out);
 void dev_axpby(Ctx* ctx, int n, double a, const double* x, double b, double* y);  // y = a x + b y

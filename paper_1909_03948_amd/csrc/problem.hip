@@ -485,6 +485,15 @@ void dev_dots(Ctx* ctx, int n, int nc, const double* a, int lda, const double* b
     }
 }
 
+void dev_dot_to(Ctx* ctx, int n, const double* a, const double* b, double* out) {
+    const int nblk = ceil_div(n, kBlock);
+    ctx->red.ensure((size_t)nblk + 1);
+    k_dot_partial<<<grid2(n, 1), kBlock, 0, ctx->stream>>>(n, a, n, b, n, ctx->red.get());
+    HINV_LAUNCH_CHECK();
+    k_dot_finish<<<1, kBlock, 0, ctx->stream>>>(ctx->red.get(), nblk, out);
+    HINV_LAUNCH_CHECK();
+}
+
 double dev_dot(Ctx* ctx, int n, const double* a, const double* b) {
     double r;
     dev_dots(ctx, n, 1, a, n, b, n, &r);
