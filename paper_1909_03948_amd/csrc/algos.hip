@@ -9,11 +9,6 @@ namespace hinv {
 
 namespace {
 
-__global__ void k_fill_cols(int n, double v, double* __restrict__ x) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) x[k] = v;
-}
-
 __global__ void k_post_scale(int k, const double* __restrict__ lam, double* __restrict__ s) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < k) s[i] = 1.0 - 1.0 / sqrt(1.0 + lam[i]);
