@@ -87,6 +87,38 @@ struct OpA {
         }
         return d * xat(i, j, k) - s;
     }
+    // Straight-line form of apply() for kernels that overlap the loads of
+    // several rows: row() and gather() issue every load of row k (an absent
+    // neighbour reads node k itself), combine() gives it weight zero.  Same
+    // operation order as apply(), so on finite vectors the two agree bit for bit.
+    struct Row {
+        T we, ww, wn, ws;
+    };
+    struct Nb {
+        T c, e, w, n, s;
+    };
+    __device__ Row row(int i, int j, int k) const {
+        const int N1 = N + 1;
+        return Row{wE[k], wE[i > 0 ? k - 1 : k], wN[k], wN[j > 0 ? k - N1 : k]};
+    }
+    __device__ Nb gather(int i, int j, int k, const T* __restrict__ x) const {
+        const int N1 = N + 1;
+        return Nb{x[k], x[i < N ? k + 1 : k], x[i > 0 ? k - 1 : k], x[j + 1 < N ? k + N1 : k],
+                  x[j > 1 ? k - N1 : k]};
+    }
+    __device__ T combine(int i, int j, const Row& r, const Nb& v) const {
+        const T we = i < N ? r.we : (T)0, ww = i > 0 ? r.ww : (T)0;
+        T s = 0, d = 0;
+        d += we;
+        s += we * v.e;
+        d += ww;
+        s += ww * v.w;
+        d += r.wn;
+        s += (j + 1 < N ? r.wn : (T)0) * v.n;
+        d += r.ws;
+        s += (j - 1 > 0 ? r.ws : (T)0) * v.s;
+        return d * v.c - s;
+    }
 };
 
 // ------------------------------------------------------- prior operator ---
@@ -123,6 +155,25 @@ __device__ inline T ka_apply(const KARow<T>& r, int N, int i, int j, int k, F xa
     return acc;
 }
 
+// Straight-line gather of the seven values a prior row reads (an absent
+// neighbour reads node k itself; its coupling is zero).
+template <typename T>
+struct KANb {
+    T c, e, w, n, s, ne, sw;
+};
+template <typename T>
+__device__ inline KANb<T> ka_gather(int N, int i, int j, int k, const T* __restrict__ x) {
+    const int N1 = N + 1;
+    const bool hE = i < N, hW = i > 0, hN = j < N, hS = j > 0;
+    return KANb<T>{x[k], x[hE ? k + 1 : k], x[hW ? k - 1 : k], x[hN ? k + N1 : k], x[hS ? k - N1 : k],
+                   x[hE && hN ? k + N1 + 1 : k], x[hW && hS ? k - N1 - 1 : k]};
+}
+// Same order of operations as ka_apply (absent neighbours add a zero product).
+template <typename T>
+__device__ inline T ka_combine(const KARow<T>& r, const KANb<T>& v) {
+    return r.c * v.c + r.e * v.e + r.w * v.w + r.n * v.n + r.s * v.s + r.ne * v.ne + r.sw * v.sw;
+}
+
 // Row tables travel by value (kernel arguments).  Interior nodes (class 0,
 // all but the boundary) read row 0 at a constant index, which the compiler
 // keeps in scalar registers; only boundary nodes index the table per lane.
@@ -153,6 +204,17 @@ struct OpKA {
         }
         return ka_apply(rows[c], N, i, j, k, xat);
     }
+    // straight-line form (see OpA): the row is the node class, its table
+    // entry is read when combining
+    struct Row {
+        int c;
+    };
+    using Nb = KANb<T>;
+    __device__ Row row(int i, int j, int) const { return Row{ka_class(i, j, N)}; }
+    __device__ Nb gather(int i, int j, int k, const T* __restrict__ x) const { return ka_gather(N, i, j, k, x); }
+    __device__ T combine(int, int, const Row& r, const Nb& v) const {
+        return r.c == 0 ? ka_combine(rows[0], v) : ka_combine(rows[r.c], v);
+    }
 };
 
 // Same operator reading its row table through a pointer (staged in LDS, or in
@@ -174,6 +236,12 @@ struct OpKARef {
     __device__ T apply(int i, int j, int k, F xat) const {
         return ka_apply(rows[ka_class(i, j, N)], N, i, j, k, xat);
     }
+    // straight-line form (see OpA): the table entry is loaded with the row
+    using Row = KARow<T>;
+    using Nb = KANb<T>;
+    __device__ Row row(int i, int j, int) const { return rows[ka_class(i, j, N)]; }
+    __device__ Nb gather(int i, int j, int k, const T* __restrict__ x) const { return ka_gather(N, i, j, k, x); }
+    __device__ T combine(int, int, const Row& r, const Nb& v) const { return ka_combine(r, v); }
 };
 
 // Prior operator of a level: the 9 row classes from the element matrices.

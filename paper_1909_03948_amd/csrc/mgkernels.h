@@ -33,23 +33,37 @@ struct ChebCoef {
 // fences are needed) sums them in a fixed order.
 // First phase: this thread's strided share of the partials (loads only, so
 // that a kernel can issue them together with its other loads).
-__device__ inline double partial_share(const double* part, int col, int stride, int nblk) {
-    double s = 0.0;
-#pragma unroll 4
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)col * stride + b];
+// In two steps, so that a kernel can issue other loads in between:
+// partial_first loads this thread's first partial (usually its only one),
+// partial_rest adds the further ones.
+__device__ inline double partial_first(const double* part, int col, int stride, int nblk) {
+    const int t = threadIdx.x;
+    return t < nblk ? part[(size_t)col * stride + t] : 0.0;
+}
+__device__ inline double partial_rest(double s, const double* part, int col, int stride, int nblk) {
+    const double* p = part + (size_t)col * stride;
+    for (int b = threadIdx.x + blockDim.x; b < nblk; b += blockDim.x) s += p[b];
     return s;
 }
+__device__ inline double partial_share(const double* part, int col, int stride, int nblk) {
+    return partial_rest(partial_first(part, col, stride, nblk), part, col, stride, nblk);
+}
+
+// Waves of the workgroup as a uniform value (read once, outside the
+// single-thread code that sums the per-wave slots).
+__device__ inline int group_waves() { return __builtin_amdgcn_readfirstlane((int)(blockDim.x >> 6)); }
 
 // Second phase: the workgroup total of the shares, returned to every thread.
 __device__ inline double share_total(double s) {
     __shared__ double ps[16];
     __shared__ double tot;
+    const int nw = group_waves();
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) ps[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += ps[w];
+        for (int w = 0; w < nw; ++w) t += ps[w];
         tot = t;
     }
     __syncthreads();
@@ -79,12 +93,13 @@ constexpr int kVecNodes = 4;
 // Workgroup sum with its own LDS slot; result valid in thread 0.
 __device__ inline double group_sum(double v) {
     __shared__ double part[16];
+    const int nw = group_waves();
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
     __syncthreads();
     double r = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += part[w];
+        for (int w = 0; w < nw; ++w) r += part[w];
     return r;
 }
 
@@ -598,52 +613,95 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
 // blockIdx.y with vec_threads(per) threads, at most kVecNodes nodes a thread.
 
 // p_new = z + beta p_old with beta = (r^T z) / rz_old (p_new = z on the first
-// iteration), q = A p_new = A z + beta A p_old, partials of p_new^T q.  The
-// loads of z, p_old (with the operator rows) and of the r^T z partials are
-// all issued before the reduction.  Workgroup 0 records r^T z for the update
+// iteration, FIRST), q = A p_new = A z + beta A p_old, partials of p_new^T q.
+// The loads of the r^T z partials and of the thread's nodes (z and p_old at
+// the stencil points, the operator rows) are issued before any of them is
+// used, so their latencies overlap: all at once where the registers allow,
+// else node by node with apply_window() nodes in flight (FP64 rows would spill).
+// Node k = j (N + 1) + i is split by a double reciprocal: (k + 1/2) / (N + 1)
+// lies at least 1 / (2 (N + 1)) from an integer and the product errs by far
+// less, so the truncation is exact.  Workgroup 0 records r^T z for the update
 // kernel, which then reads one value instead of the partials.
-template <typename T, class Op>
+template <class OpT>
+constexpr int apply_window() {
+    constexpr size_t b = sizeof(typename OpT::Row) + 2 * sizeof(typename OpT::Nb);  // loaded bytes per node
+    return b <= 96 ? kVecNodes : (b <= 128 ? 3 : 2);
+}
+
+template <typename T, class Op, bool FIRST>
 __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict__ z, const T* __restrict__ p_old,
                                                     T* __restrict__ p_new, T* __restrict__ q, int ld,
                                                     const int* __restrict__ act, ColState* __restrict__ st,
-                                                    PcgRed red, int first) {
+                                                    PcgRed red) {
     const int col = blockIdx.y;
     const auto& op = op_.at(col);  // operator of the instance owning this column
     if (!act[col]) return;
     const int N = op.N, N1 = N + 1, n = N1 * N1;
-    const bool need_rz = !first || blockIdx.x == 0;  // uniform in the workgroup
-    const double srz = need_rz ? partial_share(red.rz, col, red.stride, red.nrz) : 0.0;
+    const bool need_rz = !FIRST || blockIdx.x == 0;  // uniform in the workgroup
+    double srz = need_rz ? partial_first(red.rz, col, red.stride, red.nrz) : 0.0;
+    const double rz_old = FIRST ? 1.0 : st[col].rz;
     const T* zc = z + (size_t)col * ld;
     const T* pc = p_old + (size_t)col * ld;
     const int k0 = blockIdx.x * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
+    const double inv_n1 = 1.0 / N1;
+    using OpT = std::decay_t<decltype(op)>;
+    typename OpT::Row rw[kVecNodes];
+    typename OpT::Nb vz[kVecNodes], vp[kVecNodes];
     T zk[kVecNodes], pk[kVecNodes], az[kVecNodes], ap[kVecNodes];
-#pragma unroll
-    for (int e = 0; e < kVecNodes; ++e) {
-        const int k = k0 + e * blockDim.x + threadIdx.x;
+    auto node = [&](int e, int& i, int& j) {
+        const int k = k0 + e * (int)blockDim.x + (int)threadIdx.x;
+        j = (int)(((double)k + 0.5) * inv_n1);
+        i = k - j * N1;
+        return k;
+    };
+    auto load = [&](int e) {
+        int i, j;
+        const int k = node(e, i, j);
+        if (k < k1) {
+            rw[e] = op.row(i, j, k);
+            vz[e] = op.gather(i, j, k, zc);
+            if constexpr (!FIRST) vp[e] = op.gather(i, j, k, pc);
+        }
+    };
+    auto combine = [&](int e) {
+        int i, j;
+        const int k = node(e, i, j);
         zk[e] = pk[e] = az[e] = ap[e] = 0;
         if (k < k1) {
-            const int i = k % N1, j = k / N1;
-            zk[e] = zc[k];
-            if (!first) pk[e] = pc[k];
-            if (op.is_free(i, j)) {
-                az[e] = op.apply(i, j, k, [&](int, int, int kk) { return zc[kk]; });
-                if (!first) ap[e] = op.apply(i, j, k, [&](int, int, int kk) { return pc[kk]; });
+            const bool fr = op.is_free(i, j);
+            zk[e] = vz[e].c;
+            if (fr) az[e] = op.combine(i, j, rw[e], vz[e]);
+            if constexpr (!FIRST) {
+                pk[e] = vp[e].c;
+                if (fr) ap[e] = op.combine(i, j, rw[e], vp[e]);
             }
         }
+    };
+    constexpr int W = apply_window<OpT>();
+#pragma unroll
+    for (int e = 0; e < kVecNodes; ++e) {
+        if (e >= W) {
+            combine(e - W);
+            __builtin_amdgcn_sched_barrier(0);  // keeps the window: no later load moves above
+        }
+        load(e);
     }
+    if (need_rz) srz = partial_rest(srz, red.rz, col, red.stride, red.nrz);
+#pragma unroll
+    for (int e = kVecNodes - W; e < kVecNodes; ++e) combine(e);
     T beta = 0;
     if (need_rz) {
         const double rz = share_total(srz);
-        if (!first) beta = (T)(rz / st[col].rz);
+        if (!FIRST) beta = (T)(rz / rz_old);
         if (blockIdx.x == 0 && threadIdx.x == 0) st[col].rz_new = rz;
     }
     double dot = 0.0;
 #pragma unroll
     for (int e = 0; e < kVecNodes; ++e) {
-        const int k = k0 + e * blockDim.x + threadIdx.x;
+        const int k = k0 + e * (int)blockDim.x + (int)threadIdx.x;
         if (k < k1) {
-            const T pn = first ? zk[e] : zk[e] + beta * pk[e];
-            const T v = first ? az[e] : az[e] + beta * ap[e];
+            const T pn = FIRST ? zk[e] : zk[e] + beta * pk[e];
+            const T v = FIRST ? az[e] : az[e] + beta * ap[e];
             p_new[(size_t)col * ld + k] = pn;
             q[(size_t)col * ld + k] = v;
             dot += (double)pn * (double)v;
@@ -663,7 +721,8 @@ __global__ __launch_bounds__(1024) void k_pcg_update(T* __restrict__ x, T* __res
                                                      ColState* __restrict__ st, PcgRed red) {
     const int col = blockIdx.y;
     if (!act[col]) return;
-    const double spq = partial_share(red.pq, col, red.stride, red.nvec);
+    double spq = partial_first(red.pq, col, red.stride, red.nvec);
+    const double rz = st[col].rz_new;
     const int k0 = blockIdx.x * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
     T xk[kVecNodes], rk[kVecNodes], pk[kVecNodes], qk[kVecNodes];
 #pragma unroll
@@ -678,7 +737,7 @@ __global__ __launch_bounds__(1024) void k_pcg_update(T* __restrict__ x, T* __res
             qk[e] = q[o];
         }
     }
-    const double rz = st[col].rz_new;
+    spq = partial_rest(spq, red.pq, col, red.stride, red.nvec);
     const double pq = share_total(spq);
     const double alpha = pq > 0.0 ? rz / pq : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {

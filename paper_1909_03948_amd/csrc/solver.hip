@@ -706,8 +706,8 @@ void Hierarchy::tune_shape(int nc) {
         const PcgRed red = pcg_red(nc);
         const float ms = timed([&] {
             with_op<T>(0, [&](auto op) {
-                k_pcg_apply<T><<<dim3(red.nvec, nc), vec_threads(red.per), 0, s>>>(op, w.z.get(), w.p.get(), w.p2.get(),
-                                                                     w.q.get(), n, act_.get(), st_.get(), red, 0);
+                k_pcg_apply<T, decltype(op), false><<<dim3(red.nvec, nc), vec_threads(red.per), 0, s>>>(
+                    op, w.z.get(), w.p.get(), w.p2.get(), w.q.get(), n, act_.get(), st_.get(), red);
             });
             HINV_LAUNCH_CHECK();
         });
@@ -884,8 +884,8 @@ void Hierarchy::pcg_iteration(int nc, int cur, int first) {
             const T* pold = P[cur];
             const int* actc = act;
             ColState* stc = st_.get();
-            timed_launch(ctx_, kKPcgApply, bytes_apply, k_pcg_apply<T, Op>, g, dim3(vec_threads(red.per)), s, op, zc, pold,
-                         P[1 - cur], w.q.get(), ld, actc, stc, red, first);
+            timed_launch(ctx_, kKPcgApply, bytes_apply, first ? k_pcg_apply<T, Op, true> : k_pcg_apply<T, Op, false>, g,
+                         dim3(vec_threads(red.per)), s, op, zc, pold, P[1 - cur], w.q.get(), ld, actc, stc, red);
         });
         HINV_LAUNCH_CHECK();
     }
