@@ -244,6 +244,29 @@ struct OpKARef {
     __device__ T combine(int, int, const Row& r, const Nb& v) const { return ka_combine(r, v); }
 };
 
+// Straight-line form of either prior operator with its 9 rows staged in LDS
+// by the kernel (a boundary node then reads its row there, after its loads,
+// instead of a per-lane load from kernel arguments or global memory).
+template <typename T>
+struct OpKALds {
+    int N;
+    const KARow<T>* rows;  // LDS
+    struct Row {
+        int c;
+    };
+    using Nb = KANb<T>;
+    __device__ bool is_free(int, int) const { return true; }
+    __device__ Row row(int i, int j, int) const { return Row{ka_class(i, j, N)}; }
+    __device__ Nb gather(int i, int j, int k, const T* __restrict__ x) const { return ka_gather(N, i, j, k, x); }
+    __device__ T combine(int, int, const Row& r, const Nb& v) const { return ka_combine(rows[r.c], v); }
+};
+
+// Row c (0..8) of the operator a column uses, for staging into LDS.
+template <typename T>
+__device__ inline KARow<T> ka_row(const OpKA<T>& o, int c) { return o.rows[c]; }
+template <typename T>
+__device__ inline KARow<T> ka_row(const OpKARef<T>& o, int c) { return o.rows[c]; }
+
 // Prior operator of a level: the 9 row classes from the element matrices.
 //   K (unit stiffness): an axis edge adjacent to t triangles has weight t/2;
 //   M: |T|/12 (1 + delta_vw) per triangle, |T| = h^2/2, so an axis edge adjacent

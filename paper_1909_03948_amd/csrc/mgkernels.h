@@ -622,6 +622,24 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
 // lies at least 1 / (2 (N + 1)) from an integer and the product errs by far
 // less, so the truncation is exact.  Workgroup 0 records r^T z for the update
 // kernel, which then reads one value instead of the partials.
+// The operator form the apply kernel combines with: the state operator as it
+// is, the prior operators through their rows staged in LDS.
+template <class OpT>
+struct ApplyForm {
+    using type = OpT;
+    static constexpr bool kTable = false;
+};
+template <typename T>
+struct ApplyForm<OpKA<T>> {
+    using type = OpKALds<T>;
+    static constexpr bool kTable = true;
+};
+template <typename T>
+struct ApplyForm<OpKARef<T>> {
+    using type = OpKALds<T>;
+    static constexpr bool kTable = true;
+};
+
 template <class OpT>
 constexpr int apply_window() {
     constexpr size_t b = sizeof(typename OpT::Row) + 2 * sizeof(typename OpT::Nb);  // loaded bytes per node
@@ -644,7 +662,14 @@ __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict_
     const T* pc = p_old + (size_t)col * ld;
     const int k0 = blockIdx.x * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
     const double inv_n1 = 1.0 / N1;
-    using OpT = std::decay_t<decltype(op)>;
+    using Form = ApplyForm<std::decay_t<decltype(op)>>;
+    using OpT = typename Form::type;
+    __shared__ KARow<T> krows[Form::kTable ? 9 : 1];
+    OpT sop;
+    if constexpr (Form::kTable)
+        sop = OpT{N, krows};
+    else
+        sop = op;
     typename OpT::Row rw[kVecNodes];
     typename OpT::Nb vz[kVecNodes], vp[kVecNodes];
     T zk[kVecNodes], pk[kVecNodes], az[kVecNodes], ap[kVecNodes];
@@ -658,9 +683,9 @@ __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict_
         int i, j;
         const int k = node(e, i, j);
         if (k < k1) {
-            rw[e] = op.row(i, j, k);
-            vz[e] = op.gather(i, j, k, zc);
-            if constexpr (!FIRST) vp[e] = op.gather(i, j, k, pc);
+            rw[e] = sop.row(i, j, k);
+            vz[e] = sop.gather(i, j, k, zc);
+            if constexpr (!FIRST) vp[e] = sop.gather(i, j, k, pc);
         }
     };
     auto combine = [&](int e) {
@@ -668,22 +693,28 @@ __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict_
         const int k = node(e, i, j);
         zk[e] = pk[e] = az[e] = ap[e] = 0;
         if (k < k1) {
-            const bool fr = op.is_free(i, j);
+            const bool fr = sop.is_free(i, j);
             zk[e] = vz[e].c;
-            if (fr) az[e] = op.combine(i, j, rw[e], vz[e]);
+            if (fr) az[e] = sop.combine(i, j, rw[e], vz[e]);
             if constexpr (!FIRST) {
                 pk[e] = vp[e].c;
-                if (fr) ap[e] = op.combine(i, j, rw[e], vp[e]);
+                if (fr) ap[e] = sop.combine(i, j, rw[e], vp[e]);
             }
         }
     };
     constexpr int W = apply_window<OpT>();
 #pragma unroll
-    for (int e = 0; e < kVecNodes; ++e) {
-        if (e >= W) {
-            combine(e - W);
-            __builtin_amdgcn_sched_barrier(0);  // keeps the window: no later load moves above
-        }
+    for (int e = 0; e < W; ++e) load(e);
+    if constexpr (Form::kTable) {
+        // rows staged after the node loads are issued (waiting for them then
+        // waits for nothing those loads would not)
+        if (threadIdx.x < 9) krows[threadIdx.x] = ka_row(op, threadIdx.x);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = W; e < kVecNodes; ++e) {
+        combine(e - W);
+        __builtin_amdgcn_sched_barrier(0);  // keeps the window: no later load moves above
         load(e);
     }
     if (need_rz) srz = partial_rest(srz, red.rz, col, red.stride, red.nrz);
