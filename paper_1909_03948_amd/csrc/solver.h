@@ -2,6 +2,8 @@
 // right-hand sides, in FP64 or as FP32 PCG inside FP64 iterative refinement.
 #pragma once
 
+#include <functional>
+
 #include <memory>
 
 #include "common.h"
@@ -83,8 +85,13 @@ class Hierarchy {
     double inner_tol32 = 1e-5;  // FP32 inner relative tolerance of the refinement loop
 
   private:
+    // Runs the PCG iterations of the current inner solve.  tail, when given,
+    // is enqueued before every completion check (the refinement step, gated
+    // on the device to the columns whose PCG has finished); returns true when
+    // the last check found every column finished, its read-back (outer flags
+    // in host_flags_ + 4096, column states in host_st_) then follows the tail.
     template <typename T>
-    void pcg(int nc, int max_iter, int* iters);
+    bool pcg(int nc, int max_iter, int* iters, const std::function<void()>* tail = nullptr);
     template <typename T>
     void pcg_iteration(int nc, int cur, int first);
     template <typename T>
@@ -147,7 +154,7 @@ class Hierarchy {
     DBuf<double> pcg_part_;  // partial sums of r^T z, p^T q, r^T r per workgroup and column
     int red_stride_ = 0;
     DBuf<ColState> st_;
-    DBuf<int> act_, oact_;
+    DBuf<int> act_, oact_, tdone_;  // inner and outer activity, refinement step taken this pass
     DBuf<double> colnorm_;  // per column |r| used to scale the inner right-hand side
     int* host_flags_ = nullptr;
     ColState* host_st_ = nullptr;  // pinned: column states read by the refinement loop [0, 4096) and PCG [4096, 8192)

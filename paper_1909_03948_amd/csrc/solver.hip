@@ -23,6 +23,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <type_traits>
 
 #include "mgkernels.h"
 
@@ -211,12 +213,21 @@ __global__ void k_ir_init(Op op_, const double* __restrict__ b, int ldb, double*
     if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
-// r64 = b - A x64 on active columns, partial |r64|^2.
+// Gate of the refinement step of column c.  The step runs for an outer-active
+// column; with the inner flags given (a step enqueued before the host knows
+// whether the inner solve has finished) only once its inner solve has
+// finished and only once per outer pass (tdone, set by k_ir_finalize).
+__device__ inline bool ir_step_on(int c, const int* oact, const int* inner, const int* tdone) {
+    return oact[c] && !(inner && inner[c]) && !(tdone && tdone[c]);
+}
+
+// r64 = b - A x64 on the gated columns, partial |r64|^2.
 template <class Op>
 __global__ void k_ir_residual(Op op_, const double* __restrict__ b, int ldb,
                               const double* __restrict__ x64, double* __restrict__ r64, int ld,
-                              const int* __restrict__ act, double* __restrict__ partial) {
-    if (!act[blockIdx.y]) return;
+                              const int* __restrict__ act, const int* __restrict__ inner,
+                              const int* __restrict__ tdone, double* __restrict__ partial) {
+    if (!ir_step_on(blockIdx.y, act, inner, tdone)) return;
     const auto& op = op_.at(blockIdx.y);
     const int N1 = op.N + 1, n = N1 * N1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -246,10 +257,12 @@ __device__ inline double column_total(const double* partial, int nblk) {
 // column stays active while rr > rtol^2 bb; colnorm = |r|; inner tolerance.
 __global__ void k_ir_finalize(int first, const double* __restrict__ partial, int nblk,
                               ColState* __restrict__ st, int* __restrict__ oact,
-                              double* __restrict__ colnorm, double rtol, double tol_floor) {
-    if (!first && !oact[blockIdx.x]) return;
+                              double* __restrict__ colnorm, double rtol, double tol_floor,
+                              const int* __restrict__ inner, int* __restrict__ tdone) {
+    if (!first && !ir_step_on(blockIdx.x, oact, inner, tdone)) return;
     const double s = column_total(partial, nblk);
     if (threadIdx.x != 0) return;
+    if (tdone) tdone[blockIdx.x] = 1;
     ColState& c = st[blockIdx.x];
     if (first) c.obb = s;
     c.rr = s;
@@ -279,8 +292,9 @@ __global__ void k_ir_scale(const double* __restrict__ r64, T* __restrict__ r, T*
 
 template <typename T>
 __global__ void k_ir_update(double* __restrict__ x64, const T* __restrict__ d, int ld, int n,
-                            const int* __restrict__ oact, const double* __restrict__ colnorm) {
-    if (!oact[blockIdx.y]) return;
+                            const int* __restrict__ oact, const double* __restrict__ colnorm,
+                            const int* __restrict__ inner, const int* __restrict__ tdone) {
+    if (!ir_step_on(blockIdx.y, oact, inner, tdone)) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     col(x64, ld)[k] += colnorm[blockIdx.y] * (double)col(d, ld)[k];
@@ -308,11 +322,12 @@ __global__ void k_fill_int(int n, int v, int* __restrict__ a) {
     if (i < n) a[i] = v;
 }
 
-__global__ void k_bb_init(ColState* st, int nc) {
+__global__ void k_bb_init(ColState* st, int* tdone, int nc) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < nc) {
         st[c].bb = 1.0;
         st[c].its = 0.0;
+        tdone[c] = 0;
     }
 }
 
@@ -389,7 +404,7 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp, int ninst,
     if (nc_coarse_ > 81) fail(HINV_EINVAL, "coarsest multigrid level too large (N must be a power of two)");
     cinv64_.ensure(ni * nc_coarse_ * nc_coarse_);
     cinv32_.ensure(ni * nc_coarse_ * nc_coarse_);
-    HINV_HIP(hipHostMalloc((void**)&host_flags_, sizeof(int) * 4096, hipHostMallocDefault));
+    HINV_HIP(hipHostMalloc((void**)&host_flags_, sizeof(int) * 2 * 4096, hipHostMallocDefault));
     HINV_HIP(hipHostMalloc((void**)&host_st_, sizeof(ColState) * 2 * 4096, hipHostMallocDefault));
     HINV_HIP(hipStreamCreateWithFlags(&gs_, hipStreamNonBlocking));
     launch_stream_ = ctx_->stream;
@@ -534,6 +549,7 @@ void Hierarchy::ensure_cols(int nc) {
     st_.ensure(nc);
     act_.ensure(nc);
     oact_.ensure(nc);
+    tdone_.ensure(nc);
     colnorm_.ensure(nc);
     if (nc > 4096) fail(HINV_EINVAL, "more than 4096 right-hand sides in one call");
     cap_ = nc;
@@ -983,7 +999,7 @@ void Hierarchy::drop_graphs() {
 // the host checks for completion after a run of replays (kernels of finished
 // columns return at once).
 template <typename T>
-void Hierarchy::pcg(int nc, int max_iter, int* iters) {
+bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()>* tail) {
     hipStream_t s = ctx_->stream;
     launch_stream_ = s;
     int* act = act_.get();
@@ -1018,8 +1034,10 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
     int expect = 0;
     for (const auto& kv : last_iters_)
         if (kv.first == key) expect = kv.second;
-    bool first_check = true;
-    ColState* hst = host_st_ + 4096;  // pinned, so the read-back needs no staging copy
+    bool first_check = true, tail_state = false;
+    // pinned, so the read-backs need no staging copy; with a tail the column
+    // states are read into the refinement loop's slot (the tail wrote them)
+    ColState* hst = tail ? host_st_ : host_st_ + 4096;
     while (it < max_iter) {
         int reps = 1;
         if (first_check && expect > it + 2) reps = std::min(6, (expect - it + 1) / 2);
@@ -1050,13 +1068,18 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
             it += 2;
         }
         if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
+        if (tail) (*tail)();
         HINV_HIP(hipMemcpyAsync(host_flags_, act, sizeof(int) * nc, hipMemcpyDeviceToHost, s));
+        if (tail) HINV_HIP(hipMemcpyAsync(host_flags_ + 4096, oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToHost, s));
         HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
         HINV_HIP(hipStreamSynchronize(s));
         first_check = false;
         int live = 0;
         for (int c = 0; c < nc; ++c) live += host_flags_[c];
-        if (!live) break;
+        if (!live) {
+            tail_state = tail != nullptr;
+            break;
+        }
     }
     int taken = 0;
     for (int c = 0; c < nc; ++c) taken = std::max(taken, (int)hst[c].its);
@@ -1069,6 +1092,7 @@ void Hierarchy::pcg(int nc, int max_iter, int* iters) {
             found = true;
         }
     if (!found) last_iters_.push_back({key, taken});
+    return tail_state;
 }
 
 void Hierarchy::apply(int nc, const double* x, int ldx, double* y, int ldy) {
@@ -1126,17 +1150,14 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     auto launch_init = [&](auto op) {
         k_ir_init<<<g, kBlock, 0, s>>>(op, b, ldb, x64_.get(), r64_.get(), ld, partial_.get());
     };
-    auto launch_res = [&](auto op) {
-        k_ir_residual<<<g, kBlock, 0, s>>>(op, b, ldb, x64_.get(), r64_.get(), ld, oact_.get(),
-                                           partial_.get());
-    };
     with_op<double>(0, launch_init);
     HINV_LAUNCH_CHECK();
     const double floor32 = inner_tol32, floor64 = 1e-14;
     k_ir_finalize<<<nc, kBlock, 0, s>>>(1, partial_.get(), nblk, st_.get(), oact_.get(),
-                                        colnorm_.get(), rtol, fp32 ? floor32 : floor64);
+                                        colnorm_.get(), rtol, fp32 ? floor32 : floor64, nullptr, nullptr);
     HINV_LAUNCH_CHECK();
     int iters = 0, outer = 0, fallbacks = 0;
+    bool have_state = false;  // host_flags_ + 4096 and host_st_ already hold this pass's outer state
     const int max_outer = fp32 ? 16 : 4;
     bool use32 = fp32;
     std::vector<double> prev_rr(nc, INFINITY);  // unknown before the first pass
@@ -1146,9 +1167,14 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
         // the first pass starts without reading the flags back: its kernels
         // skip the columns that are already converged (b = 0)
         if (outer > 0) {
-            HINV_HIP(hipMemcpyAsync(host_flags_, oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToHost, s));
-            HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
-            HINV_HIP(hipStreamSynchronize(s));
+            if (have_state) {
+                std::memcpy(host_flags_, host_flags_ + 4096, sizeof(int) * nc);
+            } else {
+                HINV_HIP(hipMemcpyAsync(host_flags_, oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToHost, s));
+                HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
+                HINV_HIP(hipStreamSynchronize(s));
+            }
+            have_state = false;
             int live = 0;
             for (int c = 0; c < nc; ++c) live += host_flags_[c];
             if (!live) {
@@ -1180,35 +1206,48 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
                 ensure_work(w64_, lev_, nc);
                 // recompute the inner tolerances for FP64 from the current residuals
                 k_ir_finalize<<<nc, kBlock, 0, s>>>(0, partial_.get(), nblk, st_.get(), oact_.get(),
-                                                    colnorm_.get(), rtol, floor64);
+                                                    colnorm_.get(), rtol, floor64, nullptr, nullptr);
                 HINV_LAUNCH_CHECK();
             }
         }
         HINV_HIP(hipMemcpyAsync(act_.get(), oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToDevice, s));
         // the inner right-hand side has unit norm; its tolerance sits in tol2
-        k_bb_init<<<ceil_div(nc, 64), 64, 0, s>>>(st_.get(), nc);
+        k_bb_init<<<ceil_div(nc, 64), 64, 0, s>>>(st_.get(), tdone_.get(), nc);
         HINV_LAUNCH_CHECK();
+        // refinement step x64 += |r| x_inner, r64 = b - A x64, outer bookkeeping;
+        // with inner flags given, only for the columns whose PCG has finished
+        // (and once per pass)
+        auto step = [&](auto* xin, const int* inner) {
+            using TI = std::remove_pointer_t<decltype(xin)>;
+            k_ir_update<TI><<<g, kBlock, 0, s>>>(x64_.get(), xin, ld, n, oact_.get(), colnorm_.get(), inner,
+                                                 tdone_.get());
+            HINV_LAUNCH_CHECK();
+            with_op<double>(0, [&](auto op) {
+                k_ir_residual<<<g, kBlock, 0, s>>>(op, b, ldb, x64_.get(), r64_.get(), ld, oact_.get(), inner,
+                                                   tdone_.get(), partial_.get());
+            });
+            HINV_LAUNCH_CHECK();
+            k_ir_finalize<<<nc, kBlock, 0, s>>>(0, partial_.get(), nblk, st_.get(), oact_.get(), colnorm_.get(),
+                                                rtol, use32 ? floor32 : floor64, inner, tdone_.get());
+            HINV_LAUNCH_CHECK();
+        };
         if (use32) {
             k_ir_scale<float><<<g, kBlock, 0, s>>>(r64_.get(), w32_.r.get(), w32_.x.get(), ld, n,
                                                    oact_.get(), colnorm_.get());
             HINV_LAUNCH_CHECK();
             pcg<float>(nc, max_iter - iters, &iters);
-            k_ir_update<float><<<g, kBlock, 0, s>>>(x64_.get(), w32_.x.get(), ld, n, oact_.get(),
-                                                    colnorm_.get());
+            step(w32_.x.get(), nullptr);
         } else {
             k_ir_scale<double><<<g, kBlock, 0, s>>>(r64_.get(), w64_.r.get(), w64_.x.get(), ld, n,
                                                     oact_.get(), colnorm_.get());
             HINV_LAUNCH_CHECK();
-            pcg<double>(nc, max_iter - iters, &iters);
-            k_ir_update<double><<<g, kBlock, 0, s>>>(x64_.get(), w64_.x.get(), ld, n, oact_.get(),
-                                                     colnorm_.get());
+            // the step is enqueued before each completion check of the PCG, so
+            // that one read-back serves both checks when the PCG has finished
+            const std::function<void()> tail = [&] { step(w64_.x.get(), act_.get()); };
+            have_state = pcg<double>(nc, max_iter - iters, &iters, &tail);
+            // stopped at the iteration limit: unfinished columns take the step they have
+            if (!have_state) step(w64_.x.get(), nullptr);
         }
-        HINV_LAUNCH_CHECK();
-        with_op<double>(0, launch_res);
-        HINV_LAUNCH_CHECK();
-        k_ir_finalize<<<nc, kBlock, 0, s>>>(0, partial_.get(), nblk, st_.get(), oact_.get(),
-                                            colnorm_.get(), rtol, use32 ? floor32 : floor64);
-        HINV_LAUNCH_CHECK();
         ++outer;
         if (trace_on()) trace_cols(s, "outer", outer, st_.get(), oact_.get(), nc);
     }
