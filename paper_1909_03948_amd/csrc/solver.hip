@@ -277,12 +277,22 @@ __global__ void k_ir_finalize(int first, const double* __restrict__ partial, int
     }
 }
 
-// Inner right-hand side r / |r| in precision T; zero initial guess.
+// Inner right-hand side r / |r| in precision T; zero initial guess.  The first
+// workgroup of each column also starts the pass's column state: inner flag =
+// outer flag, unit |b|^2, no PCG iterations, refinement step not yet taken.
 template <typename T>
 __global__ void k_ir_scale(const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x,
                            int ld, int n, const int* __restrict__ oact,
-                           const double* __restrict__ colnorm) {
-    if (!oact[blockIdx.y]) return;
+                           const double* __restrict__ colnorm, int* __restrict__ act,
+                           ColState* __restrict__ st, int* __restrict__ tdone) {
+    const int c = blockIdx.y;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        act[c] = oact[c];
+        st[c].bb = 1.0;
+        st[c].its = 0.0;
+        tdone[c] = 0;
+    }
+    if (!oact[c]) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const double s = 1.0 / colnorm[blockIdx.y];
@@ -322,14 +332,6 @@ __global__ void k_fill_int(int n, int v, int* __restrict__ a) {
     if (i < n) a[i] = v;
 }
 
-__global__ void k_bb_init(ColState* st, int* tdone, int nc) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < nc) {
-        st[c].bb = 1.0;
-        st[c].its = 0.0;
-        tdone[c] = 0;
-    }
-}
 
 // State operator of level L for instance inst alone.
 template <typename T>
@@ -1147,8 +1149,13 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
         ensure_work(w64_, lev_, nc);
     const int n = n_, ld = n, nblk = ceil_div(n, kBlock);
     const dim3 g = grid2(n, nc);
+    // the FP64 iterate lives in the caller's x when its columns are contiguous
+    // and do not overlap b (x is output only), else in x64_ and is copied out
+    const auto lo = [](const void* p) { return reinterpret_cast<uintptr_t>(p); };
+    const bool disjoint = lo(x + (size_t)ldx * nc) <= lo(b) || lo(b + (size_t)ldb * nc) <= lo(x);
+    double* const xw = (ldx == n && disjoint) ? x : x64_.get();
     auto launch_init = [&](auto op) {
-        k_ir_init<<<g, kBlock, 0, s>>>(op, b, ldb, x64_.get(), r64_.get(), ld, partial_.get());
+        k_ir_init<<<g, kBlock, 0, s>>>(op, b, ldb, xw, r64_.get(), ld, partial_.get());
     };
     with_op<double>(0, launch_init);
     HINV_LAUNCH_CHECK();
@@ -1210,21 +1217,18 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
                 HINV_LAUNCH_CHECK();
             }
         }
-        HINV_HIP(hipMemcpyAsync(act_.get(), oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToDevice, s));
-        // the inner right-hand side has unit norm; its tolerance sits in tol2
-        k_bb_init<<<ceil_div(nc, 64), 64, 0, s>>>(st_.get(), tdone_.get(), nc);
-        HINV_LAUNCH_CHECK();
+        // (k_ir_scale starts the pass's column state: the inner right-hand
+        // side has unit norm, its tolerance sits in tol2)
         // refinement step x64 += |r| x_inner, r64 = b - A x64, outer bookkeeping;
         // with inner flags given, only for the columns whose PCG has finished
         // (and once per pass)
         auto step = [&](auto* xin, const int* inner) {
             using TI = std::remove_pointer_t<decltype(xin)>;
-            k_ir_update<TI><<<g, kBlock, 0, s>>>(x64_.get(), xin, ld, n, oact_.get(), colnorm_.get(), inner,
-                                                 tdone_.get());
+            k_ir_update<TI><<<g, kBlock, 0, s>>>(xw, xin, ld, n, oact_.get(), colnorm_.get(), inner, tdone_.get());
             HINV_LAUNCH_CHECK();
             with_op<double>(0, [&](auto op) {
-                k_ir_residual<<<g, kBlock, 0, s>>>(op, b, ldb, x64_.get(), r64_.get(), ld, oact_.get(), inner,
-                                                   tdone_.get(), partial_.get());
+                k_ir_residual<<<g, kBlock, 0, s>>>(op, b, ldb, xw, r64_.get(), ld, oact_.get(), inner, tdone_.get(),
+                                                   partial_.get());
             });
             HINV_LAUNCH_CHECK();
             k_ir_finalize<<<nc, kBlock, 0, s>>>(0, partial_.get(), nblk, st_.get(), oact_.get(), colnorm_.get(),
@@ -1232,14 +1236,14 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
             HINV_LAUNCH_CHECK();
         };
         if (use32) {
-            k_ir_scale<float><<<g, kBlock, 0, s>>>(r64_.get(), w32_.r.get(), w32_.x.get(), ld, n,
-                                                   oact_.get(), colnorm_.get());
+            k_ir_scale<float><<<g, kBlock, 0, s>>>(r64_.get(), w32_.r.get(), w32_.x.get(), ld, n, oact_.get(),
+                                                   colnorm_.get(), act_.get(), st_.get(), tdone_.get());
             HINV_LAUNCH_CHECK();
             pcg<float>(nc, max_iter - iters, &iters);
             step(w32_.x.get(), nullptr);
         } else {
-            k_ir_scale<double><<<g, kBlock, 0, s>>>(r64_.get(), w64_.r.get(), w64_.x.get(), ld, n,
-                                                    oact_.get(), colnorm_.get());
+            k_ir_scale<double><<<g, kBlock, 0, s>>>(r64_.get(), w64_.r.get(), w64_.x.get(), ld, n, oact_.get(),
+                                                    colnorm_.get(), act_.get(), st_.get(), tdone_.get());
             HINV_LAUNCH_CHECK();
             // the step is enqueued before each completion check of the PCG, so
             // that one read-back serves both checks when the PCG has finished
@@ -1251,8 +1255,10 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
         ++outer;
         if (trace_on()) trace_cols(s, "outer", outer, st_.get(), oact_.get(), nc);
     }
-    k_copy_cols<<<g, kBlock, 0, s>>>(x64_.get(), ld, x, ldx, n);
-    HINV_LAUNCH_CHECK();
+    if (xw != x) {
+        k_copy_cols<<<g, kBlock, 0, s>>>(xw, ld, x, ldx, n);
+        HINV_LAUNCH_CHECK();
+    }
     // final relative residuals: the column states read with the last flags
     // (no refinement step ran after that read)
     double worst = 0.0;
