@@ -82,7 +82,7 @@ class Hierarchy {
     int N() const { return N_; }
     int n() const { return n_; }
     int ninst() const { return ninst_; }
-    double inner_tol32 = 1e-5;  // FP32 inner relative tolerance of the refinement loop
+    double inner_tol32 = 1e-5;  // FP32 inner relative tolerance of the refinement loop (its lower bound)
 
   private:
     // Runs the PCG iterations of the current inner solve.  tail, when given,
@@ -147,6 +147,9 @@ class Hierarchy {
     DBuf<double> cinv64_;
     DBuf<float> cinv32_;
     int nc_coarse_ = 0;
+    // Largest true-residual reduction of one FP32 refinement pass (after the
+    // first) in the last FP32 solve: the inner PCG is not run much below it.
+    double rho32_ = 0.0;
     // refinement state
     int cap_ = 0;
     DBuf<double> x64_, r64_;

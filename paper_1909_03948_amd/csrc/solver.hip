@@ -152,40 +152,48 @@ __global__ void k_coarse_matrix(Op op, double* __restrict__ M) {
     M[id] = v;
 }
 
-// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting), one workgroup.
-// Pivot step p:  a = M[p][p];  M[i][j] -= M[i][p] M[p][j] / a (i, j != p);
-// M[p][j] /= a;  M[i][p] = -M[i][p] / a;  M[p][p] = 1 / a.
-__global__ void k_gauss_jordan(int n, double* __restrict__ M) {
+// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting), one workgroup
+// of 1024 threads, n <= kGJMaxN.  Pivot step p:  a = M[p][p];
+// M[i][j] -= M[i][p] M[p][j] / a (i, j != p);  M[p][j] /= a;
+// M[i][p] = -M[i][p] / a;  M[p][p] = 1 / a.  Thread t owns column t mod 128 of
+// rows t / 128, t / 128 + 8, ... (no index divisions in the pivot steps).
+constexpr int kGJMaxN = 128;
+__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict__ M) {
     extern __shared__ double sm[];
     double* A = sm;            // n*n
     double* rowp = sm + n * n;  // n
     double* colp = rowp + n;    // n
-    for (int id = threadIdx.x; id < n * n; id += blockDim.x) A[id] = M[id];
+    constexpr int kRowStep = 1024 / kGJMaxN;
+    const int j = threadIdx.x & (kGJMaxN - 1), i0 = threadIdx.x / kGJMaxN;
+    if (j < n)
+        for (int i = i0; i < n; i += kRowStep) A[i * n + j] = M[i * n + j];
     __syncthreads();
     for (int p = 0; p < n; ++p) {
-        for (int id = threadIdx.x; id < n; id += blockDim.x) {
-            rowp[id] = A[p * n + id];
-            colp[id] = A[id * n + p];
+        if ((int)threadIdx.x < n) {
+            rowp[threadIdx.x] = A[p * n + threadIdx.x];
+            colp[threadIdx.x] = A[threadIdx.x * n + p];
         }
         __syncthreads();
-        const double a = rowp[p];
-        const double ia = 1.0 / a;
-        for (int id = threadIdx.x; id < n * n; id += blockDim.x) {
-            const int i = id / n, j = id % n;
-            double v;
-            if (i == p && j == p)
-                v = ia;
-            else if (i == p)
-                v = rowp[j] * ia;
-            else if (j == p)
-                v = -colp[i] * ia;
-            else
-                v = A[id] - colp[i] * rowp[j] * ia;
-            A[id] = v;
+        const double ia = 1.0 / rowp[p];
+        if (j < n) {
+            const double rj = rowp[j];
+            for (int i = i0; i < n; i += kRowStep) {
+                double v;
+                if (i == p && j == p)
+                    v = ia;
+                else if (i == p)
+                    v = rj * ia;
+                else if (j == p)
+                    v = -colp[i] * ia;
+                else
+                    v = A[i * n + j] - colp[i] * rj * ia;
+                A[i * n + j] = v;
+            }
         }
         __syncthreads();
     }
-    for (int id = threadIdx.x; id < n * n; id += blockDim.x) M[id] = A[id];
+    if (j < n)
+        for (int i = i0; i < n; i += kRowStep) M[i * n + j] = A[i * n + j];
 }
 
 __global__ void k_cast_d2f(const double* a, float* b, int n) {
@@ -458,6 +466,7 @@ void Hierarchy::build_coarse(int inst) {
         k_coarse_matrix<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(
             make_prior_op<double>(L.N, inst_pp_[inst].gamma, inst_pp_[inst].delta, inst_pp_[inst].beta), c64);
     HINV_LAUNCH_CHECK();
+    if (nc > kGJMaxN) fail(HINV_EINVAL, "coarse level too large for the dense inverse");
     const size_t shm = sizeof(double) * ((size_t)nc * nc + 2 * nc);
     k_gauss_jordan<<<1, 1024, shm, s>>>(nc, c64);
     HINV_LAUNCH_CHECK();
@@ -1159,7 +1168,13 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     };
     with_op<double>(0, launch_init);
     HINV_LAUNCH_CHECK();
-    const double floor32 = inner_tol32, floor64 = 1e-14;
+    // FP32 refinement: a pass reduces the true residual by no more than about
+    // kappa eps_32, whatever the inner tolerance, so the inner PCG stops at half
+    // the reduction the passes of the last FP32 solve achieved (never below
+    // inner_tol32, never above 0.1); it adapts within the solve as passes are seen.
+    const auto floor_for = [&](double rho) { return std::min(0.1, std::max(inner_tol32, 0.5 * rho)); };
+    double floor32 = floor_for(rho32_), rho_seen = 0.0;
+    const double floor64 = 1e-14;
     k_ir_finalize<<<nc, kBlock, 0, s>>>(1, partial_.get(), nblk, st_.get(), oact_.get(),
                                         colnorm_.get(), rtol, fp32 ? floor32 : floor64, nullptr, nullptr);
     HINV_LAUNCH_CHECK();
@@ -1168,6 +1183,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     const int max_outer = fp32 ? 16 : 4;
     bool use32 = fp32;
     std::vector<double> prev_rr(nc, INFINITY);  // unknown before the first pass
+    std::vector<int> prev_on(nc, 0);             // outer flags at the start of the last pass
     ColState* hst = host_st_;  // pinned, so the read-backs need no staging copy
     bool converged = false;
     while (true) {
@@ -1204,7 +1220,22 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
             if (outer > 0) {
                 for (int c = 0; c < nc; ++c)
                     if (host_flags_[c] && hst[c].rr > 1e-2 * prev_rr[c]) stalled = true;
-                for (int c = 0; c < nc; ++c) prev_rr[c] = hst[c].rr;
+                if (outer >= 2)
+                    for (int c = 0; c < nc; ++c)
+                        if (prev_on[c] && prev_rr[c] > 0.0)
+                            rho_seen = std::max(rho_seen, std::sqrt(hst[c].rr / prev_rr[c]));
+                for (int c = 0; c < nc; ++c) {
+                    prev_rr[c] = hst[c].rr;
+                    prev_on[c] = host_flags_[c];
+                }
+                // the inner tolerances of the coming pass from the reductions seen
+                const double f = floor_for(rho_seen);
+                if (!stalled && f > 2.0 * floor32) {
+                    floor32 = f;
+                    k_ir_finalize<<<nc, kBlock, 0, s>>>(0, partial_.get(), nblk, st_.get(), oact_.get(),
+                                                        colnorm_.get(), rtol, floor32, nullptr, nullptr);
+                    HINV_LAUNCH_CHECK();
+                }
             }
             if (stalled) {
                 use32 = false;
@@ -1259,6 +1290,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
         k_copy_cols<<<g, kBlock, 0, s>>>(xw, ld, x, ldx, n);
         HINV_LAUNCH_CHECK();
     }
+    if (fp32 && rho_seen > 0.0) rho32_ = rho_seen;
     // final relative residuals: the column states read with the last flags
     // (no refinement step ran after that read)
     double worst = 0.0;
