@@ -4,7 +4,7 @@
 //   k_down: x2 = S(b) (two Chebyshev steps from zero), r = b - A x2, b_coarse = P^T r
 //   k_up:   x = x2 + P x_coarse, then two Chebyshev steps on A x = b
 // and one kernel for all levels with N_l <= kBottomN (one workgroup per column,
-// every vector in LDS, the coarsest level solved with its dense inverse).
+// every vector in LDS in FP32, the coarsest level solved with its dense inverse).
 // PCG reductions finish in the producing kernel: the last workgroup of a column
 // to arrive sums the per-workgroup partials in a fixed order.
 #pragma once
@@ -20,8 +20,7 @@ constexpr int kTCBig = 16, kTFBig = 32;      // coarse / fine nodes per tile sid
 constexpr int kTCSmall = 8, kTFSmall = 16;
 constexpr int kSmallTileCols = 8;            // batches below this use the small tiles
 constexpr int kBottomN = 32;   // levels with N_l <= kBottomN run in the bottom kernel
-constexpr int kBottomNodes = 33 * 33 + 17 * 17 + 9 * 9;  // nodes of all bottom levels
-constexpr int kBottomLevels = 3;
+constexpr int kBottomLevels = 4;  // at most (N_l = 64, 32, 16, 8 when kBottomN = 64)
 
 // Chebyshev degree-2 coefficients passed to the smoothing kernels.
 struct ChebCoef {
@@ -311,17 +310,23 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
 }
 
 // -------------------------------------------------------------- bottom ---
-// All levels with N_l <= kBottomN for one column in one workgroup.
-template <typename T>
+// All levels with N_l <= kBottomN (up to four: 64, 32, 16, 8) for one column in
+// one workgroup of 1024 threads.  The bottom computes in FP32 whatever the
+// solve's precision: it is the coarse correction of a preconditioner, so its
+// rounding changes the preconditioner slightly but no result (the PCG and the
+// refinement test residuals of the solve's own precision), and FP32 halves the
+// LDS a level takes, so that the level-64 sweeps run here instead of in two
+// more launches per V-cycle.  b and x are global level-Lb vectors of the
+// solve's precision TV.
 struct BottomArgs {
-    int nlev;                       // levels handled here (the last is the coarsest)
+    int nlev;                           // levels handled here (the last is the coarsest)
     int N[kBottomLevels];
-    const T* wE[kBottomLevels];     // state operator coefficients (unused for the prior)
-    const T* wN[kBottomLevels];
-    const T* dinv[kBottomLevels];
-    const T* cinv;                  // dense inverse of the coarsest level
-    int nc;                         // its size
-    KARow<T> ka[kBottomLevels][9];  // prior operator rows of each level
+    const float* wE[kBottomLevels];     // state operator coefficients (unused for the prior)
+    const float* wN[kBottomLevels];
+    const float* dinv[kBottomLevels];
+    const float* cinv;                  // dense inverse of the coarsest level
+    int nc;                             // its size
+    KARow<float> ka[kBottomLevels][9];  // prior operator rows of each level
     // stacked instances (cpi = 0: one instance): column c belongs to instance
     // c / cpi, whose state coefficients of level l start cs[l] elements further,
     // whose coarse inverse starts cinv_stride further and whose prior rows of
@@ -329,52 +334,70 @@ struct BottomArgs {
     int cpi;
     long long cs[kBottomLevels];
     long long cinv_stride;
-    const KARow<T>* karows[kBottomLevels];
+    const KARow<float>* karows[kBottomLevels];
 };
 
 // Bottom levels in LDS with a ring of zeros around each level (padded width
-// P_l = N_l + 3): the tile stencil applies without boundary branches, and
-// Dirichlet rows are masked by their zero inverse diagonal.
-constexpr int kBottomPadded = 35 * 35 + 19 * 19 + 11 * 11;
+// P_l = N_l + 3): the stencil applies without boundary branches (an absent
+// neighbour has a zero coupling and a zero value), and Dirichlet rows are
+// masked by their zero inverse diagonal.  Sizes for a top level of at most
+// TOP (a power of two, at least 8).
+template <int TOP>
+constexpr int bottom_padded() {
+    int s = 0;
+    for (int n = TOP; n >= 8; n /= 2) s += (n + 3) * (n + 3);
+    return s;
+}
+template <int TOP>
+constexpr int bottom_nodes() {
+    int s = 0;
+    for (int n = TOP; n >= 8; n /= 2) s += (n + 1) * (n + 1);
+    return s;
+}
+// node slots of a thread on level l (a level of N has (N + 1)^2 nodes)
+template <int TOP>
+constexpr int bottom_slots(int l) {
+    return l < kBottomLevels && (TOP >> l) >= 8 ? (((TOP >> l) + 1) * ((TOP >> l) + 1) + 1023) / 1024 : 0;
+}
 
-// q / d for 0 <= q < 2^16 and 1 <= d <= 64 by a float reciprocal: (q + 1/2) / d
-// lies at least 1 / (2 d) from an integer and the float product errs by less
-// than 2^-20 (q / d), so the truncation is exact (integer division is a long
-// instruction sequence on the vector ALU).
+// q / d for 0 <= q < 2^22 and d >= 1 by a float reciprocal: (q + 1/2) / d lies
+// at least 1 / (2 d) from an integer and the float product errs by less than
+// 2^-23 (q / d) < 1 / (2 d), so the truncation is exact (integer division is a
+// long instruction sequence on the vector ALU).
 __device__ inline int small_div(int q, float inv_d) { return (int)(((float)q + 0.5f) * inv_d); }
 
-// x_top = V-cycle(b_top) for every column (blockIdx.x = column).  b and x are
-// global level-Lb vectors.  When rv is given (the bottom is the whole
-// hierarchy), sum_k rv_k x_k is written as the single partial of r^T z.
-// Each thread keeps, per level, the padded positions of its nodes (node
-// q = threadIdx.x + 1024 s of the level), the fine position under a coarse
-// node and the two coarse ends used by the prolongation.
-template <typename T, int KIND>
-__global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __restrict__ bg, T* __restrict__ xg,
+// x_top = V-cycle(b_top) for every column (blockIdx.x = column).  When rv is
+// given (the bottom is the whole hierarchy), sum_k rv_k x_k is written as the
+// single partial of r^T z.  Thread t holds the nodes q = t + 1024 s of each
+// level (padded position and (i, j) per slot).
+template <typename TV, int KIND, int TOP>
+__global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restrict__ bg, TV* __restrict__ xg,
                                                  int ld, int* __restrict__ act, ChebCoef cc,
-                                                 const T* __restrict__ rv, PcgRed red,
+                                                 const TV* __restrict__ rv, PcgRed red,
                                                  ColState* __restrict__ st, int check) {
-    constexpr bool NE = KIND == kOpPrior;
-    constexpr int PN = kBottomPadded, NT = 1024, NS = 2, LV = kBottomLevels;
+    constexpr bool PRIOR = KIND == kOpPrior;
+    constexpr int PN = bottom_padded<TOP>(), NT = 1024, LV = kBottomLevels, MS = bottom_slots<TOP>(0);
     const int col = blockIdx.x;
     if (act && !act[col]) return;
     if (check && column_done(red, col, st, act, true)) return;
-    __shared__ T sb[PN], sx[PN], sw[PN];  // right-hand side, iterate, work vector
-    __shared__ T tc[PN], te[PN], tn[PN], tdv[PN], tg[NE ? PN : 1];
-    __shared__ KARow<T> rows[LV * 9];
+    __shared__ float sb[PN], sx[PN], sw[PN];  // right-hand side, iterate, work vector
+    __shared__ float te[PRIOR ? 1 : PN], tn[PRIOR ? 1 : PN], tdv[PRIOR ? 1 : PN];  // -wE, -wN, 1/diag
+    __shared__ KARow<float> rows[PRIOR ? LV * 9 : 1];
     const int inst = a.cpi ? col / a.cpi : 0;
-    const int L = a.nlev - 1;  // the coarsest level, solved with its dense inverse
+    const int nlev = a.nlev, L = nlev - 1;  // L: the coarsest level, solved with its dense inverse
     int Nl[LV], Pl[LV], po[LV], uo[LV + 1];
+    float inv_n1[LV];
     {
         int p = 0, u = 0;
 #pragma unroll
         for (int l = 0; l < LV; ++l) {
-            const int n = l < a.nlev ? a.N[l] : 0;
+            const int n = l < nlev ? a.N[l] : 0;
             Nl[l] = n;
             Pl[l] = n + 3;
             po[l] = p;
             uo[l] = u;
-            if (l < a.nlev) {
+            inv_n1[l] = 1.0f / (float)(n + 1);
+            if (l < nlev) {
                 p += (n + 3) * (n + 3);
                 u += (n + 1) * (n + 1);
             }
@@ -384,159 +407,163 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
     const int n0 = uo[1];
     // ---- loads: b, the state coefficients (unpadded concatenation of the
     // levels), this thread's part of the dense coarse inverse
-    constexpr int EB = (kBottomNodes + NT - 1) / NT, S = 12, kCU = 8;
-    T vb[EB], vE[EB], vN[EB], vD[EB];
-    int vp[EB], vlev[EB], vi[EB], vj[EB];
+    constexpr int EB = (bottom_nodes<TOP>() + NT - 1) / NT, S = 12, kCU = 8;
+    float vb[EB], vE[EB], vN[EB], vD[EB];
+    int vp[EB], vl[EB], vij[EB];
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
         const int t = threadIdx.x + NT * e;
-        const int l = (t >= uo[1]) + (t >= uo[2]);
+        const int l = (t >= uo[1]) + (t >= uo[2]) + (t >= uo[3]);
         const bool in = t < uo[LV];
-        const int q = t - (l == 0 ? 0 : (l == 1 ? uo[1] : uo[2]));
-        const int N1 = (l == 0 ? Nl[0] : (l == 1 ? Nl[1] : Nl[2])) + 1;
-        const int j = small_div(q, 1.0f / (float)N1);
+        const int q = t - (l == 0 ? 0 : (l == 1 ? uo[1] : (l == 2 ? uo[2] : uo[3])));
+        const int N1 = (l == 0 ? Nl[0] : (l == 1 ? Nl[1] : (l == 2 ? Nl[2] : Nl[3]))) + 1;
+        const int j = small_div(q, l == 0 ? inv_n1[0] : (l == 1 ? inv_n1[1] : (l == 2 ? inv_n1[2] : inv_n1[3])));
         const int P = N1 + 2, i = q - j * N1;
-        vlev[e] = l;
-        vi[e] = i;
-        vj[e] = j;
-        vp[e] = in ? (l == 0 ? po[0] : (l == 1 ? po[1] : po[2])) + (j + 1) * P + i + 1 : -1;
-        vb[e] = t < n0 ? bg[(size_t)col * ld + t] : (T)0;
-        vE[e] = vN[e] = vD[e] = 0;
-        if constexpr (KIND == kOpState) {
-            const long long cs = l == 0 ? a.cs[0] : (l == 1 ? a.cs[1] : a.cs[2]);
+        vl[e] = l;
+        vij[e] = i | (j << 16);
+        vp[e] = in ? (l == 0 ? po[0] : (l == 1 ? po[1] : (l == 2 ? po[2] : po[3]))) + (j + 1) * P + i + 1 : -1;
+        vb[e] = t < n0 ? (float)bg[(size_t)col * ld + t] : 0.0f;
+        vE[e] = vN[e] = vD[e] = 0.0f;
+        if constexpr (!PRIOR) {
+            const long long cs = l == 0 ? a.cs[0] : (l == 1 ? a.cs[1] : (l == 2 ? a.cs[2] : a.cs[3]));
             const long long at = (a.cpi ? inst * cs : 0) + q;
-            const T* pE = l == 0 ? a.wE[0] : (l == 1 ? a.wE[1] : a.wE[2]);
-            const T* pN = l == 0 ? a.wN[0] : (l == 1 ? a.wN[1] : a.wN[2]);
-            const T* pD = l == 0 ? a.dinv[0] : (l == 1 ? a.dinv[1] : a.dinv[2]);
-            vE[e] = in ? pE[at] : (T)0;
-            vN[e] = in ? pN[at] : (T)0;
-            vD[e] = in ? pD[at] : (T)0;
+            const float* pE = l == 0 ? a.wE[0] : (l == 1 ? a.wE[1] : (l == 2 ? a.wE[2] : a.wE[3]));
+            const float* pN = l == 0 ? a.wN[0] : (l == 1 ? a.wN[1] : (l == 2 ? a.wN[2] : a.wN[3]));
+            const float* pD = l == 0 ? a.dinv[0] : (l == 1 ? a.dinv[1] : (l == 2 ? a.dinv[2] : a.dinv[3]));
+            vE[e] = in ? pE[at] : 0.0f;
+            vN[e] = in ? pN[at] : 0.0f;
+            vD[e] = in ? pD[at] : 0.0f;
         }
     }
-    const T* ci = a.cinv + (a.cpi ? inst * a.cinv_stride : 0);
+    const float* ci = a.cinv + (a.cpi ? inst * a.cinv_stride : 0);
     const int cr = threadIdx.x / S, cpart = threadIdx.x % S;
-    T cv[kCU];
+    float cv[kCU];
 #pragma unroll
     for (int u = 0; u < kCU; ++u) {
         const int c = cpart + u * S;
-        cv[u] = (cr < a.nc && c < a.nc) ? ci[cr * a.nc + c] : (T)0;
+        cv[u] = (cr < a.nc && c < a.nc) ? ci[cr * a.nc + c] : 0.0f;
     }
-    // ---- per-thread geometry: node positions, restriction and prolongation
-    int pi[LV][NS], fi[LV][NS], ca0[LV][NS], ca1[LV][NS];
-    bool ev[LV][NS];
+    // ---- per-thread slots: padded position (-1 past the level) and (i, j)
+    int sp[LV][MS], sij[LV][MS];
 #pragma unroll
     for (int l = 0; l < LV; ++l)
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
+        for (int s = 0; s < MS; ++s) {
+            if (s >= bottom_slots<TOP>(l)) break;
             const int q = threadIdx.x + NT * s;
-            const int N1 = Nl[l] + 1, P = Pl[l];
-            const bool in = l < a.nlev && q < N1 * N1;
-            const int jq = small_div(q, 1.0f / (float)N1);
+            const int N1 = Nl[l] + 1;
+            const bool in = l < nlev && q < N1 * N1;
+            const int jq = small_div(q, inv_n1[l]);
             const int i = in ? q - jq * N1 : 0, j = in ? jq : 0;
-            pi[l][s] = in ? po[l] + (j + 1) * P + i + 1 : -1;
-            fi[l][s] = (in && l > 0) ? po[l - 1] + (2 * j + 1) * Pl[l - 1] + 2 * i + 1 : -1;
-            if (l + 1 < LV) {
-                const int I = i >> 1, J = j >> 1, Pc = Pl[l + 1];
-                ca0[l][s] = po[l + 1] + (J + 1) * Pc + I + 1;
-                ca1[l][s] = po[l + 1] + (J + 1 + (j & 1)) * Pc + I + 1 + (i & 1);
-                ev[l][s] = !((i | j) & 1);
-            } else {
-                ca0[l][s] = ca1[l][s] = 0;
-                ev[l][s] = true;
-            }
+            sp[l][s] = in ? po[l] + (j + 1) * Pl[l] + i + 1 : -1;
+            sij[l][s] = i | (j << 16);
         }
     // ---- LDS: zeros everywhere (the rings stay zero), then the interiors
-    if constexpr (KIND == kOpPrior)
-        for (int t = threadIdx.x; t < a.nlev * 9; t += NT)
+    if constexpr (PRIOR)
+        for (int t = threadIdx.x; t < nlev * 9; t += NT)
             rows[t] = a.cpi ? a.karows[t / 9][9 * inst + t % 9] : a.ka[t / 9][t % 9];
     for (int q = threadIdx.x; q < PN; q += NT) {
-        sb[q] = sx[q] = sw[q] = tc[q] = te[q] = tn[q] = tdv[q] = (T)0;
-        if constexpr (NE) tg[q] = (T)0;
+        sb[q] = sx[q] = sw[q] = 0.0f;
+        if constexpr (!PRIOR) te[q] = tn[q] = tdv[q] = 0.0f;
     }
     __syncthreads();
-    const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cA = (T)cc.cA, cB = (T)cc.cB, c1 = (T)cc.c1;
+    const float inv_theta = (float)cc.inv_theta, theta = (float)cc.theta, cA = (float)cc.cA, cB = (float)cc.cB,
+                c1 = (float)cc.c1;
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
         const int p = vp[e];
         if (p < 0) continue;
-        if constexpr (KIND == kOpState) {
+        if constexpr (!PRIOR) {
             te[p] = -vE[e];
             tn[p] = -vN[e];
             tdv[p] = vD[e];
         } else {
-            const int l = vlev[e];
-            const KARow<T>& r = rows[9 * l + ka_class(vi[e], vj[e], l == 0 ? Nl[0] : (l == 1 ? Nl[1] : Nl[2]))];
-            tc[p] = r.c;
-            te[p] = r.e;
-            tn[p] = r.n;
-            tg[p] = r.ne;
-            tdv[p] = r.dinv;
-            vD[e] = r.dinv;
+            const int l = vl[e];
+            const int N = l == 0 ? Nl[0] : (l == 1 ? Nl[1] : (l == 2 ? Nl[2] : Nl[3]));
+            vD[e] = rows[9 * l + ka_class(vij[e] & 0xffff, vij[e] >> 16, N)].dinv;
         }
         if (threadIdx.x + NT * e < n0) {
             sb[p] = vb[e];
             sw[p] = vD[e] * vb[e] * inv_theta;  // d0 of the first smoothing step
         }
     }
-    if constexpr (KIND == kOpState) {
-        __syncthreads();
-        // diagonal: the sum of the four incident edge weights
-#pragma unroll
-        for (int e = 0; e < EB; ++e) {
-            const int p = vp[e];
-            if (p < 0) continue;
-            const int P = (vlev[e] == 0 ? Pl[0] : (vlev[e] == 1 ? Pl[1] : Pl[2]));
-            tc[p] = -(te[p] + te[p - 1] + tn[p] + tn[p - P]);
-        }
-    }
     __syncthreads();
+    // (A x)_p at padded position p of level l (node ij), with the diagonal and
+    // 1/diagonal of the row
+    auto apply = [&](int l, int p, int ij, const float* x, float& diag, float& dv) -> float {
+        const int P = Pl[l];
+        if constexpr (!PRIOR) {
+            const float e0 = te[p], e1 = te[p - 1], m0 = tn[p], m1 = tn[p - P];
+            diag = -(e0 + e1 + m0 + m1);
+            dv = tdv[p];
+            return diag * x[p] + e0 * x[p + 1] + e1 * x[p - 1] + m0 * x[p + P] + m1 * x[p - P];
+        } else {
+            const KARow<float>& r = rows[9 * l + ka_class(ij & 0xffff, ij >> 16, Nl[l])];
+            diag = r.c;
+            dv = r.dinv;
+            return r.c * x[p] + r.e * x[p + 1] + r.w * x[p - 1] + r.n * x[p + P] + r.s * x[p - P] +
+                   r.ne * x[p + P + 1] + r.sw * x[p - P - 1];
+        }
+    };
+    auto inv_diag = [&](int l, int p, int ij) -> float {
+        if constexpr (!PRIOR)
+            return tdv[p];
+        else
+            return rows[9 * l + ka_class(ij & 0xffff, ij >> 16, Nl[l])].dinv;
+    };
     // ---- down
 #pragma unroll
     for (int l = 0; l < LV - 1; ++l) {
         if (l >= L) break;
         const int P = Pl[l];
-        const TileStencil<T> ts{tc, te, tn, tg, tdv};
         // x2 = cA d0 + cB D^-1 (b - A d0), d0 in sw
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int p = pi[l][s];
-            if (p >= 0) sx[p] = cA * sw[p] + cB * tdv[p] * (sb[p] - tile_apply<NE>(ts, P, p, sw));
+        for (int s = 0; s < bottom_slots<TOP>(l); ++s) {
+            const int p = sp[l][s];
+            if (p < 0) continue;
+            float dg, dv;
+            const float ad = apply(l, p, sij[l][s], sw, dg, dv);
+            sx[p] = cA * sw[p] + cB * dv * (sb[p] - ad);
         }
         __syncthreads();
         // residual b - A x2 on the free nodes, into sw
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int p = pi[l][s];
-            if (p >= 0) {
-                const T v = sb[p] - tile_apply<NE>(ts, P, p, sx);
-                sw[p] = tdv[p] != (T)0 ? v : (T)0;
-            }
+        for (int s = 0; s < bottom_slots<TOP>(l); ++s) {
+            const int p = sp[l][s];
+            if (p < 0) continue;
+            float dg, dv;
+            const float v = sb[p] - apply(l, p, sij[l][s], sx, dg, dv);
+            sw[p] = dv != 0.0f ? v : 0.0f;
         }
         __syncthreads();
         // restriction P^T to level l + 1, and its first smoothing correction d0
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int pc = pi[l + 1][s];
+        for (int s = 0; s < bottom_slots<TOP>(l + 1); ++s) {
+            const int pc = sp[l + 1][s];
             if (pc < 0) continue;
-            const int f = fi[l + 1][s];
-            T v = 0;
-            if (tdv[pc] != (T)0)
-                v = sw[f] + (T)0.5 * (sw[f - 1] + sw[f + 1] + sw[f - P] + sw[f + P] + sw[f + P + 1] + sw[f - P - 1]);
+            const int I = sij[l + 1][s] & 0xffff, J = sij[l + 1][s] >> 16;
+            const int f = po[l] + (2 * J + 1) * P + 2 * I + 1;
+            const float dvc = inv_diag(l + 1, pc, sij[l + 1][s]);
+            float v = 0.0f;
+            if (dvc != 0.0f)
+                v = sw[f] + 0.5f * (sw[f - 1] + sw[f + 1] + sw[f - P] + sw[f + P] + sw[f + P + 1] + sw[f - P - 1]);
             sb[pc] = v;
-            sw[pc] = tdv[pc] * v * inv_theta;
+            sw[pc] = dvc * v * inv_theta;
         }
         __syncthreads();
     }
     // ---- coarsest: dense inverse, S threads per row (entries prefetched in cv)
     {
-        const int N1 = (L == 0 ? Nl[0] : (L == 1 ? Nl[1] : Nl[2])) + 1;
-        const int P = N1 + 2, o = L == 0 ? po[0] : (L == 1 ? po[1] : po[2]);
-        T* tmp = sw;  // the work vector is free here (the dense solve reads b only); 12 * 81 <= PN
-        const float inv_n1 = 1.0f / (float)N1;
+        const int N1 = (L == 0 ? Nl[0] : (L == 1 ? Nl[1] : (L == 2 ? Nl[2] : Nl[3]))) + 1;
+        const int P = N1 + 2, o = L == 0 ? po[0] : (L == 1 ? po[1] : (L == 2 ? po[2] : po[3]));
+        // the work vector is free here (the dense solve reads b only; the ring
+        // entries it overwrites meet zero couplings only): 12 * 81 <= PN
+        float* tmp = sw;
+        const float inv_c = 1.0f / (float)N1;
         if (cr < a.nc) {
-            T s = 0;
+            float s = 0.0f;
             // entry c = cpart + u S at (c mod N1, c / N1), stepped without dividing
-            int jc = small_div(cpart, inv_n1), ic = cpart - jc * N1;
+            int jc = small_div(cpart, inv_c), ic = cpart - jc * N1;
 #pragma unroll
             for (int u = 0; u < kCU; ++u) {
                 const int c = cpart + u * S;
@@ -551,9 +578,9 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
         }
         __syncthreads();
         for (int r = threadIdx.x; r < a.nc; r += NT) {
-            T s = 0;
+            float s = 0.0f;
             for (int part = 0; part < S; ++part) s += tmp[r * S + part];
-            const int jr = small_div(r, inv_n1);
+            const int jr = small_div(r, inv_c);
             sx[o + (jr + 1) * P + r - jr * N1 + 1] = s;
         }
         __syncthreads();
@@ -562,42 +589,50 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs<T> a, const T* __res
 #pragma unroll
     for (int l = LV - 2; l >= 0; --l) {
         if (l >= L) continue;
-        const int P = Pl[l];
-        const TileStencil<T> ts{tc, te, tn, tg, tdv};
+        const int Pc = Pl[l + 1];
         // x += P x_coarse on the free nodes
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int p = pi[l][s];
-            if (p >= 0 && tdv[p] != (T)0)
-                sx[p] += ev[l][s] ? sx[ca0[l][s]] : (T)0.5 * (sx[ca0[l][s]] + sx[ca1[l][s]]);
+        for (int s = 0; s < bottom_slots<TOP>(l); ++s) {
+            const int p = sp[l][s];
+            if (p < 0) continue;
+            const int ij = sij[l][s], i = ij & 0xffff, j = ij >> 16;
+            if (inv_diag(l, p, ij) == 0.0f) continue;
+            const int I = i >> 1, J = j >> 1;
+            const int ca0 = po[l + 1] + (J + 1) * Pc + I + 1;
+            const int ca1 = po[l + 1] + (J + 1 + (j & 1)) * Pc + I + 1 + (i & 1);
+            sx[p] += ((i | j) & 1) ? 0.5f * (sx[ca0] + sx[ca1]) : sx[ca0];
         }
         __syncthreads();
         // d0 = D^-1 (b - A x) / theta
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int p = pi[l][s];
-            if (p >= 0) sw[p] = tdv[p] * (sb[p] - tile_apply<NE>(ts, P, p, sx)) * inv_theta;
+        for (int s = 0; s < bottom_slots<TOP>(l); ++s) {
+            const int p = sp[l][s];
+            if (p < 0) continue;
+            float dg, dv;
+            const float ax = apply(l, p, sij[l][s], sx, dg, dv);
+            sw[p] = dv * (sb[p] - ax) * inv_theta;
         }
         __syncthreads();
         // x += (1 + c1) d0 + cB D^-1 r1 with r1 = theta D d0 - A d0
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int p = pi[l][s];
-            if (p >= 0) {
-                const T dk = sw[p];
-                const T r1 = theta * dk * tc[p] - tile_apply<NE>(ts, P, p, sw);
-                sx[p] += ((T)1 + c1) * dk + cB * tdv[p] * r1;
-            }
+        for (int s = 0; s < bottom_slots<TOP>(l); ++s) {
+            const int p = sp[l][s];
+            if (p < 0) continue;
+            float dg, dv;
+            const float ad = apply(l, p, sij[l][s], sw, dg, dv);
+            const float dk = sw[p];
+            const float r1 = theta * dk * dg - ad;
+            sx[p] += (1.0f + c1) * dk + cB * dv * r1;
         }
         __syncthreads();
     }
     double dot = 0.0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
+    for (int s = 0; s < bottom_slots<TOP>(0); ++s) {
         const int q = threadIdx.x + NT * s;
-        const int p = pi[0][s];
+        const int p = sp[0][s];
         if (p >= 0) {
-            const T v = sx[p];
+            const TV v = (TV)sx[p];
             xg[(size_t)col * ld + q] = v;
             if (rv) dot += (double)v * (double)rv[(size_t)col * ld + q];
         }

@@ -798,32 +798,25 @@ void Hierarchy::vcycle(int nc, int check) {
         HINV_LAUNCH_CHECK();
     }
     {
-        BottomArgs<T> a{};
+        // the bottom computes in FP32 (its coefficients, coarse inverse and
+        // prior rows are the FP32 copies) on the solve's vectors
+        BottomArgs a{};
         a.nlev = nlev - Lb;
         if (a.nlev > kBottomLevels) fail(HINV_EINVAL, "internal: too many bottom levels");
         for (int l = 0; l < a.nlev; ++l) {
             const Level& L = *lev_[Lb + l];
             a.N[l] = L.N;
             if (kind_ == kOpState) {
-                if constexpr (sizeof(T) == 8) {
-                    a.wE[l] = L.wE64.get();
-                    a.wN[l] = L.wN64.get();
-                    a.dinv[l] = L.dinv64.get();
-                } else {
-                    a.wE[l] = L.wE32.get();
-                    a.wN[l] = L.wN32.get();
-                    a.dinv[l] = L.dinv32.get();
-                }
+                a.wE[l] = L.wE32.get();
+                a.wN[l] = L.wN32.get();
+                a.dinv[l] = L.dinv32.get();
             }
         }
-        if constexpr (sizeof(T) == 8)
-            a.cinv = cinv64_.get();
-        else
-            a.cinv = cinv32_.get();
+        a.cinv = cinv32_.get();
         a.nc = nc_coarse_;
         if (kind_ == kOpPrior && ninst_ == 1)
             for (int l = 0; l < a.nlev; ++l) {
-                const OpKA<T> o = make_opKA<T>(a.N[l], pp_);
+                const OpKA<float> o = make_opKA<float>(a.N[l], pp_);
                 for (int c = 0; c < 9; ++c) a.ka[l][c] = o.rows[c];
             }
         if (ninst_ > 1) {
@@ -832,10 +825,7 @@ void Hierarchy::vcycle(int nc, int check) {
             for (int l = 0; l < a.nlev; ++l) {
                 a.cs[l] = lev_[Lb + l]->n;
                 const size_t off = (size_t)(Lb + l) * ninst_ * 9;
-                if constexpr (sizeof(T) == 8)
-                    a.karows[l] = karow64_.get() ? karow64_.get() + off : nullptr;
-                else
-                    a.karows[l] = karow32_.get() ? karow32_.get() + off : nullptr;
+                a.karows[l] = karow32_.get() ? karow32_.get() + off : nullptr;
             }
         }
         const T* rv = Lb == 0 ? (const T*)w.r.get() : nullptr;
@@ -845,18 +835,17 @@ void Hierarchy::vcycle(int nc, int check) {
         const double nb = (double)(lev_[Lb]->n);
         double ncoef = 0.0;
         for (int l = Lb; l < nlev; ++l) ncoef += lev_[l]->n;
-        const double bytes_bottom =
-            sizeof(T) * (nc * (2.0 * nb + (rv ? nb : 0.0)) +
-                         ninst_ * ((dir ? 3.0 * ncoef : 0.0) + (double)nc_coarse_ * nc_coarse_));
+        const double bytes_bottom = sizeof(T) * nc * (2.0 * nb + (rv ? nb : 0.0)) +
+                                    sizeof(float) * ninst_ * ((dir ? 3.0 * ncoef : 0.0) + (double)nc_coarse_ * nc_coarse_);
         const T* bb = bvec(Lb);
         T* xb = xout(Lb);
         ColState* stp = st_.get();
         if (kind_ == kOpState)
-            timed_launch(ctx_, kKBottom, bytes_bottom, k_bottom<T, kOpState>, dim3(nc), dim3(1024), s, a, bb, xb,
-                         lev_[Lb]->n, act, cc, rv, red, stp, chk);
+            timed_launch(ctx_, kKBottom, bytes_bottom, k_bottom<T, kOpState, kBottomN>, dim3(nc), dim3(1024), s, a,
+                         bb, xb, lev_[Lb]->n, act, cc, rv, red, stp, chk);
         else
-            timed_launch(ctx_, kKBottom, bytes_bottom, k_bottom<T, kOpPrior>, dim3(nc), dim3(1024), s, a, bb, xb,
-                         lev_[Lb]->n, act, cc, rv, red, stp, chk);
+            timed_launch(ctx_, kKBottom, bytes_bottom, k_bottom<T, kOpPrior, kBottomN>, dim3(nc), dim3(1024), s, a,
+                         bb, xb, lev_[Lb]->n, act, cc, rv, red, stp, chk);
         HINV_LAUNCH_CHECK();
     }
     for (int l = Lb - 1; l >= 0; --l) {
