@@ -122,8 +122,10 @@ __device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int
 // [2 I0 - 1, 2 I1 + 1], hence x2 one node further out and b two nodes further
 // out.  The operator rows of the tile are staged once per problem instance;
 // the workgroup then sweeps cb consecutive columns.
-template <typename T, class Op, int kTC>
-__global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T* __restrict__ x,
+// b may be of a wider type TB than the level's vectors (the finest level of a
+// V-cycle in FP32 preconditioning an FP64 PCG reads the FP64 residual).
+template <typename T, class Op, int kTC, typename TB = T>
+__global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, T* __restrict__ x,
                                               int ld, T* __restrict__ bc, int ldc, int dirichlet,
                                               int* __restrict__ act, ChebCoef cc, PcgRed red,
                                               ColState* __restrict__ st, int check, int nc, int cb) {
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T
     for (int col = blockIdx.z * cb; col < c_end; ++col) {
         if (act && !act[col]) continue;
         const auto& op = op_.at(col);  // operator of the instance owning this column
-        const T* bcol = b + (size_t)col * ld;
+        const TB* bcol = b + (size_t)col * ld;
         T* xcol = x + (size_t)col * ld;
         // loads first: b, then the operator rows, then the convergence test,
         // so that their latencies overlap
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T
         for (int e = 0; e < E; ++e) {
             const int t = threadIdx.x + 256 * e;
             const int i = ox + t % TW, j = oy + t / TW;
-            vb[e] = (t < NN && i >= 0 && i <= N && j >= 0 && j <= N) ? bcol[j * N1 + i] : (T)0;
+            vb[e] = (t < NN && i >= 0 && i <= N && j >= 0 && j <= N) ? (T)bcol[j * N1 + i] : (T)0;
         }
         __syncthreads();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
@@ -221,12 +223,14 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const T* __restrict__ b, T
 // read from its own buffer: neighbouring workgroups write the output), b and
 // the first Chebyshev correction d0 one node around O.  Optionally writes the
 // workgroup's part of sum_k rv_k x_k (the PCG inner product r^T z).
-template <typename T, class Op, int kTF>
-__global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, const T* __restrict__ x2,
-                                            T* __restrict__ x, int ld, const T* __restrict__ xc,
+// b and rv may be of a wider type TB and the output x of a wider type TX than
+// the level's vectors (see k_down).
+template <typename T, class Op, int kTF, typename TB = T, typename TX = T>
+__global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, const T* __restrict__ x2,
+                                            TX* __restrict__ x, int ld, const T* __restrict__ xc,
                                             int ldc, int dirichlet,
                                             const int* __restrict__ act, ChebCoef cc,
-                                            const T* __restrict__ rv, PcgRed red, int nc, int cb) {
+                                            const TB* __restrict__ rv, PcgRed red, int nc, int cb) {
     constexpr int TW = kTF + 4, NN = TW * TW;
     constexpr bool NE = kNorthEast<Op>;
     __shared__ T sx[NN], sd[NN], sb[NN];
@@ -243,9 +247,9 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
     for (int col = blockIdx.z * cb; col < c_end; ++col) {
         if (act && !act[col]) continue;
         const auto& op = op_.at(col);  // operator of the instance owning this column
-        const T* bcol = b + (size_t)col * ld;
+        const TB* bcol = b + (size_t)col * ld;
         const T* x2col = x2 + (size_t)col * ld;
-        T* xcol = x + (size_t)col * ld;
+        TX* xcol = x + (size_t)col * ld;
         const T* ccol = xc + (size_t)col * ldc;
         // loads first (b, x2 and the two coarse values of the prolongation,
         // then the operator rows) so that their latencies overlap.  P x_c at
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
             const bool fr = in && !(dirichlet && (j == 0 || j == N));
             const int I = i >> 1, J = j >> 1;
             const int a0 = J * Nc1 + I, a1 = (J + (j & 1)) * Nc1 + I + (i & 1);
-            vb[e] = in ? bcol[j * N1 + i] : (T)0;
+            vb[e] = in ? (T)bcol[j * N1 + i] : (T)0;
             vx[e] = fr ? x2col[j * N1 + i] : (T)0;
             pc0[e] = fr ? ccol[a0] : (T)0;
             pc1[e] = fr ? ccol[a1] : (T)0;
@@ -299,7 +303,7 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const T* __restrict__ b, con
             const T dk = sd[l];
             const T r1 = theta * dk * tc[l] - tile_apply<NE>(ts, TW, l, sd);
             const T v = sx[l] + ((T)1 + c1) * dk + cB * tdv[l] * r1;
-            xcol[k] = v;
+            xcol[k] = (TX)v;
             if (rv) dot += (double)v * (double)rv[(size_t)col * ld + k];
         }
         if (rv) {

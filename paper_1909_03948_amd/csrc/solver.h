@@ -103,6 +103,8 @@ class Hierarchy {
     void drop_graphs();
     template <typename T>
     void vcycle(int nc, int check);
+    template <typename T, typename TI>
+    void vcycle_impl(int nc, int check);
     struct PcgRed pcg_red(int nc) const;
     template <typename T>
     PcgWork<T>& work();

@@ -755,10 +755,21 @@ void Hierarchy::tune_shape(int nc) {
                      best.per);
 }
 
+// z = V-cycle(r) for the PCG of precision T.  An FP64 PCG runs its V-cycle
+// in FP32 (a preconditioner: its rounding changes the preconditioner, not the
+// solve's result, which the PCG and the refinement test hold to their
+// tolerance in FP64): the finest-level kernels read r and write z in FP64,
+// every other vector of the cycle is FP32.
 template <typename T>
 void Hierarchy::vcycle(int nc, int check) {
+    vcycle_impl<T, float>(nc, check);
+}
+
+template <typename T, typename TI>
+void Hierarchy::vcycle_impl(int nc, int check) {
     hipStream_t s = launch_stream_;
-    PcgWork<T>& w = work<T>();
+    PcgWork<T>& wt = work<T>();
+    PcgWork<TI>& wi = work<TI>();
     const int nlev = (int)lev_.size();
     int Lb = 0;
     while (lev_[Lb]->N > kBottomN) ++Lb;
@@ -766,40 +777,44 @@ void Hierarchy::vcycle(int nc, int check) {
     const int dir = kind_ == kOpState;
     const ChebCoef cc = cheb_coef();
     PcgRed red = pcg_red(nc);
+    constexpr double st = sizeof(T), si = sizeof(TI);
 
-    auto bvec = [&](int l) { return l == 0 ? w.r.get() : w.lb[l]->get(); };
-    auto xout = [&](int l) { return l == 0 ? w.z.get() : w.lx[l]->get(); };
     for (int l = 0; l < Lb; ++l) {
         const Level& L = *lev_[l];
         const Level& C = *lev_[l + 1];
         // algorithmic bytes: read b, write x2 and b_coarse per column; the state
         // operator's three coefficient arrays once per launch and instance
-        const double bytes_down =
-            sizeof(T) * ((double)nc * (2.0 * L.n + C.n) + (dir ? 3.0 * L.n * ninst_ : 0.0));
+        const double bytes_down = nc * ((l == 0 ? st : si) * L.n + si * (L.n + C.n)) + (dir ? si * 3.0 * L.n * ninst_ : 0.0);
         const int kcls = l == 0 ? (int)kKDown : -1;
-        with_op<T>(l, [&](auto op) {
+        with_op<TI>(l, [&](auto op) {
             using Op = decltype(op);
             const int chk = l == 0 ? check : 0;
             const int cb = shape_.cb, gz = ceil_div(nc, cb);
-            const T* bl = bvec(l);
-            T* xl = w.lt[l]->get();
-            T* bcl = bvec(l + 1);
+            TI* xl = wi.lt[l]->get();
+            TI* bcl = wi.lb[l + 1]->get();
             ColState* stp = st_.get();
-            if (small_tiles(l)) {
-                const int tc = ceil_div(C.N + 1, kTCSmall);
-                timed_launch(ctx_, kcls, bytes_down, k_down<T, Op, kTCSmall>, dim3(tc, tc, gz), dim3(256), s,
-                             op, bl, xl, L.n, bcl, C.n, dir, act, cc, red, stp, chk, nc, cb);
+            auto launch = [&](auto kern, int tcs, const auto* bl) {
+                const int tc = ceil_div(C.N + 1, tcs);
+                timed_launch(ctx_, kcls, bytes_down, kern, dim3(tc, tc, gz), dim3(256), s, op, bl, xl, L.n, bcl, C.n,
+                             dir, act, cc, red, stp, chk, nc, cb);
+            };
+            if (l == 0) {
+                if (small_tiles(l))
+                    launch(k_down<TI, Op, kTCSmall, T>, kTCSmall, (const T*)wt.r.get());
+                else
+                    launch(k_down<TI, Op, kTCBig, T>, kTCBig, (const T*)wt.r.get());
             } else {
-                const int tc = ceil_div(C.N + 1, kTCBig);
-                timed_launch(ctx_, kcls, bytes_down, k_down<T, Op, kTCBig>, dim3(tc, tc, gz), dim3(256), s,
-                             op, bl, xl, L.n, bcl, C.n, dir, act, cc, red, stp, chk, nc, cb);
+                if (small_tiles(l))
+                    launch(k_down<TI, Op, kTCSmall>, kTCSmall, (const TI*)wi.lb[l]->get());
+                else
+                    launch(k_down<TI, Op, kTCBig>, kTCBig, (const TI*)wi.lb[l]->get());
             }
         });
         HINV_LAUNCH_CHECK();
     }
     {
         // the bottom computes in FP32 (its coefficients, coarse inverse and
-        // prior rows are the FP32 copies) on the solve's vectors
+        // prior rows are the FP32 copies) on the cycle's vectors
         BottomArgs a{};
         a.nlev = nlev - Lb;
         if (a.nlev > kBottomLevels) fail(HINV_EINVAL, "internal: too many bottom levels");
@@ -828,50 +843,66 @@ void Hierarchy::vcycle(int nc, int check) {
                 a.karows[l] = karow32_.get() ? karow32_.get() + off : nullptr;
             }
         }
-        const T* rv = Lb == 0 ? (const T*)w.r.get() : nullptr;
         const int chk = Lb == 0 ? check : 0;
         // per column: read b (and r for r^T z), write x; once per launch: the
         // state coefficients of every bottom level and the dense coarse inverse
         const double nb = (double)(lev_[Lb]->n);
         double ncoef = 0.0;
         for (int l = Lb; l < nlev; ++l) ncoef += lev_[l]->n;
-        const double bytes_bottom = sizeof(T) * nc * (2.0 * nb + (rv ? nb : 0.0)) +
-                                    sizeof(float) * ninst_ * ((dir ? 3.0 * ncoef : 0.0) + (double)nc_coarse_ * nc_coarse_);
-        const T* bb = bvec(Lb);
-        T* xb = xout(Lb);
+        const double coef_bytes = sizeof(float) * ninst_ * ((dir ? 3.0 * ncoef : 0.0) + (double)nc_coarse_ * nc_coarse_);
         ColState* stp = st_.get();
-        if (kind_ == kOpState)
-            timed_launch(ctx_, kKBottom, bytes_bottom, k_bottom<T, kOpState, kBottomN>, dim3(nc), dim3(1024), s, a,
-                         bb, xb, lev_[Lb]->n, act, cc, rv, red, stp, chk);
-        else
-            timed_launch(ctx_, kKBottom, bytes_bottom, k_bottom<T, kOpPrior, kBottomN>, dim3(nc), dim3(1024), s, a,
-                         bb, xb, lev_[Lb]->n, act, cc, rv, red, stp, chk);
+        const int ldb = lev_[Lb]->n;
+        auto launch = [&](auto kern, const auto* bb, auto* xb, const auto* rv, double vb) {
+            timed_launch(ctx_, kKBottom, nc * vb * (2.0 * nb + (rv ? nb : 0.0)) + coef_bytes, kern, dim3(nc),
+                         dim3(1024), s, a, bb, xb, ldb, act, cc, rv, red, stp, chk);
+        };
+        if (Lb == 0) {
+            // the whole hierarchy: r in, z out, and the r^T z partial
+            const T* r = wt.r.get();
+            if (kind_ == kOpState)
+                launch(k_bottom<T, kOpState, kBottomN>, r, wt.z.get(), r, st);
+            else
+                launch(k_bottom<T, kOpPrior, kBottomN>, r, wt.z.get(), r, st);
+        } else {
+            const TI* none = nullptr;
+            if (kind_ == kOpState)
+                launch(k_bottom<TI, kOpState, kBottomN>, (const TI*)wi.lb[Lb]->get(), wi.lx[Lb]->get(), none, si);
+            else
+                launch(k_bottom<TI, kOpPrior, kBottomN>, (const TI*)wi.lb[Lb]->get(), wi.lx[Lb]->get(), none, si);
+        }
         HINV_LAUNCH_CHECK();
     }
     for (int l = Lb - 1; l >= 0; --l) {
         const Level& L = *lev_[l];
         const Level& C = *lev_[l + 1];
-        const T* rv = l == 0 ? (const T*)w.r.get() : nullptr;
         // read b, x2, x_coarse (and r for r^T z), write x; coefficients once per instance
-        const double bytes_up =
-            sizeof(T) * ((double)nc * ((rv ? 4.0 : 3.0) * L.n + C.n) + (dir ? 3.0 * L.n * ninst_ : 0.0));
+        const double bytes_up = nc * ((l == 0 ? 3.0 * st : 2.0 * si) * L.n + si * (L.n + C.n)) +
+                                (dir ? si * 3.0 * L.n * ninst_ : 0.0);
         const int kcls = l == 0 ? (int)kKUp : -1;
-        with_op<T>(l, [&](auto op) {
+        with_op<TI>(l, [&](auto op) {
             using Op = decltype(op);
             const int cb = shape_.cb, gz = ceil_div(nc, cb);
-            const T* bl = bvec(l);
-            const T* x2l = w.lt[l]->get();
-            T* xl = xout(l);
-            const T* xcl = xout(l + 1);
+            const TI* x2l = wi.lt[l]->get();
+            const TI* xcl = wi.lx[l + 1]->get();
             const int* actc = act;
-            if (small_tiles(l)) {
-                const int tf = ceil_div(L.N + 1, kTFSmall);
-                timed_launch(ctx_, kcls, bytes_up, k_up<T, Op, kTFSmall>, dim3(tf, tf, gz), dim3(256), s,
-                             op, bl, x2l, xl, L.n, xcl, C.n, dir, actc, cc, rv, red, nc, cb);
+            auto launch = [&](auto kern, int tfs, const auto* bl, auto* xl, const auto* rv) {
+                const int tf = ceil_div(L.N + 1, tfs);
+                timed_launch(ctx_, kcls, bytes_up, kern, dim3(tf, tf, gz), dim3(256), s, op, bl, x2l, xl, L.n, xcl,
+                             C.n, dir, actc, cc, rv, red, nc, cb);
+            };
+            if (l == 0) {
+                const T* r = wt.r.get();
+                if (small_tiles(l))
+                    launch(k_up<TI, Op, kTFSmall, T, T>, kTFSmall, r, wt.z.get(), r);
+                else
+                    launch(k_up<TI, Op, kTFBig, T, T>, kTFBig, r, wt.z.get(), r);
             } else {
-                const int tf = ceil_div(L.N + 1, kTFBig);
-                timed_launch(ctx_, kcls, bytes_up, k_up<T, Op, kTFBig>, dim3(tf, tf, gz), dim3(256), s,
-                             op, bl, x2l, xl, L.n, xcl, C.n, dir, actc, cc, rv, red, nc, cb);
+                const TI* bl = wi.lb[l]->get();
+                const TI* none = nullptr;
+                if (small_tiles(l))
+                    launch(k_up<TI, Op, kTFSmall>, kTFSmall, bl, wi.lx[l]->get(), none);
+                else
+                    launch(k_up<TI, Op, kTFBig>, kTFBig, bl, wi.lx[l]->get(), none);
             }
         });
         HINV_LAUNCH_CHECK();
@@ -1113,8 +1144,9 @@ void Hierarchy::precondition(int nc, const double* r, int ldr, double* z, int ld
     hipStream_t s = ctx_->stream;
     set_columns(nc);
     ensure_cols(nc);
-    if (w64_.cap < nc) drop_graphs();
+    if (w64_.cap < nc || w32_.cap < nc) drop_graphs();
     ensure_work(w64_, lev_, nc);
+    ensure_work(w32_, lev_, nc);
     const dim3 g = grid2(n_, nc);
     with_op<double>(0, [&](auto op) {
         k_masked_copy<<<g, kBlock, 0, s>>>(op, r, ldr, w64_.r.get(), n_);
@@ -1140,11 +1172,10 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     ensure_cols(nc);
     if (precision == HINV_PREC_AUTO) precision = nc >= kAutoBatch ? HINV_PREC_FP32_IR : HINV_PREC_FP64;
     const bool fp32 = precision == HINV_PREC_FP32_IR;
-    if ((fp32 ? w32_.cap : w64_.cap) < nc) drop_graphs();
-    if (fp32)
-        ensure_work(w32_, lev_, nc);
-    else
-        ensure_work(w64_, lev_, nc);
+    // the FP32 work serves every V-cycle, the FP64 work the FP64 PCG
+    if (w32_.cap < nc || (!fp32 && w64_.cap < nc)) drop_graphs();
+    ensure_work(w32_, lev_, nc);
+    if (!fp32) ensure_work(w64_, lev_, nc);
     const int n = n_, ld = n, nblk = ceil_div(n, kBlock);
     const dim3 g = grid2(n, nc);
     // the FP64 iterate lives in the caller's x when its columns are contiguous
