@@ -12,6 +12,9 @@ namespace hinv {
 class Problem {
   public:
     Problem(Ctx* ctx, const hinv_problem_desc& d);
+    ~Problem();
+    Problem(const Problem&) = delete;
+    Problem& operator=(const Problem&) = delete;
 
     Ctx* ctx;
     int N, n, q;
@@ -51,12 +54,15 @@ class Problem {
     void inc_forward_rhs(int nc, const double* mhat, int ldm, double* rhs, int ldr);
     void inc_adjoint_rhs(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
                          double* rhs, int ldr);
+    // rm: R mhat already computed (full modes), added instead of computed here
     void hess_output(int mode, int nc, const double* mhat, int ldm, const double* uh, int ldu,
-                     const double* ph, int ldp, double* out, int ldo);
-    void prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate = false);
+                     const double* ph, int ldp, double* out, int ldo, const double* rm = nullptr);
+    // s: the stream to run on (the context's stream when null)
+    void prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate = false,
+                     hipStream_t s = nullptr);
     void prior_solve(int nc, const double* x, int ldx, double* y, int ldy, SolveStats* st);
     void mass_apply(int nc, const double* x, int ldx, double* y, int ldy);
-    void mass_solve(int nc, const double* x, int ldx, double* y, int ldy);
+    void mass_solve(int nc, const double* x, int ldx, double* y, int ldy, hipStream_t s = nullptr);
     void prior_sample(int ns, const double* eta, int ldeta, double* out, int ldo, bool add_mean,
                       SolveStats* st);
     void white_noise(uint64_t seed, uint64_t stream, long long first, int ns, double* eta, int ld);
@@ -69,7 +75,12 @@ class Problem {
     void ensure_lin_hierarchy();
 
   private:
-    static constexpr int kScratch = 9;
+    static constexpr int kScratch = 10;
+    // second stream (default priority) on which a full Hessian action computes
+    // R mhat while the two solves run on the context's stream
+    hipStream_t side_ = nullptr;
+    hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+    hipStream_t side_stream();
     int cap_ = 0;
     DBuf<double> w_[kScratch];
     int qcap_ = 0;

@@ -156,7 +156,8 @@ __global__ void k_sens(int N, const double* __restrict__ cT, const double* __res
 __global__ void k_hess_out(int N, const double* __restrict__ cT, const double* __restrict__ u,
                            const double* __restrict__ p, const double* __restrict__ uh, int ldu,
                            const double* __restrict__ ph, int ldp, const double* __restrict__ mh,
-                           int ldm, double* __restrict__ out, int ldo, int gn) {
+                           int ldm, double* __restrict__ out, int ldo, int gn,
+                           const double* __restrict__ add, int ldadd) {
     const int N1 = N + 1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N1 * N1) return;
@@ -176,6 +177,7 @@ __global__ void k_hess_out(int N, const double* __restrict__ cT, const double* _
         }
         acc += c * (1.0 / 3.0) * v;
     });
+    if (add) acc = colp(add, ldadd)[k] + acc;  // the prior term, as the accumulating apply adds it
     colp(out, ldo)[k] = acc;
 }
 
@@ -708,14 +710,32 @@ void Problem::inc_adjoint_rhs(int nc, bool gn, const double* mhat, int ldm, cons
 
 // Hessian action from the incremental states (and R mhat for the full modes).
 void Problem::hess_output(int mode, int nc, const double* mhat, int ldm, const double* uh, int ldu,
-                          const double* ph, int ldp, double* out, int ldo) {
+                          const double* ph, int ldp, double* out, int ldo, const double* rm) {
     const bool gn = mode == HINV_HESS_GN_FULL || mode == HINV_HESS_GN_MISFIT;
     const bool with_prior = mode == HINV_HESS_FULL || mode == HINV_HESS_GN_FULL;
     k_hess_out<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(N, HA->coefficient(), u_lin.get(),
                                                          p_lin.get(), uh, ldu, ph, ldp, mhat, ldm,
-                                                         out, ldo, gn ? 1 : 0);
+                                                         out, ldo, gn ? 1 : 0, with_prior ? rm : nullptr, n);
     HINV_LAUNCH_CHECK();
-    if (with_prior) prior_apply(nc, mhat, ldm, out, ldo, true);
+    if (with_prior && !rm) prior_apply(nc, mhat, ldm, out, ldo, true);
+}
+
+hipStream_t Problem::side_stream() {
+    if (!side_) {
+        HINV_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+        HINV_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+        HINV_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+    }
+    return side_;
+}
+
+Problem::~Problem() {
+    if (side_) {
+        (void)hipStreamSynchronize(side_);
+        (void)hipEventDestroy(ev_fork_);
+        (void)hipEventDestroy(ev_join_);
+        (void)hipStreamDestroy(side_);
+    }
 }
 
 void Problem::inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st) {
@@ -734,12 +754,25 @@ void Problem::inc_adjoint(int nc, bool gn, const double* mhat, int ldm, const do
 void Problem::hessian(int mode, int nc, const double* mhat, int ldm, double* out, int ldo,
                       SolveStats* st) {
     const bool gn = mode == HINV_HESS_GN_FULL || mode == HINV_HESS_GN_MISFIT;
+    const bool with_prior = mode == HINV_HESS_FULL || mode == HINV_HESS_GN_FULL;
     scratch(0, nc);
     double* uh = scratch(1, nc);
     double* ph = scratch(2, nc);
+    // R mhat does not depend on the two solves: it runs on the side stream
+    // meanwhile (its own scratch 3-9), joined before the output kernel adds it
+    double* rm = nullptr;
+    if (with_prior) {
+        rm = scratch(9, nc);
+        hipStream_t side = side_stream();
+        HINV_HIP(hipEventRecord(ev_fork_, ctx->stream));
+        HINV_HIP(hipStreamWaitEvent(side, ev_fork_, 0));
+        prior_apply(nc, mhat, ldm, rm, n, false, side);
+        HINV_HIP(hipEventRecord(ev_join_, side));
+    }
     inc_forward(nc, mhat, ldm, uh, n, st);
     inc_adjoint(nc, gn, mhat, ldm, uh, n, ph, n, st);
-    hess_output(mode, nc, mhat, ldm, uh, n, ph, n, out, ldo);
+    if (with_prior) HINV_HIP(hipStreamWaitEvent(ctx->stream, ev_join_, 0));
+    hess_output(mode, nc, mhat, ldm, uh, n, ph, n, out, ldo, rm);
 }
 
 void Problem::mass_apply(int nc, const double* x, int ldx, double* y, int ldy) {
@@ -748,10 +781,10 @@ void Problem::mass_apply(int nc, const double* x, int ldx, double* y, int ldy) {
     HINV_LAUNCH_CHECK();
 }
 
-void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx) {
+void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx, hipStream_t s) {
     // Chebyshev iteration (no inner products) on the Jacobi-scaled consistent
     // mass matrix, whose spectrum lies in [1/2, 2] for P1 triangles.
-    hipStream_t s = ctx->stream;
+    if (!s) s = ctx->stream;
     const OpKA<double> M = prior_op(N, 0.0, 1.0, 0.0);
     const double lo = 0.5, hi = 2.0;
     const double theta = 0.5 * (hi + lo), dl = 0.5 * (hi - lo), sigma1 = theta / dl;
@@ -781,14 +814,15 @@ void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx) {
     }
 }
 
-void Problem::prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate) {
-    hipStream_t s = ctx->stream;
+void Problem::prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate,
+                          hipStream_t s) {
+    if (!s) s = ctx->stream;
     const OpKA<double> K = prior_op(N, gamma, delta, beta);
     double* t1 = scratch(3, nc);
     double* t2 = scratch(4, nc);
     k_prior_apply<<<grid2(n, nc), kBlock, 0, s>>>(K, x, ldx, t1, n, 0.0);
     HINV_LAUNCH_CHECK();
-    mass_solve(nc, t1, n, t2, n);
+    mass_solve(nc, t1, n, t2, n, s);
     k_prior_apply<<<grid2(n, nc), kBlock, 0, s>>>(K, t2, n, y, ldy, accumulate ? 1.0 : 0.0);
     HINV_LAUNCH_CHECK();
 }
