@@ -72,7 +72,7 @@ extern "C" {
 #define HINV_HESS_GN_MISFIT  3  /* Gauss-Newton misfit only */
 
 /* solver precision */
-#define HINV_PREC_FP64     0  /* FP64 multigrid-preconditioned CG */
+#define HINV_PREC_FP64     0  /* FP64 CG preconditioned by an FP32 multigrid V-cycle */
 #define HINV_PREC_FP32_IR  1  /* FP32 multigrid-PCG inside FP64 iterative refinement */
 #define HINV_PREC_AUTO     2  /* per call: FP64 below 8 right-hand sides (latency bound),
                                  FP32_IR from 8 up (bandwidth bound) */
