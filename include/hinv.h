@@ -38,8 +38,10 @@
  *     frees or retains caller memory beyond the call.
  *   - State-like vectors (u) hold their Dirichlet values; adjoint-like and
  *     incremental vectors (p, uhat, phat) are zero on the Dirichlet nodes.
- *   - All work is enqueued on the context's HIP stream.  Functions that return
- *     host values (cost, info structs, eigenvalues) synchronize that stream.
+ *   - All work is ordered on the context's HIP stream (a full Hessian action
+ *     forks its prior term onto an internal stream with an event and joins it
+ *     back before it returns).  Functions that return host values (cost, info
+ *     structs, eigenvalues) synchronize that stream.
  *   - A context is not thread-safe; use one context per host thread.
  *   - Iterative solves stop at |b - A x|_2 / |b|_2 <= rtol per column, the
  *     residual evaluated in FP64.  A column that does not get there within the
