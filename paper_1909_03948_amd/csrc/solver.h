@@ -88,8 +88,8 @@ class Hierarchy {
     // Runs the PCG iterations of the current inner solve.  tail, when given,
     // is enqueued before every completion check (the refinement step, gated
     // on the device to the columns whose PCG has finished); returns true when
-    // the last check found every column finished, its read-back (outer flags
-    // in host_flags_ + 4096, column states in host_st_) then follows the tail.
+    // the last check found every column finished, its read-back (column states
+    // and outer flags in the host block) then follows the tail.
     template <typename T>
     bool pcg(int nc, int max_iter, int* iters, const std::function<void()>* tail = nullptr);
     template <typename T>
@@ -158,11 +158,26 @@ class Hierarchy {
     DBuf<double> partial_;
     DBuf<double> pcg_part_;  // partial sums of r^T z, p^T q, r^T r per workgroup and column
     int red_stride_ = 0;
-    DBuf<ColState> st_;
-    DBuf<int> act_, oact_, tdone_;  // inner and outer activity, refinement step taken this pass
+    // Column states and flags in one device block [st[cap] | act[cap] | oact[cap]
+    // | tdone[cap]] (inner and outer activity, refinement step taken this
+    // pass), so that one copy reads back what a completion check needs; the
+    // pinned host block mirrors its layout.
+    template <typename T>
+    struct View {
+        T* p = nullptr;
+        T* get() const { return p; }
+    };
+    DBuf<char> sblk_;
+    View<ColState> st_;
+    View<int> act_, oact_, tdone_;
     DBuf<double> colnorm_;  // per column |r| used to scale the inner right-hand side
-    int* host_flags_ = nullptr;
-    ColState* host_st_ = nullptr;  // pinned: column states read by the refinement loop [0, 4096) and PCG [4096, 8192)
+    char* hblk_ = nullptr;   // pinned, room for 4096 columns
+    ColState* host_st() const { return reinterpret_cast<ColState*>(hblk_); }
+    int* host_act() const { return reinterpret_cast<int*>(hblk_ + sizeof(ColState) * cap_); }
+    int* host_oact() const { return host_act() + cap_; }
+    // reads back the column states and the first nflags flag arrays (act, then
+    // oact) of nc columns in one copy; no synchronization
+    void read_state(hipStream_t s, int nc, int nflags);
     hipStream_t gs_ = nullptr;             // private stream for graph capture
     hipStream_t launch_stream_ = nullptr;  // stream the PCG kernels go to (capture or caller)
     hipGraphExec_t gexec_[2] = {nullptr, nullptr};  // FP64 / FP32 two-iteration graphs

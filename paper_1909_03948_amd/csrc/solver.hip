@@ -414,8 +414,7 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp, int ninst,
     if (nc_coarse_ > 81) fail(HINV_EINVAL, "coarsest multigrid level too large (N must be a power of two)");
     cinv64_.ensure(ni * nc_coarse_ * nc_coarse_);
     cinv32_.ensure(ni * nc_coarse_ * nc_coarse_);
-    HINV_HIP(hipHostMalloc((void**)&host_flags_, sizeof(int) * 2 * 4096, hipHostMallocDefault));
-    HINV_HIP(hipHostMalloc((void**)&host_st_, sizeof(ColState) * 2 * 4096, hipHostMallocDefault));
+    HINV_HIP(hipHostMalloc((void**)&hblk_, (sizeof(ColState) + 3 * sizeof(int)) * 4096, hipHostMallocDefault));
     HINV_HIP(hipStreamCreateWithFlags(&gs_, hipStreamNonBlocking));
     launch_stream_ = ctx_->stream;
     if (kind_ == kOpPrior) {
@@ -450,8 +449,7 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp, int ninst,
 Hierarchy::~Hierarchy() {
     drop_graphs();
     if (gs_) (void)hipStreamDestroy(gs_);
-    if (host_flags_) (void)hipHostFree(host_flags_);
-    if (host_st_) (void)hipHostFree(host_st_);
+    if (hblk_) (void)hipHostFree(hblk_);
 }
 
 void Hierarchy::build_coarse(int inst) {
@@ -557,13 +555,19 @@ void Hierarchy::ensure_cols(int nc) {
     red_stride_ = std::max(ceil_div(n, kBlock), tiles);
     partial_.ensure((size_t)red_stride_ * nc);
     pcg_part_.ensure((size_t)red_stride_ * nc * 3);
-    st_.ensure(nc);
-    act_.ensure(nc);
-    oact_.ensure(nc);
-    tdone_.ensure(nc);
-    colnorm_.ensure(nc);
     if (nc > 4096) fail(HINV_EINVAL, "more than 4096 right-hand sides in one call");
+    sblk_.ensure((sizeof(ColState) + 3 * sizeof(int)) * (size_t)nc);
+    st_.p = reinterpret_cast<ColState*>(sblk_.get());
+    act_.p = reinterpret_cast<int*>(sblk_.get() + sizeof(ColState) * nc);
+    oact_.p = act_.p + nc;
+    tdone_.p = oact_.p + nc;
+    colnorm_.ensure(nc);
     cap_ = nc;
+}
+
+void Hierarchy::read_state(hipStream_t s, int nc, int nflags) {
+    const size_t bytes = sizeof(ColState) * cap_ + sizeof(int) * ((size_t)cap_ * (nflags - 1) + nc);
+    HINV_HIP(hipMemcpyAsync(hblk_, sblk_.get(), bytes, hipMemcpyDeviceToHost, s));
 }
 
 template <typename T>
@@ -1066,9 +1070,8 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
     for (const auto& kv : last_iters_)
         if (kv.first == key) expect = kv.second;
     bool first_check = true, tail_state = false;
-    // pinned, so the read-backs need no staging copy; with a tail the column
-    // states are read into the refinement loop's slot (the tail wrote them)
-    ColState* hst = tail ? host_st_ : host_st_ + 4096;
+    const ColState* hst = host_st();  // pinned, so the read-backs need no staging copy
+    const int* hact = host_act();
     while (it < max_iter) {
         int reps = 1;
         if (first_check && expect > it + 2) reps = std::min(6, (expect - it + 1) / 2);
@@ -1100,13 +1103,11 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
         }
         if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
         if (tail) (*tail)();
-        HINV_HIP(hipMemcpyAsync(host_flags_, act, sizeof(int) * nc, hipMemcpyDeviceToHost, s));
-        if (tail) HINV_HIP(hipMemcpyAsync(host_flags_ + 4096, oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToHost, s));
-        HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
+        read_state(s, nc, tail ? 2 : 1);
         HINV_HIP(hipStreamSynchronize(s));
         first_check = false;
         int live = 0;
-        for (int c = 0; c < nc; ++c) live += host_flags_[c];
+        for (int c = 0; c < nc; ++c) live += hact[c];
         if (!live) {
             tail_state = tail != nullptr;
             break;
@@ -1199,27 +1200,25 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
                                         colnorm_.get(), rtol, fp32 ? floor32 : floor64, nullptr, nullptr);
     HINV_LAUNCH_CHECK();
     int iters = 0, outer = 0, fallbacks = 0;
-    bool have_state = false;  // host_flags_ + 4096 and host_st_ already hold this pass's outer state
+    bool have_state = false;  // the host block already holds this pass's outer state
     const int max_outer = fp32 ? 16 : 4;
     bool use32 = fp32;
     std::vector<double> prev_rr(nc, INFINITY);  // unknown before the first pass
     std::vector<int> prev_on(nc, 0);             // outer flags at the start of the last pass
-    ColState* hst = host_st_;  // pinned, so the read-backs need no staging copy
+    const ColState* hst = host_st();  // pinned, so the read-backs need no staging copy
+    const int* hoact = host_oact();
     bool converged = false;
     while (true) {
         // the first pass starts without reading the flags back: its kernels
         // skip the columns that are already converged (b = 0)
         if (outer > 0) {
-            if (have_state) {
-                std::memcpy(host_flags_, host_flags_ + 4096, sizeof(int) * nc);
-            } else {
-                HINV_HIP(hipMemcpyAsync(host_flags_, oact_.get(), sizeof(int) * nc, hipMemcpyDeviceToHost, s));
-                HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
+            if (!have_state) {
+                read_state(s, nc, 2);
                 HINV_HIP(hipStreamSynchronize(s));
             }
             have_state = false;
             int live = 0;
-            for (int c = 0; c < nc; ++c) live += host_flags_[c];
+            for (int c = 0; c < nc; ++c) live += hoact[c];
             if (!live) {
                 converged = true;
                 break;
@@ -1227,7 +1226,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
         }
         if (outer >= max_outer || iters >= max_iter) {
             if (outer == 0) {
-                HINV_HIP(hipMemcpyAsync(hst, st_.get(), sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
+                read_state(s, nc, 1);
                 HINV_HIP(hipStreamSynchronize(s));
             }
             break;
@@ -1239,14 +1238,14 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
             bool stalled = false;
             if (outer > 0) {
                 for (int c = 0; c < nc; ++c)
-                    if (host_flags_[c] && hst[c].rr > 1e-2 * prev_rr[c]) stalled = true;
+                    if (hoact[c] && hst[c].rr > 1e-2 * prev_rr[c]) stalled = true;
                 if (outer >= 2)
                     for (int c = 0; c < nc; ++c)
                         if (prev_on[c] && prev_rr[c] > 0.0)
                             rho_seen = std::max(rho_seen, std::sqrt(hst[c].rr / prev_rr[c]));
                 for (int c = 0; c < nc; ++c) {
                     prev_rr[c] = hst[c].rr;
-                    prev_on[c] = host_flags_[c];
+                    prev_on[c] = hoact[c];
                 }
                 // the inner tolerances of the coming pass from the reductions seen
                 const double f = floor_for(rho_seen);
