@@ -18,6 +18,7 @@ namespace hinv {
 // workgroups) when few columns make the V-cycle latency bound.
 constexpr int kTCBig = 16, kTFBig = 32;      // coarse / fine nodes per tile side
 constexpr int kTCSmall = 8, kTFSmall = 16;
+constexpr int kTCTiny = 4, kTFTiny = 8;     // coarse levels of single-column cycles
 constexpr int kSmallTileCols = 8;            // batches below this use the small tiles
 constexpr int kBottomN = 32;   // levels with N_l <= kBottomN run in the bottom kernel
 constexpr int kBottomLevels = 4;  // at most (N_l = 64, 32, 16, 8 when kBottomN = 64)

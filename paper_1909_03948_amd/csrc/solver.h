@@ -122,6 +122,12 @@ class Hierarchy {
         int cb;  // columns per workgroup of the V-cycle kernels
     };
     bool small_tiles(int l) const { return shape_.small || lev_[l]->N <= shape_.small_max; }
+    // levels N_l <= 128 below the finest level of a cycle with small tiles
+    // everywhere (few columns: latency bound) shrink the tiles once more,
+    // shortening each workgroup's passes (measured: faster there, slower on
+    // the bandwidth-bound N = 512 level; the finest level keeps the tiles its
+    // partial sums are counted by)
+    bool tiny_tiles(int l) const { return shape_.small && l > 0 && lev_[l]->N <= 128; }
     LaunchShape default_shape(int nc) const;
     int min_per() const;
     template <typename T>
