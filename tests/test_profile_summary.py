@@ -102,6 +102,17 @@ def test_small_quotient_by_float_reciprocal_is_exact():
         assert np.array_equal(fdiv(qq, int(d)), qq // d), d
 
 
+def test_node_row_by_double_reciprocal_is_exact():
+    # the PCG apply kernel splits node k = j (N + 1) + i by j = (k + 1/2) * (1/(N + 1))
+    # in double precision, truncated
+    import numpy as np
+    for n1 in (9, 17, 33, 65, 129, 257, 513, 1025, 2049):
+        k = np.arange(n1 * n1, dtype=np.int64)
+        inv = 1.0 / n1
+        j = ((k.astype(np.float64) + 0.5) * inv).astype(np.int64)
+        assert np.array_equal(j, k // n1), n1
+
+
 def test_short_names_keep_helper_kernels():
     assert ps.short("void hinv::(anonymous namespace)::k_cheb_mass<32>(hinv::OpKA<double>, int)") == "k_cheb_mass<32>"
     assert ps.short("void hinv::k_up<float, hinv::OpA<float>, 16>(hinv::OpA<float>)") == "k_up<float, OpA<float>, 16>"
