@@ -457,9 +457,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"auto": "f64 (single rhs) / f32 in f64 refinement (batched), bf16 block product",
-                  "fp32ir": "f32 in f64 refinement, bf16 block product",
-                  "fp64": "f64"}[a.precision] if a.tprod == "bf16" or a.precision != "fp64" else "f64",
+        # the multigrid V-cycle (the preconditioner) is f32 in every mode
+        "dtype": ({"auto": "f64 PCG (single rhs) / f32 PCG in f64 refinement (batched), f32 V-cycle",
+                   "fp32ir": "f32 PCG in f64 refinement, f32 V-cycle",
+                   "fp64": "f64 PCG, f32 V-cycle"}[a.precision]
+                  + (", bf16 block product" if a.tprod == "bf16" else "")),
         "data": "synthetic",
         "config": {"workload": workload, "N": cfg["N"], "n_params": n, "q": cfg["q"],
                    "gamma": cfg["gamma"], "delta": cfg["delta"], "k": cfg["k"], "p": cfg["p"],
