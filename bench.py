@@ -5,10 +5,11 @@ One step = the whole hot path on the 256 x 256 Poisson coefficient-inversion
 workload (66 049 parameters, 400 observations, bilaplacian prior gamma = 0.1,
 delta = 0.5): inexact Newton-CG from the prior mean to |g| <= 1e-6 |g_0|, then
 the double-pass randomized eigensolver with k = 50, p = 20 (all 70 probe
-vectors in one batched multi-right-hand-side solve per pass).  Every state
-solve reaches a relative residual of 1e-10 (FP32 multigrid-PCG inside FP64
-refinement); the eigensolver's block product Q^T (A Q) runs on BF16 matrix
-cores with FP32 accumulation.
+vectors in one batched multi-right-hand-side solve per pass).  Every PDE
+solve reaches a relative residual of 1e-10 (single right-hand sides: FP64 CG
+preconditioned by an FP32 multigrid V-cycle; batches: FP32 multigrid-PCG
+inside FP64 refinement); the eigensolver's block product Q^T (A Q) runs on
+BF16 matrix cores with FP32 accumulation.
 
 value = Hessian-vector products completed in the timed steps / wall time
 (each Newton-CG Hessian action and each eigensolver column counts one).
