@@ -731,7 +731,13 @@ void Hierarchy::tune_shape(int nc) {
     PcgWork<T>& w = work<T>();
     const int n = n_;
     best_ms = 1e30f;
+    // Few columns whose node blocks fit the partial cap one per workgroup keep
+    // one block per workgroup: measured fastest inside the solves, while timing
+    // the apply kernel alone has picked 4 in some runs (3% slower solves).
+    const bool fixed_per = nc < kSmallTileCols && min_per() == 1;
+    if (fixed_per) best.per = 1;
     for (int per : {1, 4, 8, 16}) {
+        if (fixed_per) break;
         if (per < min_per()) continue;
         shape_.per = per;
         const PcgRed red = pcg_red(nc);
