@@ -127,14 +127,27 @@ __global__ __launch_bounds__(512) void k_gram_bf16(int n, int s1, int s2, int ch
         }
 }
 
-__global__ void k_gram_reduce(int s1, int s2, int nsplit, const double* __restrict__ part,
-                              double* __restrict__ C, int ldc) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= s1 * s2) return;
-    const int i = id % s1, j = id / s1;
+// C = sum of the nsplit partial products.  A workgroup of 64 x kRedLanes
+// threads owns 64 consecutive entries: lane y sums chunks y, y + kRedLanes, ...
+// and the kRedLanes sums are added in lane order (a fixed order).
+constexpr int kRedLanes = 16;
+__global__ __launch_bounds__(64 * kRedLanes) void k_gram_reduce(int s1, int s2, int nsplit,
+                                                                const double* __restrict__ part,
+                                                                double* __restrict__ C, int ldc) {
+    __shared__ double acc[kRedLanes][64];
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+    const int id = blockIdx.x * 64 + x;
+    const size_t tot = (size_t)s1 * s2;
     double s = 0.0;
-    for (int p = 0; p < nsplit; ++p) s += part[((size_t)p * s2 + j) * s1 + i];
-    C[i + (size_t)j * ldc] = s;
+    if (id < s1 * s2)
+        for (int p = y; p < nsplit; p += kRedLanes) s += part[(size_t)p * tot + id];
+    acc[y][x] = s;
+    __syncthreads();
+    if (y == 0 && id < s1 * s2) {
+        double t = 0.0;
+        for (int l = 0; l < kRedLanes; ++l) t += acc[l][x];
+        C[id % s1 + (size_t)(id / s1) * ldc] = t;
+    }
 }
 
 // C = alpha X B + beta C (X: n x s, B: s x t).  grid.x: strips of 16
@@ -177,8 +190,12 @@ __global__ __launch_bounds__(512) void k_gemm_tall(int n, int s, int t, double a
     }
 }
 
+// The one-workgroup factorizations below run on matrices addressed through a
+// pointer and a leading dimension, either in place in global memory or, for
+// small s, on copies staged in LDS (the _lds kernels: dynamic LDS, ld = s).
+
 // Upper Cholesky in place, one workgroup; A(a, c) = A[a + c lda].
-__global__ void k_cholesky(int s, double* __restrict__ A, int lda, double shift, int* __restrict__ flag) {
+__device__ __forceinline__ void cholesky_body(int s, double* A, int lda, double shift, int* __restrict__ flag) {
     __shared__ double rj;
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
@@ -209,8 +226,21 @@ __global__ void k_cholesky(int s, double* __restrict__ A, int lda, double shift,
     if (threadIdx.x == 0) *flag = bad;
 }
 
+__global__ void k_cholesky(int s, double* __restrict__ A, int lda, double shift, int* __restrict__ flag) {
+    cholesky_body(s, A, lda, shift, flag);
+}
+
+__global__ void k_cholesky_lds(int s, double* __restrict__ A, int lda, double shift, int* __restrict__ flag) {
+    extern __shared__ double sm[];
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) sm[id] = A[id % s + (size_t)(id / s) * lda];
+    __syncthreads();
+    cholesky_body(s, sm, s, shift, flag);
+    __syncthreads();
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) A[id % s + (size_t)(id / s) * lda] = sm[id];
+}
+
 // Rinv = R^-1 (upper), column by column, one workgroup.
-__global__ void k_tri_inverse(int s, const double* __restrict__ R, int ldr, double* __restrict__ Ri, int ldi) {
+__device__ __forceinline__ void tri_inverse_body(int s, const double* R, int ldr, double* Ri, int ldi) {
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) Ri[id % s + (size_t)(id / s) * ldi] = 0.0;
     __syncthreads();
     for (int j = 0; j < s; ++j) {
@@ -230,19 +260,102 @@ __global__ void k_tri_inverse(int s, const double* __restrict__ R, int ldr, doub
     }
 }
 
-// Parallel cyclic Jacobi (round-robin pairing), one workgroup.  Stops when
-// the off-diagonal Frobenius norm is below 1e-12 of the total, or, once it is
-// below 1e-8, when a sweep no longer halves it (rounding in the rotations
-// keeps it near s eps |T|, so a fixed tighter bound may never be met).
+__global__ void k_tri_inverse(int s, const double* __restrict__ R, int ldr, double* __restrict__ Ri, int ldi) {
+    tri_inverse_body(s, R, ldr, Ri, ldi);
+}
+
+__global__ void k_tri_inverse_lds(int s, const double* __restrict__ R, int ldr, double* __restrict__ Ri,
+                                  int ldi) {
+    extern __shared__ double sm[];
+    double* sr = sm;
+    double* si = sm + (size_t)s * s;
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) sr[id] = R[id % s + (size_t)(id / s) * ldr];
+    __syncthreads();
+    tri_inverse_body(s, sr, s, si, s);
+    __syncthreads();
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) Ri[id % s + (size_t)(id / s) * ldi] = si[id];
+}
+
+// Pair k of step `step` of the round-robin ordering of an even number m of
+// indices (every pair meets once in m - 1 steps), ordered so that p < q.
+__device__ __forceinline__ void rr_pair(int step, int k, int m, int& p, int& q) {
+    if (k == 0) {
+        p = step;
+        q = m - 1;
+    } else {
+        p = (step + k) % (m - 1);
+        q = (step - k + (m - 1)) % (m - 1);
+    }
+    if (p > q) {
+        const int tmp = p;
+        p = q;
+        q = tmp;
+    }
+}
+
+// Plane rotation (c, sv) that zeroes the off-diagonal entry of the symmetric
+// 2 x 2 block [app apq; apq aqq] (the smaller of the two rotation angles).
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c, double& sv) {
+    c = 1.0;
+    sv = 0.0;
+    if (apq != 0.0) {
+        const double th = (aqq - app) / (2.0 * apq);
+        const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+        c = 1.0 / sqrt(1.0 + tt * tt);
+        sv = tt * c;
+    }
+}
+
+// Squared off-diagonal and total Frobenius norms of the s x s matrix T (ld),
+// summed in a fixed order; every thread returns both.
+__device__ __forceinline__ void jacobi_norms(int s, const double* T, int ld, double& offn, double& totn) {
+    __shared__ double wsum[32];
+    double o = 0.0, t = 0.0;
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
+        const int a = id % s, c = id / s;
+        const double v = T[a + (size_t)c * ld];
+        t += v * v;
+        if (a != c) o += v * v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        o += __shfl_xor(o, off, 64);
+        t += __shfl_xor(t, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wsum[threadIdx.x >> 6] = o;
+        wsum[16 + (threadIdx.x >> 6)] = t;
+    }
+    __syncthreads();
+    double so = 0.0, st = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        so += wsum[w];
+        st += wsum[16 + w];
+    }
+    offn = so;
+    totn = st;
+    __syncthreads();  // wsum is reused by the next call
+}
+
+// Stopping test of the Jacobi sweeps: the off-diagonal Frobenius norm is below
+// 1e-12 of the total, or, once it is below 1e-8, a sweep no longer halves it
+// (rounding in the rotations keeps it near s eps |T|, so a fixed tighter
+// bound may never be met).  prev: squared off-diagonal norm of the previous
+// sweep (negative before the first).
+__device__ __forceinline__ bool jacobi_done(double offn, double totn, double prev) {
+    if (offn <= 1e-24 * totn || totn == 0.0) return true;
+    return prev >= 0.0 && offn <= 1e-16 * totn && offn > 0.25 * prev;
+}
+
+// Parallel cyclic Jacobi (round-robin pairing), one workgroup, in place in
+// global memory: each step computes the np disjoint rotations, applies them
+// to the rows, then to the columns of T and S.
 __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restrict__ S, int lds,
                          int max_sweeps) {
     const int m = s + (s & 1);
     const int np = m / 2;
     __shared__ double cs[256], sn[256];
     __shared__ int pp[256], qq[256];
-    __shared__ double offn, totn;
     double prev = -1.0;  // off-diagonal norm^2 of the previous sweep
-    __shared__ double wsum[32];
     // symmetrize, S = I
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
         const int a = id % s, c = id / s;
@@ -255,61 +368,17 @@ __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restr
     }
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // off-diagonal and total Frobenius norms
-        double o = 0.0, t = 0.0;
-        for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
-            const int a = id % s, c = id / s;
-            const double v = T[a + (size_t)c * ldt];
-            t += v * v;
-            if (a != c) o += v * v;
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            o += __shfl_xor(o, off, 64);
-            t += __shfl_xor(t, off, 64);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            wsum[threadIdx.x >> 6] = o;
-            wsum[16 + (threadIdx.x >> 6)] = t;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double so = 0.0, st = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-                so += wsum[w];
-                st += wsum[16 + w];
-            }
-            offn = so;
-            totn = st;
-        }
-        __syncthreads();
-        if (offn <= 1e-24 * totn || totn == 0.0) break;
-        if (prev >= 0.0 && offn <= 1e-16 * totn && offn > 0.25 * prev) break;
+        double offn, totn;
+        jacobi_norms(s, T, ldt, offn, totn);
+        if (jacobi_done(offn, totn, prev)) break;
         prev = offn;
         for (int step = 0; step < m - 1; ++step) {
             for (int k = threadIdx.x; k < np; k += blockDim.x) {
                 int p, q;
-                if (k == 0) {
-                    p = step;
-                    q = m - 1;
-                } else {
-                    p = (step + k) % (m - 1);
-                    q = (step - k + (m - 1)) % (m - 1);
-                }
-                if (p > q) {
-                    const int tmp = p;
-                    p = q;
-                    q = tmp;
-                }
+                rr_pair(step, k, m, p, q);
                 double c = 1.0, sv = 0.0;
-                if (q < s) {
-                    const double apq = T[p + (size_t)q * ldt];
-                    if (apq != 0.0) {
-                        const double th = (T[q + (size_t)q * ldt] - T[p + (size_t)p * ldt]) / (2.0 * apq);
-                        const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        sv = tt * c;
-                    }
-                }
+                if (q < s)
+                    jacobi_rotation(T[p + (size_t)p * ldt], T[q + (size_t)q * ldt], T[p + (size_t)q * ldt], c, sv);
                 pp[k] = p;
                 qq[k] = q;
                 cs[k] = c;
@@ -340,6 +409,80 @@ __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restr
             }
             __syncthreads();
         }
+    }
+}
+
+// The same sweeps on copies of T and S in LDS (m x m each, ld m; for odd s the
+// extra row and column are zero and their pair's rotation is the identity).
+// One pass per step applies both sides of the rotations: the thread of pair
+// block (k, l) forms rows p_k, q_k of J^T T on columns p_l, q_l and then
+// rotates those columns, the same products in the same order as the row pass
+// followed by the column pass; the remaining threads rotate the columns of S.
+__global__ __launch_bounds__(1024) void k_jacobi_lds(int s, double* __restrict__ T, int ldt,
+                                                     double* __restrict__ S, int lds, int max_sweeps) {
+    extern __shared__ double sm[];
+    const int m = s + (s & 1);
+    const int np = m / 2;
+    double* tl = sm;
+    double* sl = sm + (size_t)m * m;
+    __shared__ double cs[256], sn[256];
+    __shared__ int pp[256], qq[256];
+    for (int id = threadIdx.x; id < m * m; id += blockDim.x) {
+        const int a = id % m, c = id / m;
+        double v = 0.0;
+        if (a < s && c < s) v = a == c ? T[a + (size_t)a * ldt] : 0.5 * (T[a + (size_t)c * ldt] + T[c + (size_t)a * ldt]);
+        tl[id] = v;
+        sl[id] = (a == c && a < s) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double prev = -1.0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        double offn, totn;
+        jacobi_norms(s, tl, m, offn, totn);
+        if (jacobi_done(offn, totn, prev)) break;
+        prev = offn;
+        for (int step = 0; step < m - 1; ++step) {
+            for (int k = threadIdx.x; k < np; k += blockDim.x) {
+                int p, q;
+                rr_pair(step, k, m, p, q);
+                double c = 1.0, sv = 0.0;
+                if (q < s) jacobi_rotation(tl[p + p * m], tl[q + q * m], tl[p + q * m], c, sv);
+                pp[k] = p;
+                qq[k] = q;
+                cs[k] = c;
+                sn[k] = sv;
+            }
+            __syncthreads();
+            const int nb = np * np;
+            for (int id = threadIdx.x; id < nb + np * s; id += blockDim.x) {
+                if (id < nb) {
+                    const int k = id % np, l = id / np;
+                    const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
+                    const double ck = cs[k], sk = sn[k], cl = cs[l], sl_ = sn[l];
+                    const double a = tl[pk + pl * m], b = tl[pk + ql * m];
+                    const double c = tl[qk + pl * m], d = tl[qk + ql * m];
+                    const double r0x = ck * a - sk * c, r0y = ck * b - sk * d;
+                    const double r1x = sk * a + ck * c, r1y = sk * b + ck * d;
+                    tl[pk + pl * m] = cl * r0x - sl_ * r0y;
+                    tl[pk + ql * m] = sl_ * r0x + cl * r0y;
+                    tl[qk + pl * m] = cl * r1x - sl_ * r1y;
+                    tl[qk + ql * m] = sl_ * r1x + cl * r1y;
+                } else {
+                    const int j = id - nb;
+                    const int r = j % s, k = j / s;
+                    const int p = pp[k], q = qq[k];
+                    const double sp = sl[r + p * m], sq = sl[r + q * m];
+                    sl[r + p * m] = cs[k] * sp - sn[k] * sq;
+                    sl[r + q * m] = sn[k] * sp + cs[k] * sq;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
+        const int a = id % s, c = id / s;
+        T[a + (size_t)c * ldt] = tl[a + c * m];
+        S[a + (size_t)c * lds] = sl[a + c * m];
     }
 }
 
@@ -405,7 +548,8 @@ void gram(Ctx* ctx, DenseWork& w, int n, int s1, int s2, const double* X, int ld
         timed_launch(ctx, kKGram, flops, k_gram_f64, dim3(blocks, nsplit), dim3(64 * kBlkWaves), ctx->stream,
                      n, s1, s2, chunk, X, ldx, Y, ldy, w.part.get());
     HINV_LAUNCH_CHECK();
-    k_gram_reduce<<<ceil_div(s1 * s2, 256), 256, 0, ctx->stream>>>(s1, s2, nsplit, w.part.get(), C, ldc);
+    k_gram_reduce<<<ceil_div(s1 * s2, 64), 64 * kRedLanes, 0, ctx->stream>>>(s1, s2, nsplit, w.part.get(), C,
+                                                                            ldc);
     HINV_LAUNCH_CHECK();
 }
 
@@ -417,9 +561,21 @@ void gemm_tall(Ctx* ctx, int n, int s, int t, double alpha, const double* X, int
     HINV_LAUNCH_CHECK();
 }
 
+// Whether a one-workgroup kernel may stage `bytes` of dynamic LDS on the
+// context's device (with room for its static LDS, at most 8 KB here).
+bool lds_fits(Ctx* ctx, size_t bytes) {
+    int v = 0;
+    HINV_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    return bytes + 8192 <= (size_t)v;
+}
+
 bool cholesky_upper(Ctx* ctx, DenseWork& w, int s, double* A, int lda, double shift) {
     w.flag.ensure(1);
-    k_cholesky<<<1, 1024, 0, ctx->stream>>>(s, A, lda, shift, w.flag.get());
+    const size_t shm = sizeof(double) * s * s;
+    if (lds_fits(ctx, shm))
+        k_cholesky_lds<<<1, 1024, shm, ctx->stream>>>(s, A, lda, shift, w.flag.get());
+    else
+        k_cholesky<<<1, 1024, 0, ctx->stream>>>(s, A, lda, shift, w.flag.get());
     HINV_LAUNCH_CHECK();
     int bad = 0;
     HINV_HIP(hipMemcpyAsync(&bad, w.flag.get(), sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -428,7 +584,11 @@ bool cholesky_upper(Ctx* ctx, DenseWork& w, int s, double* A, int lda, double sh
 }
 
 void tri_inverse_upper(Ctx* ctx, int s, const double* R, int ldr, double* Rinv, int ldi) {
-    k_tri_inverse<<<1, 1024, 0, ctx->stream>>>(s, R, ldr, Rinv, ldi);
+    const size_t shm = sizeof(double) * 2 * s * s;
+    if (lds_fits(ctx, shm))
+        k_tri_inverse_lds<<<1, 1024, shm, ctx->stream>>>(s, R, ldr, Rinv, ldi);
+    else
+        k_tri_inverse<<<1, 1024, 0, ctx->stream>>>(s, R, ldr, Rinv, ldi);
     HINV_LAUNCH_CHECK();
 }
 
@@ -437,7 +597,11 @@ void sym_eig(Ctx* ctx, DenseWork& w, int s, double* T, int ldt, double* S, int l
     w.part.ensure((size_t)s * s + s);
     double* Stmp = w.part.get();
     double* lam_u = Stmp + (size_t)s * s;
-    k_jacobi<<<1, 1024, 0, ctx->stream>>>(s, T, ldt, Stmp, s, 40);
+    const size_t m = s + (s & 1), shm = sizeof(double) * 2 * m * m;
+    if (lds_fits(ctx, shm))
+        k_jacobi_lds<<<1, 1024, shm, ctx->stream>>>(s, T, ldt, Stmp, s, 40);
+    else
+        k_jacobi<<<1, 1024, 0, ctx->stream>>>(s, T, ldt, Stmp, s, 40);
     HINV_LAUNCH_CHECK();
     k_diag_copy<<<ceil_div(s, 256), 256, 0, ctx->stream>>>(s, T, ldt, lam_u);
     HINV_LAUNCH_CHECK();
