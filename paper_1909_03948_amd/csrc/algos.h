@@ -14,13 +14,17 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
 int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int ldo, int k,
                 double* lambda_host, double* V, int ldv, SolveStats* st);
 
-// The two dense stages of the double pass for one instance (used by batches).
+// The two dense stages of the double pass for a group of ni instances of one
+// mesh size (n nodes): member j's n x s blocks start at base + j n s (Y, Zb,
+// Q, AQ), its s x s matrices at base + j s^2 (G, Ri, T, S) and its s
+// eigenvalues at lam + j s.  The s x s factorizations of all members run in
+// one launch each; the tall products run per member.
 struct DenseWork;
-int precholqr(Problem& P, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
+int precholqr(Problem* const* P, int ni, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
               double* Ri);
-void rayleigh_ritz(Problem& P, DenseWork& dw, int s, int k, int tprod, const double* Q,
-                   const double* AQ, double* T, double* S, double* lam, double* V, int ldv,
-                   double* lambda_host);
+void rayleigh_ritz(Problem* const* P, int ni, DenseWork& dw, int s, int k, int tprod, const double* Q,
+                   const double* AQ, double* T, double* S, double* lam, double* const* V, int ldv,
+                   double* const* lambda_host);
 
 // Posterior samples through the low-rank update (Sec. 4.3.2).
 void posterior_sample(Problem& P, const double* m_map, int k, const double* lambda_host,

@@ -227,55 +227,67 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
 // ------------------------------------------------------- double pass ---
 namespace {
 
-// Orthonormal basis Z of span(Y) (the qr(Y) step of Algorithm 4) by shifted
-// CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Zhang, Yamamoto 2020): one
-// Cholesky QR on the Gram matrix shifted by 11 (n s + s (s+1)) u tr(Y^T Y),
-// then two plain Cholesky QR passes.  Y is overwritten by Z.
-bool orthonormalize(Ctx* c, DenseWork& w, int n, int s, double* Y, double* tmp, double* G,
+// Orthonormal bases Z_j of span(Y_j) (the qr(Y) step of Algorithm 4) by
+// shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Zhang, Yamamoto 2020):
+// one Cholesky QR on the Gram matrix shifted by 11 (n s + s (s+1)) u
+// tr(Y^T Y), then two plain Cholesky QR passes.  Y_j is overwritten by Z_j.
+bool orthonormalize(Ctx* c, DenseWork& w, int ni, int n, int s, double* Y, double* tmp, double* G,
                     double* Ri) {
+    const size_t ts = (size_t)n * s, ss = (size_t)s * s;
+    w.shift.ensure(ni);
     for (int pass = 0; pass < 3; ++pass) {
-        gram(c, w, n, s, s, Y, n, Y, n, G, s);
-        double shift = 0.0;
-        if (pass == 0) {
-            const double tr = trace(c, w, s, G, s);
-            shift = 11.0 * ((double)n * s + (double)s * (s + 1)) * 1.1102230246251565e-16 * tr;
+        for (int j = 0; j < ni; ++j) gram(c, w, n, s, s, Y + j * ts, n, Y + j * ts, n, G + j * ss, s);
+        if (pass == 0)
+            scaled_trace(c, ni, s, G, s, ss, 11.0 * ((double)n * s + (double)s * (s + 1)) * 1.1102230246251565e-16,
+                         w.shift.get());
+        if (!cholesky_upper(c, w, ni, s, G, s, ss, pass == 0 ? w.shift.get() : nullptr)) return false;
+        tri_inverse_upper(c, ni, s, G, s, ss, Ri, s, ss);
+        for (int j = 0; j < ni; ++j) {
+            gemm_tall(c, n, s, s, 1.0, Y + j * ts, n, Ri + j * ss, s, 0.0, tmp + j * ts, n);
+            dev_copy(c, n, s, tmp + j * ts, n, Y + j * ts, n);
         }
-        if (!cholesky_upper(c, w, s, G, s, shift)) return false;
-        tri_inverse_upper(c, s, G, s, Ri, s);
-        gemm_tall(c, n, s, s, 1.0, Y, n, Ri, s, 0.0, tmp, n);
-        dev_copy(c, n, s, tmp, n, Y, n);
     }
     return true;
 }
 
 }  // namespace
 
-// PreCholQR (Algorithm 4) on Y (n x s): Z = qr(Y), Zbar = B Z, R_Z = chol(Z^T Zbar),
-// Q = Z R_Z^-1 written to Q.  Y is overwritten by Z; Zb is scratch.
-int precholqr(Problem& P, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
+// PreCholQR (Algorithm 4) on each Y_j (n x s): Z = qr(Y), Zbar = B Z,
+// R_Z = chol(Z^T Zbar), Q = Z R_Z^-1 written to Q_j.  Y_j is overwritten by
+// Z_j; Zb is scratch.
+int precholqr(Problem* const* P, int ni, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
               double* Ri) {
-    Ctx* c = P.ctx;
-    const int n = P.n;
-    if (!orthonormalize(c, dw, n, s, Y, Q, G, Ri)) return HINV_EBREAK;  // Y <- Z
-    P.prior_apply(s, Y, n, Zb, n);                                       // Zbar = B Z
-    gram(c, dw, n, s, s, Y, n, Zb, n, G, s);                             // Z^T Zbar
-    if (!cholesky_upper(c, dw, s, G, s, 0.0)) return HINV_EBREAK;        // R_Z
-    tri_inverse_upper(c, s, G, s, Ri, s);
-    gemm_tall(c, n, s, s, 1.0, Y, n, Ri, s, 0.0, Q, n);                  // Q = Z R_Z^-1
+    Ctx* c = P[0]->ctx;
+    const int n = P[0]->n;
+    const size_t ts = (size_t)n * s, ss = (size_t)s * s;
+    if (!orthonormalize(c, dw, ni, n, s, Y, Q, G, Ri)) return HINV_EBREAK;  // Y <- Z
+    for (int j = 0; j < ni; ++j) {
+        P[j]->prior_apply(s, Y + j * ts, n, Zb + j * ts, n);                       // Zbar = B Z
+        gram(c, dw, n, s, s, Y + j * ts, n, Zb + j * ts, n, G + j * ss, s);      // Z^T Zbar
+    }
+    if (!cholesky_upper(c, dw, ni, s, G, s, ss)) return HINV_EBREAK;            // R_Z
+    tri_inverse_upper(c, ni, s, G, s, ss, Ri, s, ss);
+    for (int j = 0; j < ni; ++j)
+        gemm_tall(c, n, s, s, 1.0, Y + j * ts, n, Ri + j * ss, s, 0.0, Q + j * ts, n);  // Q = Z R_Z^-1
     return HINV_OK;
 }
 
 // Rayleigh-Ritz step of Algorithm 2: T = Q^T (A Q), T = S Lambda S^T (descending),
 // V = Q S_k, Lambda_k to the host (synchronizes the stream).
-void rayleigh_ritz(Problem& P, DenseWork& dw, int s, int k, int tprod, const double* Q,
-                   const double* AQ, double* T, double* S, double* lam, double* V, int ldv,
-                   double* lambda_host) {
-    Ctx* c = P.ctx;
-    const int n = P.n;
-    gram(c, dw, n, s, s, Q, n, AQ, n, T, s, tprod == HINV_TPROD_BF16);
-    sym_eig(c, dw, s, T, s, S, s, lam);
-    gemm_tall(c, n, s, k, 1.0, Q, n, S, s, 0.0, V, ldv);
-    HINV_HIP(hipMemcpyAsync(lambda_host, lam, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+void rayleigh_ritz(Problem* const* P, int ni, DenseWork& dw, int s, int k, int tprod, const double* Q,
+                   const double* AQ, double* T, double* S, double* lam, double* const* V, int ldv,
+                   double* const* lambda_host) {
+    Ctx* c = P[0]->ctx;
+    const int n = P[0]->n;
+    const size_t ts = (size_t)n * s, ss = (size_t)s * s;
+    for (int j = 0; j < ni; ++j)
+        gram(c, dw, n, s, s, Q + j * ts, n, AQ + j * ts, n, T + j * ss, s, tprod == HINV_TPROD_BF16);
+    sym_eig(c, dw, ni, s, T, s, ss, S, s, ss, lam, s);
+    for (int j = 0; j < ni; ++j) {
+        gemm_tall(c, n, s, k, 1.0, Q + j * ts, n, S + j * ss, s, 0.0, V[j], ldv);
+        HINV_HIP(hipMemcpyAsync(lambda_host[j], lam + (size_t)j * s, sizeof(double) * k, hipMemcpyDeviceToHost,
+                                c->stream));
+    }
     HINV_HIP(hipStreamSynchronize(c->stream));
 }
 
@@ -297,11 +309,12 @@ int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int
     // pass 1: Ybar = A Omega, Y = B^-1 Ybar  (A = H_misfit, B = R)
     P.hessian(mode, s, omega, ldo, W, n, st);
     P.prior_solve(s, W, n, Y, n, st);
-    const int rc = precholqr(P, dw, s, Y, Zb, W, G, Ri);  // Q in W
+    Problem* const pp = &P;
+    const int rc = precholqr(&pp, 1, dw, s, Y, Zb, W, G, Ri);  // Q in W
     if (rc != HINV_OK) return rc;
     // pass 2: T = Q^T A Q
     P.hessian(mode, s, W, n, Zb, n, st);
-    rayleigh_ritz(P, dw, s, k, tprod, W, Zb, T, S, lam, V, ldv, lambda_host);
+    rayleigh_ritz(&pp, 1, dw, s, k, tprod, W, Zb, T, S, lam, &V, ldv, &lambda_host);
     return HINV_OK;
 }
 

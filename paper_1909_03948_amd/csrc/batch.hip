@@ -98,13 +98,16 @@ void Batch::hessian(int mode, int nrhs, const double* const* mhat, double* const
 
 int Batch::lowrank_eig(int mode, int tprod, int s, const double* const* omega, int k,
                        double* lambda_host, double* const* V, SolveStats* st) {
+    size_t most = 0;  // members of the largest group
+    for (auto& gp : G_) most = std::max(most, gp->mem.size());
+    const size_t ss = (size_t)s * s;
     DBuf<double> small;
-    small.ensure((size_t)s * s * 4 + s);
+    small.ensure(most * (4 * ss + s));
     double* G = small.get();
-    double* Ri = G + (size_t)s * s;
-    double* T = Ri + (size_t)s * s;
-    double* S = T + (size_t)s * s;
-    double* lam = S + (size_t)s * s;
+    double* Ri = G + most * ss;
+    double* T = Ri + most * ss;
+    double* S = T + most * ss;
+    double* lam = S + most * ss;
     DenseWork dw;
     int status = HINV_OK;
     for (auto& gp : G_) {
@@ -132,19 +135,19 @@ int Batch::lowrank_eig(int mode, int tprod, int s, const double* const* omega, i
         g.HK->solve(nc, W, n, Y, n, precision_, rtol_, max_iter_, st);
         P_[g.mem[0]]->mass_apply(nc, Y, n, Zb, n);
         g.HK->solve(nc, Zb, n, Y, n, precision_, rtol_, max_iter_, st);
-        // PreCholQR per member: Q into W
+        // PreCholQR of every member: Q into W
+        std::vector<Problem*> mp(ni);
+        std::vector<double*> vout(ni), lout(ni);
         for (int j = 0; j < ni; ++j) {
-            const int rc = precholqr(*P_[g.mem[j]], dw, s, at(Y, j), at(Zb, j), at(W, j), G, Ri);
-            if (rc != HINV_OK) status = rc;
+            mp[j] = &*P_[g.mem[j]];
+            vout[j] = V[g.mem[j]];
+            lout[j] = lambda_host + (size_t)g.mem[j] * k;
         }
+        status = precholqr(mp.data(), ni, dw, s, Y, Zb, W, G, Ri);
         if (status != HINV_OK) return status;
-        // pass 2: A Q for every member, then the Rayleigh-Ritz step per member
+        // pass 2: A Q for every member, then the Rayleigh-Ritz step of every member
         group_hessian(g, mode, s, wq, zout, st);
-        for (int j = 0; j < ni; ++j) {
-            const int i = g.mem[j];
-            rayleigh_ritz(*P_[i], dw, s, k, tprod, at(W, j), at(Zb, j), T, S, lam, V[i], n,
-                          lambda_host + (size_t)i * k);
-        }
+        rayleigh_ritz(mp.data(), ni, dw, s, k, tprod, W, Zb, T, S, lam, vout.data(), n, lout.data());
     }
     return status;
 }

@@ -10,6 +10,7 @@ namespace hinv {
 // Scratch for split-K partial products.
 struct DenseWork {
     DBuf<double> part;
+    DBuf<double> shift;  // per-matrix diagonal shifts
     DBuf<int> flag;
 };
 
@@ -23,20 +24,28 @@ void gram(Ctx* ctx, DenseWork& w, int n, int s1, int s2, const double* X, int ld
 void gemm_tall(Ctx* ctx, int n, int s, int t, double alpha, const double* X, int ldx,
                const double* B, int ldb, double beta, double* C, int ldc);
 
-// Upper Cholesky factor in place: A (s x s, lda) = R^T R, R upper, lower part
-// zeroed.  Adds `shift` to the diagonal first.  Returns false on a
-// non-positive pivot.
-bool cholesky_upper(Ctx* ctx, DenseWork& w, int s, double* A, int lda, double shift);
+// The small s x s routines below treat nb independent matrices at once, one
+// workgroup each: matrix b starts at base + b * stride (strides in elements).
 
-// Rinv (s x s) = R^-1 for upper-triangular R.
-void tri_inverse_upper(Ctx* ctx, int s, const double* R, int ldr, double* Rinv, int ldi);
+// Upper Cholesky factors in place: A_b (s x s, lda) = R^T R, R upper, lower
+// part zeroed, after adding shift[b] (device array, or null for none) to the
+// diagonal.  Returns false if any matrix met a non-positive pivot
+// (synchronizes the stream).
+bool cholesky_upper(Ctx* ctx, DenseWork& w, int nb, int s, double* A, int lda, size_t sa,
+                    const double* shift = nullptr);
 
-// Symmetric eigendecomposition T = S diag(lam) S^T by parallel cyclic Jacobi;
-// T is symmetrized and overwritten; eigenpairs sorted by decreasing eigenvalue.
-void sym_eig(Ctx* ctx, DenseWork& w, int s, double* T, int ldt, double* S, int lds, double* lam);
+// Rinv_b (s x s) = R_b^-1 for upper-triangular R_b.
+void tri_inverse_upper(Ctx* ctx, int nb, int s, const double* R, int ldr, size_t sr, double* Rinv, int ldi,
+                       size_t si);
 
-// Frobenius-norm trace helper: returns trace(A) (host value; synchronizes).
-double trace(Ctx* ctx, DenseWork& w, int s, const double* A, int lda);
+// Symmetric eigendecompositions T_b = S_b diag(lam_b) S_b^T by parallel
+// cyclic Jacobi; T_b is symmetrized and overwritten; eigenpairs sorted by
+// decreasing eigenvalue.
+void sym_eig(Ctx* ctx, DenseWork& w, int nb, int s, double* T, int ldt, size_t st, double* S, int lds, size_t ss,
+             double* lam, size_t sl);
+
+// out[b] = factor * trace(A_b) (device, no synchronization).
+void scaled_trace(Ctx* ctx, int nb, int s, const double* A, int lda, size_t sa, double factor, double* out);
 
 // Row scaling B[i, :] *= d[i] (B: s x t column-major).
 void scale_rows(Ctx* ctx, int s, int t, const double* d, double* B, int ldb);

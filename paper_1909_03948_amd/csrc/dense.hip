@@ -9,6 +9,7 @@
 //                  B: lane l holds B[4 (l / 16) + e][l % 16]
 //                  D: lane l, item v holds D[4 (l / 16) + v][l % 16]
 #include <algorithm>
+#include <vector>
 
 #include "dense.h"
 
@@ -193,32 +194,39 @@ __global__ __launch_bounds__(512) void k_gemm_tall(int n, int s, int t, double a
 // The one-workgroup factorizations below run on matrices addressed through a
 // pointer and a leading dimension, either in place in global memory or, for
 // small s, on copies staged in LDS (the _lds kernels: dynamic LDS, ld = s).
+// A launch factors nb independent matrices, one workgroup each: workgroup b
+// takes the matrices at base + b * stride (strides in elements).
 
-// Upper Cholesky in place, one workgroup; A(a, c) = A[a + c lda].
+// Upper Cholesky in place, one workgroup; A(a, c) = A[a + c lda].  Step j
+// reads the pivot A(j, j), final since the previous step, in every thread,
+// updates the trailing upper triangle by the outer product of row j scaled by
+// 1 / sqrt(pivot), and scales row j - 1, which that update does not read:
+// one barrier per step.
 __device__ __forceinline__ void cholesky_body(int s, double* A, int lda, double shift, int* __restrict__ flag) {
-    __shared__ double rj;
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
     for (int i = threadIdx.x; i < s; i += blockDim.x) A[i + (size_t)i * lda] += shift;
     __syncthreads();
-    for (int j = 0; j < s; ++j) {
-        if (threadIdx.x == 0) {
-            const double piv = A[j + (size_t)j * lda];
-            if (!(piv > 0.0)) bad = 1;
-            rj = bad ? 1.0 : sqrt(piv);
-            A[j + (size_t)j * lda] = rj;
+    int bad = 0;
+    double rprev = 1.0;  // sqrt of the previous pivot
+    for (int j = 0; j <= s; ++j) {
+        if (j > 0)  // row j - 1 by its pivot root
+            for (int c = j - 1 + threadIdx.x; c < s; c += blockDim.x)
+                A[j - 1 + (size_t)c * lda] = c == j - 1 ? rprev : A[j - 1 + (size_t)c * lda] / rprev;
+        if (j == s) break;
+        const double piv = A[j + (size_t)j * lda];
+        if (!(piv > 0.0)) {
+            bad = 1;
+            break;
         }
-        __syncthreads();
-        if (bad) break;
-        for (int c = j + 1 + threadIdx.x; c < s; c += blockDim.x) A[j + (size_t)c * lda] /= rj;
-        __syncthreads();
+        const double rj = sqrt(piv), irj = 1.0 / rj;
         const int m = s - j - 1;
         for (int id = threadIdx.x; id < m * m; id += blockDim.x) {
             const int a = j + 1 + id % m, c = j + 1 + id / m;
-            if (a <= c) A[a + (size_t)c * lda] -= A[j + (size_t)a * lda] * A[j + (size_t)c * lda];
+            if (a <= c) A[a + (size_t)c * lda] -= (A[j + (size_t)a * lda] * irj) * (A[j + (size_t)c * lda] * irj);
         }
+        rprev = rj;
         __syncthreads();
     }
+    __syncthreads();
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
         const int a = id % s, c = id / s;
         if (a > c) A[a + (size_t)c * lda] = 0.0;
@@ -226,21 +234,45 @@ __device__ __forceinline__ void cholesky_body(int s, double* A, int lda, double 
     if (threadIdx.x == 0) *flag = bad;
 }
 
-__global__ void k_cholesky(int s, double* __restrict__ A, int lda, double shift, int* __restrict__ flag) {
-    cholesky_body(s, A, lda, shift, flag);
+// shift: per-matrix diagonal shifts (device) or null
+__global__ void k_cholesky(int s, double* __restrict__ A, int lda, size_t sa, const double* __restrict__ shift,
+                           int* __restrict__ flag) {
+    cholesky_body(s, A + blockIdx.x * sa, lda, shift ? shift[blockIdx.x] : 0.0, flag + blockIdx.x);
 }
 
-__global__ void k_cholesky_lds(int s, double* __restrict__ A, int lda, double shift, int* __restrict__ flag) {
+__global__ void k_cholesky_lds(int s, double* __restrict__ A, int lda, size_t sa, const double* __restrict__ shift,
+                               int* __restrict__ flag) {
     extern __shared__ double sm[];
+    A += blockIdx.x * sa;
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) sm[id] = A[id % s + (size_t)(id / s) * lda];
     __syncthreads();
-    cholesky_body(s, sm, s, shift, flag);
+    cholesky_body(s, sm, s, shift ? shift[blockIdx.x] : 0.0, flag + blockIdx.x);
     __syncthreads();
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) A[id % s + (size_t)(id / s) * lda] = sm[id];
 }
 
-// Rinv = R^-1 (upper), column by column, one workgroup.
+// Rinv = R^-1 (upper), one workgroup: thread j solves R x = e_j for column j
+// by back substitution (no barriers; the longest chain is s^2 / 2 products,
+// which LDS keeps short for small s).
 __device__ __forceinline__ void tri_inverse_body(int s, const double* R, int ldr, double* Ri, int ldi) {
+    for (int j = threadIdx.x; j < s; j += blockDim.x) {
+        double* x = Ri + (size_t)j * ldi;
+        for (int i = j + 1; i < s; ++i) x[i] = 0.0;
+        for (int i = j; i >= 0; --i) {
+            double acc = i == j ? 1.0 : 0.0;
+#pragma unroll 4
+            for (int k = i + 1; k <= j; ++k) acc -= R[i + (size_t)k * ldr] * x[k];
+            x[i] = acc / R[i + (size_t)i * ldr];
+        }
+    }
+}
+
+// In global memory (large s): column by column, threads i <= j of column j
+// in parallel, each an inner product with the finished columns.
+__global__ void k_tri_inverse(int s, const double* __restrict__ R, int ldr, size_t sr, double* __restrict__ Ri,
+                              int ldi, size_t si) {
+    R += blockIdx.x * sr;
+    Ri += blockIdx.x * si;
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) Ri[id % s + (size_t)(id / s) * ldi] = 0.0;
     __syncthreads();
     for (int j = 0; j < s; ++j) {
@@ -260,20 +292,18 @@ __device__ __forceinline__ void tri_inverse_body(int s, const double* R, int ldr
     }
 }
 
-__global__ void k_tri_inverse(int s, const double* __restrict__ R, int ldr, double* __restrict__ Ri, int ldi) {
-    tri_inverse_body(s, R, ldr, Ri, ldi);
-}
-
-__global__ void k_tri_inverse_lds(int s, const double* __restrict__ R, int ldr, double* __restrict__ Ri,
-                                  int ldi) {
+__global__ void k_tri_inverse_lds(int s, const double* __restrict__ R, int ldr, size_t sr,
+                                  double* __restrict__ Ri, int ldi, size_t si) {
     extern __shared__ double sm[];
-    double* sr = sm;
-    double* si = sm + (size_t)s * s;
-    for (int id = threadIdx.x; id < s * s; id += blockDim.x) sr[id] = R[id % s + (size_t)(id / s) * ldr];
+    R += blockIdx.x * sr;
+    Ri += blockIdx.x * si;
+    double* lr = sm;
+    double* li = sm + (size_t)s * s;
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) lr[id] = R[id % s + (size_t)(id / s) * ldr];
     __syncthreads();
-    tri_inverse_body(s, sr, s, si, s);
+    tri_inverse_body(s, lr, s, li, s);
     __syncthreads();
-    for (int id = threadIdx.x; id < s * s; id += blockDim.x) Ri[id % s + (size_t)(id / s) * ldi] = si[id];
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) Ri[id % s + (size_t)(id / s) * ldi] = li[id];
 }
 
 // Pair k of step `step` of the round-robin ordering of an even number m of
@@ -349,8 +379,10 @@ __device__ __forceinline__ bool jacobi_done(double offn, double totn, double pre
 // Parallel cyclic Jacobi (round-robin pairing), one workgroup, in place in
 // global memory: each step computes the np disjoint rotations, applies them
 // to the rows, then to the columns of T and S.
-__global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restrict__ S, int lds,
-                         int max_sweeps) {
+__global__ void k_jacobi(int s, double* __restrict__ T, int ldt, size_t st, double* __restrict__ S, int lds,
+                         size_t ss, int max_sweeps) {
+    T += blockIdx.x * st;
+    S += blockIdx.x * ss;
     const int m = s + (s & 1);
     const int np = m / 2;
     __shared__ double cs[256], sn[256];
@@ -418,9 +450,11 @@ __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, double* __restr
 // block (k, l) forms rows p_k, q_k of J^T T on columns p_l, q_l and then
 // rotates those columns, the same products in the same order as the row pass
 // followed by the column pass; the remaining threads rotate the columns of S.
-__global__ __launch_bounds__(1024) void k_jacobi_lds(int s, double* __restrict__ T, int ldt,
-                                                     double* __restrict__ S, int lds, int max_sweeps) {
+__global__ __launch_bounds__(1024) void k_jacobi_lds(int s, double* __restrict__ T, int ldt, size_t st,
+                                                     double* __restrict__ S, int lds, size_t ss, int max_sweeps) {
     extern __shared__ double sm[];
+    T += blockIdx.x * st;
+    S += blockIdx.x * ss;
     const int m = s + (s & 1);
     const int np = m / 2;
     double* tl = sm;
@@ -488,10 +522,16 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int s, double* __restrict__
 
 // Sorts the eigenpairs by decreasing eigenvalue: column c of S goes to column
 // rank(c) of Sout, and lam[rank(c)] = lam_unsorted[c] (ties keep index order).
-__global__ void k_eig_permute(int s, const double* __restrict__ lam_unsorted, const double* __restrict__ S,
-                              int lds, double* __restrict__ Sout, int ldo, double* __restrict__ lam) {
+// grid.y: matrix of the batch (S, Sout, lam_unsorted and lam at their strides).
+__global__ void k_eig_permute(int s, const double* __restrict__ lam_unsorted, size_t slu,
+                              const double* __restrict__ S, int lds, size_t ss, double* __restrict__ Sout, int ldo,
+                              size_t so, double* __restrict__ lam, size_t sl) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= s * s) return;
+    lam_unsorted += blockIdx.y * slu;
+    S += blockIdx.y * ss;
+    Sout += blockIdx.y * so;
+    lam += blockIdx.y * sl;
     const int r = id % s, c = id / s;
     const double lc = lam_unsorted[c];
     int rank = 0;
@@ -503,13 +543,17 @@ __global__ void k_eig_permute(int s, const double* __restrict__ lam_unsorted, co
     if (r == 0) lam[rank] = lc;
 }
 
-__global__ void k_diag_copy(int s, const double* __restrict__ T, int ldt, double* __restrict__ d) {
+__global__ void k_diag_copy(int s, const double* __restrict__ T, int ldt, size_t st, double* __restrict__ d,
+                            size_t sd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < s) d[i] = T[i + (size_t)i * ldt];
+    if (i < s) d[blockIdx.y * sd + i] = T[blockIdx.y * st + i + (size_t)i * ldt];
 }
 
-__global__ void k_trace(int s, const double* __restrict__ A, int lda, double* __restrict__ out) {
+// out[b] = factor * trace(A_b), one workgroup per matrix.
+__global__ void k_scaled_trace(int s, const double* __restrict__ A, int lda, size_t sa, double factor,
+                               double* __restrict__ out) {
     __shared__ double w[16];
+    A += blockIdx.x * sa;
     double v = 0.0;
     for (int i = threadIdx.x; i < s; i += blockDim.x) v += A[i + (size_t)i * lda];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -518,7 +562,7 @@ __global__ void k_trace(int s, const double* __restrict__ A, int lda, double* __
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += w[k];
-        *out = t;
+        out[blockIdx.x] = factor * t;
     }
 }
 
@@ -569,54 +613,60 @@ bool lds_fits(Ctx* ctx, size_t bytes) {
     return bytes + 8192 <= (size_t)v;
 }
 
-bool cholesky_upper(Ctx* ctx, DenseWork& w, int s, double* A, int lda, double shift) {
-    w.flag.ensure(1);
+bool cholesky_upper(Ctx* ctx, DenseWork& w, int nb, int s, double* A, int lda, size_t sa,
+                    const double* shift) {
+    if (nb <= 0) return true;
+    w.flag.ensure(nb);
     const size_t shm = sizeof(double) * s * s;
     if (lds_fits(ctx, shm))
-        k_cholesky_lds<<<1, 1024, shm, ctx->stream>>>(s, A, lda, shift, w.flag.get());
+        k_cholesky_lds<<<nb, 1024, shm, ctx->stream>>>(s, A, lda, sa, shift, w.flag.get());
     else
-        k_cholesky<<<1, 1024, 0, ctx->stream>>>(s, A, lda, shift, w.flag.get());
+        k_cholesky<<<nb, 1024, 0, ctx->stream>>>(s, A, lda, sa, shift, w.flag.get());
     HINV_LAUNCH_CHECK();
-    int bad = 0;
-    HINV_HIP(hipMemcpyAsync(&bad, w.flag.get(), sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<int> bad(nb);
+    HINV_HIP(hipMemcpyAsync(bad.data(), w.flag.get(), sizeof(int) * nb, hipMemcpyDeviceToHost, ctx->stream));
     HINV_HIP(hipStreamSynchronize(ctx->stream));
-    return bad == 0;
+    for (int b : bad)
+        if (b) return false;
+    return true;
 }
 
-void tri_inverse_upper(Ctx* ctx, int s, const double* R, int ldr, double* Rinv, int ldi) {
+void tri_inverse_upper(Ctx* ctx, int nb, int s, const double* R, int ldr, size_t sr, double* Rinv, int ldi,
+                       size_t si) {
+    if (nb <= 0) return;
     const size_t shm = sizeof(double) * 2 * s * s;
     if (lds_fits(ctx, shm))
-        k_tri_inverse_lds<<<1, 1024, shm, ctx->stream>>>(s, R, ldr, Rinv, ldi);
+        k_tri_inverse_lds<<<nb, 1024, shm, ctx->stream>>>(s, R, ldr, sr, Rinv, ldi, si);
     else
-        k_tri_inverse<<<1, 1024, 0, ctx->stream>>>(s, R, ldr, Rinv, ldi);
+        k_tri_inverse<<<nb, 1024, 0, ctx->stream>>>(s, R, ldr, sr, Rinv, ldi, si);
     HINV_LAUNCH_CHECK();
 }
 
-void sym_eig(Ctx* ctx, DenseWork& w, int s, double* T, int ldt, double* S, int lds, double* lam) {
+void sym_eig(Ctx* ctx, DenseWork& w, int nb, int s, double* T, int ldt, size_t st, double* S, int lds, size_t ss,
+             double* lam, size_t sl) {
     if (s > 512) fail(HINV_EINVAL, "eigenproblem larger than 512");
-    w.part.ensure((size_t)s * s + s);
+    if (nb <= 0 || s <= 0) return;
+    const size_t s2 = (size_t)s * s;
+    w.part.ensure(nb * (s2 + s));
     double* Stmp = w.part.get();
-    double* lam_u = Stmp + (size_t)s * s;
+    double* lam_u = Stmp + nb * s2;
     const size_t m = s + (s & 1), shm = sizeof(double) * 2 * m * m;
     if (lds_fits(ctx, shm))
-        k_jacobi_lds<<<1, 1024, shm, ctx->stream>>>(s, T, ldt, Stmp, s, 40);
+        k_jacobi_lds<<<nb, 1024, shm, ctx->stream>>>(s, T, ldt, st, Stmp, s, s2, 40);
     else
-        k_jacobi<<<1, 1024, 0, ctx->stream>>>(s, T, ldt, Stmp, s, 40);
+        k_jacobi<<<nb, 1024, 0, ctx->stream>>>(s, T, ldt, st, Stmp, s, s2, 40);
     HINV_LAUNCH_CHECK();
-    k_diag_copy<<<ceil_div(s, 256), 256, 0, ctx->stream>>>(s, T, ldt, lam_u);
+    k_diag_copy<<<dim3(ceil_div(s, 256), nb), 256, 0, ctx->stream>>>(s, T, ldt, st, lam_u, s);
     HINV_LAUNCH_CHECK();
-    k_eig_permute<<<ceil_div(s * s, 256), 256, 0, ctx->stream>>>(s, lam_u, Stmp, s, S, lds, lam);
+    k_eig_permute<<<dim3(ceil_div(s * s, 256), nb), 256, 0, ctx->stream>>>(s, lam_u, s, Stmp, s, s2, S, lds, ss,
+                                                                            lam, sl);
     HINV_LAUNCH_CHECK();
 }
 
-double trace(Ctx* ctx, DenseWork& w, int s, const double* A, int lda) {
-    w.part.ensure(1);
-    k_trace<<<1, 1024, 0, ctx->stream>>>(s, A, lda, w.part.get());
+void scaled_trace(Ctx* ctx, int nb, int s, const double* A, int lda, size_t sa, double factor, double* out) {
+    if (nb <= 0) return;
+    k_scaled_trace<<<nb, 1024, 0, ctx->stream>>>(s, A, lda, sa, factor, out);
     HINV_LAUNCH_CHECK();
-    double t = 0.0;
-    HINV_HIP(hipMemcpyAsync(&t, w.part.get(), sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HINV_HIP(hipStreamSynchronize(ctx->stream));
-    return t;
 }
 
 void scale_rows(Ctx* ctx, int s, int t, const double* d, double* B, int ldb) {

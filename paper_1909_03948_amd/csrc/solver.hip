@@ -152,48 +152,51 @@ __global__ void k_coarse_matrix(Op op, double* __restrict__ M) {
     M[id] = v;
 }
 
-// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting), one workgroup
-// of 1024 threads, n <= kGJMaxN.  Pivot step p:  a = M[p][p];
+// Gauss-Jordan inversion of an SPD matrix (no pivoting), one workgroup of
+// 1024 threads, n <= kGJMaxN, in place in M.  Pivot step p:  a = M[p][p];
 // M[i][j] -= M[i][p] M[p][j] / a (i, j != p);  M[p][j] /= a;
-// M[i][p] = -M[i][p] / a;  M[p][p] = 1 / a.  Thread t owns column t mod 128 of
-// rows t / 128, t / 128 + 8, ... (no index divisions in the pivot steps).
-constexpr int kGJMaxN = 128;
+// M[i][p] = -M[i][p] / a;  M[p][p] = 1 / a.  The matrix is held twice in LDS:
+// step p reads one copy and writes the other, so a step needs one barrier
+// and no staging of the pivot row and column.  Thread t owns the entries
+// t, t + 1024, ... of the row-major matrix (indices divided once, up front).
+constexpr int kGJMaxN = 81;
+constexpr int kGJOwn = (kGJMaxN * kGJMaxN + 1023) / 1024;
 __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict__ M) {
     extern __shared__ double sm[];
-    double* A = sm;            // n*n
-    double* rowp = sm + n * n;  // n
-    double* colp = rowp + n;    // n
-    constexpr int kRowStep = 1024 / kGJMaxN;
-    const int j = threadIdx.x & (kGJMaxN - 1), i0 = threadIdx.x / kGJMaxN;
-    if (j < n)
-        for (int i = i0; i < n; i += kRowStep) A[i * n + j] = M[i * n + j];
+    const int nn = n * n;
+    int oi[kGJOwn], oj[kGJOwn];
+#pragma unroll
+    for (int e = 0; e < kGJOwn; ++e) {
+        const int id = threadIdx.x + 1024 * e;
+        oi[e] = id < nn ? id / n : 0;
+        oj[e] = id < nn ? id - oi[e] * n : 0;
+        if (id < nn) sm[id] = M[id];
+    }
     __syncthreads();
     for (int p = 0; p < n; ++p) {
-        if ((int)threadIdx.x < n) {
-            rowp[threadIdx.x] = A[p * n + threadIdx.x];
-            colp[threadIdx.x] = A[threadIdx.x * n + p];
-        }
-        __syncthreads();
-        const double ia = 1.0 / rowp[p];
-        if (j < n) {
-            const double rj = rowp[j];
-            for (int i = i0; i < n; i += kRowStep) {
-                double v;
-                if (i == p && j == p)
-                    v = ia;
-                else if (i == p)
-                    v = rj * ia;
-                else if (j == p)
-                    v = -colp[i] * ia;
-                else
-                    v = A[i * n + j] - colp[i] * rj * ia;
-                A[i * n + j] = v;
-            }
+        const double* A = sm + (p & 1) * nn;
+        double* B = sm + (1 - (p & 1)) * nn;
+        const double ia = 1.0 / A[p * n + p];
+#pragma unroll
+        for (int e = 0; e < kGJOwn; ++e) {
+            const int id = threadIdx.x + 1024 * e;
+            if (id >= nn) break;
+            const int i = oi[e], j = oj[e];
+            double v;
+            if (i == p && j == p)
+                v = ia;
+            else if (i == p)
+                v = A[id] * ia;
+            else if (j == p)
+                v = -A[id] * ia;
+            else
+                v = A[id] - A[i * n + p] * A[p * n + j] * ia;
+            B[id] = v;
         }
         __syncthreads();
     }
-    if (j < n)
-        for (int i = i0; i < n; i += kRowStep) M[i * n + j] = A[i * n + j];
+    const double* A = sm + (n & 1) * nn;
+    for (int id = threadIdx.x; id < nn; id += 1024) M[id] = A[id];
 }
 
 __global__ void k_cast_d2f(const double* a, float* b, int n) {
@@ -465,7 +468,7 @@ void Hierarchy::build_coarse(int inst) {
             make_prior_op<double>(L.N, inst_pp_[inst].gamma, inst_pp_[inst].delta, inst_pp_[inst].beta), c64);
     HINV_LAUNCH_CHECK();
     if (nc > kGJMaxN) fail(HINV_EINVAL, "coarse level too large for the dense inverse");
-    const size_t shm = sizeof(double) * ((size_t)nc * nc + 2 * nc);
+    const size_t shm = sizeof(double) * 2 * (size_t)nc * nc;
     k_gauss_jordan<<<1, 1024, shm, s>>>(nc, c64);
     HINV_LAUNCH_CHECK();
     k_cast_d2f<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(c64, cinv32_.get() + (size_t)inst * tot, tot);
