@@ -202,6 +202,11 @@ __global__ __launch_bounds__(512) void k_gemm_tall(int n, int s, int t, double a
 // updates the trailing upper triangle by the outer product of row j scaled by
 // 1 / sqrt(pivot), and scales row j - 1, which that update does not read:
 // one barrier per step.
+// With U > 1, U items of the trailing update per thread are loaded before
+// they are stored; item indices advance by the workgroup size without
+// dividing.  (Measured: U = 8 gains nothing in global memory, where the
+// single-CU bandwidth bounds the update.)
+template <int U>
 __device__ __forceinline__ void cholesky_body(int s, double* A, int lda, double shift, int* __restrict__ flag) {
     for (int i = threadIdx.x; i < s; i += blockDim.x) A[i + (size_t)i * lda] += shift;
     __syncthreads();
@@ -218,10 +223,35 @@ __device__ __forceinline__ void cholesky_body(int s, double* A, int lda, double 
             break;
         }
         const double rj = sqrt(piv), irj = 1.0 / rj;
-        const int m = s - j - 1;
-        for (int id = threadIdx.x; id < m * m; id += blockDim.x) {
-            const int a = j + 1 + id % m, c = j + 1 + id / m;
-            if (a <= c) A[a + (size_t)c * lda] -= (A[j + (size_t)a * lda] * irj) * (A[j + (size_t)c * lda] * irj);
+        const int m = s - j - 1, bd = blockDim.x;
+        if (m > 0) {
+            const int da = bd % m, dc = bd / m;
+            int a = threadIdx.x % m, c = threadIdx.x / m;  // trailing block offsets, a fastest
+            for (int id = threadIdx.x; id < m * m; id += U * bd) {
+                double x[U], ya[U], yc[U];
+                int as[U], cs[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    as[u] = a;
+                    cs[u] = c;
+                    x[u] = ya[u] = yc[u] = 0.0;
+                    if (id + u * bd < m * m && a <= c) {
+                        ya[u] = A[j + (size_t)(j + 1 + a) * lda];
+                        yc[u] = A[j + (size_t)(j + 1 + c) * lda];
+                        x[u] = A[j + 1 + a + (size_t)(j + 1 + c) * lda];
+                    }
+                    a += da;
+                    c += dc;
+                    if (a >= m) {
+                        a -= m;
+                        ++c;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (id + u * bd < m * m && as[u] <= cs[u])
+                        A[j + 1 + as[u] + (size_t)(j + 1 + cs[u]) * lda] = x[u] - (ya[u] * irj) * (yc[u] * irj);
+            }
         }
         rprev = rj;
         __syncthreads();
@@ -235,18 +265,18 @@ __device__ __forceinline__ void cholesky_body(int s, double* A, int lda, double 
 }
 
 // shift: per-matrix diagonal shifts (device) or null
-__global__ void k_cholesky(int s, double* __restrict__ A, int lda, size_t sa, const double* __restrict__ shift,
+__global__ __launch_bounds__(1024) void k_cholesky(int s, double* __restrict__ A, int lda, size_t sa, const double* __restrict__ shift,
                            int* __restrict__ flag) {
-    cholesky_body(s, A + blockIdx.x * sa, lda, shift ? shift[blockIdx.x] : 0.0, flag + blockIdx.x);
+    cholesky_body<1>(s, A + blockIdx.x * sa, lda, shift ? shift[blockIdx.x] : 0.0, flag + blockIdx.x);
 }
 
-__global__ void k_cholesky_lds(int s, double* __restrict__ A, int lda, size_t sa, const double* __restrict__ shift,
+__global__ __launch_bounds__(1024) void k_cholesky_lds(int s, double* __restrict__ A, int lda, size_t sa, const double* __restrict__ shift,
                                int* __restrict__ flag) {
     extern __shared__ double sm[];
     A += blockIdx.x * sa;
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) sm[id] = A[id % s + (size_t)(id / s) * lda];
     __syncthreads();
-    cholesky_body(s, sm, s, shift ? shift[blockIdx.x] : 0.0, flag + blockIdx.x);
+    cholesky_body<1>(s, sm, s, shift ? shift[blockIdx.x] : 0.0, flag + blockIdx.x);
     __syncthreads();
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) A[id % s + (size_t)(id / s) * lda] = sm[id];
 }
@@ -376,29 +406,101 @@ __device__ __forceinline__ bool jacobi_done(double offn, double totn, double pre
     return prev >= 0.0 && offn <= 1e-16 * totn && offn > 0.25 * prev;
 }
 
-// Parallel cyclic Jacobi (round-robin pairing), one workgroup, in place in
-// global memory: each step computes the np disjoint rotations, applies them
-// to the rows, then to the columns of T and S.
-__global__ void k_jacobi(int s, double* __restrict__ T, int ldt, size_t st, double* __restrict__ S, int lds,
-                         size_t ss, int max_sweeps) {
-    T += blockIdx.x * st;
-    S += blockIdx.x * ss;
+// One step of the parallel Jacobi sweep: the np rotations (pp, qq, cs, sn)
+// applied to both sides of T and to the columns of S.  The thread of pair
+// block (k, l) forms rows p_k, q_k of J^T T on columns p_l, q_l and rotates
+// those columns: the same products in the same order as a row pass followed
+// by a column pass, with every entry of T read and written once.  A pair
+// with q >= s (odd s) has the identity rotation and no row or column q.  Each
+// thread keeps U items' loads in flight before their stores, and advances
+// its item indices by the workgroup size without dividing.
+template <int U>
+__device__ __forceinline__ void jacobi_apply(int s, int np, double* T, int ldt, double* S, int lds,
+                                             const int* pp, const int* qq, const double* cs, const double* sn) {
+    const int bd = blockDim.x;
+    {
+        const int nb = np * np, dk = bd % np, dl = bd / np;
+        int k = threadIdx.x % np, l = threadIdx.x / np;
+        for (int id = threadIdx.x; id < nb; id += U * bd) {
+            double va[U], vb[U], vc[U], vd[U];
+            int ks[U], ls[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ks[u] = k;
+                ls[u] = l;
+                va[u] = vb[u] = vc[u] = vd[u] = 0.0;
+                if (id + u * bd < nb) {
+                    const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
+                    va[u] = T[pk + (size_t)pl * ldt];
+                    if (ql < s) vb[u] = T[pk + (size_t)ql * ldt];
+                    if (qk < s) vc[u] = T[qk + (size_t)pl * ldt];
+                    if (qk < s && ql < s) vd[u] = T[qk + (size_t)ql * ldt];
+                }
+                k += dk;
+                l += dl;
+                if (k >= np) {
+                    k -= np;
+                    ++l;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (id + u * bd >= nb) break;
+                const int kk = ks[u], ll = ls[u];
+                const int pk = pp[kk], qk = qq[kk], pl = pp[ll], ql = qq[ll];
+                const double ck = cs[kk], sk = sn[kk], cl = cs[ll], sl = sn[ll];
+                const double r0x = ck * va[u] - sk * vc[u], r0y = ck * vb[u] - sk * vd[u];
+                const double r1x = sk * va[u] + ck * vc[u], r1y = sk * vb[u] + ck * vd[u];
+                T[pk + (size_t)pl * ldt] = cl * r0x - sl * r0y;
+                if (ql < s) T[pk + (size_t)ql * ldt] = sl * r0x + cl * r0y;
+                if (qk < s) T[qk + (size_t)pl * ldt] = cl * r1x - sl * r1y;
+                if (qk < s && ql < s) T[qk + (size_t)ql * ldt] = sl * r1x + cl * r1y;
+            }
+        }
+    }
+    {
+        const int ns = np * s, dr = bd % s, dq = bd / s;
+        int r = threadIdx.x % s, k = threadIdx.x / s;
+        for (int id = threadIdx.x; id < ns; id += U * bd) {
+            double vp[U], vq[U];
+            int rs[U], ks[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                rs[u] = r;
+                ks[u] = k;
+                vp[u] = vq[u] = 0.0;
+                if (id + u * bd < ns && qq[k] < s) {
+                    vp[u] = S[r + (size_t)pp[k] * lds];
+                    vq[u] = S[r + (size_t)qq[k] * lds];
+                }
+                r += dr;
+                k += dq;
+                if (r >= s) {
+                    r -= s;
+                    ++k;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (id + u * bd >= ns) break;
+                const int kk = ks[u], rr = rs[u];
+                if (qq[kk] >= s) continue;
+                S[rr + (size_t)pp[kk] * lds] = cs[kk] * vp[u] - sn[kk] * vq[u];
+                S[rr + (size_t)qq[kk] * lds] = sn[kk] * vp[u] + cs[kk] * vq[u];
+            }
+        }
+    }
+}
+
+// Parallel cyclic Jacobi (round-robin pairing), one workgroup, on T and S
+// (ld ldt, lds): per step, the np disjoint rotations, then jacobi_apply.
+template <int U>
+__device__ __forceinline__ void jacobi_sweeps(int s, double* T, int ldt, double* S, int lds, int max_sweeps) {
     const int m = s + (s & 1);
     const int np = m / 2;
     __shared__ double cs[256], sn[256];
     __shared__ int pp[256], qq[256];
     double prev = -1.0;  // off-diagonal norm^2 of the previous sweep
-    // symmetrize, S = I
-    for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
-        const int a = id % s, c = id / s;
-        if (a < c) {
-            const double v = 0.5 * (T[a + (size_t)c * ldt] + T[c + (size_t)a * ldt]);
-            T[a + (size_t)c * ldt] = v;
-            T[c + (size_t)a * ldt] = v;
-        }
-        S[a + (size_t)c * lds] = a == c ? 1.0 : 0.0;
-    }
-    __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double offn, totn;
         jacobi_norms(s, T, ldt, offn, totn);
@@ -417,106 +519,51 @@ __global__ void k_jacobi(int s, double* __restrict__ T, int ldt, size_t st, doub
                 sn[k] = sv;
             }
             __syncthreads();
-            // rows p, q  <- J^T T
-            for (int id = threadIdx.x; id < np * s; id += blockDim.x) {
-                const int k = id % np, c = id / np;
-                const int p = pp[k], q = qq[k];
-                if (q >= s) continue;
-                const double tp = T[p + (size_t)c * ldt], tq = T[q + (size_t)c * ldt];
-                T[p + (size_t)c * ldt] = cs[k] * tp - sn[k] * tq;
-                T[q + (size_t)c * ldt] = sn[k] * tp + cs[k] * tq;
-            }
-            __syncthreads();
-            // columns p, q  <- T J, S J (consecutive threads on consecutive rows)
-            for (int id = threadIdx.x; id < np * s; id += blockDim.x) {
-                const int r = id % s, k = id / s;
-                const int p = pp[k], q = qq[k];
-                if (q >= s) continue;
-                const double tp = T[r + (size_t)p * ldt], tq = T[r + (size_t)q * ldt];
-                T[r + (size_t)p * ldt] = cs[k] * tp - sn[k] * tq;
-                T[r + (size_t)q * ldt] = sn[k] * tp + cs[k] * tq;
-                const double sp = S[r + (size_t)p * lds], sq = S[r + (size_t)q * lds];
-                S[r + (size_t)p * lds] = cs[k] * sp - sn[k] * sq;
-                S[r + (size_t)q * lds] = sn[k] * sp + cs[k] * sq;
-            }
+            jacobi_apply<U>(s, np, T, ldt, S, lds, pp, qq, cs, sn);
             __syncthreads();
         }
     }
 }
 
-// The same sweeps on copies of T and S in LDS (m x m each, ld m; for odd s the
-// extra row and column are zero and their pair's rotation is the identity).
-// One pass per step applies both sides of the rotations: the thread of pair
-// block (k, l) forms rows p_k, q_k of J^T T on columns p_l, q_l and then
-// rotates those columns, the same products in the same order as the row pass
-// followed by the column pass; the remaining threads rotate the columns of S.
+// In place in global memory (large s); eight items per thread in flight.
+__global__ __launch_bounds__(1024) void k_jacobi(int s, double* __restrict__ T, int ldt, size_t st,
+                                                 double* __restrict__ S, int lds, size_t ss, int max_sweeps) {
+    T += blockIdx.x * st;
+    S += blockIdx.x * ss;
+    // symmetrize, S = I
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
+        const int a = id % s, c = id / s;
+        if (a < c) {
+            const double v = 0.5 * (T[a + (size_t)c * ldt] + T[c + (size_t)a * ldt]);
+            T[a + (size_t)c * ldt] = v;
+            T[c + (size_t)a * ldt] = v;
+        }
+        S[a + (size_t)c * lds] = a == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_sweeps<8>(s, T, ldt, S, lds, max_sweeps);
+}
+
+// The same sweeps on copies of T and S in LDS (ld s), written back at the end;
+// one item per thread at a time (LDS latency needs no loads in flight).
 __global__ __launch_bounds__(1024) void k_jacobi_lds(int s, double* __restrict__ T, int ldt, size_t st,
                                                      double* __restrict__ S, int lds, size_t ss, int max_sweeps) {
     extern __shared__ double sm[];
     T += blockIdx.x * st;
     S += blockIdx.x * ss;
-    const int m = s + (s & 1);
-    const int np = m / 2;
     double* tl = sm;
-    double* sl = sm + (size_t)m * m;
-    __shared__ double cs[256], sn[256];
-    __shared__ int pp[256], qq[256];
-    for (int id = threadIdx.x; id < m * m; id += blockDim.x) {
-        const int a = id % m, c = id / m;
-        double v = 0.0;
-        if (a < s && c < s) v = a == c ? T[a + (size_t)a * ldt] : 0.5 * (T[a + (size_t)c * ldt] + T[c + (size_t)a * ldt]);
-        tl[id] = v;
-        sl[id] = (a == c && a < s) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    double prev = -1.0;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        double offn, totn;
-        jacobi_norms(s, tl, m, offn, totn);
-        if (jacobi_done(offn, totn, prev)) break;
-        prev = offn;
-        for (int step = 0; step < m - 1; ++step) {
-            for (int k = threadIdx.x; k < np; k += blockDim.x) {
-                int p, q;
-                rr_pair(step, k, m, p, q);
-                double c = 1.0, sv = 0.0;
-                if (q < s) jacobi_rotation(tl[p + p * m], tl[q + q * m], tl[p + q * m], c, sv);
-                pp[k] = p;
-                qq[k] = q;
-                cs[k] = c;
-                sn[k] = sv;
-            }
-            __syncthreads();
-            const int nb = np * np;
-            for (int id = threadIdx.x; id < nb + np * s; id += blockDim.x) {
-                if (id < nb) {
-                    const int k = id % np, l = id / np;
-                    const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
-                    const double ck = cs[k], sk = sn[k], cl = cs[l], sl_ = sn[l];
-                    const double a = tl[pk + pl * m], b = tl[pk + ql * m];
-                    const double c = tl[qk + pl * m], d = tl[qk + ql * m];
-                    const double r0x = ck * a - sk * c, r0y = ck * b - sk * d;
-                    const double r1x = sk * a + ck * c, r1y = sk * b + ck * d;
-                    tl[pk + pl * m] = cl * r0x - sl_ * r0y;
-                    tl[pk + ql * m] = sl_ * r0x + cl * r0y;
-                    tl[qk + pl * m] = cl * r1x - sl_ * r1y;
-                    tl[qk + ql * m] = sl_ * r1x + cl * r1y;
-                } else {
-                    const int j = id - nb;
-                    const int r = j % s, k = j / s;
-                    const int p = pp[k], q = qq[k];
-                    const double sp = sl[r + p * m], sq = sl[r + q * m];
-                    sl[r + p * m] = cs[k] * sp - sn[k] * sq;
-                    sl[r + q * m] = sn[k] * sp + cs[k] * sq;
-                }
-            }
-            __syncthreads();
-        }
-    }
+    double* sl = sm + (size_t)s * s;
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
         const int a = id % s, c = id / s;
-        T[a + (size_t)c * ldt] = tl[a + c * m];
-        S[a + (size_t)c * lds] = sl[a + c * m];
+        tl[id] = a == c ? T[a + (size_t)a * ldt] : 0.5 * (T[a + (size_t)c * ldt] + T[c + (size_t)a * ldt]);
+        sl[id] = a == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_sweeps<1>(s, tl, s, sl, s, max_sweeps);
+    for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
+        const int a = id % s, c = id / s;
+        T[a + (size_t)c * ldt] = tl[id];
+        S[a + (size_t)c * lds] = sl[id];
     }
 }
 
@@ -650,7 +697,7 @@ void sym_eig(Ctx* ctx, DenseWork& w, int nb, int s, double* T, int ldt, size_t s
     w.part.ensure(nb * (s2 + s));
     double* Stmp = w.part.get();
     double* lam_u = Stmp + nb * s2;
-    const size_t m = s + (s & 1), shm = sizeof(double) * 2 * m * m;
+    const size_t shm = sizeof(double) * 2 * s2;
     if (lds_fits(ctx, shm))
         k_jacobi_lds<<<nb, 1024, shm, ctx->stream>>>(s, T, ldt, st, Stmp, s, s2, 40);
     else
