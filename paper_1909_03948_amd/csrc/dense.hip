@@ -34,6 +34,10 @@ __device__ inline short to_bf16(double x) {
 // (kBlkTiles matrix-core tiles sharing one operand), so each column of X and
 // Y is read by ceil(s / 128) workgroups instead of ceil(s / 16).
 constexpr int kBlkWaves = 8, kBlkTiles = 8, kBlk = 128;
+// FP64 products load the operands of kKSteps matrix-core K steps before
+// issuing their products (in K order), so each wave has that many L2 round
+// trips in flight instead of one.
+constexpr int kKSteps = 4;
 
 // Split-K Gram C = X^T Y: grid.x = output block, grid.y = K chunk.
 __global__ __launch_bounds__(512) void k_gram_f64(int n, int s1, int s2, int chunk,
@@ -59,15 +63,21 @@ __global__ __launch_bounds__(512) void k_gram_f64(int n, int s1, int s2, int chu
         yc[t] = Y + (size_t)(jv[t] ? j : 0) * ldy;
         acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
     }
-    for (int k0 = k_begin; k0 < k_end; k0 += 4) {
-        const int k = k0 + kr;
-        const bool kv = k < k_end;
-        const double a = (i < s1 && kv) ? xc[k] : 0.0;
+    for (int k0 = k_begin; k0 < k_end; k0 += 4 * kKSteps) {
+        double a[kKSteps], b[kKSteps][kBlkTiles];
 #pragma unroll
-        for (int t = 0; t < kBlkTiles; ++t) {
-            const double b = (jv[t] && kv) ? yc[t][k] : 0.0;
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        for (int u = 0; u < kKSteps; ++u) {
+            const int k = k0 + 4 * u + kr;
+            const bool kv = k < k_end;
+            a[u] = (i < s1 && kv) ? xc[k] : 0.0;
+#pragma unroll
+            for (int t = 0; t < kBlkTiles; ++t) b[u][t] = (jv[t] && kv) ? yc[t][k] : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < kKSteps; ++u)
+#pragma unroll
+            for (int t = 0; t < kBlkTiles; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < kBlkTiles; ++t)
@@ -167,15 +177,23 @@ __global__ __launch_bounds__(512) void k_gemm_tall(int n, int s, int t, double a
     d4_t acc[kBlkTiles];
 #pragma unroll
     for (int tt = 0; tt < kBlkTiles; ++tt) acc[tt] = d4_t{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < s; k0 += 4) {
-        const int k = k0 + kr;
-        const double a = (row < n && k < s) ? X[(size_t)k * ldx + row] : 0.0;
+    for (int k0 = 0; k0 < s; k0 += 4 * kKSteps) {
+        double a[kKSteps], b[kKSteps][kBlkTiles];
 #pragma unroll
-        for (int tt = 0; tt < kBlkTiles; ++tt) {
-            const int colb = c0 + tt * 16 + (lane & 15);
-            const double b = (colb < t && k < s) ? B[k + (size_t)colb * ldb] : 0.0;
-            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[tt], 0, 0, 0);
+        for (int u = 0; u < kKSteps; ++u) {
+            const int k = k0 + 4 * u + kr;
+            a[u] = (row < n && k < s) ? X[(size_t)k * ldx + row] : 0.0;
+#pragma unroll
+            for (int tt = 0; tt < kBlkTiles; ++tt) {
+                const int colb = c0 + tt * 16 + (lane & 15);
+                b[u][tt] = (colb < t && k < s) ? B[k + (size_t)colb * ldb] : 0.0;
+            }
         }
+#pragma unroll
+        for (int u = 0; u < kKSteps; ++u)
+#pragma unroll
+            for (int tt = 0; tt < kBlkTiles; ++tt)
+                acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][tt], acc[tt], 0, 0, 0);
     }
 #pragma unroll
     for (int tt = 0; tt < kBlkTiles; ++tt) {
