@@ -101,6 +101,31 @@ def test_double_pass_eigenpairs(ctx, map32, mode, prec):
             assert abs(abs(V_o[:, i] @ RV[:, i]) - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("k,p", [(50, 21), (100, 9)])
+def test_double_pass_odd_probe_counts(ctx, k, p):
+    """Odd s = k + p on both sides of the size where the s x s factorizations
+    leave LDS (s = 71 in LDS, s = 109 in global memory): the Jacobi sweeps
+    then pair one index with a padding index every step."""
+    s = k + p
+    print(f"[gpu] double pass odd s={s}", flush=True)
+    prob, m, obs = instance(32, 300)
+    u = prob.forward(m)
+    adj = prob.adjoint(m, u)
+    Om = synth.omega(prob.n, s, seed=7)
+    A = lambda v: prob.hessian_apply(m, u, adj, v, model.HESS_GN_MISFIT)
+    lam_o, _, _ = lowrank.double_pass(A, prob.R_apply, prob.R_solve, Om.T, k)
+    gp = gpu_problem(ctx, prob, obs)
+    gp.linearize(dev(m), dev(u), dev(adj))
+    V = dev(np.zeros((k, prob.n)))
+    lam, info = gp.lowrank_eig(dev(Om), k, V, mode=hv.HESS_GN_MISFIT)
+    assert info["rc"] == 0, info
+    l1 = abs(lam_o[0])
+    assert np.max(np.abs(lam - lam_o)) <= 1e-8 * l1
+    Vg = host(V).T
+    RV = np.column_stack([prob.R_apply(v) for v in Vg.T])
+    np.testing.assert_allclose(Vg.T @ RV, np.eye(k), atol=1e-8)
+
+
 def test_double_pass_bf16_block_product(ctx, map32):
     prob, obs, m = map32
     k, p = 50, 20
