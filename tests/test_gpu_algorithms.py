@@ -126,6 +126,34 @@ def test_double_pass_odd_probe_counts(ctx, k, p):
     np.testing.assert_allclose(Vg.T @ RV, np.eye(k), atol=1e-8)
 
 
+def test_double_pass_zero_probe_column_breaks_down(ctx):
+    """A probe block with an exactly zero column has rank below s: after the
+    shifted first pass that column of Q is exactly zero, the next Cholesky
+    meets a zero pivot and the call reports HINV_EBREAK, for one problem and
+    for a batch whose other member is sound; the problems stay usable."""
+    prob, m, obs = instance(16, 40)
+    u = prob.forward(m)
+    adj = prob.adjoint(m, u)
+    gps = [gpu_problem(ctx, prob, obs) for _ in range(2)]
+    for gp in gps:
+        gp.linearize(dev(m), dev(u), dev(adj))
+    k, s = 8, 12
+    bad = synth.omega(prob.n, s, seed=3)
+    bad[5] = 0.0
+    good = synth.omega(prob.n, s, seed=4)
+    Vs = [dev(np.zeros((k, prob.n))) for _ in range(2)]
+    with pytest.raises(hv.HinvError) as e:
+        gps[0].lowrank_eig(dev(bad), k, Vs[0])
+    assert e.value.code == hv.HINV_EBREAK
+    b = hv.Batch(ctx, gps)
+    with pytest.raises(hv.HinvError) as e:
+        b.lowrank_eig([dev(good), dev(bad)], k, Vs)
+    assert e.value.code == hv.HINV_EBREAK
+    lam, info = b.lowrank_eig([dev(good), dev(good)], k, Vs)
+    assert info["rc"] == 0
+    np.testing.assert_allclose(lam[0], lam[1], rtol=0, atol=1e-12 * abs(lam[0][0]))
+
+
 def test_double_pass_bf16_block_product(ctx, map32):
     prob, obs, m = map32
     k, p = 50, 20
