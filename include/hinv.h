@@ -240,7 +240,11 @@ int hinv_map_newton(hinv_problem* p, const double* m0, double* m_map,
 /* Double-pass randomized eigensolver for H_misfit v = lambda R v at the current
  * linearization point.  omega: device n x s block (s = k + oversampling).
  * mode: HINV_HESS_MISFIT or HINV_HESS_GN_MISFIT.  tprod: HINV_TPROD_*.
- * lambda: HOST array [k] (descending); V: device n x k, R-orthonormal. */
+ * lambda: HOST array [k] (descending); V: device n x k, R-orthonormal.
+ * Errors: HINV_EINVAL unless 1 <= k <= s <= min(512, n); HINV_EBREAK when a
+ * Cholesky factor of PreCholQR (Alg. 4) meets a non-positive pivot (a probe
+ * block of rank below s, e.g. a zero column); lambda and V are then not
+ * written, and the problem stays usable. */
 int hinv_lowrank_eig(hinv_problem* p, int mode, int tprod, int s, const double* omega, int ldo,
                      int k, double* lambda_host, double* V, int ldv, hinv_solve_info* info);
 /* out[:,j] = m_map + (I - V S V^T R) x_j with x_j = K_A^{-1} C_M eta[:,j] and
@@ -271,7 +275,8 @@ int hinv_batch_hessian_apply(hinv_batch* b, int mode, int nrhs, const double* co
 /* Double pass (Alg. 2 with Alg. 4) for every problem with s probe vectors and
  * rank k: omega[i] (device, n_i x s, ld n_i), V[i] (device, n_i x k, ld n_i),
  * lambda_host (HOST, nprob x k, row i = problem i, descending).  Mode and
- * tprod as in hinv_lowrank_eig. */
+ * tprod as in hinv_lowrank_eig.  HINV_EBREAK if any member's PreCholQR breaks
+ * down (the call then stops before the second pass). */
 int hinv_batch_lowrank_eig(hinv_batch* b, int mode, int tprod, int s, const double* const* omega,
                            int k, double* lambda_host, double* const* V, hinv_solve_info* info);
 
