@@ -276,7 +276,8 @@ int hinv_batch_hessian_apply(hinv_batch* b, int mode, int nrhs, const double* co
  * rank k: omega[i] (device, n_i x s, ld n_i), V[i] (device, n_i x k, ld n_i),
  * lambda_host (HOST, nprob x k, row i = problem i, descending).  Mode and
  * tprod as in hinv_lowrank_eig.  HINV_EBREAK if any member's PreCholQR breaks
- * down (the call then stops before the second pass). */
+ * down; lambda_host and V are then unspecified (the mesh-size groups run one
+ * after another and the call stops at the failing one). */
 int hinv_batch_lowrank_eig(hinv_batch* b, int mode, int tprod, int s, const double* const* omega,
                            int k, double* lambda_host, double* const* V, hinv_solve_info* info);
 
