@@ -241,7 +241,7 @@ bool orthonormalize(Ctx* c, DenseWork& w, int ni, int n, int s, double* Y, doubl
             scaled_trace(c, ni, s, G, s, ss, 11.0 * ((double)n * s + (double)s * (s + 1)) * 1.1102230246251565e-16,
                          w.shift.get());
         if (!cholesky_upper(c, w, ni, s, G, s, ss, pass == 0 ? w.shift.get() : nullptr)) return false;
-        tri_inverse_upper(c, ni, s, G, s, ss, Ri, s, ss);
+        tri_inverse_upper(c, w, ni, s, G, s, ss, Ri, s, ss);
         for (int j = 0; j < ni; ++j) {
             gemm_tall(c, n, s, s, 1.0, Y + j * ts, n, Ri + j * ss, s, 0.0, tmp + j * ts, n);
             dev_copy(c, n, s, tmp + j * ts, n, Y + j * ts, n);
@@ -266,7 +266,7 @@ int precholqr(Problem* const* P, int ni, DenseWork& dw, int s, double* Y, double
         gram(c, dw, n, s, s, Y + j * ts, n, Zb + j * ts, n, G + j * ss, s);      // Z^T Zbar
     }
     if (!cholesky_upper(c, dw, ni, s, G, s, ss)) return HINV_EBREAK;            // R_Z
-    tri_inverse_upper(c, ni, s, G, s, ss, Ri, s, ss);
+    tri_inverse_upper(c, dw, ni, s, G, s, ss, Ri, s, ss);
     for (int j = 0; j < ni; ++j)
         gemm_tall(c, n, s, s, 1.0, Y + j * ts, n, Ri + j * ss, s, 0.0, Q + j * ts, n);  // Q = Z R_Z^-1
     return HINV_OK;

@@ -11,6 +11,8 @@ namespace hinv {
 struct DenseWork {
     DBuf<double> part;
     DBuf<double> shift;  // per-matrix diagonal shifts
+    DBuf<double> tmp;    // block products of the blocked triangular inverse
+    DBuf<double> rot;    // recorded Jacobi rotations (large s)
     DBuf<int> flag;
 };
 
@@ -34,9 +36,9 @@ void gemm_tall(Ctx* ctx, int n, int s, int t, double alpha, const double* X, int
 bool cholesky_upper(Ctx* ctx, DenseWork& w, int nb, int s, double* A, int lda, size_t sa,
                     const double* shift = nullptr);
 
-// Rinv_b (s x s) = R_b^-1 for upper-triangular R_b.
-void tri_inverse_upper(Ctx* ctx, int nb, int s, const double* R, int ldr, size_t sr, double* Rinv, int ldi,
-                       size_t si);
+// Rinv_b (s x s) = R_b^-1 for upper-triangular R_b (Rinv_b must not overlap R_b).
+void tri_inverse_upper(Ctx* ctx, DenseWork& w, int nb, int s, const double* R, int ldr, size_t sr, double* Rinv,
+                       int ldi, size_t si);
 
 // Symmetric eigendecompositions T_b = S_b diag(lam_b) S_b^T by parallel
 // cyclic Jacobi; T_b is symmetrized and overwritten; eigenpairs sorted by

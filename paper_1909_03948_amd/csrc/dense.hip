@@ -315,31 +315,6 @@ __device__ __forceinline__ void tri_inverse_body(int s, const double* R, int ldr
     }
 }
 
-// In global memory (large s): column by column, threads i <= j of column j
-// in parallel, each an inner product with the finished columns.
-__global__ void k_tri_inverse(int s, const double* __restrict__ R, int ldr, size_t sr, double* __restrict__ Ri,
-                              int ldi, size_t si) {
-    R += blockIdx.x * sr;
-    Ri += blockIdx.x * si;
-    for (int id = threadIdx.x; id < s * s; id += blockDim.x) Ri[id % s + (size_t)(id / s) * ldi] = 0.0;
-    __syncthreads();
-    for (int j = 0; j < s; ++j) {
-        const double rjj = R[j + (size_t)j * ldr];
-        for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-            double v;
-            if (i == j) {
-                v = 1.0 / rjj;
-            } else {
-                double acc = 0.0;
-                for (int k = i; k < j; ++k) acc += Ri[i + (size_t)k * ldi] * R[k + (size_t)j * ldr];
-                v = -acc / rjj;
-            }
-            Ri[i + (size_t)j * ldi] = v;
-        }
-        __syncthreads();
-    }
-}
-
 __global__ void k_tri_inverse_lds(int s, const double* __restrict__ R, int ldr, size_t sr,
                                   double* __restrict__ Ri, int ldi, size_t si) {
     extern __shared__ double sm[];
@@ -432,7 +407,7 @@ __device__ __forceinline__ bool jacobi_done(double offn, double totn, double pre
 // with q >= s (odd s) has the identity rotation and no row or column q.  Each
 // thread keeps U items' loads in flight before their stores, and advances
 // its item indices by the workgroup size without dividing.
-template <int U>
+template <int U, bool kS>
 __device__ __forceinline__ void jacobi_apply(int s, int np, double* T, int ldt, double* S, int lds,
                                              const int* pp, const int* qq, const double* cs, const double* sn) {
     const int bd = blockDim.x;
@@ -476,7 +451,7 @@ __device__ __forceinline__ void jacobi_apply(int s, int np, double* T, int ldt, 
             }
         }
     }
-    {
+    if (kS) {
         const int ns = np * s, dr = bd % s, dq = bd / s;
         int r = threadIdx.x % s, k = threadIdx.x / s;
         for (int id = threadIdx.x; id < ns; id += U * bd) {
@@ -512,14 +487,18 @@ __device__ __forceinline__ void jacobi_apply(int s, int np, double* T, int ldt, 
 
 // Parallel cyclic Jacobi (round-robin pairing), one workgroup, on T and S
 // (ld ldt, lds): per step, the np disjoint rotations, then jacobi_apply.
-template <int U>
-__device__ __forceinline__ void jacobi_sweeps(int s, double* T, int ldt, double* S, int lds, int max_sweeps) {
+// With rot given, S is left alone: step t of the run stores its rotations
+// (c, s) at rot[t np + k] and the number of sweeps run goes to *nsweeps.
+template <int U, bool kS>
+__device__ __forceinline__ void jacobi_sweeps(int s, double* T, int ldt, double* S, int lds, int max_sweeps,
+                                              double2* __restrict__ rot = nullptr, int* nsweeps = nullptr) {
     const int m = s + (s & 1);
     const int np = m / 2;
     __shared__ double cs[256], sn[256];
     __shared__ int pp[256], qq[256];
     double prev = -1.0;  // off-diagonal norm^2 of the previous sweep
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
         double offn, totn;
         jacobi_norms(s, T, ldt, offn, totn);
         if (jacobi_done(offn, totn, prev)) break;
@@ -535,20 +514,25 @@ __device__ __forceinline__ void jacobi_sweeps(int s, double* T, int ldt, double*
                 qq[k] = q;
                 cs[k] = c;
                 sn[k] = sv;
+                if (!kS) rot[((size_t)sweep * (m - 1) + step) * np + k] = make_double2(c, sv);
             }
             __syncthreads();
-            jacobi_apply<U>(s, np, T, ldt, S, lds, pp, qq, cs, sn);
+            jacobi_apply<U, kS>(s, np, T, ldt, S, lds, pp, qq, cs, sn);
             __syncthreads();
         }
     }
+    if (!kS && threadIdx.x == 0) *nsweeps = sweep;
 }
 
-// In place in global memory (large s); eight items per thread in flight.
+// In place in global memory (large s); six items per thread in flight.
+// The rotations are recorded (rot: max_sweeps (m - 1) np per matrix, stride
+// srot) and applied to S afterwards by k_jacobi_rows, so each step moves T
+// alone through the one CU.
 __global__ __launch_bounds__(1024) void k_jacobi(int s, double* __restrict__ T, int ldt, size_t st,
-                                                 double* __restrict__ S, int lds, size_t ss, int max_sweeps) {
+                                                 double2* __restrict__ rot, size_t srot, int* __restrict__ nsweeps,
+                                                 int max_sweeps) {
     T += blockIdx.x * st;
-    S += blockIdx.x * ss;
-    // symmetrize, S = I
+    // symmetrize
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
         const int a = id % s, c = id / s;
         if (a < c) {
@@ -556,10 +540,61 @@ __global__ __launch_bounds__(1024) void k_jacobi(int s, double* __restrict__ T, 
             T[a + (size_t)c * ldt] = v;
             T[c + (size_t)a * ldt] = v;
         }
-        S[a + (size_t)c * lds] = a == c ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi_sweeps<8>(s, T, ldt, S, lds, max_sweeps);
+    jacobi_sweeps<6, false>(s, T, ldt, nullptr, 0, max_sweeps, rot + blockIdx.x * srot, nsweeps + blockIdx.x);
+}
+
+// S = J_1 J_2 ... (the recorded rotations in order, S starting as I).  Rows of
+// S never mix, so workgroup (x, b) takes kRotRows rows of matrix b into LDS
+// and applies every recorded step to them; the rotations of kRotSteps steps
+// (with their pairs) are staged in LDS at a time.
+constexpr int kRotRows = 4, kRotSteps = 8;
+__global__ __launch_bounds__(256) void k_jacobi_rows(int s, const double2* __restrict__ rot, size_t srot,
+                                                     const int* __restrict__ nsweeps, double* __restrict__ S,
+                                                     int lds, size_t ss) {
+    __shared__ double rows[kRotRows][512];
+    __shared__ double2 rcs[kRotSteps][256];
+    __shared__ short rp[kRotSteps][256], rq[kRotSteps][256];
+    const int b = blockIdx.y, r0 = blockIdx.x * kRotRows;
+    const int m = s + (s & 1), np = m / 2;
+    rot += b * srot;
+    S += b * ss;
+    for (int t = threadIdx.x; t < kRotRows * s; t += blockDim.x) {
+        const int r = t / s, c = t - r * s;
+        rows[r][c] = r0 + r == c ? 1.0 : 0.0;
+    }
+    const int nst = nsweeps[b] * (m - 1);
+    for (int st0 = 0; st0 < nst; st0 += kRotSteps) {
+        const int nk = min(kRotSteps, nst - st0);
+        __syncthreads();  // the previous chunk is applied (and rows initialized)
+        for (int t = threadIdx.x; t < nk * np; t += blockDim.x) {
+            const int j = t / np, k = t - j * np;
+            int p, q;
+            rr_pair((st0 + j) % (m - 1), k, m, p, q);
+            rp[j][k] = (short)p;
+            rq[j][k] = (short)q;
+            rcs[j][k] = rot[(size_t)(st0 + j) * np + k];
+        }
+        __syncthreads();
+        for (int j = 0; j < nk; ++j) {
+            for (int t = threadIdx.x; t < kRotRows * np; t += blockDim.x) {
+                const int r = t / np, k = t - r * np;
+                const int p = rp[j][k], q = rq[j][k];
+                if (q >= s) continue;
+                const double2 c = rcs[j][k];
+                const double sp = rows[r][p], sq = rows[r][q];
+                rows[r][p] = c.x * sp - c.y * sq;
+                rows[r][q] = c.y * sp + c.x * sq;
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kRotRows * s; t += blockDim.x) {
+        const int r = t / s, c = t - r * s;
+        if (r0 + r < s) S[r0 + r + (size_t)c * lds] = rows[r][c];
+    }
 }
 
 // The same sweeps on copies of T and S in LDS (ld s), written back at the end;
@@ -577,7 +612,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int s, double* __restrict__
         sl[id] = a == c ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi_sweeps<1>(s, tl, s, sl, s, max_sweeps);
+    jacobi_sweeps<1, true>(s, tl, s, sl, s, max_sweeps);
     for (int id = threadIdx.x; id < s * s; id += blockDim.x) {
         const int a = id % s, c = id / s;
         T[a + (size_t)c * ldt] = tl[id];
@@ -629,6 +664,28 @@ __global__ void k_scaled_trace(int s, const double* __restrict__ A, int lda, siz
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += w[k];
         out[blockIdx.x] = factor * t;
     }
+}
+
+// C_b (m x n) = alpha A_b (m x kk) B_b (kk x n), one thread per entry of C
+// (column-major, grid.y: matrix of the batch, strides in elements).
+__global__ void k_small_gemm(int m, int n, int kk, double alpha, const double* __restrict__ A, int lda,
+                             size_t sa, const double* __restrict__ B, int ldb, size_t sb, double* __restrict__ C,
+                             int ldc, size_t sc) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= m * n) return;
+    const int i = id % m, j = id / m;
+    A += blockIdx.y * sa;
+    B += blockIdx.y * sb;
+    C += blockIdx.y * sc;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kk; ++k) acc += A[i + (size_t)k * lda] * B[k + (size_t)j * ldb];
+    C[i + (size_t)j * ldc] = alpha * acc;
+}
+
+__global__ void k_zero_matrix(int m, int n, double* __restrict__ C, int ldc, size_t sc) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < m * n) C[blockIdx.y * sc + id % m + (size_t)(id / m) * ldc] = 0.0;
 }
 
 __global__ void k_scale_rows(int s, int t, const double* __restrict__ d, double* __restrict__ B, int ldb) {
@@ -696,15 +753,43 @@ bool cholesky_upper(Ctx* ctx, DenseWork& w, int nb, int s, double* A, int lda, s
     return true;
 }
 
-void tri_inverse_upper(Ctx* ctx, int nb, int s, const double* R, int ldr, size_t sr, double* Rinv, int ldi,
-                       size_t si) {
-    if (nb <= 0) return;
-    const size_t shm = sizeof(double) * 2 * s * s;
-    if (lds_fits(ctx, shm))
-        k_tri_inverse_lds<<<nb, 1024, shm, ctx->stream>>>(s, R, ldr, sr, Rinv, ldi, si);
-    else
-        k_tri_inverse<<<nb, 1024, 0, ctx->stream>>>(s, R, ldr, sr, Rinv, ldi, si);
+void tri_inverse_upper(Ctx* ctx, DenseWork& w, int nb, int s, const double* R, int ldr, size_t sr, double* Rinv,
+                       int ldi, size_t si) {
+    if (nb <= 0 || s <= 0) return;
+    auto diag_inverse = [&](int o, int sz) {
+        k_tri_inverse_lds<<<nb, 1024, sizeof(double) * 2 * sz * sz, ctx->stream>>>(
+            sz, R + o + (size_t)o * ldr, ldr, sr, Rinv + o + (size_t)o * ldi, ldi, si);
+        HINV_LAUNCH_CHECK();
+    };
+    if (lds_fits(ctx, sizeof(double) * 2 * s * s)) {
+        diag_inverse(0, s);
+        return;
+    }
+    // Blocked for large s: the diagonal blocks (at most bs, in LDS), then block
+    // rows bottom-up, Rinv(I, J) = -Rinv(I, I) [R(I, I+1..J) Rinv(I+1..J, J)].
+    int bs = 128;
+    while (bs > 8 && !lds_fits(ctx, sizeof(double) * 2 * bs * bs)) bs -= 8;
+    const int nbk = ceil_div(s, bs);
+    const dim3 gz(ceil_div(s * s, 256), nb);
+    k_zero_matrix<<<gz, 256, 0, ctx->stream>>>(s, s, Rinv, ldi, si);
     HINV_LAUNCH_CHECK();
+    for (int I = 0; I < nbk; ++I) diag_inverse(I * bs, std::min(bs, s - I * bs));
+    const size_t ts = (size_t)bs * bs;
+    w.tmp.ensure(nb * ts);
+    double* tmp = w.tmp.get();
+    for (int I = nbk - 2; I >= 0; --I) {
+        const int oi = I * bs, mi = std::min(bs, s - oi), k0 = oi + mi;
+        for (int J = I + 1; J < nbk; ++J) {
+            const int oj = J * bs, nj = std::min(bs, s - oj), k1 = oj + nj;
+            const dim3 g(ceil_div(mi * nj, 256), nb);
+            k_small_gemm<<<g, 256, 0, ctx->stream>>>(mi, nj, k1 - k0, 1.0, R + oi + (size_t)k0 * ldr, ldr, sr,
+                                                    Rinv + k0 + (size_t)oj * ldi, ldi, si, tmp, mi, ts);
+            HINV_LAUNCH_CHECK();
+            k_small_gemm<<<g, 256, 0, ctx->stream>>>(mi, nj, mi, -1.0, Rinv + oi + (size_t)oi * ldi, ldi, si, tmp,
+                                                    mi, ts, Rinv + oi + (size_t)oj * ldi, ldi, si);
+            HINV_LAUNCH_CHECK();
+        }
+    }
 }
 
 void sym_eig(Ctx* ctx, DenseWork& w, int nb, int s, double* T, int ldt, size_t st, double* S, int lds, size_t ss,
@@ -716,11 +801,22 @@ void sym_eig(Ctx* ctx, DenseWork& w, int nb, int s, double* T, int ldt, size_t s
     double* Stmp = w.part.get();
     double* lam_u = Stmp + nb * s2;
     const size_t shm = sizeof(double) * 2 * s2;
-    if (lds_fits(ctx, shm))
-        k_jacobi_lds<<<nb, 1024, shm, ctx->stream>>>(s, T, ldt, st, Stmp, s, s2, 40);
-    else
-        k_jacobi<<<nb, 1024, 0, ctx->stream>>>(s, T, ldt, st, Stmp, s, s2, 40);
-    HINV_LAUNCH_CHECK();
+    constexpr int kMaxSweeps = 40;
+    if (lds_fits(ctx, shm)) {
+        k_jacobi_lds<<<nb, 1024, shm, ctx->stream>>>(s, T, ldt, st, Stmp, s, s2, kMaxSweeps);
+        HINV_LAUNCH_CHECK();
+    } else {
+        const int m = s + (s & 1), np = m / 2;
+        const size_t srot = (size_t)kMaxSweeps * (m - 1) * np;
+        w.rot.ensure(nb * srot * 2);
+        w.flag.ensure(nb);
+        double2* rot = reinterpret_cast<double2*>(w.rot.get());
+        k_jacobi<<<nb, 1024, 0, ctx->stream>>>(s, T, ldt, st, rot, srot, w.flag.get(), kMaxSweeps);
+        HINV_LAUNCH_CHECK();
+        k_jacobi_rows<<<dim3(ceil_div(s, kRotRows), nb), 256, 0, ctx->stream>>>(s, rot, srot, w.flag.get(), Stmp, s,
+                                                                                 s2);
+        HINV_LAUNCH_CHECK();
+    }
     k_diag_copy<<<dim3(ceil_div(s, 256), nb), 256, 0, ctx->stream>>>(s, T, ldt, st, lam_u, s);
     HINV_LAUNCH_CHECK();
     k_eig_permute<<<dim3(ceil_div(s * s, 256), nb), 256, 0, ctx->stream>>>(s, lam_u, s, Stmp, s, s2, S, lds, ss,
