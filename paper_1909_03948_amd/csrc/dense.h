@@ -1,6 +1,6 @@
 // Dense kernels of the randomized eigensolver and the posterior sampler:
 // tall-skinny block products on the matrix cores (FP64, or BF16 inputs with
-// FP32 accumulation) and small s x s factorizations in one workgroup.
+// FP32 accumulation) and small s x s factorizations, batched over matrices.
 #pragma once
 
 #include "common.h"

@@ -1,5 +1,6 @@
-// Dense kernels: matrix-core tall-skinny products and one-workgroup s x s
-// factorizations (s = k + oversampling <= 512).
+// Dense kernels: matrix-core tall-skinny products and s x s factorizations
+// (s = k + oversampling <= 512), one workgroup per matrix in LDS while it
+// fits, blocked or in global memory beyond.
 //
 // Matrix-core operand layouts (wave64), checked on the device:
 //   f64 16x16x4:   A (16 x 4): lane l holds A[l % 16][l / 16]
