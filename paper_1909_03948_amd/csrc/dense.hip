@@ -40,46 +40,74 @@ constexpr int kBlkWaves = 8, kBlkTiles = 8, kBlk = 128;
 // trips in flight instead of one.
 constexpr int kKSteps = 4;
 
-// Split-K Gram C = X^T Y: grid.x = output block, grid.y = K chunk.
+// Split-K Gram C = X^T Y: grid.x = output block, grid.y = K chunk (a multiple
+// of kGramKC rows).  The block's 128 columns of Y are staged in LDS kGramKC
+// rows at a time (double-buffered: the next stage is loaded into registers
+// while the matrix cores work on the current one), so the eight waves share
+// one read of Y; each wave loads its 16 columns of X for the stage's eight K
+// steps at once.  Products are accumulated in K order.
+constexpr int kGramKC = 32;   // K rows per LDS stage
+constexpr int kGramLd = 144;  // LDS row stride (doubles): rows k and k + 1 fall in different bank halves
 __global__ __launch_bounds__(512) void k_gram_f64(int n, int s1, int s2, int chunk,
                                                   const double* __restrict__ X, int ldx,
                                                   const double* __restrict__ Y, int ldy,
                                                   double* __restrict__ part) {
+    __shared__ double ys[2][kGramKC * kGramLd];
     const int blocks_i = (s1 + kBlk - 1) / kBlk;
     const int bi = blockIdx.x % blocks_i, bj = blockIdx.x / blocks_i;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = bi * kBlk + wave * 16 + (lane & 15);
-    if (bi * kBlk + wave * 16 >= s1) return;  // no rows for this wave (no barrier below)
+    const bool rows_on = bi * kBlk + wave * 16 < s1;  // this wave has output rows (all waves stage Y)
     const int kr = lane >> 4;
     const int k_begin = blockIdx.y * chunk;
     const int k_end = min(n, k_begin + chunk);
     const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
-    const double* yc[kBlkTiles];
-    bool jv[kBlkTiles];
+    // staging: thread t loads rows 8 (t mod 4) .. + 8 of block column t / 4
+    const int jj = threadIdx.x >> 2, r8 = (threadIdx.x & 3) * 8;
+    const bool jok = bj * kBlk + jj < s2;
+    const double* ycol = Y + (size_t)(jok ? bj * kBlk + jj : 0) * ldy;
+    double stg[8];
+    auto load_stage = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + r8 + e;
+            stg[e] = (jok && k < k_end) ? ycol[k] : 0.0;
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ys[buf][(r8 + e) * kGramLd + jj] = stg[e];
+    };
     d4_t acc[kBlkTiles];
 #pragma unroll
-    for (int t = 0; t < kBlkTiles; ++t) {
-        const int j = bj * kBlk + t * 16 + (lane & 15);
-        jv[t] = j < s2;
-        yc[t] = Y + (size_t)(jv[t] ? j : 0) * ldy;
-        acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
-    }
-    for (int k0 = k_begin; k0 < k_end; k0 += 4 * kKSteps) {
-        double a[kKSteps], b[kKSteps][kBlkTiles];
+    for (int t = 0; t < kBlkTiles; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    load_stage(k_begin);
+    store_stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = k_begin; k0 < k_end; k0 += kGramKC) {
+        const bool more = k0 + kGramKC < k_end;
+        if (more) load_stage(k0 + kGramKC);
+        if (rows_on) {
+            double a[kGramKC / 4];
 #pragma unroll
-        for (int u = 0; u < kKSteps; ++u) {
-            const int k = k0 + 4 * u + kr;
-            const bool kv = k < k_end;
-            a[u] = (i < s1 && kv) ? xc[k] : 0.0;
+            for (int u = 0; u < kGramKC / 4; ++u) {
+                const int k = k0 + 4 * u + kr;
+                a[u] = (i < s1 && k < k_end) ? xc[k] : 0.0;
+            }
+            const double* yb = ys[buf] + kr * kGramLd + (lane & 15);
 #pragma unroll
-            for (int t = 0; t < kBlkTiles; ++t) b[u][t] = (jv[t] && kv) ? yc[t][k] : 0.0;
+            for (int u = 0; u < kGramKC / 4; ++u)
+#pragma unroll
+                for (int t = 0; t < kBlkTiles; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], yb[4 * u * kGramLd + t * 16], acc[t], 0, 0, 0);
         }
-#pragma unroll
-        for (int u = 0; u < kKSteps; ++u)
-#pragma unroll
-            for (int t = 0; t < kBlkTiles; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
+        // the other buffer was last read before the previous barrier
+        if (more) store_stage(1 - buf);
+        __syncthreads();
+        buf = 1 - buf;
     }
+    if (!rows_on) return;
 #pragma unroll
     for (int t = 0; t < kBlkTiles; ++t)
         for (int v = 0; v < 4; ++v) {
@@ -704,7 +732,7 @@ void gram(Ctx* ctx, DenseWork& w, int n, int s1, int s2, const double* X, int ld
     // K split: about 2048 workgroups, chunks of at least 256 rows (a multiple
     // of the 16-row matrix-core step)
     int nsplit = std::max(1, std::min(ceil_div(2048, blocks), ceil_div(n, 256)));
-    const int chunk = ceil_div(ceil_div(n, nsplit), 16) * 16;
+    const int chunk = ceil_div(ceil_div(n, nsplit), kGramKC) * kGramKC;  // a multiple of both kernels' K steps
     nsplit = ceil_div(n, chunk);
     w.part.ensure((size_t)nsplit * s1 * s2);
     const double flops = 2.0 * n * s1 * s2;
