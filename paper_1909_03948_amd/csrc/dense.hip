@@ -35,10 +35,6 @@ __device__ inline short to_bf16(double x) {
 // (kBlkTiles matrix-core tiles sharing one operand), so each column of X and
 // Y is read by ceil(s / 128) workgroups instead of ceil(s / 16).
 constexpr int kBlkWaves = 8, kBlkTiles = 8, kBlk = 128;
-// FP64 products load the operands of kKSteps matrix-core K steps before
-// issuing their products (in K order), so each wave has that many L2 round
-// trips in flight instead of one.
-constexpr int kKSteps = 4;
 
 // Split-K Gram C = X^T Y: grid.x = output block, grid.y = K chunk (a multiple
 // of kGramKC rows).  The block's 128 columns of Y are staged in LDS kGramKC
@@ -193,37 +189,64 @@ __global__ __launch_bounds__(64 * kRedLanes) void k_gram_reduce(int s1, int s2, 
 // C = alpha X B + beta C (X: n x s, B: s x t).  grid.x: strips of 16
 // kBlkWaves rows (one 16-row strip per wave), grid.y: 128-column blocks; a
 // wave computes its 16 rows against the block's kBlkTiles column tiles, so
-// X is read once per column block.
+// X is read once per column block.  The block's columns of B are staged in
+// LDS kGramKC rows at a time and shared by the eight waves, as in the Gram.
 __global__ __launch_bounds__(512) void k_gemm_tall(int n, int s, int t, double alpha,
                                                    const double* __restrict__ X, int ldx,
                                                    const double* __restrict__ B, int ldb,
                                                    double beta, double* __restrict__ C, int ldc) {
+    __shared__ double bsh[2][kGramKC * kGramLd];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r0 = (blockIdx.x * kBlkWaves + wave) * 16;
-    if (r0 >= n) return;
+    const bool rows_on = r0 < n;  // this wave has output rows (all waves stage B)
     const int c0 = blockIdx.y * kBlk;
     const int row = r0 + (lane & 15), kr = lane >> 4;
+    const int jj = threadIdx.x >> 2, r8 = (threadIdx.x & 3) * 8;
+    const bool jok = c0 + jj < t;
+    const double* bcol = B + (size_t)(jok ? c0 + jj : 0) * ldb;
+    double stg[8];
+    auto load_stage = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + r8 + e;
+            stg[e] = (jok && k < s) ? bcol[k] : 0.0;
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsh[buf][(r8 + e) * kGramLd + jj] = stg[e];
+    };
     d4_t acc[kBlkTiles];
 #pragma unroll
     for (int tt = 0; tt < kBlkTiles; ++tt) acc[tt] = d4_t{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < s; k0 += 4 * kKSteps) {
-        double a[kKSteps], b[kKSteps][kBlkTiles];
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < s; k0 += kGramKC) {
+        const bool more = k0 + kGramKC < s;
+        if (more) load_stage(k0 + kGramKC);
+        if (rows_on) {
+            double a[kGramKC / 4];
 #pragma unroll
-        for (int u = 0; u < kKSteps; ++u) {
-            const int k = k0 + 4 * u + kr;
-            a[u] = (row < n && k < s) ? X[(size_t)k * ldx + row] : 0.0;
-#pragma unroll
-            for (int tt = 0; tt < kBlkTiles; ++tt) {
-                const int colb = c0 + tt * 16 + (lane & 15);
-                b[u][tt] = (colb < t && k < s) ? B[k + (size_t)colb * ldb] : 0.0;
+            for (int u = 0; u < kGramKC / 4; ++u) {
+                const int k = k0 + 4 * u + kr;
+                a[u] = (row < n && k < s) ? X[(size_t)k * ldx + row] : 0.0;
             }
+            const double* bb = bsh[buf] + kr * kGramLd + (lane & 15);
+#pragma unroll
+            for (int u = 0; u < kGramKC / 4; ++u)
+#pragma unroll
+                for (int tt = 0; tt < kBlkTiles; ++tt)
+                    acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[4 * u * kGramLd + tt * 16], acc[tt], 0,
+                                                                   0, 0);
         }
-#pragma unroll
-        for (int u = 0; u < kKSteps; ++u)
-#pragma unroll
-            for (int tt = 0; tt < kBlkTiles; ++tt)
-                acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][tt], acc[tt], 0, 0, 0);
+        // the other buffer was last read before the previous barrier
+        if (more) store_stage(1 - buf);
+        __syncthreads();
+        buf = 1 - buf;
     }
+    if (!rows_on) return;
 #pragma unroll
     for (int tt = 0; tt < kBlkTiles; ++tt) {
         const int cc = c0 + tt * 16 + (lane & 15);
