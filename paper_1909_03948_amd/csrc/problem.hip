@@ -161,23 +161,60 @@ __global__ void k_hess_out(int N, const double* __restrict__ cT, const double* _
     const int N1 = N + 1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N1 * N1) return;
-    const int i = k % N1, j = k / N1;
+    const int j = k / N1, i = k - j * N1;
+    // The six triangles around node C = (i, j) (cells split along the SW-NE
+    // diagonal), in the order the sum takes them:
+    //   cell (i, j):         (C, E, NE), (C, N, NE)
+    //   cell (i - 1, j):     (W, C, N)       cell (i, j - 1): (S, C, E)
+    //   cell (i - 1, j - 1): (SW, S, C), (SW, W, C)
+    // A triangle outside the mesh reads C in place of its missing nodes and
+    // has weight 0, so every load is issued before the first product.
+    const bool e = i < N, w = i > 0, nn = j < N, sd = j > 0;
+    const int kE = e ? k + 1 : k, kW = w ? k - 1 : k, kN = nn ? k + N1 : k, kS = sd ? k - N1 : k;
+    const int kNE = e && nn ? k + N1 + 1 : k, kSW = w && sd ? k - N1 - 1 : k;
+    const int c0 = j * N + i;  // cell (i, j)
+    const double w1 = e && nn ? 1.0 : 0.0, w3 = w && nn ? 1.0 : 0.0, w4 = e && sd ? 1.0 : 0.0,
+                 w5 = w && sd ? 1.0 : 0.0;
+    const double t1 = w1 * cT[e && nn ? 2 * c0 : 0], t2 = w1 * cT[e && nn ? 2 * c0 + 1 : 0];
+    const double t3 = w3 * cT[w && nn ? 2 * (c0 - 1) : 0], t4 = w4 * cT[e && sd ? 2 * (c0 - N) + 1 : 0];
+    const double t5 = w5 * cT[w && sd ? 2 * (c0 - N - 1) : 0], t6 = w5 * cT[w && sd ? 2 * (c0 - N - 1) + 1 : 0];
+    const int nd[7] = {k, kE, kN, kNE, kW, kS, kSW};  // C E N NE W S SW
+    double vu[7], vph[7], vp[7], vuh[7], vmh[7];
     const double* uhc = colp(uh, ldu);
     const double* phc = colp(ph, ldp);
     const double* mhc = colp(mh, ldm);
-    double acc = 0.0;
-    for_incident_triangles(N, i, j, [&](int ci, int cj, int s, int) {
-        int a, r, b;
-        tri_nodes(N, ci, cj, s, a, r, b);
-        const double c = cT[2 * (cj * N + ci) + s];
-        double v = tri_form(u[a], u[r], u[b], phc[a], phc[r], phc[b]);
-        if (!gn) {
-            v += tri_form(uhc[a], uhc[r], uhc[b], p[a], p[r], p[b]);
-            v += (1.0 / 3.0) * (mhc[a] + mhc[r] + mhc[b]) * tri_form(u[a], u[r], u[b], p[a], p[r], p[b]);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        vu[q] = u[nd[q]];
+        vph[q] = phc[nd[q]];
+        vp[q] = vuh[q] = vmh[q] = 0.0;
+    }
+    if (!gn) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            vp[q] = p[nd[q]];
+            vuh[q] = uhc[nd[q]];
+            vmh[q] = mhc[nd[q]];
         }
-        acc += c * (1.0 / 3.0) * v;
-    });
-    if (add) acc = colp(add, ldadd)[k] + acc;  // the prior term, as the accumulating apply adds it
+    }
+    const double addv = add ? colp(add, ldadd)[k] : 0.0;
+    auto tri = [&](int a, int r, int b) {
+        double v = tri_form(vu[a], vu[r], vu[b], vph[a], vph[r], vph[b]);
+        if (!gn) {
+            v += tri_form(vuh[a], vuh[r], vuh[b], vp[a], vp[r], vp[b]);
+            v += (1.0 / 3.0) * (vmh[a] + vmh[r] + vmh[b]) * tri_form(vu[a], vu[r], vu[b], vp[a], vp[r], vp[b]);
+        }
+        return v;
+    };
+    constexpr int C = 0, E = 1, NN = 2, NE = 3, W = 4, S = 5, SW = 6;
+    double acc = 0.0;
+    acc += t1 * (1.0 / 3.0) * tri(C, E, NE);
+    acc += t2 * (1.0 / 3.0) * tri(C, NN, NE);
+    acc += t3 * (1.0 / 3.0) * tri(W, C, NN);
+    acc += t4 * (1.0 / 3.0) * tri(S, C, E);
+    acc += t5 * (1.0 / 3.0) * tri(SW, S, C);
+    acc += t6 * (1.0 / 3.0) * tri(SW, W, C);
+    if (add) acc = addv + acc;  // the prior term, as the accumulating apply adds it
     colp(out, ldo)[k] = acc;
 }
 
