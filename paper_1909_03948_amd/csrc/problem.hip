@@ -123,29 +123,36 @@ __global__ void k_sens(int N, const double* __restrict__ cT, const double* __res
     const int N1 = N + 1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N1 * N1) return;
-    const int i = k % N1, j = k / N1;
+    const int j = k / N1, i = k - j * N1;
     double v = 0.0;
     if (j > 0 && j < N) {
+        // Straight-line form: the six triangles around C = (i, j), as in the
+        // Hessian output kernel; a triangle outside the mesh (i = 0 or N)
+        // reads C in place of its missing nodes and has weight 0, so every
+        // load is issued before the first product.  Each edge takes the mean
+        // of the coefficients of its two triangles, in the order E, W, N, S.
         const double* mh = colp(mhat, ldm);
-        const double wk = w[k];
-        if (i < N) {
-            const double e = 0.5 * (sens_coef(N, cT, mh, i, j, 0) + sens_coef(N, cT, mh, i, j - 1, 1));
-            v += e * (wk - w[k + 1]);
-        }
-        if (i > 0) {
-            const double e = 0.5 * (sens_coef(N, cT, mh, i - 1, j, 0) +
-                                    sens_coef(N, cT, mh, i - 1, j - 1, 1));
-            v += e * (wk - w[k - 1]);
-        }
-        {
-            const double e = 0.5 * (sens_coef(N, cT, mh, i, j, 1) + sens_coef(N, cT, mh, i - 1, j, 0));
-            v += e * (wk - w[k + N1]);
-        }
-        {
-            const double e = 0.5 * (sens_coef(N, cT, mh, i, j - 1, 1) +
-                                    sens_coef(N, cT, mh, i - 1, j - 1, 0));
-            v += e * (wk - w[k - N1]);
-        }
+        const bool e = i < N, wv = i > 0;
+        const int kE = e ? k + 1 : k, kW = wv ? k - 1 : k, kN = k + N1, kS = k - N1;
+        const int kNE = e ? k + N1 + 1 : k, kSW = wv ? k - N1 - 1 : k;
+        const int c0 = j * N + i;  // cell (i, j)
+        const double fe = e ? 1.0 : 0.0, fw = wv ? 1.0 : 0.0;
+        const double t1 = fe * cT[e ? 2 * c0 : 0], t2 = fe * cT[e ? 2 * c0 + 1 : 0];
+        const double t3 = fw * cT[wv ? 2 * (c0 - 1) : 0], t4 = fe * cT[e ? 2 * (c0 - N) + 1 : 0];
+        const double t5 = fw * cT[wv ? 2 * (c0 - N - 1) : 0], t6 = fw * cT[wv ? 2 * (c0 - N - 1) + 1 : 0];
+        const double mC = mh[k], mE = mh[kE], mN = mh[kN], mNE = mh[kNE], mW = mh[kW], mS = mh[kS],
+                     mSW = mh[kSW];
+        const double wk = w[k], wE = w[kE], wW = w[kW], wN = w[kN], wS = w[kS];
+        const double s1 = t1 * (1.0 / 3.0) * (mC + mE + mNE);   // (C, E, NE)
+        const double s2 = t2 * (1.0 / 3.0) * (mC + mN + mNE);   // (C, N, NE)
+        const double s3 = t3 * (1.0 / 3.0) * (mW + mC + mN);    // (W, C, N)
+        const double s4 = t4 * (1.0 / 3.0) * (mS + mC + mE);    // (S, C, E)
+        const double s5 = t5 * (1.0 / 3.0) * (mSW + mS + mC);   // (SW, S, C)
+        const double s6 = t6 * (1.0 / 3.0) * (mSW + mW + mC);   // (SW, W, C)
+        if (e) v += 0.5 * (s1 + s4) * (wk - wE);
+        if (wv) v += 0.5 * (s3 + s6) * (wk - wW);
+        v += 0.5 * (s2 + s3) * (wk - wN);
+        v += 0.5 * (s4 + s5) * (wk - wS);
         v *= scale;
     }
     colp(y, ldy)[k] = v;

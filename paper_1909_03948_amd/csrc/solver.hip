@@ -243,15 +243,36 @@ __global__ void k_ir_residual(Op op_, const double* __restrict__ b, int ldb,
     const int N1 = op.N + 1, n = N1 * N1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     double v2 = 0.0;
-    if (k < n) {
-        const int i = k % N1, j = k / N1;
-        double v = 0.0;
-        if (op.is_free(i, j)) {
-            const double* xc = col(x64, ld);
-            v = col(b, ldb)[k] - op.apply(i, j, k, [&](int, int, int kk) { return xc[kk]; });
+    if constexpr (ApplyForm<std::decay_t<decltype(op)>>::kTable) {
+        // prior operators: node by node (the LDS row table costs a barrier
+        // that one node per thread does not repay; measured)
+        if (k < n) {
+            const int i = k % N1, j = k / N1;
+            double v = 0.0;
+            if (op.is_free(i, j)) {
+                const double* xc = col(x64, ld);
+                v = col(b, ldb)[k] - op.apply(i, j, k, [&](int, int, int kk) { return xc[kk]; });
+            }
+            col(r64, ld)[k] = v;
+            v2 = v * v;
         }
-        col(r64, ld)[k] = v;
-        v2 = v * v;
+    } else {
+        // state operator: straight-line form (the PCG apply kernel's), the
+        // node's row, stencil values and b loaded before the first product
+        const bool in = k < n;
+        const int j = in ? k / N1 : 0, i = k - j * N1;
+        typename std::decay_t<decltype(op)>::Row rw{};
+        typename std::decay_t<decltype(op)>::Nb nb{};
+        double bk = 0.0;
+        if (in) {
+            rw = op.row(i, j, k);
+            nb = op.gather(i, j, k, col(x64, ld));
+            bk = col(b, ldb)[k];
+            double v = 0.0;
+            if (op.is_free(i, j)) v = bk - op.combine(i, j, rw, nb);
+            col(r64, ld)[k] = v;
+            v2 = v * v;
+        }
     }
     const double s = block_sum(v2);
     if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
