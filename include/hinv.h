@@ -213,6 +213,18 @@ int hinv_hessian_apply(hinv_problem* p, int mode, int nrhs, const double* mhat, 
 int hinv_prior_apply(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy);
 int hinv_prior_solve(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy,
                      hinv_solve_info* info);
+/* y = R x exactly as hinv_prior_apply, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the call allocates nothing.  Its intermediate vectors live in a
+ * fixed scratch array of 8 388 608 doubles (64 MiB) that the library holds on
+ * every GPU it runs on until the process ends (its address is looked up when
+ * a context is created on that GPU).  Limit: 6 n nrhs <= 8 388 608, e.g.
+ * nrhs <= 1 at N = 1024, 5 at N = 512, 21 at N = 256; larger calls return
+ * HINV_EINVAL and write nothing.  Every scratch element is written before it
+ * is read, so nothing carries over from earlier calls.  All calls on one GPU
+ * share the array: calls that overlap in time on one GPU (other streams,
+ * contexts or host threads) race and give undefined results. */
+int hinv_prior_apply_noalloc(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy);
 /* out[:,s] = m_pr + K_A^{-1} C_M eta[:,s]: a draw from N(m_pr, R^{-1}).
  * eta: device, ns columns of 6 N^2 i.i.d. N(0,1) values with leading dimension
  * ldeta; entry 3 t + e sits at the midpoint of edge e of triangle t, edges

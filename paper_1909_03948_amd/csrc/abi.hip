@@ -11,6 +11,7 @@
 #include "batch.h"
 #include "cnn.h"
 #include "fcg.h"
+#include "noalloc.h"
 #include "problem.h"
 
 struct hinv_ctx {
@@ -107,6 +108,8 @@ int hinv_ctx_create(int device, void* stream, hinv_ctx** out) {
         c->c.device = device;
         c->c.stream = (hipStream_t)stream;
         HINV_HIP(hipSetDevice(device));
+        // device address of the fixed scratch of hinv_prior_apply_noalloc
+        hinv::noalloc_init(device);
     });
     if (rc != HINV_OK) {
         delete c;
@@ -330,6 +333,23 @@ int hinv_prior_apply(hinv_problem* p, int nrhs, const double* x, int ldx, double
         REQUIRE(nrhs >= 0 && ldx >= n && ldy >= n, "bad size or leading dimension");
         REQUIRE(nrhs == 0 || (x && y), "null vector");
         if (nrhs) p->p->prior_apply(nrhs, x, ldx, y, ldy);
+    });
+}
+
+int hinv_prior_apply_noalloc(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(nrhs >= 0 && ldx >= n && ldy >= n, "bad size or leading dimension");
+        REQUIRE(nrhs == 0 || (x && y), "null vector");
+        const size_t need = (size_t)6 * n * nrhs;
+        if (need > hinv::kNoAllocScratchDoubles)
+            hinv::fail(HINV_EINVAL, "hinv_prior_apply_noalloc: 6 n nrhs = " + std::to_string(need) +
+                                        " doubles exceed the fixed scratch of " +
+                                        std::to_string(hinv::kNoAllocScratchDoubles));
+        if (nrhs)
+            p->p->prior_apply(nrhs, x, ldx, y, ldy, false, nullptr,
+                              hinv::noalloc_scratch(ctx_of(p)->device));
     });
 }
 

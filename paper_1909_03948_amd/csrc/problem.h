@@ -57,12 +57,15 @@ class Problem {
     // rm: R mhat already computed (full modes), added instead of computed here
     void hess_output(int mode, int nc, const double* mhat, int ldm, const double* uh, int ldu,
                      const double* ph, int ldp, double* out, int ldo, const double* rm = nullptr);
-    // s: the stream to run on (the context's stream when null)
+    // s: the stream to run on (the context's stream when null); ws: when not
+    // null, 6 n nc doubles of workspace used instead of the problem's scratch
     void prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate = false,
-                     hipStream_t s = nullptr);
+                     hipStream_t s = nullptr, double* ws = nullptr);
     void prior_solve(int nc, const double* x, int ldx, double* y, int ldy, SolveStats* st);
     void mass_apply(int nc, const double* x, int ldx, double* y, int ldy);
-    void mass_solve(int nc, const double* x, int ldx, double* y, int ldy, hipStream_t s = nullptr);
+    // ws: when not null, 4 n nc doubles of workspace instead of the problem's scratch
+    void mass_solve(int nc, const double* x, int ldx, double* y, int ldy, hipStream_t s = nullptr,
+                    double* ws = nullptr);
     void prior_sample(int ns, const double* eta, int ldeta, double* out, int ldo, bool add_mean,
                       SolveStats* st);
     void white_noise(uint64_t seed, uint64_t stream, long long first, int ns, double* eta, int ld);

@@ -825,15 +825,16 @@ void Problem::mass_apply(int nc, const double* x, int ldx, double* y, int ldy) {
     HINV_LAUNCH_CHECK();
 }
 
-void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx, hipStream_t s) {
+void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx, hipStream_t s, double* ws) {
     // Chebyshev iteration (no inner products) on the Jacobi-scaled consistent
     // mass matrix, whose spectrum lies in [1/2, 2] for P1 triangles.
     if (!s) s = ctx->stream;
     const OpKA<double> M = prior_op(N, 0.0, 1.0, 0.0);
     const double lo = 0.5, hi = 2.0;
     const double theta = 0.5 * (hi + lo), dl = 0.5 * (hi - lo), sigma1 = theta / dl;
-    double* r[2] = {scratch(5, nc), scratch(8, nc)};
-    double* d[2] = {scratch(6, nc), scratch(7, nc)};
+    const size_t blk = (size_t)n * nc;
+    double* r[2] = {ws ? ws : scratch(5, nc), ws ? ws + 3 * blk : scratch(8, nc)};
+    double* d[2] = {ws ? ws + blk : scratch(6, nc), ws ? ws + 2 * blk : scratch(7, nc)};
     if (ldx != n) fail(HINV_EINVAL, "mass_solve needs a packed output");
     if (nc > 65535) fail(HINV_EINVAL, "mass_solve: at most 65535 columns per call");
     const bool small = (long long)ceil_div(N + 1, 32) * ceil_div(N + 1, 32) * nc < 512;
@@ -859,14 +860,15 @@ void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx, h
 }
 
 void Problem::prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate,
-                          hipStream_t s) {
+                          hipStream_t s, double* ws) {
     if (!s) s = ctx->stream;
     const OpKA<double> K = prior_op(N, gamma, delta, beta);
-    double* t1 = scratch(3, nc);
-    double* t2 = scratch(4, nc);
+    const size_t blk = (size_t)n * nc;
+    double* t1 = ws ? ws : scratch(3, nc);
+    double* t2 = ws ? ws + blk : scratch(4, nc);
     k_prior_apply<<<grid2(n, nc), kBlock, 0, s>>>(K, x, ldx, t1, n, 0.0);
     HINV_LAUNCH_CHECK();
-    mass_solve(nc, t1, n, t2, n, s);
+    mass_solve(nc, t1, n, t2, n, s, ws ? ws + 2 * blk : nullptr);
     k_prior_apply<<<grid2(n, nc), kBlock, 0, s>>>(K, t2, n, y, ldy, accumulate ? 1.0 : 0.0);
     HINV_LAUNCH_CHECK();
 }

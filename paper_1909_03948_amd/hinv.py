@@ -77,7 +77,7 @@ EXPORTS = [
     "hinv_status_string", "hinv_problem_create", "hinv_problem_destroy", "hinv_problem_size",
     "hinv_set_data", "hinv_set_solver", "hinv_forward", "hinv_cost", "hinv_observe",
     "hinv_gradient", "hinv_linearize", "hinv_inc_forward", "hinv_inc_adjoint",
-    "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_solve", "hinv_prior_sample",
+    "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_apply_noalloc", "hinv_prior_solve", "hinv_prior_sample",
     "hinv_map_newton", "hinv_lowrank_eig", "hinv_posterior_sample", "hinv_ctx_kernel_timer",
     "hinv_ctx_kernel_timer_read", "hinv_white_noise", "hinv_batch_create", "hinv_batch_destroy",
     "hinv_batch_hessian_apply", "hinv_batch_lowrank_eig", "hinv_state_apply", "hinv_state_solve",
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_inc_adjoint": [P, I, I, V, I, V, I, V, I, C.POINTER(SolveInfo)],
         "hinv_hessian_apply": [P, I, I, V, I, V, I, C.POINTER(SolveInfo)],
         "hinv_prior_apply": [P, I, V, I, V, I],
+        "hinv_prior_apply_noalloc": [P, I, V, I, V, I],
         "hinv_prior_solve": [P, I, V, I, V, I, C.POINTER(SolveInfo)],
         "hinv_prior_sample": [P, I, V, I, V, I, C.POINTER(SolveInfo)],
         "hinv_map_newton": [P, V, V, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)],
@@ -322,6 +323,12 @@ class Problem:
         px, nc, ldx = _cols(x, self.n)
         py, _, ldy = _cols(y, self.n)
         self._check(self.lib.hinv_prior_apply(self.h, nc, px, ldx, py, ldy), allow=())
+
+    def prior_apply_noalloc(self, x, y):
+        """y = R x through the entry point that allocates nothing."""
+        px, nc, ldx = _cols(x, self.n)
+        py, _, ldy = _cols(y, self.n)
+        self._check(self.lib.hinv_prior_apply_noalloc(self.h, nc, px, ldx, py, ldy), allow=())
 
     def prior_solve(self, x, y):
         px, nc, ldx = _cols(x, self.n)
