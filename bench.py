@@ -1,25 +1,31 @@
 """Benchmark: Hessian-vector products/s at a 1e-10 residual and time to MAP +
 rank-k posterior, on one MI355X.
 
-One step = the whole hot path on the 256 x 256 Poisson coefficient-inversion
-workload (66 049 parameters, 400 observations, bilaplacian prior gamma = 0.1,
-delta = 0.5): inexact Newton-CG from the prior mean to |g| <= 1e-6 |g_0|, then
-the double-pass randomized eigensolver with k = 50, p = 20 (all 70 probe
-vectors in one batched multi-right-hand-side solve per pass).  Every PDE
-solve reaches a relative residual of 1e-10 (single right-hand sides: FP64 CG
-preconditioned by an FP32 multigrid V-cycle; batches: FP32 multigrid-PCG
-inside FP64 refinement); the eigensolver's block product Q^T (A Q) runs on
-BF16 matrix cores with FP32 accumulation.
+One step = the whole hot path on the 1024 x 1024 Poisson coefficient-inversion
+workload (1 050 625 parameters, 2 000 observations, bilaplacian prior
+gamma = 0.05, delta = 1): inexact Newton-CG from the prior mean to
+|g| <= 1e-6 |g_0| (Alg. 1), the double-pass randomized eigensolver (Alg. 2
+with PreCholQR, Alg. 4) of the Gauss-Newton data-misfit Hessian with k = 200,
+p = 20 (all 220 probe vectors in one batched multi-right-hand-side solve per
+pass), then 1 000 posterior samples through the low-rank update (Sec. 4.3.2),
+their white noise drawn on the device by the counter-based generator.  Every
+PDE solve reaches a relative residual of 1e-10 (single right-hand sides: FP64
+CG preconditioned by an FP32 multigrid V-cycle; batches: FP32 multigrid-PCG
+inside FP64 refinement); the eigensolver's block products run on FP64 matrix
+cores.
 
-value = Hessian-vector products completed in the timed steps / wall time
-(each Newton-CG Hessian action and each eigensolver column counts one).
-ms_per_step = time to MAP + rank-k posterior.  Inputs (probe matrix, data) are
-resident on the device before timing starts.
+value = Hessian-vector products completed in the MAP + eigensolver part of
+the timed steps / its wall time (each Newton-CG Hessian action and each
+eigensolver column counts one); ms_per_step = the whole step, samples
+included; time_to_map_plus_posterior_s excludes the samples, which are timed
+separately.  Inputs (probe matrix, data) are resident on the device before
+timing starts.  After the timed steps the same step runs once in the plain
+FP64 form (FP64 PCG for every solve, FP64 block products) for the speedup,
+the block product once in BF16 for its eigenvalue error, and the oracle is
+timed on the host (cpu_baseline).
 
-``--workload poisson1024`` runs the 1024 x 1024 workload instead (1 050 625
-parameters, 2 000 observations, gamma = 0.05, delta = 1, k = 200, p = 20): the
-same step followed by 1 000 posterior samples through the low-rank update,
-their white noise drawn on the device by the counter-based generator.
+``--workload poisson256`` runs the 256 x 256 workload (66 049 parameters,
+400 observations, gamma = 0.1, delta = 0.5, k = 50, p = 20, no samples).
 
 ``--workload learned1024`` runs the learned correction on the 1024 x 1024
 problem: 20 000 training pairs harvested from the incremental solves of 50
@@ -48,11 +54,14 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 
-WORKLOAD = "poisson256"
+WORKLOAD = "poisson1024"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFLOPS = 78.6   # dense FP64 matrix cores
 BF16_MFMA_PEAK_TFLOPS = 2500.0
-TIMED_CLASSES = ["mg_down", "mg_up", "mg_bottom", "pcg_apply", "pcg_update", "gram"]
+# timer classes: single-column launches, the same kernels batched (_b), the
+# one-workgroup bottom levels (latency-bound) and the block product (MFMA)
+HBM_CLASSES = ["mg_down", "mg_up", "pcg_apply", "pcg_update", "mg_down_b", "mg_up_b", "pcg_apply_b", "pcg_update_b"]
+TIMED_CLASSES = HBM_CLASSES + ["mg_bottom", "gram"]
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
@@ -84,18 +93,19 @@ def setup_gpu(cfg, precision, seed=synth.MASTER_SEED):
     s = cfg["k"] + cfg["p"]
     omega = dev(synth.omega(n, s, seed=seed))
     torch.cuda.synchronize()
-    return ctx, prob, omega, dict(n=n, sigma=sigma)
+    return ctx, prob, omega, dict(n=n, sigma=sigma, d=d)
 
 
-def run_step(prob, omega, cfg, tprod, m_map, V, samples=None):
+def run_step(prob, omega, cfg, tprod, m_map, V, samples=None, mode=None):
     """MAP point, rank-k eigenpairs and (if ``samples`` = (count, chunk, eta, out))
     posterior samples drawn with device white noise."""
     import torch
     from paper_1909_03948_amd import hinv as hv
+    mode = hv.HESS_GN_MISFIT if mode is None else mode
     t0 = time.perf_counter()
     ninfo = prob.map_newton(m_map, rel_tol=1e-6)
     t1 = time.perf_counter()
-    lam, einfo = prob.lowrank_eig(omega, cfg["k"], V, mode=hv.HESS_MISFIT, tprod=tprod)
+    lam, einfo = prob.lowrank_eig(omega, cfg["k"], V, mode=mode, tprod=tprod)
     t2 = time.perf_counter()
     if samples is not None:
         count, chunk, eta, out = samples
@@ -114,8 +124,24 @@ def run_step(prob, omega, cfg, tprod, m_map, V, samples=None):
                 eig=einfo, lam=lam)
 
 
-def roofline(ctx, steps, tprod, workload):
-    """Per-class sampled event timings -> roofline of the dominant class."""
+def _traffic(workload, cls):
+    """HBM bytes per launch of a class from the committed counter summary of this
+    workload, while the kernel sources are those the counters were taken on."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    from paper_1909_03948_amd.profile_summary import kernel_source_hash
+    wl = json.load(open(PMC_FILE)).get("workloads", {}).get(workload, {})
+    ent = wl.get("kernels", {}).get(cls)
+    if ent and wl.get("source_hash") == kernel_source_hash(os.path.join(ROOT, "paper_1909_03948_amd")):
+        return ent["hbm_bytes_per_launch"]
+    return None
+
+
+def roofline(ctx, tprod, workload):
+    """Per-class sampled event timings -> roofline of the dominant bandwidth-bound
+    class (by estimated total time); the bottom levels are reported as time
+    (one workgroup per column: latency-bound), the block product against the
+    matrix-core peak of its precision."""
     kern = {}
     for name in TIMED_CLASSES:
         r = ctx.kernel_timer_read(name)
@@ -126,53 +152,65 @@ def roofline(ctx, steps, tprod, workload):
                           est_total_ms=avg_ms * r["launches"],
                           work_per_launch=r["work"] / r["timed"],
                           rate=r["work"] / (r["ms"] * 1e-3) / 1e9)  # GB/s or GFLOP/s
-    if not kern:
+    for name, k in kern.items():
+        if name in HBM_CLASSES:
+            k["bound"] = "hbm"
+            k["frac"] = k["rate"] / HBM_PEAK_GBS
+            k["traffic"] = _traffic(workload, name)
+        elif name == "gram":
+            k["bound"] = "mfma"
+            peak = BF16_MFMA_PEAK_TFLOPS if tprod == "bf16" else FP64_MFMA_PEAK_TFLOPS
+            k["frac"] = k["rate"] / 1e3 / peak
+        else:
+            k["bound"] = "latency"
+    hbm = [c for c in kern if c in HBM_CLASSES]
+    if not hbm:
         return None, kern
-    dom = max(kern, key=lambda k: kern[k]["est_total_ms"])
+    dom = max(hbm, key=lambda c: kern[c]["est_total_ms"])
     k = kern[dom]
-    if dom == "gram":
-        peak = BF16_MFMA_PEAK_TFLOPS if tprod == "bf16" else FP64_MFMA_PEAK_TFLOPS
-        roof = dict(bound="mfma", achieved=k["rate"] / 1e3, peak=peak, unit="TFLOP/s",
-                    frac=k["rate"] / 1e3 / peak, traffic=None)
-    else:
-        roof = dict(bound="hbm", achieved=k["rate"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=k["rate"] / HBM_PEAK_GBS, traffic=None)
-    roof["kernel"] = dom
-    roof["avg_us"] = k["avg_us"]
-    roof["algorithmic_bytes_per_launch" if dom != "gram" else "flops_per_launch"] = k["work_per_launch"]
-    # HBM bytes per launch from the committed counter summary of this workload,
-    # valid while the kernel sources are those the counters were taken on
-    if os.path.exists(PMC_FILE) and dom != "gram":
-        from paper_1909_03948_amd.profile_summary import kernel_source_hash
-        wl = json.load(open(PMC_FILE)).get("workloads", {}).get(workload, {})
-        ent = wl.get("kernels", {}).get(dom)
-        src = os.path.join(ROOT, "paper_1909_03948_amd")
-        if ent and wl.get("source_hash") == kernel_source_hash(src):
-            roof["traffic"] = ent["hbm_bytes_per_launch"]
+    roof = dict(bound="hbm", achieved=k["rate"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=k["rate"] / HBM_PEAK_GBS, traffic=k["traffic"], kernel=dom, avg_us=k["avg_us"],
+                algorithmic_bytes_per_launch=k["work_per_launch"],
+                population="batched (>= 8 columns)" if dom.endswith("_b") else "single right-hand side")
     return roof, kern
 
 
-def cpu_baseline(cfg, workload, budget_s=20.0):
-    """Oracle HVPs (misfit part) at the true parameter of the same workload,
-    factorization reused, until the time budget is spent."""
+def cpu_baseline(cfg, workload, budget_s=15.0):
+    """The oracle's misfit Hessian actions on this workload's mesh, prior and
+    observation points at m = m_pr + 0.6 x a smooth field (the cost of an action
+    does not depend on the point or the data): sparse LU of A(m) timed apart,
+    then actions with that factorization reused until the budget is spent (at
+    least 3); value = 1 / median time per action."""
     from oracle import model
     N, q = cfg["N"], cfg["q"]
-    prob, m_true, _ = model.make_instance(dict(N=N, q=q, gamma=cfg["gamma"], delta=cfg["delta"],
-                                               m_prior=cfg["m_prior"]), synth.MASTER_SEED,
-                                          synth.white_noise(N)[0], synth.obs_points(q),
-                                          synth.obs_noise(q))
-    u = prob.forward(m_true)
-    p = prob.adjoint(m_true, u)
-    dirs = synth.test_vectors(prob.n, 160, stream=synth.STREAM_OMEGA)
-    prob.hessian_apply(m_true, u, p, dirs[0], model.HESS_MISFIT)  # factorization outside timing
-    count, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and count < len(dirs):
-        prob.hessian_apply(m_true, u, p, dirs[count], model.HESS_MISFIT)
-        count += 1
-    dt = time.perf_counter() - t0
-    return dict(value=count / dt, unit="HVP/s", cores=1, kind="oracle",
-                sample=f"{count} misfit Hessian actions of the {workload} workload at the true "
-                       f"parameter, sparse LU of A(m) reused, {dt:.1f} s single-threaded SuperLU")
+    t0 = time.perf_counter()
+    prob = model.Problem(N, cfg["gamma"], cfg["delta"], cfg["m_prior"], obs_xy=synth.obs_points(q),
+                         d_obs=np.zeros(q))
+    m = prob.m_pr + 0.6 * synth.smooth_field(N, seed=4)
+    t1 = time.perf_counter()
+    prob.stiffness(m)  # assembly and sparse LU of A(m)
+    t2 = time.perf_counter()
+    u = prob.forward(m)
+    p = prob.adjoint(m, u)
+    dirs = synth.test_vectors(prob.n, 16, stream=synth.STREAM_OMEGA)
+    times = []
+    ts = time.perf_counter()
+    while len(times) < 3 or (time.perf_counter() - ts < budget_s and len(times) < len(dirs)):
+        t = time.perf_counter()
+        prob.hessian_apply(m, u, p, dirs[len(times)], model.HESS_GN_MISFIT)
+        times.append(time.perf_counter() - t)
+    med = float(np.median(times))
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return dict(value=1.0 / med, unit="HVP/s", cores=1, kind="oracle",
+                sample=f"{len(times)} Gauss-Newton misfit Hessian actions of the {workload} workload "
+                       f"(N = {N}, {q} observations) at m_pr + 0.6 smooth field, sparse LU of A(m) reused; "
+                       f"median {med:.3f} s per action, single-threaded SuperLU and NumPy",
+                median_s_per_hvp=med, hvps_timed=len(times), factorization_s=t2 - t1,
+                setup_s=t1 - t0, host_cores_available=cores)
+
 
 
 def run_uneven(a):
@@ -239,7 +277,7 @@ def run_uneven(a):
         log(f"step {st}: batched done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    roof, kern = roofline(ctx, a.steps, a.tprod, "uneven64")
+    roof, kern = roofline(ctx, a.tprod, "uneven64")
     for name in TIMED_CLASSES:
         ctx.kernel_timer(name, False, 16)
     t2 = time.perf_counter()
@@ -280,7 +318,6 @@ def run_uneven(a):
 def run_learned(a):
     """Learned correction on the 1024 x 1024 problem (harvest, train, compare)."""
     import torch
-    from oracle import cnn as ocnn  # parameter initialisation only (He normal)
     from paper_1909_03948_amd import hinv as hv
     cfg = synth.WORKLOADS["poisson1024"]
     N, q = cfg["N"], cfg["q"]
@@ -317,7 +354,7 @@ def run_learned(a):
     torch.cuda.synchronize()
     harvest_s = time.perf_counter() - t0
     net = hv.Cnn(ctx)
-    net.set_params(ocnn.init_params(np.random.default_rng(0)))
+    net.he_init(seed=0)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
     t0 = time.perf_counter()
@@ -390,9 +427,13 @@ def main():
     ap.add_argument("--samples", type=int, default=1000,
                     help="posterior samples per step (poisson1024 only)")
     ap.add_argument("--precision", choices=["auto", "fp32ir", "fp64"], default="auto")
-    ap.add_argument("--tprod", choices=["bf16", "fp64"], default="bf16")
+    ap.add_argument("--tprod", choices=["bf16", "fp64"], default="fp64")
+    ap.add_argument("--hess", choices=["gn", "full"], default="gn",
+                    help="data-misfit Hessian of the low-rank posterior: Gauss-Newton or full")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the plain FP64 form, the BF16 block product and the single-column timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a 256 MiB device copy (reference for HBM counters)")
     a = ap.parse_args()
@@ -414,20 +455,23 @@ def main():
     cfg = synth.WORKLOADS[workload]
     prec = {"auto": hv.PREC_AUTO, "fp32ir": hv.PREC_FP32_IR, "fp64": hv.PREC_FP64}[a.precision]
     tprod = hv.TPROD_BF16 if a.tprod == "bf16" else hv.TPROD_FP64
-    log("setup", workload, a.precision, a.tprod)
+    log("setup", workload, a.precision, a.tprod, a.hess)
     ctx, prob, omega, meta = setup_gpu(cfg, prec)
     n = meta["n"]
+    hmode = hv.HESS_GN_MISFIT if a.hess == "gn" else hv.HESS_MISFIT
+    s = cfg["k"] + cfg["p"]
     m_map = torch.zeros(n, dtype=torch.float64, device="cuda")
     V = torch.zeros((cfg["k"], n), dtype=torch.float64, device="cuda")
     samples = None
     if workload != "poisson256" and a.samples > 0:
-        chunk = min(a.samples, cfg["k"] + cfg["p"])
+        chunk = min(a.samples, s)
         N = cfg["N"]
         samples = (a.samples, chunk,
                    torch.zeros((chunk, 6 * N * N), dtype=torch.float64, device="cuda"),
                    torch.zeros((chunk, n), dtype=torch.float64, device="cuda"))
+    step = lambda p, tp: run_step(p, omega, cfg, tp, m_map, V, samples, hmode)
     for w in range(a.warmup):
-        r = run_step(prob, omega, cfg, tprod, m_map, V, samples)
+        r = step(prob, tprod)
         log(f"warmup {w}: newton {r['newton_s']:.3f}s ({r['newton']['iterations']} it, "
             f"{r['newton']['hessian_applies']} HVP) eig {r['eig_s']:.3f}s "
             f"samples {r['sample_s']:.3f}s")
@@ -437,19 +481,23 @@ def main():
     t0 = time.perf_counter()
     res = []
     for k in range(a.steps):
-        res.append(run_step(prob, omega, cfg, tprod, m_map, V, samples))
+        res.append(step(prob, tprod))
         log(f"step {k}: newton {res[-1]['newton_s']:.3f}s eig {res[-1]['eig_s']:.3f}s "
             f"samples {res[-1]['sample_s']:.3f}s")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    roof, kern = roofline(ctx, a.tprod, workload)
+    for name in TIMED_CLASSES:
+        ctx.kernel_timer(name, False, 16)
     hvps = sum(r["hvps"] for r in res)
-    s = cfg["k"] + cfg["p"]
     eig_s = sum(r["eig_s"] for r in res)
     newton_s = sum(r["newton_s"] for r in res)
     sample_s = sum(r["sample_s"] for r in res)
+    post_s = (dt - sample_s) / a.steps
+    lam = res[-1]["lam"]
     line = {
         "metric": "Hessian-vector products/sec at 1e-10 residual; time to MAP + rank-k posterior",
-        "value": hvps / dt,
+        "value": hvps / (dt - sample_s),
         "unit": "HVP/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -462,32 +510,33 @@ def main():
         "dtype": ({"auto": "f64 PCG (single rhs) / f32 PCG in f64 refinement (batched), f32 V-cycle",
                    "fp32ir": "f32 PCG in f64 refinement, f32 V-cycle",
                    "fp64": "f64 PCG, f32 V-cycle"}[a.precision]
-                  + (", bf16 block product" if a.tprod == "bf16" else "")),
+                  + (", bf16 block product" if a.tprod == "bf16" else ", f64 block products")),
         "data": "synthetic",
         "config": {"workload": workload, "N": cfg["N"], "n_params": n, "q": cfg["q"],
                    "gamma": cfg["gamma"], "delta": cfg["delta"], "k": cfg["k"], "p": cfg["p"],
                    "rtol": 1e-10, "newton_rel_tol": 1e-6, "precision": a.precision,
-                   "tprod": a.tprod},
-        "time_to_map_plus_posterior_s": (dt - sample_s) / a.steps,
+                   "tprod": a.tprod, "posterior_hessian": a.hess,
+                   "posterior_samples": a.samples if samples is not None else 0},
+        "value_covers": "Newton-CG and eigensolver Hessian actions over the MAP + eigensolver wall time "
+                        "(posterior samples timed separately)",
+        "time_to_map_plus_posterior_s": post_s,
         "newton_s_per_step": newton_s / a.steps,
         "eigensolver_s_per_step": eig_s / a.steps,
         "batched_hvp_per_s": 2 * s * a.steps / eig_s,
         "newton_iterations": res[-1]["newton"]["iterations"],
         "newton_converged": all(r["newton"]["converged"] for r in res),
         "newton_hvps": res[-1]["newton"]["hessian_applies"],
-        "lambda_1": float(res[-1]["lam"][0]),
-        "lambda_k": float(res[-1]["lam"][-1]),
+        "lambda_1": float(lam[0]),
+        "lambda_k": float(lam[-1]),
     }
     if samples is not None:
-        line["config"]["posterior_samples"] = a.samples
+        line["posterior_samples_s_per_step"] = sample_s / a.steps
         line["posterior_samples_per_s"] = a.samples * a.steps / sample_s
-        line["value"] = hvps / (dt - sample_s)
-        line["metric"] += " (HVP/s over the MAP + eigensolver part; samples timed separately)"
-    roof, kern = roofline(ctx, a.steps, a.tprod, workload)
-    for name in TIMED_CLASSES:
-        ctx.kernel_timer(name, False, 16)
+        line["time_to_map_plus_posterior_plus_samples_s"] = dt / a.steps
     line["roofline"] = roof
     line["kernels"] = kern
+    if not a.no_extras:
+        line.update(extras(a, cfg, ctx, prob, omega, meta, hmode, lam, post_s, res[-1], samples))
     if a.calibration_copy:
         # plain device copy of known size for scaling the HBM counters
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -496,13 +545,79 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         log("calibration copy: 256 MiB read + 256 MiB written")
-    if not a.no_cpu_baseline and workload != "poisson256":
-        # the oracle's sparse factorisations alone take minutes at this size
-        log("cpu baseline skipped for", workload)
-    elif not a.no_cpu_baseline:
-        log("cpu baseline")
-        line["cpu_baseline"] = cpu_baseline(cfg, workload, a.cpu_budget)
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            line["cpu_baseline"] = cpu_baseline(cfg, workload, a.cpu_budget)
     print(json.dumps(line), flush=True)
+
+
+def extras(a, cfg, ctx, prob, omega, meta, hmode, lam, post_s, last, samples):
+    """After the timed steps: the plain FP64 form of the same step, the BF16
+    block product's eigenvalue error, and batched against single-column
+    Hessian actions."""
+    import torch
+    from paper_1909_03948_amd import hinv as hv
+    n, s, k = meta["n"], cfg["k"] + cfg["p"], cfg["k"]
+    out = {}
+    # BF16 block product at the same linearization point and probe matrix
+    V16 = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lam16, _ = prob.lowrank_eig(omega, k, V16, mode=hmode, tprod=hv.TPROD_BF16)
+    t16 = time.perf_counter() - t
+    e16 = np.abs(lam16 - lam) / abs(lam[0])
+    out["bf16_block_product"] = dict(eigensolver_s=t16, max_abs_lambda_err_over_lambda_1=float(e16.max()),
+                                     lambda_1_rel_err=float(e16[0]),
+                                     note="same point and probe matrix as the FP64 block products")
+    del V16
+    # batched against one column at a time (the eigensolver's probe columns)
+    X = omega[:s].contiguous()
+    Y = torch.zeros_like(X)
+    prob.hessian_apply(hmode, X[:1], Y[:1])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for c in range(4):
+        prob.hessian_apply(hmode, X[c:c + 1], Y[c:c + 1])
+    torch.cuda.synchronize()
+    t1 = (time.perf_counter() - t) / 4
+    prob.hessian_apply(hmode, X, Y)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    prob.hessian_apply(hmode, X, Y)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    out["hvp_single_column_ms"] = 1e3 * t1
+    out["hvp_batched_ms_per_column"] = 1e3 * tb / s
+    out["speedup_batched_vs_single_column"] = t1 * s / tb
+    # the plain FP64 form: FP64 PCG for every solve (batched too), FP64 block products
+    log("plain FP64 form")
+    p64 = hv.Problem(ctx, cfg["N"], cfg["gamma"], cfg["delta"], obs_xy=synth.obs_points(cfg["q"]),
+                     d_obs=meta["d"], sigma=meta["sigma"], m_prior=cfg["m_prior"],
+                     precision=hv.PREC_FP64, rtol=1e-10)
+    r64 = None
+    for rep in range(2):  # the first builds its graphs and launch shapes
+        r64 = run_step(p64, omega, cfg, hv.TPROD_FP64, torch.zeros(n, dtype=torch.float64, device="cuda"),
+                       torch.zeros((k, n), dtype=torch.float64, device="cuda"), samples, hmode)
+        log(f"fp64 form {rep}: newton {r64['newton_s']:.3f}s eig {r64['eig_s']:.3f}s "
+            f"samples {r64['sample_s']:.3f}s")
+    t64 = r64["newton_s"] + r64["eig_s"]
+    mixed = last["newton_s"] + last["eig_s"]
+    out["fp64_form"] = dict(
+        time_to_map_plus_posterior_s=t64, newton_s=r64["newton_s"], eigensolver_s=r64["eig_s"],
+        posterior_samples_s=r64["sample_s"],
+        max_abs_lambda_diff_over_lambda_1=float(np.max(np.abs(r64["lam"] - lam)) / abs(lam[0])),
+        note="FP64 PCG for every solve, FP64 block products, same inputs; both forms solve to 1e-10")
+    out["speedup_vs_fp64"] = dict(
+        time_to_map_plus_posterior=t64 / post_s,
+        eigensolver=r64["eig_s"] / last["eig_s"],
+        posterior_samples=(r64["sample_s"] / last["sample_s"]) if samples is not None else None,
+        note="mixed precision and batching against the plain FP64 form; the Newton-CG phase is "
+             "FP64 single-column in both (same work), last timed step against the FP64 form's second run "
+             f"(mixed {mixed:.3f} s)")
+    p64.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -154,6 +154,13 @@ const char* hinv_status_string(int status);
 #define HINV_KCLASS_PCG_APPLY   3  /* p = z + beta p, q = A p */
 #define HINV_KCLASS_PCG_UPDATE  4  /* x += alpha p, r -= alpha q */
 #define HINV_KCLASS_GRAM        5  /* tall-skinny block product X^T Y on the matrix cores */
+/* Classes 0, 1, 3 and 4 count launches of one to seven columns (single
+ * right-hand sides); the same kernels launched for eight or more columns
+ * (batched solves) are timed apart in these classes: */
+#define HINV_KCLASS_MG_DOWN_BATCHED     6
+#define HINV_KCLASS_MG_UP_BATCHED       7
+#define HINV_KCLASS_PCG_APPLY_BATCHED   8
+#define HINV_KCLASS_PCG_UPDATE_BATCHED  9
 /* Enables (enable = 1) or disables sampled timing of one kernel class: every
  * `period`-th launch (period >= 1) is bracketed by HIP events on the context's
  * stream, at most 2048 launches per class.  Enabling clears the record. */

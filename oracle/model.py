@@ -64,9 +64,8 @@ class Problem:
         self.M = msh.mass(self.mesh, self.geo).tocsc()
         self.Mb = msh.boundary_mass(self.mesh)
         self.KA = (self.gamma * K + self.delta * self.M + self.beta * self.Mb).tocsc()
-        self._KA_lu = spla.splu(self.KA)
-        self._M_lu = spla.splu(self.M)
-        self.CM = msh.mass_factor(self.mesh, self.geo)
+        # factorizations of K_A and M and the mass factor C_M are built at first use
+        self._KA_lu_, self._M_lu_, self._CM = None, None, None
         # state boundary data
         self.free = self.mesh.free
         self.uD = np.zeros(self.n)
@@ -85,6 +84,25 @@ class Problem:
         self.d = np.zeros(self.B.shape[0]) if d_obs is None else np.asarray(d_obs, dtype=float)
 
     # -- prior (Sec. 5.1, Sec. 2.3) -------------------------------------------
+    @property
+    def _KA_lu(self):
+        if self._KA_lu_ is None:
+            self._KA_lu_ = spla.splu(self.KA)
+        return self._KA_lu_
+
+    @property
+    def _M_lu(self):
+        if self._M_lu_ is None:
+            self._M_lu_ = spla.splu(self.M)
+        return self._M_lu_
+
+    @property
+    def CM(self):
+        """Rectangular mass factor C_M (n x 6 N^2), C_M C_M^T = M (Appendix C)."""
+        if self._CM is None:
+            self._CM = msh.mass_factor(self.mesh, self.geo)
+        return self._CM
+
     def M_solve(self, x):
         return self._M_lu.solve(np.asarray(x, dtype=float))
 

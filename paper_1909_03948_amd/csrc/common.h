@@ -72,7 +72,7 @@ struct DBuf {
 // execution alone, and the algorithmic bytes (or flops) of that launch are
 // recorded with it.
 struct KernelTimer {
-    static constexpr int kClasses = 8;
+    static constexpr int kClasses = 12;
     static constexpr int kPool = 2048;  // event pairs per class
     struct Class {
         bool on = false;
@@ -127,7 +127,13 @@ struct Ctx {
 };
 
 // Kernel classes of the timer (values of HINV_KCLASS_* in the public header).
-enum KClass { kKDown = 0, kKUp = 1, kKBottom = 2, kKPcgApply = 3, kKPcgUpdate = 4, kKGram = 5 };
+// The bandwidth-bound classes are timed apart for launches of one to seven
+// columns (single right-hand sides: latency-bound at every mesh size here)
+// and of eight or more (batched: bandwidth-bound).
+enum KClass {
+    kKDown = 0, kKUp = 1, kKBottom = 2, kKPcgApply = 3, kKPcgUpdate = 4, kKGram = 5,
+    kKDownB = 6, kKUpB = 7, kKPcgApplyB = 8, kKPcgUpdateB = 9
+};
 
 // Launch of a timed class (-1: untimed): a sampled launch carries the class's
 // next event pair in its dispatch.
@@ -148,6 +154,18 @@ constexpr int kBlock = 256;   // threads per workgroup for grid kernels
 constexpr int kCoarseMaxN = 8;  // coarsest multigrid level has N_c <= 8
 constexpr int kMaxVecPartials = 520;  // partial sums per column of the PCG vector kernels
 constexpr int kAutoBatch = 8;   // HINV_PREC_AUTO switches to FP32 refinement from this many columns
+
+// Timer class of a launch of `nc` columns (the batched class from kAutoBatch up).
+inline int kclass_for(int base, int nc) {
+    if (nc < kAutoBatch) return base;
+    switch (base) {
+        case kKDown: return kKDownB;
+        case kKUp: return kKUpB;
+        case kKPcgApply: return kKPcgApplyB;
+        case kKPcgUpdate: return kKPcgUpdateB;
+        default: return base;
+    }
+}
 
 // Chebyshev smoother: degree 2, targets the interval [0.5, 2] of the
 // Jacobi-scaled operator (2 bounds the spectrum by Gershgorin for both the

@@ -819,7 +819,7 @@ void Hierarchy::vcycle_impl(int nc, int check) {
         // algorithmic bytes: read b, write x2 and b_coarse per column; the state
         // operator's three coefficient arrays once per launch and instance
         const double bytes_down = nc * ((l == 0 ? st : si) * L.n + si * (L.n + C.n)) + (dir ? si * 3.0 * L.n * ninst_ : 0.0);
-        const int kcls = l == 0 ? (int)kKDown : -1;
+        const int kcls = l == 0 ? kclass_for(kKDown, nc) : -1;
         with_op<TI>(l, [&](auto op) {
             using Op = decltype(op);
             const int chk = l == 0 ? check : 0;
@@ -912,7 +912,7 @@ void Hierarchy::vcycle_impl(int nc, int check) {
         // read b, x2, x_coarse (and r for r^T z), write x; coefficients once per instance
         const double bytes_up = nc * ((l == 0 ? 3.0 * st : 2.0 * si) * L.n + si * (L.n + C.n)) +
                                 (dir ? si * 3.0 * L.n * ninst_ : 0.0);
-        const int kcls = l == 0 ? (int)kKUp : -1;
+        const int kcls = l == 0 ? kclass_for(kKUp, nc) : -1;
         with_op<TI>(l, [&](auto op) {
             using Op = decltype(op);
             const int cb = shape_.cb, gz = ceil_div(nc, cb);
@@ -965,7 +965,7 @@ void Hierarchy::pcg_iteration(int nc, int cur, int first) {
             const T* pold = P[cur];
             const int* actc = act;
             ColState* stc = st_.get();
-            timed_launch(ctx_, kKPcgApply, bytes_apply, first ? k_pcg_apply<T, Op, true> : k_pcg_apply<T, Op, false>, g,
+            timed_launch(ctx_, kclass_for(kKPcgApply, nc), bytes_apply, first ? k_pcg_apply<T, Op, true> : k_pcg_apply<T, Op, false>, g,
                          dim3(vec_threads(red.per)), s, op, zc, pold, P[1 - cur], w.q.get(), ld, actc, stc, red);
         });
         HINV_LAUNCH_CHECK();
@@ -974,7 +974,7 @@ void Hierarchy::pcg_iteration(int nc, int cur, int first) {
         // x, r in/out, p, q in
         const T* pn = P[1 - cur];
         const T* qc = w.q.get();
-        timed_launch(ctx_, kKPcgUpdate, sizeof(T) * (double)nc * 6.0 * n, k_pcg_update<T>, g,
+        timed_launch(ctx_, kclass_for(kKPcgUpdate, nc), sizeof(T) * (double)nc * 6.0 * n, k_pcg_update<T>, g,
                      dim3(vec_threads(red.per)), s,
                      w.x.get(), w.r.get(), pn, qc, ld, n, act, st_.get(), red);
         HINV_LAUNCH_CHECK();
@@ -1080,8 +1080,8 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
     if (graphs && max_iter > 0) {
         HINV_HIP(hipGraphLaunch(prologue_graph<T>(nc), s));
         it = 1;
-        for (int k : {(int)kKDown, (int)kKUp, (int)kKBottom}) ctx_->timer.count_only(k, 2);
-        for (int k : {(int)kKPcgApply, (int)kKPcgUpdate}) ctx_->timer.count_only(k, 1);
+        for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom}) ctx_->timer.count_only(k, 2);
+        for (int k : {kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)}) ctx_->timer.count_only(k, 1);
     } else {
         vcycle<T>(nc, 0);
         if (max_iter > 0) {
@@ -1116,14 +1116,16 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
             if (reps > 1 && graphs) {
                 for (int rep = 1; rep < reps; ++rep) HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
                 it += 2 * (reps - 1);
-                for (int k : {(int)kKDown, (int)kKUp, (int)kKBottom, (int)kKPcgApply, (int)kKPcgUpdate})
+                for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom,
+                              kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)})
                     ctx_->timer.count_only(k, 2 * (reps - 1));
             }
         } else if (graphs && reps > 0) {
             for (int rep = 0; rep < reps; ++rep) HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
             it += 2 * reps;
             // two iterations per replay: two launches of each finest-level class
-            for (int k : {(int)kKDown, (int)kKUp, (int)kKBottom, (int)kKPcgApply, (int)kKPcgUpdate})
+            for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom,
+                              kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)})
                 ctx_->timer.count_only(k, 2 * reps);
         } else {
             // odd tail: one eager iteration keeps the ping-pong parity at P[1]

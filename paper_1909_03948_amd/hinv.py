@@ -86,7 +86,9 @@ EXPORTS = [
     "hinv_cnn_train_step", "hinv_cnn_harvest",
 ]
 
-KCLASS = {"mg_down": 0, "mg_up": 1, "mg_bottom": 2, "pcg_apply": 3, "pcg_update": 4, "gram": 5}
+# timer classes: single-column launches, and the same kernels batched (>= 8 columns)
+KCLASS = {"mg_down": 0, "mg_up": 1, "mg_bottom": 2, "pcg_apply": 3, "pcg_update": 4, "gram": 5,
+          "mg_down_b": 6, "mg_up_b": 7, "pcg_apply_b": 8, "pcg_update_b": 9}
 
 _lib = None
 
@@ -450,6 +452,20 @@ class Cnn:
         if a.size != self.nparams:
             raise ValueError("parameter count mismatch")
         self._check(self.lib.hinv_cnn_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+    # (c_out, c_in) of the six convolutions: 3 -> 32, four 32 -> 32, 32 -> 1
+    LAYERS = ((32, 3), (32, 32), (32, 32), (32, 32), (32, 32), (1, 32))
+
+    def he_init(self, seed=0):
+        """Seeded He-normal weights (std sqrt(2 / (9 c_in)), the last layer's
+        scaled by 0.1 so the initial correction is small), zero biases, packed
+        per layer as W[c_out][c_in][3][3] then b[c_out]; resets Adam."""
+        rng = np.random.default_rng(seed)
+        parts = []
+        for li, (co, ci) in enumerate(self.LAYERS):
+            std = np.sqrt(2.0 / (9.0 * ci)) * (0.1 if li == len(self.LAYERS) - 1 else 1.0)
+            parts += [std * rng.standard_normal(co * ci * 9), np.zeros(co)]
+        self.set_params(np.concatenate(parts))
 
     def get_params(self):
         a = np.zeros(self.nparams, dtype=np.float32)

@@ -7,7 +7,13 @@
 The classes match the library's sampled timer: mg_down / mg_up are the fused
 V-cycle kernels of the finest level only (in dispatch order, the first k_down
 and the last k_up of each run of multigrid kernels), mg_bottom, pcg_apply and
-pcg_update are single-level, gram is the block product.  `trace` reads the
+pcg_update are single-level, gram is the block product.  The bandwidth-bound
+classes are split into two launch populations as the timer splits them:
+single right-hand sides (mg_down, ...) and batched solves (mg_down_b, ...).
+The split goes by the finest level's precision in the kernel name: in the
+default precision mode every solve of fewer than eight columns is an FP64
+PCG (its finest-level kernels take double vectors) and every solve of eight
+or more an FP32 PCG inside FP64 refinement (float vectors throughout).  `trace` reads the
 kernel-trace CSV (per-dispatch durations); `pmc` reads a one-counter
 counter-collection CSV (FETCH_SIZE or WRITE_SIZE, KiB per dispatch) and also
 reports the counter of the run's last plain device copy (the benchmark ends
@@ -44,6 +50,17 @@ def short(name):
     return name.split("(")[0].replace("void ", "").replace("hinv::", "").strip()
 
 
+SPLIT = ("mg_down", "mg_up", "pcg_apply", "pcg_update")
+
+
+def population(cls, name):
+    """Class of a finest-level dispatch with its launch population: the batched
+    (FP32) variants of the bandwidth-bound classes get the suffix _b."""
+    if cls in SPLIT and "double" not in short(name):
+        return cls + "_b"
+    return cls
+
+
 def finest_mask(classes):
     """Per dispatch (in dispatch order): does it belong to its class's timed population."""
     out = []
@@ -78,6 +95,7 @@ def summarize_trace(d):
         per_name[short(name)][0] += 1
         per_name[short(name)][1] += dur
         if c and m:
+            c = population(c, name)
             agg[c][0] += 1
             agg[c][1] += dur
     top = sorted(per_name.items(), key=lambda kv: -kv[1][1])[:20]
@@ -100,6 +118,7 @@ def summarize_pmc(d):
         if name.startswith(COPY_KERNEL):
             copy = v
         if c and m:
+            c = population(c, name)
             agg[c][0] += 1
             agg[c][1] += v
             agg[c][2][short(name)] += 1

@@ -1,8 +1,9 @@
 """GPU parity of the paper's algorithms against the FP64 oracle.
 
 * MAP point (Alg. 1): the oracle's own gradient at the GPU's MAP point is
-  <= 1e-8 |g_0|, and the two MAP points agree to <= 1e-7 in the R-norm
-  relative to |m_map - m_pr|_R (both stop at their own gradient tolerance).
+  <= 1e-8 |g_0|, and the two MAP points agree to <= 1e-8 in the R-norm
+  relative to |m_map - m_pr|_R (both run Newton-CG to |g| <= 1e-11 |g_0| or
+  to the floor where Armijo can no longer resolve the decrease of J).
 * Eigenpairs (Alg. 2 + Alg. 4) at the oracle's MAP point with the same probe
   matrix: |lambda_gpu - lambda_orc| <= 1e-8 lambda_1 for all k, relative error
   <= 1e-8 for the leading eigenvalues (lambda >= 1e-2 lambda_1), eigenvectors
@@ -46,7 +47,7 @@ def gpu_problem(ctx, prob, obs, precision=hv.PREC_FP64):
 def map32():
     prob, _, obs = instance(32, 100)
     m_map, info = newton.newton_cg(prob, rel_tol=1e-11)
-    assert info["converged"]
+    assert info["gnorm"][-1] <= 1e-10 * info["gnorm"][0], info
     return prob, obs, m_map
 
 
@@ -56,8 +57,10 @@ def test_newton_map_point(ctx, map32, prec):
     prob, obs, m_orc = map32
     gp = gpu_problem(ctx, prob, obs, prec)
     md = dev(np.zeros(prob.n))
-    info = gp.map_newton(md, rel_tol=1e-9)
-    assert info["rc"] == 0 and info["converged"], info
+    info = gp.map_newton(md, rel_tol=1e-11)
+    # converged, or stopped by the line search at the floor of J's resolution
+    assert info["rc"] in (hv.HINV_OK, hv.HINV_ESTATE), info
+    assert info["gnorm"][-1] <= 1e-9 * info["gnorm"][0], info
     m_gpu = host(md)
     u = prob.forward(m_gpu)
     g = prob.gradient(m_gpu, u, prob.adjoint(m_gpu, u))
@@ -65,7 +68,9 @@ def test_newton_map_point(ctx, map32, prec):
     assert np.linalg.norm(g) <= 1e-8 * g0
     d = m_gpu - m_orc
     dm = m_orc - prob.m_pr
-    assert np.sqrt(d @ prob.R_apply(d)) / np.sqrt(dm @ prob.R_apply(dm)) < 1e-7
+    err = np.sqrt(d @ prob.R_apply(d)) / np.sqrt(dm @ prob.R_apply(dm))
+    print(f"[gpu] MAP R-norm rel diff {err:.2e}, |g|/|g0| {info['gnorm'][-1] / g0:.2e}", flush=True)
+    assert err <= 1e-8
     # Newton iterations are mesh-independent and few
     assert info["iterations"] <= 20
 

@@ -82,35 +82,29 @@ def test_traffic_scales_by_the_closing_copy(tmp_path):
     assert json.load(open(out))["workloads"]["w1"]["source_hash"] == ent["source_hash"]
 
 
-def test_small_quotient_by_float_reciprocal_is_exact():
-    # the bottom kernel divides node indices q by level widths d as
-    # (q + 1/2) * (1/d) in single precision, truncated; exact for q < 2^22
-    # (the product errs by at most (q + 1/2) / d * 2^-23, the quotient lies at
-    # least 1 / (2 d) from an integer)
-    import numpy as np
-    def fdiv(q, d):
-        inv = np.float32(1.0) / np.float32(d)
-        return ((q.astype(np.float32) + np.float32(0.5)) * inv).astype(np.int64)
-    q = np.arange(1 << 16, dtype=np.int64)
-    for d in range(1, 130):          # every level width of the bottom kernel and more
-        assert np.array_equal(fdiv(q, d), q // d), d
-    rng = np.random.default_rng(7)
-    for d in rng.integers(1, 1 << 12, 200):  # near multiples of d up to 2^22
-        k = rng.integers(0, ((1 << 22) - 1) // d, 500)
-        qq = np.concatenate([k * d, k * d + d - 1, np.maximum(k * d - 1, 0)])
-        qq = qq[qq < (1 << 22) - 1]
-        assert np.array_equal(fdiv(qq, int(d)), qq // d), d
-
-
-def test_node_row_by_double_reciprocal_is_exact():
-    # the PCG apply kernel splits node k = j (N + 1) + i by j = (k + 1/2) * (1/(N + 1))
-    # in double precision, truncated
-    import numpy as np
-    for n1 in (9, 17, 33, 65, 129, 257, 513, 1025, 2049):
-        k = np.arange(n1 * n1, dtype=np.int64)
-        inv = 1.0 / n1
-        j = ((k.astype(np.float64) + 0.5) * inv).astype(np.int64)
-        assert np.array_equal(j, k // n1), n1
+def test_batched_variants_form_their_own_population():
+    # a batched FP32 cycle: float vectors on every level
+    names = ["void hinv::k_down<float, hinv::OpA<float>, 16, float>(...)",
+             "void hinv::k_down<float, hinv::OpA<float>, 16, float>(...)",
+             "void hinv::k_bottom<float, 0, 32>(...)",
+             "void hinv::k_up<float, hinv::OpA<float>, 32, float, float>(...)",
+             "void hinv::k_up<float, hinv::OpA<float>, 32, float, float>(...)",
+             "void hinv::k_pcg_apply<float, hinv::OpA<float>, false>(...)",
+             "void hinv::k_pcg_update<float>(...)"]
+    # a single-column FP64 cycle: double vectors on the finest level only
+    single = ["void hinv::k_down<float, hinv::OpA<float>, 8, double>(...)",
+              "void hinv::k_down<float, hinv::OpA<float>, 8, float>(...)",
+              "void hinv::k_bottom<float, 0, 32>(...)",
+              "void hinv::k_up<float, hinv::OpA<float>, 16, float, float>(...)",
+              "void hinv::k_up<float, hinv::OpA<float>, 16, double, double>(...)",
+              "void hinv::k_pcg_apply<double, hinv::OpA<double>, false>(...)",
+              "void hinv::k_pcg_update<double>(...)"]
+    seq = names + single
+    cls = [ps.kernel_class(n) for n in seq]
+    mask = ps.finest_mask(cls)
+    picked = [ps.population(c, n) for c, n, m in zip(cls, seq, mask) if m]
+    assert picked == ["mg_down_b", "mg_bottom", "mg_up_b", "pcg_apply_b", "pcg_update_b",
+                      "mg_down", "mg_bottom", "mg_up", "pcg_apply", "pcg_update"]
 
 
 def test_short_names_keep_helper_kernels():
