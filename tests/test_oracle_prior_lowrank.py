@@ -91,6 +91,111 @@ def test_double_pass_with_full_probe_set_is_exact(gn):
         assert (ref[prob.B.shape[0]:] < 1e-8 * ref[0]).all()   # rank <= q
 
 
+def test_symmetric_least_squares_solver():
+    rng = np.random.default_rng(5)
+    s = 6
+    W = rng.standard_normal((s, s))
+    X0 = rng.standard_normal((s, s))
+    X0 = X0 + X0.T
+    # consistent data: the symmetric X0 is recovered
+    np.testing.assert_allclose(lowrank.symmetric_least_squares(W, X0 @ W), X0, atol=1e-11)
+    # inconsistent data: the solution is symmetric and satisfies the normal
+    # equations of the symmetric problem, X W W^T + W W^T X = Z W^T + W Z^T
+    Z = rng.standard_normal((s, s))
+    X = lowrank.symmetric_least_squares(W, Z)
+    np.testing.assert_allclose(X, X.T, atol=1e-13)
+    G = W @ W.T
+    np.testing.assert_allclose(X @ G + G @ X, Z @ W.T + W @ Z.T, atol=1e-10)
+    # and no symmetric perturbation lowers the residual
+    r0 = np.linalg.norm(X @ W - Z)
+    for _ in range(20):
+        E = rng.standard_normal((s, s))
+        assert np.linalg.norm((X + 1e-3 * (E + E.T)) @ W - Z) >= r0
+
+
+@pytest.mark.parametrize("gn", [False, True])
+def test_single_pass_with_full_probe_set_is_exact(gn):
+    """Algorithm 3 with as many probe vectors as unknowns: Q spans the space,
+    A = B Q T Q^T B holds exactly, and the eigenvalues are those of the dense
+    generalized problem (H_misfit, R); the Saibaba-Lee-Kitanidis T as read
+    agrees (in exact arithmetic both equal W^-T Omega^T A Omega W^-1)."""
+    prob, m, u, p = _tiny_problem()
+    n = prob.n
+    mode = model.HESS_GN_MISFIT if gn else model.HESS_MISFIT
+    A = lambda v: prob.hessian_apply(m, u, p, v, mode)
+    Om = synth.omega(n, n).T
+    lam, V, ex = lowrank.single_pass(A, prob.R_apply, prob.R_solve, Om, k=8)
+    lam2, _, _ = lowrank.single_pass_slk(A, prob.R_apply, prob.R_solve, Om, k=8)
+    Hd = _dense(A, n)
+    Hd = 0.5 * (Hd + Hd.T)
+    Rd = _dense(prob.R_apply, n)
+    Rd = 0.5 * (Rd + Rd.T)
+    ref = sla.eigh(Hd, Rd, eigvals_only=True)[::-1]
+    np.testing.assert_allclose(lam, ref[:8], rtol=1e-6, atol=1e-9 * abs(ref[0]))
+    np.testing.assert_allclose(lam2, ref[:8], rtol=1e-6, atol=1e-9 * abs(ref[0]))
+    np.testing.assert_allclose(V.T @ Rd @ V, np.eye(8), atol=1e-8)
+    # T is the symmetric least-squares solution: zero residual here
+    W, Z, T = ex["W"], ex["Z"], ex["T"]
+    assert np.linalg.norm(T @ W - Z) <= 1e-8 * np.linalg.norm(Z)
+
+
+def test_single_pass_exact_for_low_rank_operator():
+    """Gauss-Newton misfit Hessian with q observations has rank <= q; with
+    s > q probe vectors the first pass captures its range and Algorithm 3 is
+    exact for every nonzero eigenvalue, as is Algorithm 2."""
+    prob, m, u, p = _tiny_problem(N=8, q=6)
+    A = lambda v: prob.hessian_apply(m, u, p, v, model.HESS_GN_MISFIT)
+    Om = synth.omega(prob.n, 10).T
+    lam1, _, _ = lowrank.single_pass(A, prob.R_apply, prob.R_solve, Om, k=6)
+    lam2, _, _ = lowrank.double_pass(A, prob.R_apply, prob.R_solve, Om, k=6)
+    Hd = _dense(A, prob.n)
+    Rd = _dense(prob.R_apply, prob.n)
+    ref = sla.eigh(0.5 * (Hd + Hd.T), 0.5 * (Rd + Rd.T), eigvals_only=True)[::-1][:6]
+    np.testing.assert_allclose(lam2, ref, rtol=1e-7)
+    np.testing.assert_allclose(lam1, ref, rtol=1e-6)
+
+
+def test_prior_variance_exact_with_every_eigenpair():
+    """Eq. eq:prior_mvar with rbar = n eigenpairs of R^-1 (Algorithm 2, B = I,
+    l = 0) is the exact diagonal of R^-1; Eq. eq:post_mvar with every eigenpair
+    of (H_misfit, R) is the exact diagonal of (H_misfit + R)^-1 (Eq. eq:sm with
+    zero remainder); the stochastic estimator with the unit vectors as probes
+    is exact too."""
+    prob, m, u, p = _tiny_problem()
+    n = prob.n
+    Rd = _dense(prob.R_apply, n)
+    Rd = 0.5 * (Rd + Rd.T)
+    Rinv = np.linalg.inv(Rd)
+    dg, mu = lowrank.prior_variance(prob.R_solve, synth.omega(n, n).T)
+    np.testing.assert_allclose(dg, np.diag(Rinv), rtol=1e-8)
+    assert np.all(np.diff(mu) <= 0) and mu[-1] > 0
+    A = lambda v: prob.hessian_apply(m, u, p, v, model.HESS_GN_MISFIT)
+    Hd = _dense(A, n)
+    Hd = 0.5 * (Hd + Hd.T)
+    lam, V = sla.eigh(Hd, Rd)
+    post = lowrank.posterior_variance(np.diag(Rinv), V, lam)
+    np.testing.assert_allclose(post, np.diag(np.linalg.inv(Hd + Rd)), rtol=1e-8)
+    np.testing.assert_allclose(lowrank.stochastic_diagonal(prob.R_solve, np.eye(n)), np.diag(Rinv),
+                               rtol=1e-10)
+
+
+def test_prior_variance_converges_with_rank():
+    """The truncated sum approaches diag(R^-1) as rbar grows (the eigenvalues of
+    R^-1 decay fast: it is the discretization of a compact operator), and its
+    eigenvalues mu_i are Ritz values of R^-1: below its largest eigenvalue."""
+    prob, m, u, p = _tiny_problem(N=8)
+    n = prob.n
+    Rinv = np.linalg.inv(_dense(prob.R_apply, n))
+    d = np.diag(Rinv)
+    top = np.linalg.eigvalsh(0.5 * (Rinv + Rinv.T))[-1]
+    errs = []
+    for r in (5, 20, 60):
+        dg, mu = lowrank.prior_variance(prob.R_solve, synth.omega(n, r).T)
+        assert mu[0] <= top * (1 + 1e-10)
+        errs.append(np.linalg.norm(dg - d) / np.linalg.norm(d))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-2, errs
+
+
 def test_posterior_sample_covariance_identities():
     prob, m, u, p = _tiny_problem()
     n = prob.n
