@@ -266,6 +266,36 @@ int hinv_map_newton(hinv_problem* p, const double* m0, double* m_map,
  * written, and the problem stays usable. */
 int hinv_lowrank_eig(hinv_problem* p, int mode, int tprod, int s, const double* omega, int ldo,
                      int k, double* lambda_host, double* V, int ldv, hinv_solve_info* info);
+/* Single-pass randomized eigensolver for H_misfit v = lambda R v (Alg. 3): one
+ * pass of the Hessian over omega (n x s), Y = R^-1 H omega, PreCholQR of Y
+ * (Alg. 4) giving Q (Q^T R Q = I) and Qbar = R Q; T is the least-squares
+ * solution over symmetric s x s matrices of T (Qbar^T omega) = Qbar^T Y in the
+ * Frobenius norm (Eq. eq:Tsinglepass), computed from its normal equations in
+ * the eigenbasis of W W^T, W = Qbar^T omega; T = S Lambda S^T, V = Q S_k.
+ * s Hessian actions instead of the double pass's 2 s, less accurate where the
+ * spectrum beyond s is not negligible.  Arguments, layout and errors as in
+ * hinv_lowrank_eig (FP64 block products; W must be nonsingular, which a
+ * Gaussian omega gives with probability one). */
+int hinv_lowrank_eig_single(hinv_problem* p, int mode, int s, const double* omega, int ldo, int k,
+                            double* lambda_host, double* V, int ldv, hinv_solve_info* info);
+
+/* Pointwise variance of the prior (Sec. 4.4.1, Eq. eq:prior_mvar): diag[n]
+ * (device) = sum_i mu_i vbar_i (.) vbar_i, the (mu_i, vbar_i) being the s
+ * eigenpairs of R^-1 from Alg. 2 with A = R^-1, B = I and no oversampling
+ * (2 s prior solves).  omega: device n x s Gaussian block (ld ldo); mu_host:
+ * HOST [s] (descending) or NULL.  Errors: HINV_EINVAL unless
+ * 1 <= s <= min(512, n); HINV_EBREAK if Y = R^-1 omega has rank below s. */
+int hinv_prior_variance(hinv_problem* p, int s, const double* omega, int ldo, double* diag, double* mu_host,
+                        hinv_solve_info* info);
+
+/* Pointwise variance of the Laplace posterior (Sec. 4.4.2, Eq. eq:post_mvar):
+ * diag[n] = prior_diag - sum_i lambda_i / (1 + lambda_i) v_i (.) v_i with the
+ * eigenpairs of hinv_lowrank_eig (lambda: HOST [k]; V: device n x k, ld ldv;
+ * prior_diag, diag: device [n], may alias).  HINV_ENEGEIG if some
+ * lambda_i <= -1.  Synchronizes the stream. */
+int hinv_posterior_variance(hinv_problem* p, const double* prior_diag, int k, const double* lambda_host,
+                            const double* V, int ldv, double* diag);
+
 /* out[:,j] = m_map + (I - V S V^T R) x_j with x_j = K_A^{-1} C_M eta[:,j] and
  * S = diag(1 - (1 + lambda)^{-1/2}) (Eq. eq:sample_post).  lambda: HOST [k]. */
 int hinv_posterior_sample(hinv_problem* p, const double* m_map, int k, const double* lambda_host,

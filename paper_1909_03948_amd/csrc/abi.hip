@@ -436,6 +436,57 @@ int hinv_lowrank_eig(hinv_problem* p, int mode, int tprod, int s, const double* 
     return conv_status(st);
 }
 
+int hinv_lowrank_eig_single(hinv_problem* p, int mode, int s, const double* omega, int ldo, int k,
+                            double* lambda_host, double* V, int ldv, hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int status = HINV_OK;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(mode == HINV_HESS_MISFIT || mode == HINV_HESS_GN_MISFIT, "mode must be a misfit mode");
+        REQUIRE(s >= 1 && s <= 512 && s <= n, "probe count s must be in [1, min(512, n)]");
+        REQUIRE(k >= 1 && k <= s, "k must be in [1, s]");
+        REQUIRE(ldo >= n && ldv >= n, "bad leading dimension");
+        REQUIRE(omega && lambda_host && V, "null argument");
+        status = hinv::lowrank_eig_single(*p->p, mode, s, omega, ldo, k, lambda_host, V, ldv, &st);
+    });
+    fill_info(info, st);
+    if (rc != HINV_OK) return rc;
+    if (status != HINV_OK) return status;
+    return conv_status(st);
+}
+
+int hinv_prior_variance(hinv_problem* p, int s, const double* omega, int ldo, double* diag, double* mu_host,
+                        hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int status = HINV_OK;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(s >= 1 && s <= 512 && s <= n, "probe count s must be in [1, min(512, n)]");
+        REQUIRE(ldo >= n, "bad leading dimension");
+        REQUIRE(omega && diag, "null argument");
+        status = hinv::prior_variance(*p->p, s, omega, ldo, diag, mu_host, &st);
+    });
+    fill_info(info, st);
+    if (rc != HINV_OK) return rc;
+    if (status != HINV_OK) return status;
+    return conv_status(st);
+}
+
+int hinv_posterior_variance(hinv_problem* p, const double* prior_diag, int k, const double* lambda_host,
+                            const double* V, int ldv, double* diag) {
+    if (!p) return HINV_EINVAL;
+    return guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(k >= 0 && (k == 0 || ldv >= n), "bad size or leading dimension");
+        REQUIRE(prior_diag && diag && (k == 0 || (lambda_host && V)), "null argument");
+        for (int i = 0; i < k; ++i)
+            if (!(lambda_host[i] > -1.0)) hinv::fail(HINV_ENEGEIG, "eigenvalue <= -1");
+        hinv::posterior_variance(*p->p, prior_diag, k, lambda_host, V, ldv, diag);
+    });
+}
+
 int hinv_posterior_sample(hinv_problem* p, const double* m_map, int k, const double* lambda_host,
                           const double* V, int ldv, int ns, const double* eta, int ldeta,
                           double* out, int ldo, hinv_solve_info* info) {

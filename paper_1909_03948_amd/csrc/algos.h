@@ -20,11 +20,24 @@ int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int
 // eigenvalues at lam + j s.  The s x s factorizations of all members run in
 // one launch each; the tall products run per member.
 struct DenseWork;
+// b_identity: B = I (Zbar = Z) instead of the prior operator R.
 int precholqr(Problem* const* P, int ni, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
-              double* Ri);
+              double* Ri, bool b_identity = false);
 void rayleigh_ritz(Problem* const* P, int ni, DenseWork& dw, int s, int k, int tprod, const double* Q,
                    const double* AQ, double* T, double* S, double* lam, double* const* V, int ldv,
                    double* const* lambda_host);
+
+// Single-pass randomized generalized eigensolver (Alg. 3) with PreCholQR (Alg. 4).
+int lowrank_eig_single(Problem& P, int mode, int s, const double* omega, int ldo, int k,
+                       double* lambda_host, double* V, int ldv, SolveStats* st);
+
+// Pointwise variance (Sec. 4.4): the prior's from a randomized
+// eigendecomposition of R^-1 (Eq. eq:prior_mvar), the posterior's by the
+// low-rank correction (Eq. eq:post_mvar).
+int prior_variance(Problem& P, int s, const double* omega, int ldo, double* diag, double* mu_host,
+                   SolveStats* st);
+void posterior_variance(Problem& P, const double* prior_diag, int k, const double* lambda_host, const double* V,
+                        int ldv, double* diag);
 
 // Posterior samples through the low-rank update (Sec. 4.3.2).
 void posterior_sample(Problem& P, const double* m_map, int k, const double* lambda_host,

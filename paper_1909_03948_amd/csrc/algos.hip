@@ -256,13 +256,16 @@ bool orthonormalize(Ctx* c, DenseWork& w, int ni, int n, int s, double* Y, doubl
 // R_Z = chol(Z^T Zbar), Q = Z R_Z^-1 written to Q_j.  Y_j is overwritten by
 // Z_j; Zb is scratch.
 int precholqr(Problem* const* P, int ni, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
-              double* Ri) {
+              double* Ri, bool b_identity) {
     Ctx* c = P[0]->ctx;
     const int n = P[0]->n;
     const size_t ts = (size_t)n * s, ss = (size_t)s * s;
     if (!orthonormalize(c, dw, ni, n, s, Y, Q, G, Ri)) return HINV_EBREAK;  // Y <- Z
     for (int j = 0; j < ni; ++j) {
-        P[j]->prior_apply(s, Y + j * ts, n, Zb + j * ts, n);                       // Zbar = B Z
+        if (b_identity)
+            dev_copy(c, n, s, Y + j * ts, n, Zb + j * ts, n);                      // Zbar = Z
+        else
+            P[j]->prior_apply(s, Y + j * ts, n, Zb + j * ts, n);                   // Zbar = B Z
         gram(c, dw, n, s, s, Y + j * ts, n, Zb + j * ts, n, G + j * ss, s);      // Z^T Zbar
     }
     if (!cholesky_upper(c, dw, ni, s, G, s, ss)) return HINV_EBREAK;            // R_Z
@@ -316,6 +319,121 @@ int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int
     P.hessian(mode, s, W, n, Zb, n, st);
     rayleigh_ritz(&pp, 1, dw, s, k, tprod, W, Zb, T, S, lam, &V, ldv, &lambda_host);
     return HINV_OK;
+}
+
+// ------------------------------------------------------- single pass ---
+// Algorithm 3: one pass of A over Omega.  PreCholQR of Y = B^-1 A Omega gives
+// Q and Qbar = B Q; T is the least-squares solution over symmetric matrices of
+// T W = Z with W = Qbar^T Omega, Z = Qbar^T Y (Eq. eq:Tsinglepass).  Its
+// normal equations T G + G T = C with G = W W^T, C = Z W^T + W Z^T are solved
+// in the eigenbasis of G = U diag(g) U^T: (U^T T U)_ij = (U^T C U)_ij / (g_i + g_j).
+int lowrank_eig_single(Problem& P, int mode, int s, const double* omega, int ldo, int k,
+                       double* lambda_host, double* V, int ldv, SolveStats* st) {
+    Ctx* c = P.ctx;
+    const int n = P.n;
+    const size_t ts = (size_t)n * s, ss = (size_t)s * s;
+    DBuf<double> big, small;
+    big.ensure(ts * 5);
+    small.ensure(ss * 9 + 2 * (size_t)s);
+    double* Yb = big.get();      // A Omega, later Qbar
+    double* Y = Yb + ts;         // B^-1 A Omega, overwritten by Z
+    double* Yk = Y + ts;         // B^-1 A Omega, kept
+    double* Zb = Yk + ts;        // B Z
+    double* Q = Zb + ts;
+    double* G = small.get();
+    double* Ri = G + ss;
+    double* Wm = Ri + ss;
+    double* Zm = Wm + ss;
+    double* Cm = Zm + ss;
+    double* U = Cm + ss;
+    double* Tm = U + ss;
+    double* S = Tm + ss;
+    double* tmp = S + ss;
+    double* g = tmp + ss;
+    double* lam = g + s;
+    DenseWork dw;
+    P.hessian(mode, s, omega, ldo, Yb, n, st);       // Ybar = A Omega
+    P.prior_solve(s, Yb, n, Y, n, st);                // Y = B^-1 Ybar
+    dev_copy(c, n, s, Y, n, Yk, n);
+    Problem* const pp = &P;
+    const int rc = precholqr(&pp, 1, dw, s, Y, Zb, Q, G, Ri);  // Q; Zb = B Z; Ri = R_Z^-1
+    if (rc != HINV_OK) return rc;
+    gemm_tall(c, n, s, s, 1.0, Zb, n, Ri, s, 0.0, Yb, n);        // Qbar = B Z R_Z^-1 = B Q
+    gram(c, dw, n, s, s, Yb, n, omega, ldo, Wm, s);              // W = Qbar^T Omega
+    gram(c, dw, n, s, s, Yb, n, Yk, n, Zm, s);                   // Z = Qbar^T Y
+    small_gemm(c, false, true, s, s, s, 1.0, Wm, s, Wm, s, 0.0, G, s);    // G = W W^T
+    small_gemm(c, false, true, s, s, s, 1.0, Zm, s, Wm, s, 0.0, Cm, s);   // C = Z W^T
+    small_gemm(c, false, true, s, s, s, 1.0, Wm, s, Zm, s, 1.0, Cm, s);   //   + W Z^T
+    sym_eig(c, dw, 1, s, G, s, ss, U, s, ss, g, s);                       // G = U diag(g) U^T
+    small_gemm(c, false, false, s, s, s, 1.0, Cm, s, U, s, 0.0, tmp, s);  // C U
+    small_gemm(c, true, false, s, s, s, 1.0, U, s, tmp, s, 0.0, Tm, s);   // U^T C U
+    sylvester_diag(c, s, g, Tm, s);                                       // / (g_i + g_j)
+    small_gemm(c, false, false, s, s, s, 1.0, U, s, Tm, s, 0.0, tmp, s);  // U X
+    small_gemm(c, false, true, s, s, s, 1.0, tmp, s, U, s, 0.0, Tm, s);   // T = U X U^T
+    sym_eig(c, dw, 1, s, Tm, s, ss, S, s, ss, lam, s);
+    gemm_tall(c, n, s, k, 1.0, Q, n, S, s, 0.0, V, ldv);                  // V = Q S_k
+    HINV_HIP(hipMemcpyAsync(lambda_host, lam, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    HINV_HIP(hipStreamSynchronize(c->stream));
+    return HINV_OK;
+}
+
+// ----------------------------------------------------- pointwise variance ---
+namespace {
+__global__ void k_post_var_weight(int k, const double* __restrict__ lam, double* __restrict__ w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) w[i] = -lam[i] / (1.0 + lam[i]);
+}
+}  // namespace
+
+// Eq. eq:prior_mvar: Algorithm 2 with A = R^-1, B = I and no oversampling
+// (s probe vectors, s eigenpairs (mu, vbar)), diag(R^-1) ~ sum mu_i vbar_i^2.
+int prior_variance(Problem& P, int s, const double* omega, int ldo, double* diag, double* mu_host,
+                   SolveStats* st) {
+    Ctx* c = P.ctx;
+    const int n = P.n;
+    const size_t ts = (size_t)n * s, ss = (size_t)s * s;
+    DBuf<double> big, small;
+    big.ensure(ts * 4);
+    small.ensure(ss * 4 + s);
+    double* Y = big.get();
+    double* Zb = Y + ts;
+    double* Q = Zb + ts;
+    double* Vb = Q + ts;
+    double* G = small.get();
+    double* Ri = G + ss;
+    double* T = Ri + ss;
+    double* S = T + ss;
+    double* mu = S + ss;
+    DenseWork dw;
+    P.prior_solve(s, omega, ldo, Y, n, st);                   // Y = R^-1 Omega (B = I)
+    Problem* const pp = &P;
+    const int rc = precholqr(&pp, 1, dw, s, Y, Zb, Q, G, Ri, /*b_identity=*/true);
+    if (rc != HINV_OK) return rc;
+    P.prior_solve(s, Q, n, Zb, n, st);                        // R^-1 Q
+    gram(c, dw, n, s, s, Q, n, Zb, n, T, s);                  // T = Q^T R^-1 Q
+    sym_eig(c, dw, 1, s, T, s, ss, S, s, ss, mu, s);
+    gemm_tall(c, n, s, s, 1.0, Q, n, S, s, 0.0, Vb, n);       // vbar = Q S
+    weighted_squares(c, n, s, Vb, n, mu, nullptr, diag);
+    if (mu_host) HINV_HIP(hipMemcpyAsync(mu_host, mu, sizeof(double) * s, hipMemcpyDeviceToHost, c->stream));
+    HINV_HIP(hipStreamSynchronize(c->stream));
+    return HINV_OK;
+}
+
+// Eq. eq:post_mvar: diag = prior_diag - sum lambda_i / (1 + lambda_i) v_i^2.
+void posterior_variance(Problem& P, const double* prior_diag, int k, const double* lambda_host, const double* V,
+                        int ldv, double* diag) {
+    Ctx* c = P.ctx;
+    DBuf<double> small;
+    small.ensure(2 * (size_t)std::max(k, 1));
+    double* lam = small.get();
+    double* w = lam + std::max(k, 1);
+    if (k > 0) {
+        HINV_HIP(hipMemcpyAsync(lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+        k_post_var_weight<<<ceil_div(k, 256), 256, 0, c->stream>>>(k, lam, w);
+        HINV_LAUNCH_CHECK();
+    }
+    weighted_squares(c, P.n, k, V, ldv, w, prior_diag, diag);
+    HINV_HIP(hipStreamSynchronize(c->stream));
 }
 
 // ------------------------------------------------------ posterior sample ---

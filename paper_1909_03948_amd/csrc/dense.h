@@ -49,6 +49,18 @@ void sym_eig(Ctx* ctx, DenseWork& w, int nb, int s, double* T, int ldt, size_t s
 // out[b] = factor * trace(A_b) (device, no synchronization).
 void scaled_trace(Ctx* ctx, int nb, int s, const double* A, int lda, size_t sa, double factor, double* out);
 
+// C (m x n) = alpha op(A) op(B) + beta C, op(X) = X^T when its flag is set
+// (kk inner dimension; small matrices, one thread per entry of C).
+void small_gemm(Ctx* ctx, bool ta, bool tb, int m, int n, int kk, double alpha, const double* A, int lda,
+                const double* B, int ldb, double beta, double* C, int ldc);
+
+// C[i, j] /= d[i] + d[j] for the s x s matrix C (device d).
+void sylvester_diag(Ctx* ctx, int s, const double* d, double* C, int ldc);
+
+// out[i] = base[i] + sum_j w[j] V[i, j]^2 (base may be null: 0; w: device, k).
+void weighted_squares(Ctx* ctx, int n, int k, const double* V, int ldv, const double* w, const double* base,
+                      double* out);
+
 // Row scaling B[i, :] *= d[i] (B: s x t column-major).
 void scale_rows(Ctx* ctx, int s, int t, const double* d, double* B, int ldb);
 

@@ -735,6 +735,45 @@ __global__ void k_small_gemm(int m, int n, int kk, double alpha, const double* _
     C[i + (size_t)j * ldc] = alpha * acc;
 }
 
+// C (m x n) = alpha op(A) op(B) + beta C with op(X) = X or X^T (flags ta, tb),
+// one thread per entry of C; the small s x s products of the single-pass
+// eigensolver.
+__global__ void k_small_gemm_t(int m, int n, int kk, int ta, int tb, double alpha, const double* __restrict__ A,
+                               int lda, const double* __restrict__ B, int ldb, double beta, double* __restrict__ C,
+                               int ldc) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= m * n) return;
+    const int i = id % m, j = id / m;
+    const size_t ai = ta ? (size_t)i * lda : i, ak = ta ? 1 : lda;
+    const size_t bj = tb ? j : (size_t)j * ldb, bk = tb ? ldb : 1;
+    double acc = 0.0;
+    for (int k = 0; k < kk; ++k) acc += A[ai + k * ak] * B[bj + k * bk];
+    double* c = C + i + (size_t)j * ldc;
+    *c = beta == 0.0 ? alpha * acc : alpha * acc + beta * *c;
+}
+
+// C[i, j] /= d[i] + d[j] (s x s): the solution of the Sylvester equation
+// D X + X D = C for diagonal D.
+__global__ void k_sylvester_diag(int s, const double* __restrict__ d, double* __restrict__ C, int ldc) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= s * s) return;
+    const int i = id % s, j = id / s;
+    C[i + (size_t)j * ldc] /= d[i] + d[j];
+}
+
+// out[i] = base[i] (0 when null) + sum_j w[j] V[i, j]^2 (V: n x k, ldv).
+__global__ void k_weighted_squares(int n, int k, const double* __restrict__ V, int ldv, const double* __restrict__ w,
+                                   const double* __restrict__ base, double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const double v = V[i + (size_t)j * ldv];
+        acc += w[j] * v * v;
+    }
+    out[i] = (base ? base[i] : 0.0) + acc;
+}
+
 __global__ void k_zero_matrix(int m, int n, double* __restrict__ C, int ldc, size_t sc) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id < m * n) C[blockIdx.y * sc + id % m + (size_t)(id / m) * ldc] = 0.0;
@@ -879,6 +918,26 @@ void sym_eig(Ctx* ctx, DenseWork& w, int nb, int s, double* T, int ldt, size_t s
 void scaled_trace(Ctx* ctx, int nb, int s, const double* A, int lda, size_t sa, double factor, double* out) {
     if (nb <= 0) return;
     k_scaled_trace<<<nb, 1024, 0, ctx->stream>>>(s, A, lda, sa, factor, out);
+    HINV_LAUNCH_CHECK();
+}
+
+void small_gemm(Ctx* ctx, bool ta, bool tb, int m, int n, int kk, double alpha, const double* A, int lda,
+                const double* B, int ldb, double beta, double* C, int ldc) {
+    if (m * n == 0) return;
+    k_small_gemm_t<<<ceil_div((long)m * n, 256), 256, 0, ctx->stream>>>(m, n, kk, ta, tb, alpha, A, lda, B, ldb,
+                                                                         beta, C, ldc);
+    HINV_LAUNCH_CHECK();
+}
+
+void sylvester_diag(Ctx* ctx, int s, const double* d, double* C, int ldc) {
+    if (s == 0) return;
+    k_sylvester_diag<<<ceil_div((long)s * s, 256), 256, 0, ctx->stream>>>(s, d, C, ldc);
+    HINV_LAUNCH_CHECK();
+}
+
+void weighted_squares(Ctx* ctx, int n, int k, const double* V, int ldv, const double* w, const double* base,
+                      double* out) {
+    k_weighted_squares<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(n, k, V, ldv, w, base, out);
     HINV_LAUNCH_CHECK();
 }
 

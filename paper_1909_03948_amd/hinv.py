@@ -78,7 +78,8 @@ EXPORTS = [
     "hinv_set_data", "hinv_set_solver", "hinv_forward", "hinv_cost", "hinv_observe",
     "hinv_gradient", "hinv_linearize", "hinv_inc_forward", "hinv_inc_adjoint",
     "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_apply_noalloc", "hinv_prior_solve", "hinv_prior_sample",
-    "hinv_map_newton", "hinv_lowrank_eig", "hinv_posterior_sample", "hinv_ctx_kernel_timer",
+    "hinv_map_newton", "hinv_lowrank_eig", "hinv_lowrank_eig_single", "hinv_prior_variance",
+    "hinv_posterior_variance", "hinv_posterior_sample", "hinv_ctx_kernel_timer",
     "hinv_ctx_kernel_timer_read", "hinv_white_noise", "hinv_batch_create", "hinv_batch_destroy",
     "hinv_batch_hessian_apply", "hinv_batch_lowrank_eig", "hinv_state_apply", "hinv_state_solve",
     "hinv_state_solve_fcg", "hinv_cnn_create", "hinv_cnn_destroy", "hinv_cnn_param_count",
@@ -131,6 +132,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_map_newton": [P, V, V, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)],
         "hinv_lowrank_eig": [P, I, I, I, V, I, I, DP, V, I, C.POINTER(SolveInfo)],
         "hinv_posterior_sample": [P, V, I, DP, V, I, I, V, I, V, I, C.POINTER(SolveInfo)],
+        "hinv_lowrank_eig_single": [P, I, I, V, I, I, DP, V, I, C.POINTER(SolveInfo)],
+        "hinv_prior_variance": [P, I, V, I, V, DP, C.POINTER(SolveInfo)],
+        "hinv_posterior_variance": [P, V, I, DP, V, I, V],
         "hinv_ctx_kernel_timer": [P, I, I, I],
         "hinv_white_noise": [P, C.c_uint64, C.c_uint64, C.c_int64, I, V, I],
         "hinv_ctx_kernel_timer_read": [P, I, C.POINTER(I), C.POINTER(C.c_long), DP, DP],
@@ -174,6 +178,15 @@ def _ptr(t):
     if t.dim() > 0 and t.numel() > 0 and t.stride(-1) != 1:
         raise ValueError("last dimension must be contiguous")
     return C.c_void_p(t.data_ptr())
+
+
+def _vec(t, n):
+    """Pointer of a vector of at least n entries (a 1-D tensor or one packed row)."""
+    if t.dim() != 1 and not (t.dim() == 2 and t.shape[0] == 1):
+        raise ValueError("expected a vector")
+    if t.numel() < n:
+        raise ValueError(f"vector has {t.numel()} entries, needs {n}")
+    return _ptr(t)
 
 
 def _cols(t, n):
@@ -397,6 +410,39 @@ class Problem:
         rc = self._check(self.lib.hinv_lowrank_eig(self.h, mode, tprod, s, po, ldo, k, lam, pv, ldv,
                                                    C.byref(info)))
         return np.array(lam[:]), info.as_dict() | {"rc": rc}
+
+    def lowrank_eig_single(self, omega, k, V, mode=HESS_MISFIT):
+        """Single-pass eigensolver (Alg. 3): (lambda[k], info); V (>= k, n) receives V_k."""
+        po, s, ldo = _cols(omega, self.n)
+        pv, kv, ldv = _cols(V, self.n)
+        if not 1 <= k <= min(s, kv):
+            raise ValueError("need 1 <= k <= number of probe vectors and of V's columns")
+        lam = (C.c_double * k)()
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_lowrank_eig_single(self.h, mode, s, po, ldo, k, lam, pv, ldv,
+                                                          C.byref(info)))
+        return np.array(lam[:]), info.as_dict() | {"rc": rc}
+
+    def prior_variance(self, omega, diag):
+        """diag(R^-1) by Eq. eq:prior_mvar with the s columns of omega: (mu[s], info)."""
+        po, s, ldo = _cols(omega, self.n)
+        _vec(diag, self.n)
+        mu = (C.c_double * max(s, 1))()
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_prior_variance(self.h, s, po, ldo, _ptr(diag), mu, C.byref(info)))
+        return np.array(mu[:s]), info.as_dict() | {"rc": rc}
+
+    def posterior_variance(self, prior_diag, lam, V, diag):
+        """diag = prior_diag - sum lambda/(1+lambda) v^2 (Eq. eq:post_mvar)."""
+        k = len(lam)
+        _vec(prior_diag, self.n)
+        _vec(diag, self.n)
+        pv, kv, ldv = _cols(V, self.n)
+        if kv < k:
+            raise ValueError("V has fewer columns than eigenvalues")
+        lam_arr = (C.c_double * max(k, 1))(*[float(x) for x in lam])
+        self._check(self.lib.hinv_posterior_variance(self.h, _ptr(prior_diag), k, lam_arr, pv, ldv,
+                                                     _ptr(diag)), allow=())
 
     def posterior_sample(self, m_map, lam, V, eta, out):
         k = len(lam)
