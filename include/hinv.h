@@ -51,6 +51,7 @@
 #ifndef HINV_H
 #define HINV_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -137,12 +138,35 @@ typedef struct {
     hinv_solve_info solves; /* accumulated over all PDE solves */
 } hinv_newton_info;
 
+/* Device memory for the library's workspaces, supplied by the caller (e.g. a
+ * framework's caching allocator).  Every device buffer the library owns -- the
+ * multigrid hierarchies, solver and eigensolver workspaces, reduction scratch
+ * -- is obtained through it; the library never frees caller-owned vectors.
+ *   alloc: returns `bytes` bytes of device memory on the context's device, for
+ *          work the library enqueues on `stream` (the context's stream), or
+ *          NULL on failure (the call then returns HINV_ENOMEM);
+ *   free:  returns memory obtained from alloc, stream-ordered: work already
+ *          enqueued on `stream` may still use it, so it must not be handed to
+ *          work that is not ordered after that stream (the semantics of
+ *          hipFreeAsync, or of a caching allocator that records the stream).
+ * Workspaces grow to the largest call and are kept until the object that owns
+ * them is destroyed: repeated calls of one shape allocate nothing. */
+typedef struct hinv_allocator {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, size_t bytes, void* stream, void* user);
+    void* user;
+} hinv_allocator;
+
 /* ---- context ------------------------------------------------------------- */
 /* Creates a context on HIP device `device` that enqueues on `hip_stream`
- * (a hipStream_t; NULL = the legacy default stream). */
-int hinv_ctx_create(int device, void* hip_stream, hinv_ctx** out);
+ * (a hipStream_t; NULL = the legacy default stream).  alloc: device allocator
+ * (copied; both callbacks non-NULL) or NULL for hipMalloc / hipFree, in which
+ * case a buffer is freed only after the context's stream has finished with it.
+ * Problems, batches and networks of a context must be destroyed before it. */
+int hinv_ctx_create(int device, void* hip_stream, const hinv_allocator* alloc, hinv_ctx** out);
 int hinv_ctx_destroy(hinv_ctx* ctx);
-/* Switches the stream later calls enqueue on. */
+/* Switches the stream later calls enqueue on; waits for the previous stream
+ * first, so buffers it still uses can be returned on the new one. */
 int hinv_ctx_set_stream(hinv_ctx* ctx, void* hip_stream);
 const char* hinv_last_error(const hinv_ctx* ctx);
 const char* hinv_status_string(int status);

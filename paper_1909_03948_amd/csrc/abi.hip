@@ -41,6 +41,7 @@ thread_local std::string g_noctx_err;
 
 template <class F>
 int guarded(hinv::Ctx* c, F f) {
+    hinv::CtxScope scope(c);  // buffers made by this call use c's allocator
     try {
         f();
         return HINV_OK;
@@ -96,9 +97,13 @@ const char* hinv_status_string(int s) {
     }
 }
 
-int hinv_ctx_create(int device, void* stream, hinv_ctx** out) {
+int hinv_ctx_create(int device, void* stream, const hinv_allocator* alloc, hinv_ctx** out) {
     if (!out) return HINV_EINVAL;
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) {
+        g_noctx_err = "allocator needs both callbacks";
+        return HINV_EINVAL;
+    }
     hinv_ctx* c = new (std::nothrow) hinv_ctx;
     if (!c) return HINV_ENOMEM;
     const int rc = guarded(nullptr, [&] {
@@ -107,6 +112,10 @@ int hinv_ctx_create(int device, void* stream, hinv_ctx** out) {
         REQUIRE(device >= 0 && device < ndev, "no such HIP device");
         c->c.device = device;
         c->c.stream = (hipStream_t)stream;
+        if (alloc) {
+            c->c.alloc = *alloc;
+            c->c.has_alloc = true;
+        }
         HINV_HIP(hipSetDevice(device));
         // device address of the fixed scratch of hinv_prior_apply_noalloc
         hinv::noalloc_init(device);
@@ -127,8 +136,11 @@ int hinv_ctx_destroy(hinv_ctx* c) {
 
 int hinv_ctx_set_stream(hinv_ctx* c, void* stream) {
     if (!c) return HINV_EINVAL;
-    c->c.stream = (hipStream_t)stream;
-    return HINV_OK;
+    return guarded(&c->c, [&] {
+        // buffers in use by work on the old stream are freed on the new one later
+        HINV_HIP(hipStreamSynchronize(c->c.stream));
+        c->c.stream = (hipStream_t)stream;
+    });
 }
 
 const char* hinv_last_error(const hinv_ctx* c) {

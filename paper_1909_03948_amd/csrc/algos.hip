@@ -80,15 +80,13 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
     Ctx* c = P.ctx;
     const int n = P.n;
     std::memset(info, 0, sizeof(*info));
-    DBuf<double> buf;
-    buf.ensure((size_t)n * 10);
-    DBuf<double> cgsb;
-    cgsb.ensure(8);
-    double* cgs = cgsb.get();
+    P.ws_newton.ensure((size_t)n * 10);
+    P.ws_scal.ensure(8);
+    double* cgs = P.ws_scal.get();
     if (!c->host_red)
         HINV_HIP(hipHostMalloc((void**)&c->host_red, sizeof(double) * Ctx::kHostRed, hipHostMallocDefault));
     double* m = m_map;
-    double* u = buf.get();
+    double* u = P.ws_newton.get();
     double* p = u + n;
     double* g = p + n;
     double* mh = g + n;
@@ -297,18 +295,17 @@ void rayleigh_ritz(Problem* const* P, int ni, DenseWork& dw, int s, int k, int t
 int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int ldo, int k,
                 double* lambda_host, double* V, int ldv, SolveStats* st) {
     const int n = P.n;
-    DBuf<double> big, small;
-    big.ensure((size_t)n * s * 3);
-    small.ensure((size_t)s * s * 4 + s);
-    double* Y = big.get();
+    P.ws_big.ensure((size_t)n * s * 3);
+    P.ws_small.ensure((size_t)s * s * 4 + s);
+    double* Y = P.ws_big.get();
     double* Zb = Y + (size_t)n * s;
     double* W = Zb + (size_t)n * s;
-    double* G = small.get();
+    double* G = P.ws_small.get();
     double* Ri = G + (size_t)s * s;
     double* T = Ri + (size_t)s * s;
     double* S = T + (size_t)s * s;
     double* lam = S + (size_t)s * s;
-    DenseWork dw;
+    DenseWork& dw = P.dw;
     // pass 1: Ybar = A Omega, Y = B^-1 Ybar  (A = H_misfit, B = R)
     P.hessian(mode, s, omega, ldo, W, n, st);
     P.prior_solve(s, W, n, Y, n, st);
@@ -332,15 +329,14 @@ int lowrank_eig_single(Problem& P, int mode, int s, const double* omega, int ldo
     Ctx* c = P.ctx;
     const int n = P.n;
     const size_t ts = (size_t)n * s, ss = (size_t)s * s;
-    DBuf<double> big, small;
-    big.ensure(ts * 5);
-    small.ensure(ss * 9 + 2 * (size_t)s);
-    double* Yb = big.get();      // A Omega, later Qbar
+    P.ws_big.ensure(ts * 5);
+    P.ws_small.ensure(ss * 9 + 2 * (size_t)s);
+    double* Yb = P.ws_big.get();  // A Omega, later Qbar
     double* Y = Yb + ts;         // B^-1 A Omega, overwritten by Z
     double* Yk = Y + ts;         // B^-1 A Omega, kept
     double* Zb = Yk + ts;        // B Z
     double* Q = Zb + ts;
-    double* G = small.get();
+    double* G = P.ws_small.get();
     double* Ri = G + ss;
     double* Wm = Ri + ss;
     double* Zm = Wm + ss;
@@ -351,7 +347,7 @@ int lowrank_eig_single(Problem& P, int mode, int s, const double* omega, int ldo
     double* tmp = S + ss;
     double* g = tmp + ss;
     double* lam = g + s;
-    DenseWork dw;
+    DenseWork& dw = P.dw;
     P.hessian(mode, s, omega, ldo, Yb, n, st);       // Ybar = A Omega
     P.prior_solve(s, Yb, n, Y, n, st);                // Y = B^-1 Ybar
     dev_copy(c, n, s, Y, n, Yk, n);
@@ -392,19 +388,18 @@ int prior_variance(Problem& P, int s, const double* omega, int ldo, double* diag
     Ctx* c = P.ctx;
     const int n = P.n;
     const size_t ts = (size_t)n * s, ss = (size_t)s * s;
-    DBuf<double> big, small;
-    big.ensure(ts * 4);
-    small.ensure(ss * 4 + s);
-    double* Y = big.get();
+    P.ws_big.ensure(ts * 4);
+    P.ws_small.ensure(ss * 4 + s);
+    double* Y = P.ws_big.get();
     double* Zb = Y + ts;
     double* Q = Zb + ts;
     double* Vb = Q + ts;
-    double* G = small.get();
+    double* G = P.ws_small.get();
     double* Ri = G + ss;
     double* T = Ri + ss;
     double* S = T + ss;
     double* mu = S + ss;
-    DenseWork dw;
+    DenseWork& dw = P.dw;
     P.prior_solve(s, omega, ldo, Y, n, st);                   // Y = R^-1 Omega (B = I)
     Problem* const pp = &P;
     const int rc = precholqr(&pp, 1, dw, s, Y, Zb, Q, G, Ri, /*b_identity=*/true);
@@ -423,9 +418,8 @@ int prior_variance(Problem& P, int s, const double* omega, int ldo, double* diag
 void posterior_variance(Problem& P, const double* prior_diag, int k, const double* lambda_host, const double* V,
                         int ldv, double* diag) {
     Ctx* c = P.ctx;
-    DBuf<double> small;
-    small.ensure(2 * (size_t)std::max(k, 1));
-    double* lam = small.get();
+    P.ws_small.ensure(2 * (size_t)std::max(k, 1));
+    double* lam = P.ws_small.get();
     double* w = lam + std::max(k, 1);
     if (k > 0) {
         HINV_HIP(hipMemcpyAsync(lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
@@ -442,18 +436,17 @@ void posterior_sample(Problem& P, const double* m_map, int k, const double* lamb
                       int ldo, SolveStats* st) {
     Ctx* c = P.ctx;
     const int n = P.n;
-    DBuf<double> Wk, small;
     // x = K_A^-1 C_M eta (zero-mean prior draws)
     P.prior_sample(ns, eta, ldeta, out, ldo, false, st);
     if (k > 0) {
-        Wk.ensure((size_t)n * k);
-        small.ensure((size_t)k * ns + 2 * (size_t)k);
-        double* C = small.get();
+        P.ws_big.ensure((size_t)n * k);
+        P.ws_small.ensure((size_t)k * ns + 2 * (size_t)k);
+        double* Wk = P.ws_big.get();
+        double* C = P.ws_small.get();
         double* lam = C + (size_t)k * ns;
         double* sc = lam + k;
-        P.prior_apply(k, V, ldv, Wk.get(), n);                 // W = R V
-        DenseWork dw;
-        gram(c, dw, n, k, ns, Wk.get(), n, out, ldo, C, k);     // W^T x = V^T R x
+        P.prior_apply(k, V, ldv, Wk, n);                       // W = R V
+        gram(c, P.dw, n, k, ns, Wk, n, out, ldo, C, k);         // W^T x = V^T R x
         HINV_HIP(hipMemcpyAsync(lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
         k_post_scale<<<ceil_div(k, 256), 256, 0, c->stream>>>(k, lam, sc);
         HINV_LAUNCH_CHECK();

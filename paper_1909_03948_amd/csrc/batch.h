@@ -35,6 +35,7 @@ class Batch {
         std::vector<long long> ver;  // linearization applied per member (-1: none)
         std::unique_ptr<Hierarchy> HA, HK;
         DBuf<double> a, b, c;  // stacked n x (members x cap) work blocks
+        DBuf<double> blocks;   // the double pass's three stacked n x (members x s) blocks
         int cap = 0;
     };
     void sync(Group& g);
@@ -44,6 +45,8 @@ class Batch {
     void group_hessian(Group& g, int mode, int nrhs, const std::vector<const double*>& mh,
                        const std::vector<double*>& out, SolveStats* st);
 
+    DBuf<double> small_;  // s x s matrices of the double pass, every member of a group
+    DenseWork dw_;
     std::vector<Problem*> P_;
     std::vector<std::unique_ptr<Group>> G_;
     int precision_, max_iter_;

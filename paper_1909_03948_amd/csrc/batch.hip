@@ -101,23 +101,21 @@ int Batch::lowrank_eig(int mode, int tprod, int s, const double* const* omega, i
     size_t most = 0;  // members of the largest group
     for (auto& gp : G_) most = std::max(most, gp->mem.size());
     const size_t ss = (size_t)s * s;
-    DBuf<double> small;
-    small.ensure(most * (4 * ss + s));
-    double* G = small.get();
+    small_.ensure(most * (4 * ss + s));
+    double* G = small_.get();
     double* Ri = G + most * ss;
     double* T = Ri + most * ss;
     double* S = T + most * ss;
     double* lam = S + most * ss;
-    DenseWork dw;
+    DenseWork& dw = dw_;
     int status = HINV_OK;
     for (auto& gp : G_) {
         Group& g = *gp;
         const int ni = (int)g.mem.size(), n = g.n, nc = ni * s;
         // three stacked blocks of s columns per member: W, Y, Zb; the Hessian
         // action uses g.a/g.b/g.c internally, so these live apart
-        DBuf<double> blocks;
-        blocks.ensure((size_t)3 * n * nc);
-        double* W = blocks.get();
+        g.blocks.ensure((size_t)3 * n * nc);
+        double* W = g.blocks.get();
         double* Y = W + (size_t)n * nc;
         double* Zb = Y + (size_t)n * nc;
         auto at = [&](double* base, int j) { return base + (size_t)j * s * n; };

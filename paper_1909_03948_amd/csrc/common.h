@@ -39,27 +39,46 @@ struct Error {
 #define HINV_LAUNCH_CHECK() HINV_HIP(hipGetLastError())
 
 // -------------------------------------------------------- device buffers ---
+struct Ctx;
+
+// The context whose entry point is running on this thread: device buffers
+// created meanwhile take their memory from its allocator.
+inline thread_local Ctx* tl_ctx = nullptr;
+struct CtxScope {
+    Ctx* prev;
+    explicit CtxScope(Ctx* c) : prev(tl_ctx) { tl_ctx = c; }
+    ~CtxScope() { tl_ctx = prev; }
+    CtxScope(const CtxScope&) = delete;
+    CtxScope& operator=(const CtxScope&) = delete;
+};
+
+// Device memory of `owner` (its allocator callback, else hipMalloc; owner may
+// be null: hipMalloc), and its stream-ordered return (defined below Ctx).
+void* dev_alloc(Ctx* owner, size_t bytes);
+void dev_free(Ctx* owner, void* p, size_t bytes);
+
 template <typename T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
+    Ctx* owner = nullptr;  // context whose allocator provided p
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() { release(); }
     void release() {
-        // work queued on any stream may still use the buffer
-        if (p) (void)hipDeviceSynchronize();
-        if (p) (void)hipFree(p);
+        if (p) dev_free(owner, p, n * sizeof(T));
         p = nullptr;
         n = 0;
+        owner = nullptr;
     }
     // (Re)allocates to hold at least cnt elements; contents are not kept.
     void ensure(size_t cnt) {
         if (cnt <= n && p) return;
         release();
         if (cnt == 0) return;
-        HINV_HIP(hipMalloc(&p, cnt * sizeof(T)));
+        owner = tl_ctx;
+        p = static_cast<T*>(dev_alloc(owner, cnt * sizeof(T)));
         n = cnt;
     }
     T* get() const { return p; }
@@ -114,6 +133,11 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    // caller-supplied device allocator (declared before every buffer of the
+    // context, so it outlives them); has_alloc = false: hipMalloc / hipFree
+    hinv_allocator alloc{};
+    bool has_alloc = false;
+    long long allocations = 0;  // device allocations made for this context
     DBuf<double> red;  // reduction scratch of the vector helpers
     double* host_red = nullptr;  // pinned landing buffer of their results (kHostRed doubles)
     static constexpr int kHostRed = 4096;
@@ -124,6 +148,39 @@ struct Ctx {
     ~Ctx() {
         if (host_red) (void)hipHostFree(host_red);
     }
+};
+
+inline void* dev_alloc(Ctx* owner, size_t bytes) {
+    void* p = nullptr;
+    if (owner && owner->has_alloc) {
+        p = owner->alloc.alloc(bytes, owner->stream, owner->alloc.user);
+        if (!p) fail(HINV_ENOMEM, "allocator callback returned no memory for " + std::to_string(bytes) + " bytes");
+    } else {
+        HINV_HIP(hipMalloc(&p, bytes));
+    }
+    if (owner) ++owner->allocations;
+    return p;
+}
+
+inline void dev_free(Ctx* owner, void* p, size_t bytes) {
+    if (owner && owner->has_alloc) {
+        // stream-ordered: work already queued on the stream may still use p
+        owner->alloc.free(p, bytes, owner->stream, owner->alloc.user);
+        return;
+    }
+    // library-owned memory: let the context's stream finish with it first (a
+    // full Hessian action's internal stream joins that stream before returning)
+    (void)hipStreamSynchronize(owner ? owner->stream : nullptr);
+    (void)hipFree(p);
+}
+
+// Scratch for split-K partial products and the small dense factorizations.
+struct DenseWork {
+    DBuf<double> part;
+    DBuf<double> shift;  // per-matrix diagonal shifts
+    DBuf<double> tmp;    // block products of the blocked triangular inverse
+    DBuf<double> rot;    // recorded Jacobi rotations (large s)
+    DBuf<int> flag;
 };
 
 // Kernel classes of the timer (values of HINV_KCLASS_* in the public header).

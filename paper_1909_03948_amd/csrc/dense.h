@@ -7,15 +7,6 @@
 
 namespace hinv {
 
-// Scratch for split-K partial products.
-struct DenseWork {
-    DBuf<double> part;
-    DBuf<double> shift;  // per-matrix diagonal shifts
-    DBuf<double> tmp;    // block products of the blocked triangular inverse
-    DBuf<double> rot;    // recorded Jacobi rotations (large s)
-    DBuf<int> flag;
-};
-
 // C (s1 x s2, column-major, ldc) = X^T Y with X: n x s1 (ldx), Y: n x s2 (ldy).
 // bf16: inputs rounded to BF16, products accumulated in FP32 per K-chunk and
 // the chunks summed in FP64 in a fixed order.

@@ -119,9 +119,8 @@ void state_solve_fcg(Problem& P, Cnn* cnn, const double* b, double* x, double rt
     double* cv = P.scratch(4, 1);
     double* Acv = P.scratch(5, 1);
     // the last mt directions p_j and q_j = A p_j (ring buffer)
-    DBuf<double> hist_buf;
-    hist_buf.ensure((size_t)2 * mt * n);
-    double* Pd = hist_buf.get();
+    P.ws_fcg.ensure((size_t)2 * mt * n);
+    double* Pd = P.ws_fcg.get();
     double* Qd = Pd + (size_t)mt * n;
     std::vector<double> pqs(mt, 0.0);
     const dim3 g1(ceil_div(n, kBlock), 1);

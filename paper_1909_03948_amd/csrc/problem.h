@@ -77,6 +77,12 @@ class Problem {
     // A(m_lin) rebuilt in HA if a solve at another parameter replaced it
     void ensure_lin_hierarchy();
 
+    // Workspaces of the algorithm drivers (Newton-CG, eigensolvers, samples,
+    // variance, flexible CG): grown to the largest call, kept until the
+    // problem is destroyed, so repeated calls of one shape allocate nothing.
+    DBuf<double> ws_newton, ws_scal, ws_big, ws_small, ws_fcg;
+    DenseWork dw;
+
   private:
     static constexpr int kScratch = 10;
     // second stream (default priority) on which a full Hessian action computes

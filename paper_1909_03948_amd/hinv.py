@@ -9,7 +9,6 @@ dimension ld = tensor.stride(0)).  The library must be built first
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 
 import numpy as np
@@ -72,6 +71,46 @@ class NewtonInfo(C.Structure):
                     solves=self.solves.as_dict())
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """hinv_allocator: device memory callbacks of a context."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device memory for the library's workspaces from PyTorch's caching
+    allocator, on the stream the library names (stream-ordered reuse).
+    Counts the allocations and frees it serves."""
+
+    def __init__(self, device=0):
+        import torch
+        self.device = device
+        self.allocs = 0
+        self.frees = 0
+        self.live_bytes = 0
+
+        def alloc(nbytes, stream, _user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:  # out of memory: the library reports HINV_ENOMEM
+                return None
+            self.allocs += 1
+            self.live_bytes += int(nbytes)
+            return p
+
+        def free(ptr, nbytes, _stream, _user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+            self.frees += 1
+            self.live_bytes -= int(nbytes)
+
+        # the callback objects must live as long as the context
+        self._alloc, self._free = _ALLOC_FN(alloc), _FREE_FN(free)
+        self.struct = Allocator(self._alloc, self._free, None)
+
+
 EXPORTS = [
     "hinv_ctx_create", "hinv_ctx_destroy", "hinv_ctx_set_stream", "hinv_last_error",
     "hinv_status_string", "hinv_problem_create", "hinv_problem_destroy", "hinv_problem_size",
@@ -107,7 +146,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     DP = C.POINTER(C.c_double)
     FP = C.POINTER(C.c_float)
     sig = {
-        "hinv_ctx_create": [I, V, C.POINTER(P)],
+        "hinv_ctx_create": [I, V, C.POINTER(Allocator), C.POINTER(P)],
         "hinv_ctx_destroy": [P],
         "hinv_ctx_set_stream": [P, V],
         "hinv_last_error": [P],
@@ -180,6 +219,12 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _same(*counts):
+    """Every multivector of a call has the same number of columns."""
+    if len(set(counts)) != 1:
+        raise ValueError(f"column counts differ: {counts}")
+
+
 def _vec(t, n):
     """Pointer of a vector of at least n entries (a 1-D tensor or one packed row)."""
     if t.dim() != 1 and not (t.dim() == 2 and t.shape[0] == 1):
@@ -203,13 +248,21 @@ def _cols(t, n):
 
 
 class Context:
-    def __init__(self, device: int = 0, stream=None):
+    """hinv_ctx on a device and stream (default: torch's current stream).
+    allocator: "torch" (default: workspaces come from PyTorch's caching
+    allocator), a TorchAllocator, or None (the library's hipMalloc)."""
+
+    def __init__(self, device: int = 0, stream=None, allocator="torch"):
         import torch
         self.lib = load()
         if stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
+        if allocator == "torch":
+            allocator = TorchAllocator(device)
+        self.allocator = allocator
         h = C.c_void_p()
-        rc = self.lib.hinv_ctx_create(device, C.c_void_p(stream), C.byref(h))
+        ap = C.byref(allocator.struct) if allocator is not None else None
+        rc = self.lib.hinv_ctx_create(device, C.c_void_p(stream), ap, C.byref(h))
         if rc != HINV_OK:
             raise HinvError(rc, self.lib.hinv_last_error(None).decode())
         self.h = h
@@ -290,37 +343,41 @@ class Problem:
 
     def forward(self, m, u):
         info = SolveInfo()
-        rc = self._check(self.lib.hinv_forward(self.h, _ptr(m), _ptr(u), C.byref(info)))
+        rc = self._check(self.lib.hinv_forward(self.h, _vec(m, self.n), _vec(u, self.n), C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
     def cost(self, m, u):
         mis, reg = C.c_double(), C.c_double()
-        self._check(self.lib.hinv_cost(self.h, _ptr(m), _ptr(u), C.byref(mis), C.byref(reg)), allow=())
+        self._check(self.lib.hinv_cost(self.h, _vec(m, self.n), _vec(u, self.n), C.byref(mis), C.byref(reg)),
+                    allow=())
         return mis.value, reg.value
 
     def observe(self, u, Bu):
-        self._check(self.lib.hinv_observe(self.h, _ptr(u), _ptr(Bu)), allow=())
+        self._check(self.lib.hinv_observe(self.h, _vec(u, self.n), _vec(Bu, self.q)), allow=())
 
     def gradient(self, m, u, p, g):
         info = SolveInfo()
-        rc = self._check(self.lib.hinv_gradient(self.h, _ptr(m), _ptr(u), _ptr(p), _ptr(g), C.byref(info)))
+        rc = self._check(self.lib.hinv_gradient(self.h, _vec(m, self.n), _vec(u, self.n), _vec(p, self.n),
+                                                _vec(g, self.n), C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
     def linearize(self, m, u, p):
-        self._check(self.lib.hinv_linearize(self.h, _ptr(m), _ptr(u), _ptr(p)), allow=())
+        self._check(self.lib.hinv_linearize(self.h, _vec(m, self.n), _vec(u, self.n), _vec(p, self.n)),
+                    allow=())
 
     def inc_forward(self, mhat, uhat):
         pm, nc, ldm = _cols(mhat, self.n)
         pu, nc2, ldu = _cols(uhat, self.n)
-        assert nc == nc2
+        _same(nc, nc2)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_inc_forward(self.h, nc, pm, ldm, pu, ldu, C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
     def inc_adjoint(self, mhat, uhat, phat, gauss_newton=False):
         pm, nc, ldm = _cols(mhat, self.n)
-        pu, _, ldu = _cols(uhat, self.n)
-        pp, _, ldp = _cols(phat, self.n)
+        pu, nc2, ldu = _cols(uhat, self.n)
+        pp, nc3, ldp = _cols(phat, self.n)
+        _same(nc, nc2, nc3)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_inc_adjoint(self.h, nc, int(gauss_newton), pm, ldm, pu, ldu,
                                                    pp, ldp, C.byref(info)))
@@ -329,32 +386,36 @@ class Problem:
     def hessian_apply(self, mode, mhat, out):
         pm, nc, ldm = _cols(mhat, self.n)
         po, nc2, ldo = _cols(out, self.n)
-        assert nc == nc2
+        _same(nc, nc2)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_hessian_apply(self.h, mode, nc, pm, ldm, po, ldo, C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
     def prior_apply(self, x, y):
         px, nc, ldx = _cols(x, self.n)
-        py, _, ldy = _cols(y, self.n)
+        py, nc2, ldy = _cols(y, self.n)
+        _same(nc, nc2)
         self._check(self.lib.hinv_prior_apply(self.h, nc, px, ldx, py, ldy), allow=())
 
     def prior_apply_noalloc(self, x, y):
         """y = R x through the entry point that allocates nothing."""
         px, nc, ldx = _cols(x, self.n)
-        py, _, ldy = _cols(y, self.n)
+        py, nc2, ldy = _cols(y, self.n)
+        _same(nc, nc2)
         self._check(self.lib.hinv_prior_apply_noalloc(self.h, nc, px, ldx, py, ldy), allow=())
 
     def prior_solve(self, x, y):
         px, nc, ldx = _cols(x, self.n)
-        py, _, ldy = _cols(y, self.n)
+        py, nc2, ldy = _cols(y, self.n)
+        _same(nc, nc2)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_prior_solve(self.h, nc, px, ldx, py, ldy, C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
     def prior_sample(self, eta, out):
         pe, ns, lde = _cols(eta, 6 * self.N * self.N)
-        po, _, ldo = _cols(out, self.n)
+        po, ns2, ldo = _cols(out, self.n)
+        _same(ns, ns2)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_prior_sample(self.h, ns, pe, lde, po, ldo, C.byref(info)))
         return info.as_dict() | {"rc": rc}
@@ -369,26 +430,29 @@ class Problem:
                           max_backtrack=max_backtrack, c_armijo=c_armijo, max_cg=max_cg,
                           gn_iters=int(gn_iters))
         info = NewtonInfo()
-        rc = self.lib.hinv_map_newton(self.h, None if m0 is None else _ptr(m0), _ptr(m_map),
+        rc = self.lib.hinv_map_newton(self.h, None if m0 is None else _vec(m0, self.n), _vec(m_map, self.n),
                                       C.byref(opts), C.byref(info))
         self._check(rc, allow=(HINV_ENOCONV, HINV_ESTATE))
         return info.as_dict() | {"rc": rc}
 
     def state_apply(self, x, y):
         px, nc, ldx = _cols(x, self.n)
-        py, _, ldy = _cols(y, self.n)
+        py, nc2, ldy = _cols(y, self.n)
+        _same(nc, nc2)
         self._check(self.lib.hinv_state_apply(self.h, nc, px, ldx, py, ldy), allow=())
 
     def state_solve(self, b, x):
         pb, nc, ldb = _cols(b, self.n)
-        px, _, ldx = _cols(x, self.n)
+        px, nc2, ldx = _cols(x, self.n)
+        _same(nc, nc2)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_state_solve(self.h, nc, pb, ldb, px, ldx, C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
     def state_solve_fcg(self, b, x, net=None, rtol=1e-10, max_iter=200, truncation=1):
         info = FcgInfo()
-        rc = self._check(self.lib.hinv_state_solve_fcg(self.h, None if net is None else net.h, _ptr(b), _ptr(x),
+        rc = self._check(self.lib.hinv_state_solve_fcg(self.h, None if net is None else net.h, _vec(b, self.n),
+                                                       _vec(x, self.n),
                                                        rtol, max_iter, truncation, C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
@@ -404,7 +468,8 @@ class Problem:
     def lowrank_eig(self, omega, k, V, mode=HESS_MISFIT, tprod=TPROD_FP64):
         po, s, ldo = _cols(omega, self.n)
         pv, kv, ldv = _cols(V, self.n)
-        assert kv >= k
+        if not 1 <= k <= min(s, kv):
+            raise ValueError("need 1 <= k <= number of probe vectors and of V's columns")
         lam = (C.c_double * k)()
         info = SolveInfo()
         rc = self._check(self.lib.hinv_lowrank_eig(self.h, mode, tprod, s, po, ldo, k, lam, pv, ldv,
@@ -447,11 +512,14 @@ class Problem:
     def posterior_sample(self, m_map, lam, V, eta, out):
         k = len(lam)
         lam_arr = (C.c_double * max(k, 1))(*[float(x) for x in lam])
-        pv, _, ldv = _cols(V, self.n)
+        pv, kv, ldv = _cols(V, self.n)
+        if kv < k:
+            raise ValueError("V has fewer columns than eigenvalues")
         pe, ns, lde = _cols(eta, 6 * self.N * self.N)
-        po, _, ldo = _cols(out, self.n)
+        po, ns2, ldo = _cols(out, self.n)
+        _same(ns, ns2)
         info = SolveInfo()
-        rc = self._check(self.lib.hinv_posterior_sample(self.h, _ptr(m_map), k, lam_arr, pv, ldv, ns,
+        rc = self._check(self.lib.hinv_posterior_sample(self.h, _vec(m_map, self.n), k, lam_arr, pv, ldv, ns,
                                                         pe, lde, po, ldo, C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
@@ -611,6 +679,3 @@ class Batch:
                                                          lam, self._ptrs(Vs, k), C.byref(info)))
         return np.array(lam[:]).reshape(len(self.problems), k), info.as_dict() | {"rc": rc}
 
-
-def default_beta(gamma, delta):
-    return math.sqrt(gamma * delta) / 1.42

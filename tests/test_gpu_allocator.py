@@ -1,0 +1,89 @@
+"""Device memory through the caller's allocator (hinv_allocator, C ABI).
+
+A context created with PyTorch's caching allocator gets every workspace from
+it: after one call of each shape, repeated Hessian actions (one column and a
+batch), Newton-CG solves, double passes and posterior samples allocate
+nothing more and give the same results bit for bit, equal to those of a
+context on the library's own hipMalloc to the solves' tolerance.
+Destroying the problem returns its buffers.
+"""
+import numpy as np
+import pytest
+
+import synth
+from cases import instance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hv = pytest.importorskip("paper_1909_03948_amd.hinv")
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def run_calls(gp, prob, m, n):
+    """One round of the calls whose workspaces must persist; returns their outputs."""
+    out = {}
+    u, p, g = dev(np.zeros(n)), dev(np.zeros(n)), dev(np.zeros(n))
+    gp.forward(dev(m), u)
+    gp.gradient(dev(m), u, p, g)
+    gp.linearize(dev(m), u, p)
+    for nc in (1, 9):
+        mh = dev(synth.test_vectors(n, nc, seed=40 + nc))
+        o = dev(np.zeros((nc, n)))
+        gp.hessian_apply(hv.HESS_FULL, mh, o)
+        out[f"h{nc}"] = o
+    mm = dev(np.zeros(n))
+    info = gp.map_newton(mm, rel_tol=1e-6)
+    out["map"] = mm
+    out["newton_iters"] = info["iterations"]
+    k, s = 10, 16
+    V = dev(np.zeros((k, n)))
+    lam, _ = gp.lowrank_eig(dev(synth.omega(n, s)), k, V, mode=hv.HESS_GN_MISFIT)
+    out["lam"] = torch.as_tensor(lam)
+    eta = dev(synth.white_noise(prob.N, 3, stream=synth.STREAM_POST))
+    smp = dev(np.zeros((3, n)))
+    gp.posterior_sample(mm, lam, V, eta, smp)
+    out["samples"] = smp
+    torch.cuda.synchronize()
+    return out
+
+
+def test_torch_allocator_serves_every_workspace_once():
+    prob, m_true, obs = instance(32, 100)
+    n = prob.n
+    m = prob.m_pr + 0.3 * synth.smooth_field(32)
+    alloc = hv.TorchAllocator(0)
+    ctx = hv.Context(0, allocator=alloc)
+    gp = hv.Problem(ctx, 32, prob.gamma, prob.delta, obs_xy=obs, d_obs=prob.d, sigma=prob.sigma,
+                    beta=prob.beta, precision=hv.PREC_AUTO)
+    first = run_calls(gp, prob, m, n)
+    a0 = alloc.allocs
+    print(f"[gpu-alloc] after the first round: {a0} allocations, {alloc.live_bytes / 2**20:.1f} MiB live",
+          flush=True)
+    assert a0 > 0
+    for _ in range(2):
+        again = run_calls(gp, prob, m, n)
+    print(f"[gpu-alloc] after two more rounds: {alloc.allocs} allocations", flush=True)
+    assert alloc.allocs == a0
+    # the library's own hipMalloc gives bit-identical results
+    ctx2 = hv.Context(0, allocator=None)
+    gp2 = hv.Problem(ctx2, 32, prob.gamma, prob.delta, obs_xy=obs, d_obs=prob.d, sigma=prob.sigma,
+                     beta=prob.beta, precision=hv.PREC_AUTO)
+    ref = run_calls(gp2, prob, m, n)
+    for key in ("h1", "h9", "map", "lam", "samples"):
+        # same problem, same launch shapes: bit for bit
+        assert torch.equal(again[key], first[key]), key
+        # another problem may get other launch shapes from the tuner (other
+        # reduction orders): equal to the solves' tolerance
+        a, b = again[key].double(), ref[key].double()
+        e = float((a - b).norm() / b.norm())
+        print(f"[gpu-alloc] {key}: torch allocator vs hipMalloc rel {e:.1e}", flush=True)
+        assert e <= 1e-8, key
+    live = alloc.live_bytes
+    frees = alloc.frees
+    gp.close()
+    assert alloc.frees > frees and alloc.live_bytes < live
+    print(f"[gpu-alloc] problem destroyed: {alloc.frees - frees} buffers returned", flush=True)
