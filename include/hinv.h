@@ -46,7 +46,10 @@
  *   - Iterative solves stop at |b - A x|_2 / |b|_2 <= rtol per column, the
  *     residual evaluated in FP64.  A column that does not get there within the
  *     iteration limit makes the call return HINV_ENOCONV; outputs are still
- *     written and info->status holds the same code.
+ *     written and info->status holds the same code.  A NaN or infinite
+ *     residual (a non-finite entry in an input, or one met during the solve)
+ *     stops its column at once: the call returns HINV_ENOCONV and
+ *     info->max_relres is NaN.
  */
 #ifndef HINV_H
 #define HINV_H

@@ -31,7 +31,7 @@ struct SolveStats {
         iterations += o.iterations;
         refinements += o.refinements;
         fallbacks += o.fallbacks;
-        max_relres = o.max_relres > max_relres ? o.max_relres : max_relres;
+        if (o.max_relres != o.max_relres || o.max_relres > max_relres) max_relres = o.max_relres;  // NaN stays
         converged = converged && o.converged;
     }
 };

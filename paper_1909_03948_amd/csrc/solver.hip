@@ -20,6 +20,7 @@
 //     r = b - A x in FP64, inner PCG in FP64 or FP32 on r / |r|, x += |r| d,
 //     until |r| <= rtol |b| per column.
 #include <algorithm>
+#include <limits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -298,7 +299,9 @@ __global__ void k_ir_finalize(int first, const double* __restrict__ partial, int
     ColState& c = st[blockIdx.x];
     if (first) c.obb = s;
     c.rr = s;
-    const bool a = s > rtol * rtol * c.obb && s > 0.0;
+    // a non-finite residual (NaN or infinity in b, or met in the solve) stops
+    // the column; the host reports it as not converged
+    const bool a = isfinite(s) && isfinite(c.obb) && s > rtol * rtol * c.obb && s > 0.0;
     oact[blockIdx.x] = a ? 1 : 0;
     colnorm[blockIdx.x] = sqrt(s);
     if (a) {
@@ -1345,17 +1348,25 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     // final relative residuals: the column states read with the last flags
     // (no refinement step ran after that read)
     double worst = 0.0;
+    bool finite = true;
     for (int c = 0; c < nc; ++c) {
-        const double rel = hst[c].obb > 0 ? std::sqrt(hst[c].rr / hst[c].obb) : 0.0;
+        const double rr = hst[c].rr, obb = hst[c].obb;
+        if (!std::isfinite(rr) || !std::isfinite(obb)) {
+            finite = false;
+            continue;
+        }
+        const double rel = obb > 0 ? std::sqrt(rr / obb) : 0.0;
         worst = rel > worst ? rel : worst;
     }
+    if (!finite) worst = std::numeric_limits<double>::quiet_NaN();
     if (stats) {
         stats->solves += nc;
         stats->iterations += iters;
         stats->refinements += outer;
         stats->fallbacks += fallbacks;
-        stats->max_relres = worst > stats->max_relres ? worst : stats->max_relres;
-        stats->converged = stats->converged && converged;
+        // a NaN stays NaN for the rest of the call's accumulated solves
+        if (std::isnan(worst) || worst > stats->max_relres) stats->max_relres = worst;
+        stats->converged = stats->converged && converged && finite;
     }
 }
 
