@@ -97,7 +97,7 @@ def setup_gpu(cfg, precision, seed=synth.MASTER_SEED):
 
 
 def run_step(prob, omega, cfg, tprod, m_map, V, samples=None, mode=None):
-    """MAP point, rank-k eigenpairs and (if ``samples`` = (count, chunk, eta, out))
+    """MAP point, rank-k eigenpairs and (if ``samples``, an (ns, n) tensor) ns
     posterior samples drawn with device white noise."""
     import torch
     from paper_1909_03948_amd import hinv as hv
@@ -108,11 +108,8 @@ def run_step(prob, omega, cfg, tprod, m_map, V, samples=None, mode=None):
     lam, einfo = prob.lowrank_eig(omega, cfg["k"], V, mode=mode, tprod=tprod)
     t2 = time.perf_counter()
     if samples is not None:
-        count, chunk, eta, out = samples
-        for first in range(0, count, chunk):
-            c = min(chunk, count - first)
-            prob.white_noise(synth.MASTER_SEED, synth.STREAM_POST, first, eta[:c])
-            prob.posterior_sample(m_map, lam, V, eta[:c], out[:c])
+        # noise drawn on the device by the counter-based generator, chunked inside
+        prob.posterior_sample_seeded(m_map, lam, V, synth.MASTER_SEED, synth.STREAM_POST, 0, samples)
         torch.cuda.synchronize()
     t3 = time.perf_counter()
     if not ninfo["converged"]:
@@ -464,11 +461,7 @@ def main():
     V = torch.zeros((cfg["k"], n), dtype=torch.float64, device="cuda")
     samples = None
     if workload != "poisson256" and a.samples > 0:
-        chunk = min(a.samples, s)
-        N = cfg["N"]
-        samples = (a.samples, chunk,
-                   torch.zeros((chunk, 6 * N * N), dtype=torch.float64, device="cuda"),
-                   torch.zeros((chunk, n), dtype=torch.float64, device="cuda"))
+        samples = torch.zeros((a.samples, n), dtype=torch.float64, device="cuda")
     step = lambda p, tp: run_step(p, omega, cfg, tp, m_map, V, samples, hmode)
     for w in range(a.warmup):
         r = step(prob, tprod)

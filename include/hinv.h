@@ -329,6 +329,17 @@ int hinv_posterior_sample(hinv_problem* p, const double* m_map, int k, const dou
                           const double* V, int ldv, int ns, const double* eta, int ldeta,
                           double* out, int ldo, hinv_solve_info* info);
 
+/* The same samples with their white noise drawn on the device: sample j of
+ * the call is sample first + j of the counter-based stream (seed, stream) of
+ * hinv_white_noise, so any range of samples can be drawn alone and equals the
+ * corresponding columns of a larger call.  The noise is generated and used in
+ * internal chunks of up to 256 samples (6 N^2 x 256 doubles of workspace,
+ * 12.9 GB at N = 1024); R V is formed once per call.  out: device n x ns,
+ * ld ldo.  Errors as in hinv_posterior_sample. */
+int hinv_posterior_sample_seeded(hinv_problem* p, const double* m_map, int k, const double* lambda_host,
+                                 const double* V, int ldv, uint64_t seed, uint64_t stream, int64_t first, int ns,
+                                 double* out, int ldo, hinv_solve_info* info);
+
 /* ---- batches of independent inversions ------------------------------------ */
 /* Many independent problems (own mesh size N_i, prior gamma_i / delta_i / beta_i,
  * observations and linearization point) whose Hessian actions and double

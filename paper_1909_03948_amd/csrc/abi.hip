@@ -516,6 +516,25 @@ int hinv_posterior_sample(hinv_problem* p, const double* m_map, int k, const dou
     return rc != HINV_OK ? rc : conv_status(st);
 }
 
+int hinv_posterior_sample_seeded(hinv_problem* p, const double* m_map, int k, const double* lambda_host,
+                                 const double* V, int ldv, uint64_t seed, uint64_t stream, int64_t first, int ns,
+                                 double* out, int ldo, hinv_solve_info* info) {
+    if (!p) return HINV_EINVAL;
+    hinv::SolveStats st;
+    int rc = guarded(ctx_of(p), [&] {
+        const int n = p->p->n;
+        REQUIRE(k >= 0 && ns >= 0 && first >= 0 && ldv >= n && ldo >= n, "bad size");
+        REQUIRE(m_map && (k == 0 || (lambda_host && V)) && (ns == 0 || out), "null argument");
+        for (int i = 0; i < k; ++i)
+            if (!(lambda_host[i] > -1.0)) hinv::fail(HINV_ENEGEIG, "eigenvalue <= -1");
+        if (ns)
+            hinv::posterior_sample_seeded(*p->p, m_map, k, lambda_host, V, ldv, seed, stream, first, ns, out, ldo,
+                                          &st);
+    });
+    fill_info(info, st);
+    return rc != HINV_OK ? rc : conv_status(st);
+}
+
 // ------------------------------------------------------------- batches ---
 int hinv_batch_create(hinv_ctx* c, int nprob, hinv_problem* const* probs, hinv_batch** out) {
     if (!c || !out) return HINV_EINVAL;

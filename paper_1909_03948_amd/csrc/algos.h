@@ -39,6 +39,17 @@ int prior_variance(Problem& P, int s, const double* omega, int ldo, double* diag
 void posterior_variance(Problem& P, const double* prior_diag, int k, const double* lambda_host, const double* V,
                         int ldv, double* diag);
 
+// Samples per internal chunk of posterior_sample_seeded (its white noise:
+// 6 N^2 kSampleChunk doubles, 12.9 GB at N = 1024).
+constexpr int kSampleChunk = 256;
+
+// Posterior samples with their white noise drawn on the device in chunks
+// (samples first .. first + ns - 1 of the counter-based stream), R V formed
+// once per call.
+void posterior_sample_seeded(Problem& P, const double* m_map, int k, const double* lambda_host, const double* V,
+                             int ldv, uint64_t seed, uint64_t stream, long long first, int ns, double* out, int ldo,
+                             SolveStats* st);
+
 // Posterior samples through the low-rank update (Sec. 4.3.2).
 void posterior_sample(Problem& P, const double* m_map, int k, const double* lambda_host,
                       const double* V, int ldv, int ns, const double* eta, int ldeta, double* out,

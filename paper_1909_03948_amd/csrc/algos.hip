@@ -431,31 +431,79 @@ void posterior_variance(Problem& P, const double* prior_diag, int k, const doubl
 }
 
 // ------------------------------------------------------ posterior sample ---
-void posterior_sample(Problem& P, const double* m_map, int k, const double* lambda_host,
-                      const double* V, int ldv, int ns, const double* eta, int ldeta, double* out,
-                      int ldo, SolveStats* st) {
+namespace {
+
+// Device state of the low-rank update y = x - V S V^T R x shared by the
+// samples of one call: W = R V (n x k, in ws_big) and the scales
+// S = 1 - (1 + lambda)^-1/2 (k, in ws_small after the k x ns coefficients).
+struct LowRankUpdate {
+    const double* W = nullptr;
+    double* C = nullptr;
+    const double* sc = nullptr;
+};
+
+LowRankUpdate prepare_update(Problem& P, int k, const double* lambda_host, const double* V, int ldv, int ns) {
     Ctx* c = P.ctx;
     const int n = P.n;
-    // x = K_A^-1 C_M eta (zero-mean prior draws)
-    P.prior_sample(ns, eta, ldeta, out, ldo, false, st);
+    LowRankUpdate u;
+    if (k == 0) return u;
+    P.ws_big.ensure((size_t)n * k);
+    P.ws_small.ensure((size_t)k * ns + 2 * (size_t)k);
+    double* W = P.ws_big.get();
+    double* C = P.ws_small.get();
+    double* lam = C + (size_t)k * ns;
+    double* sc = lam + k;
+    P.prior_apply(k, V, ldv, W, n);  // W = R V, once for every sample of the call
+    HINV_HIP(hipMemcpyAsync(lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+    k_post_scale<<<ceil_div(k, 256), 256, 0, c->stream>>>(k, lam, sc);
+    HINV_LAUNCH_CHECK();
+    u.W = W;
+    u.C = C;
+    u.sc = sc;
+    return u;
+}
+
+// out[:, j] = m_map + x_j - V S V^T R x_j for the ns prior draws x_j in out.
+void apply_update(Problem& P, const LowRankUpdate& u, const double* m_map, int k, const double* V, int ldv,
+                  int ns, double* out, int ldo) {
+    Ctx* c = P.ctx;
+    const int n = P.n;
     if (k > 0) {
-        P.ws_big.ensure((size_t)n * k);
-        P.ws_small.ensure((size_t)k * ns + 2 * (size_t)k);
-        double* Wk = P.ws_big.get();
-        double* C = P.ws_small.get();
-        double* lam = C + (size_t)k * ns;
-        double* sc = lam + k;
-        P.prior_apply(k, V, ldv, Wk, n);                       // W = R V
-        gram(c, P.dw, n, k, ns, Wk, n, out, ldo, C, k);         // W^T x = V^T R x
-        HINV_HIP(hipMemcpyAsync(lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
-        k_post_scale<<<ceil_div(k, 256), 256, 0, c->stream>>>(k, lam, sc);
-        HINV_LAUNCH_CHECK();
-        scale_rows(c, k, ns, sc, C, k);                        // S V^T R x
-        gemm_tall(c, n, k, ns, -1.0, V, ldv, C, k, 1.0, out, ldo);  // x - V S V^T R x
+        gram(c, P.dw, n, k, ns, u.W, n, out, ldo, u.C, k);           // W^T x = V^T R x
+        scale_rows(c, k, ns, u.sc, u.C, k);                          // S V^T R x
+        gemm_tall(c, n, k, ns, -1.0, V, ldv, u.C, k, 1.0, out, ldo);  // x - V S V^T R x
     }
     k_add_vec<<<dim3(ceil_div(n, 256), ns), 256, 0, c->stream>>>(n, m_map, out, ldo);
     HINV_LAUNCH_CHECK();
-    HINV_HIP(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace
+
+void posterior_sample(Problem& P, const double* m_map, int k, const double* lambda_host,
+                      const double* V, int ldv, int ns, const double* eta, int ldeta, double* out,
+                      int ldo, SolveStats* st) {
+    // x = K_A^-1 C_M eta (zero-mean prior draws)
+    P.prior_sample(ns, eta, ldeta, out, ldo, false, st);
+    const LowRankUpdate u = prepare_update(P, k, lambda_host, V, ldv, ns);
+    apply_update(P, u, m_map, k, V, ldv, ns, out, ldo);
+    HINV_HIP(hipStreamSynchronize(P.ctx->stream));
+}
+
+void posterior_sample_seeded(Problem& P, const double* m_map, int k, const double* lambda_host, const double* V,
+                             int ldv, uint64_t seed, uint64_t stream, long long first, int ns, double* out, int ldo,
+                             SolveStats* st) {
+    const int chunk = std::min(ns, kSampleChunk);
+    const size_t L = (size_t)6 * P.N * P.N;
+    P.ws_eta.ensure(L * chunk);
+    const LowRankUpdate u = prepare_update(P, k, lambda_host, V, ldv, chunk);
+    for (int s0 = 0; s0 < ns; s0 += chunk) {
+        const int cnt = std::min(chunk, ns - s0);
+        double* o = out + (size_t)s0 * ldo;
+        P.white_noise(seed, stream, first + s0, cnt, P.ws_eta.get(), (int)L);
+        P.prior_sample(cnt, P.ws_eta.get(), (int)L, o, ldo, false, st);
+        apply_update(P, u, m_map, k, V, ldv, cnt, o, ldo);
+    }
+    HINV_HIP(hipStreamSynchronize(P.ctx->stream));
 }
 
 }  // namespace hinv

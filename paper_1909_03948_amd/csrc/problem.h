@@ -80,7 +80,7 @@ class Problem {
     // Workspaces of the algorithm drivers (Newton-CG, eigensolvers, samples,
     // variance, flexible CG): grown to the largest call, kept until the
     // problem is destroyed, so repeated calls of one shape allocate nothing.
-    DBuf<double> ws_newton, ws_scal, ws_big, ws_small, ws_fcg;
+    DBuf<double> ws_newton, ws_scal, ws_big, ws_small, ws_fcg, ws_eta;
     DenseWork dw;
 
   private:

@@ -118,7 +118,7 @@ EXPORTS = [
     "hinv_gradient", "hinv_linearize", "hinv_inc_forward", "hinv_inc_adjoint",
     "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_apply_noalloc", "hinv_prior_solve", "hinv_prior_sample",
     "hinv_map_newton", "hinv_lowrank_eig", "hinv_lowrank_eig_single", "hinv_prior_variance",
-    "hinv_posterior_variance", "hinv_posterior_sample", "hinv_ctx_kernel_timer",
+    "hinv_posterior_variance", "hinv_posterior_sample", "hinv_posterior_sample_seeded", "hinv_ctx_kernel_timer",
     "hinv_ctx_kernel_timer_read", "hinv_white_noise", "hinv_batch_create", "hinv_batch_destroy",
     "hinv_batch_hessian_apply", "hinv_batch_lowrank_eig", "hinv_state_apply", "hinv_state_solve",
     "hinv_state_solve_fcg", "hinv_cnn_create", "hinv_cnn_destroy", "hinv_cnn_param_count",
@@ -172,6 +172,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_lowrank_eig": [P, I, I, I, V, I, I, DP, V, I, C.POINTER(SolveInfo)],
         "hinv_posterior_sample": [P, V, I, DP, V, I, I, V, I, V, I, C.POINTER(SolveInfo)],
         "hinv_lowrank_eig_single": [P, I, I, V, I, I, DP, V, I, C.POINTER(SolveInfo)],
+        "hinv_posterior_sample_seeded": [P, V, I, DP, V, I, C.c_uint64, C.c_uint64, C.c_int64, I, V, I,
+                                         C.POINTER(SolveInfo)],
         "hinv_prior_variance": [P, I, V, I, V, DP, C.POINTER(SolveInfo)],
         "hinv_posterior_variance": [P, V, I, DP, V, I, V],
         "hinv_ctx_kernel_timer": [P, I, I, I],
@@ -508,6 +510,19 @@ class Problem:
         lam_arr = (C.c_double * max(k, 1))(*[float(x) for x in lam])
         self._check(self.lib.hinv_posterior_variance(self.h, _ptr(prior_diag), k, lam_arr, pv, ldv,
                                                      _ptr(diag)), allow=())
+
+    def posterior_sample_seeded(self, m_map, lam, V, seed, stream, first, out):
+        """out[j] = posterior sample first + j of the counter-based stream (seed, stream)."""
+        k = len(lam)
+        lam_arr = (C.c_double * max(k, 1))(*[float(x) for x in lam])
+        pv, kv, ldv = _cols(V, self.n)
+        if kv < k:
+            raise ValueError("V has fewer columns than eigenvalues")
+        po, ns, ldo = _cols(out, self.n)
+        info = SolveInfo()
+        rc = self._check(self.lib.hinv_posterior_sample_seeded(self.h, _vec(m_map, self.n), k, lam_arr, pv, ldv,
+                                                               seed, stream, first, ns, po, ldo, C.byref(info)))
+        return info.as_dict() | {"rc": rc}
 
     def posterior_sample(self, m_map, lam, V, eta, out):
         k = len(lam)

@@ -227,3 +227,30 @@ def test_posterior_samples_from_device_noise(ctx, map32):
     out = dev(np.zeros((ns, prob.n)))
     gp.posterior_sample(dev(m), lam, dev(V.T), eta, out)
     assert col_rel(host(out), ref) < 1e-8
+
+
+def test_seeded_posterior_samples_in_chunks(ctx, map32):
+    """hinv_posterior_sample_seeded draws its noise on the device in chunks of
+    256 samples: 300 samples (two chunks) equal the oracle's draws from the
+    same counter-based noise, and a later range drawn alone equals the
+    corresponding columns."""
+    prob, obs, m = map32
+    k, ns, first = 12, 300, 7
+    u = prob.forward(m)
+    adj = prob.adjoint(m, u)
+    Om = synth.omega(prob.n, k + 8)
+    A = lambda v: prob.hessian_apply(m, u, adj, v, model.HESS_GN_MISFIT)
+    lam, V, _ = lowrank.double_pass(A, prob.R_apply, prob.R_solve, Om.T, k)
+    eta_o = synth.philox_white_noise(32, ns, seed=5, stream=synth.STREAM_POST, first=first)
+    ref = np.array([m + lowrank.posterior_sample_update(prob.KA_solve(prob.CM @ e), V, lam, prob.R_apply)
+                    for e in eta_o])
+    gp = gpu_problem(ctx, prob, obs, hv.PREC_AUTO)
+    out = dev(np.zeros((ns, prob.n)))
+    info = gp.posterior_sample_seeded(dev(m), lam, dev(V.T), 5, synth.STREAM_POST, first, out)
+    assert info["rc"] == 0, info
+    got = host(out)
+    print(f"[gpu] seeded samples: max column rel err {col_rel(got, ref):.2e}", flush=True)
+    assert col_rel(got, ref) < 1e-8
+    part = dev(np.zeros((4, prob.n)))
+    gp.posterior_sample_seeded(dev(m), lam, dev(V.T), 5, synth.STREAM_POST, first + 260, part)
+    assert col_rel(host(part), ref[260:264]) < 1e-8
