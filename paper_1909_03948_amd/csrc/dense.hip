@@ -43,6 +43,29 @@ constexpr int kBlkWaves = 8, kBlkTiles = 8, kBlk = 128;
 // one read of Y; each wave loads its 16 columns of X for the stage's eight K
 // steps at once.  Products are accumulated in K order.
 constexpr int kGramKC = 32;   // K rows per LDS stage
+
+// XCD-aware order of the workgroups of a (per x chunks) grid: the hardware
+// hands consecutive workgroups to the eight XCDs in turn, so with the plain
+// order the `per` output blocks of one K chunk (which read the same rows of
+// X and Y) land on different XCDs and each XCD's L2 fetches those rows again.
+// Workgroup h is mapped to block b and chunk c such that the blocks of chunk
+// c run on one XCD one after another (h = 8 j + x: XCD x, its j-th
+// workgroup); the chunks beyond the last multiple of 8 keep the plain order.
+// A bijection of [0, per * chunks) onto the (block, chunk) pairs, whatever
+// the grid's shape (h is the dispatch order, x fastest).
+__device__ inline void xcd_block_chunk(int per, int chunks, int& b, int& c) {
+    const int h = blockIdx.x + gridDim.x * blockIdx.y;
+    const int full = chunks & ~7;
+    if (h < full * per) {
+        const int x = h & 7, j = h >> 3;
+        b = j % per;
+        c = (j / per) * 8 + x;
+    } else {
+        const int t = h - full * per;
+        b = t % per;
+        c = full + t / per;
+    }
+}
 constexpr int kGramLd = 144;  // LDS row stride (doubles): rows k and k + 1 fall in different bank halves
 __global__ __launch_bounds__(512) void k_gram_f64(int n, int s1, int s2, int chunk,
                                                   const double* __restrict__ X, int ldx,
@@ -50,12 +73,14 @@ __global__ __launch_bounds__(512) void k_gram_f64(int n, int s1, int s2, int chu
                                                   double* __restrict__ part) {
     __shared__ double ys[2][kGramKC * kGramLd];
     const int blocks_i = (s1 + kBlk - 1) / kBlk;
-    const int bi = blockIdx.x % blocks_i, bj = blockIdx.x / blocks_i;
+    int blk, split;
+    xcd_block_chunk(gridDim.x, gridDim.y, blk, split);
+    const int bi = blk % blocks_i, bj = blk / blocks_i;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = bi * kBlk + wave * 16 + (lane & 15);
     const bool rows_on = bi * kBlk + wave * 16 < s1;  // this wave has output rows (all waves stage Y)
     const int kr = lane >> 4;
-    const int k_begin = blockIdx.y * chunk;
+    const int k_begin = split * chunk;
     const int k_end = min(n, k_begin + chunk);
     const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
     // staging: thread t loads rows 8 (t mod 4) .. + 8 of block column t / 4
@@ -109,7 +134,7 @@ __global__ __launch_bounds__(512) void k_gram_f64(int n, int s1, int s2, int chu
         for (int v = 0; v < 4; ++v) {
             const int gi = bi * kBlk + wave * 16 + 4 * v + (lane >> 4);
             const int gj = bj * kBlk + t * 16 + (lane & 15);
-            if (gi < s1 && gj < s2) part[((size_t)blockIdx.y * s2 + gj) * s1 + gi] = acc[t][v];
+            if (gi < s1 && gj < s2) part[((size_t)split * s2 + gj) * s1 + gi] = acc[t][v];
         }
 }
 
@@ -118,12 +143,14 @@ __global__ __launch_bounds__(512) void k_gram_bf16(int n, int s1, int s2, int ch
                                                    const double* __restrict__ Y, int ldy,
                                                    double* __restrict__ part) {
     const int blocks_i = (s1 + kBlk - 1) / kBlk;
-    const int bi = blockIdx.x % blocks_i, bj = blockIdx.x / blocks_i;
+    int blk, split;
+    xcd_block_chunk(gridDim.x, gridDim.y, blk, split);
+    const int bi = blk % blocks_i, bj = blk / blocks_i;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = bi * kBlk + wave * 16 + (lane & 15);
     if (bi * kBlk + wave * 16 >= s1) return;  // no rows for this wave (no barrier below)
     const int kq = (lane >> 4) * 4;
-    const int k_begin = blockIdx.y * chunk;
+    const int k_begin = split * chunk;
     const int k_end = min(n, k_begin + chunk);
     const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
     const double* yc[kBlkTiles];
@@ -159,7 +186,7 @@ __global__ __launch_bounds__(512) void k_gram_bf16(int n, int s1, int s2, int ch
         for (int v = 0; v < 4; ++v) {
             const int gi = bi * kBlk + wave * 16 + 4 * (lane >> 4) + v;
             const int gj = bj * kBlk + t * 16 + (lane & 15);
-            if (gi < s1 && gj < s2) part[((size_t)blockIdx.y * s2 + gj) * s1 + gi] = (double)acc[t][v];
+            if (gi < s1 && gj < s2) part[((size_t)split * s2 + gj) * s1 + gi] = (double)acc[t][v];
         }
 }
 
@@ -197,9 +224,13 @@ __global__ __launch_bounds__(512) void k_gemm_tall(int n, int s, int t, double a
                                                    double beta, double* __restrict__ C, int ldc) {
     __shared__ double bsh[2][kGramKC * kGramLd];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = (blockIdx.x * kBlkWaves + wave) * 16;
+    // the column blocks of one row strip read the same rows of X: they run on
+    // one XCD one after another (grid: row strips x column blocks)
+    int cb, strip;
+    xcd_block_chunk(gridDim.y, gridDim.x, cb, strip);
+    const int r0 = (strip * kBlkWaves + wave) * 16;
     const bool rows_on = r0 < n;  // this wave has output rows (all waves stage B)
-    const int c0 = blockIdx.y * kBlk;
+    const int c0 = cb * kBlk;
     const int row = r0 + (lane & 15), kr = lane >> 4;
     const int jj = threadIdx.x >> 2, r8 = (threadIdx.x & 3) * 8;
     const bool jok = c0 + jj < t;

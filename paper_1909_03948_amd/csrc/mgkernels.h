@@ -117,6 +117,25 @@ __device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int
     return done;
 }
 
+// XCD-aware tile order.  The hardware hands consecutive workgroups to the
+// eight XCDs in turn, so in the plain order the tiles next to a tile (which
+// read its halo rows) run on other XCDs and fetch those rows into their own
+// L2 again.  Here the j-th workgroup of XCD x (dispatch index h = 8 j + x)
+// takes logical tile x P + j with P = floor(T / 8) of the T workgroups: each
+// XCD sweeps a contiguous run of tiles in row-major order (x fastest, then y,
+// then the column block), so left/right and most upper/lower halos come from
+// its own L2.  The last T - 8 P workgroups keep the plain order.  A
+// bijection of [0, T); returns the logical (x, y, z) of this workgroup.
+__device__ inline int3 xcd_tile() {
+    const int X = gridDim.x, Y = gridDim.y;
+    const int T = X * Y * gridDim.z;
+    const int h = blockIdx.x + X * (blockIdx.y + Y * blockIdx.z);
+    const int P = T >> 3;
+    const int L = h < 8 * P ? (h & 7) * P + (h >> 3) : h;
+    const int z = L / (X * Y), r = L - z * X * Y;
+    return make_int3(r % X, r / X, z);
+}
+
 // --------------------------------------------------------------- k_down ---
 // Grid: (tiles over coarse x, tiles over coarse y, column blocks).  Coarse
 // tile [I0, I0+kTC) x [J0, J0+kTC) needs the fine residual on
@@ -136,15 +155,16 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
     __shared__ T tc[NN], te[NN], tn[NN], tdv[NN], tg[NE ? NN : 1];
     const TileStencil<T> ts{tc, te, tn, tg, tdv};
     const int N = op_.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
-    const int I0 = blockIdx.x * kTC, J0 = blockIdx.y * kTC;
+    const int3 tb = xcd_tile();
+    const int I0 = tb.x * kTC, J0 = tb.y * kTC;
     const int I1 = min(I0 + kTC - 1, Nc), J1 = min(J0 + kTC - 1, Nc);
     const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // global coordinates of local (0, 0)
     const T inv_theta = (T)cc.inv_theta, cA = (T)cc.cA, cB = (T)cc.cB;
     const int own_i1 = min(2 * I1 + 1, N), own_j1 = min(2 * J1 + 1, N);
     constexpr int E = (NN + 255) / 256;  // tile elements per thread
     const void* staged = nullptr;  // the staged rows belong to this instance
-    const int c_end = min(nc, (int)(blockIdx.z + 1) * cb);
-    for (int col = blockIdx.z * cb; col < c_end; ++col) {
+    const int c_end = min(nc, (tb.z + 1) * cb);
+    for (int col = tb.z * cb; col < c_end; ++col) {
         if (act && !act[col]) continue;
         const auto& op = op_.at(col);  // operator of the instance owning this column
         const TB* bcol = b + (size_t)col * ld;
@@ -163,7 +183,7 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
             stage_stencil<TW, 256>(op, ts, ox, oy);
             staged = instance_key(op);
         }
-        if (check && column_done(red, col, st, act, blockIdx.x == 0 && blockIdx.y == 0)) continue;
+        if (check && column_done(red, col, st, act, tb.x == 0 && tb.y == 0)) continue;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int t = threadIdx.x + 256 * e;
@@ -238,14 +258,15 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
     __shared__ T tc[NN], te[NN], tn[NN], tdv[NN], tg[NE ? NN : 1];
     const TileStencil<T> ts{tc, te, tn, tg, tdv};
     const int N = op_.N, N1 = N + 1, Nc1 = N / 2 + 1;
-    const int i0 = blockIdx.x * kTF, j0 = blockIdx.y * kTF;
+    const int3 tb = xcd_tile();
+    const int i0 = tb.x * kTF, j0 = tb.y * kTF;
     const int i1 = min(i0 + kTF - 1, N), j1 = min(j0 + kTF - 1, N);
     const int ox = i0 - 2, oy = j0 - 2;
     const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
     constexpr int E = (NN + 255) / 256;  // tile elements per thread
     const void* staged = nullptr;
-    const int c_end = min(nc, (int)(blockIdx.z + 1) * cb);
-    for (int col = blockIdx.z * cb; col < c_end; ++col) {
+    const int c_end = min(nc, (tb.z + 1) * cb);
+    for (int col = tb.z * cb; col < c_end; ++col) {
         if (act && !act[col]) continue;
         const auto& op = op_.at(col);  // operator of the instance owning this column
         const TB* bcol = b + (size_t)col * ld;
@@ -309,7 +330,7 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
         }
         if (rv) {
             const double sm = group_sum(dot);
-            if (threadIdx.x == 0) red.rz[(size_t)col * red.stride + blockIdx.y * gridDim.x + blockIdx.x] = sm;
+            if (threadIdx.x == 0) red.rz[(size_t)col * red.stride + tb.y * gridDim.x + tb.x] = sm;
         }
     }
 }
@@ -691,16 +712,19 @@ __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict_
                                                     T* __restrict__ p_new, T* __restrict__ q, int ld,
                                                     const int* __restrict__ act, ColState* __restrict__ st,
                                                     PcgRed red) {
-    const int col = blockIdx.y;
+    // node blocks in XCD-aware order: the rows above and below a block's
+    // nodes belong to blocks on the same XCD
+    const int3 tb = xcd_tile();
+    const int col = tb.y, bx = tb.x;
     const auto& op = op_.at(col);  // operator of the instance owning this column
     if (!act[col]) return;
     const int N = op.N, N1 = N + 1, n = N1 * N1;
-    const bool need_rz = !FIRST || blockIdx.x == 0;  // uniform in the workgroup
+    const bool need_rz = !FIRST || bx == 0;  // uniform in the workgroup
     double srz = need_rz ? partial_first(red.rz, col, red.stride, red.nrz) : 0.0;
     const double rz_old = FIRST ? 1.0 : st[col].rz;
     const T* zc = z + (size_t)col * ld;
     const T* pc = p_old + (size_t)col * ld;
-    const int k0 = blockIdx.x * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
+    const int k0 = bx * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
     const double inv_n1 = 1.0 / N1;
     using Form = ApplyForm<std::decay_t<decltype(op)>>;
     using OpT = typename Form::type;
@@ -764,7 +788,7 @@ __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict_
     if (need_rz) {
         const double rz = share_total(srz);
         if (!FIRST) beta = (T)(rz / rz_old);
-        if (blockIdx.x == 0 && threadIdx.x == 0) st[col].rz_new = rz;
+        if (bx == 0 && threadIdx.x == 0) st[col].rz_new = rz;
     }
     double dot = 0.0;
 #pragma unroll
@@ -779,7 +803,7 @@ __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict_
         }
     }
     const double sm = group_sum(dot);
-    if (threadIdx.x == 0) red.pq[(size_t)col * red.stride + blockIdx.x] = sm;
+    if (threadIdx.x == 0) red.pq[(size_t)col * red.stride + bx] = sm;
 }
 
 // alpha = (r^T z) / (p^T q); x += alpha p, r -= alpha q; partials of r^T r.
