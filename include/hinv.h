@@ -200,6 +200,19 @@ int hinv_ctx_kernel_timer(hinv_ctx* ctx, int kclass, int enable, int period);
 int hinv_ctx_kernel_timer_read(hinv_ctx* ctx, int kclass, int* timed, long* launches_total,
                                double* total_ms, double* total_work);
 
+/* ---- launch-shape tuner ---------------------------------------------------- */
+/* The first solve of each (operator, mesh size, column count, precision) times
+ * candidate launch shapes on its own right-hand sides -- tile sizes of the
+ * V-cycle kernels, the RHS-block width (columns one V-cycle workgroup sweeps:
+ * 1, 2, 4, 8, 16) and node blocks per workgroup of the PCG vector kernels --
+ * and keeps the fastest for the hierarchy's lifetime.  With the environment
+ * variable HINV_TUNE_CACHE naming a file, the choices are appended to it as
+ * JSON lines keyed by device architecture, compute units, operator kind, mesh
+ * size, stacked instances, columns and precision, and later processes take
+ * them from there instead of timing again (HINV_AUTOTUNE=0 disables both).
+ * Returns the process-wide counts of shapes timed and taken from the file. */
+int hinv_tuner_counts(long long* timed, long long* cached);
+
 /* ---- problem -------------------------------------------------------------- */
 /* Builds mesh data, prior multigrid hierarchy and observation operator.
  * Observation points are located in their cells on the device; the host only

@@ -148,6 +148,15 @@ const char* hinv_last_error(const hinv_ctx* c) {
     return c->c.err.c_str();
 }
 
+int hinv_tuner_counts(long long* timed, long long* cached) {
+    if (!timed || !cached) return HINV_EINVAL;
+    long t = 0, c = 0;
+    hinv::tuner_counts(&t, &c);
+    *timed = t;
+    *cached = c;
+    return HINV_OK;
+}
+
 int hinv_ctx_kernel_timer(hinv_ctx* c, int kclass, int enable, int period) {
     if (!c) return HINV_EINVAL;
     return guarded(&c->c, [&] {

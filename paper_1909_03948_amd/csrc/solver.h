@@ -22,6 +22,9 @@ struct Level {
     DBuf<float> wE32, wN32, dinv32;
 };
 
+// Launch shapes tuned by timing and taken from the persistent cache, process-wide.
+void tuner_counts(long* timed, long* cached);
+
 struct SolveStats {
     int solves = 0, iterations = 0, refinements = 0, fallbacks = 0;
     double max_relres = 0.0;

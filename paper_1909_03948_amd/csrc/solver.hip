@@ -25,6 +25,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "mgkernels.h"
@@ -680,6 +682,62 @@ int Hierarchy::min_per() const {
     return 16;
 }
 
+// ---- persistent tuner cache ------------------------------------------------
+// Launch shapes the tuner picked, kept in the file named by HINV_TUNE_CACHE
+// (JSON lines, one object a shape, appended as shapes are tuned; the last
+// line of a key wins), so that later processes on the same kind of device
+// reuse them instead of timing again.  Key: device architecture and compute
+// unit count, operator kind, mesh size, stacked instances, columns, solve
+// precision, and the version of the kernels' launch-shape rules.
+namespace {
+constexpr int kTuneVersion = 2;
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+struct TuneRec {
+    std::string arch;
+    int kind, N, ninst, nc, fp32, small, small_max, per, cb;
+};
+std::vector<TuneRec> g_tune;
+long g_tune_timed = 0, g_tune_cached = 0;
+
+std::string device_tag(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    return std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("HINV_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512], arch[128];
+    while (std::fgets(line, sizeof line, f)) {
+        TuneRec r;
+        int ver = 0;
+        if (std::sscanf(line,
+                        "{\"version\": %d, \"device\": \"%127[^\"]\", \"kind\": %d, \"N\": %d, "
+                        "\"instances\": %d, \"columns\": %d, \"fp32\": %d, \"small\": %d, "
+                        "\"small_max\": %d, \"per\": %d, \"cb\": %d}",
+                        &ver, arch, &r.kind, &r.N, &r.ninst, &r.nc, &r.fp32, &r.small, &r.small_max, &r.per,
+                        &r.cb) == 11 &&
+            ver == kTuneVersion && r.per >= 1 && r.per <= 16 && r.cb >= 1 && r.cb <= 64) {
+            r.arch = arch;
+            g_tune.push_back(r);
+        }
+    }
+    std::fclose(f);
+}
+}  // namespace
+
+void tuner_counts(long* timed, long* cached) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    *timed = g_tune_timed;
+    *cached = g_tune_cached;
+}
+
 // Times the candidate shapes on the call's own right-hand sides (w.r is set):
 // the V-cycle with each tile choice, then the PCG apply kernel in its general
 // form (beta from the r^T z partials) with 1, 4, 8 and 16 node blocks per
@@ -708,6 +766,23 @@ void Hierarchy::tune_shape(int nc) {
     }
     const char* env = std::getenv("HINV_AUTOTUNE");
     if (env && env[0] == '0') return;
+    const std::string arch = device_tag(ctx_->device);
+    const int fp32 = sizeof(T) == 4;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+            if (it->arch == arch && it->kind == (int)kind_ && it->N == N_ && it->ninst == ninst_ && it->nc == nc &&
+                it->fp32 == fp32 && it->per >= min_per()) {
+                shape_.small = it->small != 0;
+                shape_.small_max = it->small_max;
+                shape_.per = it->per;
+                shape_.cb = it->cb;
+                tuned_.push_back({key, shape_});
+                ++g_tune_cached;
+                return;
+            }
+    }
     hipStream_t s = ctx_->stream;
     launch_stream_ = s;
     hipEvent_t e0, e1;
@@ -737,8 +812,9 @@ void Hierarchy::tune_shape(int nc) {
     // to back, the V-cycle's vectors stay in cache and favour large tiles
     // (less halo), while inside PCG iterations they do not.
     const int N0 = lev_[0]->N;
+    // cb: the RHS-block width, columns one workgroup of the V-cycle kernels sweeps
     for (int small_max : {-1, 0, 128, 256})
-        for (int cb : {1, 2, 4, 8}) {
+        for (int cb : {1, 2, 4, 8, 16}) {
             if (nc < kSmallTileCols && (cb > 1 || small_max >= 0)) continue;
             if (small_max > 0 && small_max >= N0) continue;
             shape_.small = small_max < 0;
@@ -785,6 +861,23 @@ void Hierarchy::tune_shape(int nc) {
     (void)hipEventDestroy(e1);
     shape_ = best;
     tuned_.push_back({key, best});
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        ++g_tune_timed;
+        TuneRec r{arch, (int)kind_, N_, ninst_, nc, fp32, best.small ? 1 : 0, best.small_max, best.per, best.cb};
+        g_tune.push_back(r);
+        const char* path = std::getenv("HINV_TUNE_CACHE");
+        if (path && *path)
+            if (std::FILE* f = std::fopen(path, "a")) {
+                std::fprintf(f,
+                             "{\"version\": %d, \"device\": \"%s\", \"kind\": %d, \"N\": %d, \"instances\": %d, "
+                             "\"columns\": %d, \"fp32\": %d, \"small\": %d, \"small_max\": %d, \"per\": %d, "
+                             "\"cb\": %d}\n",
+                             kTuneVersion, r.arch.c_str(), r.kind, r.N, r.ninst, r.nc, r.fp32, r.small, r.small_max,
+                             r.per, r.cb);
+                std::fclose(f);
+            }
+    }
     if (std::getenv("HINV_TRACE_SHAPES"))
         std::fprintf(stderr, "[hinv] launch shape N=%d nc=%d %s: %s tiles, %d columns per V-cycle workgroup, "
                      "%d node blocks per workgroup\n", N_, nc, sizeof(T) == 8 ? "fp64" : "fp32",

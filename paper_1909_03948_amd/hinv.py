@@ -119,7 +119,7 @@ EXPORTS = [
     "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_apply_noalloc", "hinv_prior_solve", "hinv_prior_sample",
     "hinv_map_newton", "hinv_lowrank_eig", "hinv_lowrank_eig_single", "hinv_prior_variance",
     "hinv_posterior_variance", "hinv_posterior_sample", "hinv_posterior_sample_seeded", "hinv_ctx_kernel_timer",
-    "hinv_ctx_kernel_timer_read", "hinv_white_noise", "hinv_batch_create", "hinv_batch_destroy",
+    "hinv_ctx_kernel_timer_read", "hinv_tuner_counts", "hinv_white_noise", "hinv_batch_create", "hinv_batch_destroy",
     "hinv_batch_hessian_apply", "hinv_batch_lowrank_eig", "hinv_state_apply", "hinv_state_solve",
     "hinv_state_solve_fcg", "hinv_cnn_create", "hinv_cnn_destroy", "hinv_cnn_param_count",
     "hinv_cnn_set_params", "hinv_cnn_get_params", "hinv_cnn_forward", "hinv_cnn_gradient",
@@ -178,6 +178,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_posterior_variance": [P, V, I, DP, V, I, V],
         "hinv_ctx_kernel_timer": [P, I, I, I],
         "hinv_white_noise": [P, C.c_uint64, C.c_uint64, C.c_int64, I, V, I],
+        "hinv_tuner_counts": [C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)],
         "hinv_ctx_kernel_timer_read": [P, I, C.POINTER(I), C.POINTER(C.c_long), DP, DP],
         "hinv_batch_create": [P, I, C.POINTER(P), C.POINTER(P)],
         "hinv_batch_destroy": [P],
@@ -203,6 +204,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         f.restype = C.c_char_p if name in ("hinv_last_error", "hinv_status_string") else C.c_int
     _lib = lib
     return lib
+
+
+def tuner_counts():
+    """(launch shapes timed, launch shapes taken from the HINV_TUNE_CACHE file) in this process."""
+    lib = load()
+    t, c = C.c_longlong(), C.c_longlong()
+    lib.hinv_tuner_counts(C.byref(t), C.byref(c))
+    return t.value, c.value
 
 
 class HinvError(RuntimeError):

@@ -179,3 +179,54 @@ def test_batch_hessian_stacked_large(batch_large, shape, monkeypatch):
             assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
             for i in range(len(insts)):
                 assert col_rel(host(outs[i]), refs[i]) < 1e-8, (i, mode, rep)
+
+
+# the uneven batch's largest sizes: two stacked N = 256 members and one at N = 512
+SPECS_C5 = [(256, 300, 0.12, 0.9, 31), (512, 500, 0.07, 1.4, 32), (256, 150, 0.18, 1.8, 33)]
+
+
+@pytest.fixture(scope="module")
+def batch_c5():
+    print("[gpu-batch] N = 256 / 512 setup", flush=True)
+    ctx = hv.Context(0)
+    insts, gps = [], []
+    for N, q, g, d, seed in SPECS_C5:
+        prob, _, obs = instance(N, q, g, d, seed)
+        m = prob.m_pr + 0.6 * synth.smooth_field(N, seed=seed)
+        u = prob.forward(m)
+        p = prob.adjoint(m, u)
+        gp = hv.Problem(ctx, N, g, d, obs_xy=obs, d_obs=prob.d, sigma=prob.sigma,
+                        m_prior=prob.m_pr[0], beta=prob.beta, precision=hv.PREC_AUTO, rtol=1e-10)
+        gp.linearize(dev(m), dev(u), dev(p))
+        insts.append((prob, m, u, p))
+        gps.append(gp)
+    return ctx, insts, gps
+
+
+def test_batch_hessian_and_double_pass_at_256_and_512(batch_c5):
+    """The uneven batch's largest members: stacked N = 256 pair and N = 512,
+    Hessian actions (FP32 refinement, 4 columns per member) within 1e-8 and
+    double-pass eigenvalues within 1e-8 lambda_1 of the oracle."""
+    ctx, insts, gps = batch_c5
+    b = hv.Batch(ctx, gps)
+    nrhs = 4
+    mh = [synth.test_vectors(prob.n, nrhs, stream=80 + i) for i, (prob, *_) in enumerate(insts)]
+    outs = [dev(np.zeros((nrhs, prob.n))) for prob, *_ in insts]
+    info = b.hessian_apply(hv.HESS_GN_MISFIT, [dev(x) for x in mh], outs)
+    assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
+    for i, (prob, m, u, p) in enumerate(insts):
+        ref = np.array([prob.hessian_apply(m, u, p, v, model.HESS_GN_MISFIT) for v in mh[i][:2]])
+        e = col_rel(host(outs[i])[:2], ref)
+        print(f"[gpu-batch] N={prob.N} Hessian action rel {e:.2e}", flush=True)
+        assert e < 1e-8, i
+    k, s = 8, 12
+    oms = [synth.omega(prob.n, s, seed=300 + i) for i, (prob, *_) in enumerate(insts)]
+    Vs = [dev(np.zeros((k, prob.n))) for prob, *_ in insts]
+    lam, info = b.lowrank_eig([dev(o) for o in oms], k, Vs, mode=hv.HESS_GN_MISFIT)
+    assert info["rc"] == 0, info
+    for i, (prob, m, u, p) in enumerate(insts):
+        A = lambda v: prob.hessian_apply(m, u, p, v, model.HESS_GN_MISFIT)
+        lam_o, _, _ = lowrank.double_pass(A, prob.R_apply, prob.R_solve, oms[i].T, k)
+        err = np.max(np.abs(lam[i] - lam_o)) / abs(lam_o[0])
+        print(f"[gpu-batch] N={prob.N}: lambda_1 {lam_o[0]:.3e} max err {err:.2e}", flush=True)
+        assert err <= 1e-8, i
