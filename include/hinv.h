@@ -105,6 +105,16 @@ typedef struct {
     int    precision;  /* HINV_PREC_* for the state-equation solves */
     double rtol;       /* relative residual of every solve, e.g. 1e-10 */
     int    max_iter;   /* iteration cap per solve (0: 200) */
+    /* Anisotropic tensor of the prior's diffusion term, -gamma div(Theta grad m)
+     * (Sec. 5.1, Eq. eq:PoissonPrior): Theta = theta1 v v^T + theta2 w w^T with
+     * v = (sin alpha, cos alpha), w = (cos alpha, -sin alpha) -- the s.p.d.
+     * tensor with the eigenvalues and directions the section states (the matrix
+     * printed there is not s.p.d. for its own parameters).  theta1 <= 0 selects
+     * Theta = I.  The mesh needs 0 <= Theta_12 <= min(Theta_11, Theta_22) (its
+     * diagonals lie along the principal direction; HINV_EINVAL otherwise), which
+     * holds for theta1 >= theta2 > 0 and 0 <= alpha <= pi/2, e.g. the paper's
+     * theta = (2, 0.5), alpha = pi/4. */
+    double theta1, theta2, alpha;
 } hinv_problem_desc;
 
 typedef struct {

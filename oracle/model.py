@@ -262,8 +262,11 @@ def make_instance(cfg: dict, seed: int, eta_truth: np.ndarray, obs_xy: np.ndarra
     sigma = 1% of max|u_true| (Sec. 5.1 observation model).
 
     Returns (problem, m_true, u_true).  The random inputs come from ``synth``.
+    cfg["theta"] = (theta1, theta2, alpha), if present, gives the prior's
+    anisotropic tensor (mesh.anisotropic_theta).
     """
-    prob = Problem(cfg["N"], cfg["gamma"], cfg["delta"], cfg["m_prior"], beta=beta,
+    Theta = msh.anisotropic_theta(*cfg["theta"]) if cfg.get("theta") else None
+    prob = Problem(cfg["N"], cfg["gamma"], cfg["delta"], cfg["m_prior"], beta=beta, Theta=Theta,
                    obs_xy=obs_xy)
     m_true = prob.prior_sample(eta_truth)
     u_true = prob.forward(m_true)

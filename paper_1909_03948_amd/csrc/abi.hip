@@ -209,6 +209,21 @@ int hinv_problem_create(hinv_ctx* c, const hinv_problem_desc* d, hinv_problem** 
                 "N must be a power of two in [4, 8192]");
         REQUIRE(d->gamma > 0 && d->delta > 0, "gamma and delta must be positive");
         REQUIRE(std::isnan(d->beta) || d->beta >= 0, "beta must be >= 0 or NaN");
+        if (d->theta1 > 0.0) {
+            REQUIRE(d->theta2 > 0.0 && std::isfinite(d->theta1) && std::isfinite(d->theta2) &&
+                        std::isfinite(d->alpha),
+                    "Theta needs theta1, theta2 > 0 and a finite alpha");
+            // the smoother's spectral bound needs K_Theta's couplings <= 0:
+            // 0 <= t12 <= min(t11, t22) (the mesh diagonal along Theta's
+            // principal direction)
+            const double sa = std::sin(d->alpha), ca = std::cos(d->alpha);
+            const double t11 = d->theta1 * sa * sa + d->theta2 * ca * ca;
+            const double t12 = (d->theta1 - d->theta2) * sa * ca;
+            const double t22 = d->theta1 * ca * ca + d->theta2 * sa * sa;
+            const double eps = 1e-12 * (t11 + t22);
+            REQUIRE(t12 >= -eps && t12 <= std::min(t11, t22) + eps,
+                    "Theta must satisfy 0 <= Theta_12 <= min(Theta_11, Theta_22) on this mesh");
+        }
         REQUIRE(d->q >= 0, "q must be >= 0");
         REQUIRE(d->q == 0 || d->obs_xy, "obs_xy is required when q > 0");
         REQUIRE(d->sigma > 0, "sigma must be positive");

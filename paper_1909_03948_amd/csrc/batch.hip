@@ -34,7 +34,7 @@ Batch::Batch(Ctx* ctx, int nprob, Problem* const* probs) {
         std::vector<PriorParams> pps(ni);
         for (int j = 0; j < ni; ++j) {
             const Problem* p = P_[g->mem[j]];
-            pps[j] = PriorParams{p->gamma, p->delta, p->beta};
+            pps[j] = p->prior;
         }
         g->HA = std::make_unique<Hierarchy>(ctx, kOpState, g->N, pps[0], ni);
         g->HK = std::make_unique<Hierarchy>(ctx, kOpPrior, g->N, pps[0], ni, pps.data());

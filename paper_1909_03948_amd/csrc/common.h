@@ -233,10 +233,12 @@ __host__ __device__ inline int knode(int i, int j, int N) { return j * (N + 1) +
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
-// Prior operator K_A = gamma K + delta M + beta M_boundary on a level with N
-// cells (isotropic Theta = I).  All coefficients are constants of the mesh.
+// Prior operator K_A = gamma K_Theta + delta M + beta M_boundary on a level
+// with N cells; Theta = [[t11, t12], [t12, t22]] (identity by default).  All
+// coefficients are constants of the mesh.
 struct PriorParams {
     double gamma, delta, beta;
+    double t11 = 1.0, t12 = 0.0, t22 = 1.0;
 };
 
 }  // namespace hinv

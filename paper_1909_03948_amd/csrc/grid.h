@@ -268,13 +268,20 @@ template <typename T>
 __device__ inline KARow<T> ka_row(const OpKARef<T>& o, int c) { return o.rows[c]; }
 
 // Prior operator of a level: the 9 row classes from the element matrices.
-//   K (unit stiffness): an axis edge adjacent to t triangles has weight t/2;
-//   M: |T|/12 (1 + delta_vw) per triangle, |T| = h^2/2, so an axis edge adjacent
-//      to t triangles couples with t h^2/24, the diagonal edge (2 triangles) with
+//   K_Theta: per triangle |T| grad(phi_v) . Theta grad(phi_w) with |T| = h^2/2;
+//      on both triangles of a cell the gradients are (-1, 0), (1, -1), (0, 1)
+//      / h (lower) and (0, -1), (-1, 1), (1, 0) / h (upper), so every
+//      triangle couples its horizontal edge with (t12 - t11)/2, its vertical
+//      edge with (t12 - t22)/2 and its diagonal edge with -t12/2 (Theta = I:
+//      axis edges -1/2 per triangle, diagonal 0), and the rows sum to zero;
+//   M: |T|/12 (1 + delta_vw) per triangle, so an axis edge adjacent to t
+//      triangles couples with t h^2/24, the diagonal edge (2 triangles) with
 //      h^2/12 and the diagonal is (number of incident triangles) h^2/12;
 //   M_boundary: (h/6) [[2,1],[1,2]] per boundary edge.
 template <typename T>
-inline OpKA<T> make_prior_op(int N, double g, double dl, double bt) {
+inline OpKA<T> make_prior_op(int N, const PriorParams& pp) {
+    const double g = pp.gamma, dl = pp.delta, bt = pp.beta;
+    const double kh = 0.5 * (pp.t12 - pp.t11), kv = 0.5 * (pp.t12 - pp.t22), kd = -pp.t12;  // K couplings
     OpKA<T> o;
     o.N = N;
     const double h = 1.0 / N, h2 = h * h;
@@ -287,20 +294,23 @@ inline OpKA<T> make_prior_op(int N, double g, double dl, double bt) {
             const int iin = (i < N) + (i > 0);  // triangles on a vertical edge at column i
             const int bh = (j == 0 || j == N);  // horizontal edges at row j are boundary edges
             const int bv = (i == 0 || i == N);  // vertical edges at column i are boundary edges
-            const double eh = -g * 0.5 * jin + dl * jin * h2 / 24.0 + bt * (h / 6.0) * bh;
-            const double ev = -g * 0.5 * iin + dl * iin * h2 / 24.0 + bt * (h / 6.0) * bv;
-            const int ntri = 2 * (hasE && hasN) + (hasW && hasN) + (hasE && hasS) + 2 * (hasW && hasS);
+            const int ne = hasE && hasN, sw = hasW && hasS;  // diagonal edges (2 triangles each)
+            const double eh = g * kh * jin + dl * jin * h2 / 24.0 + bt * (h / 6.0) * bh;
+            const double ev = g * kv * iin + dl * iin * h2 / 24.0 + bt * (h / 6.0) * bv;
+            const double ed = g * kd + dl * h2 / 12.0;
+            const int ntri = 2 * ne + (hasW && hasN) + (hasE && hasS) + 2 * sw;
             const int nbe = bh * (hasE + hasW) + bv * (hasN + hasS);
-            const double c = g * 0.5 * (jin * (hasE + hasW) + iin * (hasN + hasS)) +
-                             dl * ntri * h2 / 12.0 + bt * (h / 3.0) * nbe;
+            // K_Theta's diagonal: minus its couplings (zero row sums)
+            const double cK = -(kh * jin * (hasE + hasW) + kv * iin * (hasN + hasS) + kd * (ne + sw));
+            const double c = g * cK + dl * ntri * h2 / 12.0 + bt * (h / 3.0) * nbe;
             KARow<T>& r = o.rows[ci + 3 * cj];
             r.c = (T)c;
             r.e = (T)(hasE ? eh : 0.0);
             r.w = (T)(hasW ? eh : 0.0);
             r.n = (T)(hasN ? ev : 0.0);
             r.s = (T)(hasS ? ev : 0.0);
-            r.ne = (T)((hasE && hasN) ? dl * h2 / 12.0 : 0.0);
-            r.sw = (T)((hasW && hasS) ? dl * h2 / 12.0 : 0.0);
+            r.ne = (T)(ne ? ed : 0.0);
+            r.sw = (T)(sw ? ed : 0.0);
             r.dinv = (T)(1.0 / c);
         }
     return o;

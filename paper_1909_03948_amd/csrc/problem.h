@@ -19,6 +19,7 @@ class Problem {
     Ctx* ctx;
     int N, n, q;
     double gamma, delta, beta, m_prior, sigma;
+    PriorParams prior;  // gamma, delta, beta and the tensor Theta of K_A
     int precision;
     double rtol;
     int max_iter;

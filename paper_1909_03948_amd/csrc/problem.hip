@@ -499,9 +499,10 @@ __global__ void k_white_noise(int L, uint64_t seed, uint64_t stream, long long f
     box_muller(c[2], c[3], e[2], e[3]);
 }
 
-OpKA<double> prior_op(int N, double g, double dl, double bt) {
-    return make_prior_op<double>(N, g, dl, bt);
-}
+OpKA<double> prior_op(int N, const PriorParams& pp) { return make_prior_op<double>(N, pp); }
+
+// The mass matrix as a prior operator (gamma = 0, delta = 1, beta = 0).
+OpKA<double> mass_op(int N) { return make_prior_op<double>(N, PriorParams{0.0, 1.0, 0.0}); }
 
 // Chebyshev iteration count for M: error factor 2 (1/3)^K <= 2e-15.
 constexpr int kMassCheb = 32;
@@ -569,6 +570,15 @@ Problem::Problem(Ctx* c, const hinv_problem_desc& desc)
       rtol(desc.rtol), max_iter(desc.max_iter > 0 ? desc.max_iter : 200) {
     beta = std::isnan(desc.beta) ? std::sqrt(gamma * delta) / 1.42 : desc.beta;
     PriorParams pp{gamma, delta, beta};
+    if (desc.theta1 > 0.0) {
+        // Theta = theta1 v v^T + theta2 w w^T, v = (sin a, cos a), w = (cos a, -sin a):
+        // the s.p.d. tensor with the eigenvalues and directions Sec. 5.1 states
+        const double sa = std::sin(desc.alpha), ca = std::cos(desc.alpha);
+        pp.t11 = desc.theta1 * sa * sa + desc.theta2 * ca * ca;
+        pp.t12 = (desc.theta1 - desc.theta2) * sa * ca;
+        pp.t22 = desc.theta1 * ca * ca + desc.theta2 * sa * sa;
+    }
+    prior = pp;
     HA = std::make_unique<Hierarchy>(ctx, kOpState, N, pp);
     HK = std::make_unique<Hierarchy>(ctx, kOpPrior, N, pp);
     m_lin.ensure(n);
@@ -820,7 +830,7 @@ void Problem::hessian(int mode, int nc, const double* mhat, int ldm, double* out
 }
 
 void Problem::mass_apply(int nc, const double* x, int ldx, double* y, int ldy) {
-    k_prior_apply<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(prior_op(N, 0.0, 1.0, 0.0), x, ldx, y,
+    k_prior_apply<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(mass_op(N), x, ldx, y,
                                                             ldy, 0.0);
     HINV_LAUNCH_CHECK();
 }
@@ -829,7 +839,7 @@ void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx, h
     // Chebyshev iteration (no inner products) on the Jacobi-scaled consistent
     // mass matrix, whose spectrum lies in [1/2, 2] for P1 triangles.
     if (!s) s = ctx->stream;
-    const OpKA<double> M = prior_op(N, 0.0, 1.0, 0.0);
+    const OpKA<double> M = mass_op(N);
     const double lo = 0.5, hi = 2.0;
     const double theta = 0.5 * (hi + lo), dl = 0.5 * (hi - lo), sigma1 = theta / dl;
     const size_t blk = (size_t)n * nc;
@@ -862,7 +872,7 @@ void Problem::mass_solve(int nc, const double* b, int ldb, double* x, int ldx, h
 void Problem::prior_apply(int nc, const double* x, int ldx, double* y, int ldy, bool accumulate,
                           hipStream_t s, double* ws) {
     if (!s) s = ctx->stream;
-    const OpKA<double> K = prior_op(N, gamma, delta, beta);
+    const OpKA<double> K = prior_op(N, prior);
     const size_t blk = (size_t)n * nc;
     double* t1 = ws ? ws : scratch(3, nc);
     double* t2 = ws ? ws + blk : scratch(4, nc);

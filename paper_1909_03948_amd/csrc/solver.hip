@@ -390,7 +390,7 @@ OpA<T> make_opA(const Level& L, int inst = 0) {
 
 template <typename T>
 OpKA<T> make_opKA(int N, const PriorParams& pp) {
-    return make_prior_op<T>(N, pp.gamma, pp.delta, pp.beta);
+    return make_prior_op<T>(N, pp);
 }
 
 }  // namespace
@@ -455,8 +455,8 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp, int ninst,
             for (size_t l = 0; l < nl; ++l)
                 for (size_t i = 0; i < ni; ++i) {
                     const PriorParams& q = inst_pp_[i];
-                    const OpKA<double> o64 = make_prior_op<double>(lev_[l]->N, q.gamma, q.delta, q.beta);
-                    const OpKA<float> o32 = make_prior_op<float>(lev_[l]->N, q.gamma, q.delta, q.beta);
+                    const OpKA<double> o64 = make_prior_op<double>(lev_[l]->N, q);
+                    const OpKA<float> o32 = make_prior_op<float>(lev_[l]->N, q);
                     for (int c = 0; c < 9; ++c) {
                         h64[(l * ni + i) * 9 + c] = o64.rows[c];
                         h32[(l * ni + i) * 9 + c] = o32.rows[c];
@@ -491,7 +491,7 @@ void Hierarchy::build_coarse(int inst) {
         k_coarse_matrix<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(make_opA<double>(L, inst), c64);
     else
         k_coarse_matrix<<<ceil_div(tot, kBlock), kBlock, 0, s>>>(
-            make_prior_op<double>(L.N, inst_pp_[inst].gamma, inst_pp_[inst].delta, inst_pp_[inst].beta), c64);
+            make_prior_op<double>(L.N, inst_pp_[inst]), c64);
     HINV_LAUNCH_CHECK();
     if (nc > kGJMaxN) fail(HINV_EINVAL, "coarse level too large for the dense inverse");
     const size_t shm = sizeof(double) * 2 * (size_t)nc * nc;

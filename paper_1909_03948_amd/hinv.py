@@ -37,7 +37,8 @@ class ProblemDesc(C.Structure):
                 ("beta", C.c_double), ("m_prior", C.c_double), ("q", C.c_int),
                 ("obs_xy", C.POINTER(C.c_double)), ("d_obs", C.POINTER(C.c_double)),
                 ("sigma", C.c_double), ("precision", C.c_int), ("rtol", C.c_double),
-                ("max_iter", C.c_int)]
+                ("max_iter", C.c_int), ("theta1", C.c_double), ("theta2", C.c_double),
+                ("alpha", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -311,7 +312,9 @@ class Problem:
     """Binding of hinv_problem; method names follow the C functions."""
 
     def __init__(self, ctx: Context, N, gamma, delta, obs_xy=None, d_obs=None, sigma=0.01,
-                 m_prior=-2.0, beta=float("nan"), precision=PREC_FP64, rtol=1e-10, max_iter=0):
+                 m_prior=-2.0, beta=float("nan"), precision=PREC_FP64, rtol=1e-10, max_iter=0,
+                 theta=None):
+        """theta: None (Theta = I) or (theta1, theta2, alpha) of the prior's anisotropic tensor."""
         self.ctx, self.lib = ctx, ctx.lib
         xy = np.ascontiguousarray(np.zeros((0, 2)) if obs_xy is None else obs_xy, dtype=np.float64)
         q = xy.shape[0]
@@ -321,7 +324,9 @@ class Problem:
         desc = ProblemDesc(N=N, gamma=gamma, delta=delta, beta=beta, m_prior=m_prior, q=q,
                            obs_xy=self._xy.ctypes.data_as(DP) if q else None,
                            d_obs=self._d.ctypes.data_as(DP) if self._d is not None else None,
-                           sigma=sigma, precision=precision, rtol=rtol, max_iter=max_iter)
+                           sigma=sigma, precision=precision, rtol=rtol, max_iter=max_iter,
+                           theta1=theta[0] if theta else 0.0, theta2=theta[1] if theta else 0.0,
+                           alpha=theta[2] if theta else 0.0)
         h = C.c_void_p()
         self._check(self.lib.hinv_problem_create(ctx.h, C.byref(desc), C.byref(h)), allow=())
         self.h = h

@@ -36,6 +36,12 @@ WORKLOADS = {
     "poisson32": dict(N=32, q=100, gamma=0.1, delta=0.5, m_prior=-2.0, k=50, p=20),
     "poisson256": dict(N=256, q=400, gamma=0.1, delta=0.5, m_prior=-2.0, k=50, p=20),
     "poisson1024": dict(N=1024, q=2000, gamma=0.05, delta=1.0, m_prior=-2.0, k=200, p=20),
+    # the paper's own Poisson setup (Sec. 5.1) on a P1 state: 64 x 64 cells
+    # (4 225 parameters), 50 observations in [0.1, 0.9] x [0.1, 0.5],
+    # anisotropic prior theta = (2, 0.5), alpha = pi/4
+    # (rank r = 30 and oversampling l = 20 as in the section's low-rank posterior)
+    "poisson64_paper": dict(N=64, q=50, gamma=0.1, delta=0.5, m_prior=-2.0, k=30, p=20,
+                            theta=(2.0, 0.5, float(np.pi / 4)), obs_box=(0.1, 0.9, 0.1, 0.5)),
 }
 
 
@@ -102,9 +108,14 @@ def philox_white_noise(N: int, ns: int, seed: int = MASTER_SEED, stream: int = S
 
 
 def obs_points(q: int, seed: int = MASTER_SEED, lo: float = 0.05,
-               hi: float = 0.95) -> np.ndarray:
-    """(q, 2) locations drawn uniformly in [lo, hi]^2."""
-    return _gen(seed, STREAM_OBS_POINTS).uniform(lo, hi, size=(q, 2))
+               hi: float = 0.95, box=None) -> np.ndarray:
+    """(q, 2) locations drawn uniformly in [lo, hi]^2, or in the rectangle
+    box = (x0, x1, y0, y1) when given."""
+    if box is None:
+        return _gen(seed, STREAM_OBS_POINTS).uniform(lo, hi, size=(q, 2))
+    u = _gen(seed, STREAM_OBS_POINTS).uniform(0.0, 1.0, size=(q, 2))
+    x0, x1, y0, y1 = box
+    return np.column_stack([x0 + (x1 - x0) * u[:, 0], y0 + (y1 - y0) * u[:, 1]])
 
 
 def obs_noise(q: int, seed: int = MASTER_SEED) -> np.ndarray:
