@@ -261,7 +261,13 @@ int hinv_inc_forward(hinv_problem* p, int nrhs, const double* mhat, int ldm,
 int hinv_inc_adjoint(hinv_problem* p, int nrhs, int gauss_newton, const double* mhat, int ldm,
                      const double* uhat, int ldu, double* phat, int ldp, hinv_solve_info* info);
 /* out[:,c] = H mhat[:,c] in the given HINV_HESS_* mode (Eq. eq:incrementals3).
- * All nrhs columns go through one batched multi-right-hand-side solve. */
+ * All nrhs columns go through one batched multi-right-hand-side solve.  The
+ * incremental adjoint's right-hand side carries uhat, so when the solves run
+ * in FP32 refinement (HINV_PREC_FP32_IR, or HINV_PREC_AUTO with 8 or more
+ * columns) the incremental forward solve aims at rtol / 10 (a column whose
+ * FP64 residual stops falling above that but at or below rtol is accepted);
+ * the adjoint solve, and every solve of hinv_inc_forward / hinv_inc_adjoint,
+ * run to rtol. */
 int hinv_hessian_apply(hinv_problem* p, int mode, int nrhs, const double* mhat, int ldm,
                        double* out, int ldo, hinv_solve_info* info);
 

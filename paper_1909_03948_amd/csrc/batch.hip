@@ -72,7 +72,8 @@ void Batch::group_hessian(Group& g, int mode, int nrhs, const std::vector<const 
     auto blk = [&](const DBuf<double>& b, int j) { return b.get() + (size_t)j * nrhs * n; };
     // incremental forward: one solve for the columns of every member
     for (int j = 0; j < ni; ++j) P_[g.mem[j]]->inc_forward_rhs(nrhs, mh[j], n, blk(g.a, j), n);
-    g.HA->solve(nc, g.a.get(), n, g.b.get(), n, precision_, rtol_, max_iter_, st);
+    g.HA->solve(nc, g.a.get(), n, g.b.get(), n, precision_, chained_first_rtol(precision_, nc, rtol_), max_iter_,
+                st, rtol_);
     // incremental adjoint
     for (int j = 0; j < ni; ++j)
         P_[g.mem[j]]->inc_adjoint_rhs(nrhs, gn, mh[j], n, blk(g.b, j), n, blk(g.a, j), n);

@@ -212,6 +212,21 @@ constexpr int kCoarseMaxN = 8;  // coarsest multigrid level has N_c <= 8
 constexpr int kMaxVecPartials = 520;  // partial sums per column of the PCG vector kernels
 constexpr int kAutoBatch = 8;   // HINV_PREC_AUTO switches to FP32 refinement from this many columns
 
+// A Hessian action chains two solves: the incremental adjoint's right-hand
+// side carries u-hat, so the first solve's error reaches the output through
+// the observation and W_uu terms.  Solved by FP32 refinement, the first solve
+// runs to a tenth of the tolerance: at 1025^2 nodes and 1e-10 the action's
+// relative error was 1.3e-8 with both solves at 1e-10 and 8.8e-10 with the
+// first at 1e-11 (tightening the second instead changed nothing), while FP64
+// PCG, which overshoots the tolerance by up to one iteration's reduction,
+// gave 3.8e-10 without it.  The problem's tolerance stays the acceptance
+// bar: a column whose FP64 residual cannot go lower (its rounding floor, seen
+// near 3e-11 for some R-orthonormal directions at that size) ends there.
+inline double chained_first_rtol(int precision, int nc, double rtol) {
+    const bool ir = precision == HINV_PREC_FP32_IR || (precision == HINV_PREC_AUTO && nc >= kAutoBatch);
+    return ir ? 0.1 * rtol : rtol;
+}
+
 // Timer class of a launch of `nc` columns (the batched class from kAutoBatch up).
 inline int kclass_for(int base, int nc) {
     if (nc < kAutoBatch) return base;

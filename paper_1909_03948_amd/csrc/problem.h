@@ -46,7 +46,9 @@ class Problem {
     void cost(const double* m, const double* u, double* misfit, double* reg);
     void gradient(const double* m, const double* u, double* p, double* g, SolveStats* st);
     void linearize(const double* m, const double* u, const double* p);
-    void inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st);
+    // tol <= 0: the problem's tolerance
+    void inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st,
+                     double tol = 0.0);
     void inc_adjoint(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
                      double* phat, int ldp, SolveStats* st);
     void hessian(int mode, int nc, const double* mhat, int ldm, double* out, int ldo,

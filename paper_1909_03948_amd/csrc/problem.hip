@@ -792,10 +792,12 @@ Problem::~Problem() {
     }
 }
 
-void Problem::inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st) {
+void Problem::inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st,
+                          double tol) {
     double* rhs = scratch(0, nc);
     inc_forward_rhs(nc, mhat, ldm, rhs, n);
-    HA->solve(nc, rhs, n, uhat, ldu, precision, rtol, max_iter, st);
+    // a tighter goal still accepts the problem's tolerance at the rounding floor
+    HA->solve(nc, rhs, n, uhat, ldu, precision, tol > 0 ? tol : rtol, max_iter, st, rtol);
 }
 
 void Problem::inc_adjoint(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
@@ -823,7 +825,7 @@ void Problem::hessian(int mode, int nc, const double* mhat, int ldm, double* out
         prior_apply(nc, mhat, ldm, rm, n, false, side);
         HINV_HIP(hipEventRecord(ev_join_, side));
     }
-    inc_forward(nc, mhat, ldm, uh, n, st);
+    inc_forward(nc, mhat, ldm, uh, n, st, chained_first_rtol(precision, nc, rtol));
     inc_adjoint(nc, gn, mhat, ldm, uh, n, ph, n, st);
     if (with_prior) HINV_HIP(hipStreamWaitEvent(ctx->stream, ev_join_, 0));
     hess_output(mode, nc, mhat, ldm, uh, n, ph, n, out, ldo, rm);

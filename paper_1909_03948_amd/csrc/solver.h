@@ -68,8 +68,11 @@ class Hierarchy {
     void set_state_coefficient(const double* m, int inst = 0);
     // Solves A x = b for nc columns.  b and x: device FP64, column-major.
     // Only the free rows of b are read; x is zero on Dirichlet rows.
+    // accept > rtol: rtol is a goal; once an FP64 pass no longer lowers the
+    // residuals of the remaining columns (their FP64 rounding floor) and all
+    // of them are at or below accept, the solve ends as converged.
     void solve(int nc, const double* b, int ldb, double* x, int ldx, int precision, double rtol,
-               int max_iter, SolveStats* st);
+               int max_iter, SolveStats* st, double accept = 0.0);
     // y = A x (FP64, masked to free rows).
     void apply(int nc, const double* x, int ldx, double* y, int ldy);
     // z = one V-cycle (FP64) applied to r, zero on Dirichlet rows.

@@ -1293,7 +1293,7 @@ void Hierarchy::precondition(int nc, const double* r, int ldr, double* z, int ld
 }
 
 void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int precision,
-                      double rtol, int max_iter, SolveStats* stats) {
+                      double rtol, int max_iter, SolveStats* stats, double accept) {
     if (!ready_) fail(HINV_ESTATE, "solve before the operator coefficient was set");
     if (nc <= 0) return;
     hipStream_t s = ctx_->stream;
@@ -1333,6 +1333,8 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
     bool use32 = fp32;
     std::vector<double> prev_rr(nc, INFINITY);  // unknown before the first pass
     std::vector<int> prev_on(nc, 0);             // outer flags at the start of the last pass
+    std::vector<double> rr_before(nc, INFINITY);  // residuals at the start of the last FP64 pass
+    bool last64 = false;                          // the last pass ran in FP64
     const ColState* hst = host_st();  // pinned, so the read-backs need no staging copy
     const int* hoact = host_oact();
     bool converged = false;
@@ -1351,6 +1353,23 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
                 converged = true;
                 break;
             }
+            // a goal below the acceptable tolerance: an FP64 pass that left every
+            // remaining residual where it was (within 2x) has met the columns'
+            // rounding floor; stop if all of them are acceptable
+            if (accept > rtol && last64) {
+                bool ok = true, moved = false;
+                for (int c = 0; c < nc && ok; ++c) {
+                    if (!hoact[c]) continue;
+                    const double rr = hst[c].rr, obb = hst[c].obb;
+                    ok = std::isfinite(rr) && obb > 0 && rr <= accept * accept * obb;
+                    moved = moved || rr < 0.25 * rr_before[c];
+                }
+                if (ok && !moved) {
+                    converged = true;
+                    break;
+                }
+            }
+            for (int c = 0; c < nc; ++c) rr_before[c] = hst[c].rr;
         }
         if (outer >= max_outer || iters >= max_iter) {
             if (outer == 0) {
@@ -1419,6 +1438,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
             HINV_LAUNCH_CHECK();
             pcg<float>(nc, max_iter - iters, &iters);
             step(w32_.x.get(), nullptr);
+            last64 = false;
         } else {
             k_ir_scale<double><<<g, kBlock, 0, s>>>(r64_.get(), w64_.r.get(), w64_.x.get(), ld, n, oact_.get(),
                                                     colnorm_.get(), act_.get(), st_.get(), tdone_.get());
@@ -1429,6 +1449,7 @@ void Hierarchy::solve(int nc, const double* b, int ldb, double* x, int ldx, int 
             have_state = pcg<double>(nc, max_iter - iters, &iters, &tail);
             // stopped at the iteration limit: unfinished columns take the step they have
             if (!have_state) step(w64_.x.get(), nullptr);
+            last64 = true;
         }
         ++outer;
         if (trace_on()) trace_cols(s, "outer", outer, st_.get(), oact_.get(), nc);

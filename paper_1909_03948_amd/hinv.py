@@ -8,8 +8,10 @@ dimension ld = tensor.stride(0)).  The library must be built first
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -79,6 +81,30 @@ _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 class Allocator(C.Structure):
     """hinv_allocator: device memory callbacks of a context."""
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+# Handles still open at interpreter exit are closed by an exit hook, batches
+# and networks before problems before contexts, while torch is still whole:
+# at module teardown the allocator's free callback would find torch cleared.
+_LIVE = {kind: weakref.WeakSet() for kind in ("batch", "cnn", "problem", "ctx")}
+_EXIT_HOOK = []
+
+
+def _close_all():
+    for kind in ("batch", "cnn", "problem", "ctx"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+def _track(kind, obj):
+    if not _EXIT_HOOK:
+        # registered after torch is imported, so it runs before torch's own hooks
+        atexit.register(_close_all)
+        _EXIT_HOOK.append(True)
+    _LIVE[kind].add(obj)
 
 
 class TorchAllocator:
@@ -278,6 +304,7 @@ class Context:
         if rc != HINV_OK:
             raise HinvError(rc, self.lib.hinv_last_error(None).decode())
         self.h = h
+        _track("ctx", self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -330,6 +357,7 @@ class Problem:
         h = C.c_void_p()
         self._check(self.lib.hinv_problem_create(ctx.h, C.byref(desc), C.byref(h)), allow=())
         self.h = h
+        _track("problem", self)
         self.N, self.n, self.q = N, (N + 1) ** 2, q
 
     def _check(self, rc, allow=(HINV_ENOCONV,)):
@@ -572,6 +600,7 @@ class Cnn:
         if rc != HINV_OK:
             raise HinvError(rc, ctx.error() or self.lib.hinv_status_string(rc).decode())
         self.h = h
+        _track("cnn", self)
         self.nparams = self.lib.hinv_cnn_param_count()
 
     def _check(self, rc):
@@ -666,6 +695,7 @@ class Batch:
         if rc != HINV_OK:
             raise HinvError(rc, ctx.error() or self.lib.hinv_status_string(rc).decode())
         self.h = h
+        _track("batch", self)
 
     def _check(self, rc, allow=(HINV_ENOCONV,)):
         if rc != HINV_OK and rc not in allow:

@@ -87,3 +87,32 @@ def test_torch_allocator_serves_every_workspace_once():
     gp.close()
     assert alloc.frees > frees and alloc.live_bytes < live
     print(f"[gpu-alloc] problem destroyed: {alloc.frees - frees} buffers returned", flush=True)
+
+
+EXIT_CHILD = r"""
+import sys
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import synth
+from paper_1909_03948_amd import hinv as hv
+ctx = hv.Context(0)
+gp = hv.Problem(ctx, 16, 0.1, 0.5, obs_xy=synth.obs_points(20), d_obs=np.zeros(20), sigma=0.01)
+n = 17 * 17
+x = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+y = torch.zeros_like(x)
+gp.prior_apply(x, y)
+torch.cuda.synchronize()
+print("done", flush=True)
+# exits with the context and problem still open
+"""
+
+
+def test_open_handles_close_cleanly_at_exit():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", EXIT_CHILD, root], capture_output=True, text=True, timeout=240)
+    print(f"[gpu-alloc] exit with open handles: rc {r.returncode}", flush=True)
+    assert r.returncode == 0 and "done" in r.stdout, r.stderr[-2000:]
+    assert "Exception ignored" not in r.stderr and "Traceback" not in r.stderr, r.stderr[-2000:]

@@ -10,7 +10,8 @@ vector, and per output the values at 4 096 seeded indices, the 2-norm and the
 inner products with two standard-normal vectors w.  Bar, each relative to the
 output's norm: sampled entries, the norm, and |<w, gpu - oracle>| (an unbiased
 estimate of the 2-norm error in which every entry takes part) within 1e-8;
-for the Hessian action at the benchmark's 1e-10 residual, 5e-8 (see the test).  The eigensolver is checked
+the Hessian action at the benchmark's 1e-10 residual included, in both of
+its launch forms (8 columns in FP32 refinement, one column in FP64 PCG).  The eigensolver is checked
 by properties that hold at any size, through operators whose parity the first
 test establishes: R-orthonormality of V, Ritz values equal to the Rayleigh
 quotients v^T H v of their vectors, and eigen-residuals
@@ -83,20 +84,19 @@ def test_forward_gradient_hessian_at_full_size(big):
     check(z, W, "p", host(pd))
     check(z, W, "g", host(gd))
     gp.linearize(md, ud, pd)
-    mh = synth.test_vectors(n, 8, stream=31)  # 8 columns: FP32 inside FP64 refinement
-    out = dev(np.zeros((8, n)))
+    mh = synth.test_vectors(n, 8, stream=31)
     # A Hessian action chains two solves (the right-hand side of p-hat holds
-    # u-hat), so its error is the 1e-10 residual amplified by the conditioning of
-    # A(m), which grows as N^2: about 1.3e-8 here against ~1e-9 at N = 256.  At
-    # the benchmark's 1e-10 the bar is 5e-8; at 1e-11 the same kernels meet 1e-8.
-    for rtol, tol in ((1e-10, 5e-8), (1e-11, 1e-8)):
-        gp.set_solver(hv.PREC_AUTO, rtol)
-        info = gp.hessian_apply(hv.HESS_MISFIT, dev(mh), out)
-        assert info["rc"] == 0 and info["max_relres"] <= rtol, info
+    # u-hat).  With both FP32-refined solves stopped at 1e-10 its error was
+    # 1.3e-8 here; the library runs the first of them to 1e-11 in that form,
+    # and the bar is 1e-8 at the benchmark's 1e-10.
+    for nc, cols in ((8, (0, 5)), (1, (0,))):   # FP32 refinement / FP64 PCG
+        print(f"[gpu-large] Hessian action, {nc} column(s)", flush=True)
+        out = dev(np.zeros((nc, n)))
+        info = gp.hessian_apply(hv.HESS_MISFIT, dev(mh[:nc]), out)
+        assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
         got = host(out)
-        for c in (0, 5):
-            check(z, W, f"h{c}", got[c], tol)
-    gp.set_solver(hv.PREC_AUTO, 1e-10)
+        for c in cols:
+            check(z, W, f"h{c}", got[c])
 
 
 def test_eigenpairs_at_full_size_by_properties(big):
