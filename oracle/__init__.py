@@ -15,6 +15,8 @@ Modules:
   mesh     -- structured right-diagonal triangulation, element assembly of
               A(m), M, K_Theta, boundary mass, observation operator B,
               rectangular mass factor C_M (Appendix C).
+  p2       -- quadratic (P2) state space on the same triangles: the state
+              discretization of the paper's Poisson experiment (Sec. 5.1).
   model    -- forward, cost, adjoint, gradient, incremental forward/adjoint,
               Hessian action, bilaplacian prior R and R^{-1}, prior sampling
               (Sec. 2, Sec. 4.3, Sec. 5.1 and Appendix A).

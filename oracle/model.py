@@ -31,6 +31,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import mesh as msh
+from . import p2 as p2sp
 
 HESS_FULL = 0        # full Hessian of J (misfit + prior)
 HESS_MISFIT = 1      # data-misfit part only
@@ -43,17 +44,50 @@ def default_beta(gamma: float, delta: float) -> float:
     return np.sqrt(gamma * delta) / 1.42
 
 
+class P1State:
+    """Linear state space: the parameter's own nodes (the workloads' default)."""
+
+    def __init__(self, mesh: msh.Mesh, geo: msh.Geometry):
+        self.mesh, self.geo = mesh, geo
+        self.n = mesh.n
+        self.free = mesh.free
+        self.uD = np.zeros(mesh.n)
+        self.uD[mesh.xy[:, 1] == 1.0] = 1.0
+
+    def stiffness(self, cT):
+        return msh.stiffness(self.mesh, self.geo, cT)
+
+    def tri_forms(self, v, w):
+        """Per-triangle |T| grad(v) . grad(w) for nodal vectors v, w (unit coefficient)."""
+        G = self.geo.grads                         # (nt, 3, 2)
+        gv = np.einsum('tai,ta->ti', G, v[self.mesh.tris])
+        gw = np.einsum('tai,ta->ti', G, w[self.mesh.tris])
+        return self.geo.area * np.einsum('ti,ti->t', gv, gw)
+
+    def observation_operator(self, pts):
+        return msh.observation_operator(self.mesh, pts)
+
+
 class Problem:
-    """One instance of the discrete coefficient-inversion problem."""
+    """One instance of the discrete coefficient-inversion problem.
+
+    state_degree 1: P1 state on the parameter's nodes; 2: P2 state (the
+    paper's Sec. 5.1 pairing), vectors u, p, uhat, phat then live on the
+    (2N+1)^2 nodes of ``p2.P2Space`` while m, g and H mhat stay P1."""
 
     def __init__(self, N: int, gamma: float, delta: float, m_prior: float = -2.0,
                  beta: float | None = None, Theta: np.ndarray | None = None,
                  obs_xy: np.ndarray | None = None, d_obs: np.ndarray | None = None,
-                 sigma: float = 0.01):
+                 sigma: float = 0.01, state_degree: int = 1):
         self.mesh = msh.Mesh(N)
         self.geo = msh.Geometry(self.mesh)
         self.N = N
         self.n = self.mesh.n
+        if state_degree not in (1, 2):
+            raise ValueError("state_degree must be 1 or 2")
+        self.state_degree = state_degree
+        self.S = P1State(self.mesh, self.geo) if state_degree == 1 else p2sp.P2Space(self.mesh, self.geo)
+        self.ns = self.S.n
         self.gamma, self.delta = float(gamma), float(delta)
         self.beta = default_beta(gamma, delta) if beta is None else float(beta)
         self.Theta = None if Theta is None else np.asarray(Theta, dtype=float)
@@ -67,20 +101,19 @@ class Problem:
         # factorizations of K_A and M and the mass factor C_M are built at first use
         self._KA_lu_, self._M_lu_, self._CM = None, None, None
         # state boundary data
-        self.free = self.mesh.free
-        self.uD = np.zeros(self.n)
-        self.uD[self.mesh.xy[:, 1] == 1.0] = 1.0
+        self.free = self.S.free
+        self.uD = self.S.uD
         self.set_observations(obs_xy, d_obs)
         self._fact_m = None  # cache of (m, c_T, A, LU of A_FF)
 
     # -- observations ---------------------------------------------------------
     def set_observations(self, obs_xy, d_obs):
         if obs_xy is None:
-            self.B = sp.csr_matrix((0, self.n))
+            self.B = sp.csr_matrix((0, self.ns))
             self.d = np.zeros(0)
             return
         self.obs_xy = np.asarray(obs_xy, dtype=float)
-        self.B = msh.observation_operator(self.mesh, self.obs_xy)
+        self.B = self.S.observation_operator(self.obs_xy)
         self.d = np.zeros(self.B.shape[0]) if d_obs is None else np.asarray(d_obs, dtype=float)
 
     # -- prior (Sec. 5.1, Sec. 2.3) -------------------------------------------
@@ -127,7 +160,7 @@ class Problem:
         if self._fact_m is not None and np.array_equal(self._fact_m[0], m):
             return self._fact_m
         cT = msh.coefficient(self.mesh, m)
-        A = msh.stiffness(self.mesh, self.geo, cT).tocsr()
+        A = self.S.stiffness(cT).tocsr()
         f = self.free
         AFF = A[f][:, f].tocsc()
         lu = spla.splu(AFF)
@@ -174,17 +207,14 @@ class Problem:
     def adjoint(self, m, u):
         """A_FF p_F = -[B^T (B u - d)]_F / sigma^2, p = 0 on the Dirichlet nodes (Eq. eq:firstadj)."""
         rhs = -(self.B.T @ (self.B @ u - self.d)) / self.sigma ** 2
-        p = np.zeros(self.n)
+        p = np.zeros(self.ns)
         # A(m) is symmetric, so the adjoint operator is A_FF itself
         p[self.free] = self._solve_free(m, rhs[self.free])
         return p
 
     def _tri_forms(self, v, w):
-        """Per-triangle |T| grad(v) . grad(w) for nodal vectors v, w (unit coefficient)."""
-        G = self.geo.grads                         # (nt, 3, 2)
-        gv = np.einsum('tai,ta->ti', G, v[self.mesh.tris])
-        gw = np.einsum('tai,ta->ti', G, w[self.mesh.tris])
-        return self.geo.area * np.einsum('ti,ti->t', gv, gw)
+        """Per-triangle int_T grad(v) . grad(w) for state vectors v, w (unit coefficient)."""
+        return self.S.tri_forms(v, w)
 
     def _vertex_sum(self, per_tri):
         """Scatter per-triangle values to their three vertices (sum)."""
@@ -207,14 +237,14 @@ class Problem:
         per-triangle coefficient s_T applied to w).
         """
         sT = cT / 3.0 * mhat[self.mesh.tris].sum(axis=1)
-        Ks = msh.stiffness(self.mesh, self.geo, sT)
+        Ks = self.S.stiffness(sT)
         return Ks @ w
 
     def inc_forward(self, m, u, mhat):
         """A_FF uhat_F = -[C(u) mhat]_F, uhat_D = 0 (Eq. eq:incrementals1)."""
         cT = self.coefficient(m)
         rhs = -self._sens_apply(cT, mhat, u)
-        uh = np.zeros(self.n)
+        uh = np.zeros(self.ns)
         uh[self.free] = self._solve_free(m, rhs[self.free])
         return uh
 
@@ -227,7 +257,7 @@ class Problem:
         rhs = -(self.B.T @ (self.B @ uhat)) / self.sigma ** 2
         if not gauss_newton:
             rhs = rhs - self._sens_apply(cT, mhat, p)
-        ph = np.zeros(self.n)
+        ph = np.zeros(self.ns)
         ph[self.free] = self._solve_free(m, rhs[self.free])
         return ph
 
@@ -267,7 +297,7 @@ def make_instance(cfg: dict, seed: int, eta_truth: np.ndarray, obs_xy: np.ndarra
     """
     Theta = msh.anisotropic_theta(*cfg["theta"]) if cfg.get("theta") else None
     prob = Problem(cfg["N"], cfg["gamma"], cfg["delta"], cfg["m_prior"], beta=beta, Theta=Theta,
-                   obs_xy=obs_xy)
+                   obs_xy=obs_xy, state_degree=cfg.get("state_degree", 1))
     m_true = prob.prior_sample(eta_truth)
     u_true = prob.forward(m_true)
     sigma = 0.01 * float(np.max(np.abs(u_true)))

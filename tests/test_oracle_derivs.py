@@ -2,7 +2,8 @@
 
 Finite differences of the cost and of the gradient (the paper's own check,
 Sec. 1), symmetry of the Hessian, and brute-force dense Hessians built from
-second differences of the cost functional alone on a tiny mesh.
+second differences of the cost functional alone on a tiny mesh; each for the
+P1 state and for the P2 state of the paper's Sec. 5.1 pairing (deg = 2).
 """
 import numpy as np
 import pytest
@@ -11,8 +12,11 @@ import synth
 from oracle import model
 
 
-def _instance(N=8, q=12, seed=1909):
-    cfg = dict(N=N, q=q, gamma=0.1, delta=0.5, m_prior=-2.0)
+DEGREES = pytest.mark.parametrize("deg", [1, 2])
+
+
+def _instance(N=8, q=12, seed=1909, deg=1):
+    cfg = dict(N=N, q=q, gamma=0.1, delta=0.5, m_prior=-2.0, state_degree=deg)
     prob, mt, _ = model.make_instance(cfg, seed, synth.white_noise(N, seed=seed)[0],
                                       synth.obs_points(q, seed=seed), synth.obs_noise(q, seed=seed))
     m = prob.m_pr + 0.4 * synth.smooth_field(N, seed=seed)
@@ -23,8 +27,9 @@ def _fd_rates(errs):
     return [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
 
 
-def test_gradient_central_differences_second_order():
-    prob, m = _instance()
+@DEGREES
+def test_gradient_central_differences_second_order(deg):
+    prob, m = _instance(deg=deg)
     u = prob.forward(m)
     g = prob.gradient(m, u, prob.adjoint(m, u))
     dm = synth.test_vectors(prob.n, 1)[0]
@@ -39,8 +44,9 @@ def test_gradient_central_differences_second_order():
 
 
 @pytest.mark.parametrize("mode", [model.HESS_FULL, model.HESS_MISFIT])
-def test_hessian_central_differences_of_gradient(mode):
-    prob, m = _instance()
+@DEGREES
+def test_hessian_central_differences_of_gradient(mode, deg):
+    prob, m = _instance(deg=deg)
     u = prob.forward(m)
     p = prob.adjoint(m, u)
     dm = synth.test_vectors(prob.n, 1, stream=9)[0]
@@ -63,8 +69,9 @@ def test_hessian_central_differences_of_gradient(mode):
 
 @pytest.mark.parametrize("mode", [model.HESS_FULL, model.HESS_MISFIT,
                                   model.HESS_GN_FULL, model.HESS_GN_MISFIT])
-def test_hessian_symmetry(mode):
-    prob, m = _instance()
+@DEGREES
+def test_hessian_symmetry(mode, deg):
+    prob, m = _instance(deg=deg)
     u = prob.forward(m)
     p = prob.adjoint(m, u)
     v1, v2 = synth.test_vectors(prob.n, 2, stream=10)
@@ -73,9 +80,10 @@ def test_hessian_symmetry(mode):
     assert abs(a - b) <= 1e-11 * max(abs(a), 1.0)
 
 
-def test_misfit_hessian_matches_second_differences_of_cost():
+@DEGREES
+def test_misfit_hessian_matches_second_differences_of_cost(deg):
     """Dense misfit Hessian from mixed second differences of the misfit term alone (N = 3)."""
-    prob, m = _instance(N=3, q=6)
+    prob, m = _instance(N=3, q=6, deg=deg)
     n = prob.n
     u = prob.forward(m)
     p = prob.adjoint(m, u)
@@ -96,9 +104,10 @@ def test_misfit_hessian_matches_second_differences_of_cost():
     assert np.linalg.norm(Hfd - Hcols) / np.linalg.norm(Hcols) < 1e-5
 
 
-def test_gauss_newton_matches_brute_force_jacobian():
+@DEGREES
+def test_gauss_newton_matches_brute_force_jacobian(deg):
     """GN misfit Hessian = J^T J / sigma^2 with J the FD Jacobian of m -> B u(m) (N = 4)."""
-    prob, m = _instance(N=4, q=9)
+    prob, m = _instance(N=4, q=9, deg=deg)
     n = prob.n
     u = prob.forward(m)
     p = prob.adjoint(m, u)
@@ -113,12 +122,13 @@ def test_gauss_newton_matches_brute_force_jacobian():
     assert np.linalg.norm(Hfull - Hcols - Rd) / np.linalg.norm(Hfull) < 1e-12
 
 
-def test_incremental_forward_is_derivative_of_state():
-    prob, m = _instance()
+@DEGREES
+def test_incremental_forward_is_derivative_of_state(deg):
+    prob, m = _instance(deg=deg)
     u = prob.forward(m)
     dm = synth.test_vectors(prob.n, 1, stream=12)[0]
     uh = prob.inc_forward(m, u, dm)
     eps = 1e-4
     fd = (prob.forward(m + eps * dm) - prob.forward(m - eps * dm)) / (2 * eps)
     assert np.linalg.norm(fd - uh) / np.linalg.norm(uh) < 1e-7
-    assert np.all(uh[prob.mesh.dirichlet] == 0.0)
+    assert np.all(uh[~prob.free] == 0.0)
