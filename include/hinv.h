@@ -115,6 +115,17 @@ typedef struct {
      * holds for theta1 >= theta2 > 0 and 0 <= alpha <= pi/2, e.g. the paper's
      * theta = (2, 0.5), alpha = pi/4. */
     double theta1, theta2, alpha;
+    /* Degree of the state space: 0 or 1 -- P1 on the parameter's nodes;
+     * 2 -- P2, the pairing of Sec. 5.1 (quadratic state, linear parameter).
+     * With 2, every state-space vector (u, adjoint p, uhat, phat, and the
+     * arguments of hinv_state_apply / hinv_state_solve) has ns = (2N+1)^2
+     * entries, node J (2N+1) + I at (I h/2, J h/2) (vertices and edge
+     * midpoints); the parameter-space vectors keep n = (N+1)^2.  Its solves
+     * are FP64 PCG with a two-level preconditioner (P2 Chebyshev-Jacobi
+     * smoothing around one V-cycle of the P1 operator, the exact Galerkin
+     * coarse space) whatever the precision setting.  Batches, flexible CG and
+     * the CNN pair harvest take P1 problems only (HINV_EINVAL). */
+    int state_degree;
 } hinv_problem_desc;
 
 typedef struct {
@@ -231,6 +242,9 @@ int hinv_problem_create(hinv_ctx* ctx, const hinv_problem_desc* d, hinv_problem*
 int hinv_problem_destroy(hinv_problem* p);
 /* n = (N+1)^2 */
 int hinv_problem_size(const hinv_problem* p, int* n);
+/* Entries of a state-space vector: (N+1)^2 for a P1 state, (2N+1)^2 for a P2
+ * state (hinv_problem_desc.state_degree; Sec. 5.1). */
+int hinv_problem_state_size(const hinv_problem* p, int* ns);
 /* Replaces the data vector d (host array of q values) and/or sigma (> 0). */
 int hinv_set_data(hinv_problem* p, const double* d_obs_host, double sigma);
 /* Overrides precision and tolerance of the state-equation solves. */

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhinv.so")
 ARCH = os.environ.get("HINV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["solver.hip", "problem.hip", "dense.hip", "algos.hip", "batch.hip", "cnn.hip", "fcg.hip", "noalloc.hip", "abi.hip"]
+SOURCES = ["solver.hip", "problem.hip", "dense.hip", "algos.hip", "batch.hip", "cnn.hip", "fcg.hip", "noalloc.hip", "p2.hip", "abi.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -224,6 +224,7 @@ int hinv_problem_create(hinv_ctx* c, const hinv_problem_desc* d, hinv_problem** 
             REQUIRE(t12 >= -eps && t12 <= std::min(t11, t22) + eps,
                     "Theta must satisfy 0 <= Theta_12 <= min(Theta_11, Theta_22) on this mesh");
         }
+        REQUIRE(d->state_degree >= 0 && d->state_degree <= 2, "state_degree must be 0, 1 or 2");
         REQUIRE(d->q >= 0, "q must be >= 0");
         REQUIRE(d->q == 0 || d->obs_xy, "obs_xy is required when q > 0");
         REQUIRE(d->sigma > 0, "sigma must be positive");
@@ -250,6 +251,12 @@ int hinv_problem_destroy(hinv_problem* p) {
 int hinv_problem_size(const hinv_problem* p, int* n) {
     if (!p || !n) return HINV_EINVAL;
     *n = p->p->n;
+    return HINV_OK;
+}
+
+int hinv_problem_state_size(const hinv_problem* p, int* ns) {
+    if (!p || !ns) return HINV_EINVAL;
+    *ns = p->p->ns;
     return HINV_OK;
 }
 
@@ -295,7 +302,7 @@ int hinv_observe(hinv_problem* p, const double* u, double* Bu) {
     if (!p) return HINV_EINVAL;
     return guarded(ctx_of(p), [&] {
         REQUIRE(u && (Bu || p->p->q == 0), "null argument");
-        p->p->observe(u, p->p->n, 1, Bu, p->p->q, false);
+        p->p->observe(u, p->p->ns, 1, Bu, p->p->q, false);
     });
 }
 
@@ -324,8 +331,8 @@ int hinv_inc_forward(hinv_problem* p, int nrhs, const double* mhat, int ldm, dou
     if (!p) return HINV_EINVAL;
     hinv::SolveStats st;
     int rc = guarded(ctx_of(p), [&] {
-        const int n = p->p->n;
-        REQUIRE(nrhs >= 0 && ldm >= n && ldu >= n, "bad size or leading dimension");
+        const int n = p->p->n, ns = p->p->ns;
+        REQUIRE(nrhs >= 0 && ldm >= n && ldu >= ns, "bad size or leading dimension");
         REQUIRE(nrhs == 0 || (mhat && uhat), "null vector");
         if (nrhs) p->p->inc_forward(nrhs, mhat, ldm, uhat, ldu, &st);
     });
@@ -338,8 +345,8 @@ int hinv_inc_adjoint(hinv_problem* p, int nrhs, int gauss_newton, const double* 
     if (!p) return HINV_EINVAL;
     hinv::SolveStats st;
     int rc = guarded(ctx_of(p), [&] {
-        const int n = p->p->n;
-        REQUIRE(nrhs >= 0 && ldm >= n && ldu >= n && ldp >= n, "bad size or leading dimension");
+        const int n = p->p->n, ns = p->p->ns;
+        REQUIRE(nrhs >= 0 && ldm >= n && ldu >= ns && ldp >= ns, "bad size or leading dimension");
         REQUIRE(nrhs == 0 || (mhat && uhat && phat), "null vector");
         if (nrhs) p->p->inc_adjoint(nrhs, gauss_newton != 0, mhat, ldm, uhat, ldu, phat, ldp, &st);
     });
@@ -571,6 +578,7 @@ int hinv_batch_create(hinv_ctx* c, int nprob, hinv_problem* const* probs, hinv_b
         for (int i = 0; i < nprob; ++i) {
             REQUIRE(probs[i] && probs[i]->owner == c, "every problem must belong to this context");
             for (int j = 0; j < i; ++j) REQUIRE(probs[j] != probs[i], "a problem appears twice");
+            REQUIRE(probs[i]->p->deg == 1, "batches take P1-state problems only");
             ps.push_back(probs[i]->p.get());
             ++count[probs[i]->p->N];
         }
@@ -636,13 +644,13 @@ int hinv_batch_lowrank_eig(hinv_batch* b, int mode, int tprod, int s, const doub
 int hinv_state_apply(hinv_problem* p, int nrhs, const double* x, int ldx, double* y, int ldy) {
     if (!p) return HINV_EINVAL;
     return guarded(ctx_of(p), [&] {
-        const int n = p->p->n;
-        REQUIRE(nrhs >= 0 && ldx >= n && ldy >= n, "bad size or leading dimension");
+        const int ns = p->p->ns;
+        REQUIRE(nrhs >= 0 && ldx >= ns && ldy >= ns, "bad size or leading dimension");
         REQUIRE(nrhs == 0 || (x && y), "null vector");
         REQUIRE(p->p->linearized, "state operator used before hinv_linearize");
         if (!nrhs) return;
         p->p->ensure_lin_hierarchy();
-        p->p->HA->apply(nrhs, x, ldx, y, ldy);
+        p->p->state_apply(nrhs, x, ldx, y, ldy);
     });
 }
 
@@ -651,14 +659,14 @@ int hinv_state_solve(hinv_problem* p, int nrhs, const double* b, int ldb, double
     if (!p) return HINV_EINVAL;
     hinv::SolveStats st;
     int rc = guarded(ctx_of(p), [&] {
-        const int n = p->p->n;
-        REQUIRE(nrhs >= 0 && ldb >= n && ldx >= n, "bad size or leading dimension");
+        const int ns = p->p->ns;
+        REQUIRE(nrhs >= 0 && ldb >= ns && ldx >= ns, "bad size or leading dimension");
         REQUIRE(nrhs == 0 || (b && x), "null vector");
         REQUIRE(p->p->linearized, "state operator used before hinv_linearize");
         if (!nrhs) return;
         hinv::Problem& P = *p->p;
         P.ensure_lin_hierarchy();
-        P.HA->solve(nrhs, b, ldb, x, ldx, P.precision, P.rtol, P.max_iter, &st);
+        P.state_solve(nrhs, b, ldb, x, ldx, P.rtol, &st);
     });
     fill_info(info, st);
     return rc != HINV_OK ? rc : conv_status(st);
@@ -675,6 +683,7 @@ int hinv_state_solve_fcg(hinv_problem* p, hinv_cnn* net, const double* b, double
         REQUIRE(truncation >= 1 && truncation <= 32, "truncation must be in [1, 32]");
         REQUIRE(!net || net->owner == p->owner, "network and problem must share the context");
         REQUIRE(p->p->linearized, "state operator used before hinv_linearize");
+        REQUIRE(p->p->deg == 1, "flexible CG takes P1-state problems only");
         hinv::state_solve_fcg(*p->p, net ? net->net.get() : nullptr, b, x, rtol, max_iter, truncation, &st);
     });
     if (info) {
@@ -766,6 +775,7 @@ int hinv_cnn_harvest(hinv_problem* p, int npairs, uint64_t seed, int crop, float
         REQUIRE(crop >= 3 && crop <= p->p->N + 1, "crop must be in [3, N + 1]");
         REQUIRE(npairs == 0 || (in && target), "null output");
         REQUIRE(p->p->linearized, "harvest before hinv_linearize");
+        REQUIRE(p->p->deg == 1, "the pair harvest takes P1-state problems only");
         if (npairs) hinv::cnn_harvest(*p->p, npairs, seed, crop, in, target, &st);
     });
     fill_info(info, st);

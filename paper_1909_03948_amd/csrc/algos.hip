@@ -78,24 +78,25 @@ constexpr double kOuterRtol = 1e-12;
 int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_opts& o,
                hinv_newton_info* info) {
     Ctx* c = P.ctx;
-    const int n = P.n;
+    const int n = P.n, ns = P.ns;
     std::memset(info, 0, sizeof(*info));
-    P.ws_newton.ensure((size_t)n * 10);
+    P.ws_newton.ensure((size_t)n * 7 + (size_t)ns * 3);
     P.ws_scal.ensure(8);
     double* cgs = P.ws_scal.get();
     if (!c->host_red)
         HINV_HIP(hipHostMalloc((void**)&c->host_red, sizeof(double) * Ctx::kHostRed, hipHostMallocDefault));
     double* m = m_map;
+    // state vectors (ns entries): u, p, ut; parameter vectors (n): the rest
     double* u = P.ws_newton.get();
-    double* p = u + n;
-    double* g = p + n;
+    double* p = u + ns;
+    double* ut = p + ns;
+    double* g = ut + ns;
     double* mh = g + n;
     double* r = mh + n;
     double* z = r + n;
     double* d = z + n;
     double* Hd = d + n;
     double* mt = Hd + n;
-    double* ut = mt + n;
     SolveStats st;
     if (m0)
         dev_copy(c, n, 1, m0, n, m, n);
@@ -186,7 +187,7 @@ int map_newton(Problem& P, const double* m0, double* m_map, const hinv_newton_op
             const double Jt = mt_mis + mt_reg;
             if (solved && Jt < J + alpha * o.c_armijo * gm) {
                 dev_copy(c, n, 1, mt, n, m, n);
-                dev_copy(c, n, 1, ut, n, u, n);
+                dev_copy(c, ns, 1, ut, ns, u, ns);
                 J = Jt;
                 accepted = true;
                 break;

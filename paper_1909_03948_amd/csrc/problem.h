@@ -5,6 +5,7 @@
 
 #include <memory>
 
+#include "p2.h"
 #include "solver.h"
 
 namespace hinv {
@@ -24,8 +25,11 @@ class Problem {
     double rtol;
     int max_iter;
 
-    std::unique_ptr<Hierarchy> HA;  // state operator A(m)
+    std::unique_ptr<Hierarchy> HA;  // state operator A(m) (the P1 state, or the coarse space of P2)
     std::unique_ptr<Hierarchy> HK;  // prior operator K_A
+    int deg = 1;                    // state degree (1: P1, 2: P2 on the (2N+1)^2 nodes)
+    int ns = 0;                     // entries of a state vector
+    std::unique_ptr<P2Space> S2;    // the P2 state space (deg == 2)
 
     // observation operator: 3 (node, weight) pairs per point; transpose in CSR
     DBuf<double> obs_xy, obs_w, d;
@@ -79,6 +83,12 @@ class Problem {
 
     // A(m_lin) rebuilt in HA if a solve at another parameter replaced it
     void ensure_lin_hierarchy();
+    // the state operator at parameter m (P1 hierarchy, and the P2 diagonal)
+    void set_state(const double* m);
+    // state solve / apply in the problem's state space (P1 or P2)
+    void state_solve(int nc, const double* b, int ldb, double* x, int ldx, double tol, SolveStats* st,
+                     double accept = 0.0);
+    void state_apply(int nc, const double* x, int ldx, double* y, int ldy);
 
     // Workspaces of the algorithm drivers (Newton-CG, eigensolvers, samples,
     // variance, flexible CG): grown to the largest call, kept until the

@@ -579,11 +579,14 @@ Problem::Problem(Ctx* c, const hinv_problem_desc& desc)
         pp.t22 = desc.theta1 * ca * ca + desc.theta2 * sa * sa;
     }
     prior = pp;
+    deg = desc.state_degree == 2 ? 2 : 1;
+    ns = deg == 2 ? (2 * N + 1) * (2 * N + 1) : n;
     HA = std::make_unique<Hierarchy>(ctx, kOpState, N, pp);
     HK = std::make_unique<Hierarchy>(ctx, kOpPrior, N, pp);
+    if (deg == 2) S2 = std::make_unique<P2Space>(ctx, N);
     m_lin.ensure(n);
-    u_lin.ensure(n);
-    p_lin.ensure(n);
+    u_lin.ensure(ns);
+    p_lin.ensure(ns);
     hipStream_t s = ctx->stream;
     if (q > 0) {
         obs_xy.ensure(2 * (size_t)q);
@@ -618,6 +621,7 @@ Problem::Problem(Ctx* c, const hinv_problem_desc& desc)
         HINV_HIP(hipMemcpyAsync(t_ptr.get(), tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, s));
         HINV_HIP(hipMemcpyAsync(t_ent.get(), te.data(), sizeof(int) * te.size(), hipMemcpyHostToDevice, s));
         HINV_HIP(hipStreamSynchronize(s));
+        if (S2) S2->set_observations(q, obs_xy.get());
         set_data(desc.d_obs, sigma);
     }
 }
@@ -639,7 +643,7 @@ double* Problem::scratch(int which, int nc) {
     if (which < 0 || which >= kScratch) fail(HINV_EINVAL, "internal: scratch index out of range");
     if (nc > cap_) {
         for (auto& w : w_) w.release();
-        for (auto& w : w_) w.ensure((size_t)n * nc);
+        for (auto& w : w_) w.ensure((size_t)std::max(n, ns) * nc);
         cap_ = nc;
     }
     return w_[which].get();
@@ -653,11 +657,37 @@ double* Problem::obs_scratch(int nc) {
     return wq_.get();
 }
 
+void Problem::set_state(const double* m) {
+    HA->set_state_coefficient(m);
+    if (S2) S2->set_coefficient(HA->coefficient());
+}
+
+void Problem::state_solve(int nc, const double* b, int ldb, double* x, int ldx, double tol, SolveStats* st,
+                          double accept) {
+    if (S2)
+        S2->solve(nc, b, ldb, x, ldx, *HA, tol, max_iter, st);
+    else
+        HA->solve(nc, b, ldb, x, ldx, precision, tol, max_iter, st, accept);
+}
+
+void Problem::state_apply(int nc, const double* x, int ldx, double* y, int ldy) {
+    if (S2)
+        S2->apply(nc, x, ldx, y, ldy, 1.0);
+    else
+        HA->apply(nc, x, ldx, y, ldy);
+}
+
 void Problem::forward(const double* m, double* u, SolveStats* st) {
     hipStream_t s = ctx->stream;
-    HA->set_state_coefficient(m);
+    set_state(m);
     ha_is_lin = false;
     double* rhs = scratch(0, 1);
+    if (S2) {
+        S2->forward_rhs(rhs);
+        state_solve(1, rhs, ns, u, ns, rtol, st);
+        S2->set_top(u);
+        return;
+    }
     k_forward_rhs<<<ceil_div(n, kBlock), kBlock, 0, s>>>(N, HA->weightsN(), rhs);
     HINV_LAUNCH_CHECK();
     HA->solve(1, rhs, n, u, n, precision, rtol, max_iter, st);
@@ -667,6 +697,10 @@ void Problem::forward(const double* m, double* u, SolveStats* st) {
 
 void Problem::observe(const double* u, int ldu, int nc, double* out, int ldo, bool minus_data) {
     if (q == 0) return;
+    if (S2) {
+        S2->observe(nc, u, ldu, minus_data ? d.get() : nullptr, out, ldo);
+        return;
+    }
     k_obs_gather<<<grid2(q, nc), kBlock, 0, ctx->stream>>>(q, obs_node.get(), obs_w.get(), u, ldu,
                                                            minus_data ? d.get() : nullptr, out, ldo);
     HINV_LAUNCH_CHECK();
@@ -676,7 +710,7 @@ void Problem::cost(const double* m, const double* u, double* misfit, double* reg
     double mis = 0.0;
     if (q > 0) {
         double* r = obs_scratch(1);
-        observe(u, n, 1, r, q, true);
+        observe(u, ns, 1, r, q, true);
         double ss;
         dev_dots(ctx, q, 1, r, q, r, q, &ss);
         mis = 0.5 * ss / (sigma * sigma);
@@ -693,22 +727,30 @@ void Problem::cost(const double* m, const double* u, double* misfit, double* reg
 
 void Problem::gradient(const double* m, const double* u, double* p, double* g, SolveStats* st) {
     hipStream_t s = ctx->stream;
-    HA->set_state_coefficient(m);
+    set_state(m);
     ha_is_lin = false;
     double* rhs = scratch(0, 1);
-    k_fill<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, 0.0, rhs);
+    k_fill<<<ceil_div(ns, kBlock), kBlock, 0, s>>>(ns, 0.0, rhs);
     HINV_LAUNCH_CHECK();
     if (q > 0) {
         double* r = obs_scratch(1);
-        observe(u, n, 1, r, q, true);
-        k_obs_scatter<<<ceil_div(n_touch, kBlock), kBlock, 0, s>>>(
-            n_touch, t_node.get(), t_ptr.get(), t_ent.get(), obs_w.get(), r, q,
-            -1.0 / (sigma * sigma), rhs, n);
+        observe(u, ns, 1, r, q, true);
+        if (S2) {
+            S2->observe_adjoint(1, r, q, -1.0 / (sigma * sigma), rhs, ns);
+        } else {
+            k_obs_scatter<<<ceil_div(n_touch, kBlock), kBlock, 0, s>>>(
+                n_touch, t_node.get(), t_ptr.get(), t_ent.get(), obs_w.get(), r, q,
+                -1.0 / (sigma * sigma), rhs, n);
+            HINV_LAUNCH_CHECK();
+        }
+    }
+    state_solve(1, rhs, ns, p, ns, rtol, st);
+    if (S2) {
+        S2->grad(u, p, g);
+    } else {
+        k_grad<<<ceil_div(n, kBlock), kBlock, 0, s>>>(N, HA->coefficient(), u, p, g);
         HINV_LAUNCH_CHECK();
     }
-    HA->solve(1, rhs, n, p, n, precision, rtol, max_iter, st);
-    k_grad<<<ceil_div(n, kBlock), kBlock, 0, s>>>(N, HA->coefficient(), u, p, g);
-    HINV_LAUNCH_CHECK();
     double* dm = scratch(1, 1);
     dev_copy(ctx, n, 1, m, n, dm, n);
     k_add_scalar<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, -m_prior, dm, n);
@@ -718,9 +760,9 @@ void Problem::gradient(const double* m, const double* u, double* p, double* g, S
 
 void Problem::linearize(const double* m, const double* u, const double* p) {
     dev_copy(ctx, n, 1, m, n, m_lin.get(), n);
-    dev_copy(ctx, n, 1, u, n, u_lin.get(), n);
-    dev_copy(ctx, n, 1, p, n, p_lin.get(), n);
-    HA->set_state_coefficient(m_lin.get());
+    dev_copy(ctx, ns, 1, u, ns, u_lin.get(), ns);
+    dev_copy(ctx, ns, 1, p, ns, p_lin.get(), ns);
+    set_state(m_lin.get());
     ha_is_lin = true;
     linearized = true;
     ++lin_version;
@@ -729,7 +771,7 @@ void Problem::linearize(const double* m, const double* u, const double* p) {
 void Problem::ensure_lin_hierarchy() {
     if (!linearized) fail(HINV_ESTATE, "Hessian action before hinv_linearize");
     if (!ha_is_lin) {
-        HA->set_state_coefficient(m_lin.get());
+        set_state(m_lin.get());
         ha_is_lin = true;
     }
 }
@@ -737,6 +779,10 @@ void Problem::ensure_lin_hierarchy() {
 // Right-hand side -[C(u) mhat]_F of the incremental forward problem.
 void Problem::inc_forward_rhs(int nc, const double* mhat, int ldm, double* rhs, int ldr) {
     ensure_lin_hierarchy();
+    if (S2) {
+        S2->sens(nc, mhat, ldm, u_lin.get(), -1.0, rhs, ldr);
+        return;
+    }
     k_sens<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(N, HA->coefficient(), mhat, ldm, u_lin.get(),
                                                      -1.0, rhs, ldr);
     HINV_LAUNCH_CHECK();
@@ -748,6 +794,16 @@ void Problem::inc_adjoint_rhs(int nc, bool gn, const double* mhat, int ldm, cons
                               int ldu, double* rhs, int ldr) {
     ensure_lin_hierarchy();
     hipStream_t s = ctx->stream;
+    if (S2) {
+        // the scale 0 zeroes the column under Gauss-Newton
+        S2->sens(nc, mhat, ldm, p_lin.get(), gn ? 0.0 : -1.0, rhs, ldr);
+        if (q > 0) {
+            double* Bu = obs_scratch(nc);
+            observe(uhat, ldu, nc, Bu, q, false);
+            S2->observe_adjoint(nc, Bu, q, -1.0 / (sigma * sigma), rhs, ldr);
+        }
+        return;
+    }
     // the scale 0 zeroes the column under Gauss-Newton
     k_sens<<<grid2(n, nc), kBlock, 0, s>>>(N, HA->coefficient(), mhat, ldm, p_lin.get(),
                                            gn ? 0.0 : -1.0, rhs, ldr);
@@ -767,6 +823,12 @@ void Problem::hess_output(int mode, int nc, const double* mhat, int ldm, const d
                           const double* ph, int ldp, double* out, int ldo, const double* rm) {
     const bool gn = mode == HINV_HESS_GN_FULL || mode == HINV_HESS_GN_MISFIT;
     const bool with_prior = mode == HINV_HESS_FULL || mode == HINV_HESS_GN_FULL;
+    if (S2) {
+        S2->hess_out(nc, gn, u_lin.get(), p_lin.get(), uh, ldu, ph, ldp, mhat, ldm, out, ldo,
+                     with_prior ? rm : nullptr, n);
+        if (with_prior && !rm) prior_apply(nc, mhat, ldm, out, ldo, true);
+        return;
+    }
     k_hess_out<<<grid2(n, nc), kBlock, 0, ctx->stream>>>(N, HA->coefficient(), u_lin.get(),
                                                          p_lin.get(), uh, ldu, ph, ldp, mhat, ldm,
                                                          out, ldo, gn ? 1 : 0, with_prior ? rm : nullptr, n);
@@ -795,16 +857,16 @@ Problem::~Problem() {
 void Problem::inc_forward(int nc, const double* mhat, int ldm, double* uhat, int ldu, SolveStats* st,
                           double tol) {
     double* rhs = scratch(0, nc);
-    inc_forward_rhs(nc, mhat, ldm, rhs, n);
+    inc_forward_rhs(nc, mhat, ldm, rhs, ns);
     // a tighter goal still accepts the problem's tolerance at the rounding floor
-    HA->solve(nc, rhs, n, uhat, ldu, precision, tol > 0 ? tol : rtol, max_iter, st, rtol);
+    state_solve(nc, rhs, ns, uhat, ldu, tol > 0 ? tol : rtol, st, rtol);
 }
 
 void Problem::inc_adjoint(int nc, bool gn, const double* mhat, int ldm, const double* uhat, int ldu,
                           double* phat, int ldp, SolveStats* st) {
     double* rhs = scratch(0, nc);
-    inc_adjoint_rhs(nc, gn, mhat, ldm, uhat, ldu, rhs, n);
-    HA->solve(nc, rhs, n, phat, ldp, precision, rtol, max_iter, st);
+    inc_adjoint_rhs(nc, gn, mhat, ldm, uhat, ldu, rhs, ns);
+    state_solve(nc, rhs, ns, phat, ldp, rtol, st);
 }
 
 void Problem::hessian(int mode, int nc, const double* mhat, int ldm, double* out, int ldo,
@@ -825,10 +887,11 @@ void Problem::hessian(int mode, int nc, const double* mhat, int ldm, double* out
         prior_apply(nc, mhat, ldm, rm, n, false, side);
         HINV_HIP(hipEventRecord(ev_join_, side));
     }
-    inc_forward(nc, mhat, ldm, uh, n, st, chained_first_rtol(precision, nc, rtol));
-    inc_adjoint(nc, gn, mhat, ldm, uh, n, ph, n, st);
+    // the P2 state solves in FP64 PCG: no chained tightening
+    inc_forward(nc, mhat, ldm, uh, ns, st, S2 ? rtol : chained_first_rtol(precision, nc, rtol));
+    inc_adjoint(nc, gn, mhat, ldm, uh, ns, ph, ns, st);
     if (with_prior) HINV_HIP(hipStreamWaitEvent(ctx->stream, ev_join_, 0));
-    hess_output(mode, nc, mhat, ldm, uh, n, ph, n, out, ldo, rm);
+    hess_output(mode, nc, mhat, ldm, uh, ns, ph, ns, out, ldo, rm);
 }
 
 void Problem::mass_apply(int nc, const double* x, int ldx, double* y, int ldy) {

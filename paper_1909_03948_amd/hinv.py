@@ -40,7 +40,7 @@ class ProblemDesc(C.Structure):
                 ("obs_xy", C.POINTER(C.c_double)), ("d_obs", C.POINTER(C.c_double)),
                 ("sigma", C.c_double), ("precision", C.c_int), ("rtol", C.c_double),
                 ("max_iter", C.c_int), ("theta1", C.c_double), ("theta2", C.c_double),
-                ("alpha", C.c_double)]
+                ("alpha", C.c_double), ("state_degree", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -141,6 +141,7 @@ class TorchAllocator:
 EXPORTS = [
     "hinv_ctx_create", "hinv_ctx_destroy", "hinv_ctx_set_stream", "hinv_last_error",
     "hinv_status_string", "hinv_problem_create", "hinv_problem_destroy", "hinv_problem_size",
+    "hinv_problem_state_size",
     "hinv_set_data", "hinv_set_solver", "hinv_forward", "hinv_cost", "hinv_observe",
     "hinv_gradient", "hinv_linearize", "hinv_inc_forward", "hinv_inc_adjoint",
     "hinv_hessian_apply", "hinv_prior_apply", "hinv_prior_apply_noalloc", "hinv_prior_solve", "hinv_prior_sample",
@@ -181,6 +182,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hinv_problem_create": [P, C.POINTER(ProblemDesc), C.POINTER(P)],
         "hinv_problem_destroy": [P],
         "hinv_problem_size": [P, C.POINTER(I)],
+        "hinv_problem_state_size": [P, C.POINTER(I)],
         "hinv_set_data": [P, DP, D],
         "hinv_set_solver": [P, I, D, I],
         "hinv_forward": [P, V, V, C.POINTER(SolveInfo)],
@@ -340,8 +342,9 @@ class Problem:
 
     def __init__(self, ctx: Context, N, gamma, delta, obs_xy=None, d_obs=None, sigma=0.01,
                  m_prior=-2.0, beta=float("nan"), precision=PREC_FP64, rtol=1e-10, max_iter=0,
-                 theta=None):
-        """theta: None (Theta = I) or (theta1, theta2, alpha) of the prior's anisotropic tensor."""
+                 theta=None, state_degree=1):
+        """theta: None (Theta = I) or (theta1, theta2, alpha) of the prior's anisotropic tensor.
+        state_degree: 1 (P1 state) or 2 (P2 state: state vectors have ns = (2N+1)^2 entries)."""
         self.ctx, self.lib = ctx, ctx.lib
         xy = np.ascontiguousarray(np.zeros((0, 2)) if obs_xy is None else obs_xy, dtype=np.float64)
         q = xy.shape[0]
@@ -353,12 +356,15 @@ class Problem:
                            d_obs=self._d.ctypes.data_as(DP) if self._d is not None else None,
                            sigma=sigma, precision=precision, rtol=rtol, max_iter=max_iter,
                            theta1=theta[0] if theta else 0.0, theta2=theta[1] if theta else 0.0,
-                           alpha=theta[2] if theta else 0.0)
+                           alpha=theta[2] if theta else 0.0, state_degree=state_degree)
         h = C.c_void_p()
         self._check(self.lib.hinv_problem_create(ctx.h, C.byref(desc), C.byref(h)), allow=())
         self.h = h
         _track("problem", self)
         self.N, self.n, self.q = N, (N + 1) ** 2, q
+        nsv = C.c_int()
+        self._check(self.lib.hinv_problem_state_size(self.h, C.byref(nsv)), allow=())
+        self.ns = nsv.value
 
     def _check(self, rc, allow=(HINV_ENOCONV,)):
         if rc != HINV_OK and rc not in allow:
@@ -387,31 +393,31 @@ class Problem:
 
     def forward(self, m, u):
         info = SolveInfo()
-        rc = self._check(self.lib.hinv_forward(self.h, _vec(m, self.n), _vec(u, self.n), C.byref(info)))
+        rc = self._check(self.lib.hinv_forward(self.h, _vec(m, self.n), _vec(u, self.ns), C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
     def cost(self, m, u):
         mis, reg = C.c_double(), C.c_double()
-        self._check(self.lib.hinv_cost(self.h, _vec(m, self.n), _vec(u, self.n), C.byref(mis), C.byref(reg)),
+        self._check(self.lib.hinv_cost(self.h, _vec(m, self.n), _vec(u, self.ns), C.byref(mis), C.byref(reg)),
                     allow=())
         return mis.value, reg.value
 
     def observe(self, u, Bu):
-        self._check(self.lib.hinv_observe(self.h, _vec(u, self.n), _vec(Bu, self.q)), allow=())
+        self._check(self.lib.hinv_observe(self.h, _vec(u, self.ns), _vec(Bu, self.q)), allow=())
 
     def gradient(self, m, u, p, g):
         info = SolveInfo()
-        rc = self._check(self.lib.hinv_gradient(self.h, _vec(m, self.n), _vec(u, self.n), _vec(p, self.n),
+        rc = self._check(self.lib.hinv_gradient(self.h, _vec(m, self.n), _vec(u, self.ns), _vec(p, self.ns),
                                                 _vec(g, self.n), C.byref(info)))
         return info.as_dict() | {"rc": rc}
 
     def linearize(self, m, u, p):
-        self._check(self.lib.hinv_linearize(self.h, _vec(m, self.n), _vec(u, self.n), _vec(p, self.n)),
+        self._check(self.lib.hinv_linearize(self.h, _vec(m, self.n), _vec(u, self.ns), _vec(p, self.ns)),
                     allow=())
 
     def inc_forward(self, mhat, uhat):
         pm, nc, ldm = _cols(mhat, self.n)
-        pu, nc2, ldu = _cols(uhat, self.n)
+        pu, nc2, ldu = _cols(uhat, self.ns)
         _same(nc, nc2)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_inc_forward(self.h, nc, pm, ldm, pu, ldu, C.byref(info)))
@@ -419,8 +425,8 @@ class Problem:
 
     def inc_adjoint(self, mhat, uhat, phat, gauss_newton=False):
         pm, nc, ldm = _cols(mhat, self.n)
-        pu, nc2, ldu = _cols(uhat, self.n)
-        pp, nc3, ldp = _cols(phat, self.n)
+        pu, nc2, ldu = _cols(uhat, self.ns)
+        pp, nc3, ldp = _cols(phat, self.ns)
         _same(nc, nc2, nc3)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_inc_adjoint(self.h, nc, int(gauss_newton), pm, ldm, pu, ldu,
@@ -480,14 +486,14 @@ class Problem:
         return info.as_dict() | {"rc": rc}
 
     def state_apply(self, x, y):
-        px, nc, ldx = _cols(x, self.n)
-        py, nc2, ldy = _cols(y, self.n)
+        px, nc, ldx = _cols(x, self.ns)
+        py, nc2, ldy = _cols(y, self.ns)
         _same(nc, nc2)
         self._check(self.lib.hinv_state_apply(self.h, nc, px, ldx, py, ldy), allow=())
 
     def state_solve(self, b, x):
-        pb, nc, ldb = _cols(b, self.n)
-        px, nc2, ldx = _cols(x, self.n)
+        pb, nc, ldb = _cols(b, self.ns)
+        px, nc2, ldx = _cols(x, self.ns)
         _same(nc, nc2)
         info = SolveInfo()
         rc = self._check(self.lib.hinv_state_solve(self.h, nc, pb, ldb, px, ldx, C.byref(info)))

@@ -41,7 +41,8 @@ WORKLOADS = {
     # anisotropic prior theta = (2, 0.5), alpha = pi/4
     # (rank r = 30 and oversampling l = 20 as in the section's low-rank posterior)
     "poisson64_paper": dict(N=64, q=50, gamma=0.1, delta=0.5, m_prior=-2.0, k=30, p=20,
-                            theta=(2.0, 0.5, float(np.pi / 4)), obs_box=(0.1, 0.9, 0.1, 0.5)),
+                            theta=(2.0, 0.5, float(np.pi / 4)), obs_box=(0.1, 0.9, 0.1, 0.5),
+                            state_degree=2),
 }
 
 

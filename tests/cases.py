@@ -16,8 +16,9 @@ from oracle import model
 
 
 @functools.lru_cache(maxsize=8)
-def instance(N: int, q: int, gamma: float = 0.1, delta: float = 0.5, seed: int = synth.MASTER_SEED):
-    cfg = dict(N=N, q=q, gamma=gamma, delta=delta, m_prior=-2.0)
+def instance(N: int, q: int, gamma: float = 0.1, delta: float = 0.5, seed: int = synth.MASTER_SEED,
+             state_degree: int = 1):
+    cfg = dict(N=N, q=q, gamma=gamma, delta=delta, m_prior=-2.0, state_degree=state_degree)
     prob, m_true, u_true = model.make_instance(
         cfg, seed, synth.white_noise(N, seed=seed)[0], synth.obs_points(q, seed=seed),
         synth.obs_noise(q, seed=seed))

@@ -1,9 +1,9 @@
-"""The paper's own Poisson setup (Sec. 5.1) on the GPU against the oracle, with
-a P1 state (the paper's state is P2; the reading is stated in the design
-notes): the anisotropic prior -gamma div(Theta grad m) + delta m with
-theta = (2, 0.5), alpha = pi/4 (Theta as read: the s.p.d. tensor with those
-eigenvalues and directions), 50 observations in [0.1, 0.9] x [0.1, 0.5],
-64 x 64 cells (4 225 parameters).
+"""The paper's own Poisson setup (Sec. 5.1) on the GPU against the oracle: a
+quadratic (P2) state with a linear parameter on 64 x 64 cells (16 641 state
+and 4 225 parameter unknowns), the anisotropic prior
+-gamma div(Theta grad m) + delta m with theta = (2, 0.5), alpha = pi/4 (Theta
+as read: the s.p.d. tensor with those eigenvalues and directions), 50
+observations in [0.1, 0.9] x [0.1, 0.5].
 
 * prior R x, R^-1 x and prior draws with Theta: 1e-10 (apply) and 1e-8
   (solves) relative per column at N = 16 and 64;
@@ -15,6 +15,10 @@ eigenvalues and directions), 50 observations in [0.1, 0.9] x [0.1, 0.5],
   the library's Cholesky-based QR reports HINV_EBREAK);
   the spectrum is printed and compared with Fig. 7 qualitatively: it decays
   fast, and fewer eigenvalues exceed 0.07 than there are observations;
+* pointwise variance (Sec. 4.4, the Fig. 8 analog) at the MAP point: the
+  prior variance from r = 300 eigenpairs of R^-1 and the posterior variance
+  with the Gauss-Newton eigenpairs, each within 1e-8 of the oracle's; the
+  data lower the variance most inside the observation box;
 * a tensor whose off-diagonal has the wrong sign for this mesh is rejected.
 """
 import numpy as np
@@ -59,7 +63,8 @@ def paper_instance(N):
 
 def gpu_problem(ctx, prob, obs, precision=hv.PREC_AUTO, theta=THETA):
     return hv.Problem(ctx, prob.N, prob.gamma, prob.delta, obs_xy=obs, d_obs=prob.d, sigma=prob.sigma,
-                      m_prior=prob.m_pr[0], beta=prob.beta, precision=precision, rtol=1e-10, theta=theta)
+                      m_prior=prob.m_pr[0], beta=prob.beta, precision=precision, rtol=1e-10, theta=theta,
+                      state_degree=CFG["state_degree"])
 
 
 @pytest.mark.parametrize("N", [16, 64])
@@ -90,6 +95,7 @@ def test_full_hessian_with_anisotropic_prior(ctx):
     gp.linearize(dev(m), dev(u), dev(p))
     mh = synth.test_vectors(prob.n, 3, seed=71)
     out = dev(np.zeros((3, prob.n)))
+    assert prob.ns == gp.ns == 65 ** 2
     gp.hessian_apply(hv.HESS_FULL, dev(mh), out)
     ref = np.array([prob.hessian_apply(m, u, p, v, model.HESS_FULL) for v in mh])
     assert col_rel(host(out), ref) <= 1e-8
@@ -123,6 +129,27 @@ def test_paper_setup_map_and_spectrum(ctx):
     print("[gpu-paper] lambda_1..30:", np.array2string(lam, precision=3), flush=True)
     assert e <= 1e-8
     assert above < CFG["q"] and lam[0] / lam[-1] > 100
+    # pointwise variance at the MAP point (Fig. 8 analog)
+    rbar = 300
+    Omv = synth.omega(prob.n, rbar, seed=synth.MASTER_SEED + 7)
+    pd_o, _ = lowrank.prior_variance(prob.R_solve, Omv.T)
+    pdg = dev(np.zeros(prob.n))
+    mu, info = gp.prior_variance(dev(Omv), pdg)
+    assert info["rc"] == 0, info
+    ep = rel(host(pdg), pd_o)
+    _, V_o, _ = lowrank.double_pass(A, prob.R_apply, prob.R_solve, Om.T, k)
+    post_o = lowrank.posterior_variance(pd_o, V_o, lam_o)
+    post = dev(np.zeros(prob.n))
+    gp.posterior_variance(pdg, lam, V, post)
+    eq = rel(host(post), post_o)
+    ratio = host(post) / host(pdg)
+    xy = np.array([(i / 64, j / 64) for j in range(65) for i in range(65)])
+    box = (xy[:, 0] >= 0.1) & (xy[:, 0] <= 0.9) & (xy[:, 1] >= 0.1) & (xy[:, 1] <= 0.5)
+    print(f"[gpu-paper] variance (rbar = {rbar}): prior {ep:.1e}, posterior {eq:.1e} from the oracle; "
+          f"max prior variance {host(pdg).max():.3e}; mean posterior/prior inside the box "
+          f"{ratio[box].mean():.3f}, outside {ratio[~box].mean():.3f}", flush=True)
+    assert ep <= 1e-8 and eq <= 1e-8
+    assert ratio[box].mean() < ratio[~box].mean() and np.all(ratio <= 1 + 1e-12)
 
 
 def test_tensor_outside_the_mesh_condition_is_rejected(ctx):
