@@ -82,7 +82,8 @@ struct PcgRed {
     int stride;
     int nrz;  // number of partials of r^T z (workgroups of the last V-cycle kernel)
     int nvec; // number of partials of p^T q and r^T r (workgroups of the PCG vector kernels)
-    int per;  // consecutive blocks of 256 nodes per workgroup in the PCG vector kernels
+    int per;  // node blocks of 256 per workgroup: sets the PCG vector kernels' threads
+    int chunk;  // consecutive nodes per workgroup in the PCG vector kernels (<= kVecNodes threads)
 };
 
 // Threads per workgroup of the PCG vector kernels: 256 per node block up to
@@ -670,7 +671,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
 }
 
 // ------------------------------------------------------------------ PCG ---
-// Workgroup blockIdx.x covers nodes [256 per x, 256 per (x + 1)) of column
+// Workgroup blockIdx.x covers nodes [chunk x, chunk (x + 1)) of column
 // blockIdx.y with vec_threads(per) threads, at most kVecNodes nodes a thread.
 
 // p_new = z + beta p_old with beta = (r^T z) / rz_old (p_new = z on the first
@@ -724,7 +725,7 @@ __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict_
     const double rz_old = FIRST ? 1.0 : st[col].rz;
     const T* zc = z + (size_t)col * ld;
     const T* pc = p_old + (size_t)col * ld;
-    const int k0 = bx * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
+    const int k0 = bx * red.chunk, k1 = min(n, k0 + red.chunk);
     const double inv_n1 = 1.0 / N1;
     using Form = ApplyForm<std::decay_t<decltype(op)>>;
     using OpT = typename Form::type;
@@ -818,7 +819,7 @@ __global__ __launch_bounds__(1024) void k_pcg_update(T* __restrict__ x, T* __res
     if (!act[col]) return;
     double spq = partial_first(red.pq, col, red.stride, red.nvec);
     const double rz = st[col].rz_new;
-    const int k0 = blockIdx.x * 256 * red.per, k1 = min(n, k0 + 256 * red.per);
+    const int k0 = blockIdx.x * red.chunk, k1 = min(n, k0 + red.chunk);
     T xk[kVecNodes], rk[kVecNodes], pk[kVecNodes], qk[kVecNodes];
 #pragma unroll
     for (int e = 0; e < kVecNodes; ++e) {

@@ -126,6 +126,10 @@ class Hierarchy {
         int small_max = 0;  // otherwise small tiles on the levels with N_l <= small_max
         int per;
         int cb;  // columns per workgroup of the V-cycle kernels
+        // nodes per workgroup of the PCG vector kernels; 0: 256 per.  A
+        // balanced chunk spreads a column over a whole number of workgroups
+        // per compute unit instead of whole 256-node blocks.
+        int chunk = 0;
     };
     bool small_tiles(int l) const { return shape_.small || lev_[l]->N <= shape_.small_max; }
     // levels N_l <= 128 below the finest level of a cycle with small tiles

@@ -652,7 +652,8 @@ PcgRed Hierarchy::pcg_red(int nc) const {
     const int tf = small_tiles(0) ? kTFSmall : kTFBig;
     r.nrz = Lb == 0 ? 1 : ceil_div(lev_[0]->N + 1, tf) * ceil_div(lev_[0]->N + 1, tf);
     r.per = shape_.per;
-    r.nvec = ceil_div(n_, kBlock * r.per);
+    r.chunk = shape_.chunk > 0 ? shape_.chunk : kBlock * r.per;
+    r.nvec = ceil_div(n_, r.chunk);
     return r;
 }
 
@@ -690,12 +691,12 @@ int Hierarchy::min_per() const {
 // unit count, operator kind, mesh size, stacked instances, columns, solve
 // precision, and the version of the kernels' launch-shape rules.
 namespace {
-constexpr int kTuneVersion = 2;
+constexpr int kTuneVersion = 3;
 std::mutex g_tune_mu;
 bool g_tune_loaded = false;
 struct TuneRec {
     std::string arch;
-    int kind, N, ninst, nc, fp32, small, small_max, per, cb;
+    int kind, N, ninst, nc, fp32, small, small_max, per, cb, chunk;
 };
 std::vector<TuneRec> g_tune;
 long g_tune_timed = 0, g_tune_cached = 0;
@@ -720,10 +721,11 @@ void tune_load_locked() {
         if (std::sscanf(line,
                         "{\"version\": %d, \"device\": \"%127[^\"]\", \"kind\": %d, \"N\": %d, "
                         "\"instances\": %d, \"columns\": %d, \"fp32\": %d, \"small\": %d, "
-                        "\"small_max\": %d, \"per\": %d, \"cb\": %d}",
+                        "\"small_max\": %d, \"per\": %d, \"cb\": %d, \"chunk\": %d}",
                         &ver, arch, &r.kind, &r.N, &r.ninst, &r.nc, &r.fp32, &r.small, &r.small_max, &r.per,
-                        &r.cb) == 11 &&
-            ver == kTuneVersion && r.per >= 1 && r.per <= 16 && r.cb >= 1 && r.cb <= 64) {
+                        &r.cb, &r.chunk) == 12 &&
+            ver == kTuneVersion && r.per >= 1 && r.per <= 16 && r.cb >= 1 && r.cb <= 64 && r.chunk >= 0 &&
+            r.chunk % 64 == 0 && r.chunk <= kVecNodes * vec_threads(r.per)) {
             r.arch = arch;
             g_tune.push_back(r);
         }
@@ -754,13 +756,18 @@ void Hierarchy::tune_shape(int nc) {
     shape_ = default_shape(nc);
     // HINV_SHAPE forces a shape (tests of every launch path)
     if (const char* f = std::getenv("HINV_SHAPE")) {
-        // HINV_SHAPE=<s|l><per>[c<cb>]
+        // HINV_SHAPE=<s|l><per>[c<cb>][k<chunk>]
         if ((f[0] == 's' || f[0] == 'l') && std::atoi(f + 1) >= 1) {
             shape_.small = f[0] == 's';
             shape_.small_max = 0;
             shape_.per = std::min(16, std::atoi(f + 1));
             const char* c = std::strchr(f, 'c');
             shape_.cb = c ? std::max(1, std::min(64, std::atoi(c + 1))) : 1;
+            const char* k = std::strchr(f, 'k');
+            shape_.chunk = k ? std::atoi(k + 1) : 0;
+            if (shape_.chunk && (shape_.chunk % 64 || shape_.chunk > kVecNodes * vec_threads(shape_.per) ||
+                                 ceil_div(n_, shape_.chunk) > red_stride_))
+                fail(HINV_EINVAL, "HINV_SHAPE: chunk must be a multiple of 64 that the per's threads cover");
             return;
         }
     }
@@ -778,6 +785,7 @@ void Hierarchy::tune_shape(int nc) {
                 shape_.small_max = it->small_max;
                 shape_.per = it->per;
                 shape_.cb = it->cb;
+                shape_.chunk = it->chunk;
                 tuned_.push_back({key, shape_});
                 ++g_tune_cached;
                 return;
@@ -839,10 +847,25 @@ void Hierarchy::tune_shape(int nc) {
     // the apply kernel alone has picked 4 in some runs (3% slower solves).
     const bool fixed_per = nc < kSmallTileCols && min_per() == 1;
     if (fixed_per) best.per = 1;
-    for (int per : {1, 4, 8, 16}) {
-        if (fixed_per) break;
-        if (per < min_per()) continue;
-        shape_.per = per;
+    // candidates (per, chunk): whole 256-node blocks, and for few columns the
+    // column split into one or two workgroups of 1024 threads per compute unit
+    // (a partial last round of workgroups costs as much as a full one)
+    std::vector<std::pair<int, int>> cand;
+    for (int per : {1, 4, 8, 16})
+        if (!fixed_per && per >= min_per()) cand.push_back({per, 0});
+    if (!fixed_per && nc < kSmallTileCols) {
+        hipDeviceProp_t prop;
+        HINV_HIP(hipGetDeviceProperties(&prop, ctx_->device));
+        for (int w : {1, 2}) {
+            const int want = prop.multiProcessorCount * w;
+            const int chunk = ceil_div(ceil_div(n, want), 64) * 64;
+            if (chunk <= kVecNodes * 1024 && ceil_div(n, chunk) <= kMaxVecPartials) cand.push_back({16, chunk});
+        }
+    }
+    best.chunk = 0;
+    for (const auto& pc : cand) {
+        shape_.per = pc.first;
+        shape_.chunk = pc.second;
         const PcgRed red = pcg_red(nc);
         const float ms = timed([&] {
             with_op<T>(0, [&](auto op) {
@@ -853,7 +876,8 @@ void Hierarchy::tune_shape(int nc) {
         });
         if (ms < best_ms) {
             best_ms = ms;
-            best.per = per;
+            best.per = pc.first;
+            best.chunk = pc.second;
         }
     }
     ctx_->timer.paused = timer_was;
@@ -864,7 +888,8 @@ void Hierarchy::tune_shape(int nc) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         ++g_tune_timed;
-        TuneRec r{arch, (int)kind_, N_, ninst_, nc, fp32, best.small ? 1 : 0, best.small_max, best.per, best.cb};
+        TuneRec r{arch, (int)kind_, N_, ninst_, nc, fp32, best.small ? 1 : 0, best.small_max, best.per, best.cb,
+                  best.chunk};
         g_tune.push_back(r);
         const char* path = std::getenv("HINV_TUNE_CACHE");
         if (path && *path)
@@ -872,17 +897,17 @@ void Hierarchy::tune_shape(int nc) {
                 std::fprintf(f,
                              "{\"version\": %d, \"device\": \"%s\", \"kind\": %d, \"N\": %d, \"instances\": %d, "
                              "\"columns\": %d, \"fp32\": %d, \"small\": %d, \"small_max\": %d, \"per\": %d, "
-                             "\"cb\": %d}\n",
+                             "\"cb\": %d, \"chunk\": %d}\n",
                              kTuneVersion, r.arch.c_str(), r.kind, r.N, r.ninst, r.nc, r.fp32, r.small, r.small_max,
-                             r.per, r.cb);
+                             r.per, r.cb, r.chunk);
                 std::fclose(f);
             }
     }
     if (std::getenv("HINV_TRACE_SHAPES"))
         std::fprintf(stderr, "[hinv] launch shape N=%d nc=%d %s: %s tiles, %d columns per V-cycle workgroup, "
-                     "%d node blocks per workgroup\n", N_, nc, sizeof(T) == 8 ? "fp64" : "fp32",
+                     "%d node blocks per workgroup, chunk %d\n", N_, nc, sizeof(T) == 8 ? "fp64" : "fp32",
                      best.small ? "small" : (best.small_max ? "large above N=256/128, small" : "large"), best.cb,
-                     best.per);
+                     best.per, best.chunk);
 }
 
 // z = V-cycle(r) for the PCG of precision T.  An FP64 PCG runs its V-cycle
