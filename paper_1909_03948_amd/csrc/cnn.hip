@@ -1,16 +1,18 @@
 // Residual CNN of the learned preconditioner: forward, backward and Adam on
 // the device (see cnn.h).
 //
-// Convolutions are implicit GEMMs on the BF16 matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation): a workgroup owns a 16 x 16
-// pixel tile of one image and all output channels; its input tile with a
-// one-pixel halo and the layer's 3x3 x C_out x C_in weights sit in LDS.  Each
-// of the 4 waves computes 4 rows of 16 pixels; per tap (dy, dx) and K-step of
-// 16 input channels, operand A is 16 pixels x 16 channels read from the halo
-// tile at the shifted position and operand B the tap's 16 x 16 weight block.
-// Operand layouts (wave64): A: lane l holds A[l % 16][4 (l / 16) + e],
-// B: lane l holds B[4 (l / 16) + e][l % 16], D: lane l item v holds
-// D[4 (l / 16) + v][l % 16].
+// Convolutions are implicit GEMMs on the BF16 matrix cores (FP32
+// accumulation): gfx950's v_mfma_f32_16x16x32_bf16 for K-steps of 32, the
+// 16x16x16 form where a layer has only 16 (padded) input channels.  A
+// workgroup owns a 16 x 16 pixel tile of one image and all output channels;
+// its input tile with a one-pixel halo and the layer's 3x3 x C_out x C_in
+// weights sit in LDS.  Each of the 4 waves computes 4 rows of 16 pixels; per
+// tap (dy, dx) and K-step of input channels, operand A is 16 pixels x K
+// channels read from the halo tile at the shifted position and operand B the
+// tap's K x 16 weight block.  Operand layouts (wave64; checked on the device
+// against a host product): with K = 32, A: lane l holds A[l % 16][8 (l / 16) + e],
+// B: lane l holds B[8 (l / 16) + e][l % 16] (e < 8); with K = 16 the same
+// with 4 (l / 16) + e (e < 4); D: lane l item v holds D[4 (l / 16) + v][l % 16].
 //
 // The backward pass reuses the same kernel: the input gradient of a
 // convolution is a convolution of the output gradient with the weights
@@ -29,6 +31,14 @@ namespace {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef short s8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+// D += A B with K = 32 (operands as BF16 bit patterns)
+__device__ inline f4_t mfma_k32(s8_t a, s8_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, a), __builtin_bit_cast(bf8_t, b), c, 0,
+                                                   0, 0);
+}
 
 constexpr int kT = 16;       // output tile side (pixels)
 constexpr int kH = kT + 2;   // tile side with halo
@@ -111,8 +121,8 @@ __global__ __launch_bounds__(256) void k_conv(int S, const short* __restrict__ i
                                               const float* __restrict__ res, const float* __restrict__ zmask,
                                               float* __restrict__ zout, float* __restrict__ out32,
                                               short* __restrict__ out16) {
-    __shared__ short sin[kH * kH * CI];
-    __shared__ short sw[9 * CO * CI];
+    __shared__ __attribute__((aligned(16))) short sin[kH * kH * CI];
+    __shared__ __attribute__((aligned(16))) short sw[9 * CO * CI];
     const int tx0 = blockIdx.x * kT, ty0 = blockIdx.y * kT, b = blockIdx.z;
     for (int e = threadIdx.x; e < 9 * CO * CI / 4; e += blockDim.x)
         reinterpret_cast<long long*>(sw)[e] = reinterpret_cast<const long long*>(w)[e];
@@ -133,15 +143,29 @@ __global__ __launch_bounds__(256) void k_conv(int S, const short* __restrict__ i
         for (int nt = 0; nt < NT; ++nt) acc[r][nt] = f4_t{0.f, 0.f, 0.f, 0.f};
     for (int t = 0; t < 9; ++t) {
         const int dy = t / 3, dx = t % 3;
-        for (int c0 = 0; c0 < CI; c0 += 16) {
-            s4_t bw[NT];
-            for (int nt = 0; nt < NT; ++nt)
-                bw[nt] = *reinterpret_cast<const s4_t*>(sw + (t * CO + nt * 16 + pi) * CI + c0 + kq);
-            for (int r = 0; r < 4; ++r) {
-                const int ly = wave * 4 + r + dy, lx = pi + dx;
-                const s4_t a = *reinterpret_cast<const s4_t*>(sin + (ly * kH + lx) * CI + c0 + kq);
+        if constexpr (CI % 32 == 0) {
+            const int k8 = (lane >> 4) * 8;
+            for (int c0 = 0; c0 < CI; c0 += 32) {
+                s8_t bw[NT];
                 for (int nt = 0; nt < NT; ++nt)
-                    acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[nt], acc[r][nt], 0, 0, 0);
+                    bw[nt] = *reinterpret_cast<const s8_t*>(sw + (t * CO + nt * 16 + pi) * CI + c0 + k8);
+                for (int r = 0; r < 4; ++r) {
+                    const int ly = wave * 4 + r + dy, lx = pi + dx;
+                    const s8_t a = *reinterpret_cast<const s8_t*>(sin + (ly * kH + lx) * CI + c0 + k8);
+                    for (int nt = 0; nt < NT; ++nt) acc[r][nt] = mfma_k32(a, bw[nt], acc[r][nt]);
+                }
+            }
+        } else {
+            for (int c0 = 0; c0 < CI; c0 += 16) {
+                s4_t bw[NT];
+                for (int nt = 0; nt < NT; ++nt)
+                    bw[nt] = *reinterpret_cast<const s4_t*>(sw + (t * CO + nt * 16 + pi) * CI + c0 + kq);
+                for (int r = 0; r < 4; ++r) {
+                    const int ly = wave * 4 + r + dy, lx = pi + dx;
+                    const s4_t a = *reinterpret_cast<const s4_t*>(sin + (ly * kH + lx) * CI + c0 + kq);
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[nt], acc[r][nt], 0, 0, 0);
+                }
             }
         }
     }
@@ -210,13 +234,16 @@ __global__ __launch_bounds__(256) void k_conv_dw(int S, const short* __restrict_
         const int t = tile / (NCO * NCI), cot = (tile / NCI) % NCO, cit = tile % NCI;
         const int dy = t / 3, dx = t % 3;
         f4_t acc = {0.f, 0.f, 0.f, 0.f};
-        for (int rr = 0; rr < kT; ++rr) {
-            s4_t a, bb;
-            for (int e = 0; e < 4; ++e) {
-                a[e] = sdz[(rr * kT + kq + e) * CO + cot * 16 + pi];
-                bb[e] = sin[((rr + dy) * kH + kq + e + dx) * CI + cit * 16 + pi];
+        // K = the tile's pixels, 32 (two rows) per step: pixel 32 st + 8 (l / 16) + e
+        const int k8 = (lane >> 4) * 8;
+        for (int st = 0; st < kT * kT / 32; ++st) {
+            const int p0 = 32 * st + k8, rr = p0 / kT, cc = p0 % kT;
+            s8_t a, bb;
+            for (int e = 0; e < 8; ++e) {
+                a[e] = sdz[(p0 + e) * CO + cot * 16 + pi];
+                bb[e] = sin[((rr + dy) * kH + cc + e + dx) * CI + cit * 16 + pi];
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
+            acc = mfma_k32(a, bb, acc);
         }
         for (int v = 0; v < 4; ++v) {
             const int co = cot * 16 + kq + v, ci = cit * 16 + pi;

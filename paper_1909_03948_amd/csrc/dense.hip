@@ -6,8 +6,8 @@
 //   f64 16x16x4:   A (16 x 4): lane l holds A[l % 16][l / 16]
 //                  B (4 x 16): lane l holds B[l / 16][l % 16]
 //                  D (16 x 16): lane l, item v holds D[4 v + l / 16][l % 16]
-//   bf16 16x16x16: A: lane l holds A[l % 16][4 (l / 16) + e], e = 0..3
-//                  B: lane l holds B[4 (l / 16) + e][l % 16]
+//   bf16 16x16x32 (gfx950): A: lane l holds A[l % 16][8 (l / 16) + e], e = 0..7
+//                  B: lane l holds B[8 (l / 16) + e][l % 16]
 //                  D: lane l, item v holds D[4 (l / 16) + v][l % 16]
 #include <algorithm>
 #include <vector>
@@ -21,6 +21,8 @@ namespace {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef short s8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 __device__ inline short to_bf16(double x) {
     // round-to-nearest-even of the float value
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(512) void k_gram_bf16(int n, int s1, int s2, int ch
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = bi * kBlk + wave * 16 + (lane & 15);
     if (bi * kBlk + wave * 16 >= s1) return;  // no rows for this wave (no barrier below)
-    const int kq = (lane >> 4) * 4;
+    const int kq = (lane >> 4) * 8;  // gfx950 16x16x32 BF16: 8 consecutive K per lane
     const int k_begin = split * chunk;
     const int k_end = min(n, k_begin + chunk);
     const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
@@ -163,22 +165,23 @@ __global__ __launch_bounds__(512) void k_gram_bf16(int n, int s1, int s2, int ch
         yc[t] = Y + (size_t)(jv[t] ? j : 0) * ldy;
         acc[t] = f4_t{0.f, 0.f, 0.f, 0.f};
     }
-    for (int k0 = k_begin; k0 < k_end; k0 += 16) {
-        s4_t a;
+    for (int k0 = k_begin; k0 < k_end; k0 += 32) {
+        s8_t a;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 8; ++e) {
             const int k = k0 + kq + e;
             a[e] = to_bf16((i < s1 && k < k_end) ? xc[k] : 0.0);
         }
 #pragma unroll
         for (int t = 0; t < kBlkTiles; ++t) {
-            s4_t b;
+            s8_t b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < 8; ++e) {
                 const int k = k0 + kq + e;
                 b[e] = to_bf16((jv[t] && k < k_end) ? yc[t][k] : 0.0);
             }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, a), __builtin_bit_cast(bf8_t, b),
+                                                             acc[t], 0, 0, 0);
         }
     }
 #pragma unroll
