@@ -330,10 +330,14 @@ int hinv_map_newton(hinv_problem* p, const double* m0, double* m_map,
  * linearization point.  omega: device n x s block (s = k + oversampling).
  * mode: HINV_HESS_MISFIT or HINV_HESS_GN_MISFIT.  tprod: HINV_TPROD_*.
  * lambda: HOST array [k] (descending); V: device n x k, R-orthonormal.
- * Errors: HINV_EINVAL unless 1 <= k <= s <= min(512, n); HINV_EBREAK when a
- * Cholesky factor of PreCholQR (Alg. 4) meets a non-positive pivot (a probe
- * block of rank below s, e.g. a zero column); lambda and V are then not
- * written, and the problem stays usable. */
+ * A block Y = R^-1 A omega of numerical rank r < s (e.g. the Gauss-Newton
+ * Hessian, of rank <= q, probed with s > q vectors, or a zero column in
+ * omega) is orthonormalized on its r leading directions (eigendecomposition
+ * of Y^T Y, directions below 100 rtol^2 of the largest dropped) and the
+ * second pass runs on r columns.  Errors: HINV_EINVAL unless
+ * 1 <= k <= s <= min(512, n); HINV_EBREAK when r < k or a Cholesky factor
+ * still meets a non-positive pivot; lambda and V are then not written, and
+ * the problem stays usable. */
 int hinv_lowrank_eig(hinv_problem* p, int mode, int tprod, int s, const double* omega, int ldo,
                      int k, double* lambda_host, double* V, int ldv, hinv_solve_info* info);
 /* Single-pass randomized eigensolver for H_misfit v = lambda R v (Alg. 3): one

@@ -21,8 +21,11 @@ int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int
 // one launch each; the tall products run per member.
 struct DenseWork;
 // b_identity: B = I (Zbar = Z) instead of the prior operator R.
+// rank: when given (one instance only), a block Y of numerical rank r < s does
+// not fail: qr(Y) keeps the r leading directions of Y^T Y (U: s x s and g: s
+// doubles of workspace), Q gets r columns and *rank = r; otherwise *rank = s.
 int precholqr(Problem* const* P, int ni, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
-              double* Ri, bool b_identity = false);
+              double* Ri, bool b_identity = false, int* rank = nullptr, double* U = nullptr, double* g = nullptr);
 void rayleigh_ritz(Problem* const* P, int ni, DenseWork& dw, int s, int k, int tprod, const double* Q,
                    const double* AQ, double* T, double* S, double* lam, double* const* V, int ldv,
                    double* const* lambda_host);

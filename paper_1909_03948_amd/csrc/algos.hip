@@ -1,5 +1,6 @@
 // Drivers of the paper's algorithms on top of the device operations.
 #include <algorithm>
+#include <vector>
 #include <cmath>
 
 #include "algos.h"
@@ -249,17 +250,69 @@ bool orthonormalize(Ctx* c, DenseWork& w, int ni, int n, int s, double* Y, doubl
     return true;
 }
 
+__global__ void k_scale_cols(int s, int r, const double* __restrict__ U, const double* __restrict__ g,
+                             double* __restrict__ M) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s * r) return;
+    const int col = i / s;
+    M[i] = U[i] / sqrt(g[col]);
+}
+
+// qr(Y) of a block of numerical rank r < s (one instance): Y^T Y = U diag(g) U^T
+// (descending), the r directions with g_i > tau g_1 kept, Z = Y U_r diag(g_r)^-1/2,
+// then two Cholesky QR passes on the n x r block (its condition number is at
+// most tau^-1/2).  tau = (10 rtol)^2: the solves that produced Y leave
+// components of relative size rtol outside its exact range.  Returns r, 0 on
+// failure.  Y <- Z (n x r, ld n).
+int orthonormalize_rank(Ctx* c, DenseWork& w, int n, int s, double rtol, double* Y, double* tmp, double* G,
+                        double* Ri, double* U, double* g) {
+    const size_t ss = (size_t)s * s;
+    gram(c, w, n, s, s, Y, n, Y, n, G, s);
+    sym_eig(c, w, 1, s, G, s, ss, U, s, ss, g, s);
+    std::vector<double> hg(s);
+    HINV_HIP(hipMemcpyAsync(hg.data(), g, sizeof(double) * s, hipMemcpyDeviceToHost, c->stream));
+    HINV_HIP(hipStreamSynchronize(c->stream));
+    if (!(hg[0] > 0.0)) return 0;
+    const double tau = std::max(1e-24, 100.0 * rtol * rtol);
+    int r = 0;
+    while (r < s && hg[r] > tau * hg[0]) ++r;
+    k_scale_cols<<<ceil_div(s * r, kBlock), kBlock, 0, c->stream>>>(s, r, U, g, Ri);
+    HINV_LAUNCH_CHECK();
+    gemm_tall(c, n, s, r, 1.0, Y, n, Ri, s, 0.0, tmp, n);
+    dev_copy(c, n, r, tmp, n, Y, n);
+    const size_t rr = (size_t)r * r;
+    for (int pass = 0; pass < 2; ++pass) {
+        gram(c, w, n, r, r, Y, n, Y, n, G, r);
+        if (!cholesky_upper(c, w, 1, r, G, r, rr, nullptr)) return 0;
+        tri_inverse_upper(c, w, 1, r, G, r, rr, Ri, r, rr);
+        gemm_tall(c, n, r, r, 1.0, Y, n, Ri, r, 0.0, tmp, n);
+        dev_copy(c, n, r, tmp, n, Y, n);
+    }
+    return r;
+}
+
 }  // namespace
 
 // PreCholQR (Algorithm 4) on each Y_j (n x s): Z = qr(Y), Zbar = B Z,
 // R_Z = chol(Z^T Zbar), Q = Z R_Z^-1 written to Q_j.  Y_j is overwritten by
 // Z_j; Zb is scratch.
 int precholqr(Problem* const* P, int ni, DenseWork& dw, int s, double* Y, double* Zb, double* Q, double* G,
-              double* Ri, bool b_identity) {
+              double* Ri, bool b_identity, int* rank, double* U, double* g) {
     Ctx* c = P[0]->ctx;
     const int n = P[0]->n;
+    const bool revealing = rank && ni == 1 && U && g;
+    if (rank) *rank = s;
+    // a copy of Y for the rank-revealing retry (Zb is not needed before Z exists)
+    if (revealing) dev_copy(c, n, s, Y, n, Zb, n);
+    if (!orthonormalize(c, dw, ni, n, s, Y, Q, G, Ri)) {  // Y <- Z
+        if (!revealing) return HINV_EBREAK;
+        dev_copy(c, n, s, Zb, n, Y, n);
+        const int r = orthonormalize_rank(c, dw, n, s, P[0]->rtol, Y, Q, G, Ri, U, g);
+        if (r == 0) return HINV_EBREAK;
+        *rank = r;
+        s = r;
+    }
     const size_t ts = (size_t)n * s, ss = (size_t)s * s;
-    if (!orthonormalize(c, dw, ni, n, s, Y, Q, G, Ri)) return HINV_EBREAK;  // Y <- Z
     for (int j = 0; j < ni; ++j) {
         if (b_identity)
             dev_copy(c, n, s, Y + j * ts, n, Zb + j * ts, n);                      // Zbar = Z
@@ -311,11 +364,13 @@ int lowrank_eig(Problem& P, int mode, int tprod, int s, const double* omega, int
     P.hessian(mode, s, omega, ldo, W, n, st);
     P.prior_solve(s, W, n, Y, n, st);
     Problem* const pp = &P;
-    const int rc = precholqr(&pp, 1, dw, s, Y, Zb, W, G, Ri);  // Q in W
+    int r = s;  // numerical rank of Y: below s when A has lower rank than the probe count
+    const int rc = precholqr(&pp, 1, dw, s, Y, Zb, W, G, Ri, false, &r, T, lam);  // Q in W (n x r)
     if (rc != HINV_OK) return rc;
+    if (r < k) return HINV_EBREAK;
     // pass 2: T = Q^T A Q
-    P.hessian(mode, s, W, n, Zb, n, st);
-    rayleigh_ritz(&pp, 1, dw, s, k, tprod, W, Zb, T, S, lam, &V, ldv, &lambda_host);
+    P.hessian(mode, r, W, n, Zb, n, st);
+    rayleigh_ritz(&pp, 1, dw, r, k, tprod, W, Zb, T, S, lam, &V, ldv, &lambda_host);
     return HINV_OK;
 }
 

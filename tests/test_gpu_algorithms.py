@@ -131,11 +131,14 @@ def test_double_pass_odd_probe_counts(ctx, k, p):
     np.testing.assert_allclose(Vg.T @ RV, np.eye(k), atol=1e-8)
 
 
-def test_double_pass_zero_probe_column_breaks_down(ctx):
-    """A probe block with an exactly zero column has rank below s: after the
-    shifted first pass that column of Q is exactly zero, the next Cholesky
-    meets a zero pivot and the call reports HINV_EBREAK, for one problem and
-    for a batch whose other member is sound; the problems stay usable."""
+def test_double_pass_rank_deficient_probe_block(ctx):
+    """A probe block with exactly zero columns has rank below s.  One problem:
+    qr(Y) falls back to the leading directions of Y^T Y and the double pass
+    returns the eigenpairs of the nonzero columns' span (equal to those from
+    the probe block without the zero columns, 1e-8 lambda_1; V R-orthonormal);
+    with fewer directions than k it reports HINV_EBREAK.  A batch whose member
+    has such a block reports HINV_EBREAK (its Cholesky QR has no fallback);
+    the problems stay usable."""
     prob, m, obs = instance(16, 40)
     u = prob.forward(m)
     adj = prob.adjoint(m, u)
@@ -147,8 +150,19 @@ def test_double_pass_zero_probe_column_breaks_down(ctx):
     bad[5] = 0.0
     good = synth.omega(prob.n, s, seed=4)
     Vs = [dev(np.zeros((k, prob.n))) for _ in range(2)]
+    lam_bad, info = gps[0].lowrank_eig(dev(bad), k, Vs[0])
+    assert info["rc"] == 0, info
+    lam_ref, _ = gps[1].lowrank_eig(dev(np.delete(bad, 5, axis=0)), k, Vs[1])
+    e = np.max(np.abs(lam_bad - lam_ref)) / lam_ref[0]
+    Vg = host(Vs[0]).T
+    RV = np.column_stack([prob.R_apply(v) for v in Vg.T])
+    print(f"[gpu-alg] zero probe column: |dlambda|/lambda_1 {e:.1e} against the 11-column block", flush=True)
+    assert e <= 1e-8
+    np.testing.assert_allclose(Vg.T @ RV, np.eye(k), atol=1e-8)
+    worse = bad.copy()
+    worse[:5] = 0.0     # rank 7 < k = 8
     with pytest.raises(hv.HinvError) as e:
-        gps[0].lowrank_eig(dev(bad), k, Vs[0])
+        gps[0].lowrank_eig(dev(worse), k, Vs[0])
     assert e.value.code == hv.HINV_EBREAK
     b = hv.Batch(ctx, gps)
     with pytest.raises(hv.HinvError) as e:

@@ -10,9 +10,9 @@ observations in [0.1, 0.9] x [0.1, 0.5].
 * the full Hessian action (which contains R) at N = 32: 1e-8;
 * MAP point (Alg. 1) within 1e-8 in the R-norm, eigenvalues of the
   Gauss-Newton misfit Hessian at the oracle's MAP point within 1e-8 lambda_1,
-  with the section's r = 30 and l = 20 (s = 50 = q probe vectors: more than q
-  would make the Gauss-Newton block Y = R^-1 H Omega rank-deficient, where
-  the library's Cholesky-based QR reports HINV_EBREAK);
+  with the section's r = 30 and l = 20 (s = 50 = q probe vectors), and with
+  l = 40 (s = 70 > q: the Gauss-Newton block Y = R^-1 H Omega has rank <= q,
+  qr(Y) keeps its numerical range);
   the spectrum is printed and compared with Fig. 7 qualitatively: it decays
   fast, and fewer eigenvalues exceed 0.07 than there are observations;
 * pointwise variance (Sec. 4.4, the Fig. 8 analog) at the MAP point: the
@@ -129,6 +129,17 @@ def test_paper_setup_map_and_spectrum(ctx):
     print("[gpu-paper] lambda_1..30:", np.array2string(lam, precision=3), flush=True)
     assert e <= 1e-8
     assert above < CFG["q"] and lam[0] / lam[-1] > 100
+    # more probes than observations: a rank-deficient probe block
+    s70 = k + 40
+    Om70 = synth.omega(prob.n, s70)
+    lam70_o, _, _ = lowrank.double_pass(A, prob.R_apply, prob.R_solve, Om70.T, k)
+    V70 = dev(np.zeros((k, prob.n)))
+    lam70, info = gp.lowrank_eig(dev(Om70), k, V70, mode=hv.HESS_GN_MISFIT)
+    assert info["rc"] == 0, info
+    e70 = np.max(np.abs(lam70 - lam70_o)) / lam70_o[0]
+    print(f"[gpu-paper] s = {s70} > q: max |dlambda|/lambda_1 {e70:.2e}; against s = {s}: "
+          f"{np.max(np.abs(lam70 - lam)) / lam[0]:.2e}", flush=True)
+    assert e70 <= 1e-8
     # pointwise variance at the MAP point (Fig. 8 analog)
     rbar = 300
     Omv = synth.omega(prob.n, rbar, seed=synth.MASTER_SEED + 7)
