@@ -59,7 +59,7 @@ class Cnn {
     DBuf<short> wf_[kLayers], wb_[kLayers];  // forward [9][co][ci], backward [9][ci][co] (flipped)
     DBuf<short> in0_, a_[kLayers - 1], dz_[2], gy_;
     DBuf<float> z_[kLayers], h_[kLayers - 1], gh_[2], part_, loss_;
-    DBuf<double> lpart_, ratio_;
+    DBuf<double> lpart_, ratio_, dwtmp_;
     int B_ = 0, S_ = 0, nwg_ = 0;
 };
 

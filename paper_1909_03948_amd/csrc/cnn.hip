@@ -258,24 +258,35 @@ __global__ __launch_bounds__(256) void k_conv_dw(int S, const short* __restrict_
 }
 
 // Sum of the per-tile partials (fixed order) into the packed gradient of a layer.
-__global__ void k_dw_reduce(int nwg, int co_r, int ci_r, int COp, int CIp, const float* __restrict__ part,
-                            float* __restrict__ gW, float* __restrict__ gb) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nw = co_r * ci_r * 9;
-    if (id >= nw + co_r) return;
-    size_t src;
-    if (id < nw) {
-        const int co = id / (ci_r * 9), ci = (id / 9) % ci_r, t = id % 9;
-        src = (size_t)(t * COp + co) * CIp + ci;
-    } else {
-        src = (size_t)9 * COp * CIp + (id - nw);
-    }
+// Weight and bias gradients from the per-tile partials, in two fixed-order
+// stages that read the partials coalesced (index j runs over one tile's
+// partial layout [t][co][ci] then the biases):
+//   tmp[sp][j] = sum over the tiles of split sp of part[tile][j],
+//   then the kDwSplit sums in order, scattered into the packed gradient.
+constexpr int kDwSplit = 16;
+__global__ void k_dw_partial(int nwg, int J, const float* __restrict__ part, double* __restrict__ tmp) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sp = blockIdx.y;
+    if (j >= J) return;
+    const int g0 = (int)((long long)sp * nwg / kDwSplit), g1 = (int)((long long)(sp + 1) * nwg / kDwSplit);
     double s = 0.0;
-    for (int g = 0; g < nwg; ++g) s += part[(size_t)g * kWgStride + src];
-    if (id < nw)
-        gW[id] = (float)s;
-    else
-        gb[id - nw] = (float)s;
+    for (int g = g0; g < g1; ++g) s += part[(size_t)g * kWgStride + j];
+    tmp[(size_t)sp * J + j] = s;
+}
+
+__global__ void k_dw_reduce(int J, int co_r, int ci_r, int COp, int CIp, const double* __restrict__ tmp,
+                            float* __restrict__ gW, float* __restrict__ gb) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= J) return;
+    double s = 0.0;
+    for (int sp = 0; sp < kDwSplit; ++sp) s += tmp[(size_t)sp * J + j];
+    const int nw = 9 * COp * CIp;
+    if (j < nw) {
+        const int t = j / (COp * CIp), r = j - t * COp * CIp, co = r / CIp, ci = r - co * CIp;
+        if (co < co_r && ci < ci_r) gW[(co * ci_r + ci) * 9 + t] = (float)s;
+    } else if (j - nw < co_r) {
+        gb[j - nw] = (float)s;
+    }
 }
 
 // Per-sample partial sums of |y - t|^2 and |t|^2 (grid: chunks x images).
@@ -586,10 +597,13 @@ double Cnn::gradient(int B, int S, const float* in, const float* target, int tch
     const dim3 g(tiles, tiles, B);
     const int nwg = tiles * tiles * B;
     float* gr = grad_.get();
+    dwtmp_.ensure((size_t)kDwSplit * (9 * 32 * 32 + 32));
     auto reduce = [&](int l) {
-        const int tot = L[l].co * L[l].ci * 9 + L[l].co;
-        k_dw_reduce<<<ceil_div(tot, 256), 256, 0, s>>>(nwg, L[l].co, L[l].ci, L[l].COp, L[l].CIp, part_.get(),
-                                                        gr + L[l].woff, gr + L[l].boff);
+        const int J = 9 * L[l].COp * L[l].CIp + L[l].COp;
+        k_dw_partial<<<dim3(ceil_div(J, 256), kDwSplit), 256, 0, s>>>(nwg, J, part_.get(), dwtmp_.get());
+        HINV_LAUNCH_CHECK();
+        k_dw_reduce<<<ceil_div(J, 256), 256, 0, s>>>(J, L[l].co, L[l].ci, L[l].COp, L[l].CIp, dwtmp_.get(),
+                                                      gr + L[l].woff, gr + L[l].boff);
         HINV_LAUNCH_CHECK();
     };
     const int top = kLayers - 1;

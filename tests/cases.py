@@ -35,3 +35,15 @@ def rel(a, b):
 def col_rel(A, B):
     """Largest per-column relative 2-norm difference of (c, n) arrays."""
     return max(rel(a, b) for a, b in zip(np.atleast_2d(A), np.atleast_2d(B)))
+
+
+def col_maxabs(A, B):
+    """Largest per-column max-entry difference relative to the column's largest
+    entry of B: an error confined to a few rows (a boundary row, a tile edge)
+    shows here at full size while the 2-norm dilutes it."""
+    A, B = np.atleast_2d(A), np.atleast_2d(B)
+    out = 0.0
+    for a, b in zip(A, B):
+        den = np.max(np.abs(b))
+        out = max(out, np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+    return out

@@ -4,12 +4,15 @@ Tolerance: relative 2-norm error <= 1e-8 for quantities that the GPU reaches
 by iterative solves to a 1e-10 relative residual (the oracle solves exactly);
 1e-12 for quantities without a solve (operator applies, cost).  Both solver
 precisions (FP64 and FP32 inside FP64 refinement) must meet the same bar.
+The solved fields and the Hessian actions also meet it entry by entry:
+max |gpu - oracle| <= 1e-8 max |oracle| per column, so that an error
+confined to a boundary row or a tile edge cannot hide in the 2-norm.
 """
 import numpy as np
 import pytest
 
 import synth
-from cases import col_rel, instance, rel
+from cases import col_maxabs, col_rel, instance, rel
 from oracle import model
 
 pytestmark = pytest.mark.gpu
@@ -59,14 +62,14 @@ def test_forward_cost_gradient(ctx, N, q, prec):
     md, ud, pd, gd = dev(m), dev(np.zeros(prob.n)), dev(np.zeros(prob.n)), dev(np.zeros(prob.n))
     info = gp.forward(md, ud)
     assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
-    assert rel(host(ud), u_o) < 1e-8
+    assert rel(host(ud), u_o) < 1e-8 and col_maxabs(host(ud), u_o) < 1e-8
     mis, reg = gp.cost(md, ud)
     assert abs(mis - mis_o) <= 1e-8 * abs(mis_o)
     assert abs(reg - reg_o) <= 1e-10 * abs(reg_o)
     info = gp.gradient(md, ud, pd, gd)
     assert info["rc"] == 0, info
-    assert rel(host(pd), p_o) < 1e-8
-    assert rel(host(gd), g_o) < 1e-8
+    assert rel(host(pd), p_o) < 1e-8 and col_maxabs(host(pd), p_o) < 1e-8
+    assert rel(host(gd), g_o) < 1e-8 and col_maxabs(host(gd), g_o) < 1e-8
     # exact data-consistent cost at the truth: u(m_true) reproduces B u_true
     Bu = dev(np.zeros(q))
     gp.forward(dev(m_true), ud)
@@ -94,6 +97,7 @@ def test_hessian_modes(ctx, N, q, nc, prec):
         ref = np.array([prob.hessian_apply(m, u, p, mh[c, :prob.n], mode) for c in range(nc)])
         res = host(out)
         assert col_rel(res[:, :prob.n], ref) < 1e-8, mode
+        assert col_maxabs(res[:, :prob.n], ref) < 1e-8, mode
         assert np.all(res[:, prob.n:] == 7.0)  # padding untouched
 
 
@@ -111,11 +115,11 @@ def test_incremental_solves(ctx, prec):
     ph = dev(np.zeros((nc, prob.n)))
     gp.inc_forward(dev(mh), uh)
     uh_o = np.array([prob.inc_forward(m, u, v) for v in mh])
-    assert col_rel(host(uh), uh_o) < 1e-8
+    assert col_rel(host(uh), uh_o) < 1e-8 and col_maxabs(host(uh), uh_o) < 1e-8
     for gn in (False, True):
         gp.inc_adjoint(dev(mh), uh, ph, gauss_newton=gn)
         ph_o = np.array([prob.inc_adjoint(m, p, v, w, gauss_newton=gn) for v, w in zip(mh, uh_o)])
-        assert col_rel(host(ph), ph_o) < 1e-8
+        assert col_rel(host(ph), ph_o) < 1e-8 and col_maxabs(host(ph), ph_o) < 1e-8
 
 
 @pytest.mark.parametrize("N", [4, 32, 256])
