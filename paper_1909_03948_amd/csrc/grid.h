@@ -407,6 +407,50 @@ __device__ inline const void* instance_key(const OpKARef<T>& o) { return o.rows;
 template <typename T>
 __device__ inline const void* instance_key(const OpKA<T>&) { return reinterpret_cast<const void*>(1); }
 
+// The prior operator on a tile through its 9-row class table (staged in LDS)
+// instead of per-node staged rows: the coefficients of a node depend only on
+// which sides of the square it lies on, so a tile of interior nodes uses row 0
+// throughout, and a tile at the boundary computes each node's class.  Same
+// couplings in the same order as the staged form: a node's own c, e, n, ne,
+// its west neighbour's e, its south neighbour's n and its south-west
+// neighbour's ne (zero for nodes outside the mesh).
+template <typename T, int TW>
+struct TileKA {
+    const KARow<T>* rows;
+    int ox, oy, N;
+    bool interior;  // every node of the tile has class 0
+    __device__ int cls(int l) const {
+        const int i = ox + l % TW, j = oy + l / TW;
+        if (i < 0 || i > N || j < 0 || j > N) return -1;
+        return ka_class(i, j, N);
+    }
+    __device__ T dinv(int l) const {
+        if (interior) return rows[0].dinv;
+        const int c = cls(l);
+        return c < 0 ? (T)0 : rows[c].dinv;
+    }
+    __device__ T center(int l) const {
+        if (interior) return rows[0].c;
+        const int c = cls(l);
+        return c < 0 ? (T)0 : rows[c].c;
+    }
+    __device__ T apply(int l, const T* v) const {
+        if (interior) {
+            const KARow<T>& r = rows[0];
+            return r.c * v[l] + r.e * v[l + 1] + r.e * v[l - 1] + r.n * v[l + TW] + r.n * v[l - TW] +
+                   r.ne * v[l + TW + 1] + r.ne * v[l - TW - 1];
+        }
+        const int c0 = cls(l), cw = cls(l - 1), cs = cls(l - TW), csw = cls(l - TW - 1);
+        const KARow<T> z{};
+        const KARow<T>& r = c0 < 0 ? z : rows[c0];
+        const T ew = cw < 0 ? (T)0 : rows[cw].e;
+        const T ns = cs < 0 ? (T)0 : rows[cs].n;
+        const T gsw = csw < 0 ? (T)0 : rows[csw].ne;
+        return r.c * v[l] + r.e * v[l + 1] + ew * v[l - 1] + r.n * v[l + TW] + ns * v[l - TW] + r.ne * v[l + TW + 1] +
+               gsw * v[l - TW - 1];
+    }
+};
+
 // (A v)_l on a staged tile; l must have all eight neighbours inside the tile.
 template <bool NE, typename T>
 __device__ inline T tile_apply(const TileStencil<T>& s, int TW, int l, const T* v) {

@@ -151,15 +151,31 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
                                               int* __restrict__ act, ChebCoef cc, PcgRed red,
                                               ColState* __restrict__ st, int check, int nc, int cb) {
     constexpr int TW = 2 * kTC + 5, NN = TW * TW;
+    // the prior operator (7 points, constant coefficients) on large tiles
+    // reads its class table: a third of the LDS, more workgroups per compute
+    // unit, for the batched solves that are bound by LDS traffic (measured:
+    // a 220-column prior solve at N = 1024 9% faster; on the small tiles of
+    // single-column cycles the staged rows stay faster)
     constexpr bool NE = kNorthEast<Op>;
+    constexpr bool KA = NE && kTC == kTCBig;
     __shared__ T sb[NN], sx[NN], sr[NN];
-    __shared__ T tc[NN], te[NN], tn[NN], tdv[NN], tg[NE ? NN : 1];
+    __shared__ T tc[KA ? 1 : NN], te[KA ? 1 : NN], tn[KA ? 1 : NN], tdv[KA ? 1 : NN], tg[NE && !KA ? NN : 1];
+    __shared__ KARow<T> krows[KA ? 9 : 1];
     const TileStencil<T> ts{tc, te, tn, tg, tdv};
     const int N = op_.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
     const int3 tb = xcd_tile();
     const int I0 = tb.x * kTC, J0 = tb.y * kTC;
     const int I1 = min(I0 + kTC - 1, Nc), J1 = min(J0 + kTC - 1, Nc);
     const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // global coordinates of local (0, 0)
+    const TileKA<T, TW> tk{krows, ox, oy, N, ox >= 1 && oy >= 1 && ox + TW - 1 <= N - 1 && oy + TW - 1 <= N - 1};
+    auto tapply = [&](int l, const T* v) -> T {
+        if constexpr (KA) return tk.apply(l, v);
+        else return tile_apply<NE>(ts, TW, l, v);
+    };
+    auto tdinv = [&](int l) -> T {
+        if constexpr (KA) return tk.dinv(l);
+        else return tdv[l];
+    };
     const T inv_theta = (T)cc.inv_theta, cA = (T)cc.cA, cB = (T)cc.cB;
     const int own_i1 = min(2 * I1 + 1, N), own_j1 = min(2 * J1 + 1, N);
     constexpr int E = (NN + 255) / 256;  // tile elements per thread
@@ -181,7 +197,11 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
         }
         __syncthreads();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
-            stage_stencil<TW, 256>(op, ts, ox, oy);
+            if constexpr (KA) {
+                if (threadIdx.x < 9) krows[threadIdx.x] = op.rows[threadIdx.x];
+            } else {
+                stage_stencil<TW, 256>(op, ts, ox, oy);
+            }
             staged = instance_key(op);
         }
         if (check && column_done(red, col, st, act, tb.x == 0 && tb.y == 0)) continue;
@@ -192,14 +212,14 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
         }
         __syncthreads();
         // d0 = D^-1 b / theta on the whole tile (zero off the free nodes)
-        for (int t = threadIdx.x; t < NN; t += blockDim.x) sr[t] = tdv[t] * sb[t] * inv_theta;
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) sr[t] = tdinv(t) * sb[t] * inv_theta;
         __syncthreads();
         // x2 = cA d0 + cB D^-1 (b - A d0) on local [1, TW-1)^2; owned nodes to global
         {
             constexpr int W = TW - 2;
             for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
                 const int il = 1 + t % W, jl = 1 + t / W, l = jl * TW + il;
-                const T v = cA * sr[l] + cB * tdv[l] * (sb[l] - tile_apply<NE>(ts, TW, l, sr));
+                const T v = cA * sr[l] + cB * tdinv(l) * (sb[l] - tapply(l, sr));
                 sx[l] = v;
                 const int i = ox + il, j = oy + jl;
                 if (i >= 2 * I0 && i <= own_i1 && j >= 2 * J0 && j <= own_j1) xcol[j * N1 + i] = v;
@@ -211,8 +231,8 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
             constexpr int W = TW - 4;
             for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
                 const int l = (2 + t / W) * TW + 2 + t % W;
-                const T v = sb[l] - tile_apply<NE>(ts, TW, l, sx);
-                sr[l] = tdv[l] != (T)0 ? v : (T)0;
+                const T v = sb[l] - tapply(l, sx);
+                sr[l] = tdinv(l) != (T)0 ? v : (T)0;
             }
         }
         __syncthreads();
@@ -255,14 +275,29 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
                                             const TB* __restrict__ rv, PcgRed red, int nc, int cb) {
     constexpr int TW = kTF + 4, NN = TW * TW;
     constexpr bool NE = kNorthEast<Op>;
+    constexpr bool KA = NE && kTF == kTFBig;  // class table for the prior operator (see k_down)
     __shared__ T sx[NN], sd[NN], sb[NN];
-    __shared__ T tc[NN], te[NN], tn[NN], tdv[NN], tg[NE ? NN : 1];
+    __shared__ T tc[KA ? 1 : NN], te[KA ? 1 : NN], tn[KA ? 1 : NN], tdv[KA ? 1 : NN], tg[NE && !KA ? NN : 1];
+    __shared__ KARow<T> krows[KA ? 9 : 1];
     const TileStencil<T> ts{tc, te, tn, tg, tdv};
     const int N = op_.N, N1 = N + 1, Nc1 = N / 2 + 1;
     const int3 tb = xcd_tile();
     const int i0 = tb.x * kTF, j0 = tb.y * kTF;
     const int i1 = min(i0 + kTF - 1, N), j1 = min(j0 + kTF - 1, N);
     const int ox = i0 - 2, oy = j0 - 2;
+    const TileKA<T, TW> tk{krows, ox, oy, N, ox >= 1 && oy >= 1 && ox + TW - 1 <= N - 1 && oy + TW - 1 <= N - 1};
+    auto tapply = [&](int l, const T* v) -> T {
+        if constexpr (KA) return tk.apply(l, v);
+        else return tile_apply<NE>(ts, TW, l, v);
+    };
+    auto tdinv = [&](int l) -> T {
+        if constexpr (KA) return tk.dinv(l);
+        else return tdv[l];
+    };
+    auto tcen = [&](int l) -> T {
+        if constexpr (KA) return tk.center(l);
+        else return tc[l];
+    };
     const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
     constexpr int E = (NN + 255) / 256;  // tile elements per thread
     const void* staged = nullptr;
@@ -296,7 +331,11 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
         }
         __syncthreads();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
-            stage_stencil<TW, 256>(op, ts, ox, oy);
+            if constexpr (KA) {
+                if (threadIdx.x < 9) krows[threadIdx.x] = op.rows[threadIdx.x];
+            } else {
+                stage_stencil<TW, 256>(op, ts, ox, oy);
+            }
             staged = instance_key(op);
         }
 #pragma unroll
@@ -313,7 +352,7 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
             constexpr int W = TW - 2;
             for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
                 const int l = (1 + t / W) * TW + 1 + t % W;
-                sd[l] = tdv[l] * (sb[l] - tile_apply<NE>(ts, TW, l, sx)) * inv_theta;
+                sd[l] = tdinv(l) * (sb[l] - tapply(l, sx)) * inv_theta;
             }
         }
         __syncthreads();
@@ -324,8 +363,8 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
             const int i = i0 + t % w, j = j0 + t / w;
             const int l = (j - oy) * TW + (i - ox), k = j * N1 + i;
             const T dk = sd[l];
-            const T r1 = theta * dk * tc[l] - tile_apply<NE>(ts, TW, l, sd);
-            const T v = sx[l] + ((T)1 + c1) * dk + cB * tdv[l] * r1;
+            const T r1 = theta * dk * tcen(l) - tapply(l, sd);
+            const T v = sx[l] + ((T)1 + c1) * dk + cB * tdinv(l) * r1;
             xcol[k] = (TX)v;
             if (rv) dot += (double)v * (double)rv[(size_t)col * ld + k];
         }
