@@ -182,7 +182,12 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
     const void* staged = nullptr;  // the staged rows belong to this instance
     const int c_end = min(nc, (tb.z + 1) * cb);
     for (int col = tb.z * cb; col < c_end; ++col) {
-        if (act && !act[col]) continue;
+        // with the convergence test on, the lead workgroup clears act[col]
+        // (column_done below) while other workgroups of this launch read it:
+        // one decision for the whole workgroup, or its waves could see
+        // different values and meet different barriers (without the test no
+        // kernel of the launch writes act)
+        if (act && !(check ? __syncthreads_or(act[col]) : act[col])) continue;
         const auto& op = op_.at(col);  // operator of the instance owning this column
         const TB* bcol = b + (size_t)col * ld;
         T* xcol = x + (size_t)col * ld;
@@ -855,7 +860,9 @@ __global__ __launch_bounds__(1024) void k_pcg_update(T* __restrict__ x, T* __res
                                                      int ld, int n, int* __restrict__ act,
                                                      ColState* __restrict__ st, PcgRed red) {
     const int col = blockIdx.y;
-    if (!act[col]) return;
+    // workgroup 0 clears act[col] on breakdown while the others read it: one
+    // decision per workgroup (see k_down)
+    if (!__syncthreads_or(act[col])) return;
     double spq = partial_first(red.pq, col, red.stride, red.nvec);
     const double rz = st[col].rz_new;
     const int k0 = blockIdx.x * red.chunk, k1 = min(n, k0 + red.chunk);
