@@ -18,7 +18,10 @@ namespace hinv {
 // workgroups) when few columns make the V-cycle latency bound.
 constexpr int kTCBig = 16, kTFBig = 32;      // coarse / fine nodes per tile side
 constexpr int kTCSmall = 8, kTFSmall = 16;
-constexpr int kTCTiny = 4, kTFTiny = 8;     // coarse levels of single-column cycles
+constexpr int kTPair = 4;      // k_down2: level-C tile side
+constexpr int kPairMaxN = 256;  // k_down2 pairs levels whose finer one has N_l <= this
+constexpr int kTFChain = 16;   // k_up_chain: level-0 tile side
+constexpr int kChainLen = 4;   // k_up_chain: levels a launch (measured: 4 > 2 at N = 1024)
 constexpr int kSmallTileCols = 8;            // batches below this use the small tiles
 constexpr int kBottomN = 32;   // levels with N_l <= kBottomN run in the bottom kernel
 constexpr int kBottomLevels = 4;  // at most (N_l = 64, 32, 16, 8 when kBottomN = 64)
@@ -377,6 +380,375 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
             const double sm = group_sum(dot);
             if (threadIdx.x == 0) red.rz[(size_t)col * red.stride + tb.y * gridDim.x + tb.x] = sm;
         }
+    }
+}
+
+// ------------------------------------------------- two levels a launch ---
+// Few columns make the coarse levels latency bound: a launch there costs
+// ~4.5 us however small its level.  k_down2 does the down steps of two
+// consecutive levels F (N) and M (N/2) in one launch, k_up_chain the up
+// steps of up to kChainMax levels: each workgroup recomputes the coarser
+// values its tile needs on a larger tile (redundant work on the halo instead
+// of more launches).  The arithmetic per node is that of k_down / k_up, so
+// the cycle's result is the same bit for bit.
+
+// Grid: (tiles over level-C x, tiles over level-C y, column blocks), C = N/4.
+// Level-C tile [K0, K0+kT) x [L0, L0+kT) needs b_M on level-M nodes
+// [2 K0 - 3, 2 K1 + 3] (the k_down tile of width MW = 2 kT + 5), which in
+// turn needs b_F on the level-F tile of width FW = 2 MW + 5.  Writes x2_F and
+// x2_M, and b_M (read again by the up step of level M) on the nodes the tile
+// owns, and b_C on the level-C tile.
+template <typename T, class Op, int kT, int NT>
+__global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restrict__ bF, T* __restrict__ xF,
+                                               int ldF, T* __restrict__ bM, T* __restrict__ xM, int ldM,
+                                               T* __restrict__ bC, int ldC, int dirichlet,
+                                               const int* __restrict__ act, ChebCoef cc, int nc, int cb) {
+    constexpr int MW = 2 * kT + 5, FW = 2 * MW + 5, NM = MW * MW, NF = FW * FW;
+    constexpr bool NE = kNorthEast<Op>;
+    __shared__ T fb[NF], fx[NF], fr[NF];
+    __shared__ T fc[NF], fe[NF], fn[NF], fdv[NF], fg[NE ? NF : 1];
+    __shared__ T mb[NM], mx[NM], mr[NM];
+    __shared__ T mc[NM], me[NM], mn[NM], mdv[NM], mg[NE ? NM : 1];
+    const TileStencil<T> tsF{fc, fe, fn, fg, fdv}, tsM{mc, me, mn, mg, mdv};
+    const int Nf = opF_.N, Nf1 = Nf + 1, Nm = Nf / 2, Nm1 = Nm + 1, Nc = Nm / 2, Nc1 = Nc + 1;
+    const int3 tb = xcd_tile();
+    const int K0 = tb.x * kT, L0 = tb.y * kT;
+    const int K1 = min(K0 + kT - 1, Nc), L1 = min(L0 + kT - 1, Nc);
+    const int mox = 2 * K0 - 3, moy = 2 * L0 - 3;  // level-M coordinates of local (0, 0)
+    const int fox = 2 * mox - 3, foy = 2 * moy - 3;  // level-F coordinates of local (0, 0)
+    // owned nodes: level M [2 K0, 2 K1 + 1], level F [2 i0, 2 i1 + 1] of those
+    const int mi0 = 2 * K0, mj0 = 2 * L0, mi1 = min(2 * K1 + 1, Nm), mj1 = min(2 * L1 + 1, Nm);
+    const int fi0 = 2 * mi0, fj0 = 2 * mj0, fi1 = min(2 * mi1 + 1, Nf), fj1 = min(2 * mj1 + 1, Nf);
+    const T inv_theta = (T)cc.inv_theta, cA = (T)cc.cA, cB = (T)cc.cB;
+    constexpr int E = (NF + NT - 1) / NT;
+    const void* staged = nullptr;
+    const int c_end = min(nc, (tb.z + 1) * cb);
+    for (int col = tb.z * cb; col < c_end; ++col) {
+        // no kernel of the launch writes act (the convergence test runs on the finest level)
+        if (act && !act[col]) continue;
+        const auto& opF = opF_.at(col);
+        const auto& opM = opM_.at(col);
+        const T* bcol = bF + (size_t)col * ldF;
+        T vb[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + NT * e;
+            const int i = fox + t % FW, j = foy + t / FW;
+            vb[e] = (t < NF && i >= 0 && i <= Nf && j >= 0 && j <= Nf) ? bcol[j * Nf1 + i] : (T)0;
+        }
+        __syncthreads();  // the previous column's LDS reads are done
+        if (instance_key(opF) != staged) {
+            stage_stencil<FW, NT>(opF, tsF, fox, foy);
+            stage_stencil<MW, NT>(opM, tsM, mox, moy);
+            staged = instance_key(opF);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = threadIdx.x + NT * e;
+            if (t < NF) fb[t] = vb[e];
+        }
+        __syncthreads();
+        // level F: d0 = D^-1 b / theta; x2 = cA d0 + cB D^-1 (b - A d0) on
+        // local [1, FW-1)^2 (owned nodes to global); residual on [2, FW-2)^2
+        for (int t = threadIdx.x; t < NF; t += blockDim.x) fr[t] = fdv[t] * fb[t] * inv_theta;
+        __syncthreads();
+        {
+            T* xcol = xF + (size_t)col * ldF;
+            constexpr int W = FW - 2;
+            for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+                const int il = 1 + t % W, jl = 1 + t / W, l = jl * FW + il;
+                const T v = cA * fr[l] + cB * fdv[l] * (fb[l] - tile_apply<NE>(tsF, FW, l, fr));
+                fx[l] = v;
+                const int i = fox + il, j = foy + jl;
+                if (i >= fi0 && i <= fi1 && j >= fj0 && j <= fj1) xcol[j * Nf1 + i] = v;
+            }
+        }
+        __syncthreads();
+        {
+            constexpr int W = FW - 4;
+            for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+                const int l = (2 + t / W) * FW + 2 + t % W;
+                const T v = fb[l] - tile_apply<NE>(tsF, FW, l, fx);
+                fr[l] = fdv[l] != (T)0 ? v : (T)0;
+            }
+        }
+        __syncthreads();
+        // P^T onto the whole level-M tile: b_M, zero off the mesh and on
+        // Dirichlet rows; owned nodes to global
+        {
+            T* bcol2 = bM + (size_t)col * ldM;
+            auto res = [&](int i, int j) { return fr[(j - foy) * FW + (i - fox)]; };
+            for (int t = threadIdx.x; t < NM; t += blockDim.x) {
+                const int I = mox + t % MW, J = moy + t / MW;
+                T v = 0;
+                if (I >= 0 && I <= Nm && J >= 0 && J <= Nm && !(dirichlet && (J == 0 || J == Nm))) {
+                    const int i = 2 * I, j = 2 * J;
+                    T sm = 0;
+                    if (i > 0) sm += res(i - 1, j);
+                    if (i < Nf) sm += res(i + 1, j);
+                    if (j > 0) sm += res(i, j - 1);
+                    if (j < Nf) sm += res(i, j + 1);
+                    if (i < Nf && j < Nf) sm += res(i + 1, j + 1);
+                    if (i > 0 && j > 0) sm += res(i - 1, j - 1);
+                    v = res(i, j) + (T)0.5 * sm;
+                }
+                if (I >= mi0 && I <= mi1 && J >= mj0 && J <= mj1) bcol2[J * Nm1 + I] = v;
+                mb[t] = v;
+            }
+        }
+        __syncthreads();
+        // level M: the same three steps on the level-M tile
+        for (int t = threadIdx.x; t < NM; t += blockDim.x) mr[t] = mdv[t] * mb[t] * inv_theta;
+        __syncthreads();
+        {
+            T* xcol = xM + (size_t)col * ldM;
+            constexpr int W = MW - 2;
+            for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+                const int il = 1 + t % W, jl = 1 + t / W, l = jl * MW + il;
+                const T v = cA * mr[l] + cB * mdv[l] * (mb[l] - tile_apply<NE>(tsM, MW, l, mr));
+                mx[l] = v;
+                const int I = mox + il, J = moy + jl;
+                if (I >= mi0 && I <= mi1 && J >= mj0 && J <= mj1) xcol[J * Nm1 + I] = v;
+            }
+        }
+        __syncthreads();
+        {
+            constexpr int W = MW - 4;
+            for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+                const int l = (2 + t / W) * MW + 2 + t % W;
+                const T v = mb[l] - tile_apply<NE>(tsM, MW, l, mx);
+                mr[l] = mdv[l] != (T)0 ? v : (T)0;
+            }
+        }
+        __syncthreads();
+        // P^T onto the level-C tile
+        T* bccol = bC + (size_t)col * ldC;
+        const int cw = K1 - K0 + 1, ch = L1 - L0 + 1;
+        auto res = [&](int I, int J) { return mr[(J - moy) * MW + (I - mox)]; };
+        for (int t = threadIdx.x; t < cw * ch; t += blockDim.x) {
+            const int K = K0 + t % cw, L = L0 + t / cw;
+            T v = 0;
+            if (!(dirichlet && (L == 0 || L == Nc))) {
+                const int I = 2 * K, J = 2 * L;
+                T sm = 0;
+                if (I > 0) sm += res(I - 1, J);
+                if (I < Nm) sm += res(I + 1, J);
+                if (J > 0) sm += res(I, J - 1);
+                if (J < Nm) sm += res(I, J + 1);
+                if (I < Nm && J < Nm) sm += res(I + 1, J + 1);
+                if (I > 0 && J > 0) sm += res(I - 1, J - 1);
+                v = res(I, J) + (T)0.5 * sm;
+            }
+            bccol[L * Nc1 + K] = v;
+        }
+    }
+}
+
+// Up steps of NL consecutive levels 0 (finest of the chain) .. NL-1 in one
+// launch.  Grid: (tiles over level-0 x, tiles over level-0 y, column blocks).
+// Level 0 is the k_up tile: the output tile O of kTF x kTF nodes at local
+// [2, kTF+2) of a tile of width W_0 = kTF + 4 whose every node forms
+// x2 + P x_1.  The level-(k+1) values that prolongation reads are the nodes
+// [floor(o_k / 2), ceil((o_k + W_k - 1) / 2)] (o_k: the tile's origin), at
+// most (W_k + 1) / 2 + 1 of them per side; they are the output region of the
+// level-(k+1) up step on a tile two nodes wider on each side, so
+// o_{k+1} = floor(o_k / 2) - 2 and W_{k+1} = (W_k + 1) / 2 + 5.  The widths
+// settle at 11, so the redundant work per level stays bounded (kTF = 16:
+// 20, 15, 13, 12, 11, ...); each level still adds its passes to the
+// workgroup's latency.  Every input (b and x2 of each level,
+// the level-NL correction x_C, the operator rows) is loaded at the start; the
+// levels then run coarse to fine in LDS.  Writes x of level 0 on O only (the
+// coarser x are used by nothing else).
+template <int kTF>
+constexpr int chain_width(int k) {
+    int w = kTF + 4;
+    for (int i = 0; i < k; ++i) w = (w + 1) / 2 + 5;
+    return w;
+}
+template <int kTF>
+constexpr int chain_offset(int k) {
+    int s = 0;
+    for (int i = 0; i < k; ++i) s += chain_width<kTF>(i) * chain_width<kTF>(i);
+    return s;
+}
+constexpr int kChainMax = kChainLen;  // levels a chain may hold
+
+template <typename T, class Op>
+struct ChainArgs {
+    Op op[kChainMax];
+    const T* b[kChainMax];
+    const T* x2[kChainMax];
+    int ld[kChainMax];
+    T* x;         // level-0 output
+    const T* xc;  // level-NL correction (from the level below the chain)
+    int ldc;
+};
+
+// Row of node (i, j) in the tile-stencil form (zero off the mesh), same
+// arithmetic as stage_stencil.
+template <typename T>
+struct TileRow {
+    T c, e, n, g, dv;
+};
+template <typename T>
+__device__ inline TileRow<T> tile_row(const OpA<T>& op, int i, int j) {
+    const int N = op.N, N1 = N + 1, k = j * N1 + i;
+    if (i < 0 || i > N || j < 0 || j > N) return TileRow<T>{};
+    const T we = op.wE[k], wn = op.wN[k], ww = i > 0 ? op.wE[k - 1] : (T)0, ws = j > 0 ? op.wN[k - N1] : (T)0;
+    return TileRow<T>{we + wn + ww + ws, -we, -wn, (T)0, op.dinv[k]};
+}
+template <typename T, class OpK>
+__device__ inline TileRow<T> tile_row(const OpK& op, int i, int j) {
+    const int N = op.N;
+    if (i < 0 || i > N || j < 0 || j > N) return TileRow<T>{};
+    const KARow<T>& r = op.rows[ka_class(i, j, N)];
+    return TileRow<T>{r.c, r.e, r.n, r.ne, r.dinv};
+}
+
+// Level k of the chain (then k - 1, ..., 0): x2 + P x_{k+1} (except on the
+// coarsest level, whose P x_C came with the loads), d0, then x in place
+// (level 0: to global on O).
+template <typename T, class Op, int kTF, int NL, int k>
+__device__ inline void chain_step(const ChainArgs<T, Op>& a, const int* ox, const int* oy, T* sx, T* sd,
+                                  const T* sb, const TileStencil<T>& ts, int dirichlet, const ChebCoef& cc,
+                                  int i0, int i1, int j0, int j1, int col) {
+    constexpr int W = chain_width<kTF>(k), off = chain_offset<kTF>(k), NN = W * W;
+    constexpr bool NE = kNorthEast<Op>;
+    const TileStencil<T> st{ts.c + off, ts.e + off, ts.n + off, NE ? ts.g + off : ts.g, ts.dv + off};
+    T* x = sx + off;
+    T* d = sd + off;
+    const T* b = sb + off;
+    const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
+    if constexpr (k < NL - 1) {
+        constexpr int W1 = chain_width<kTF>(k + 1), off1 = chain_offset<kTF>(k + 1);
+        const T* x1 = sx + off1;
+        const int N = a.op[k].N, ox1 = ox[k + 1], oy1 = oy[k + 1];
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) {
+            const int i = ox[k] + t % W, j = oy[k] + t / W;
+            if (i >= 0 && i <= N && j >= 0 && j <= N && !(dirichlet && (j == 0 || j == N))) {
+                const int I = i >> 1, J = j >> 1;
+                const T p0 = x1[(J - oy1) * W1 + (I - ox1)];
+                x[t] += ((i | j) & 1) ? (T)0.5 * (p0 + x1[(J + (j & 1) - oy1) * W1 + (I + (i & 1) - ox1)]) : p0;
+            }
+        }
+        __syncthreads();
+    }
+    {
+        constexpr int Wi = W - 2;
+        for (int t = threadIdx.x; t < Wi * Wi; t += blockDim.x) {
+            const int l = (1 + t / Wi) * W + 1 + t % Wi;
+            d[l] = st.dv[l] * (b[l] - tile_apply<NE>(st, W, l, x)) * inv_theta;
+        }
+    }
+    __syncthreads();
+    if constexpr (k > 0) {
+        // x on [2, W-2)^2 in place of x2 + P x (each node reads only its own entry)
+        constexpr int Wi = W - 4;
+        for (int t = threadIdx.x; t < Wi * Wi; t += blockDim.x) {
+            const int l = (2 + t / Wi) * W + 2 + t % Wi;
+            const T dk = d[l];
+            const T r1 = theta * dk * st.c[l] - tile_apply<NE>(st, W, l, d);
+            x[l] = x[l] + ((T)1 + c1) * dk + cB * st.dv[l] * r1;
+        }
+        __syncthreads();
+        chain_step<T, Op, kTF, NL, k - 1>(a, ox, oy, sx, sd, sb, ts, dirichlet, cc, i0, i1, j0, j1, col);
+    } else {
+        const int N1 = a.op[0].N + 1;
+        T* xcol = a.x + (size_t)col * a.ld[0];
+        const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+        for (int t = threadIdx.x; t < w * h; t += blockDim.x) {
+            const int i = i0 + t % w, j = j0 + t / w;
+            const int l = (j - oy[0]) * W + (i - ox[0]);
+            const T dk = d[l];
+            const T r1 = theta * dk * st.c[l] - tile_apply<NE>(st, W, l, d);
+            xcol[j * N1 + i] = x[l] + ((T)1 + c1) * dk + cB * st.dv[l] * r1;
+        }
+    }
+}
+
+// Loads of level k of the chain (then k + 1, ...), kept in registers until
+// every level's loads are issued, then stored to LDS: b, x2 (plus P x_C on
+// the coarsest level) and, when stage is set, the operator rows.
+template <typename T, class Op, int kTF, int NL, int NT, int k>
+__device__ inline void chain_load(const ChainArgs<T, Op>& a, const int* ox, const int* oy, int dirichlet, int col,
+                                  bool stage, T* sx, T* sb, const TileStencil<T>& ts) {
+    constexpr int W = chain_width<kTF>(k), off = chain_offset<kTF>(k), NN = W * W, E = (NN + NT - 1) / NT;
+    constexpr bool NE = kNorthEast<Op>;
+    const Op& op = a.op[k];
+    const int N = op.N;
+    T vb[E], vx[E];
+    TileRow<T> vr[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + NT * e;
+        const int i = ox[k] + t % W, j = oy[k] + t / W;
+        const bool in = t < NN && i >= 0 && i <= N && j >= 0 && j <= N;
+        const bool fr = in && !(dirichlet && (j == 0 || j == N));
+        const size_t g = (size_t)col * a.ld[k] + (size_t)j * (N + 1) + i;
+        vb[e] = in ? a.b[k][g] : (T)0;
+        T v = fr ? a.x2[k][g] : (T)0;
+        if constexpr (k == NL - 1) {
+            // P x_C: the coarse node when i and j are even, else the mean of
+            // the two coarse ends of the fine edge through (i, j)
+            if (fr) {
+                const int Nc1 = N / 2 + 1, I = i >> 1, J = j >> 1;
+                const T* xcc = a.xc + (size_t)col * a.ldc;
+                const T p0 = xcc[J * Nc1 + I];
+                v += ((i | j) & 1) ? (T)0.5 * (p0 + xcc[(J + (j & 1)) * Nc1 + I + (i & 1)]) : p0;
+            }
+        }
+        vx[e] = v;
+        vr[e] = stage && t < NN ? tile_row<T>(op.at(col), i, j) : TileRow<T>{};
+    }
+    if constexpr (k + 1 < NL) chain_load<T, Op, kTF, NL, NT, k + 1>(a, ox, oy, dirichlet, col, stage, sx, sb, ts);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = threadIdx.x + NT * e;
+        if (t < NN) {
+            sb[off + t] = vb[e];
+            sx[off + t] = vx[e];
+            if (stage) {
+                ts.c[off + t] = vr[e].c;
+                ts.e[off + t] = vr[e].e;
+                ts.n[off + t] = vr[e].n;
+                if constexpr (NE) ts.g[off + t] = vr[e].g;
+                ts.dv[off + t] = vr[e].dv;
+            }
+        }
+    }
+}
+
+template <typename T, class Op, int kTF, int NL, int NT>
+__global__ __launch_bounds__(NT) void k_up_chain(ChainArgs<T, Op> a, int dirichlet, const int* __restrict__ act,
+                                                 ChebCoef cc, int nc, int cb) {
+    static_assert(kTF % 2 == 0 && NL >= 2 && NL <= kChainMax, "chain shape");
+    constexpr int NA = chain_offset<kTF>(NL);  // nodes of all the chain's tiles
+    constexpr bool NE = kNorthEast<Op>;
+    __shared__ T sx[NA], sd[NA], sb[NA];
+    __shared__ T tc[NA], te[NA], tn[NA], tdv[NA], tg[NE ? NA : 1];
+    const TileStencil<T> ts{tc, te, tn, tg, tdv};
+    const int3 tb = xcd_tile();
+    const int i0 = tb.x * kTF, j0 = tb.y * kTF;
+    const int i1 = min(i0 + kTF - 1, a.op[0].N), j1 = min(j0 + kTF - 1, a.op[0].N);
+    int ox[NL], oy[NL];
+    ox[0] = i0 - 2;
+    oy[0] = j0 - 2;
+#pragma unroll
+    for (int k = 1; k < NL; ++k) {
+        ox[k] = (ox[k - 1] >> 1) - 2;  // floor(o / 2) - 2
+        oy[k] = (oy[k - 1] >> 1) - 2;
+    }
+    const void* staged = nullptr;
+    const int c_end = min(nc, (tb.z + 1) * cb);
+    for (int col = tb.z * cb; col < c_end; ++col) {
+        // no kernel of the launch writes act (the convergence test runs on the finest level)
+        if (act && !act[col]) continue;
+        const void* key = instance_key(a.op[0].at(col));
+        __syncthreads();  // the previous column's LDS reads are done
+        chain_load<T, Op, kTF, NL, NT, 0>(a, ox, oy, dirichlet, col, key != staged, sx, sb, ts);
+        staged = key;
+        __syncthreads();
+        chain_step<T, Op, kTF, NL, NL - 1>(a, ox, oy, sx, sd, sb, ts, dirichlet, cc, i0, i1, j0, j1, col);
     }
 }
 

@@ -2,6 +2,8 @@
 // right-hand sides, in FP64 or as FP32 PCG inside FP64 iterative refinement.
 #pragma once
 
+#include <algorithm>
+#include <cstdlib>
 #include <functional>
 
 #include <memory>
@@ -132,12 +134,12 @@ class Hierarchy {
         int chunk = 0;
     };
     bool small_tiles(int l) const { return shape_.small || lev_[l]->N <= shape_.small_max; }
-    // levels N_l <= 128 below the finest level of a cycle with small tiles
-    // everywhere (few columns: latency bound) shrink the tiles once more,
-    // shortening each workgroup's passes (measured: faster there, slower on
-    // the bandwidth-bound N = 512 level; the finest level keeps the tiles its
-    // partial sums are counted by)
-    bool tiny_tiles(int l) const { return shape_.small && l > 0 && lev_[l]->N <= 128; }
+    // Cycles with small tiles everywhere (few columns: the coarse launches are
+    // latency bound) run two coarse levels a launch; one instance only
+    // (HINV_NO_PAIRS: one level a launch throughout).
+    bool pair_levels() const { return shape_.small && ninst_ == 1 && !no_pairs_; }
+    bool no_pairs_ = std::getenv("HINV_NO_PAIRS") != nullptr;
+    int cus_ = 0;  // compute units of the device
     LaunchShape default_shape(int nc) const;
     int min_per() const;
     template <typename T>

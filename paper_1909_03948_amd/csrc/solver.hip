@@ -414,6 +414,7 @@ Hierarchy::Hierarchy(Ctx* ctx, OpKind kind, int N, PriorParams pp, int ninst,
                      const PriorParams* inst_pp)
     : ctx_(ctx), kind_(kind), N_(N), n_((N + 1) * (N + 1)), pp_(pp), ninst_(ninst) {
     if (ninst < 1) fail(HINV_EINVAL, "a hierarchy needs at least one instance");
+    HINV_HIP(hipDeviceGetAttribute(&cus_, hipDeviceAttributeMultiprocessorCount, ctx->device));
     inst_pp_.assign(ninst, pp);
     if (inst_pp)
         for (int i = 0; i < ninst; ++i) inst_pp_[i] = inst_pp[i];
@@ -920,6 +921,30 @@ void Hierarchy::vcycle(int nc, int check) {
     vcycle_impl<T, float>(nc, check);
 }
 
+// k_up_chain for NL levels with nt threads per workgroup (template dispatch).
+template <typename T, class Op, int NL, int NT>
+static void launch_chain1(dim3 g, hipStream_t s, const ChainArgs<T, Op>& ca, int dir, const int* act,
+                          const ChebCoef& cc, int nc, int cb) {
+    hipLaunchKernelGGL((k_up_chain<T, Op, kTFChain, NL, NT>), g, dim3(NT), 0, s, ca, dir, act, cc, nc, cb);
+}
+template <typename T, class Op, int NL>
+static void launch_chain_nt(int nt, dim3 g, hipStream_t s, const ChainArgs<T, Op>& ca, int dir, const int* act,
+                            const ChebCoef& cc, int nc, int cb) {
+    if (nt == 512)
+        launch_chain1<T, Op, NL, 512>(g, s, ca, dir, act, cc, nc, cb);
+    else
+        launch_chain1<T, Op, NL, 256>(g, s, ca, dir, act, cc, nc, cb);
+}
+template <typename T, class Op>
+static void launch_chain(int NL, int nt, dim3 g, hipStream_t s, const ChainArgs<T, Op>& ca, int dir,
+                         const int* act, const ChebCoef& cc, int nc, int cb) {
+    switch (NL) {
+        case 2: launch_chain_nt<T, Op, 2>(nt, g, s, ca, dir, act, cc, nc, cb); break;
+        case 3: launch_chain_nt<T, Op, 3>(nt, g, s, ca, dir, act, cc, nc, cb); break;
+        default: launch_chain_nt<T, Op, 4>(nt, g, s, ca, dir, act, cc, nc, cb); break;
+    }
+}
+
 template <typename T, typename TI>
 void Hierarchy::vcycle_impl(int nc, int check) {
     hipStream_t s = launch_stream_;
@@ -933,10 +958,49 @@ void Hierarchy::vcycle_impl(int nc, int check) {
     const ChebCoef cc = cheb_coef();
     PcgRed red = pcg_red(nc);
     constexpr double st = sizeof(T), si = sizeof(TI);
+    // Few columns: pair[l] = levels l and l + 1 take one k_down2 launch
+    // (coarse levels paired from the bottom up while the finer of the two has
+    // N_l <= kPairMaxN: above it the larger tiles cost what the launch saves),
+    // and the up steps of levels chain_lo .. Lb-1 one k_up_chain launch.
+    std::vector<char> pair(nlev, 0);
+    std::vector<int> chain(nlev, 0);  // chain[l] = n: the up steps of levels l-n+1 .. l in one launch
+    if (pair_levels()) {
+        for (int l = Lb - 2; l >= 1 && lev_[l]->N <= kPairMaxN; l -= 2) pair[l] = true;
+        // chains of up to kChainLen levels from the bottom up; a last one of
+        // a single level stays a plain k_up
+        for (int top = Lb - 1; top >= 2; top -= kChainLen) chain[top] = std::min(kChainLen, top);
+    }
+    // workgroups of 512 threads where a launch has fewer tiles than compute
+    // units (each workgroup's passes are then the whole launch's latency)
+    auto threads_for = [&](int tiles) { return tiles < cus_ ? 512 : 256; };
 
     for (int l = 0; l < Lb; ++l) {
         const Level& L = *lev_[l];
         const Level& C = *lev_[l + 1];
+        if (pair[l]) {
+            const Level& Cc = *lev_[l + 2];
+            with_op<TI>(l, [&](auto opF) {
+                with_op<TI>(l + 1, [&](auto opM) {
+                    if constexpr (std::is_same_v<decltype(opF), decltype(opM)>) {
+                        using Op = decltype(opF);
+                        const int tc = ceil_div(Cc.N + 1, kTPair), gz = ceil_div(nc, shape_.cb);
+                        auto go = [&](auto kern, int nt) {
+                            timed_launch(ctx_, -1, 0.0, kern, dim3(tc, tc, gz), dim3(nt), s, opF, opM,
+                                         (const TI*)wi.lb[l]->get(), wi.lt[l]->get(), L.n, wi.lb[l + 1]->get(),
+                                         wi.lt[l + 1]->get(), C.n, wi.lb[l + 2]->get(), Cc.n, dir,
+                                         (const int*)act, cc, nc, shape_.cb);
+                        };
+                        if (threads_for(tc * tc) == 512)
+                            go(k_down2<TI, Op, kTPair, 512>, 512);
+                        else
+                            go(k_down2<TI, Op, kTPair, 256>, 256);
+                    }
+                });
+            });
+            HINV_LAUNCH_CHECK();
+            ++l;
+            continue;
+        }
         // algorithmic bytes: read b, write x2 and b_coarse per column; the state
         // operator's three coefficient arrays once per launch and instance
         const double bytes_down = nc * ((l == 0 ? st : si) * L.n + si * (L.n + C.n)) + (dir ? si * 3.0 * L.n * ninst_ : 0.0);
@@ -1030,6 +1094,36 @@ void Hierarchy::vcycle_impl(int nc, int check) {
     for (int l = Lb - 1; l >= 0; --l) {
         const Level& L = *lev_[l];
         const Level& C = *lev_[l + 1];
+        if (chain[l] >= 2) {
+            const int NL = chain[l], lo = l - NL + 1;
+            with_op<TI>(lo, [&](auto op0) {
+                using Op = decltype(op0);
+                ChainArgs<TI, Op> ca{};
+                bool same = true;
+                for (int k = 0; k < NL; ++k) {
+                    const int lk = lo + k;
+                    with_op<TI>(lk, [&](auto opk) {
+                        if constexpr (std::is_same_v<decltype(opk), Op>)
+                            ca.op[k] = opk;
+                        else
+                            same = false;
+                    });
+                    ca.b[k] = wi.lb[lk]->get();
+                    ca.x2[k] = wi.lt[lk]->get();
+                    ca.ld[k] = lev_[lk]->n;
+                }
+                if (!same) fail(HINV_EINVAL, "internal: mixed operator types in a chain");
+                ca.x = wi.lx[lo]->get();
+                ca.xc = wi.lx[l + 1]->get();
+                ca.ldc = lev_[l + 1]->n;
+                const int tf = ceil_div(lev_[lo]->N + 1, kTFChain), gz = ceil_div(nc, shape_.cb);
+                launch_chain<TI, Op>(NL, threads_for(tf * tf), dim3(tf, tf, gz), s, ca, dir, act, cc, nc,
+                                     shape_.cb);
+            });
+            HINV_LAUNCH_CHECK();
+            l = lo;  // the loop's decrement continues below the chain
+            continue;
+        }
         // read b, x2, x_coarse (and r for r^T z), write x; coefficients once per instance
         const double bytes_up = nc * ((l == 0 ? 3.0 * st : 2.0 * si) * L.n + si * (L.n + C.n)) +
                                 (dir ? si * 3.0 * L.n * ninst_ : 0.0);
