@@ -108,10 +108,12 @@ __device__ inline double group_sum(double v) {
 }
 
 // Convergence test at the start of a V-cycle: r^T r of the PCG update that
-// precedes it is summed from its partials; a column at its tolerance stops
-// (every workgroup reaches the same decision; workgroup 0 records it).
-__device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int* act, bool lead) {
-    const double rr = partial_total(red.rr, col, red.stride, red.nvec);
+// precedes it is summed from its partials (share: this thread's part of
+// them, loaded ahead by the caller); a column at its tolerance stops (every
+// workgroup reaches the same decision; workgroup 0 records it).
+__device__ inline bool column_done_share(double share, const PcgRed& red, int col, ColState* st, int* act,
+                                         bool lead) {
+    const double rr = share_total(share);
     const ColState& c = st[col];
     const bool done = rr <= c.tol2 * c.bb;
     if (lead && threadIdx.x == 0) {
@@ -119,6 +121,9 @@ __device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int
         if (done) act[col] = 0;
     }
     return done;
+}
+__device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int* act, bool lead) {
+    return column_done_share(partial_share(red.rr, col, red.stride, red.nvec), red, col, st, act, lead);
 }
 
 // XCD-aware tile order.  The hardware hands consecutive workgroups to the
@@ -194,8 +199,8 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
         const auto& op = op_.at(col);  // operator of the instance owning this column
         const TB* bcol = b + (size_t)col * ld;
         T* xcol = x + (size_t)col * ld;
-        // loads first: b, then the operator rows, then the convergence test,
-        // so that their latencies overlap
+        // loads first: b, the convergence test's partials, then the operator
+        // rows, so that their latencies overlap
         T vb[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -203,6 +208,7 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
             const int i = ox + t % TW, j = oy + t / TW;
             vb[e] = (t < NN && i >= 0 && i <= N && j >= 0 && j <= N) ? (T)bcol[j * N1 + i] : (T)0;
         }
+        const double rr_share = check ? partial_share(red.rr, col, red.stride, red.nvec) : 0.0;
         __syncthreads();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
             if constexpr (KA) {
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
             }
             staged = instance_key(op);
         }
-        if (check && column_done(red, col, st, act, tb.x == 0 && tb.y == 0)) continue;
+        if (check && column_done_share(rr_share, red, col, st, act, tb.x == 0 && tb.y == 0)) continue;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int t = threadIdx.x + 256 * e;
@@ -337,6 +343,15 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
             pc1[e] = fr ? ccol[a1] : (T)0;
             even[e] = !((i | j) & 1);
         }
+        // rv at the output nodes, in the order of the output loop below
+        const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+        constexpr int EO = (kTF * kTF + 255) / 256;
+        TB rvv[EO];
+#pragma unroll
+        for (int e = 0; e < EO; ++e) {
+            const int t = threadIdx.x + 256 * e;
+            rvv[e] = (rv && t < w * h) ? rv[(size_t)col * ld + (j0 + t / w) * N1 + (i0 + t % w)] : (TB)0;
+        }
         __syncthreads();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
             if constexpr (KA) {
@@ -366,15 +381,18 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
         __syncthreads();
         // x += (1 + c1) d0 + cB D^-1 r1 on O with r1 = r0 - A d0 = theta D d0 - A d0
         double dot = 0.0;
-        const int w = i1 - i0 + 1, h = j1 - j0 + 1;
-        for (int t = threadIdx.x; t < w * h; t += blockDim.x) {
-            const int i = i0 + t % w, j = j0 + t / w;
-            const int l = (j - oy) * TW + (i - ox), k = j * N1 + i;
-            const T dk = sd[l];
-            const T r1 = theta * dk * tcen(l) - tapply(l, sd);
-            const T v = sx[l] + ((T)1 + c1) * dk + cB * tdinv(l) * r1;
-            xcol[k] = (TX)v;
-            if (rv) dot += (double)v * (double)rv[(size_t)col * ld + k];
+#pragma unroll
+        for (int e = 0; e < EO; ++e) {
+            const int t = threadIdx.x + 256 * e;
+            if (t < w * h) {
+                const int i = i0 + t % w, j = j0 + t / w;
+                const int l = (j - oy) * TW + (i - ox), k = j * N1 + i;
+                const T dk = sd[l];
+                const T r1 = theta * dk * tcen(l) - tapply(l, sd);
+                const T v = sx[l] + ((T)1 + c1) * dk + cB * tdinv(l) * r1;
+                xcol[k] = (TX)v;
+                if (rv) dot += (double)v * (double)rvv[e];
+            }
         }
         if (rv) {
             const double sm = group_sum(dot);
