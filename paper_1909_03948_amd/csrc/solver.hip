@@ -35,18 +35,6 @@ namespace hinv {
 
 namespace {
 
-// Chebyshev degree-2 constants for the interval [kChebLo, kChebHi].
-struct Cheb {
-    double theta, delta, rho0, rho1;
-    Cheb() {
-        theta = 0.5 * (kChebHi + kChebLo);
-        delta = 0.5 * (kChebHi - kChebLo);
-        const double sigma = theta / delta;
-        rho0 = 1.0 / sigma;
-        rho1 = 1.0 / (2.0 * sigma - rho0);
-    }
-};
-
 inline dim3 grid2(int n, int nc) { return dim3(ceil_div(n, kBlock), nc); }
 
 template <typename T>
@@ -961,9 +949,9 @@ void Hierarchy::vcycle_impl(int nc, int check) {
     // Few columns: pair[l] = levels l and l + 1 take one k_down2 launch
     // (coarse levels paired from the bottom up while the finer of the two has
     // N_l <= kPairMaxN: above it the larger tiles cost what the launch saves),
-    // and the up steps of levels chain_lo .. Lb-1 one k_up_chain launch.
+    // and chain[l] = n: the up steps of levels l-n+1 .. l one k_up_chain launch.
     std::vector<char> pair(nlev, 0);
-    std::vector<int> chain(nlev, 0);  // chain[l] = n: the up steps of levels l-n+1 .. l in one launch
+    std::vector<int> chain(nlev, 0);
     if (pair_levels()) {
         for (int l = Lb - 2; l >= 1 && lev_[l]->N <= kPairMaxN; l -= 2) pair[l] = true;
         // chains of up to kChainLen levels from the bottom up; a last one of
