@@ -195,15 +195,20 @@ enum KClass {
 // Launch of a timed class (-1: untimed): a sampled launch carries the class's
 // next event pair in its dispatch.
 template <typename F, typename... Args>
-inline void timed_launch(Ctx* ctx, int cls, double work, F kernel, dim3 grid, dim3 block,
-                         hipStream_t s, Args... args) {
+inline void timed_launch_shm(Ctx* ctx, int cls, double work, F kernel, dim3 grid, dim3 block, size_t shm,
+                             hipStream_t s, Args... args) {
     const int slot = ctx->timer.sample(cls, work);
     if (slot >= 0) {
         auto& k = ctx->timer.cls[cls];
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, k.ev[2 * slot], k.ev[2 * slot + 1], 0, args...);
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, k.ev[2 * slot], k.ev[2 * slot + 1], 0, args...);
     } else {
-        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
     }
+}
+template <typename F, typename... Args>
+inline void timed_launch(Ctx* ctx, int cls, double work, F kernel, dim3 grid, dim3 block,
+                         hipStream_t s, Args... args) {
+    timed_launch_shm(ctx, cls, work, kernel, grid, block, 0, s, args...);
 }
 
 // ------------------------------------------------------------ constants ---

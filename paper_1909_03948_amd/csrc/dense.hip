@@ -193,6 +193,123 @@ __global__ __launch_bounds__(512) void k_gram_bf16(int n, int s1, int s2, int ch
         }
 }
 
+// Wide Gram for s2 <= 16 kWideMaxCT: grid.x = row blocks of rt row tiles,
+// grid.y = K chunk.  A workgroup of eight waves stages the K step's rows of
+// Y for all CT column tiles in LDS (double-buffered), so a K chunk of Y is
+// read once per row block, and waves 0 .. rt-1 each compute one 16-row tile
+// of the output against the CT column tiles (CT matrix-core accumulators).
+// The output is covered by 16 x 16 tiles instead of 128 x 128 blocks (s =
+// 220: 224^2 instead of 256^2 products).  For X = Y (self) a wave's A
+// operand comes from the same staged rows, so X is not read at all.
+constexpr int kWideKC = 32, kWideMaxCT = 16;
+__host__ __device__ constexpr int wide_ld(int ct) { return 16 * ct + 16; }  // rows k, k + 1 in different bank halves
+
+template <int CT>
+__global__ __launch_bounds__(512) void k_gram_wide(int n, int s1, int s2, int chunk, int rt, int self,
+                                                   const double* __restrict__ X, int ldx,
+                                                   const double* __restrict__ Y, int ldy,
+                                                   double* __restrict__ part) {
+    extern __shared__ double wsh[];  // [2][kWideKC][LD]
+    constexpr int LD = wide_ld(CT), SEG = 16 * CT * (kWideKC / 8), SPT = (SEG + 511) / 512;
+    int blk, split;
+    xcd_block_chunk(gridDim.x, gridDim.y, blk, split);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rtile = blk * rt + wave;
+    const bool rows_on = wave < rt && rtile * 16 < s1;  // this wave has output rows (all waves stage Y)
+    const int i = rtile * 16 + (lane & 15);
+    const int kr = lane >> 4;
+    const int k_begin = split * chunk;
+    const int k_end = min(n, k_begin + chunk);
+    const double* xc = X + (size_t)(i < s1 ? i : 0) * ldx;
+    // staging: segment g = 8 consecutive rows (g mod 4) of column g / 4
+    double stg[SPT][8];
+    auto load_stage = [&](int k0) {
+#pragma unroll
+        for (int sp = 0; sp < SPT; ++sp) {
+            const int g = threadIdx.x + 512 * sp;
+            const int j = g >> 2, r8 = (g & 3) * 8;
+            const bool jok = g < SEG && j < s2;
+            const double* yc = Y + (size_t)(jok ? j : 0) * ldy;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + r8 + e;
+                stg[sp][e] = (jok && k < k_end) ? yc[k] : 0.0;
+            }
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int sp = 0; sp < SPT; ++sp) {
+            const int g = threadIdx.x + 512 * sp;
+            if (g < SEG) {
+                const int j = g >> 2, r8 = (g & 3) * 8;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) wsh[(buf * kWideKC + r8 + e) * LD + j] = stg[sp][e];
+            }
+        }
+    };
+    // X != Y: a wave's A operand of the next K step is loaded with the staging
+    // loads, a step ahead of its use
+    double xa[kWideKC / 4];
+    auto load_x = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < kWideKC / 4; ++u) {
+            const int k = k0 + 4 * u + kr;
+            xa[u] = (!self && rows_on && i < s1 && k < k_end) ? xc[k] : 0.0;
+        }
+    };
+    d4_t acc[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    load_stage(k_begin);
+    load_x(k_begin);
+    store_stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = k_begin; k0 < k_end; k0 += kWideKC) {
+        const bool more = k0 + kWideKC < k_end;
+        double a[kWideKC / 4];
+#pragma unroll
+        for (int u = 0; u < kWideKC / 4; ++u) a[u] = xa[u];
+        if (more) {
+            load_stage(k0 + kWideKC);
+            load_x(k0 + kWideKC);
+        }
+        if (rows_on) {
+            // A[l % 16][l / 16] = X[k0 + 4 u + l / 16][i], B[l / 16][l % 16] = Y[k0 + 4 u + l / 16][16 t + l % 16]
+            const double* yb = wsh + (buf * kWideKC + kr) * LD + (lane & 15);
+            if (self) {
+#pragma unroll
+                for (int u = 0; u < kWideKC / 4; ++u) a[u] = yb[4 * u * LD + 16 * rtile];
+            }
+#pragma unroll
+            for (int u = 0; u < kWideKC / 4; ++u)
+#pragma unroll
+                for (int t = 0; t < CT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], yb[4 * u * LD + t * 16], acc[t], 0, 0, 0);
+        }
+        // the other buffer was last read before the previous barrier
+        if (more) store_stage(1 - buf);
+        __syncthreads();
+        buf = 1 - buf;
+    }
+    if (!rows_on) return;
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+        for (int v = 0; v < 4; ++v) {
+            const int gi = rtile * 16 + 4 * v + (lane >> 4);
+            const int gj = t * 16 + (lane & 15);
+            if (gi < s1 && gj < s2) part[((size_t)split * s2 + gj) * s1 + gi] = acc[t][v];
+        }
+}
+
+template <int CT>
+void launch_gram_wide(Ctx* ctx, double flops, dim3 g, size_t shm, int n, int s1, int s2, int chunk, int rt, int self,
+                      const double* X, int ldx, const double* Y, int ldy, double* part) {
+    timed_launch_shm(ctx, kKGram, flops, k_gram_wide<CT>, g, dim3(512), shm, ctx->stream, n, s1, s2, chunk, rt, self,
+                     X, ldx, Y, ldy, part);
+}
+
 // C = sum of the nsplit partial products.  A workgroup of 64 x kRedLanes
 // threads owns 64 consecutive entries: lane y sums chunks y, y + kRedLanes, ...
 // and the kRedLanes sums are added in lane order (a fixed order).
@@ -824,6 +941,35 @@ __global__ void k_scale_rows(int s, int t, const double* __restrict__ d, double*
 
 void gram(Ctx* ctx, DenseWork& w, int n, int s1, int s2, const double* X, int ldx, const double* Y,
           int ldy, double* C, int ldc, bool bf16) {
+    if (!bf16 && s2 <= 16 * kWideMaxCT) {
+        const int ct = ceil_div(s2, 16), rtt = ceil_div(s1, 16);
+        const int nrb = ceil_div(rtt, 8), rt = ceil_div(rtt, nrb);
+        int cus = 0;
+        HINV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        // about one workgroup a compute unit (the staging takes most of the
+        // LDS), chunks of at least 256 rows in whole K steps
+        int nsplit = std::max(1, std::min(ceil_div(cus, nrb), ceil_div(n, 256)));
+        const int chunk = ceil_div(ceil_div(n, nsplit), kWideKC) * kWideKC;
+        nsplit = ceil_div(n, chunk);
+        w.part.ensure((size_t)nsplit * s1 * s2);
+        const size_t shm = sizeof(double) * 2 * kWideKC * wide_ld(ct);
+        const int self = X == Y && ldx == ldy && s1 <= s2;
+        const dim3 g(nrb, nsplit);
+        const double flops = 2.0 * n * s1 * s2;
+        switch (ct) {
+#define HINV_WIDE(c) \
+    case c: launch_gram_wide<c>(ctx, flops, g, shm, n, s1, s2, chunk, rt, self, X, ldx, Y, ldy, w.part.get()); break;
+            HINV_WIDE(1) HINV_WIDE(2) HINV_WIDE(3) HINV_WIDE(4) HINV_WIDE(5) HINV_WIDE(6) HINV_WIDE(7) HINV_WIDE(8)
+            HINV_WIDE(9) HINV_WIDE(10) HINV_WIDE(11) HINV_WIDE(12) HINV_WIDE(13) HINV_WIDE(14) HINV_WIDE(15)
+            default: launch_gram_wide<16>(ctx, flops, g, shm, n, s1, s2, chunk, rt, self, X, ldx, Y, ldy, w.part.get());
+#undef HINV_WIDE
+        }
+        HINV_LAUNCH_CHECK();
+        k_gram_reduce<<<ceil_div(s1 * s2, 64), 64 * kRedLanes, 0, ctx->stream>>>(s1, s2, nsplit, w.part.get(), C,
+                                                                                ldc);
+        HINV_LAUNCH_CHECK();
+        return;
+    }
     const int blocks = ((s1 + kBlk - 1) / kBlk) * ((s2 + kBlk - 1) / kBlk);
     // K split: about 2048 workgroups, chunks of at least 256 rows (a multiple
     // of the 16-row matrix-core step)
