@@ -343,14 +343,15 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
             pc1[e] = fr ? ccol[a1] : (T)0;
             even[e] = !((i | j) & 1);
         }
-        // rv at the output nodes, in the order of the output loop below
+        // small tiles (one output node a thread, the few-column cycles): rv at
+        // the thread's output node is loaded with the tile; large tiles read it
+        // at use (prefetching four values costs them occupancy)
         const int w = i1 - i0 + 1, h = j1 - j0 + 1;
-        constexpr int EO = (kTF * kTF + 255) / 256;
-        TB rvv[EO];
-#pragma unroll
-        for (int e = 0; e < EO; ++e) {
-            const int t = threadIdx.x + 256 * e;
-            rvv[e] = (rv && t < w * h) ? rv[(size_t)col * ld + (j0 + t / w) * N1 + (i0 + t % w)] : (TB)0;
+        constexpr bool kPre = kTF * kTF <= 256;
+        TB rv0 = 0;
+        if constexpr (kPre) {
+            const int t = threadIdx.x;
+            if (rv && t < w * h) rv0 = rv[(size_t)col * ld + (j0 + t / w) * N1 + (i0 + t % w)];
         }
         __syncthreads();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
@@ -381,18 +382,14 @@ __global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, co
         __syncthreads();
         // x += (1 + c1) d0 + cB D^-1 r1 on O with r1 = r0 - A d0 = theta D d0 - A d0
         double dot = 0.0;
-#pragma unroll
-        for (int e = 0; e < EO; ++e) {
-            const int t = threadIdx.x + 256 * e;
-            if (t < w * h) {
-                const int i = i0 + t % w, j = j0 + t / w;
-                const int l = (j - oy) * TW + (i - ox), k = j * N1 + i;
-                const T dk = sd[l];
-                const T r1 = theta * dk * tcen(l) - tapply(l, sd);
-                const T v = sx[l] + ((T)1 + c1) * dk + cB * tdinv(l) * r1;
-                xcol[k] = (TX)v;
-                if (rv) dot += (double)v * (double)rvv[e];
-            }
+        for (int t = threadIdx.x; t < w * h; t += blockDim.x) {
+            const int i = i0 + t % w, j = j0 + t / w;
+            const int l = (j - oy) * TW + (i - ox), k = j * N1 + i;
+            const T dk = sd[l];
+            const T r1 = theta * dk * tcen(l) - tapply(l, sd);
+            const T v = sx[l] + ((T)1 + c1) * dk + cB * tdinv(l) * r1;
+            xcol[k] = (TX)v;
+            if (rv) dot += (double)v * (double)(kPre ? rv0 : rv[(size_t)col * ld + k]);
         }
         if (rv) {
             const double sm = group_sum(dot);

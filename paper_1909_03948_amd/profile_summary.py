@@ -34,7 +34,7 @@ import sys
 
 CLASSES = (("hinv::k_down<", "mg_down"), ("hinv::k_up<", "mg_up"), ("hinv::k_bottom<", "mg_bottom"),
            ("hinv::k_pcg_apply<", "pcg_apply"), ("hinv::k_pcg_update<", "pcg_update"),
-           ("k_gram_bf16", "gram"), ("k_gram_f64", "gram"))
+           ("k_gram_bf16", "gram"), ("k_gram_f64", "gram"), ("k_gram_wide", "gram"))
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
