@@ -18,6 +18,7 @@ namespace hinv {
 // workgroups) when few columns make the V-cycle latency bound.
 constexpr int kTCBig = 16, kTFBig = 32;      // coarse / fine nodes per tile side
 constexpr int kTCSmall = 8, kTFSmall = 16;
+constexpr int kTCWide = 9, kTFWide = 18;     // finest level of small-tile cycles with many workgroups
 constexpr int kTPair = 4;      // k_down2: level-C tile side
 constexpr int kPairMaxN = 256;  // k_down2 pairs levels whose finer one has N_l <= this
 constexpr int kTFChain = 16;   // k_up_chain: level-0 tile side
@@ -153,8 +154,8 @@ __device__ inline int3 xcd_tile() {
 // the workgroup then sweeps cb consecutive columns.
 // b may be of a wider type TB than the level's vectors (the finest level of a
 // V-cycle in FP32 preconditioning an FP64 PCG reads the FP64 residual).
-template <typename T, class Op, int kTC, typename TB = T>
-__global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, T* __restrict__ x,
+template <typename T, class Op, int kTC, typename TB = T, int WPE = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_down(Op op_, const TB* __restrict__ b, T* __restrict__ x,
                                               int ld, T* __restrict__ bc, int ldc, int dirichlet,
                                               int* __restrict__ act, ChebCoef cc, PcgRed red,
                                               ColState* __restrict__ st, int check, int nc, int cb) {
@@ -281,8 +282,8 @@ __global__ __launch_bounds__(256) void k_down(Op op_, const TB* __restrict__ b, 
 // workgroup's part of sum_k rv_k x_k (the PCG inner product r^T z).
 // b and rv may be of a wider type TB and the output x of a wider type TX than
 // the level's vectors (see k_down).
-template <typename T, class Op, int kTF, typename TB = T, typename TX = T>
-__global__ __launch_bounds__(256) void k_up(Op op_, const TB* __restrict__ b, const T* __restrict__ x2,
+template <typename T, class Op, int kTF, typename TB = T, typename TX = T, int WPE = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_up(Op op_, const TB* __restrict__ b, const T* __restrict__ x2,
                                             TX* __restrict__ x, int ld, const T* __restrict__ xc,
                                             int ldc, int dirichlet,
                                             const int* __restrict__ act, ChebCoef cc,

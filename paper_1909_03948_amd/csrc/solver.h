@@ -140,6 +140,7 @@ class Hierarchy {
     bool pair_levels() const { return shape_.small && ninst_ == 1 && !no_pairs_; }
     bool no_pairs_ = std::getenv("HINV_NO_PAIRS") != nullptr;
     int cus_ = 0;  // compute units of the device
+    bool finest_wide(int nc) const;
     LaunchShape default_shape(int nc) const;
     int min_per() const;
     template <typename T>

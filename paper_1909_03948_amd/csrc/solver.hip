@@ -615,6 +615,18 @@ static void ensure_work(PcgWork<T>& w, const std::vector<std::unique_ptr<Level>>
     w.cap = nc;
 }
 
+// The finest level of a small-tile cycle takes 9 x 9 coarse / 18 x 18 fine
+// tiles at eight waves a SIMD when its 8 x 8 / 16 x 16 tiles (seven
+// workgroups a compute unit) would need more than two rounds of workgroups:
+// at N = 1024, 4 225 workgroups in three rounds against 3 249 in two, 20%
+// more halo work each (measured: one-column actions 3% faster there, 2%
+// slower at N = 256, where one round holds the smaller tiles).
+bool Hierarchy::finest_wide(int nc) const {
+    if (!shape_.small || lev_.size() < 2 || lev_[0]->N <= kBottomN) return false;
+    const long long t = ceil_div(lev_[1]->N + 1, kTCSmall);
+    return t * t * ceil_div(nc, shape_.cb) > 2LL * 7 * cus_;
+}
+
 static ChebCoef cheb_coef() {
     const double theta = 0.5 * (kChebHi + kChebLo), delta = 0.5 * (kChebHi - kChebLo);
     const double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
@@ -637,8 +649,7 @@ PcgRed Hierarchy::pcg_red(int nc) const {
     r.rr = r.pq + (size_t)red_stride_ * cap_;
     int Lb = 0;
     while (lev_[Lb]->N > kBottomN) ++Lb;
-    (void)nc;
-    const int tf = small_tiles(0) ? kTFSmall : kTFBig;
+    const int tf = finest_wide(nc) ? kTFWide : small_tiles(0) ? kTFSmall : kTFBig;
     r.nrz = Lb == 0 ? 1 : ceil_div(lev_[0]->N + 1, tf) * ceil_div(lev_[0]->N + 1, tf);
     r.per = shape_.per;
     r.chunk = shape_.chunk > 0 ? shape_.chunk : kBlock * r.per;
@@ -1006,7 +1017,9 @@ void Hierarchy::vcycle_impl(int nc, int check) {
                              dir, act, cc, red, stp, chk, nc, cb);
             };
             if (l == 0) {
-                if (small_tiles(l))
+                if (finest_wide(nc))
+                    launch(k_down<TI, Op, kTCWide, T, 8>, kTCWide, (const T*)wt.r.get());
+                else if (small_tiles(l))
                     launch(k_down<TI, Op, kTCSmall, T>, kTCSmall, (const T*)wt.r.get());
                 else
                     launch(k_down<TI, Op, kTCBig, T>, kTCBig, (const T*)wt.r.get());
@@ -1129,7 +1142,9 @@ void Hierarchy::vcycle_impl(int nc, int check) {
             };
             if (l == 0) {
                 const T* r = wt.r.get();
-                if (small_tiles(l))
+                if (finest_wide(nc))
+                    launch(k_up<TI, Op, kTFWide, T, T, 8>, kTFWide, r, wt.z.get(), r);
+                else if (small_tiles(l))
                     launch(k_up<TI, Op, kTFSmall, T, T>, kTFSmall, r, wt.z.get(), r);
                 else
                     launch(k_up<TI, Op, kTFBig, T, T>, kTFBig, r, wt.z.get(), r);
