@@ -122,7 +122,9 @@ def test_fig2_analog_on_the_gpu(ctx, map32):
         assert np.max(np.abs(lam1 - o1)) <= 1e-8 * exact[0]
 
 
-@pytest.mark.parametrize("N,s", [(32, 50), (256, 100)])
+# s = 300 is the paper's r-bar (Sec. 4.4.1); above 256 columns the block
+# products take the 128 x 128-block kernels instead of the whole-row ones
+@pytest.mark.parametrize("N,s", [(32, 50), (256, 100), (32, 300)])
 def test_prior_variance_matches_oracle(ctx, N, s):
     print(f"[gpu-sp] prior variance N={N} s={s}", flush=True)
     prob, _, obs = instance(N, 10)
