@@ -1289,12 +1289,15 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
     tune_shape<T>(nc);
     const bool graphs = !std::getenv("HINV_NO_GRAPHS");
     // The prologue (V-cycle of the initial residual, first iteration) is a
-    // graph too.  While the kernel timer runs, every 16th solve launches its
-    // second and third iterations eagerly with every launch sampled: like the
-    // replayed iterations they find the operator in cache (the prologue's
-    // first V-cycle does not); graph replays are counted only.
+    // graph too.  While the kernel timer runs, every 16th solve of few columns
+    // and every batched solve launch their second and third iterations eagerly
+    // with every launch sampled: like the replayed iterations they find the
+    // operator in cache (the prologue's first V-cycle does not); graph replays
+    // are counted only.  (Batched kernels run for a millisecond or more, so
+    // their eager launches cost nothing measurable, and sampling each batched
+    // solve keeps the mix of operators in the class averages fixed.)
     int it = 0;
-    bool sampled = ctx_->timer.any_on() && solves_++ % 16 == 0;
+    bool sampled = ctx_->timer.any_on() && (nc >= kSmallTileCols || solves_++ % 16 == 0);
     if (graphs && max_iter > 0) {
         HINV_HIP(hipGraphLaunch(prologue_graph<T>(nc), s));
         it = 1;

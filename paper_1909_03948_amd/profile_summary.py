@@ -3,6 +3,8 @@
     python -m paper_1909_03948_amd.profile_summary trace <rocprofv3 -d dir> <out.json>
     python -m paper_1909_03948_amd.profile_summary pmc <rocprofv3 -d dir> <out.json>
     python -m paper_1909_03948_amd.profile_summary traffic <fetch.json> <write.json> <workload> <traffic.json>
+    python -m paper_1909_03948_amd.profile_summary markdown <trace.json> <bench.json> <traffic.json> <workload> <profiles dir>
+    python -m paper_1909_03948_amd.profile_summary stats-markdown <rocprofv3 -d dir> <bench.json> <out.md>
 
 The classes match the library's sampled timer: mg_down / mg_up are the fused
 V-cycle kernels of the finest level only (in dispatch order, the first k_down
@@ -21,7 +23,11 @@ with a 256 MiB copy), the reference for scaling the counter to bytes.
 `traffic` scales a FETCH_SIZE and a WRITE_SIZE summary of one workload by
 their copies (256 MiB read and written) into HBM bytes per launch and merges
 them into the traffic file under that workload, with the hash of the kernel
-sources they were taken on.
+sources they were taken on.  `markdown` writes the two committed summaries of
+a workload (kernel_trace_<workload>.md, hbm_traffic.md) from a trace
+summary, the benchmark's JSON line of the same workload and the traffic
+file; `stats-markdown` writes the top kernels of a rocprofv3 --stats run
+(the learned-preconditioner workload) beside its benchmark line.
 """
 from __future__ import annotations
 
@@ -162,7 +168,115 @@ def merge_traffic(fetch_json, write_json, workload, out):
     return doc["workloads"][workload]
 
 
+def _bench_line(path):
+    return json.loads(open(path).read().strip().splitlines()[-1])
+
+
+def write_markdown(trace_json, bench_json, traffic_json, workload, outdir):
+    """kernel_trace_<workload>.md and hbm_traffic.md from the summaries."""
+    t = json.load(open(trace_json))
+    b = _bench_line(bench_json)
+    doc = json.load(open(traffic_json))
+    pm = doc["workloads"][workload]
+    cfg = b.get("config", {})
+    what = (f"{cfg['N']} x {cfg['N']} mesh: Newton-CG MAP, double pass k = {cfg['k']}, p = {cfg['p']}, "
+            f"{cfg.get('posterior_samples', 0)} posterior samples") if "N" in cfg and "k" in cfg else "benchmark workload"
+    L = [f"# Kernel trace: {workload} ({what})\n",
+         "Command (from the repository root, on the MI355X machine; the run's CSV stays under its output directory):\n",
+         "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o run -- "
+         "python3 <repo>/bench.py --steps 1 --warmup 1 --no-extras --no-cpu-baseline\n",
+         "Summarized with `python -m paper_1909_03948_amd.profile_summary trace <out>/trace <out>/trace.json` and "
+         "`python -m paper_1909_03948_amd.profile_summary markdown <out>/trace.json <bench.json> profiles/pmc_traffic.json "
+         f"{workload} profiles`.  One warm-up and one timed step.\n",
+         f"Total kernel time {t['total_ms']:.1f} ms over {t['dispatches']} dispatches (profiled run, both steps).\n",
+         "## Timed classes: trace against the benchmark's live HIP-event samples\n",
+         "Live figures: `python bench.py --steps 3 --warmup 1` (same workload, no profiler).  The classes without `_b` "
+         "are the finest-level kernels of single-right-hand-side solves (the Newton-CG phase), `_b` the same kernels in "
+         "batched solves (eigensolver passes, samples).  The events time the eagerly launched second and third PCG "
+         "iterations of every 16th single-column solve and of every batched solve; the trace averages every "
+         "finest-level dispatch, graph replays included.\n",
+         "| class | trace dispatches | trace avg µs | bench sampled | bench avg µs | algorithmic bytes (or flops) per launch "
+         "| bench rate | HBM bytes per launch (counters) |",
+         "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for c, v in t["classes"].items():
+        k = b.get("kernels", {}).get(c, {})
+        unit = "TFLOP/s" if c == "gram" else "GB/s"
+        rate = k.get("rate", 0.0) / (1e3 if c == "gram" else 1.0)
+        hb = pm["kernels"].get(c, {}).get("hbm_bytes_per_launch")
+        L.append(f"| {c} | {v['dispatches']} | {v['avg_us']:.2f} | {k.get('timed', '-')} | {k.get('avg_us', 0.0):.2f} | "
+                 f"{k.get('work_per_launch', 0.0):.4g} | {rate:.0f} {unit} | {f'{hb:.4g}' if hb else '-'} |")
+    r = b.get("roofline")
+    if r:
+        L.append(f"\nBench roofline line: dominant bandwidth-bound class `{r['kernel']}` ({r['population']}), "
+                 f"{r['avg_us']:.2f} µs per launch (events; trace {t['classes'][r['kernel']]['avg_us']:.2f} µs), "
+                 f"achieved {r['achieved']:.0f} GB/s of {r['peak']:.0f} ({100 * r['frac']:.1f}%).\n")
+    L += ["## Top kernels (all levels)\n", "| kernel | calls | total ms | share | avg µs |", "|---|---:|---:|---:|---:|"]
+    for k in t["top_kernels"][:16]:
+        L.append(f"| `{k['kernel']}` | {k['calls']} | {k['total_ms']:.2f} | {100 * k['share']:.1f}% | {k['avg_us']:.2f} |")
+    open(os.path.join(outdir, f"kernel_trace_{workload}.md"), "w").write("\n".join(L) + "\n")
+    c = pm["calibration"]
+    H = ["# HBM traffic of the timed classes (rocprofv3 counters)\n",
+         "Commands (one counter per run, on the MI355X machine):\n",
+         "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/FETCH_SIZE -o run -- "
+         "python3 <repo>/bench.py --steps 1 --warmup 0 --no-extras --no-cpu-baseline --calibration-copy",
+         "    (the same with --pmc WRITE_SIZE)",
+         "    python -m paper_1909_03948_amd.profile_summary pmc <out>/FETCH_SIZE <out>/FETCH_SIZE.json   (and WRITE_SIZE)",
+         f"    python -m paper_1909_03948_amd.profile_summary traffic <out>/FETCH_SIZE.json <out>/WRITE_SIZE.json {workload} "
+         "profiles/pmc_traffic.json\n",
+         "Each counter is averaged over the finest-level dispatches of a class (single-column and batched populations "
+         "apart, by the finest level's precision in the kernel name) and scaled by what it reads for the run's closing "
+         "256 MiB device copy.  `bench.py` reports the HBM bytes per launch of each class while the V-cycle kernel "
+         "sources hash to `source_hash`.\n",
+         f"## {workload}\n",
+         f"Calibration: FETCH_SIZE {c['fetch_kib']:.0f} KiB and WRITE_SIZE {c['write_kib']:.0f} KiB for 256 MiB read and "
+         f"written: factors {c['fetch_factor']:.4f} and {c['write_factor']:.4f}; kernel sources {pm['source_hash']}.\n",
+         "| class | dispatches | fetch bytes / launch | write bytes / launch | HBM bytes / launch | algorithmic bytes / "
+         "launch (bench) | HBM / algorithmic |",
+         "|---|---:|---:|---:|---:|---:|---:|"]
+    for cl, v in pm["kernels"].items():
+        alg = b.get("kernels", {}).get(cl, {}).get("work_per_launch")
+        ratio = f"{v['hbm_bytes_per_launch'] / alg:.2f}" if alg and cl != "gram" else "-"
+        H.append(f"| {cl} | {v['dispatches']} | {v['fetch_bytes_per_launch']:.4g} | {v['write_bytes_per_launch']:.4g} | "
+                 f"{v['hbm_bytes_per_launch']:.4g} | {f'{alg:.4g}' if alg else '-'} | {ratio} |")
+    if cfg.get("n_params") and cfg.get("k") is not None:
+        nn, ss = cfg["n_params"], cfg["k"] + cfg.get("p", 0)
+        H.append(f"\nThe gram row's algorithmic figure is flops, not bytes: its compulsory traffic is n (s1 + s2) 8 bytes "
+                 f"= {nn * 2 * ss * 8:.3g} at n = {nn}, s = {ss} (X ≠ Y; half of it for YᵀY).")
+    open(os.path.join(outdir, "hbm_traffic.md"), "w").write("\n".join(H) + "\n")
+
+
+def write_stats_markdown(d, bench_json, out):
+    """Top kernels of a rocprofv3 --stats run beside the benchmark line (learned workload)."""
+    rows = read_csv(d, "kernel_stats.csv")
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    b = _bench_line(bench_json)
+    keys = ("value", "unit", "harvest_s", "train_s", "heldout_energy_loss", "solvers")
+    L = ["# Kernel trace: learned1024 (harvest 20 000 pairs on the 1024 x 1024 problem, 4 000 Adam steps of the "
+         "residual CNN, flexible CG with and without it)\n",
+         "Command (from the repository root, on the MI355X machine):\n",
+         "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <out>/learned -o run "
+         "-- python3 <repo>/bench.py --workload learned1024\n",
+         "Summarized with `python -m paper_1909_03948_amd.profile_summary stats-markdown <out>/learned <bench.json> "
+         "profiles/kernel_trace_learned1024.md`, the bench line from `python bench.py --workload learned1024`.\n",
+         f"Total kernel time {tot / 1e6:.1f} ms.  The convolution kernels multiply BF16 operands on the matrix cores "
+         "(gfx950 16x16x32 for the 32-channel layers); their rate counts 2 x pixels x 9 x C_in x C_out flops per layer "
+         "and image.\n",
+         "Bench line of the same workload (no profiler): " + json.dumps({k: b.get(k) for k in keys}) + "\n",
+         "| kernel | calls | total ms | share | avg µs |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:20]:
+        L.append(f"| `{short(r['Name'])[:90]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                 f"{100 * float(r['TotalDurationNs']) / tot:.1f}% | {float(r['AverageNs']) / 1e3:.2f} |")
+    open(out, "w").write("\n".join(L) + "\n")
+
+
 def main(argv):
+    if len(argv) == 7 and argv[1] == "markdown":
+        write_markdown(argv[2], argv[3], argv[4], argv[5], argv[6])
+        return
+    if len(argv) == 5 and argv[1] == "stats-markdown":
+        write_stats_markdown(argv[2], argv[3], argv[4])
+        return
     if len(argv) == 6 and argv[1] == "traffic":
         res = merge_traffic(argv[2], argv[3], argv[4], argv[5])
         print(json.dumps({c: round(v["hbm_bytes_per_launch"]) for c, v in res["kernels"].items()}))

@@ -110,3 +110,33 @@ def test_batched_variants_form_their_own_population():
 def test_short_names_keep_helper_kernels():
     assert ps.short("void hinv::(anonymous namespace)::k_cheb_mass<32>(hinv::OpKA<double>, int)") == "k_cheb_mass<32>"
     assert ps.short("void hinv::k_up<float, hinv::OpA<float>, 16>(hinv::OpA<float>)") == "k_up<float, OpA<float>, 16>"
+
+
+def test_markdown_summaries_from_the_json_summaries(tmp_path):
+    """The committed summaries are written from the trace summary, the bench
+    line and the traffic file; every timed class gets a row with its figures."""
+    trace = {"total_ms": 12.5, "dispatches": 40,
+             "classes": {"mg_down": {"dispatches": 4, "avg_us": 18.0}, "gram": {"dispatches": 1, "avg_us": 2900.0}},
+             "top_kernels": [{"kernel": "k_down<float>", "calls": 4, "total_ms": 0.072, "share": 0.5, "avg_us": 18.0}]}
+    bench = {"config": {"N": 1024, "k": 200, "p": 20, "posterior_samples": 1000, "n_params": 1050625},
+             "kernels": {"mg_down": {"timed": 3, "avg_us": 19.0, "work_per_launch": 2.0e7, "rate": 1052.0},
+                         "gram": {"timed": 1, "avg_us": 2950.0, "work_per_launch": 1.0e11, "rate": 35000.0}},
+             "roofline": {"kernel": "mg_down", "population": "single right-hand side", "avg_us": 19.0,
+                          "achieved": 1052.0, "peak": 8000.0, "frac": 0.1315}}
+    traffic = {"workloads": {"poisson1024": {
+        "source_hash": "abc", "calibration": {"fetch_kib": 131091, "write_kib": 262144, "fetch_factor": 2.0,
+                                              "write_factor": 1.0},
+        "kernels": {"mg_down": {"dispatches": 4, "fetch_bytes_per_launch": 1.5e7, "write_bytes_per_launch": 4.5e6,
+                                "hbm_bytes_per_launch": 1.95e7}}}}}
+    for name, doc in (("trace.json", trace), ("traffic.json", traffic)):
+        json.dump(doc, open(tmp_path / name, "w"))
+    (tmp_path / "bench.json").write_text("[bench] log line\n" + json.dumps(bench) + "\n")
+    ps.write_markdown(str(tmp_path / "trace.json"), str(tmp_path / "bench.json"), str(tmp_path / "traffic.json"),
+                      "poisson1024", str(tmp_path))
+    kt = (tmp_path / "kernel_trace_poisson1024.md").read_text()
+    assert "1024 x 1024 mesh" in kt and "| mg_down | 4 | 18.00 | 3 | 19.00 | 2e+07 | 1052 GB/s | 1.95e+07 |" in kt
+    assert "| gram | 1 | 2900.00 | 1 | 2950.00 | 1e+11 | 35 TFLOP/s | - |" in kt
+    assert "achieved 1052 GB/s of 8000 (13.2%)" in kt
+    hb = (tmp_path / "hbm_traffic.md").read_text()
+    assert "| mg_down | 4 | 1.5e+07 | 4.5e+06 | 1.95e+07 | 2e+07 | 0.97 |" in hb
+    assert "kernel sources abc" in hb
