@@ -14,6 +14,18 @@
 
 namespace hinv {
 
+// Workgroup barrier for data exchanged through LDS.  __syncthreads() also
+// orders global memory, so every wave first waits for all of its outstanding
+// global loads; no kernel here exchanges data through global memory within a
+// launch (each reads buffers that only earlier launches write), so with this
+// barrier loads issued before it stay in flight across it and their latency
+// overlaps the staging and reductions that follow.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Tile sides: large tiles (less halo work) for batches, small tiles (more
 // workgroups) when few columns make the V-cycle latency bound.
 constexpr int kTCBig = 16, kTFBig = 32;      // coarse / fine nodes per tile side
@@ -49,9 +61,33 @@ __device__ inline double partial_rest(double s, const double* part, int col, int
     for (int b = threadIdx.x + blockDim.x; b < nblk; b += blockDim.x) s += p[b];
     return s;
 }
+// The whole share of nblk >= 1 partials with the first kShareLoads per thread
+// loaded without branches (clamped index, dropped afterwards), so that they
+// are in flight together with the caller's other loads (a loop waits for
+// each load it accumulates); more partials than kShareLoads per thread
+// follow in a loop.  Summed in index order, as partial_rest does.
+constexpr int kShareLoads = 3;
 __device__ inline double partial_share(const double* part, int col, int stride, int nblk) {
-    return partial_rest(partial_first(part, col, stride, nblk), part, col, stride, nblk);
+    const double* p = part + (size_t)col * stride;
+    const int t = threadIdx.x, nt = blockDim.x;
+    double v[kShareLoads];
+#pragma unroll
+    for (int k = 0; k < kShareLoads; ++k) v[k] = p[min(t + k * nt, nblk - 1)];
+    double s = t < nblk ? v[0] : 0.0;
+#pragma unroll
+    for (int k = 1; k < kShareLoads; ++k)
+        if (t + k * nt < nblk) s += v[k];
+    for (int b = t + kShareLoads * nt; b < nblk; b += nt) s += p[b];
+    return s;
 }
+
+// Index i clamped into the mesh [0, N]: tile loads read a valid node for
+// every slot and drop the off-mesh ones afterwards.  Used on tiles of at
+// most kFlatLoads elements a thread (the few-column cycles, latency bound);
+// larger tiles keep branched loads and fewer registers.
+__device__ inline int clamp_node(int i, int N) { return min(max(i, 0), N); }
+template <int E>
+constexpr bool kFlatLoads = E <= 3;
 
 // Waves of the workgroup as a uniform value (read once, outside the
 // single-thread code that sums the per-wave slots).
@@ -64,13 +100,13 @@ __device__ inline double share_total(double s) {
     const int nw = group_waves();
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) ps[threadIdx.x >> 6] = s;
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < nw; ++w) t += ps[w];
         tot = t;
     }
-    __syncthreads();
+    lds_barrier();
     return tot;
 }
 
@@ -101,7 +137,7 @@ __device__ inline double group_sum(double v) {
     const int nw = group_waves();
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-    __syncthreads();
+    lds_barrier();
     double r = 0.0;
     if (threadIdx.x == 0)
         for (int w = 0; w < nw; ++w) r += part[w];
@@ -122,9 +158,6 @@ __device__ inline bool column_done_share(double share, const PcgRed& red, int co
         if (done) act[col] = 0;
     }
     return done;
-}
-__device__ inline bool column_done(const PcgRed& red, int col, ColState* st, int* act, bool lead) {
-    return column_done_share(partial_share(red.rr, col, red.stride, red.nvec), red, col, st, act, lead);
 }
 
 // XCD-aware tile order.  The hardware hands consecutive workgroups to the
@@ -192,7 +225,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const int c_end = min(nc, (tb.z + 1) * cb);
     for (int col = tb.z * cb; col < c_end; ++col) {
         // with the convergence test on, the lead workgroup clears act[col]
-        // (column_done below) while other workgroups of this launch read it:
+        // (column_done_share below) while other workgroups of this launch read it:
         // one decision for the whole workgroup, or its waves could see
         // different values and meet different barriers (without the test no
         // kernel of the launch writes act)
@@ -201,16 +234,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         const TB* bcol = b + (size_t)col * ld;
         T* xcol = x + (size_t)col * ld;
         // loads first: b, the convergence test's partials, then the operator
-        // rows, so that their latencies overlap
+        // rows, so that their latencies overlap.  On small tiles of the prior
+        // operator b is read at a clamped node without a branch (a load
+        // converted inside its branch waits there for its data) and the
+        // off-mesh entries are dropped at the LDS store.  Large tiles (many
+        // workgroups a compute unit) keep the branch and their registers, and
+        // so does the state operator, whose rows (five loads a node) come
+        // from global memory with the tile: with both in flight its finest
+        // single-column kernel spills (measured: 1% slower actions)
+        constexpr bool kFlat = kFlatLoads<E> && NE;
         T vb[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int t = threadIdx.x + 256 * e;
             const int i = ox + t % TW, j = oy + t / TW;
-            vb[e] = (t < NN && i >= 0 && i <= N && j >= 0 && j <= N) ? (T)bcol[j * N1 + i] : (T)0;
+            if constexpr (kFlat)
+                vb[e] = (T)bcol[clamp_node(j, N) * N1 + clamp_node(i, N)];
+            else
+                vb[e] = (t < NN && i >= 0 && i <= N && j >= 0 && j <= N) ? (T)bcol[j * N1 + i] : (T)0;
         }
         const double rr_share = check ? partial_share(red.rr, col, red.stride, red.nvec) : 0.0;
-        __syncthreads();  // the previous column's LDS reads are done
+        lds_barrier();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
             if constexpr (KA) {
                 if (threadIdx.x < 9) krows[threadIdx.x] = op.rows[threadIdx.x];
@@ -223,12 +267,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int t = threadIdx.x + 256 * e;
-            if (t < NN) sb[t] = vb[e];
+            const int i = ox + t % TW, j = oy + t / TW;
+            if (t < NN) sb[t] = !kFlat || (i >= 0 && i <= N && j >= 0 && j <= N) ? vb[e] : (T)0;
         }
-        __syncthreads();
+        lds_barrier();
         // d0 = D^-1 b / theta on the whole tile (zero off the free nodes)
         for (int t = threadIdx.x; t < NN; t += blockDim.x) sr[t] = tdinv(t) * sb[t] * inv_theta;
-        __syncthreads();
+        lds_barrier();
         // x2 = cA d0 + cB D^-1 (b - A d0) on local [1, TW-1)^2; owned nodes to global
         {
             constexpr int W = TW - 2;
@@ -240,7 +285,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 if (i >= 2 * I0 && i <= own_i1 && j >= 2 * J0 && j <= own_j1) xcol[j * N1 + i] = v;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // residual b - A x2 on the free nodes of local [2, TW-2)^2
         {
             constexpr int W = TW - 4;
@@ -250,7 +295,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 sr[l] = tdinv(l) != (T)0 ? v : (T)0;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // restriction P^T onto the coarse tile
         T* bccol = bc + (size_t)col * ldc;
         const int cw = I1 - I0 + 1, ch = J1 - J0 + 1;
@@ -328,7 +373,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         // then the operator rows) so that their latencies overlap.  P x_c at
         // (i, j): the coarse node (i/2, j/2) when both are even, else the mean
         // of the two coarse ends of the fine edge through (i, j).
-        T vb[E], vx[E], pc0[E], pc1[E];
+        TB vb[E];  // small tiles: read at a clamped node without a branch (see k_down)
+        T vx[E], pc0[E], pc1[E];
         bool even[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -338,7 +384,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             const bool fr = in && !(dirichlet && (j == 0 || j == N));
             const int I = i >> 1, J = j >> 1;
             const int a0 = J * Nc1 + I, a1 = (J + (j & 1)) * Nc1 + I + (i & 1);
-            vb[e] = in ? (T)bcol[j * N1 + i] : (T)0;
+            if constexpr (kFlatLoads<E>)
+                vb[e] = bcol[clamp_node(j, N) * N1 + clamp_node(i, N)];  // dropped at its store when !in
+            else
+                vb[e] = in ? bcol[j * N1 + i] : (TB)0;
             vx[e] = fr ? x2col[j * N1 + i] : (T)0;
             pc0[e] = fr ? ccol[a0] : (T)0;
             pc1[e] = fr ? ccol[a1] : (T)0;
@@ -354,7 +403,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             const int t = threadIdx.x;
             if (rv && t < w * h) rv0 = rv[(size_t)col * ld + (j0 + t / w) * N1 + (i0 + t % w)];
         }
-        __syncthreads();  // the previous column's LDS reads are done
+        lds_barrier();  // the previous column's LDS reads are done
         if (instance_key(op) != staged) {
             if constexpr (KA) {
                 if (threadIdx.x < 9) krows[threadIdx.x] = op.rows[threadIdx.x];
@@ -367,11 +416,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         for (int e = 0; e < E; ++e) {
             const int t = threadIdx.x + 256 * e;
             if (t < NN) {
+                const int i = ox + t % TW, j = oy + t / TW;
                 sx[t] = vx[e] + (even[e] ? pc0[e] : (T)0.5 * (pc0[e] + pc1[e]));
-                sb[t] = vb[e];
+                sb[t] = (i >= 0 && i <= N && j >= 0 && j <= N) ? (T)vb[e] : (T)0;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // d0 = D^-1 (b - A x) / theta on local [1, TW-1)^2 (zero off the free nodes)
         {
             constexpr int W = TW - 2;
@@ -380,7 +430,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 sd[l] = tdinv(l) * (sb[l] - tapply(l, sx)) * inv_theta;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // x += (1 + c1) d0 + cB D^-1 r1 on O with r1 = r0 - A d0 = theta D d0 - A d0
         double dot = 0.0;
         for (int t = threadIdx.x; t < w * h; t += blockDim.x) {
@@ -452,7 +502,7 @@ __global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restr
             const int i = fox + t % FW, j = foy + t / FW;
             vb[e] = (t < NF && i >= 0 && i <= Nf && j >= 0 && j <= Nf) ? bcol[j * Nf1 + i] : (T)0;
         }
-        __syncthreads();  // the previous column's LDS reads are done
+        lds_barrier();  // the previous column's LDS reads are done
         if (instance_key(opF) != staged) {
             stage_stencil<FW, NT>(opF, tsF, fox, foy);
             stage_stencil<MW, NT>(opM, tsM, mox, moy);
@@ -463,11 +513,11 @@ __global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restr
             const int t = threadIdx.x + NT * e;
             if (t < NF) fb[t] = vb[e];
         }
-        __syncthreads();
+        lds_barrier();
         // level F: d0 = D^-1 b / theta; x2 = cA d0 + cB D^-1 (b - A d0) on
         // local [1, FW-1)^2 (owned nodes to global); residual on [2, FW-2)^2
         for (int t = threadIdx.x; t < NF; t += blockDim.x) fr[t] = fdv[t] * fb[t] * inv_theta;
-        __syncthreads();
+        lds_barrier();
         {
             T* xcol = xF + (size_t)col * ldF;
             constexpr int W = FW - 2;
@@ -479,7 +529,7 @@ __global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restr
                 if (i >= fi0 && i <= fi1 && j >= fj0 && j <= fj1) xcol[j * Nf1 + i] = v;
             }
         }
-        __syncthreads();
+        lds_barrier();
         {
             constexpr int W = FW - 4;
             for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
@@ -488,7 +538,7 @@ __global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restr
                 fr[l] = fdv[l] != (T)0 ? v : (T)0;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // P^T onto the whole level-M tile: b_M, zero off the mesh and on
         // Dirichlet rows; owned nodes to global
         {
@@ -512,10 +562,10 @@ __global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restr
                 mb[t] = v;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // level M: the same three steps on the level-M tile
         for (int t = threadIdx.x; t < NM; t += blockDim.x) mr[t] = mdv[t] * mb[t] * inv_theta;
-        __syncthreads();
+        lds_barrier();
         {
             T* xcol = xM + (size_t)col * ldM;
             constexpr int W = MW - 2;
@@ -527,7 +577,7 @@ __global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restr
                 if (I >= mi0 && I <= mi1 && J >= mj0 && J <= mj1) xcol[J * Nm1 + I] = v;
             }
         }
-        __syncthreads();
+        lds_barrier();
         {
             constexpr int W = MW - 4;
             for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
@@ -536,7 +586,7 @@ __global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restr
                 mr[l] = mdv[l] != (T)0 ? v : (T)0;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // P^T onto the level-C tile
         T* bccol = bC + (size_t)col * ldC;
         const int cw = K1 - K0 + 1, ch = L1 - L0 + 1;
@@ -647,7 +697,7 @@ __device__ inline void chain_step(const ChainArgs<T, Op>& a, const int* ox, cons
                 x[t] += ((i | j) & 1) ? (T)0.5 * (p0 + x1[(J + (j & 1) - oy1) * W1 + (I + (i & 1) - ox1)]) : p0;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     {
         constexpr int Wi = W - 2;
@@ -656,7 +706,7 @@ __device__ inline void chain_step(const ChainArgs<T, Op>& a, const int* ox, cons
             d[l] = st.dv[l] * (b[l] - tile_apply<NE>(st, W, l, x)) * inv_theta;
         }
     }
-    __syncthreads();
+    lds_barrier();
     if constexpr (k > 0) {
         // x on [2, W-2)^2 in place of x2 + P x (each node reads only its own entry)
         constexpr int Wi = W - 4;
@@ -666,7 +716,7 @@ __device__ inline void chain_step(const ChainArgs<T, Op>& a, const int* ox, cons
             const T r1 = theta * dk * st.c[l] - tile_apply<NE>(st, W, l, d);
             x[l] = x[l] + ((T)1 + c1) * dk + cB * st.dv[l] * r1;
         }
-        __syncthreads();
+        lds_barrier();
         chain_step<T, Op, kTF, NL, k - 1>(a, ox, oy, sx, sd, sb, ts, dirichlet, cc, i0, i1, j0, j1, col);
     } else {
         const int N1 = a.op[0].N + 1;
@@ -760,10 +810,10 @@ __global__ __launch_bounds__(NT) void k_up_chain(ChainArgs<T, Op> a, int dirichl
         // no kernel of the launch writes act (the convergence test runs on the finest level)
         if (act && !act[col]) continue;
         const void* key = instance_key(a.op[0].at(col));
-        __syncthreads();  // the previous column's LDS reads are done
+        lds_barrier();  // the previous column's LDS reads are done
         chain_load<T, Op, kTF, NL, NT, 0>(a, ox, oy, dirichlet, col, key != staged, sx, sb, ts);
         staged = key;
-        __syncthreads();
+        lds_barrier();
         chain_step<T, Op, kTF, NL, NL - 1>(a, ox, oy, sx, sd, sb, ts, dirichlet, cc, i0, i1, j0, j1, col);
     }
 }
@@ -838,7 +888,9 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
     constexpr int PN = bottom_padded<TOP>(), NT = 1024, LV = kBottomLevels, MS = bottom_slots<TOP>(0);
     const int col = blockIdx.x;
     if (act && !act[col]) return;
-    if (check && column_done(red, col, st, act, true)) return;
+    // the convergence test's partials load together with the level data
+    // below; the test itself follows the loads
+    const double rr_share = check ? partial_share(red.rr, col, red.stride, red.nvec) : 0.0;
     __shared__ float sb[PN], sx[PN], sw[PN];  // right-hand side, iterate, work vector
     __shared__ float te[PRIOR ? 1 : PN], tn[PRIOR ? 1 : PN], tdv[PRIOR ? 1 : PN];  // -wE, -wN, 1/diag
     __shared__ KARow<float> rows[PRIOR ? LV * 9 : 1];
@@ -902,6 +954,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
         const int c = cpart + u * S;
         cv[u] = (cr < a.nc && c < a.nc) ? ci[cr * a.nc + c] : 0.0f;
     }
+    if (check && column_done_share(rr_share, red, col, st, act, true)) return;
     // ---- per-thread slots: padded position (-1 past the level) and (i, j)
     int sp[LV][MS], sij[LV][MS];
 #pragma unroll
@@ -925,7 +978,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
         sb[q] = sx[q] = sw[q] = 0.0f;
         if constexpr (!PRIOR) te[q] = tn[q] = tdv[q] = 0.0f;
     }
-    __syncthreads();
+    lds_barrier();
     const float inv_theta = (float)cc.inv_theta, theta = (float)cc.theta, cA = (float)cc.cA, cB = (float)cc.cB,
                 c1 = (float)cc.c1;
 #pragma unroll
@@ -946,7 +999,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
             sw[p] = vD[e] * vb[e] * inv_theta;  // d0 of the first smoothing step
         }
     }
-    __syncthreads();
+    lds_barrier();
     // (A x)_p at padded position p of level l (node ij), with the diagonal and
     // 1/diagonal of the row
     auto apply = [&](int l, int p, int ij, const float* x, float& diag, float& dv) -> float {
@@ -984,7 +1037,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
             const float ad = apply(l, p, sij[l][s], sw, dg, dv);
             sx[p] = cA * sw[p] + cB * dv * (sb[p] - ad);
         }
-        __syncthreads();
+        lds_barrier();
         // residual b - A x2 on the free nodes, into sw
 #pragma unroll
         for (int s = 0; s < bottom_slots<TOP>(l); ++s) {
@@ -994,7 +1047,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
             const float v = sb[p] - apply(l, p, sij[l][s], sx, dg, dv);
             sw[p] = dv != 0.0f ? v : 0.0f;
         }
-        __syncthreads();
+        lds_barrier();
         // restriction P^T to level l + 1, and its first smoothing correction d0
 #pragma unroll
         for (int s = 0; s < bottom_slots<TOP>(l + 1); ++s) {
@@ -1009,7 +1062,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
             sb[pc] = v;
             sw[pc] = dvc * v * inv_theta;
         }
-        __syncthreads();
+        lds_barrier();
     }
     // ---- coarsest: dense inverse, S threads per row (entries prefetched in cv)
     {
@@ -1035,14 +1088,14 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
             }
             tmp[threadIdx.x] = s;
         }
-        __syncthreads();
+        lds_barrier();
         for (int r = threadIdx.x; r < a.nc; r += NT) {
             float s = 0.0f;
             for (int part = 0; part < S; ++part) s += tmp[r * S + part];
             const int jr = small_div(r, inv_c);
             sx[o + (jr + 1) * P + r - jr * N1 + 1] = s;
         }
-        __syncthreads();
+        lds_barrier();
     }
     // ---- up
 #pragma unroll
@@ -1061,7 +1114,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
             const int ca1 = po[l + 1] + (J + 1 + (j & 1)) * Pc + I + 1 + (i & 1);
             sx[p] += ((i | j) & 1) ? 0.5f * (sx[ca0] + sx[ca1]) : sx[ca0];
         }
-        __syncthreads();
+        lds_barrier();
         // d0 = D^-1 (b - A x) / theta
 #pragma unroll
         for (int s = 0; s < bottom_slots<TOP>(l); ++s) {
@@ -1071,7 +1124,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
             const float ax = apply(l, p, sij[l][s], sx, dg, dv);
             sw[p] = dv * (sb[p] - ax) * inv_theta;
         }
-        __syncthreads();
+        lds_barrier();
         // x += (1 + c1) d0 + cB D^-1 r1 with r1 = theta D d0 - A d0
 #pragma unroll
         for (int s = 0; s < bottom_slots<TOP>(l); ++s) {
@@ -1083,7 +1136,7 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs a, const TV* __restr
             const float r1 = theta * dk * dg - ad;
             sx[p] += (1.0f + c1) * dk + cB * dv * r1;
         }
-        __syncthreads();
+        lds_barrier();
     }
     double dot = 0.0;
 #pragma unroll
@@ -1206,7 +1259,7 @@ __global__ __launch_bounds__(1024) void k_pcg_apply(Op op_, const T* __restrict_
         // rows staged after the node loads are issued (waiting for them then
         // waits for nothing those loads would not)
         if (threadIdx.x < 9) krows[threadIdx.x] = ka_row(op, threadIdx.x);
-        __syncthreads();
+        lds_barrier();
     }
 #pragma unroll
     for (int e = W; e < kVecNodes; ++e) {
