@@ -333,7 +333,7 @@ constexpr bool kNorthEast<OpA<T>> = false;
 
 template <typename T>
 struct TileStencil {
-    T* c;
+    T* c;   // unused (size 1) for the state operator: see tile_center
     T* e;
     T* n;
     T* g;   // unused (size 1) for the state operator
@@ -343,11 +343,15 @@ struct TileStencil {
 // Stages the rows of the TW x TW tile whose local (0, 0) is node (ox, oy),
 // NT threads.  Every global load of a thread is issued before its first LDS
 // store, so the load latencies of its NT-strided elements overlap.
+// The state operator stages its two edge weights and 1/d per node; the
+// diagonal is summed from the staged weights of the node and of its west and
+// south neighbours where it is used (tile_center), so no diagonal array is
+// staged (three loads a node instead of five, a sixth less LDS).
 template <int TW, int NT, typename T>
 __device__ inline void stage_stencil(const OpA<T>& op, const TileStencil<T>& s, int ox, int oy) {
     constexpr int NN = TW * TW, E = (NN + NT - 1) / NT;
     const int N = op.N, N1 = N + 1;
-    T we[E], wn[E], ww[E], ws[E], dv[E];
+    T we[E], wn[E], dv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int t = threadIdx.x + e * NT;
@@ -356,15 +360,12 @@ __device__ inline void stage_stencil(const OpA<T>& op, const TileStencil<T>& s, 
         const int k = j * N1 + i;
         we[e] = in ? op.wE[k] : (T)0;
         wn[e] = in ? op.wN[k] : (T)0;
-        ww[e] = in && i > 0 ? op.wE[k - 1] : (T)0;
-        ws[e] = in && j > 0 ? op.wN[k - N1] : (T)0;
         dv[e] = in ? op.dinv[k] : (T)0;
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int t = threadIdx.x + e * NT;
         if (t < NN) {
-            s.c[t] = we[e] + wn[e] + ww[e] + ws[e];
             s.e[t] = -we[e];
             s.n[t] = -wn[e];
             s.dv[t] = dv[e];
@@ -451,10 +452,22 @@ struct TileKA {
     }
 };
 
+// Diagonal of row l on a staged tile (l must have its west and south
+// neighbours inside the tile): the prior operator's staged value; for the
+// state operator the sum w_E + w_N + w_W + w_S of the four incident edge
+// weights, in that order (off the mesh, and for absent edges, the staged
+// weights are zero).
+template <bool NE, typename T>
+__device__ inline T tile_center(const TileStencil<T>& s, int TW, int l) {
+    if constexpr (NE) return s.c[l];
+    else return -s.e[l] + -s.n[l] + -s.e[l - 1] + -s.n[l - TW];
+}
+
 // (A v)_l on a staged tile; l must have all eight neighbours inside the tile.
 template <bool NE, typename T>
 __device__ inline T tile_apply(const TileStencil<T>& s, int TW, int l, const T* v) {
-    T a = s.c[l] * v[l] + s.e[l] * v[l + 1] + s.e[l - 1] * v[l - 1] + s.n[l] * v[l + TW] + s.n[l - TW] * v[l - TW];
+    T a = tile_center<NE>(s, TW, l) * v[l] + s.e[l] * v[l + 1] + s.e[l - 1] * v[l - 1] + s.n[l] * v[l + TW] +
+          s.n[l - TW] * v[l - TW];
     if constexpr (NE) a += s.g[l] * v[l + TW + 1] + s.g[l - TW - 1] * v[l - TW - 1];
     return a;
 }

@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     constexpr bool NE = kNorthEast<Op>;
     constexpr bool KA = NE && kTC == kTCBig;
     __shared__ T sb[NN], sx[NN], sr[NN];
-    __shared__ T tc[KA ? 1 : NN], te[KA ? 1 : NN], tn[KA ? 1 : NN], tdv[KA ? 1 : NN], tg[NE && !KA ? NN : 1];
+    __shared__ T tc[NE && !KA ? NN : 1], te[KA ? 1 : NN], tn[KA ? 1 : NN], tdv[KA ? 1 : NN], tg[NE && !KA ? NN : 1];
     __shared__ KARow<T> krows[KA ? 9 : 1];
     const TileStencil<T> ts{tc, te, tn, tg, tdv};
     const int N = op_.N, N1 = N + 1, Nc = N / 2, Nc1 = Nc + 1;
@@ -239,9 +239,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         // converted inside its branch waits there for its data) and the
         // off-mesh entries are dropped at the LDS store.  Large tiles (many
         // workgroups a compute unit) keep the branch and their registers, and
-        // so does the state operator, whose rows (five loads a node) come
-        // from global memory with the tile: with both in flight its finest
-        // single-column kernel spills (measured: 1% slower actions)
+        // so does the state operator, whose row loads from global memory
+        // cover the latency of b (measured: the branch-free form no faster)
         constexpr bool kFlat = kFlatLoads<E> && NE;
         T vb[E];
 #pragma unroll
@@ -337,7 +336,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     constexpr bool NE = kNorthEast<Op>;
     constexpr bool KA = NE && kTF == kTFBig;  // class table for the prior operator (see k_down)
     __shared__ T sx[NN], sd[NN], sb[NN];
-    __shared__ T tc[KA ? 1 : NN], te[KA ? 1 : NN], tn[KA ? 1 : NN], tdv[KA ? 1 : NN], tg[NE && !KA ? NN : 1];
+    __shared__ T tc[NE && !KA ? NN : 1], te[KA ? 1 : NN], tn[KA ? 1 : NN], tdv[KA ? 1 : NN], tg[NE && !KA ? NN : 1];
     __shared__ KARow<T> krows[KA ? 9 : 1];
     const TileStencil<T> ts{tc, te, tn, tg, tdv};
     const int N = op_.N, N1 = N + 1, Nc1 = N / 2 + 1;
@@ -356,7 +355,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     };
     auto tcen = [&](int l) -> T {
         if constexpr (KA) return tk.center(l);
-        else return tc[l];
+        else return tile_center<NE>(ts, TW, l);
     };
     const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
     constexpr int E = (NN + 255) / 256;  // tile elements per thread
@@ -472,9 +471,9 @@ __global__ __launch_bounds__(NT) void k_down2(Op opF_, Op opM_, const T* __restr
     constexpr int MW = 2 * kT + 5, FW = 2 * MW + 5, NM = MW * MW, NF = FW * FW;
     constexpr bool NE = kNorthEast<Op>;
     __shared__ T fb[NF], fx[NF], fr[NF];
-    __shared__ T fc[NF], fe[NF], fn[NF], fdv[NF], fg[NE ? NF : 1];
+    __shared__ T fc[NE ? NF : 1], fe[NF], fn[NF], fdv[NF], fg[NE ? NF : 1];
     __shared__ T mb[NM], mx[NM], mr[NM];
-    __shared__ T mc[NM], me[NM], mn[NM], mdv[NM], mg[NE ? NM : 1];
+    __shared__ T mc[NE ? NM : 1], me[NM], mn[NM], mdv[NM], mg[NE ? NM : 1];
     const TileStencil<T> tsF{fc, fe, fn, fg, fdv}, tsM{mc, me, mn, mg, mdv};
     const int Nf = opF_.N, Nf1 = Nf + 1, Nm = Nf / 2, Nm1 = Nm + 1, Nc = Nm / 2, Nc1 = Nc + 1;
     const int3 tb = xcd_tile();
@@ -660,8 +659,7 @@ template <typename T>
 __device__ inline TileRow<T> tile_row(const OpA<T>& op, int i, int j) {
     const int N = op.N, N1 = N + 1, k = j * N1 + i;
     if (i < 0 || i > N || j < 0 || j > N) return TileRow<T>{};
-    const T we = op.wE[k], wn = op.wN[k], ww = i > 0 ? op.wE[k - 1] : (T)0, ws = j > 0 ? op.wN[k - N1] : (T)0;
-    return TileRow<T>{we + wn + ww + ws, -we, -wn, (T)0, op.dinv[k]};
+    return TileRow<T>{(T)0, -op.wE[k], -op.wN[k], (T)0, op.dinv[k]};  // diagonal: tile_center
 }
 template <typename T, class OpK>
 __device__ inline TileRow<T> tile_row(const OpK& op, int i, int j) {
@@ -680,7 +678,7 @@ __device__ inline void chain_step(const ChainArgs<T, Op>& a, const int* ox, cons
                                   int i0, int i1, int j0, int j1, int col) {
     constexpr int W = chain_width<kTF>(k), off = chain_offset<kTF>(k), NN = W * W;
     constexpr bool NE = kNorthEast<Op>;
-    const TileStencil<T> st{ts.c + off, ts.e + off, ts.n + off, NE ? ts.g + off : ts.g, ts.dv + off};
+    const TileStencil<T> st{NE ? ts.c + off : ts.c, ts.e + off, ts.n + off, NE ? ts.g + off : ts.g, ts.dv + off};
     T* x = sx + off;
     T* d = sd + off;
     const T* b = sb + off;
@@ -713,7 +711,7 @@ __device__ inline void chain_step(const ChainArgs<T, Op>& a, const int* ox, cons
         for (int t = threadIdx.x; t < Wi * Wi; t += blockDim.x) {
             const int l = (2 + t / Wi) * W + 2 + t % Wi;
             const T dk = d[l];
-            const T r1 = theta * dk * st.c[l] - tile_apply<NE>(st, W, l, d);
+            const T r1 = theta * dk * tile_center<NE>(st, W, l) - tile_apply<NE>(st, W, l, d);
             x[l] = x[l] + ((T)1 + c1) * dk + cB * st.dv[l] * r1;
         }
         lds_barrier();
@@ -726,7 +724,7 @@ __device__ inline void chain_step(const ChainArgs<T, Op>& a, const int* ox, cons
             const int i = i0 + t % w, j = j0 + t / w;
             const int l = (j - oy[0]) * W + (i - ox[0]);
             const T dk = d[l];
-            const T r1 = theta * dk * st.c[l] - tile_apply<NE>(st, W, l, d);
+            const T r1 = theta * dk * tile_center<NE>(st, W, l) - tile_apply<NE>(st, W, l, d);
             xcol[j * N1 + i] = x[l] + ((T)1 + c1) * dk + cB * st.dv[l] * r1;
         }
     }
@@ -774,7 +772,7 @@ __device__ inline void chain_load(const ChainArgs<T, Op>& a, const int* ox, cons
             sb[off + t] = vb[e];
             sx[off + t] = vx[e];
             if (stage) {
-                ts.c[off + t] = vr[e].c;
+                if constexpr (NE) ts.c[off + t] = vr[e].c;
                 ts.e[off + t] = vr[e].e;
                 ts.n[off + t] = vr[e].n;
                 if constexpr (NE) ts.g[off + t] = vr[e].g;
@@ -791,7 +789,7 @@ __global__ __launch_bounds__(NT) void k_up_chain(ChainArgs<T, Op> a, int dirichl
     constexpr int NA = chain_offset<kTF>(NL);  // nodes of all the chain's tiles
     constexpr bool NE = kNorthEast<Op>;
     __shared__ T sx[NA], sd[NA], sb[NA];
-    __shared__ T tc[NA], te[NA], tn[NA], tdv[NA], tg[NE ? NA : 1];
+    __shared__ T tc[NE ? NA : 1], te[NA], tn[NA], tdv[NA], tg[NE ? NA : 1];
     const TileStencil<T> ts{tc, te, tn, tg, tdv};
     const int3 tb = xcd_tile();
     const int i0 = tb.x * kTF, j0 = tb.y * kTF;
