@@ -463,6 +463,15 @@ __device__ inline T tile_center(const TileStencil<T>& s, int TW, int l) {
     else return -s.e[l] + -s.n[l] + -s.e[l - 1] + -s.n[l - TW];
 }
 
+// (A v)_l with row r at every node (a tile of interior prior-operator
+// nodes), in the operation order of tile_apply<true> on staged rows.
+template <typename T>
+__device__ inline T row_apply(const KARow<T>& r, int TW, int l, const T* v) {
+    T a = r.c * v[l] + r.e * v[l + 1] + r.e * v[l - 1] + r.n * v[l + TW] + r.n * v[l - TW];
+    a += r.ne * v[l + TW + 1] + r.ne * v[l - TW - 1];
+    return a;
+}
+
 // (A v)_l on a staged tile; l must have all eight neighbours inside the tile.
 template <bool NE, typename T>
 __device__ inline T tile_apply(const TileStencil<T>& s, int TW, int l, const T* v) {

@@ -197,9 +197,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // reads its class table: a third of the LDS, more workgroups per compute
     // unit, for the batched solves that are bound by LDS traffic (measured:
     // a 220-column prior solve at N = 1024 9% faster; on the small tiles of
-    // single-column cycles the staged rows stay faster)
+    // single-column cycles the staged rows stay faster, except on tiles of
+    // interior nodes only, which apply row 0 of the table throughout (HYB)
     constexpr bool NE = kNorthEast<Op>;
     constexpr bool KA = NE && kTC == kTCBig;
+    constexpr bool HYB = NE && !KA;
     __shared__ T sb[NN], sx[NN], sr[NN];
     __shared__ T tc[NE && !KA ? NN : 1], te[KA ? 1 : NN], tn[KA ? 1 : NN], tdv[KA ? 1 : NN], tg[NE && !KA ? NN : 1];
     __shared__ KARow<T> krows[KA ? 9 : 1];
@@ -210,12 +212,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const int I1 = min(I0 + kTC - 1, Nc), J1 = min(J0 + kTC - 1, Nc);
     const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // global coordinates of local (0, 0)
     const TileKA<T, TW> tk{krows, ox, oy, N, ox >= 1 && oy >= 1 && ox + TW - 1 <= N - 1 && oy + TW - 1 <= N - 1};
+    const bool inner = HYB && tk.interior;  // uniform in the workgroup
+    KARow<T> r0{};  // inner tiles: row 0 of the instance's class table (uniform: scalar registers)
     auto tapply = [&](int l, const T* v) -> T {
         if constexpr (KA) return tk.apply(l, v);
+        else if constexpr (HYB) return inner ? row_apply(r0, TW, l, v) : tile_apply<NE>(ts, TW, l, v);
         else return tile_apply<NE>(ts, TW, l, v);
     };
     auto tdinv = [&](int l) -> T {
         if constexpr (KA) return tk.dinv(l);
+        else if constexpr (HYB) return inner ? r0.dinv : tdv[l];
         else return tdv[l];
     };
     const T inv_theta = (T)cc.inv_theta, cA = (T)cc.cA, cB = (T)cc.cB;
@@ -257,6 +263,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         if (instance_key(op) != staged) {
             if constexpr (KA) {
                 if (threadIdx.x < 9) krows[threadIdx.x] = op.rows[threadIdx.x];
+            } else if constexpr (HYB) {
+                if (inner)
+                    r0 = op.rows[0];
+                else
+                    stage_stencil<TW, 256>(op, ts, ox, oy);
             } else {
                 stage_stencil<TW, 256>(op, ts, ox, oy);
             }
@@ -335,6 +346,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     constexpr int TW = kTF + 4, NN = TW * TW;
     constexpr bool NE = kNorthEast<Op>;
     constexpr bool KA = NE && kTF == kTFBig;  // class table for the prior operator (see k_down)
+    constexpr bool HYB = NE && !KA;           // row 0 on interior small tiles (see k_down)
     __shared__ T sx[NN], sd[NN], sb[NN];
     __shared__ T tc[NE && !KA ? NN : 1], te[KA ? 1 : NN], tn[KA ? 1 : NN], tdv[KA ? 1 : NN], tg[NE && !KA ? NN : 1];
     __shared__ KARow<T> krows[KA ? 9 : 1];
@@ -345,16 +357,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const int i1 = min(i0 + kTF - 1, N), j1 = min(j0 + kTF - 1, N);
     const int ox = i0 - 2, oy = j0 - 2;
     const TileKA<T, TW> tk{krows, ox, oy, N, ox >= 1 && oy >= 1 && ox + TW - 1 <= N - 1 && oy + TW - 1 <= N - 1};
+    const bool inner = HYB && tk.interior;  // uniform in the workgroup
+    KARow<T> r0{};  // inner tiles: row 0 of the instance's class table (uniform: scalar registers)
     auto tapply = [&](int l, const T* v) -> T {
         if constexpr (KA) return tk.apply(l, v);
+        else if constexpr (HYB) return inner ? row_apply(r0, TW, l, v) : tile_apply<NE>(ts, TW, l, v);
         else return tile_apply<NE>(ts, TW, l, v);
     };
     auto tdinv = [&](int l) -> T {
         if constexpr (KA) return tk.dinv(l);
+        else if constexpr (HYB) return inner ? r0.dinv : tdv[l];
         else return tdv[l];
     };
     auto tcen = [&](int l) -> T {
         if constexpr (KA) return tk.center(l);
+        else if constexpr (HYB) return inner ? r0.c : tile_center<NE>(ts, TW, l);
         else return tile_center<NE>(ts, TW, l);
     };
     const T inv_theta = (T)cc.inv_theta, theta = (T)cc.theta, cB = (T)cc.cB, c1 = (T)cc.c1;
@@ -406,6 +423,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         if (instance_key(op) != staged) {
             if constexpr (KA) {
                 if (threadIdx.x < 9) krows[threadIdx.x] = op.rows[threadIdx.x];
+            } else if constexpr (HYB) {
+                if (inner)
+                    r0 = op.rows[0];
+                else
+                    stage_stencil<TW, 256>(op, ts, ox, oy);
             } else {
                 stage_stencil<TW, 256>(op, ts, ox, oy);
             }
