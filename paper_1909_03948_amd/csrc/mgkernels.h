@@ -677,17 +677,18 @@ template <typename T>
 struct TileRow {
     T c, e, n, g, dv;
 };
+// The loads are issued without a branch, at the node clamped into the mesh
+// (chain_load zeroes the row off the mesh): a load inside a branch makes the
+// wave wait for it, and with it for every load issued before.
 template <typename T>
 __device__ inline TileRow<T> tile_row(const OpA<T>& op, int i, int j) {
-    const int N = op.N, N1 = N + 1, k = j * N1 + i;
-    if (i < 0 || i > N || j < 0 || j > N) return TileRow<T>{};
+    const int N = op.N, N1 = N + 1, k = clamp_node(j, N) * N1 + clamp_node(i, N);
     return TileRow<T>{(T)0, -op.wE[k], -op.wN[k], (T)0, op.dinv[k]};  // diagonal: tile_center
 }
 template <typename T, class OpK>
 __device__ inline TileRow<T> tile_row(const OpK& op, int i, int j) {
     const int N = op.N;
-    if (i < 0 || i > N || j < 0 || j > N) return TileRow<T>{};
-    const KARow<T>& r = op.rows[ka_class(i, j, N)];
+    const KARow<T>& r = op.rows[ka_class(clamp_node(i, N), clamp_node(j, N), N)];
     return TileRow<T>{r.c, r.e, r.n, r.ne, r.dinv};
 }
 
@@ -762,43 +763,52 @@ __device__ inline void chain_load(const ChainArgs<T, Op>& a, const int* ox, cons
     constexpr bool NE = kNorthEast<Op>;
     const Op& op = a.op[k];
     const int N = op.N;
-    T vb[E], vx[E];
+    // every load at a node clamped into the mesh, without a branch (a load
+    // inside a branch waits there, and with it every load issued before it);
+    // off-mesh and off-tile slots are dropped at the LDS stores
+    T vb[E], vx[E], pc0[E], pc1[E];
     TileRow<T> vr[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int t = threadIdx.x + NT * e;
         const int i = ox[k] + t % W, j = oy[k] + t / W;
-        const bool in = t < NN && i >= 0 && i <= N && j >= 0 && j <= N;
-        const bool fr = in && !(dirichlet && (j == 0 || j == N));
-        const size_t g = (size_t)col * a.ld[k] + (size_t)j * (N + 1) + i;
-        vb[e] = in ? a.b[k][g] : (T)0;
-        T v = fr ? a.x2[k][g] : (T)0;
+        const size_t g = (size_t)col * a.ld[k] + (size_t)clamp_node(j, N) * (N + 1) + clamp_node(i, N);
+        vb[e] = a.b[k][g];
+        vx[e] = a.x2[k][g];
         if constexpr (k == NL - 1) {
-            // P x_C: the coarse node when i and j are even, else the mean of
-            // the two coarse ends of the fine edge through (i, j)
-            if (fr) {
-                const int Nc1 = N / 2 + 1, I = i >> 1, J = j >> 1;
-                const T* xcc = a.xc + (size_t)col * a.ldc;
-                const T p0 = xcc[J * Nc1 + I];
-                v += ((i | j) & 1) ? (T)0.5 * (p0 + xcc[(J + (j & 1)) * Nc1 + I + (i & 1)]) : p0;
-            }
+            // P x_C operands: the coarse node (i/2, j/2) and the far coarse
+            // end of the fine edge through (i, j)
+            const int Nc = N / 2, ic = clamp_node(i, N), jc = clamp_node(j, N), I = ic >> 1, J = jc >> 1;
+            const T* xcc = a.xc + (size_t)col * a.ldc;
+            pc0[e] = xcc[J * (Nc + 1) + I];
+            pc1[e] = xcc[min(J + (jc & 1), Nc) * (Nc + 1) + min(I + (ic & 1), Nc)];
         }
-        vx[e] = v;
-        vr[e] = stage && t < NN ? tile_row<T>(op.at(col), i, j) : TileRow<T>{};
+        // rows loaded whether or not this column stages them (few-column
+        // cycles: the next columns of a workgroup find them in cache)
+        vr[e] = tile_row<T>(op.at(col), i, j);
     }
     if constexpr (k + 1 < NL) chain_load<T, Op, kTF, NL, NT, k + 1>(a, ox, oy, dirichlet, col, stage, sx, sb, ts);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int t = threadIdx.x + NT * e;
         if (t < NN) {
-            sb[off + t] = vb[e];
-            sx[off + t] = vx[e];
+            const int i = ox[k] + t % W, j = oy[k] + t / W;
+            const bool in = i >= 0 && i <= N && j >= 0 && j <= N;
+            const bool fr = in && !(dirichlet && (j == 0 || j == N));
+            T v = fr ? vx[e] : (T)0;
+            // x2 + P x_C on the coarsest level of the chain: the coarse node
+            // when i and j are even, else the mean of the edge's two ends
+            if constexpr (k == NL - 1)
+                if (fr) v += ((i | j) & 1) ? (T)0.5 * (pc0[e] + pc1[e]) : pc0[e];
+            sb[off + t] = in ? vb[e] : (T)0;
+            sx[off + t] = v;
             if (stage) {
-                if constexpr (NE) ts.c[off + t] = vr[e].c;
-                ts.e[off + t] = vr[e].e;
-                ts.n[off + t] = vr[e].n;
-                if constexpr (NE) ts.g[off + t] = vr[e].g;
-                ts.dv[off + t] = vr[e].dv;
+                const TileRow<T> r = in ? vr[e] : TileRow<T>{};
+                if constexpr (NE) ts.c[off + t] = r.c;
+                ts.e[off + t] = r.e;
+                ts.n[off + t] = r.n;
+                if constexpr (NE) ts.g[off + t] = r.g;
+                ts.dv[off + t] = r.dv;
             }
         }
     }
