@@ -346,7 +346,7 @@ struct TileStencil {
 // The state operator stages its two edge weights and 1/d per node; the
 // diagonal is summed from the staged weights of the node and of its west and
 // south neighbours where it is used (tile_center), so no diagonal array is
-// staged (three loads a node instead of five, a sixth less LDS).
+// staged (three loads a node instead of five, one LDS array fewer).
 template <int TW, int NT, typename T>
 __device__ inline void stage_stencil(const OpA<T>& op, const TileStencil<T>& s, int ox, int oy) {
     constexpr int NN = TW * TW, E = (NN + NT - 1) / NT;
