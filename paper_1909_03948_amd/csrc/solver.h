@@ -103,11 +103,11 @@ class Hierarchy {
     template <typename T>
     void pcg_iteration(int nc, int cur, int first);
     template <typename T>
-    hipGraphExec_t pcg_graph(int nc);
+    hipGraphExec_t pcg_graph(int nc, int reps);
     template <typename T>
     hipGraphExec_t prologue_graph(int nc);
     template <typename T>
-    hipGraphExec_t capture(int nc, bool prologue);
+    hipGraphExec_t capture(int nc, bool prologue, int reps);
     void drop_graphs();
     template <typename T>
     void vcycle(int nc, int check);
@@ -199,8 +199,11 @@ class Hierarchy {
     void read_state(hipStream_t s, int nc, int nflags);
     hipStream_t gs_ = nullptr;             // private stream for graph capture
     hipStream_t launch_stream_ = nullptr;  // stream the PCG kernels go to (capture or caller)
-    hipGraphExec_t gexec_[2] = {nullptr, nullptr};  // FP64 / FP32 two-iteration graphs
-    int gexec_nc_[2] = {0, 0};
+    // FP64 / FP32 graphs of 2 reps iterations, reps = 1 .. kMaxReps: a run of
+    // iterations is one graph launch (each launch costs ~8 us of idle GPU)
+    static constexpr int kMaxReps = 6;
+    hipGraphExec_t gexec_[2][kMaxReps] = {};
+    int gexec_nc_[2][kMaxReps] = {};
     hipGraphExec_t gpro_[2] = {nullptr, nullptr};   // FP64 / FP32 prologue graphs (V-cycle, first iteration)
     int gpro_nc_[2] = {0, 0};
     long solves_ = 0;  // inner solves so far (every 16th runs its prologue eagerly while timing)

@@ -1200,10 +1200,11 @@ void Hierarchy::pcg_iteration(int nc, int cur, int first) {
     vcycle<T>(nc, 1);
 }
 
-// Graph of two PCG iterations starting from P[1] (captured once per precision
-// and column count; replayed on the caller's stream).
+// Graph of 2 reps PCG iterations starting from P[1], or of the prologue
+// (captured once per precision and column count; replayed on the caller's
+// stream).
 template <typename T>
-hipGraphExec_t Hierarchy::capture(int nc, bool prologue) {
+hipGraphExec_t Hierarchy::capture(int nc, bool prologue, int reps) {
     hipGraph_t graph = nullptr;
     HINV_HIP(hipStreamBeginCapture(gs_, hipStreamCaptureModeRelaxed));
     launch_stream_ = gs_;
@@ -1213,8 +1214,10 @@ hipGraphExec_t Hierarchy::capture(int nc, bool prologue) {
             vcycle<T>(nc, 0);
             pcg_iteration<T>(nc, 0, 1);
         } else {
-            pcg_iteration<T>(nc, 1, 0);
-            pcg_iteration<T>(nc, 0, 0);
+            for (int r = 0; r < reps; ++r) {
+                pcg_iteration<T>(nc, 1, 0);
+                pcg_iteration<T>(nc, 0, 0);
+            }
         }
     } catch (...) {
         ctx_->timer.paused = false;
@@ -1233,18 +1236,20 @@ hipGraphExec_t Hierarchy::capture(int nc, bool prologue) {
     return exec;
 }
 
-// Graph of two PCG iterations starting from P[1].
+// Graph of 2 reps PCG iterations starting from P[1] (1 <= reps <= kMaxReps).
 template <typename T>
-hipGraphExec_t Hierarchy::pcg_graph(int nc) {
-    const int slot = sizeof(T) == 8 ? 0 : 1;
-    if (gexec_[slot] && gexec_nc_[slot] == nc) return gexec_[slot];
-    if (gexec_[slot]) {
-        HINV_HIP(hipGraphExecDestroy(gexec_[slot]));
-        gexec_[slot] = nullptr;
+hipGraphExec_t Hierarchy::pcg_graph(int nc, int reps) {
+    const int slot = sizeof(T) == 8 ? 0 : 1, r = reps - 1;
+    if (reps < 1 || reps > kMaxReps) fail(HINV_EINVAL, "PCG graph length out of range");
+    hipGraphExec_t& g = gexec_[slot][r];
+    if (g && gexec_nc_[slot][r] == nc) return g;
+    if (g) {
+        HINV_HIP(hipGraphExecDestroy(g));
+        g = nullptr;
     }
-    gexec_[slot] = capture<T>(nc, false);
-    gexec_nc_[slot] = nc;
-    return gexec_[slot];
+    g = capture<T>(nc, false, reps);
+    gexec_nc_[slot][r] = nc;
+    return g;
 }
 
 // Graph of the start of a solve: the V-cycle of the initial residual and the
@@ -1257,17 +1262,18 @@ hipGraphExec_t Hierarchy::prologue_graph(int nc) {
         HINV_HIP(hipGraphExecDestroy(gpro_[slot]));
         gpro_[slot] = nullptr;
     }
-    gpro_[slot] = capture<T>(nc, true);
+    gpro_[slot] = capture<T>(nc, true, 1);
     gpro_nc_[slot] = nc;
     return gpro_[slot];
 }
 
 void Hierarchy::drop_graphs() {
     for (int i = 0; i < 2; ++i) {
-        if (gexec_[i]) {
-            (void)hipGraphExecDestroy(gexec_[i]);
-            gexec_[i] = nullptr;
-        }
+        for (auto& g : gexec_[i])
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
         if (gpro_[i]) {
             (void)hipGraphExecDestroy(gpro_[i]);
             gpro_[i] = nullptr;
@@ -1278,9 +1284,10 @@ void Hierarchy::drop_graphs() {
 // Inner PCG on w.r (right-hand side, overwritten by the residual) -> w.x.
 // Columns: act_ (cleared on the device as columns converge); tolerances in
 // st_.tol2 relative to st_.bb.  The start (V-cycle of the residual, first
-// iteration) is one captured graph, the rest replays of a two-iteration graph;
-// the host checks for completion after a run of replays (kernels of finished
-// columns return at once).
+// iteration) is one captured graph; the run of iterations up to the first
+// completion check is one launch of a graph of that many iterations, later
+// runs two iterations each; the host checks for completion after each run
+// (kernels of finished columns return at once).
 template <typename T>
 bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()>* tail) {
     hipStream_t s = ctx_->stream;
@@ -1310,7 +1317,7 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
             it = 1;
         }
     }
-    // Replays before the first completion check follow the iteration count of
+    // Iterations before the first completion check follow the iteration count of
     // the last solve of this shape: the columns count their own iterations in
     // the column state, so the estimate is the slowest column's count, not the
     // replays (kernels of finished columns return at once, so a late check
@@ -1325,7 +1332,7 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
     const int* hact = host_act();
     while (it < max_iter) {
         int reps = 1;
-        if (first_check && expect > it + 2) reps = std::min(6, (expect - it + 1) / 2);
+        if (first_check && expect > it + 2) reps = std::min(kMaxReps, (expect - it + 1) / 2);
         while (reps > 0 && it + 2 * reps > max_iter) --reps;
         if (sampled && it + 2 <= max_iter) {
             ctx_->timer.force = true;
@@ -1335,14 +1342,14 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
             sampled = false;
             it += 2;
             if (reps > 1 && graphs) {
-                for (int rep = 1; rep < reps; ++rep) HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
+                HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc, reps - 1), s));
                 it += 2 * (reps - 1);
                 for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom,
                               kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)})
                     ctx_->timer.count_only(k, 2 * (reps - 1));
             }
         } else if (graphs && reps > 0) {
-            for (int rep = 0; rep < reps; ++rep) HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc), s));
+            HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc, reps), s));
             it += 2 * reps;
             // two iterations per replay: two launches of each finest-level class
             for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom,
