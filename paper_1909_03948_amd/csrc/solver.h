@@ -105,7 +105,7 @@ class Hierarchy {
     template <typename T>
     hipGraphExec_t pcg_graph(int nc, int reps);
     template <typename T>
-    hipGraphExec_t prologue_graph(int nc);
+    hipGraphExec_t prologue_graph(int nc, int reps);
     template <typename T>
     hipGraphExec_t capture(int nc, bool prologue, int reps);
     void drop_graphs();
@@ -204,8 +204,10 @@ class Hierarchy {
     static constexpr int kMaxReps = 6;
     hipGraphExec_t gexec_[2][kMaxReps] = {};
     int gexec_nc_[2][kMaxReps] = {};
-    hipGraphExec_t gpro_[2] = {nullptr, nullptr};   // FP64 / FP32 prologue graphs (V-cycle, first iteration)
-    int gpro_nc_[2] = {0, 0};
+    // FP64 / FP32 prologue graphs (V-cycle, first iteration) followed by
+    // 2 reps iterations, reps = 0 .. kMaxReps
+    hipGraphExec_t gpro_[2][kMaxReps + 1] = {};
+    int gpro_nc_[2][kMaxReps + 1] = {};
     long solves_ = 0;  // inner solves so far (every 16th runs its prologue eagerly while timing)
     PcgWork<double> w64_;
     PcgWork<float> w32_;

@@ -1213,11 +1213,10 @@ hipGraphExec_t Hierarchy::capture(int nc, bool prologue, int reps) {
         if (prologue) {
             vcycle<T>(nc, 0);
             pcg_iteration<T>(nc, 0, 1);
-        } else {
-            for (int r = 0; r < reps; ++r) {
-                pcg_iteration<T>(nc, 1, 0);
-                pcg_iteration<T>(nc, 0, 0);
-            }
+        }
+        for (int r = 0; r < reps; ++r) {
+            pcg_iteration<T>(nc, 1, 0);
+            pcg_iteration<T>(nc, 0, 0);
         }
     } catch (...) {
         ctx_->timer.paused = false;
@@ -1255,16 +1254,18 @@ hipGraphExec_t Hierarchy::pcg_graph(int nc, int reps) {
 // Graph of the start of a solve: the V-cycle of the initial residual and the
 // first PCG iteration (ends with p in P[1]).
 template <typename T>
-hipGraphExec_t Hierarchy::prologue_graph(int nc) {
+hipGraphExec_t Hierarchy::prologue_graph(int nc, int reps) {
     const int slot = sizeof(T) == 8 ? 0 : 1;
-    if (gpro_[slot] && gpro_nc_[slot] == nc) return gpro_[slot];
-    if (gpro_[slot]) {
-        HINV_HIP(hipGraphExecDestroy(gpro_[slot]));
-        gpro_[slot] = nullptr;
+    if (reps < 0 || reps > kMaxReps) fail(HINV_EINVAL, "PCG graph length out of range");
+    hipGraphExec_t& g = gpro_[slot][reps];
+    if (g && gpro_nc_[slot][reps] == nc) return g;
+    if (g) {
+        HINV_HIP(hipGraphExecDestroy(g));
+        g = nullptr;
     }
-    gpro_[slot] = capture<T>(nc, true, 1);
-    gpro_nc_[slot] = nc;
-    return gpro_[slot];
+    g = capture<T>(nc, true, reps);
+    gpro_nc_[slot][reps] = nc;
+    return g;
 }
 
 void Hierarchy::drop_graphs() {
@@ -1274,20 +1275,21 @@ void Hierarchy::drop_graphs() {
                 (void)hipGraphExecDestroy(g);
                 g = nullptr;
             }
-        if (gpro_[i]) {
-            (void)hipGraphExecDestroy(gpro_[i]);
-            gpro_[i] = nullptr;
-        }
+        for (auto& g : gpro_[i])
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
     }
 }
 
 // Inner PCG on w.r (right-hand side, overwritten by the residual) -> w.x.
 // Columns: act_ (cleared on the device as columns converge); tolerances in
 // st_.tol2 relative to st_.bb.  The start (V-cycle of the residual, first
-// iteration) is one captured graph; the run of iterations up to the first
-// completion check is one launch of a graph of that many iterations, later
-// runs two iterations each; the host checks for completion after each run
-// (kernels of finished columns return at once).
+// iteration) and the run of iterations up to the first completion check are
+// one launch of a captured graph, later runs two iterations each; the host
+// checks for completion after each run (kernels of finished columns return
+// at once).
 template <typename T>
 bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()>* tail) {
     hipStream_t s = ctx_->stream;
@@ -1305,11 +1307,26 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
     // solve keeps the mix of operators in the class averages fixed.)
     int it = 0;
     bool sampled = ctx_->timer.any_on() && (nc >= kSmallTileCols || solves_++ % 16 == 0);
+    // Iterations before the first completion check follow the iteration count of
+    // the last solve of this shape: the columns count their own iterations in
+    // the column state, so the estimate is the slowest column's count, not the
+    // replays (kernels of finished columns return at once, so a late check
+    // costs launches, not work).  At most 13 iterations run before the first
+    // check, 2 between later ones.
+    const long long key = 2LL * nc + (sizeof(T) == 4);
+    int expect = 0;
+    for (const auto& kv : last_iters_)
+        if (kv.first == key) expect = kv.second;
+    // iterations after the prologue up to the first check: with graphs (and
+    // no eager sampled iterations) they are part of the prologue's launch
+    int pre = 0;
     if (graphs && max_iter > 0) {
-        HINV_HIP(hipGraphLaunch(prologue_graph<T>(nc), s));
-        it = 1;
-        for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom}) ctx_->timer.count_only(k, 2);
-        for (int k : {kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)}) ctx_->timer.count_only(k, 1);
+        if (!sampled) pre = expect > 3 ? std::min(kMaxReps, expect / 2) : 1;
+        while (pre > 0 && 1 + 2 * pre > max_iter) --pre;
+        HINV_HIP(hipGraphLaunch(prologue_graph<T>(nc, pre), s));
+        it = 1 + 2 * pre;
+        for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom}) ctx_->timer.count_only(k, 2 + 2 * pre);
+        for (int k : {kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)}) ctx_->timer.count_only(k, 1 + 2 * pre);
     } else {
         vcycle<T>(nc, 0);
         if (max_iter > 0) {
@@ -1317,49 +1334,44 @@ bool Hierarchy::pcg(int nc, int max_iter, int* iters, const std::function<void()
             it = 1;
         }
     }
-    // Iterations before the first completion check follow the iteration count of
-    // the last solve of this shape: the columns count their own iterations in
-    // the column state, so the estimate is the slowest column's count, not the
-    // replays (kernels of finished columns return at once, so a late check
-    // costs launches, not work).  At most 12 iterations run before the first
-    // check, 2 between later ones.
-    const long long key = 2LL * nc + (sizeof(T) == 4);
-    int expect = 0;
-    for (const auto& kv : last_iters_)
-        if (kv.first == key) expect = kv.second;
     bool first_check = true, tail_state = false;
     const ColState* hst = host_st();  // pinned, so the read-backs need no staging copy
     const int* hact = host_act();
-    while (it < max_iter) {
-        int reps = 1;
-        if (first_check && expect > it + 2) reps = std::min(kMaxReps, (expect - it + 1) / 2);
-        while (reps > 0 && it + 2 * reps > max_iter) --reps;
-        if (sampled && it + 2 <= max_iter) {
-            ctx_->timer.force = true;
-            pcg_iteration<T>(nc, 1, 0);
-            pcg_iteration<T>(nc, 0, 0);
-            ctx_->timer.force = false;
-            sampled = false;
-            it += 2;
-            if (reps > 1 && graphs) {
-                HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc, reps - 1), s));
-                it += 2 * (reps - 1);
-                for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom,
-                              kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)})
-                    ctx_->timer.count_only(k, 2 * (reps - 1));
-            }
-        } else if (graphs && reps > 0) {
-            HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc, reps), s));
-            it += 2 * reps;
-            // two iterations per replay: two launches of each finest-level class
-            for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom,
-                              kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)})
-                ctx_->timer.count_only(k, 2 * reps);
+    bool pre_ran = pre > 0;
+    while (it < max_iter || pre_ran) {
+        if (pre_ran) {
+            pre_ran = false;  // the first run came with the prologue
         } else {
-            // odd tail: one eager iteration keeps the ping-pong parity at P[1]
-            pcg_iteration<T>(nc, 1, 0);
-            pcg_iteration<T>(nc, 0, 0);
-            it += 2;
+            int reps = 1;
+            if (first_check && expect > it + 2) reps = std::min(kMaxReps, (expect - it + 1) / 2);
+            while (reps > 0 && it + 2 * reps > max_iter) --reps;
+            if (sampled && it + 2 <= max_iter) {
+                ctx_->timer.force = true;
+                pcg_iteration<T>(nc, 1, 0);
+                pcg_iteration<T>(nc, 0, 0);
+                ctx_->timer.force = false;
+                sampled = false;
+                it += 2;
+                if (reps > 1 && graphs) {
+                    HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc, reps - 1), s));
+                    it += 2 * (reps - 1);
+                    for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom,
+                                  kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)})
+                        ctx_->timer.count_only(k, 2 * (reps - 1));
+                }
+            } else if (graphs && reps > 0) {
+                HINV_HIP(hipGraphLaunch(pcg_graph<T>(nc, reps), s));
+                it += 2 * reps;
+                // two iterations per replay: two launches of each finest-level class
+                for (int k : {kclass_for(kKDown, nc), kclass_for(kKUp, nc), (int)kKBottom,
+                                  kclass_for(kKPcgApply, nc), kclass_for(kKPcgUpdate, nc)})
+                    ctx_->timer.count_only(k, 2 * reps);
+            } else {
+                // odd tail: one eager iteration keeps the ping-pong parity at P[1]
+                pcg_iteration<T>(nc, 1, 0);
+                pcg_iteration<T>(nc, 0, 0);
+                it += 2;
+            }
         }
         if (trace_on()) trace_cols(s, "pcg", it, st_.get(), act, nc);
         if (tail) (*tail)();
