@@ -1251,8 +1251,9 @@ hipGraphExec_t Hierarchy::pcg_graph(int nc, int reps) {
     return g;
 }
 
-// Graph of the start of a solve: the V-cycle of the initial residual and the
-// first PCG iteration (ends with p in P[1]).
+// Graph of the start of a solve: the V-cycle of the initial residual, the
+// first PCG iteration and 2 reps more (0 <= reps <= kMaxReps; ends with p in
+// P[1]).
 template <typename T>
 hipGraphExec_t Hierarchy::prologue_graph(int nc, int reps) {
     const int slot = sizeof(T) == 8 ? 0 : 1;
