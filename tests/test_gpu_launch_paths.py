@@ -71,3 +71,38 @@ def test_timed_and_eager_paths_match_graph_path(ctx, N, q, nc, monkeypatch):
     monkeypatch.setenv("HINV_NO_GRAPHS", "1")
     eager = run(gp, mh, 1)
     assert np.array_equal(eager[0], ref[0])
+
+
+@pytest.mark.parametrize("max_iter", [2, 3, 5, 6])
+def test_iteration_cap_same_iterate_on_graph_and_eager_paths(ctx, max_iter, monkeypatch):
+    """With the iteration cap inside the run that the prologue graph carries,
+    the graph path (prologue plus a run shortened to the cap) and the eager
+    path stop at the same iterate: the state solve reports HINV_ENOCONV with
+    identical outputs, and a solve after lifting the cap reaches 1e-10 on
+    both paths."""
+    print(f"[gpu-paths] max_iter={max_iter}", flush=True)
+    prob, gp = linearized(ctx, 64, 120)
+    b = synth.test_vectors(prob.n, 1, stream=81)
+    b[:, ~prob.free] = 0.0
+    bd = dev(b)
+    # a solve without the cap first: its iteration count sets the length of
+    # the run before the first completion check
+    x0 = torch.zeros_like(bd)
+    assert gp.state_solve(bd, x0)["rc"] == 0
+    outs = []
+    for eager in (False, True):
+        if eager:
+            monkeypatch.setenv("HINV_NO_GRAPHS", "1")
+        gp.set_solver(hv.PREC_FP64, 1e-10, max_iter)
+        x = torch.zeros_like(bd)
+        info = gp.state_solve(bd, x)
+        torch.cuda.synchronize()
+        assert info["rc"] == hv.HINV_ENOCONV, info
+        outs.append((x.cpu().numpy(), info["iterations"]))
+        gp.set_solver(hv.PREC_FP64, 1e-10, 0)
+        x = torch.zeros_like(bd)
+        info = gp.state_solve(bd, x)
+        assert info["rc"] == 0 and info["max_relres"] <= 1e-10, info
+        monkeypatch.delenv("HINV_NO_GRAPHS", raising=False)
+    assert outs[0][1] == outs[1][1], outs
+    assert np.array_equal(outs[0][0], outs[1][0])
